@@ -1,0 +1,509 @@
+"""CPU FP64 oracle for approximate products of matrices with decay.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the GPU library (no kernels, headers, helpers or tables); it reads its
+inputs from the ``synth`` generators or from plain arrays.
+
+It follows A. G. Artemov, "Approximate multiplication of nearly sparse
+matrices with decay in a fully recursive distributed task-based parallel
+framework" (arXiv:1906.08148):
+
+* Sec. 2 (SpAMM algorithm): a matrix is a quadtree whose level-t node splits
+  into four level-(t+1) children; every node carries its squared Frobenius
+  norm, the sum of its children's squared norms.
+* Alg. 1 (SpAMM): child product (i,k,j) is formed only when
+  ||A_ik||_F * ||B_kj||_F >= tau; the lowest level returns the plain product.
+* Alg. 2 (MatrixMultiply) and Sec. 4.2: zero sub-matrices are stored as null;
+  a product with a null operand is null.
+* Sec. 4.4 (leaf level library): the hierarchy stops at a dense leaf block,
+  kept when it holds at least one non-zero value.
+* Sec. 3, eq. (truncated_matrices) and Thms 1-3: Truncmul multiplies the
+  truncated inputs, SpAMM skips small products, Hybrid applies SpAMM to the
+  truncated inputs with the same tau (proof of Thm 3).
+
+Readings where the paper is silent (each listed with its reason in the design
+notes of the repository):
+
+* Truncation drops whole leaf blocks: the leaves are ordered by (squared norm,
+  Morton key) and the longest prefix whose *exact* summed squared norm is
+  <= tau^2 is dropped, so ||A - A~||_F <= tau.  Element-wise truncation
+  (the theorems' object) is ``truncate_elementwise``.
+* The norm test is ``sqrt(sA) * sqrt(sB) >= tau`` in FP64 with correctly
+  rounded square roots; null blocks never form products, also at tau = 0.
+* The test is applied uniformly at leaf triples, so a single-leaf matrix is
+  also tested (the task type of Sec. 4.3 checks its own operands).
+* Products within one C block are summed over k ascending.
+* Parent squared norms are summed as ((c00 + c01) + c10) + c11.
+
+Everything is FP64.  Nothing here is blocked, fused or reordered beyond what
+the definitions above state.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TRUNCMUL, SPAMM, HYBRID = 0, 1, 2
+MODE_NAMES = {TRUNCMUL: "truncmul", SPAMM: "spamm", HYBRID: "hybrid"}
+
+
+# --------------------------------------------------------------------------
+# Quadtree layout (Sec. 2): level 0 is the root, level L holds the G x G leaves
+# --------------------------------------------------------------------------
+
+def grid_size(n: int, bs: int):
+    """G = ceil(n/bs) rounded up to a power of two, and L = log2(G)."""
+    g = -(-n // bs)
+    G = 1
+    while G < g:
+        G *= 2
+    return G, G.bit_length() - 1
+
+
+def morton_key(I, J):
+    """Z-order key of block (I, J); the row bit sits above the column bit,
+    so the children of node (I, J) are 4*key(I,J) + 2a + b for (2I+a, 2J+b)."""
+    I = np.asarray(I, dtype=np.int64)
+    J = np.asarray(J, dtype=np.int64)
+    key = np.zeros(np.broadcast(I, J).shape, dtype=np.int64)
+    for b in range(31):
+        key |= ((I >> b) & 1) << (2 * b + 1)
+        key |= ((J >> b) & 1) << (2 * b)
+    return key
+
+
+@dataclass
+class Tree:
+    """A matrix as a quadtree of bs x bs leaves (Sec. 2, Sec. 4.4).
+
+    ``index[I, J]`` is the row of ``blocks`` holding leaf (I, J), or -1 when
+    the leaf is null.  ``sq[l]`` is the (2^l x 2^l) array of squared Frobenius
+    norms at level l (0 for null nodes) and ``present[l]`` says which nodes
+    are non-null.
+    """
+    n: int
+    bs: int
+    G: int
+    L: int
+    index: np.ndarray
+    blocks: np.ndarray
+    sq: list = field(default_factory=list)
+    present: list = field(default_factory=list)
+
+    def leaf(self, I: int, J: int) -> np.ndarray:
+        return self.blocks[self.index[I, J]]
+
+    @property
+    def leaf_sq(self) -> np.ndarray:
+        return self.sq[self.L]
+
+    @property
+    def leaf_present(self) -> np.ndarray:
+        return self.present[self.L]
+
+    def fro(self) -> float:
+        return math.sqrt(self.sq[0][0, 0])
+
+    def to_dense(self) -> np.ndarray:
+        bs, G = self.bs, self.G
+        full = np.zeros((G * bs, G * bs), dtype=np.float64)
+        for I, J in zip(*np.nonzero(self.index >= 0)):
+            full[I * bs:(I + 1) * bs, J * bs:(J + 1) * bs] = self.leaf(I, J)
+        return full[:self.n, :self.n]
+
+    def nonnull_count(self) -> int:
+        return int((self.index >= 0).sum())
+
+
+def pyramid(leaf_sq: np.ndarray, leaf_present: np.ndarray):
+    """Squared norms of every level (Sec. 2): a parent is the FP64 sum of its
+    four children, taken as ((c00 + c01) + c10) + c11."""
+    sq = [leaf_sq]
+    present = [leaf_present]
+    while sq[0].shape[0] > 1:
+        c = sq[0]
+        p = present[0]
+        parent = ((c[0::2, 0::2] + c[0::2, 1::2]) + c[1::2, 0::2]) + c[1::2, 1::2]
+        par_p = p[0::2, 0::2] | p[0::2, 1::2] | p[1::2, 0::2] | p[1::2, 1::2]
+        sq.insert(0, parent)
+        present.insert(0, par_p)
+    return sq, present
+
+
+def _from_leaves(n, bs, G, L, coords, blocks) -> Tree:
+    """Tree from candidate leaves ``blocks[t]`` at ``coords[t] = (I, J)``
+    (zero-padded bs x bs each); all-zero candidates become null."""
+    index = np.full((G, G), -1, dtype=np.int64)
+    leaf_sq = np.zeros((G, G), dtype=np.float64)
+    nonzero = np.zeros((G, G), dtype=bool)
+    kept = []
+    for (I, J), b in zip(coords, blocks):
+        if not np.any(b != 0):
+            continue
+        index[I, J] = len(kept)
+        kept.append(b)
+        nonzero[I, J] = True
+        leaf_sq[I, J] = np.sum(b * b)
+    store = np.asarray(kept, dtype=np.float64).reshape(-1, bs, bs)
+    sq, present = pyramid(leaf_sq, nonzero)
+    return Tree(n, bs, G, L, index, store, sq, present)
+
+
+def build(dense: np.ndarray, bs: int) -> Tree:
+    """Pad A to bs*G, cut it into G x G leaves, null the all-zero leaves and
+    compute the squared-norm pyramid (Sec. 2; Sec. 4.2; Sec. 4.4)."""
+    dense = np.asarray(dense, dtype=np.float64)
+    n = dense.shape[0]
+    if n < 1 or dense.shape != (n, n):
+        raise ValueError("need a square matrix with n >= 1")
+    G, L = grid_size(n, bs)
+    full = np.zeros((G * bs, G * bs), dtype=np.float64)
+    full[:n, :n] = dense
+    leafs4 = full.reshape(G, bs, G, bs).transpose(0, 2, 1, 3)
+    coords = [(I, J) for I in range(G) for J in range(G)]
+    return _from_leaves(n, bs, G, L, coords, (leafs4[I, J] for I, J in coords))
+
+
+def build_from_blocks(n: int, bs: int, coords: np.ndarray, data: np.ndarray) -> Tree:
+    """Same as ``build`` for a list of (I, J) blocks: unlisted blocks are zero,
+    a repeated coordinate keeps its last block and entries beyond row or
+    column n are padding (zero)."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    G, L = grid_size(n, bs)
+    gmax = -(-n // bs)
+    last = {}
+    for t, (I, J) in enumerate(np.asarray(coords).reshape(-1, 2)):
+        if not (0 <= I < gmax and 0 <= J < gmax):
+            raise ValueError("block coordinate outside the matrix")
+        last[(int(I), int(J))] = t
+    cs, bl = [], []
+    for (I, J), t in sorted(last.items()):
+        b = np.array(data[t], dtype=np.float64, copy=True)
+        b[max(0, n - I * bs):, :] = 0.0
+        b[:, max(0, n - J * bs):] = 0.0
+        cs.append((I, J))
+        bl.append(b)
+    return _from_leaves(n, bs, G, L, cs, bl)
+
+
+def with_leaves_dropped(t: Tree, drop_mask: np.ndarray) -> Tree:
+    """Copy of ``t`` with the leaves in ``drop_mask`` set to null, pyramid
+    recomputed from the surviving leaves."""
+    index = t.index.copy()
+    index[drop_mask] = -1
+    present = index >= 0
+    leaf_sq = np.where(present, t.leaf_sq, 0.0)
+    sq, pres = pyramid(leaf_sq, present)
+    return Tree(t.n, t.bs, t.G, t.L, index, t.blocks, sq, pres)
+
+
+# --------------------------------------------------------------------------
+# Input truncation (vector-space truncation, Sec. 3)
+# --------------------------------------------------------------------------
+
+def _exact_scaled(x: float) -> int:
+    """x * 2**1074 as an exact integer (every finite double is a multiple
+    of 2**-1074)."""
+    num, den = float(x).as_integer_ratio()
+    return num * (1 << 1074) // den
+
+
+@dataclass
+class Truncation:
+    tree: Tree
+    dropped: np.ndarray          # (r, 2) leaf coords dropped, in drop order
+    dropped_sq: float            # FP64 of the exact dropped squared norm
+    boundary_sq: tuple           # exact (sum up to r*, sum up to r*+1) as floats
+    tie: bool                    # boundary within the 1e-12 tie band
+
+
+def truncate(t: Tree, tau: float) -> Truncation:
+    """Leaf-block truncation with a global Frobenius budget tau.
+
+    Order the non-null leaves by (squared norm, Morton key) ascending and drop
+    the longest prefix whose exact summed squared norm is <= tau^2; the
+    Frobenius norm of what is removed is then <= tau."""
+    if not (tau >= 0.0) or math.isinf(tau):
+        raise ValueError("tau must be finite and >= 0")
+    I, J = np.nonzero(t.index >= 0)
+    s = t.leaf_sq[I, J]
+    keys = morton_key(I, J)
+    order = np.lexsort((keys, s))      # primary s, secondary Morton key
+    tnum, tden = float(tau).as_integer_ratio()
+    # compare  sum * 2^-1074 <= (tnum/tden)^2  exactly
+    limit_lhs_scale = tden * tden
+    limit_rhs = tnum * tnum * (1 << 1074)
+    acc = 0
+    r = 0
+    for idx in order:
+        nxt = acc + _exact_scaled(s[idx])
+        if nxt * limit_lhs_scale <= limit_rhs:
+            acc = nxt
+            r += 1
+        else:
+            break
+    nxt_sum = acc + (_exact_scaled(s[order[r]]) if r < len(order) else 0)
+    dropped_idx = order[:r]
+    drop_mask = np.zeros_like(t.index, dtype=bool)
+    drop_mask[I[dropped_idx], J[dropped_idx]] = True
+    tau2 = float(tau) * float(tau)
+    b0 = float(Fraction(acc, 1 << 1074))
+    b1 = float(Fraction(nxt_sum, 1 << 1074)) if r < len(order) else math.inf
+    band = 1e-12 * tau2
+    tie = abs(b0 - tau2) <= band or (r < len(order) and abs(b1 - tau2) <= band)
+    # equal-norm run straddling the boundary also counts as a tie
+    if 0 < r < len(order) and s[order[r - 1]] == s[order[r]]:
+        tie = True
+    dropped = np.stack([I[dropped_idx], J[dropped_idx]], axis=1)
+    return Truncation(with_leaves_dropped(t, drop_mask), dropped, b0, (b0, b1), tie)
+
+
+def truncate_elementwise(dense: np.ndarray, tau: float) -> np.ndarray:
+    """Eq. (truncated_matrices): zero every entry with |a_ij| < tau."""
+    out = np.array(dense, dtype=np.float64, copy=True)
+    out[np.abs(out) < tau] = 0.0
+    return out
+
+
+# --------------------------------------------------------------------------
+# Which leaf products are formed (Alg. 1, Alg. 2)
+# --------------------------------------------------------------------------
+
+def norm_test(sa, sb, tau) -> np.ndarray:
+    """Alg. 1's test: ||A_ik||_F ||B_kj||_F >= tau, from squared norms."""
+    return np.sqrt(sa) * np.sqrt(sb) >= tau
+
+
+def kept_flat(A: Tree, B: Tree, tau: float, use_norms: bool) -> np.ndarray:
+    """All leaf triples (I, K, J) whose product is formed: both operands
+    non-null and, when ``use_norms``, the norm test passes.
+
+    Returns an int64 (m, 3) array sorted by (Morton key of (I, J), K)."""
+    G = A.G
+    pa, pb = A.leaf_present, B.leaf_present
+    out = []
+    for I in range(G):
+        ks = np.nonzero(pa[I])[0]
+        if len(ks) == 0:
+            continue
+        ok = pb[ks, :]                                   # (|ks|, G)
+        if use_norms:
+            ok = ok & norm_test(A.leaf_sq[I, ks][:, None], B.leaf_sq[ks, :], tau)
+        kk, jj = np.nonzero(ok)
+        if len(kk):
+            out.append(morton_key(I, jj) * G + ks[kk])
+    return _decode_sorted(out, G)
+
+
+def _decode_sorted(keys_list, G) -> np.ndarray:
+    """Sort keys morton(I,J)*G + K and turn them back into (I, K, J) rows."""
+    if not keys_list:
+        return np.zeros((0, 3), dtype=np.int64)
+    keys = np.sort(np.concatenate(keys_list).astype(np.int64))
+    K = keys % G
+    m = keys // G
+    I = np.zeros_like(m)
+    J = np.zeros_like(m)
+    for b in range(31):
+        I |= ((m >> (2 * b + 1)) & 1) << b
+        J |= ((m >> (2 * b)) & 1) << b
+    return np.stack([I, K, J], axis=1)
+
+
+def count_candidates(A: Tree, B: Tree) -> int:
+    """Number of leaf triples with both operands non-null."""
+    pa = A.leaf_present.astype(np.int64)
+    pb = B.leaf_present.astype(np.int64)
+    return int((pa.sum(axis=0) * pb.sum(axis=1)).sum())
+
+
+def kept_recursive(A: Tree, B: Tree, tau: float, use_norms: bool) -> np.ndarray:
+    """Alg. 1 (and, without norms, Alg. 2's null rule) run literally on the
+    two quadtrees from the root, recording each leaf triple reached.
+
+    The first call tests the root pair itself, as the SpAMM task type of
+    Sec. 4.3 checks its operands; for L >= 1 that test never changes the
+    result because a parent's norm is never smaller than a child's."""
+    L = A.L
+    found = []
+
+    def passes(level, ia, ka, kb, jb):
+        if not (A.present[level][ia, ka] and B.present[level][kb, jb]):
+            return False
+        if not use_norms:
+            return True
+        return bool(norm_test(A.sq[level][ia, ka], B.sq[level][kb, jb], tau))
+
+    def rec(level, I, K, J):
+        if level == L:
+            found.append((I, K, J))
+            return
+        for i in (0, 1):
+            for j in (0, 1):
+                for k in (0, 1):
+                    ci, ck, cj = 2 * I + i, 2 * K + k, 2 * J + j
+                    if passes(level + 1, ci, ck, ck, cj):
+                        rec(level + 1, ci, ck, cj)
+
+    if passes(0, 0, 0, 0, 0):
+        rec(0, 0, 0, 0)
+    if not found:
+        return np.zeros((0, 3), dtype=np.int64)
+    t = np.asarray(found, dtype=np.int64)
+    return _decode_sorted([morton_key(t[:, 0], t[:, 2]) * A.G + t[:, 1]], A.G)
+
+
+# --------------------------------------------------------------------------
+# The product and its accounting
+# --------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    C: Tree
+    kept: np.ndarray             # (m, 3) (I, K, J), C-Morton order, K ascending
+    A_used: Tree                 # operand after truncation (or A itself)
+    B_used: Tree
+    skipped_bound: np.ndarray    # (G, G) b_IJ = sum of skipped norm products
+    stats: dict
+
+
+def _check_pair(A: Tree, B: Tree, tau: float):
+    if A.n != B.n or A.bs != B.bs:
+        raise ValueError("A and B differ in n or leaf size")
+    if not (tau >= 0.0) or math.isinf(tau):
+        raise ValueError("tau must be finite and >= 0")
+
+
+def multiply(A: Tree, B: Tree, tau: float, mode: int, c_blocks=None) -> Result:
+    """C ~= A B by Truncmul, SpAMM or Hybrid.
+
+    Truncmul multiplies the truncated inputs and forms every non-null product
+    (Sec. 5.2 notes that no gemm is skipped); SpAMM forms the products that
+    pass Alg. 1's norm test; Hybrid applies SpAMM to the inputs truncated with
+    the same tau.  ``c_blocks`` (optional list of (I, J)) limits which C leaves
+    are computed numerically; structure and accounting are always complete.
+    """
+    _check_pair(A, B, tau)
+    dA = dB = 0.0
+    tieA = tieB = False
+    if mode in (TRUNCMUL, HYBRID):
+        ta = truncate(A, tau)
+        tb = ta if B is A else truncate(B, tau)
+        Au, Bu = ta.tree, tb.tree
+        dA, dB = math.sqrt(ta.dropped_sq), math.sqrt(tb.dropped_sq)
+        tieA, tieB = ta.tie, tb.tie
+    elif mode == SPAMM:
+        Au, Bu = A, B
+    else:
+        raise ValueError("unknown mode")
+    use_norms = mode in (SPAMM, HYBRID)
+    kept = kept_flat(Au, Bu, tau, use_norms)
+    n_candidates = count_candidates(Au, Bu)
+
+    G, bs = A.G, A.bs
+    # skipped-product bound b_IJ: sum over non-null but skipped k, k ascending
+    bnd = np.zeros((G, G), dtype=np.float64)
+    if use_norms:
+        for I in range(G):
+            ks = np.nonzero(Au.leaf_present[I])[0]
+            if len(ks) == 0:
+                continue
+            prod = np.sqrt(Au.leaf_sq[I, ks])[:, None] * np.sqrt(Bu.leaf_sq[ks, :])
+            skip = Bu.leaf_present[ks, :] & ~(prod >= tau)
+            # row-by-row accumulation = a sequential sum over k ascending
+            bnd[I, :] = np.where(skip, prod, 0.0).sum(axis=0)
+
+    # C leaves: sum over kept k ascending of A_IK @ B_KJ
+    want = None if c_blocks is None else {(int(a), int(b)) for a, b in c_blocks}
+    c_index = np.full((G, G), -1, dtype=np.int64)
+    c_list = []
+    c_present = np.zeros((G, G), dtype=bool)
+    if len(kept):
+        c_present[kept[:, 0], kept[:, 2]] = True
+    groups = {}
+    for I, K, J in kept:
+        groups.setdefault((int(I), int(J)), []).append(int(K))
+    for (I, J), ks in groups.items():
+        if want is not None and (I, J) not in want:
+            continue
+        acc = np.zeros((bs, bs), dtype=np.float64)
+        for K in ks:
+            acc = acc + Au.leaf(I, K) @ Bu.leaf(K, J)
+        c_index[I, J] = len(c_list)
+        c_list.append(acc)
+    blocks = np.asarray(c_list, dtype=np.float64).reshape(-1, bs, bs)
+    c_sq = np.zeros((G, G), dtype=np.float64)
+    for I, J in zip(*np.nonzero(c_index >= 0)):
+        b = blocks[c_index[I, J]]
+        c_sq[I, J] = np.sum(b * b)
+    sq, pres = pyramid(c_sq, c_present)
+    C = Tree(A.n, bs, G, A.L, c_index, blocks, sq, pres)
+
+    B1 = float(np.sum(bnd)) if use_norms else 0.0
+    B2 = math.sqrt(float(np.sum(bnd * bnd))) if use_norms else 0.0
+    normA, normB = A.fro(), B.fro()
+    normAu = Au.fro()
+    if mode == SPAMM:
+        bound = B2
+    elif mode == TRUNCMUL:
+        bound = dA * normB + normAu * dB
+    else:
+        bound = dA * normB + normAu * dB + B2
+    stats = dict(
+        mode=mode, tau=tau, bs=bs, n=A.n, G=G, L=A.L,
+        n_kept=int(len(kept)), n_candidates=n_candidates,
+        flops=2.0 * bs ** 3 * len(kept),
+        c_nonnull=int(c_present.sum()),
+        B1=B1, B2=B2, dA=dA, dB=dB, normA=normA, normB=normB,
+        err_bound=bound, trunc_tie=(tieA or tieB),
+    )
+    return Result(C, kept, Au, Bu, bnd, stats)
+
+
+def exact_product(A_dense: np.ndarray, B_dense: np.ndarray) -> np.ndarray:
+    """The untruncated product, the reference for the error E (Thms 1-3)."""
+    return np.asarray(A_dense, dtype=np.float64) @ np.asarray(B_dense, dtype=np.float64)
+
+
+def tie_triples(A: Tree, B: Tree, tau: float, band: float = 1e-12) -> np.ndarray:
+    """Non-null triples whose norm product lies within band*tau of tau; either
+    outcome of the test is accepted for them."""
+    G = A.G
+    out = []
+    for I in range(G):
+        ks = np.nonzero(A.leaf_present[I])[0]
+        if len(ks) == 0:
+            continue
+        prod = np.sqrt(A.leaf_sq[I, ks])[:, None] * np.sqrt(B.leaf_sq[ks, :])
+        near = B.leaf_present[ks, :] & (np.abs(prod - tau) <= band * tau)
+        kk, jj = np.nonzero(near)
+        if len(kk):
+            out.append(np.stack([np.full(len(kk), I), ks[kk], jj], axis=1))
+    if not out:
+        return np.zeros((0, 3), dtype=np.int64)
+    return np.concatenate(out).astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Element-level SpAMM (the object of Thm 2's proof) for tiny cases
+# --------------------------------------------------------------------------
+
+def spamm_elementwise(A: np.ndarray, B: np.ndarray, tau: float) -> np.ndarray:
+    """[C]_ij = sum_k chi_ikj with chi_ikj = a_ik b_kj unless
+    |a_ik| |b_kj| < tau (proof of Thm 2); zero operands contribute nothing."""
+    n = A.shape[0]
+    C = np.zeros((n, n), dtype=np.float64)
+    for i in range(n):
+        for j in range(n):
+            acc = 0.0
+            for k in range(n):
+                a, b = A[i, k], B[k, j]
+                if a != 0.0 and b != 0.0 and not (abs(a) * abs(b) < tau):
+                    acc += a * b
+            C[i, j] = acc
+    return C
