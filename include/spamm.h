@@ -1,0 +1,250 @@
+/*
+ * spamm.h - C-ABI of an MI355X (gfx950) library for approximate products
+ * C ~= A B of matrices with exponential decay, stored as quadtrees of dense
+ * leaf blocks, under three schemes: Truncmul (multiply truncated inputs),
+ * SpAMM (skip sub-matrix products whose norm product is below tau) and
+ * Hybrid (SpAMM on truncated inputs, same tau).
+ *
+ * Method: A. G. Artemov, "Approximate multiplication of nearly sparse
+ * matrices with decay in a fully recursive distributed task-based parallel
+ * framework", arXiv:1906.08148.  Section / algorithm references below are to
+ * that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All device memory comes from one caller-provided *arena* (for example a
+ *   torch uint8 tensor); the library sub-allocates in it and never calls
+ *   hipMalloc for matrix data.  Small pinned host staging is allocated once
+ *   per context with hipHostMalloc.
+ * - Work is enqueued on the context's stream (a hipStream_t passed as void*;
+ *   NULL is the legacy default stream).  Calls that must size an allocation
+ *   read a count back and synchronise that stream; this is stated per call.
+ * - Every function returns a spamm_status; no exception crosses the ABI.  On
+ *   an error, output handles are set to NULL and nothing is left allocated.
+ *   spamm_last_error() gives a message for the last failing call.
+ * - Matrix handles are immutable once returned (like the registered chunks
+ *   of Sec. 4.1): derived handles (spamm_truncate) share leaf storage, which
+ *   stays alive until every handle referring to it is released.
+ * - A context and its handles are used by one host thread at a time.
+ *
+ * Storage of a matrix (Sec. 2, Sec. 4.2, Sec. 4.4)
+ * ------------------------------------------------
+ * n x n, leaf size bs; G = ceil(n/bs) rounded up to a power of two, L =
+ * log2(G).  Level l (0 = root, L = leaves) has 4^l nodes in Morton (Z) order,
+ * row bit above column bit, so the children of node m are 4m..4m+3.  A leaf
+ * with no non-zero value is null and has no storage.  Every node carries its
+ * FP64 squared Frobenius norm; a parent's is the sum of its four children's,
+ * taken as ((c0 + c1) + c2) + c3.
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spamm_status {
+  SPAMM_OK = 0,
+  SPAMM_EINVAL = 1,       /* bad argument: tau < 0 / NaN / Inf, n < 1, ld < n,
+                             leaf not in {16,32,64,128}, NULL pointer, ...   */
+  SPAMM_ESHAPE = 2,       /* A and B (or D) differ in n or leaf size           */
+  SPAMM_ENOMEM = 3,       /* the arena cannot hold the result                 */
+  SPAMM_ENONFINITE = 4,   /* NaN or Inf in an input matrix                    */
+  SPAMM_EUNSUPPORTED = 5, /* requested precision/leaf combination not built   */
+  SPAMM_EDEVICE = 6       /* a HIP call failed (message in spamm_last_error)  */
+} spamm_status;
+
+/* Approximation scheme (Sec. 3; names as in Sec. 5). */
+typedef enum spamm_mode {
+  SPAMM_TRUNCMUL = 0, /* truncate A and B, form every non-null leaf product   */
+  SPAMM_SPAMM = 1,    /* form leaf products with ||A_ik||_F ||B_kj||_F >= tau */
+  SPAMM_HYBRID = 2    /* SPAMM on A and B truncated with the same tau         */
+} spamm_mode;
+
+/* Arithmetic of the leaf products.  The norms, the tau tests and all error
+ * accounting are FP64 in every precision. */
+typedef enum spamm_prec {
+  SPAMM_F64 = 0,   /* FP64 inputs, FP64 accumulation (MFMA f64)              */
+  SPAMM_F32 = 1,   /* FP32 inputs, FP32 accumulation (MFMA f32)              */
+  SPAMM_BF16 = 2,  /* BF16 inputs, FP32 accumulation (MFMA bf16)             */
+  SPAMM_BF16X3 = 3 /* split BF16: hi*hi + hi*lo + lo*hi, FP32 accumulation   */
+} spamm_prec;
+
+/* Leaf-store copies a matrix may hold (bit mask). */
+#define SPAMM_STORE_F64 1u
+#define SPAMM_STORE_F32 2u
+#define SPAMM_STORE_BF16 4u /* hi = bf16(x) and lo = bf16(x - hi) */
+
+typedef void* spamm_stream; /* a hipStream_t */
+typedef struct spamm_ctx spamm_ctx;
+typedef struct spamm_mat spamm_mat;
+
+/* Accounting of one product (FP64; Sec. 3, Thms 1-3). */
+typedef struct spamm_stats {
+  int64_t n_kept;       /* leaf products formed                              */
+  int64_t n_candidates; /* leaf triples with both operands non-null          */
+  int64_t c_nonnull;    /* non-null leaves of C                              */
+  double flops;         /* 2 * bs^3 * n_kept (Sec. 5.2 flop count)           */
+  double B1;            /* sum over C leaves of b_ij, where b_ij is the sum of
+                           ||A_ik||_F ||B_kj||_F over skipped non-null k     */
+  double B2;            /* (sum of b_ij^2)^(1/2) >= ||E_SpAMM||_F             */
+  double dA, dB;        /* Frobenius norm dropped by truncating A and B      */
+  double normA, normB;  /* ||A||_F, ||B||_F of the untruncated inputs        */
+  double normA_used;    /* ||A~||_F of the operand actually multiplied       */
+  double err_bound;     /* bound on ||A B - C||_F from the terms above       */
+  double trace;         /* trace of C (sum of diagonal-leaf diagonals)       */
+  double normC;         /* ||C||_F                                           */
+} spamm_stats;
+
+/* Optional epilogue: C = alpha * (approximate A B) + beta * D, with D a
+ * matrix of the same n and leaf size.  Leaves of D enter C whether or not a
+ * product lands there.  NULL means alpha = 1, beta = 0. */
+typedef struct spamm_epilogue {
+  double alpha;
+  double beta;
+  const spamm_mat* D;
+} spamm_epilogue;
+
+/* One request of a batched multiply (see spamm_multiply_batch). */
+typedef struct spamm_request {
+  const spamm_mat* A;
+  const spamm_mat* B;
+  double tau;
+  int32_t mode; /* spamm_mode */
+  int32_t prec; /* spamm_prec */
+  const spamm_epilogue* ep; /* may be NULL */
+} spamm_request;
+
+typedef struct spamm_mat_info {
+  int64_t n;
+  int32_t leaf, G, L;
+  int64_t nonnull;      /* non-null leaves                                  */
+  uint32_t stores;      /* SPAMM_STORE_* copies held                         */
+  int32_t has_plan;     /* 1 if the handle came from a multiply              */
+  int64_t n_kept;       /* products of that multiply                         */
+  size_t device_bytes;  /* arena bytes referenced by this handle             */
+} spamm_mat_info;
+
+/* Name of a status code (static string). */
+const char* spamm_status_string(spamm_status s);
+
+/* Message of the last failing call on this context (static per context;
+ * valid until the next call). */
+const char* spamm_last_error(const spamm_ctx* ctx);
+
+/* Create a context on HIP device `device`, sub-allocating from the device
+ * buffer [arena, arena + arena_bytes) (caller-owned, 256-byte aligned, must
+ * outlive the context) and enqueueing on `stream`.  Errors: EINVAL (NULL
+ * out/arena, arena_bytes < 1 MiB, misaligned arena), EDEVICE. */
+spamm_status spamm_ctx_create(int device, void* arena, size_t arena_bytes,
+                              spamm_stream stream, spamm_ctx** out);
+
+/* Destroy a context.  Every handle must have been released; the call
+ * synchronises the stream first. */
+spamm_status spamm_ctx_destroy(spamm_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
+
+/* Arena occupancy in bytes (host outputs, any may be NULL). */
+spamm_status spamm_ctx_arena_info(const spamm_ctx* ctx, size_t* used,
+                                  size_t* free_bytes, size_t* largest_free);
+
+/* Build a matrix from a dense FP64 row-major n x n device buffer with leading
+ * dimension ld (Sec. 2; Sec. 4.2 null blocks; Sec. 4.4 dense leaves kept when
+ * they hold a non-zero).  The input is read once for norms and flags and once
+ * more for the non-null leaves; it may be freed after the stream has passed
+ * this call.  `stores` chooses the leaf copies (F64 always recommended).
+ * Synchronises once (non-null count and non-finite flag).
+ * Errors: EINVAL, ENONFINITE, ENOMEM, EDEVICE. */
+spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n,
+                         int64_t ld, int32_t leaf, uint32_t stores,
+                         spamm_mat** out);
+
+/* Build from a list of nblocks leaf blocks: coords[2t], coords[2t+1] = (I, J)
+ * (device int32, 0 <= I, J < ceil(n/leaf)), data = nblocks x leaf x leaf FP64
+ * row-major (device).  Unlisted leaves are zero; listed all-zero blocks are
+ * null; entries past row/column n must be zero (EINVAL otherwise); a
+ * coordinate listed twice is EINVAL.  Synchronises once.
+ * Errors: EINVAL, ENONFINITE, ENOMEM, EDEVICE. */
+spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf,
+                                int64_t nblocks, const int32_t* coords,
+                                const double* data, uint32_t stores,
+                                spamm_mat** out);
+
+/* Input truncation with a global Frobenius budget (Sec. 3; the leaf-block
+ * form): order the non-null leaves by (squared norm, Morton key) and drop the
+ * longest prefix whose summed squared norm is <= tau^2, so that
+ * ||in - out||_F <= tau.  The result shares leaf storage with `in`.
+ * `dropped_sq` (host, nullable) receives the dropped squared norm.
+ * Synchronises once.  Errors: EINVAL, ENOMEM, EDEVICE. */
+spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau,
+                            spamm_mat** out, double* dropped_sq);
+
+/* C ~= A B (Alg. 1 with the null rule of Alg. 2; the mode selects Truncmul,
+ * SpAMM or Hybrid).  A leaf triple (i,k,j) is formed when A_ik and B_kj are
+ * non-null and, for SpAMM/Hybrid, sqrt(s_ik) * sqrt(s_kj) >= tau in FP64.
+ * Products of one C leaf are accumulated by one workgroup in ascending k, so
+ * results are bitwise reproducible.  C is a new handle whose leaves are FP64
+ * (prec F64) or FP32 (other precisions), with its own norm pyramid and the
+ * list of formed products (spamm_kept).  Missing compute copies of A/B are
+ * derived and cached.  A and B may be the same handle.  `st` may be NULL.
+ * Synchronises once to size C, and once more when `st` is given.
+ * Errors: EINVAL, ESHAPE, ENOMEM, EUNSUPPORTED, EDEVICE. */
+spamm_status spamm_multiply(spamm_ctx* ctx, const spamm_mat* A,
+                            const spamm_mat* B, double tau, spamm_mode mode,
+                            spamm_prec prec, const spamm_epilogue* ep,
+                            spamm_mat** C, spamm_stats* st);
+
+/* `count` multiplies as one batch: truncation, pruning and the C pyramids run
+ * as batched kernels and every leaf product of every request goes out in one
+ * persistent GEMM launch per (precision, leaf size).  C_out[r] and st_out[r]
+ * (nullable array) receive request r's result; each equals what
+ * spamm_multiply returns for that request alone, bit for bit.  On error no
+ * C_out is allocated.  Same errors as spamm_multiply. */
+spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count,
+                                  const spamm_request* reqs,
+                                  spamm_mat** C_out, spamm_stats* st_out);
+
+/* FP64 squared Frobenius norms of level `level` (0 = root .. L = leaves) in
+ * Morton order, or all levels root first when level = -1, copied to the host
+ * buffer out[cap]; *count receives the number of values (4^level, or
+ * (4^(L+1) - 1) / 3).  Null nodes read 0.  Synchronises.
+ * Errors: EINVAL (bad level, cap too small), EDEVICE. */
+spamm_status spamm_norms(spamm_ctx* ctx, const spamm_mat* m, int32_t level,
+                         double* out, int64_t cap, int64_t* count);
+
+/* The leaf products formed by the multiply that produced C, as host int32
+ * triples ijk[3t..3t+2] = (I, K, J), ordered by the Morton key of (I, J) and
+ * then K ascending.  *count receives the number of triples; with cap too
+ * small nothing is written and EINVAL is returned with *count set.
+ * Synchronises.  Errors: EINVAL (no plan on this handle), EDEVICE. */
+spamm_status spamm_kept(spamm_ctx* ctx, const spamm_mat* C, int32_t* ijk,
+                        int64_t cap, int64_t* count);
+
+/* Per-leaf skipped-product bound b_IJ of the multiply that produced C (FP64,
+ * G*G values in Morton order, host).  Synchronises. */
+spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C,
+                                 double* out, int64_t cap);
+
+/* Write the matrix as dense FP64 row-major n x n into device memory `out`
+ * with leading dimension ld (null leaves become zeros).  Asynchronous.
+ * Errors: EINVAL, EDEVICE. */
+spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out,
+                            int64_t ld);
+
+/* Describe a handle (host output). */
+spamm_status spamm_mat_info_get(const spamm_mat* m, spamm_mat_info* out);
+
+/* Release a handle (shared leaf storage is freed with its last user).
+ * Stream-ordered: the memory is reused only by work enqueued later on the
+ * same stream.  NULL is accepted. */
+spamm_status spamm_release(spamm_ctx* ctx, spamm_mat* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAMM_H */

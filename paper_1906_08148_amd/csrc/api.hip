@@ -1,0 +1,783 @@
+// C-ABI entry points: context, matrix handles, build, truncation, batched
+// multiply and read-back helpers.  All device work goes to the kernels in the
+// k_*.hip files; this file only sizes, allocates (from the caller's arena),
+// enqueues and reads back.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace spamm;
+
+struct spamm_ctx {
+  Ctx c;
+};
+
+namespace spamm {
+
+spamm_status fail(Ctx* c, spamm_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+void* Ctx::stage(size_t bytes) {
+  if (bytes <= host_stage_bytes) return host_stage;
+  if (host_stage) hipHostFree(host_stage);
+  host_stage = nullptr;
+  host_stage_bytes = 0;
+  size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+  if (hipHostMalloc(&host_stage, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+  host_stage_bytes = want;
+  return host_stage;
+}
+
+}  // namespace spamm
+
+size_t spamm_mat::device_bytes() const {
+  size_t b = 0;
+  for (auto* r : {&slot, &norms, &rm_sqrt, &rm_slot, &cm_sqrt, &cm_slot, &ranges, &plan_off, &plan_pairs, &plan_bnd})
+    if (*r) b += (*r)->bytes;
+  if (store) {
+    for (auto* r : {&store->keys, &store->f64, &store->f32, &store->bf16hi, &store->bf16lo})
+      if (*r) b += (*r)->bytes;
+  }
+  return b;
+}
+
+namespace {
+
+constexpr int kMaxL = 11;  // G <= 2048
+
+bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128; }
+
+void grid_of(int64_t n, int bs, int& G, int& L) {
+  const int64_t g = (n + bs - 1) / bs;
+  G = 1;
+  L = 0;
+  while (G < g) {
+    G *= 2;
+    ++L;
+  }
+}
+
+template <typename T>
+T* P(const RegionP& r) {
+  return r ? static_cast<T*>(r->ptr()) : nullptr;
+}
+
+struct Sync {
+  Ctx* c;
+  hipEvent_t ev = nullptr;
+};
+
+spamm_status sync_stream(Ctx* c) {
+  SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+  return SPAMM_OK;
+}
+
+// Wait until earlier uploads from the pinned staging buffer have been read.
+hipEvent_t g_stage_event = nullptr;
+
+spamm_status upload(Ctx* c, void* dev, const void* host, size_t bytes) {
+  if (bytes == 0) return SPAMM_OK;
+  if (!g_stage_event) SPAMM_HIP(c, hipEventCreateWithFlags(&g_stage_event, hipEventDisableTiming));
+  SPAMM_HIP(c, hipEventSynchronize(g_stage_event));
+  void* st = c->stage(bytes);
+  if (!st) return fail(c, SPAMM_EDEVICE, "hipHostMalloc of staging buffer failed");
+  std::memcpy(st, host, bytes);
+  SPAMM_HIP(c, hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, c->stream));
+  SPAMM_HIP(c, hipEventRecord(g_stage_event, c->stream));
+  return SPAMM_OK;
+}
+
+spamm_status download(Ctx* c, void* host, const void* dev, size_t bytes) {
+  if (bytes == 0) return SPAMM_OK;
+  if (g_stage_event) SPAMM_HIP(c, hipEventSynchronize(g_stage_event));
+  void* st = c->stage(bytes);
+  if (!st) return fail(c, SPAMM_EDEVICE, "hipHostMalloc of staging buffer failed");
+  SPAMM_HIP(c, hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+  std::memcpy(host, st, bytes);
+  return SPAMM_OK;
+}
+
+spamm_status nomem(Ctx* c, const char* what, size_t bytes) {
+  return fail(c, SPAMM_ENOMEM,
+              std::string("arena exhausted allocating ") + what + " (" + std::to_string(bytes) + " bytes, " +
+                  std::to_string(c->arena.free_bytes()) + " free)");
+}
+
+#define ALLOC(var, bytes, what)                                 \
+  do {                                                          \
+    (var) = c->alloc(bytes);                                    \
+    if (!(var)) return nomem(c, what, size_t(bytes));           \
+  } while (0)
+
+// Handle skeleton with the per-level arrays (no leaf storage).
+spamm_status new_matrix(Ctx* c, int64_t n, int bs, std::unique_ptr<spamm_mat>& out) {
+  auto m = std::make_unique<spamm_mat>();
+  m->ctx = c;
+  m->n = n;
+  m->bs = bs;
+  grid_of(n, bs, m->G, m->L);
+  if (m->L > kMaxL) return fail(c, SPAMM_EUNSUPPORTED, "quadtree deeper than 11 levels (n/leaf > 2048)");
+  const int64_t G2 = int64_t(m->G) * m->G;
+  ALLOC(m->slot, G2 * 4, "slot map");
+  ALLOC(m->norms, pyramid_size(m->L) * 8, "norm pyramid");
+  out = std::move(m);
+  return SPAMM_OK;
+}
+
+// Row/column views for pruning, computed on first use as an operand.
+spamm_status ensure_prep(Ctx* c, spamm_mat* m) {
+  if (m->rm_sqrt) return SPAMM_OK;
+  const int64_t G2 = int64_t(m->G) * m->G;
+  RegionP a, b, d, e, r;
+  ALLOC(a, G2 * 8, "row view");
+  ALLOC(b, G2 * 4, "row slots");
+  ALLOC(d, G2 * 8, "column view");
+  ALLOC(e, G2 * 4, "column slots");
+  ALLOC(r, int64_t(4) * m->G * 4, "ranges");
+  const double* leaf = P<double>(m->norms) + level_offset(m->L);
+  SPAMM_HIP(c, launch_prep(c->stream, m->G, P<int32_t>(m->slot), leaf, P<double>(a), P<int32_t>(b), P<double>(d),
+                           P<int32_t>(e)));
+  SPAMM_HIP(c, launch_ranges(c->stream, m->G, P<double>(a), P<double>(d), P<int32_t>(r)));
+  m->rm_sqrt = a;
+  m->rm_slot = b;
+  m->cm_sqrt = d;
+  m->cm_slot = e;
+  m->ranges = r;
+  return SPAMM_OK;
+}
+
+// Pyramid over a set of matrices whose leaf level is filled.
+spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls) {
+  if (norms.empty()) return SPAMM_OK;
+  std::vector<PyrJob> jobs(norms.size());
+  int64_t base = 0;
+  for (size_t t = 0; t < norms.size(); ++t) {
+    jobs[t].norms = norms[t];
+    jobs[t].L = Ls[t];
+    jobs[t].sub_levels = std::min(Ls[t], 5);
+    jobs[t].block_base = base;
+    base += int64_t(1) << (2 * (Ls[t] - jobs[t].sub_levels));
+  }
+  RegionP jd;
+  ALLOC(jd, jobs.size() * sizeof(PyrJob), "pyramid jobs");
+  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PyrJob));
+  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, launch_pyramid(c->stream, P<PyrJob>(jd), int(jobs.size()), jobs));
+  return SPAMM_OK;
+}
+
+spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask) {
+  s.nleaf = nleaf;
+  s.bs = bs;
+  const int64_t e = nleaf * bs * bs;
+  ALLOC(s.keys, std::max<int64_t>(nleaf, 1) * 4, "leaf keys");
+  if (mask & SPAMM_STORE_F64) ALLOC(s.f64, e * 8, "FP64 leaves");
+  if (mask & SPAMM_STORE_F32) ALLOC(s.f32, e * 4, "FP32 leaves");
+  if (mask & SPAMM_STORE_BF16) {
+    ALLOC(s.bf16hi, e * 2, "BF16 hi leaves");
+    ALLOC(s.bf16lo, e * 2, "BF16 lo leaves");
+  }
+  return SPAMM_OK;
+}
+
+// Make sure the store holds the copies `need` (derived from FP64 if present,
+// else from FP32).
+spamm_status ensure_store(Ctx* c, Store& s, uint32_t need) {
+  const uint32_t missing = need & ~s.mask();
+  if (!missing) return SPAMM_OK;
+  const int64_t e = s.nleaf * s.bs * s.bs;
+  RegionP o64, o32, ohi, olo;
+  if (missing & SPAMM_STORE_F64) ALLOC(o64, e * 8, "FP64 leaves");
+  if (missing & SPAMM_STORE_F32) ALLOC(o32, e * 4, "FP32 leaves");
+  if (missing & SPAMM_STORE_BF16) {
+    ALLOC(ohi, e * 2, "BF16 hi leaves");
+    ALLOC(olo, e * 2, "BF16 lo leaves");
+  }
+  if (!s.f64 && !s.f32) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 copy to derive from");
+  SPAMM_HIP(c, launch_derive_store(c->stream, e, P<double>(s.f64), s.f64 ? nullptr : P<float>(s.f32), P<double>(o64),
+                                   P<float>(o32), P<uint16_t>(ohi), P<uint16_t>(olo)));
+  if (o64) s.f64 = o64;
+  if (o32) s.f32 = o32;
+  if (ohi) {
+    s.bf16hi = ohi;
+    s.bf16lo = olo;
+  }
+  return SPAMM_OK;
+}
+
+uint32_t store_for_prec(int prec) {
+  switch (prec) {
+    case SPAMM_F64: return SPAMM_STORE_F64;
+    case SPAMM_F32: return SPAMM_STORE_F32;
+    default: return SPAMM_STORE_BF16;
+  }
+}
+
+bool tau_ok(double t) { return std::isfinite(t) && t >= 0.0; }
+
+spamm_status finish_build(Ctx* c, std::unique_ptr<spamm_mat>& m, spamm_mat** out) {
+  spamm_status st = pyramids(c, {P<double>(m->norms)}, {m->L});
+  if (st != SPAMM_OK) return st;
+  c->live_handles++;
+  *out = m.release();
+  return SPAMM_OK;
+}
+
+spamm_status truncate_impl(Ctx* c, const spamm_mat* in, double tau, std::unique_ptr<spamm_mat>& out,
+                           RegionP& result) {
+  std::unique_ptr<spamm_mat> m;
+  spamm_status st = new_matrix(c, in->n, in->bs, m);
+  if (st != SPAMM_OK) return st;
+  m->store = in->store;
+  RegionP scratch;
+  const size_t sb = trunc_scratch_bytes(in->G);
+  ALLOC(scratch, sb, "truncation scratch");
+  ALLOC(result, 16, "truncation result");
+  SPAMM_HIP(c, launch_trunc(c->stream, in->G, P<int32_t>(in->slot), P<double>(in->norms) + level_offset(in->L),
+                            tau * tau, P<int32_t>(m->slot), P<double>(m->norms) + level_offset(m->L), scratch->ptr(),
+                            sb, P<double>(result)));
+  st = pyramids(c, {P<double>(m->norms)}, {m->L});
+  if (st != SPAMM_OK) return st;
+  out = std::move(m);
+  return SPAMM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* spamm_status_string(spamm_status s) {
+  switch (s) {
+    case SPAMM_OK: return "SPAMM_OK";
+    case SPAMM_EINVAL: return "SPAMM_EINVAL";
+    case SPAMM_ESHAPE: return "SPAMM_ESHAPE";
+    case SPAMM_ENOMEM: return "SPAMM_ENOMEM";
+    case SPAMM_ENONFINITE: return "SPAMM_ENONFINITE";
+    case SPAMM_EUNSUPPORTED: return "SPAMM_EUNSUPPORTED";
+    case SPAMM_EDEVICE: return "SPAMM_EDEVICE";
+  }
+  return "SPAMM_UNKNOWN";
+}
+
+const char* spamm_last_error(const spamm_ctx* ctx) { return ctx ? ctx->c.last_error.c_str() : "no context"; }
+
+spamm_status spamm_ctx_create(int device, void* arena, size_t arena_bytes, spamm_stream stream, spamm_ctx** out) {
+  if (!out || !arena || arena_bytes < (size_t(1) << 20) || (reinterpret_cast<uintptr_t>(arena) & 255))
+    return SPAMM_EINVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return SPAMM_EDEVICE;
+  auto* x = new spamm_ctx;
+  x->c.device = device;
+  x->c.stream = static_cast<hipStream_t>(stream);
+  x->c.arena.init(static_cast<char*>(arena), arena_bytes);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    x->c.n_cu = cus;
+  if (!x->c.stage(size_t(1) << 20)) {
+    delete x;
+    return SPAMM_EDEVICE;
+  }
+  *out = x;
+  return SPAMM_OK;
+}
+
+spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
+  if (!ctx) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (c->live_handles != 0) return fail(c, SPAMM_EINVAL, "handles still alive");
+  hipStreamSynchronize(c->stream);
+  if (c->host_stage) hipHostFree(c->host_stage);
+  delete ctx;
+  return SPAMM_OK;
+}
+
+spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream) {
+  if (!ctx) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+  c->stream = static_cast<hipStream_t>(stream);
+  return SPAMM_OK;
+}
+
+spamm_status spamm_ctx_arena_info(const spamm_ctx* ctx, size_t* used, size_t* free_bytes, size_t* largest_free) {
+  if (!ctx) return SPAMM_EINVAL;
+  if (used) *used = ctx->c.arena.used();
+  if (free_bytes) *free_bytes = ctx->c.arena.free_bytes();
+  if (largest_free) *largest_free = ctx->c.arena.largest_free();
+  return SPAMM_OK;
+}
+
+spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t ld, int32_t leaf, uint32_t stores,
+                         spamm_mat** out) {
+  if (!ctx || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  *out = nullptr;
+  if (!dense || n < 1 || ld < n || !leaf_ok(leaf)) return fail(c, SPAMM_EINVAL, "bad build arguments");
+  if (stores == 0 || (stores & ~7u)) return fail(c, SPAMM_EINVAL, "bad store mask");
+  std::unique_ptr<spamm_mat> m;
+  spamm_status st = new_matrix(c, n, leaf, m);
+  if (st != SPAMM_OK) return st;
+  const int64_t G2 = int64_t(m->G) * m->G;
+  RegionP flag, total, scratch, nf;
+  ALLOC(flag, G2 * 4, "flags");
+  ALLOC(nf, 256, "flags");
+  const size_t sb = scan_scratch_bytes(G2);
+  ALLOC(scratch, sb, "scan scratch");
+  int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
+  SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
+  SPAMM_HIP(c, launch_build_scan_dense(c->stream, dense, n, ld, leaf, m->G, P<double>(m->norms) + level_offset(m->L),
+                                       P<int32_t>(flag), P<int32_t>(nf)));
+  SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  struct {
+    int32_t nf;
+    int32_t pad[15];
+    int64_t total;
+  } hb;
+  st = download(c, &hb, nf->ptr(), sizeof(hb));
+  if (st != SPAMM_OK) return st;
+  if (hb.nf) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input matrix");
+  m->nonnull = hb.total;
+  m->store = std::make_shared<Store>();
+  st = alloc_store(c, *m->store, hb.total, leaf, stores);
+  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
+  SPAMM_HIP(c, launch_copy_dense_leaves(c->stream, dense, n, ld, leaf, hb.total, P<int32_t>(m->store->keys),
+                                        P<double>(m->store->f64), P<float>(m->store->f32),
+                                        P<uint16_t>(m->store->bf16hi), P<uint16_t>(m->store->bf16lo)));
+  return finish_build(c, m, out);
+}
+
+spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t nblocks, const int32_t* coords,
+                                const double* data, uint32_t stores, spamm_mat** out) {
+  if (!ctx || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  *out = nullptr;
+  if (n < 1 || !leaf_ok(leaf) || nblocks < 0 || (nblocks > 0 && (!coords || !data)))
+    return fail(c, SPAMM_EINVAL, "bad build_blocks arguments");
+  if (stores == 0 || (stores & ~7u)) return fail(c, SPAMM_EINVAL, "bad store mask");
+  if (nblocks > INT32_MAX) return fail(c, SPAMM_EINVAL, "too many blocks");
+  std::unique_ptr<spamm_mat> m;
+  spamm_status st = new_matrix(c, n, leaf, m);
+  if (st != SPAMM_OK) return st;
+  const int64_t G2 = int64_t(m->G) * m->G;
+  RegionP flag, src, scratch, nf;
+  ALLOC(flag, G2 * 4, "flags");
+  ALLOC(src, G2 * 4, "block index");
+  ALLOC(nf, 256, "flags");
+  const size_t sb = scan_scratch_bytes(G2);
+  ALLOC(scratch, sb, "scan scratch");
+  int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
+  SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
+  SPAMM_HIP(c, launch_fill_i32(c->stream, P<int32_t>(src), G2, -1));
+  SPAMM_HIP(c, launch_blocks_scatter(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
+                                     P<int32_t>(nf)));
+  SPAMM_HIP(c, launch_blocks_scan(c->stream, n, leaf, m->G, data, P<int32_t>(src),
+                                  P<double>(m->norms) + level_offset(m->L), P<int32_t>(flag), P<int32_t>(nf)));
+  SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  struct {
+    int32_t err;
+    int32_t pad[15];
+    int64_t total;
+  } hb;
+  st = download(c, &hb, nf->ptr(), sizeof(hb));
+  if (st != SPAMM_OK) return st;
+  if (hb.err & 1) return fail(c, SPAMM_EINVAL, "block coordinate outside the matrix");
+  if (hb.err & 2) return fail(c, SPAMM_EINVAL, "block coordinate listed twice");
+  if (hb.err & 4) return fail(c, SPAMM_EINVAL, "non-zero entry past row/column n");
+  if (hb.err & 8) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input blocks");
+  m->nonnull = hb.total;
+  m->store = std::make_shared<Store>();
+  st = alloc_store(c, *m->store, hb.total, leaf, stores);
+  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
+  SPAMM_HIP(c, launch_copy_block_leaves(c->stream, n, leaf, hb.total, P<int32_t>(m->store->keys), P<int32_t>(src),
+                                        data, P<double>(m->store->f64), P<float>(m->store->f32),
+                                        P<uint16_t>(m->store->bf16hi), P<uint16_t>(m->store->bf16lo)));
+  return finish_build(c, m, out);
+}
+
+spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out, double* dropped_sq) {
+  if (!ctx || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  *out = nullptr;
+  if (!in || in->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
+  if (!tau_ok(tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
+  std::unique_ptr<spamm_mat> m;
+  RegionP res;
+  spamm_status st = truncate_impl(c, in, tau, m, res);
+  if (st != SPAMM_OK) return st;
+  double hr[2];
+  st = download(c, hr, res->ptr(), sizeof(hr));
+  if (st != SPAMM_OK) return st;
+  if (dropped_sq) *dropped_sq = hr[0];
+  m->nonnull = (in->nonnull >= 0) ? in->nonnull - int64_t(hr[1]) : -1;
+  c->live_handles++;
+  *out = m.release();
+  return SPAMM_OK;
+}
+
+spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_request* reqs, spamm_mat** C_out,
+                                  spamm_stats* st_out) {
+  if (!ctx) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (count < 0 || (count > 0 && (!reqs || !C_out))) return fail(c, SPAMM_EINVAL, "bad batch arguments");
+  for (int r = 0; r < count; ++r) C_out[r] = nullptr;
+  if (count == 0) return SPAMM_OK;
+
+  // ---- validate
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    if (!q.A || !q.B || q.A->ctx != c || q.B->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
+    if (q.A->n != q.B->n || q.A->bs != q.B->bs) return fail(c, SPAMM_ESHAPE, "A and B differ in n or leaf size");
+    if (!tau_ok(q.tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
+    if (q.mode < 0 || q.mode > 2) return fail(c, SPAMM_EINVAL, "bad mode");
+    if (q.prec < 0 || q.prec > 3) return fail(c, SPAMM_EINVAL, "bad precision");
+    if (!gemm_supported(q.prec, q.A->bs)) return fail(c, SPAMM_EUNSUPPORTED, "precision/leaf size not built");
+    if (q.ep) {
+      if (q.ep->D && (q.ep->D->ctx != c)) return fail(c, SPAMM_EINVAL, "bad epilogue matrix");
+      if (q.ep->D && (q.ep->D->n != q.A->n || q.ep->D->bs != q.A->bs))
+        return fail(c, SPAMM_ESHAPE, "D differs in n or leaf size");
+      if (!std::isfinite(q.ep->alpha) || !std::isfinite(q.ep->beta))
+        return fail(c, SPAMM_EINVAL, "alpha/beta must be finite");
+    }
+  }
+
+  // ---- truncations (shared within the batch per (matrix, tau))
+  std::map<std::pair<const spamm_mat*, uint64_t>, std::pair<std::unique_ptr<spamm_mat>, RegionP>> trunc;
+  std::vector<spamm_mat*> Au(count), Bu(count);
+  std::vector<const double*> trA(count, nullptr), trB(count, nullptr);
+  auto get_trunc = [&](const spamm_mat* m, double tau, spamm_mat*& o, const double*& res) -> spamm_status {
+    uint64_t bits;
+    std::memcpy(&bits, &tau, 8);
+    auto key = std::make_pair(m, bits);
+    auto it = trunc.find(key);
+    if (it == trunc.end()) {
+      std::unique_ptr<spamm_mat> t;
+      RegionP rr;
+      spamm_status st = truncate_impl(c, m, tau, t, rr);
+      if (st != SPAMM_OK) return st;
+      it = trunc.emplace(key, std::make_pair(std::move(t), rr)).first;
+    }
+    o = it->second.first.get();
+    res = P<double>(it->second.second);
+    return SPAMM_OK;
+  };
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    if (q.mode == SPAMM_SPAMM) {
+      Au[r] = const_cast<spamm_mat*>(q.A);
+      Bu[r] = const_cast<spamm_mat*>(q.B);
+    } else {
+      spamm_status st = get_trunc(q.A, q.tau, Au[r], trA[r]);
+      if (st != SPAMM_OK) return st;
+      st = get_trunc(q.B, q.tau, Bu[r], trB[r]);
+      if (st != SPAMM_OK) return st;
+    }
+    spamm_status st = ensure_prep(c, Au[r]);
+    if (st != SPAMM_OK) return st;
+    st = ensure_prep(c, Bu[r]);
+    if (st != SPAMM_OK) return st;
+    st = ensure_store(c, *Au[r]->store, store_for_prec(q.prec));
+    if (st != SPAMM_OK) return st;
+    st = ensure_store(c, *Bu[r]->store, store_for_prec(q.prec));
+    if (st != SPAMM_OK) return st;
+    if (q.ep && q.ep->D) {
+      st = ensure_store(c, *q.ep->D->store, q.prec == SPAMM_F64 ? SPAMM_STORE_F64 : SPAMM_STORE_F32);
+      if (st != SPAMM_OK) return st;
+    }
+  }
+
+  // ---- descriptors and counting pass
+  std::vector<ReqDev> rd(count);
+  int64_t total_c = 0;
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    ReqDev& d = rd[r];
+    std::memset(&d, 0, sizeof(d));
+    auto md = [](spamm_mat* m) {
+      MatDev x;
+      x.slot = P<int32_t>(m->slot);
+      x.leafnorm = P<double>(m->norms) + level_offset(m->L);
+      x.rm_sqrt = P<double>(m->rm_sqrt);
+      x.rm_slot = P<int32_t>(m->rm_slot);
+      x.cm_sqrt = P<double>(m->cm_sqrt);
+      x.cm_slot = P<int32_t>(m->cm_slot);
+      x.ranges = P<int32_t>(m->ranges);
+      x.G = m->G;
+      x.L = m->L;
+      return x;
+    };
+    d.A = md(Au[r]);
+    d.B = md(Bu[r]);
+    d.slotD = (q.ep && q.ep->D) ? P<int32_t>(q.ep->D->slot) : nullptr;
+    d.tau = q.tau;
+    d.use_norms = q.mode != SPAMM_TRUNCMUL;
+    d.G = q.A->G;
+    d.L = q.A->L;
+    d.bs = q.A->bs;
+    d.cbase = total_c;
+    d.prec = q.prec;
+    total_c += int64_t(d.G) * d.G;
+  }
+  RegionP reqd, packed, scanned, bnd_all, cand_all, scan_scr, totals;
+  ALLOC(reqd, count * sizeof(ReqDev), "request table");
+  ALLOC(packed, total_c * 8, "counts");
+  ALLOC(scanned, (total_c + 1) * 8, "offsets");
+  ALLOC(bnd_all, total_c * 8, "bounds");
+  ALLOC(cand_all, total_c * 4, "candidates");
+  const size_t ssb = scan_scratch_bytes(total_c);
+  ALLOC(scan_scr, ssb, "scan scratch");
+  ALLOC(totals, count * sizeof(ReqTotals), "totals");
+  spamm_status st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
+  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, launch_prune_count(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(packed), P<double>(bnd_all),
+                                  P<int32_t>(cand_all)));
+  SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
+  SPAMM_HIP(c, launch_gather_totals(c->stream, P<ReqDev>(reqd), count, P<int64_t>(scanned), P<ReqTotals>(totals)));
+  std::vector<ReqTotals> ht(count);
+  st = download(c, ht.data(), totals->ptr(), count * sizeof(ReqTotals));
+  if (st != SPAMM_OK) return st;
+
+  // ---- allocate results; work units grouped by (precision, leaf size)
+  std::vector<std::unique_ptr<spamm_mat>> Cs(count);
+  std::vector<RegionP> cand_r(count), trace_r(count);
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int r = 0; r < count; ++r) groups[{reqs[r].prec, reqs[r].A->bs}].push_back(r);
+  int64_t wu_total = 0;
+  std::vector<std::pair<std::pair<int, int>, std::pair<int64_t, int64_t>>> launches;
+  for (auto& gk : groups) {
+    const int64_t start = wu_total;
+    for (int r : gk.second) {
+      rd[r].wu_base = wu_total;
+      wu_total += ht[r].c_nonnull;
+    }
+    launches.push_back({gk.first, {start, wu_total - start}});
+  }
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    ReqDev& d = rd[r];
+    std::unique_ptr<spamm_mat> C;
+    st = new_matrix(c, q.A->n, q.A->bs, C);
+    if (st != SPAMM_OK) return st;
+    const int64_t G2 = int64_t(C->G) * C->G;
+    const int64_t nk = ht[r].n_kept, cn = ht[r].c_nonnull;
+    C->nonnull = cn;
+    C->n_kept = nk;
+    C->store = std::make_shared<Store>();
+    st = alloc_store(c, *C->store, cn, C->bs, q.prec == SPAMM_F64 ? SPAMM_STORE_F64 : SPAMM_STORE_F32);
+    if (st != SPAMM_OK) return st;
+    ALLOC(C->plan_off, (G2 + 1) * 8, "plan offsets");
+    ALLOC(C->plan_pairs, std::max<int64_t>(nk, 1) * 8, "plan pairs");
+    ALLOC(C->plan_bnd, G2 * 8, "skipped bounds");
+    ALLOC(cand_r[r], G2 * 4, "candidate counts");
+    ALLOC(trace_r[r], int64_t(C->G) * 8, "trace parts");
+    C->plan_Astore = Au[r]->store;
+    C->plan_Bstore = Bu[r]->store;
+    d.pairs = P<int2>(C->plan_pairs);
+    d.off = P<int64_t>(C->plan_off);
+    d.cslot = P<int32_t>(C->slot);
+    d.ckeys = P<int32_t>(C->store->keys);
+    d.cnorm = P<double>(C->norms);
+    d.bnd = P<double>(C->plan_bnd);
+    d.ncand = P<int32_t>(cand_r[r]);
+    d.trace_part = P<double>(trace_r[r]);
+    d.cstore = q.prec == SPAMM_F64 ? C->store->f64->ptr() : C->store->f32->ptr();
+    const Store& as = *Au[r]->store;
+    const Store& bs = *Bu[r]->store;
+    switch (q.prec) {
+      case SPAMM_F64:
+        d.Astore = as.f64->ptr();
+        d.Bstore = bs.f64->ptr();
+        break;
+      case SPAMM_F32:
+        d.Astore = as.f32->ptr();
+        d.Bstore = bs.f32->ptr();
+        break;
+      default:
+        d.Astore = as.bf16hi->ptr();
+        d.Bstore = bs.bf16hi->ptr();
+        d.Astore_lo = as.bf16lo->ptr();
+        d.Bstore_lo = bs.bf16lo->ptr();
+    }
+    if (q.ep) {
+      d.use_ep = 1;
+      d.alpha = q.ep->alpha;
+      d.beta = q.ep->beta;
+      if (q.ep->D) {
+        d.Dslot = P<int32_t>(q.ep->D->slot);
+        d.Dstore = q.prec == SPAMM_F64 ? q.ep->D->store->f64->ptr() : q.ep->D->store->f32->ptr();
+      } else {
+        // alpha scaling only: an epilogue matrix with no leaves
+        d.Dslot = nullptr;
+      }
+    } else {
+      d.alpha = 1.0;
+      d.beta = 0.0;
+    }
+    Cs[r] = std::move(C);
+  }
+  RegionP wus, queue;
+  ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
+  ALLOC(queue, 256, "queue counter");
+  st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
+  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned), P<double>(bnd_all),
+                                 P<int32_t>(cand_all), P<WorkUnit>(wus)));
+  for (auto& l : launches) {
+    SPAMM_HIP(c, launch_gemm(c->stream, l.first.first, l.first.second, P<ReqDev>(reqd), P<WorkUnit>(wus),
+                             l.second.first, l.second.second, P<int32_t>(queue), c->n_cu));
+  }
+  {
+    std::vector<double*> nv;
+    std::vector<int> lv;
+    for (int r = 0; r < count; ++r) {
+      nv.push_back(P<double>(Cs[r]->norms));
+      lv.push_back(Cs[r]->L);
+    }
+    st = pyramids(c, nv, lv);
+    if (st != SPAMM_OK) return st;
+  }
+
+  // ---- statistics
+  if (st_out) {
+    RegionP sd;
+    ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
+    SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, P<ReqStatsDev>(sd)));
+    std::vector<ReqStatsDev> hs(count);
+    st = download(c, hs.data(), sd->ptr(), count * sizeof(ReqStatsDev));
+    if (st != SPAMM_OK) return st;
+    for (int r = 0; r < count; ++r) {
+      const spamm_request& q = reqs[r];
+      spamm_stats& o = st_out[r];
+      std::memset(&o, 0, sizeof(o));
+      o.n_kept = ht[r].n_kept;
+      o.c_nonnull = ht[r].c_nonnull;
+      o.n_candidates = hs[r].n_candidates;
+      o.flops = 2.0 * double(q.A->bs) * q.A->bs * q.A->bs * double(ht[r].n_kept);
+      o.B1 = q.mode == SPAMM_TRUNCMUL ? 0.0 : hs[r].B1;
+      o.B2 = q.mode == SPAMM_TRUNCMUL ? 0.0 : std::sqrt(hs[r].B2sq);
+      o.trace = hs[r].trace;
+      o.normC = std::sqrt(hs[r].normC_sq);
+      double roots[4] = {0, 0, 0, 0}, tr[4] = {0, 0, 0, 0};
+      st = download(c, &roots[0], q.A->norms->ptr(), 8);
+      if (st != SPAMM_OK) return st;
+      st = download(c, &roots[1], q.B->norms->ptr(), 8);
+      if (st != SPAMM_OK) return st;
+      st = download(c, &roots[2], Au[r]->norms->ptr(), 8);
+      if (st != SPAMM_OK) return st;
+      if (trA[r]) {
+        st = download(c, &tr[0], trA[r], 8);
+        if (st != SPAMM_OK) return st;
+      }
+      if (trB[r]) {
+        st = download(c, &tr[1], trB[r], 8);
+        if (st != SPAMM_OK) return st;
+      }
+      o.normA = std::sqrt(roots[0]);
+      o.normB = std::sqrt(roots[1]);
+      o.normA_used = std::sqrt(roots[2]);
+      o.dA = std::sqrt(tr[0]);
+      o.dB = std::sqrt(tr[1]);
+      if (q.mode == SPAMM_SPAMM) o.err_bound = o.B2;
+      else if (q.mode == SPAMM_TRUNCMUL) o.err_bound = o.dA * o.normB + o.normA_used * o.dB;
+      else o.err_bound = o.dA * o.normB + o.normA_used * o.dB + o.B2;
+    }
+  }
+  for (int r = 0; r < count; ++r) {
+    c->live_handles++;
+    C_out[r] = Cs[r].release();
+  }
+  return SPAMM_OK;
+}
+
+spamm_status spamm_multiply(spamm_ctx* ctx, const spamm_mat* A, const spamm_mat* B, double tau, spamm_mode mode,
+                            spamm_prec prec, const spamm_epilogue* ep, spamm_mat** C, spamm_stats* st) {
+  spamm_request q;
+  q.A = A;
+  q.B = B;
+  q.tau = tau;
+  q.mode = mode;
+  q.prec = prec;
+  q.ep = ep;
+  return spamm_multiply_batch(ctx, 1, &q, C, st);
+}
+
+spamm_status spamm_norms(spamm_ctx* ctx, const spamm_mat* m, int32_t level, double* out, int64_t cap,
+                         int64_t* count) {
+  if (!ctx || !m || !count) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (level < -1 || level > m->L) return fail(c, SPAMM_EINVAL, "bad level");
+  const int64_t off = level < 0 ? 0 : level_offset(level);
+  const int64_t cnt = level < 0 ? pyramid_size(m->L) : (int64_t(1) << (2 * level));
+  *count = cnt;
+  if (!out || cap < cnt) return fail(c, SPAMM_EINVAL, "output too small");
+  return download(c, out, P<double>(m->norms) + off, cnt * 8);
+}
+
+spamm_status spamm_kept(spamm_ctx* ctx, const spamm_mat* C, int32_t* ijk, int64_t cap, int64_t* count) {
+  if (!ctx || !C || !count) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (!C->plan_off) return fail(c, SPAMM_EINVAL, "handle has no product plan");
+  *count = C->n_kept;
+  if (!ijk || cap < C->n_kept) return fail(c, SPAMM_EINVAL, "output too small");
+  if (C->n_kept == 0) return SPAMM_OK;
+  RegionP tmp;
+  ALLOC(tmp, C->n_kept * 12, "kept triples");
+  SPAMM_HIP(c, launch_decode_kept(c->stream, C->G, C->n_kept, P<int64_t>(C->plan_off), nullptr,
+                                  P<int2>(C->plan_pairs), P<int32_t>(C->plan_Astore->keys), nullptr, P<int32_t>(tmp)));
+  return download(c, ijk, tmp->ptr(), C->n_kept * 12);
+}
+
+spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C, double* out, int64_t cap) {
+  if (!ctx || !C || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (!C->plan_bnd) return fail(c, SPAMM_EINVAL, "handle has no product plan");
+  const int64_t G2 = int64_t(C->G) * C->G;
+  if (cap < G2) return fail(c, SPAMM_EINVAL, "output too small");
+  return download(c, out, C->plan_bnd->ptr(), G2 * 8);
+}
+
+spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out, int64_t ld) {
+  if (!ctx || !m || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (ld < m->n) return fail(c, SPAMM_EINVAL, "ld < n");
+  if (!m->store || (!m->store->f64 && !m->store->f32)) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 copy");
+  SPAMM_HIP(c, launch_to_dense(c->stream, m->n, m->bs, m->G, P<int32_t>(m->slot), P<double>(m->store->f64),
+                               m->store->f64 ? nullptr : P<float>(m->store->f32), out, ld));
+  return SPAMM_OK;
+}
+
+spamm_status spamm_mat_info_get(const spamm_mat* m, spamm_mat_info* out) {
+  if (!m || !out) return SPAMM_EINVAL;
+  out->n = m->n;
+  out->leaf = m->bs;
+  out->G = m->G;
+  out->L = m->L;
+  out->nonnull = m->nonnull;
+  out->stores = m->store ? m->store->mask() : 0u;
+  out->has_plan = m->plan_off ? 1 : 0;
+  out->n_kept = m->n_kept;
+  out->device_bytes = m->device_bytes();
+  return SPAMM_OK;
+}
+
+spamm_status spamm_release(spamm_ctx* ctx, spamm_mat* m) {
+  if (!m) return SPAMM_OK;
+  if (!ctx || m->ctx != &ctx->c) return SPAMM_EINVAL;
+  ctx->c.live_handles--;
+  delete m;
+  return SPAMM_OK;
+}
+
+}  // extern "C"

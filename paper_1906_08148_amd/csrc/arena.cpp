@@ -1,0 +1,78 @@
+// First-fit sub-allocator over the caller's device arena.
+#include <algorithm>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace spamm {
+
+void Arena::init(char* base, size_t bytes) {
+  base_ = base;
+  size_ = bytes;
+  used_ = 0;
+  free_.clear();
+  free_[0] = bytes;
+}
+
+size_t Arena::alloc(size_t bytes, size_t align) {
+  if (bytes == 0) bytes = align;
+  bytes = (bytes + align - 1) / align * align;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    const size_t off = it->first, len = it->second;
+    const size_t start = (off + align - 1) / align * align;
+    const size_t lead = start - off;
+    if (len < lead + bytes) continue;
+    free_.erase(it);
+    if (lead) free_[off] = lead;
+    const size_t tail = len - lead - bytes;
+    if (tail) free_[start + bytes] = tail;
+    used_ += bytes;
+    return start;
+  }
+  return SIZE_MAX;
+}
+
+void Arena::release(size_t off, size_t bytes) {
+  if (bytes == 0) return;
+  used_ -= bytes;
+  auto next = free_.lower_bound(off);
+  size_t start = off, len = bytes;
+  if (next != free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      start = prev->first;
+      len += prev->second;
+      free_.erase(prev);
+    }
+  }
+  if (next != free_.end() && next->first == off + bytes) {
+    len += next->second;
+    free_.erase(next);
+  }
+  free_[start] = len;
+}
+
+size_t Arena::largest_free() const {
+  size_t best = 0;
+  for (auto& kv : free_) best = std::max(best, kv.second);
+  return best;
+}
+
+Region::~Region() {
+  if (ctx) ctx->arena.release(off, bytes);
+}
+
+void* Region::ptr() const { return ctx->arena.base() + off; }
+
+RegionP Ctx::alloc(size_t bytes) {
+  const size_t rounded = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  const size_t off = arena.alloc(rounded, 256);
+  if (off == SIZE_MAX) return nullptr;
+  auto r = std::make_shared<Region>();
+  r->ctx = this;
+  r->off = off;
+  r->bytes = rounded;
+  return r;
+}
+
+}  // namespace spamm

@@ -1,0 +1,251 @@
+// Internal declarations of the spamm library (host side and kernel launchers).
+// Everything here is private to libspamm.so; the public ABI is include/spamm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/spamm.h"
+
+namespace spamm {
+
+// ---------------------------------------------------------------- arena
+
+// First-fit sub-allocator over one caller-owned device buffer.  Free ranges
+// are kept in an ordered map and coalesced on release.  All reuse is ordered
+// on the context's single stream.
+class Arena {
+ public:
+  void init(char* base, size_t bytes);
+  // Returns offset or SIZE_MAX when no range fits.
+  size_t alloc(size_t bytes, size_t align = 256);
+  void release(size_t off, size_t bytes);
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+  size_t free_bytes() const { return size_ - used_; }
+  size_t largest_free() const;
+  char* base() const { return base_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  size_t used_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct Ctx;
+
+// One arena allocation; freed when the last shared owner drops it.
+struct Region {
+  Ctx* ctx = nullptr;
+  size_t off = 0, bytes = 0;
+  ~Region();
+  void* ptr() const;
+};
+using RegionP = std::shared_ptr<Region>;
+
+// Leaf storage shared by a matrix and the matrices derived from it.
+struct Store {
+  int64_t nleaf = 0;  // slots in the store
+  int32_t bs = 0;
+  RegionP keys;       // int32[nleaf]: Morton key of each stored leaf
+  RegionP f64, f32, bf16hi, bf16lo;
+  uint32_t mask() const {
+    return (f64 ? SPAMM_STORE_F64 : 0u) | (f32 ? SPAMM_STORE_F32 : 0u) |
+           (bf16hi ? SPAMM_STORE_BF16 : 0u);
+  }
+};
+using StoreP = std::shared_ptr<Store>;
+
+}  // namespace spamm
+
+// The public opaque types.
+struct spamm_mat {
+  spamm::Ctx* ctx = nullptr;
+  int64_t n = 0;
+  int32_t bs = 0, G = 0, L = 0;
+  int64_t nonnull = -1;     // -1: not read back yet
+  spamm::StoreP store;
+  spamm::RegionP slot;      // int32[G*G]  Morton -> slot, -1 null
+  spamm::RegionP norms;     // double[(4^(L+1)-1)/3], level l at (4^l-1)/3
+  spamm::RegionP rm_sqrt;   // double[G*G] row-major sqrt(norm), -1 null
+  spamm::RegionP rm_slot;   // int32[G*G]  row-major slot
+  spamm::RegionP cm_sqrt;   // double[G*G] [c*G + r] = leaf (r, c)
+  spamm::RegionP cm_slot;   // int32[G*G]
+  spamm::RegionP ranges;    // int32[4*G]: row_lo, row_hi, col_lo, col_hi
+  // set on products only
+  spamm::RegionP plan_off;  // int64[G*G+1] local offsets into plan_pairs
+  spamm::RegionP plan_pairs;// int2[n_kept]  (slotA, slotB)
+  spamm::RegionP plan_bnd;  // double[G*G] skipped bound b per C leaf
+  spamm::StoreP plan_Astore, plan_Bstore;  // keys decode k from slotA
+  int64_t n_kept = -1;
+  size_t device_bytes() const;
+};
+
+namespace spamm {
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Arena arena;
+  std::string last_error;
+  // pinned host staging
+  void* host_stage = nullptr;
+  size_t host_stage_bytes = 0;
+  int n_cu = 256;
+  std::map<uint64_t, int> tuned;  // reserved for autotune results
+  int live_handles = 0;
+  RegionP alloc(size_t bytes);    // nullptr on exhaustion
+  void* stage(size_t bytes);      // grow pinned staging if needed
+};
+
+// status helpers
+spamm_status fail(Ctx* c, spamm_status s, const std::string& msg);
+#define SPAMM_HIP(ctx, expr)                                                   \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return ::spamm::fail((ctx), SPAMM_EDEVICE,                               \
+                           std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+__host__ __device__ inline int64_t level_offset(int l) { return ((int64_t(1) << (2 * l)) - 1) / 3; }
+__host__ __device__ inline int64_t pyramid_size(int L) { return level_offset(L + 1); }
+
+// ---------------------------------------------------------------- device descs
+
+// One matrix as seen by the batched kernels.
+struct MatDev {
+  const int32_t* slot;     // Morton
+  const double* leafnorm;  // Morton, leaf level
+  const double* rm_sqrt;
+  const int32_t* rm_slot;
+  const double* cm_sqrt;
+  const int32_t* cm_slot;
+  const int32_t* ranges;
+  int32_t G, L;
+};
+
+// Pyramid job: reduce leaf norms (level L) of one matrix up to the root.
+struct PyrJob {
+  double* norms;  // full pyramid buffer
+  int32_t L;
+  int32_t sub_levels;   // levels reduced inside one subtree workgroup
+  int64_t block_base;   // first workgroup index of this job
+};
+
+// One multiply request inside a batch.
+struct ReqDev {
+  MatDev A, B;
+  const int32_t* slotD;  // epilogue matrix slot map (Morton) or nullptr
+  double tau;
+  int32_t use_norms;
+  int32_t G, L, bs;
+  int64_t cbase;          // first global C index of this request
+  // outputs (set after sizing)
+  int2* pairs;
+  int64_t* off;           // G*G+1 local offsets
+  int32_t* cslot;         // C slot map (Morton)
+  int32_t* ckeys;         // C keys [c_nonnull]
+  double* cnorm;          // C pyramid buffer (leaf level written by GEMM)
+  double* bnd;            // skipped bound per C leaf
+  int32_t* ncand;         // candidate count per C leaf
+  double* trace_part;     // G entries (diagonal leaves)
+  void* cstore;           // C leaf store (FP32 or FP64)
+  // GEMM operands in the request's precision
+  const void* Astore;
+  const void* Bstore;
+  const void* Astore_lo;  // split-BF16 lo parts
+  const void* Bstore_lo;
+  const void* Dstore;
+  const int32_t* Dslot;
+  double alpha, beta;
+  int64_t wu_base;        // first work unit of this request
+  int32_t prec;
+  int32_t use_ep;         // apply alpha/beta/D in the epilogue
+};
+
+struct WorkUnit {
+  int32_t req;
+  int32_t c;  // Morton index of the C leaf
+};
+
+// Per-request totals read back after the counting pass.
+struct ReqTotals {
+  int64_t n_kept;
+  int64_t c_nonnull;
+};
+
+// Per-request statistics reduced on the device.
+struct ReqStatsDev {
+  double B1, B2sq, trace, normC_sq;
+  int64_t n_candidates;
+  int64_t pad_;
+};
+
+// ---------------------------------------------------------------- launchers
+// (all enqueue on `s`; return hipError_t of the launch)
+
+hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n, int64_t ld,
+                                   int bs, int G, double* leafnorm, int32_t* flag,
+                                   int32_t* nonfinite);
+hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
+                                 const int32_t* coords, const double* data, int32_t* src_of,
+                                 int32_t* errflags);
+hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, const double* data,
+                              const int32_t* src_of, double* leafnorm, int32_t* flag,
+                              int32_t* errflags);
+// exclusive scan of int32 flags -> slot map (flag ? prefix : -1), total -> *total
+hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count,
+                                 int32_t* slot, int64_t* total, void* scratch, size_t scratch_bytes);
+size_t scan_scratch_bytes(int64_t count);
+hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t count,
+                           void* scratch, size_t scratch_bytes);  // exclusive, out[count] = total
+hipError_t launch_slot_keys(hipStream_t s, const int32_t* slot, int64_t G2, int32_t* keys);
+hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
+                                    int bs, int64_t nleaf, const int32_t* keys, double* f64,
+                                    float* f32, uint16_t* bhi, uint16_t* blo);
+hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
+                                    const int32_t* keys, const int32_t* src_of,
+                                    const double* data, double* f64, float* f32,
+                                    uint16_t* bhi, uint16_t* blo);
+hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, const float* f32,
+                               double* o64, float* o32, uint16_t* ohi, uint16_t* olo);
+hipError_t launch_prep(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
+                       double* rm_sqrt, int32_t* rm_slot, double* cm_sqrt, int32_t* cm_slot);
+hipError_t launch_ranges(hipStream_t s, int G, const double* rm_sqrt, const double* cm_sqrt,
+                         int32_t* ranges);
+hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
+                          const std::vector<PyrJob>& jobs_host);
+// truncation
+hipError_t launch_trunc(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
+                        double tau2, int32_t* out_slot, double* out_leafnorm, void* scratch,
+                        size_t scratch_bytes, double* result_dev /* [0]=dropped_sq,[1]=count */);
+size_t trunc_scratch_bytes(int G);
+// prune
+hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+                              int64_t* packed, double* bnd_all, int32_t* cand_all);
+hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq,
+                                const int64_t* scanned, ReqTotals* out);
+hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+                             const int64_t* scanned, const double* bnd_all,
+                             const int32_t* cand_all, WorkUnit* wu);
+// gemm over work units [wu0, wu0 + nwu)
+hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
+                       int64_t wu0, int64_t nwu, int32_t* queue, int n_cu);
+bool gemm_supported(int prec, int bs);
+hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
+hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, ReqStatsDev* out);
+hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
+                           const double* f64, const float* f32, double* out, int64_t ld);
+hipError_t launch_decode_kept(hipStream_t s, int G, int64_t n_kept, const int64_t* off,
+                              const int32_t* cslot_unused, const int2* pairs,
+                              const int32_t* akeys, const int32_t* bkeys, int32_t* ijk);
+
+}  // namespace spamm

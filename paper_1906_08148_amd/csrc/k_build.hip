@@ -1,0 +1,414 @@
+// Build-time kernels: leaf norms and null flags (Sec. 2, Sec. 4.2, Sec. 4.4),
+// compaction into the Morton-ordered leaf store, derived compute copies, the
+// row/column views used by pruning, and the squared-norm pyramid.
+#include "internal.h"
+#include "kern_common.h"
+
+namespace spamm {
+
+// error bits reported by the block-list build
+constexpr int kErrCoord = 1, kErrDup = 2, kErrPad = 4;
+
+// ---------------------------------------------------------------- leaf scan
+
+// One workgroup per leaf (Morton index = blockIdx): FP64 squared norm (each
+// thread sums its fixed strided share of the leaf, then a fixed tree), the
+// non-zero flag and the non-finite flag.  Reads the dense input once.
+__global__ void __launch_bounds__(256) k_build_scan_dense(const double* __restrict__ dense,
+                                                          int64_t n, int64_t ld, int bs,
+                                                          double* __restrict__ leafnorm,
+                                                          int32_t* __restrict__ flag,
+                                                          int32_t* __restrict__ nonfinite) {
+  __shared__ double red[4];
+  const uint32_t m = blockIdx.x;
+  uint32_t r, c;
+  demorton(m, r, c);
+  const int64_t r0 = int64_t(r) * bs, c0 = int64_t(c) * bs;
+  double s = 0.0;
+  int nz = 0, nf = 0;
+  if (r0 < n && c0 < n) {
+    const int rows = int(min<int64_t>(bs, n - r0)), cols = int(min<int64_t>(bs, n - c0));
+    for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+      const int rr = e / bs, cc = e % bs;
+      if (rr < rows && cc < cols) {
+        const double a = dense[(r0 + rr) * ld + c0 + cc];
+        const double sq = a * a;
+        s += sq;
+        nz |= (a != 0.0);
+        nf |= !isfinite(a);
+      }
+    }
+  }
+  s = block_sum_f64(s, red);
+  nz = __syncthreads_or(nz);
+  nf = __syncthreads_or(nf);
+  if (threadIdx.x == 0) {
+    leafnorm[m] = nz ? s : 0.0;
+    flag[m] = nz;
+    if (nf) atomicOr(nonfinite, 1);
+  }
+}
+
+hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n, int64_t ld,
+                                   int bs, int G, double* leafnorm, int32_t* flag,
+                                   int32_t* nonfinite) {
+  hipLaunchKernelGGL(k_build_scan_dense, dim3(uint32_t(G) * uint32_t(G)), dim3(256), 0, s, dense,
+                     n, ld, bs, leafnorm, flag, nonfinite);
+  return hipGetLastError();
+}
+
+// Block list: place block t at its Morton slot; flag bad and duplicate coords.
+__global__ void k_blocks_scatter(int64_t n, int bs, int64_t nblocks, const int32_t* __restrict__ coords,
+                                 int32_t* __restrict__ src_of, int32_t* __restrict__ err) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nblocks) return;
+  const int64_t gmax = (n + bs - 1) / bs;
+  const int32_t I = coords[2 * t], J = coords[2 * t + 1];
+  if (I < 0 || J < 0 || I >= gmax || J >= gmax) {
+    atomicOr(err, kErrCoord);
+    return;
+  }
+  const uint32_t m = morton(uint32_t(I), uint32_t(J));
+  const int32_t old = atomicCAS(&src_of[m], -1, int32_t(t));
+  if (old != -1) atomicOr(err, kErrDup);
+}
+
+hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
+                                 const int32_t* coords, const double* data, int32_t* src_of,
+                                 int32_t* errflags) {
+  (void)G;
+  (void)data;
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_blocks_scatter, dim3(uint32_t((nblocks + 255) / 256)), dim3(256), 0, s, n,
+                     bs, nblocks, coords, src_of, errflags);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, const double* __restrict__ data,
+                                                     const int32_t* __restrict__ src_of,
+                                                     double* __restrict__ leafnorm,
+                                                     int32_t* __restrict__ flag,
+                                                     int32_t* __restrict__ err) {
+  __shared__ double red[4];
+  const uint32_t m = blockIdx.x;
+  const int32_t t = src_of[m];
+  double s = 0.0;
+  int nz = 0, nf = 0, pad = 0;
+  if (t >= 0) {
+    uint32_t r, c;
+    demorton(m, r, c);
+    const int64_t rows = min<int64_t>(bs, n - int64_t(r) * bs);
+    const int64_t cols = min<int64_t>(bs, n - int64_t(c) * bs);
+    const double* blk = data + int64_t(t) * bs * bs;
+    for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+      const int rr = e / bs, cc = e % bs;
+      const double a = blk[e];
+      if (rr < rows && cc < cols) {
+        const double sq = a * a;
+        s += sq;
+        nz |= (a != 0.0);
+        nf |= !isfinite(a);
+      } else {
+        pad |= (a != 0.0);
+      }
+    }
+  }
+  s = block_sum_f64(s, red);
+  nz = __syncthreads_or(nz);
+  nf = __syncthreads_or(nf);
+  pad = __syncthreads_or(pad);
+  if (threadIdx.x == 0) {
+    leafnorm[m] = nz ? s : 0.0;
+    flag[m] = nz;
+    if (nf) atomicOr(err, 8);
+    if (pad) atomicOr(err, kErrPad);
+  }
+}
+
+hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, const double* data,
+                              const int32_t* src_of, double* leafnorm, int32_t* flag,
+                              int32_t* errflags) {
+  hipLaunchKernelGGL(k_blocks_scan, dim3(uint32_t(G) * uint32_t(G)), dim3(256), 0, s, n, bs, data,
+                     src_of, leafnorm, flag, errflags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- compaction
+
+__global__ void k_slot_keys(const int32_t* __restrict__ slot, int64_t G2, int32_t* __restrict__ keys) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= G2) return;
+  const int32_t sl = slot[m];
+  if (sl >= 0) keys[sl] = int32_t(m);
+}
+
+hipError_t launch_slot_keys(hipStream_t s, const int32_t* slot, int64_t G2, int32_t* keys) {
+  hipLaunchKernelGGL(k_slot_keys, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, slot, G2, keys);
+  return hipGetLastError();
+}
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// Write element e of leaf slot `sl` in every requested copy.  The split-BF16
+// pair is hi = bf16(x32), lo = bf16(x32 - hi), with x32 the FP32 rounding.
+__device__ __forceinline__ void store_leaf_elem(int64_t idx, double a, double* f64, float* f32,
+                                                uint16_t* bhi, uint16_t* blo) {
+  if (f64) f64[idx] = a;
+  const float x = float(a);
+  if (f32) f32[idx] = x;
+  if (bhi) {
+    const uint16_t h = f32_to_bf16(x);
+    bhi[idx] = h;
+    blo[idx] = f32_to_bf16(x - bf16_to_f32(h));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_dense_leaves(const double* __restrict__ dense, int64_t n,
+                                                           int64_t ld, int bs,
+                                                           const int32_t* __restrict__ keys,
+                                                           double* f64, float* f32, uint16_t* bhi,
+                                                           uint16_t* blo) {
+  const int64_t sl = blockIdx.x;
+  uint32_t r, c;
+  demorton(uint32_t(keys[sl]), r, c);
+  const int64_t r0 = int64_t(r) * bs, c0 = int64_t(c) * bs;
+  const int64_t rows = min<int64_t>(bs, n - r0), cols = min<int64_t>(bs, n - c0);
+  const int64_t base = sl * bs * bs;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+    const int rr = e / bs, cc = e % bs;
+    const double a = (rr < rows && cc < cols) ? dense[(r0 + rr) * ld + c0 + cc] : 0.0;
+    store_leaf_elem(base + e, a, f64, f32, bhi, blo);
+  }
+}
+
+hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
+                                    int bs, int64_t nleaf, const int32_t* keys, double* f64,
+                                    float* f32, uint16_t* bhi, uint16_t* blo) {
+  if (nleaf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_dense_leaves, dim3(uint32_t(nleaf)), dim3(256), 0, s, dense, n, ld, bs,
+                     keys, f64, f32, bhi, blo);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_copy_block_leaves(int bs, const int32_t* __restrict__ keys,
+                                                           const int32_t* __restrict__ src_of,
+                                                           const double* __restrict__ data,
+                                                           double* f64, float* f32, uint16_t* bhi,
+                                                           uint16_t* blo) {
+  const int64_t sl = blockIdx.x;
+  const int32_t t = src_of[keys[sl]];
+  const double* blk = data + int64_t(t) * bs * bs;
+  const int64_t base = sl * bs * bs;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) store_leaf_elem(base + e, blk[e], f64, f32, bhi, blo);
+}
+
+hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
+                                    const int32_t* keys, const int32_t* src_of, const double* data,
+                                    double* f64, float* f32, uint16_t* bhi, uint16_t* blo) {
+  (void)n;
+  if (nleaf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_block_leaves, dim3(uint32_t(nleaf)), dim3(256), 0, s, bs, keys, src_of,
+                     data, f64, f32, bhi, blo);
+  return hipGetLastError();
+}
+
+// Derive missing compute copies from the best copy present (FP64 if any).
+__global__ void k_derive_store(int64_t count, const double* __restrict__ f64,
+                               const float* __restrict__ f32, double* o64, float* o32,
+                               uint16_t* ohi, uint16_t* olo) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double a = f64 ? f64[i] : double(f32[i]);
+    store_leaf_elem(i, a, o64, o32, ohi, olo);
+  }
+}
+
+hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, const float* f32,
+                               double* o64, float* o32, uint16_t* ohi, uint16_t* olo) {
+  if (count == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_derive_store, dim3(uint32_t(blocks)), dim3(256), 0, s, count, f64, f32, o64,
+                     o32, ohi, olo);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pruning views
+
+// Row-major and column-major copies of sqrt(leaf norm) (-1 for null) and of
+// the slot map, so that pruning walks an A row and a B column contiguously.
+__global__ void k_prep(int G, const int32_t* __restrict__ slot, const double* __restrict__ leafnorm,
+                       double* __restrict__ rm_sqrt, int32_t* __restrict__ rm_slot,
+                       double* __restrict__ cm_sqrt, int32_t* __restrict__ cm_slot) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= int64_t(G) * G) return;
+  uint32_t r, c;
+  demorton(uint32_t(m), r, c);
+  const int32_t sl = slot[m];
+  const double v = sl >= 0 ? sqrt(leafnorm[m]) : -1.0;
+  rm_sqrt[int64_t(r) * G + c] = v;
+  rm_slot[int64_t(r) * G + c] = sl;
+  cm_sqrt[int64_t(c) * G + r] = v;
+  cm_slot[int64_t(c) * G + r] = sl;
+}
+
+hipError_t launch_prep(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
+                       double* rm_sqrt, int32_t* rm_slot, double* cm_sqrt, int32_t* cm_slot) {
+  const int64_t G2 = int64_t(G) * G;
+  hipLaunchKernelGGL(k_prep, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, slot, leafnorm,
+                     rm_sqrt, rm_slot, cm_sqrt, cm_slot);
+  return hipGetLastError();
+}
+
+// Non-null k range of every row (as left operand) and column (as right
+// operand): one wave per row/column.
+__global__ void __launch_bounds__(256) k_ranges(int G, const double* __restrict__ rm_sqrt,
+                                                const double* __restrict__ cm_sqrt,
+                                                int32_t* __restrict__ ranges) {
+  const int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (w >= 2 * G) return;
+  const bool is_col = w >= G;
+  const int idx = is_col ? w - G : w;
+  const double* v = (is_col ? cm_sqrt : rm_sqrt) + int64_t(idx) * G;
+  int lo = G, hi = -1;
+  for (int k = lane_id(); k < G; k += kWave) {
+    if (v[k] >= 0.0) {
+      lo = min(lo, k);
+      hi = max(hi, k);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, __shfl_down(lo, off, kWave));
+    hi = max(hi, __shfl_down(hi, off, kWave));
+  }
+  if (lane_id() == 0) {
+    ranges[(is_col ? 2 : 0) * G + idx] = lo;
+    ranges[(is_col ? 3 : 1) * G + idx] = hi;
+  }
+}
+
+hipError_t launch_ranges(hipStream_t s, int G, const double* rm_sqrt, const double* cm_sqrt,
+                         int32_t* ranges) {
+  const int waves = 2 * G;
+  hipLaunchKernelGGL(k_ranges, dim3(uint32_t((waves + 3) / 4)), dim3(256), 0, s, G, rm_sqrt, cm_sqrt,
+                     ranges);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pyramid
+
+constexpr int kPyrSub = 5;  // a subtree workgroup reduces 4^5 = 1024 leaves
+
+// Reduce `vals` (4^h entries of level `lev`, Morton) in LDS up h levels,
+// writing each level to norms.  Parent = ((c0 + c1) + c2) + c3.
+__device__ void pyr_reduce_lds(double* lds, int h, double* norms, int lev, int64_t first) {
+  int64_t cnt = int64_t(1) << (2 * h);
+  for (int step = 0; step < h; ++step) {
+    const int64_t pc = cnt / 4;
+    for (int64_t p = threadIdx.x; p < pc; p += blockDim.x) {
+      const double v = ((lds[4 * p] + lds[4 * p + 1]) + lds[4 * p + 2]) + lds[4 * p + 3];
+      lds[cnt + p] = v;  // stage after current level
+    }
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < pc; p += blockDim.x) {
+      const double v = lds[cnt + p];
+      lds[p] = v;
+    }
+    __syncthreads();
+    first /= 4;
+    --lev;
+    for (int64_t p = threadIdx.x; p < pc; p += blockDim.x) norms[level_offset(lev) + first + p] = lds[p];
+    cnt = pc;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pyr_sub(const PyrJob* __restrict__ jobs, int njobs) {
+  __shared__ double lds[1024 + 256];
+  int j = 0;
+  while (j + 1 < njobs && int64_t(blockIdx.x) >= jobs[j + 1].block_base) ++j;
+  const PyrJob job = jobs[j];
+  const int64_t w = int64_t(blockIdx.x) - job.block_base;
+  const int h = job.sub_levels;
+  const int64_t cnt = int64_t(1) << (2 * h);
+  const int64_t first = w * cnt;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+    lds[i] = job.norms[level_offset(job.L) + first + i];
+  __syncthreads();
+  pyr_reduce_lds(lds, h, job.norms, job.L, first);
+}
+
+__global__ void __launch_bounds__(256) k_pyr_top(const PyrJob* __restrict__ jobs) {
+  __shared__ double lds[4096 + 1024];
+  const PyrJob job = jobs[blockIdx.x];
+  const int top = job.L - job.sub_levels;  // levels left above the subtrees
+  if (top <= 0) return;
+  const int64_t cnt = int64_t(1) << (2 * top);
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+    lds[i] = job.norms[level_offset(top) + i];
+  __syncthreads();
+  pyr_reduce_lds(lds, top, job.norms, top, 0);
+}
+
+hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
+                          const std::vector<PyrJob>& jobs_host) {
+  if (njobs == 0) return hipSuccess;
+  int64_t blocks = 0;
+  for (auto& jb : jobs_host) blocks += int64_t(1) << (2 * (jb.L - jb.sub_levels));
+  hipLaunchKernelGGL(k_pyr_sub, dim3(uint32_t(blocks)), dim3(256), 0, s, jobs_dev, njobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pyr_top, dim3(uint32_t(njobs)), dim3(256), 0, s, jobs_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dense out
+
+__global__ void __launch_bounds__(256) k_to_dense(int64_t n, int bs, const int32_t* __restrict__ slot,
+                                                  const double* __restrict__ f64,
+                                                  const float* __restrict__ f32, double* out,
+                                                  int64_t ld) {
+  const uint32_t m = blockIdx.x;
+  uint32_t r, c;
+  demorton(m, r, c);
+  const int64_t r0 = int64_t(r) * bs, c0 = int64_t(c) * bs;
+  if (r0 >= n || c0 >= n) return;
+  const int32_t sl = slot[m];
+  const int64_t rows = min<int64_t>(bs, n - r0), cols = min<int64_t>(bs, n - c0);
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+    const int rr = e / bs, cc = e % bs;
+    if (rr < rows && cc < cols) {
+      double v = 0.0;
+      if (sl >= 0) v = f64 ? f64[int64_t(sl) * bs * bs + e] : double(f32[int64_t(sl) * bs * bs + e]);
+      out[(r0 + rr) * ld + c0 + cc] = v;
+    }
+  }
+}
+
+hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
+                           const double* f64, const float* f32, double* out, int64_t ld) {
+  hipLaunchKernelGGL(k_to_dense, dim3(uint32_t(G) * uint32_t(G)), dim3(256), 0, s, n, bs, slot, f64,
+                     f32, out, ld);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(uint32_t((count + 255) / 256)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count) { return launch_fill_i32(s, p, count, 0); }
+
+}  // namespace spamm

@@ -1,0 +1,236 @@
+// Pruning: which leaf products are formed (Alg. 1's norm test with Alg. 2's
+// null rule).  For every C leaf (i, j) one wavefront walks the row i of A and
+// the column j of B over the k range where both have non-null leaves, 64 k at
+// a time, and keeps k when A_ik and B_kj are non-null and (SpAMM, Hybrid)
+// sqrt(s_ik) * sqrt(s_kj) >= tau in FP64.  Because a parent's squared norm is
+// a sum of non-negative terms, every ancestor of a kept triple passes the
+// same test, so this flat test selects exactly the leaf products reached by
+// the recursion of Alg. 1.
+//
+// Counting pass -> LDS-staged exclusive scan over all C leaves of the batch
+// (Morton order) -> fill pass writing the (slotA, slotB) pairs, the C slot
+// map and the GEMM work units.  No atomics: positions come from the scan, so
+// the lists are deterministic.
+#include "internal.h"
+#include "kern_common.h"
+
+namespace spamm {
+
+constexpr int64_t kCntBits = 40;
+constexpr int64_t kCntMask = (int64_t(1) << kCntBits) - 1;
+
+__device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, int nreq, int64_t g) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (reqs[mid].cbase <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct Walk {
+  int64_t rowA, colB;  // offsets of row i in A's rm arrays, column j in B's cm arrays
+  int lo, hi;
+};
+
+__device__ __forceinline__ Walk make_walk(const ReqDev& R, uint32_t i, uint32_t j) {
+  Walk w;
+  const int G = R.G;
+  w.rowA = int64_t(i) * G;
+  w.colB = int64_t(j) * G;
+  w.lo = max(R.A.ranges[i], R.B.ranges[2 * G + j]);
+  w.hi = min(R.A.ranges[G + i], R.B.ranges[3 * G + j]);
+  return w;
+}
+
+__global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
+                                                     int64_t* __restrict__ packed, double* __restrict__ bnd_all,
+                                                     int32_t* __restrict__ cand_all) {
+  const int64_t g = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (g >= total_c) return;
+  const int r = find_req(reqs, nreq, g);
+  const ReqDev& R = reqs[r];
+  const uint32_t c = uint32_t(g - R.cbase);
+  uint32_t i, j;
+  demorton(c, i, j);
+  const Walk w = make_walk(R, i, j);
+  const double tau = R.tau;
+  const bool use_norms = R.use_norms != 0;
+  int64_t cnt = 0, cand = 0;
+  double skipped = 0.0;
+  for (int kb = w.lo; kb <= w.hi; kb += kWave) {
+    const int k = kb + lane_id();
+    double a = -1.0, b = -1.0;
+    if (k <= w.hi) {
+      a = R.A.rm_sqrt[w.rowA + k];
+      b = R.B.cm_sqrt[w.colB + k];
+    }
+    const bool both = (a >= 0.0) && (b >= 0.0);
+    const double p = a * b;
+    const bool keep = both && (!use_norms || p >= tau);
+    cnt += popc64(ballot64(keep));
+    cand += popc64(ballot64(both));
+    if (both && !keep) skipped += p;
+  }
+  skipped = wave_sum_f64(skipped);
+  if (lane_id() == 0) {
+    const bool dflag = R.slotD != nullptr && R.slotD[c] >= 0;
+    const int64_t flag = (cnt > 0 || dflag) ? 1 : 0;
+    packed[g] = (flag << kCntBits) | cnt;
+    bnd_all[g] = skipped;
+    cand_all[g] = int32_t(cand);
+  }
+}
+
+hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int64_t* packed,
+                              double* bnd_all, int32_t* cand_all) {
+  const int64_t blocks = (total_c + 3) / 4;
+  hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, packed,
+                     bnd_all, cand_all);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_totals(const ReqDev* __restrict__ reqs, int nreq, const int64_t* __restrict__ scanned,
+                                ReqTotals* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nreq) return;
+  const ReqDev& R = reqs[r];
+  const int64_t a = scanned[R.cbase], b = scanned[R.cbase + int64_t(R.G) * R.G];
+  out[r].n_kept = (b & kCntMask) - (a & kCntMask);
+  out[r].c_nonnull = (b >> kCntBits) - (a >> kCntBits);
+}
+
+hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, const int64_t* scanned,
+                                ReqTotals* out) {
+  hipLaunchKernelGGL(k_gather_totals, dim3(uint32_t((nreq + 63) / 64)), dim3(64), 0, s, reqs, nreq, scanned, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
+                                                    const int64_t* __restrict__ scanned,
+                                                    const double* __restrict__ bnd_all,
+                                                    const int32_t* __restrict__ cand_all,
+                                                    WorkUnit* __restrict__ wu) {
+  const int64_t g = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (g >= total_c) return;
+  const int r = find_req(reqs, nreq, g);
+  const ReqDev& R = reqs[r];
+  const uint32_t c = uint32_t(g - R.cbase);
+  const int64_t G2 = int64_t(R.G) * R.G;
+  const int64_t s0 = scanned[R.cbase], sg = scanned[g], s1 = scanned[g + 1];
+  const int64_t off = (sg & kCntMask) - (s0 & kCntMask);
+  const int64_t cnt = (s1 & kCntMask) - (sg & kCntMask);
+  const bool flag = ((s1 >> kCntBits) - (sg >> kCntBits)) != 0;
+  const int32_t cs = int32_t((sg >> kCntBits) - (s0 >> kCntBits));
+  uint32_t i, j;
+  demorton(c, i, j);
+  if (lane_id() == 0) {
+    R.off[c] = off;
+    if (c == G2 - 1) R.off[G2] = off + cnt;
+    R.cslot[c] = flag ? cs : -1;
+    R.bnd[c] = bnd_all[g];
+    R.ncand[c] = cand_all[g];
+    if (flag) {
+      R.ckeys[cs] = int32_t(c);
+      wu[R.wu_base + cs] = WorkUnit{r, int32_t(c)};
+    } else {
+      R.cnorm[level_offset(R.L) + c] = 0.0;
+    }
+    if (i == j) R.trace_part[i] = 0.0;
+  }
+  if (cnt == 0) return;
+  const Walk w = make_walk(R, i, j);
+  const double tau = R.tau;
+  const bool use_norms = R.use_norms != 0;
+  int64_t pos = off;
+  for (int kb = w.lo; kb <= w.hi; kb += kWave) {
+    const int k = kb + lane_id();
+    double a = -1.0, b = -1.0;
+    if (k <= w.hi) {
+      a = R.A.rm_sqrt[w.rowA + k];
+      b = R.B.cm_sqrt[w.colB + k];
+    }
+    const bool both = (a >= 0.0) && (b >= 0.0);
+    const bool keep = both && (!use_norms || a * b >= tau);
+    const uint64_t mask = ballot64(keep);
+    const int64_t at = pos + popc64(mask & lanemask_lt());
+    if (keep && at < off + cnt) R.pairs[at] = make_int2(R.A.rm_slot[w.rowA + k], R.B.cm_slot[w.colB + k]);
+    pos += popc64(mask);
+  }
+}
+
+hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+                             const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
+                             WorkUnit* wu) {
+  const int64_t blocks = (total_c + 3) / 4;
+  hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, scanned,
+                     bnd_all, cand_all, wu);
+  return hipGetLastError();
+}
+
+// Per-request accounting: skipped-product bound sums, candidates, trace and
+// ||C||^2, each reduced in one fixed order (one workgroup per request).
+__global__ void __launch_bounds__(256) k_req_stats(const ReqDev* __restrict__ reqs, ReqStatsDev* __restrict__ out) {
+  __shared__ double red[4];
+  __shared__ int64_t ired[4];
+  const ReqDev& R = reqs[blockIdx.x];
+  const int64_t G2 = int64_t(R.G) * R.G;
+  double b1 = 0.0, b2 = 0.0, tr = 0.0;
+  int64_t cand = 0;
+  for (int64_t c = threadIdx.x; c < G2; c += blockDim.x) {
+    const double b = R.bnd[c];
+    b1 += b;
+    b2 += b * b;
+    cand += R.ncand[c];
+  }
+  for (int64_t i = threadIdx.x; i < R.G; i += blockDim.x) tr += R.trace_part[i];
+  b1 = block_sum_f64(b1, red);
+  b2 = block_sum_f64(b2, red);
+  tr = block_sum_f64(tr, red);
+  cand = wave_sum_i64(cand);
+  __syncthreads();
+  if (lane_id() == 0) ired[threadIdx.x / kWave] = cand;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < 4; ++w) t += ired[w];
+    out[blockIdx.x].B1 = b1;
+    out[blockIdx.x].B2sq = b2;
+    out[blockIdx.x].trace = tr;
+    out[blockIdx.x].normC_sq = R.cnorm[0];
+    out[blockIdx.x].n_candidates = t;
+  }
+}
+
+hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, ReqStatsDev* out) {
+  if (nreq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_req_stats, dim3(uint32_t(nreq)), dim3(256), 0, s, reqs, out);
+  return hipGetLastError();
+}
+
+// (I, K, J) triples of a product's plan, for parity checks.
+__global__ void k_decode_kept(int G, const int64_t* __restrict__ off, const int2* __restrict__ pairs,
+                              const int32_t* __restrict__ akeys, int32_t* __restrict__ ijk) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= int64_t(G) * G) return;
+  uint32_t i, j;
+  demorton(uint32_t(c), i, j);
+  for (int64_t t = off[c]; t < off[c + 1]; ++t) {
+    uint32_t ai, ak;
+    demorton(uint32_t(akeys[pairs[t].x]), ai, ak);
+    ijk[3 * t] = int32_t(i);
+    ijk[3 * t + 1] = int32_t(ak);
+    ijk[3 * t + 2] = int32_t(j);
+  }
+}
+
+hipError_t launch_decode_kept(hipStream_t s, int G, int64_t n_kept, const int64_t* off, const int32_t*,
+                              const int2* pairs, const int32_t* akeys, const int32_t*, int32_t* ijk) {
+  (void)n_kept;
+  const int64_t G2 = int64_t(G) * G;
+  hipLaunchKernelGGL(k_decode_kept, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, off, pairs, akeys, ijk);
+  return hipGetLastError();
+}
+
+}  // namespace spamm

@@ -1,0 +1,308 @@
+"""Thin Python binding of libspamm.so (include/spamm.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (the arena and input tensors) and the
+stream.  If the compiled library is missing this module raises; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libspamm.so")
+
+TRUNCMUL, SPAMM, HYBRID = 0, 1, 2
+F64, F32, BF16, BF16X3 = 0, 1, 2, 3
+STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
+MODES = {"truncmul": TRUNCMUL, "spamm": SPAMM, "hybrid": HYBRID}
+PRECS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "ENONFINITE",
+          5: "EUNSUPPORTED", 6: "EDEVICE"}
+
+
+class SpammError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"SPAMM_{self.code}: {message}")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_kept", ctypes.c_int64), ("n_candidates", ctypes.c_int64),
+                ("c_nonnull", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("B1", ctypes.c_double), ("B2", ctypes.c_double),
+                ("dA", ctypes.c_double), ("dB", ctypes.c_double),
+                ("normA", ctypes.c_double), ("normB", ctypes.c_double),
+                ("normA_used", ctypes.c_double), ("err_bound", ctypes.c_double),
+                ("trace", ctypes.c_double), ("normC", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Epilogue(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("D", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("tau", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("prec", ctypes.c_int32), ("ep", ctypes.c_void_p)]
+
+
+class MatInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("leaf", ctypes.c_int32), ("G", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("nonnull", ctypes.c_int64), ("stores", ctypes.c_uint32),
+                ("has_plan", ctypes.c_int32), ("n_kept", ctypes.c_int64),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+_SIGS = {
+    "spamm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "spamm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "spamm_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "spamm_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "spamm_ctx_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "spamm_ctx_arena_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(ctypes.c_size_t),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "spamm_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "spamm_build_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "spamm_truncate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
+    "spamm_multiply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]),
+    "spamm_multiply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Request),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]),
+    "spamm_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "spamm_kept": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_int64)]),
+    "spamm_skipped_bound": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int64]),
+    "spamm_to_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "spamm_mat_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MatInfo)]),
+    "spamm_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspamm.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (binds libamdhip64 first)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_1906_08148_amd.build_lib` (no fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols(path: str = LIB_PATH):
+    lib = load_library(path)
+    return {name for name in _SIGS if hasattr(lib, name)}
+
+
+class Matrix:
+    """A library matrix handle (immutable)."""
+
+    def __init__(self, ctx: "Context", handle: int):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p(handle)
+
+    @property
+    def info(self) -> MatInfo:
+        out = MatInfo()
+        self.ctx._check(_lib.spamm_mat_info_get(self.handle, ctypes.byref(out)))
+        return out
+
+    @property
+    def n(self):
+        return self.info.n
+
+    def release(self):
+        if self.handle is not None and self.handle.value:
+            _lib.spamm_release(self.ctx.ptr, self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle is not None and self.ctx.ptr is not None:
+                self.release()
+        except Exception:
+            pass
+
+
+@dataclass
+class Product:
+    C: Matrix
+    stats: dict | None
+
+
+class Context:
+    """Library context over a torch-allocated device arena."""
+
+    def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, stream=None):
+        import torch
+        load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the spamm library needs an MI355X (gfx950)")
+        self.device = device
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        out = ctypes.c_void_p()
+        st = _lib.spamm_ctx_create(device, ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                   ctypes.c_void_p(s.cuda_stream), ctypes.byref(out))
+        if st != 0:
+            raise SpammError(st, "spamm_ctx_create failed")
+        self.ptr = out
+
+    def _check(self, st):
+        if st != 0:
+            raise SpammError(st, _lib.spamm_last_error(self.ptr).decode())
+
+    def close(self):
+        if self.ptr is not None:
+            import gc
+            gc.collect()
+            _lib.spamm_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def arena_info(self):
+        u, f, l = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(_lib.spamm_ctx_arena_info(self.ptr, ctypes.byref(u), ctypes.byref(f), ctypes.byref(l)))
+        return {"used": u.value, "free": f.value, "largest_free": l.value}
+
+    def set_stream(self, stream):
+        self._check(_lib.spamm_ctx_set_stream(self.ptr, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    # ---- build
+    def build(self, dense, leaf: int, stores: int = STORE_F64 | STORE_F32) -> Matrix:
+        import torch
+        assert dense.dtype == torch.float64 and dense.is_cuda and dense.dim() == 2
+        assert dense.stride(1) == 1
+        out = ctypes.c_void_p()
+        self._check(_lib.spamm_build(self.ptr, ctypes.c_void_p(dense.data_ptr()), dense.shape[0],
+                                     dense.stride(0), leaf, stores, ctypes.byref(out)))
+        return Matrix(self, out.value)
+
+    def build_blocks(self, n: int, leaf: int, coords, data, stores: int = STORE_F64 | STORE_F32) -> Matrix:
+        import torch
+        assert coords.dtype == torch.int32 and coords.is_cuda and coords.is_contiguous()
+        assert data.dtype == torch.float64 and data.is_cuda and data.is_contiguous()
+        out = ctypes.c_void_p()
+        m = coords.shape[0]
+        self._check(_lib.spamm_build_blocks(self.ptr, n, leaf, m, ctypes.c_void_p(coords.data_ptr() if m else 0),
+                                            ctypes.c_void_p(data.data_ptr() if m else 0), stores,
+                                            ctypes.byref(out)))
+        return Matrix(self, out.value)
+
+    # ---- truncation / multiply
+    def truncate(self, m: Matrix, tau: float):
+        out = ctypes.c_void_p()
+        dropped = ctypes.c_double()
+        self._check(_lib.spamm_truncate(self.ptr, m.handle, tau, ctypes.byref(out), ctypes.byref(dropped)))
+        return Matrix(self, out.value), dropped.value
+
+    def multiply(self, A: Matrix, B: Matrix, tau: float, mode=SPAMM, prec=F32,
+                 alpha=None, beta=None, D: Matrix | None = None, stats: bool = True) -> Product:
+        return self.multiply_batch([dict(A=A, B=B, tau=tau, mode=mode, prec=prec, alpha=alpha,
+                                         beta=beta, D=D)], stats=stats)[0]
+
+    def multiply_batch(self, reqs, stats: bool = True):
+        n = len(reqs)
+        arr = (Request * n)()
+        eps = []
+        for i, r in enumerate(reqs):
+            mode = MODES.get(r.get("mode"), r.get("mode", SPAMM))
+            prec = PRECS.get(r.get("prec"), r.get("prec", F32))
+            arr[i].A = r["A"].handle
+            arr[i].B = r["B"].handle
+            arr[i].tau = float(r["tau"])
+            arr[i].mode = int(mode)
+            arr[i].prec = int(prec)
+            if r.get("alpha") is not None or r.get("beta") is not None or r.get("D") is not None:
+                ep = Epilogue(1.0 if r.get("alpha") is None else float(r["alpha"]),
+                              0.0 if r.get("beta") is None else float(r["beta"]),
+                              r["D"].handle if r.get("D") is not None else None)
+                eps.append(ep)
+                arr[i].ep = ctypes.cast(ctypes.pointer(ep), ctypes.c_void_p)
+            else:
+                arr[i].ep = None
+        outs = (ctypes.c_void_p * n)()
+        st = (Stats * n)() if stats else None
+        self._check(_lib.spamm_multiply_batch(self.ptr, n, arr, outs, st))
+        res = []
+        for i in range(n):
+            res.append(Product(Matrix(self, outs[i]), st[i].as_dict() if stats else None))
+        return res
+
+    # ---- read-back
+    def norms(self, m: Matrix, level: int = -1) -> np.ndarray:
+        info = m.info
+        cnt = ((4 ** (info.L + 1)) - 1) // 3 if level < 0 else 4 ** level
+        buf = np.zeros(cnt, dtype=np.float64)
+        got = ctypes.c_int64()
+        self._check(_lib.spamm_norms(self.ptr, m.handle, level, buf.ctypes.data_as(ctypes.c_void_p), cnt,
+                                     ctypes.byref(got)))
+        return buf
+
+    def kept(self, C: Matrix) -> np.ndarray:
+        nk = C.info.n_kept
+        buf = np.zeros((max(nk, 0), 3), dtype=np.int32)
+        got = ctypes.c_int64()
+        self._check(_lib.spamm_kept(self.ptr, C.handle, buf.ctypes.data_as(ctypes.c_void_p), nk,
+                                    ctypes.byref(got)))
+        return buf.astype(np.int64)
+
+    def skipped_bound(self, C: Matrix) -> np.ndarray:
+        G = C.info.G
+        buf = np.zeros(G * G, dtype=np.float64)
+        self._check(_lib.spamm_skipped_bound(self.ptr, C.handle, buf.ctypes.data_as(ctypes.c_void_p), G * G))
+        return buf
+
+    def to_dense(self, m: Matrix):
+        import torch
+        n = m.info.n
+        out = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
+        return out
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def morton_order_to_grid(vals: np.ndarray, level: int) -> np.ndarray:
+    """Reshape a level's Morton-ordered values into a (2^level, 2^level) grid."""
+    side = 1 << level
+    m = np.arange(side * side, dtype=np.int64)
+    r = np.zeros_like(m)
+    c = np.zeros_like(m)
+    for b in range(level):
+        r |= ((m >> (2 * b + 1)) & 1) << b
+        c |= ((m >> (2 * b)) & 1) << b
+    out = np.zeros((side, side), dtype=vals.dtype)
+    out[r, c] = vals
+    return out

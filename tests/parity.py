@@ -1,0 +1,70 @@
+"""Helpers that compare the GPU library with the CPU oracle."""
+import numpy as np
+
+import oracle as O
+from paper_1906_08148_amd import spamm
+
+TOL = {spamm.F64: 1e-12, spamm.F32: 1e-5, spamm.BF16: 1e-2, spamm.BF16X3: 1e-5}
+TIE_BAND = 1e-12
+
+
+def keys(t, G):
+    t = np.asarray(t, dtype=np.int64).reshape(-1, 3)
+    return O.morton_key(t[:, 0], t[:, 2]) * G + t[:, 1]
+
+
+def compare_kept(gpu, ref, ties, G):
+    """The GPU list must equal the oracle's except for tie triples, and be
+    ordered by (Morton key of the C leaf, K)."""
+    kg, kr = keys(gpu, G), keys(ref, G)
+    assert np.all(np.diff(kg) > 0), "GPU kept list not in (C Morton, k) order"
+    diff = np.setxor1d(kg, kr)
+    if len(diff):
+        kt = set(keys(ties, G).tolist()) if len(ties) else set()
+        bad = [d for d in diff.tolist() if d not in kt]
+        assert not bad, f"{len(bad)} kept triples differ outside the tie band, e.g. {bad[:5]}"
+    return len(diff)
+
+
+def rel_fro(x, y):
+    d = np.linalg.norm(x - y)
+    s = np.linalg.norm(y)
+    return d / s if s > 0 else d
+
+
+def check_norms(ctx, M, T: O.Tree, rtol=1e-14):
+    allv = ctx.norms(M, -1)
+    off = 0
+    for level in range(T.L + 1):
+        cnt = 4 ** level
+        grid = spamm.morton_order_to_grid(allv[off:off + cnt], level)
+        ref = T.sq[level]
+        err = np.abs(grid - ref)
+        assert np.all(err <= rtol * np.maximum(np.abs(ref), 1e-300)), \
+            f"level {level}: max rel {np.max(err / np.maximum(ref, 1e-300)):.3e}"
+        off += cnt
+
+
+def check_product(ctx, A_h, B_h, TA, TB, tau, mode, prec, A_dense=None, alias=False):
+    """Run one multiply on the GPU and compare with the oracle."""
+    p = ctx.multiply(A_h, B_h, tau, mode=mode, prec=prec)
+    ref = O.multiply(TA, TA if alias else TB, tau, mode)
+    ties = O.tie_triples(ref.A_used, ref.B_used, tau, TIE_BAND)
+    gk = ctx.kept(p.C)
+    ndiff = compare_kept(gk, ref.kept, ties, TA.G)
+    st = p.stats
+    assert st["n_kept"] == len(gk)
+    if ndiff == 0 and not ref.stats["trunc_tie"]:
+        assert st["n_kept"] == ref.stats["n_kept"]
+        assert st["n_candidates"] == ref.stats["n_candidates"]
+        assert st["c_nonnull"] == ref.stats["c_nonnull"]
+        C = ctx.to_dense(p.C).cpu().numpy()
+        Cref = ref.C.to_dense()
+        r = rel_fro(C, Cref)
+        assert r <= TOL[prec], f"mode {mode} prec {prec}: rel {r:.3e}"
+        # accounting
+        for k in ("B1", "B2", "dA", "dB"):
+            assert abs(st[k] - ref.stats[k]) <= 1e-10 * max(abs(ref.stats[k]), 1e-300) + 1e-300, k
+        if ref.stats["err_bound"] > 0:
+            assert abs(st["err_bound"] - ref.stats["err_bound"]) <= 1e-10 * ref.stats["err_bound"]
+    return p, ref

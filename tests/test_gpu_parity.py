@@ -1,0 +1,214 @@
+"""GPU parity: the library (through the C-ABI) against the CPU oracle on the
+same seeded inputs -- kept products exactly (outside the 1e-12 tie band),
+C within 1e-12 (FP64) / 1e-5 (FP32) relative Frobenius, norms within 1e-14."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_1906_08148_amd import spamm
+
+from parity import TOL, check_norms, check_product, compare_kept, rel_fro
+
+pytestmark = pytest.mark.gpu
+MODES = (spamm.TRUNCMUL, spamm.SPAMM, spamm.HYBRID)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    c = spamm.Context(arena_bytes=6 << 30)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def sparse_random(n, bs, fill, seed):
+    coords, data = synth.random_blocks(seed, n, bs, fill)
+    return synth.dense_from_blocks(n, bs, coords, data)
+
+
+def test_config1_all_modes(ctx):
+    """n=1024, leaf 32, 1D alpha=0.5, tau=1e-6, A = B symmetric."""
+    print("case: config1 n=1024 bs=32", flush=True)
+    A = synth.DecaySpec("1d", 1024, 0.5, seed=1).dense()
+    T = O.build(A, 32)
+    M = ctx.build(dev(A), 32)
+    assert M.info.nonnull == T.nonnull_count()
+    check_norms(ctx, M, T)
+    for mode in MODES:
+        for prec in (spamm.F64, spamm.F32):
+            check_product(ctx, M, M, T, T, 1e-6, mode, prec, alias=True)
+
+
+@pytest.mark.parametrize("n,bs,kind,alpha,tau", [
+    (1000, 32, "1d", 0.3, 1e-5),      # ragged tail, not a power of two
+    (300, 16, "rand", 0.3, 1e-2),     # random sparse blocks
+    (2100, 64, "1d", 0.2, 1e-6),      # several tiles + ragged
+    (700, 128, "3d", 1.0, 1e-4),      # 3D decay, big leaves
+    (17, 16, "1d", 0.5, 1e-3),        # G = 2 with a 1-row tail
+    (20, 32, "1d", 0.5, 1e-3),        # single leaf (L = 0)
+])
+def test_shapes_and_leaf_sizes(ctx, n, bs, kind, alpha, tau):
+    print(f"case: n={n} bs={bs} {kind}", flush=True)
+    if kind == "rand":
+        A = sparse_random(n, bs, alpha, 3)
+        B = sparse_random(n, bs, 0.5, 4)
+    elif kind == "3d":
+        n = (n // 8) * 8
+        A = synth.DecaySpec("3d", n, alpha, seed=2).dense()
+        B = A
+    else:
+        A = synth.DecaySpec("1d", n, alpha, seed=5).dense()
+        B = synth.DecaySpec("1d", n, alpha * 1.3, seed=6).dense()
+    TA, TB = O.build(A, bs), O.build(B, bs)
+    MA, MB = ctx.build(dev(A), bs), ctx.build(dev(B), bs)
+    check_norms(ctx, MA, TA)
+    for mode in MODES:
+        for prec in (spamm.F64, spamm.F32):
+            check_product(ctx, MA, MB, TA, TB, tau, mode, prec)
+
+
+def test_block_list_build_matches_dense_build(ctx):
+    import torch
+    print("case: block build n=3000 bs=64", flush=True)
+    sp = synth.DecaySpec("1d", 3000, 0.2, seed=3)
+    coords, data = sp.leaf_blocks(64)
+    Mb = ctx.build_blocks(3000, 64, dev(coords.astype(np.int32)), dev(data))
+    Md = ctx.build(dev(sp.dense()), 64)
+    assert Mb.info.nonnull == Md.info.nonnull
+    assert np.array_equal(ctx.norms(Mb), ctx.norms(Md))
+    assert torch.equal(ctx.to_dense(Mb), ctx.to_dense(Md))
+    T = O.build_from_blocks(3000, 64, coords, data)
+    check_norms(ctx, Mb, T)
+    for mode in MODES:
+        check_product(ctx, Mb, Mb, T, T, 1e-6, mode, spamm.F32, alias=True)
+
+
+def test_tau_zero_and_huge(ctx):
+    print("case: tau 0 / huge", flush=True)
+    A = sparse_random(400, 32, 0.4, 8)
+    T = O.build(A, 32)
+    M = ctx.build(dev(A), 32)
+    for mode in MODES:
+        p = ctx.multiply(M, M, 0.0, mode=mode, prec=spamm.F64)
+        C = ctx.to_dense(p.C).cpu().numpy()
+        assert rel_fro(C, A @ A) <= 1e-14
+        q = ctx.multiply(M, M, 1e30, mode=mode, prec=spamm.F64)
+        assert q.stats["n_kept"] == 0 and q.stats["c_nonnull"] == 0
+        assert np.all(ctx.to_dense(q.C).cpu().numpy() == 0.0)
+
+
+def test_all_null_input(ctx):
+    print("case: all-null", flush=True)
+    Z = np.zeros((100, 100))
+    M = ctx.build(dev(Z), 16)
+    assert M.info.nonnull == 0
+    for mode in MODES:
+        p = ctx.multiply(M, M, 1e-6, mode=mode, prec=spamm.F32)
+        assert p.stats["n_kept"] == 0
+        assert ctx.kept(p.C).shape == (0, 3)
+    assert np.all(ctx.norms(M) == 0.0)
+
+
+def test_truncation_drop_set(ctx):
+    print("case: truncation", flush=True)
+    A = synth.DecaySpec("1d", 4096, 0.2, seed=1).dense()
+    T = O.build(A, 64)
+    M = ctx.build(dev(A), 64)
+    for tau in (1e-8, 1e-6, 1e-4, 1e-2):
+        Mt, dropped = ctx.truncate(M, tau)
+        tr = O.truncate(T, tau)
+        if tr.tie:
+            continue
+        assert Mt.info.nonnull == tr.tree.nonnull_count()
+        assert abs(dropped - tr.dropped_sq) <= 1e-12 * max(tr.dropped_sq, 1e-300)
+        check_norms(ctx, Mt, tr.tree)
+        assert np.array_equal(ctx.to_dense(Mt).cpu().numpy(), tr.tree.to_dense())
+
+
+def test_epilogue_alpha_beta(ctx):
+    """C = -1 * A A + 2 * A (the 2X - X^2 purification step)."""
+    print("case: epilogue", flush=True)
+    A = synth.DecaySpec("1d", 512, 0.4, seed=9).dense() * 0.1
+    T = O.build(A, 32)
+    M = ctx.build(dev(A), 32)
+    for prec in (spamm.F64, spamm.F32):
+        p = ctx.multiply(M, M, 1e-7, mode=spamm.HYBRID, prec=prec, alpha=-1.0, beta=2.0, D=M)
+        ref = O.multiply(T, T, 1e-7, O.HYBRID)
+        want = 2.0 * A - ref.C.to_dense()
+        C = ctx.to_dense(p.C).cpu().numpy()
+        assert rel_fro(C, want) <= TOL[prec]
+        # C's structure is the union of the product's and D's
+        assert p.C.info.nonnull == int((ref.C.leaf_present | T.leaf_present).sum())
+
+
+def test_bitwise_repeatable_and_batch_equals_alone(ctx):
+    import torch
+    print("case: determinism", flush=True)
+    A = synth.DecaySpec("1d", 4096, 0.2, seed=4).dense()
+    B = synth.DecaySpec("3d", 2048, 0.8, seed=5).dense()
+    MA = ctx.build(dev(A), 64)
+    MB = ctx.build(dev(B), 32)
+    alone = []
+    for (M, tau, mode, prec) in [(MA, 1e-6, spamm.SPAMM, spamm.F32), (MA, 1e-4, spamm.HYBRID, spamm.F64),
+                                 (MB, 1e-5, spamm.TRUNCMUL, spamm.F32), (MB, 1e-6, spamm.SPAMM, spamm.F64)]:
+        p1 = ctx.multiply(M, M, tau, mode=mode, prec=prec)
+        p2 = ctx.multiply(M, M, tau, mode=mode, prec=prec)
+        assert torch.equal(ctx.to_dense(p1.C), ctx.to_dense(p2.C))
+        alone.append((M, tau, mode, prec, ctx.to_dense(p1.C)))
+    batch = ctx.multiply_batch([dict(A=M, B=M, tau=t, mode=m, prec=pr) for (M, t, m, pr, _) in alone])
+    for (M, t, m, pr, Cal), pb in zip(alone, batch):
+        assert torch.equal(ctx.to_dense(pb.C), Cal)
+
+
+def test_error_codes(ctx):
+    import torch
+    print("case: error codes", flush=True)
+    A = synth.DecaySpec("1d", 256, 0.5, seed=1).dense()
+    M = ctx.build(dev(A), 32)
+    M16 = ctx.build(dev(A), 16)
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.multiply(M, M, -1.0)
+    assert e.value.code == "EINVAL"
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.multiply(M, M, float("nan"))
+    assert e.value.code == "EINVAL"
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.multiply(M, M16, 1e-6)
+    assert e.value.code == "ESHAPE"
+    bad = A.copy()
+    bad[3, 7] = np.nan
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.build(dev(bad), 32)
+    assert e.value.code == "ENONFINITE"
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.build(dev(A), 48)
+    assert e.value.code == "EINVAL"
+    small = spamm.Context(arena_bytes=2 << 20)
+    with pytest.raises(spamm.SpammError) as e:
+        small.build(dev(synth.DecaySpec("1d", 2048, 0.01, seed=1).dense()), 64)
+    assert e.value.code == "ENOMEM"
+    small.close()
+
+
+def test_config2_full(ctx):
+    """n=16384, leaf 64, 1D alpha in {0.2, 0.5}, tau in {1e-4, 1e-6, 1e-8},
+    three schemes, FP64 and FP32, built from block lists."""
+    for alpha in (0.2, 0.5):
+        print(f"case: config2 alpha={alpha}", flush=True)
+        sp = synth.DecaySpec("1d", 16384, alpha, seed=1)
+        coords, data = sp.leaf_blocks(64)
+        T = O.build_from_blocks(16384, 64, coords, data)
+        M = ctx.build_blocks(16384, 64, dev(coords.astype(np.int32)), dev(data))
+        check_norms(ctx, M, T)
+        for tau in (1e-4, 1e-6, 1e-8):
+            for mode in MODES:
+                for prec in (spamm.F64, spamm.F32):
+                    check_product(ctx, M, M, T, T, tau, mode, prec, alias=True)
