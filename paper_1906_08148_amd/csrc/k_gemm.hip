@@ -237,7 +237,9 @@ __global__ void __launch_bounds__((GemmCfg<T, BS>::NT)) k_gemm(const ReqDev* __r
       for (int b = 0; b < Cf::TN; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = row0 + a * 16 + 4 * g + v;
+          // accumulator layout: f32 16x16x4 holds rows 4g..4g+3 of column li;
+          // f64 16x16x4 interleaves them, register v holding row 4v + g
+          const int row = row0 + a * 16 + (std::is_same<T, float>::value ? 4 * g + v : 4 * v + g);
           const int col = col0 + b * 16 + li;
           T val = acc[a][b][v];
           if (has_ep) {
