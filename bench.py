@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Benchmark of the approximate-product hot path on one MI355X.
+
+Workload (one "step"): the 1D-decay sweep n = 16384, leaf 64,
+a_ij = (2u - 1) exp(-alpha |i - j|), alpha in {0.2, 0.5}, tau in {1e-4, 1e-6,
+1e-8}, schemes Truncmul / SpAMM / Hybrid, A = B.  A step builds both matrices
+from their device-resident leaf-block lists (norms, null map, pyramid), then
+runs the 18 multiplies as one batch: truncation, pruning, one persistent
+leaf-GEMM launch, C pyramids and the FP64 accounting.  The headline value is
+kept-leaf GFLOP/s (2 * 64^3 per formed leaf product) in FP32-MFMA mode; the
+same step in FP64 mode is reported beside it.
+
+Prints one JSON line (see the repository's measurement notes for fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kept-leaf GFLOP/s + multiplies/sec at fixed ‖E‖_F; p50/p99 latency, FP32 vs FP64"
+N, LEAF = 16384, 64
+ALPHAS = (0.2, 0.5)
+TAUS = (1e-4, 1e-6, 1e-8)
+MODE_NAMES = ("truncmul", "spamm", "hybrid")
+SEED = 1
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
+GEMM_SOURCE = os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "k_gemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leaf_gemm_f32_bs64_config2_traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs():
+    import numpy as np
+    import synth
+    out = {}
+    for a in ALPHAS:
+        coords, data = synth.DecaySpec("1d", N, a, seed=SEED).leaf_blocks(LEAF)
+        out[a] = (coords.astype(np.int32), data)
+    return out
+
+
+def gpu_inputs(host):
+    import torch
+    return {a: (torch.from_numpy(c).cuda(), torch.from_numpy(d).cuda()) for a, (c, d) in host.items()}
+
+
+def requests(mats, prec):
+    from paper_1906_08148_amd import spamm
+    reqs = []
+    for a in ALPHAS:
+        for t in TAUS:
+            for mi, _ in enumerate(MODE_NAMES):
+                reqs.append(dict(A=mats[a], B=mats[a], tau=t, mode=mi, prec=prec))
+    return reqs
+
+
+def run_step(ctx, dev, prec, keep=False):
+    """One pass of the whole path; returns (stats list, products or None)."""
+    from paper_1906_08148_amd import spamm
+    store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32
+    mats = {a: ctx.build_blocks(N, LEAF, c, d, stores=store) for a, (c, d) in dev.items()}
+    prods = ctx.multiply_batch(requests(mats, prec), stats=True)
+    stats = [p.stats for p in prods]
+    if keep:
+        return stats, prods, mats
+    for p in prods:
+        p.C.release()
+    for m in mats.values():
+        m.release()
+    return stats, None, None
+
+
+def timed_steps(ctx, dev, prec, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        run_step(ctx, dev, prec)
+    torch.cuda.synchronize()
+    ctx.timing(enable=True, reset=True)
+    lat = []
+    flops = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        stats, _, _ = run_step(ctx, dev, prec)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        flops += sum(s["flops"] for s in stats)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    tm = ctx.timing(enable=False, reset=True)
+    return total, lat, flops, tm, stats
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def errors(ctx, dev, host, prec):
+    """||C - A A||_F of every request against the FP64 dense product (torch
+    FP64 GEMM as an independent reference), outside the timed region."""
+    import numpy as np
+    import torch
+    import synth
+    stats, prods, mats = run_step(ctx, dev, prec, keep=True)
+    out = []
+    i = 0
+    for a in ALPHAS:
+        coords, data = host[a]
+        A = torch.from_numpy(synth.dense_from_blocks(N, LEAF, coords, data)).cuda()
+        exact = A @ A
+        nA = float(torch.linalg.norm(A))
+        for t in TAUS:
+            for m in MODE_NAMES:
+                C = ctx.to_dense(prods[i].C)
+                err = float(torch.linalg.norm(C - exact))
+                out.append(dict(alpha=a, tau=t, mode=m, err=err, sigma=1e-5 * nA * nA,
+                                n_kept=stats[i]["n_kept"], bound=stats[i]["err_bound"]))
+                i += 1
+                del C
+        del A, exact
+    for p in prods:
+        p.C.release()
+    for m in mats.values():
+        m.release()
+    torch.cuda.empty_cache()
+    return out
+
+
+def fixed_error_rate(ctx, dev, prec, errs, reps):
+    """Multiplies/s for the largest tau meeting ||E||_F <= 1e-5 ||A||_F^2 per
+    (alpha, scheme), matrices prebuilt (norms precomputed, as in Sec. 5.2)."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32
+    mats = {a: ctx.build_blocks(N, LEAF, c, d, stores=store) for a, (c, d) in dev.items()}
+    chosen = []
+    for a in ALPHAS:
+        for mi, m in enumerate(MODE_NAMES):
+            ok = [e for e in errs if e["alpha"] == a and e["mode"] == m and e["err"] <= e["sigma"]]
+            if ok:
+                best = max(ok, key=lambda e: e["tau"])
+                chosen.append(dict(alpha=a, mode=m, tau=best["tau"], err=best["err"], mi=mi))
+    reqs = [dict(A=mats[c["alpha"]], B=mats[c["alpha"]], tau=c["tau"], mode=c["mi"], prec=prec) for c in chosen]
+    for _ in range(2):
+        for p in ctx.multiply_batch(reqs, stats=False):
+            p.C.release()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p in ctx.multiply_batch(reqs, stats=False):
+            p.C.release()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for m in mats.values():
+        m.release()
+    return dict(multiplies_per_s=len(reqs) * reps / dt,
+                chosen=[{k: c[k] for k in ("alpha", "mode", "tau", "err")} for c in chosen])
+
+
+def cpu_baseline(host, min_s=10.0):
+    """The oracle as it stands, with one BLAS thread, on whole steps of the
+    same workload (both builds and all 18 multiplies), repeated until at
+    least ``min_s`` seconds of CPU work have run."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    t0 = time.perf_counter()
+    flops = 0.0
+    steps = 0
+    while True:
+        for a in ALPHAS:
+            coords, data = host[a]
+            tree = O.build_from_blocks(N, LEAF, coords, data)
+            for t in TAUS:
+                for mi in (O.TRUNCMUL, O.SPAMM, O.HYBRID):
+                    flops += O.multiply(tree, tree, t, mi).stats["flops"]
+        steps += 1
+        if time.perf_counter() - t0 >= min_s:
+            break
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister()
+    return {"value": round(flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} whole step(s): both builds and all 18 multiplies, {dt:.1f} s, "
+                      f"NumPy FP64, one BLAS thread"}
+
+
+def traffic_for(flops_per_launch):
+    """HBM bytes per GEMM launch from the committed rocprofv3 counter summary,
+    only when it was taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != src:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        return 2
+    import torch
+    from paper_1906_08148_amd import spamm
+
+    log("bench: generating inputs")
+    host = make_inputs()
+    dev = gpu_inputs(host)
+    ctx = spamm.Context(arena_bytes=16 << 30)
+
+    log("bench: FP32 steps")
+    total32, lat32, flops32, tm32, stats32 = timed_steps(ctx, dev, spamm.F32, args.steps, args.warmup)
+    value = flops32 / total32 / 1e9
+    gemm_per_launch_ms = tm32["gemm_ms"] / max(tm32["gemm_launches"], 1)
+    flops_per_launch = tm32["gemm_flops"] / max(tm32["gemm_launches"], 1)
+    achieved = flops_per_launch / (gemm_per_launch_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total32 / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1D decay n=16384 leaf 64, alpha {0.2,0.5} x tau {1e-4,1e-6,1e-8} x "
+                               "{truncmul,spamm,hybrid}, A=B, built from leaf-block lists; 18 multiplies "
+                               "per step, one batch",
+                   "n": N, "leaf": LEAF, "multiplies_per_step": len(stats32), "seed": SEED},
+        "multiplies_per_s": round(len(stats32) * args.steps / total32, 2),
+        "latency_ms": {"p50": round(pct(lat32, 0.5) * 1e3, 4), "p99": round(pct(lat32, 0.99) * 1e3, 4)},
+        "kept_products_per_step": int(sum(s["n_kept"] for s in stats32)),
+        "phases_ms_per_step": {k: round(tm32[k + "_ms"] / args.steps, 4)
+                               for k in ("build", "trunc", "prune", "gemm", "pyramid")},
+        "roofline": {"kernel": "k_gemm<float,64> (persistent MFMA leaf GEMM)", "bound": "mfma",
+                     "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                     "traffic": traffic_for(flops_per_launch),
+                     "flops_per_launch": flops_per_launch, "ms_per_launch": round(gemm_per_launch_ms, 5)},
+    }
+    if not args.skip_extras:
+        log("bench: FP64 steps")
+        total64, lat64, flops64, tm64, _ = timed_steps(ctx, dev, spamm.F64, args.steps, args.warmup)
+        g64 = tm64["gemm_ms"] / max(tm64["gemm_launches"], 1)
+        f64l = tm64["gemm_flops"] / max(tm64["gemm_launches"], 1)
+        out["f64"] = {"value": round(flops64 / total64 / 1e9, 3), "unit": "GFLOP/s",
+                      "ms_per_step": round(total64 / args.steps * 1e3, 4),
+                      "multiplies_per_s": round(18 * args.steps / total64, 2),
+                      "latency_ms": {"p50": round(pct(lat64, 0.5) * 1e3, 4),
+                                     "p99": round(pct(lat64, 0.99) * 1e3, 4)},
+                      "gemm_tflops": round(f64l / (g64 * 1e-3) / 1e12, 3),
+                      "gemm_frac_of_fp64_peak": round(f64l / (g64 * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)}
+        log("bench: errors and fixed-error rates")
+        e32 = errors(ctx, dev, host, spamm.F32)
+        e64 = errors(ctx, dev, host, spamm.F64)
+        out["fixed_error"] = {
+            "sigma": "1e-5 * ||A||_F * ||B||_F",
+            "f32": fixed_error_rate(ctx, dev, spamm.F32, e32, 20),
+            "f64": fixed_error_rate(ctx, dev, spamm.F64, e64, 20),
+            "errors_f32": [{k: e[k] for k in ("alpha", "tau", "mode", "err", "bound")} for e in e32],
+        }
+        out["fixed_error"]["f32_over_f64"] = round(out["fixed_error"]["f32"]["multiplies_per_s"] /
+                                                   out["fixed_error"]["f64"]["multiplies_per_s"], 3)
+    if not args.no_cpu_baseline:
+        log("bench: oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -128,6 +128,18 @@ typedef struct spamm_mat_info {
   size_t device_bytes;  /* arena bytes referenced by this handle             */
 } spamm_mat_info;
 
+/* Device time per kernel class, from HIP events recorded on the context's
+ * stream around each launch (only while timing is enabled). */
+typedef struct spamm_timing {
+  double build_ms;    /* leaf scan, compaction, copies                     */
+  double trunc_ms;    /* truncation                                        */
+  double prune_ms;    /* counting pass, scan, fill                         */
+  double gemm_ms;     /* persistent leaf-GEMM launches                     */
+  double pyramid_ms;  /* norm pyramids                                     */
+  int64_t build_launches, trunc_launches, prune_launches, gemm_launches, pyramid_launches;
+  double gemm_flops;  /* 2 * bs^3 * (products) over the timed GEMM launches */
+} spamm_timing;
+
 /* Name of a status code (static string). */
 const char* spamm_status_string(spamm_status s);
 
@@ -152,6 +164,12 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
 /* Arena occupancy in bytes (host outputs, any may be NULL). */
 spamm_status spamm_ctx_arena_info(const spamm_ctx* ctx, size_t* used,
                                   size_t* free_bytes, size_t* largest_free);
+
+/* Turn event timing on (enable = 1) or off (0) for later calls; when `out`
+ * is non-NULL, synchronise the stream and write the totals since the last
+ * reset; reset = 1 clears them afterwards.  Errors: EINVAL, EDEVICE. */
+spamm_status spamm_ctx_timing(spamm_ctx* ctx, int32_t enable, int32_t reset,
+                              spamm_timing* out);
 
 /* Build a matrix from a dense FP64 row-major n x n device buffer with leading
  * dimension ld (Sec. 2; Sec. 4.2 null blocks; Sec. 4.4 dense leaves kept when

@@ -36,6 +36,33 @@ void* Ctx::stage(size_t bytes) {
   return host_stage;
 }
 
+hipEvent_t Ctx::get_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipError_t Ctx::collect_timing() {
+  hipError_t err = hipStreamSynchronize(stream);
+  if (err != hipSuccess) return err;
+  for (auto& p : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      t_ms[p.cls] += ms;
+      t_cnt[p.cls] += 1;
+    }
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+  return hipSuccess;
+}
+
 }  // namespace spamm
 
 size_t spamm_mat::device_bytes() const {
@@ -144,6 +171,7 @@ spamm_status ensure_prep(Ctx* c, spamm_mat* m) {
   ALLOC(e, G2 * 4, "column slots");
   ALLOC(r, int64_t(4) * m->G * 4, "ranges");
   const double* leaf = P<double>(m->norms) + level_offset(m->L);
+  TimedScope ts(c, kTPrune);
   SPAMM_HIP(c, launch_prep(c->stream, m->G, P<int32_t>(m->slot), leaf, P<double>(a), P<int32_t>(b), P<double>(d),
                            P<int32_t>(e)));
   SPAMM_HIP(c, launch_ranges(c->stream, m->G, P<double>(a), P<double>(d), P<int32_t>(r)));
@@ -171,6 +199,7 @@ spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vect
   ALLOC(jd, jobs.size() * sizeof(PyrJob), "pyramid jobs");
   spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PyrJob));
   if (st != SPAMM_OK) return st;
+  TimedScope ts(c, kTPyr);
   SPAMM_HIP(c, launch_pyramid(c->stream, P<PyrJob>(jd), int(jobs.size()), jobs));
   return SPAMM_OK;
 }
@@ -203,6 +232,7 @@ spamm_status ensure_store(Ctx* c, Store& s, uint32_t need) {
     ALLOC(olo, e * 2, "BF16 lo leaves");
   }
   if (!s.f64 && !s.f32) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 copy to derive from");
+  TimedScope ts(c, kTBuild);
   SPAMM_HIP(c, launch_derive_store(c->stream, e, P<double>(s.f64), s.f64 ? nullptr : P<float>(s.f32), P<double>(o64),
                                    P<float>(o32), P<uint16_t>(ohi), P<uint16_t>(olo)));
   if (o64) s.f64 = o64;
@@ -242,9 +272,12 @@ spamm_status truncate_impl(Ctx* c, const spamm_mat* in, double tau, std::unique_
   const size_t sb = trunc_scratch_bytes(in->G);
   ALLOC(scratch, sb, "truncation scratch");
   ALLOC(result, 16, "truncation result");
-  SPAMM_HIP(c, launch_trunc(c->stream, in->G, P<int32_t>(in->slot), P<double>(in->norms) + level_offset(in->L),
+  {
+    TimedScope ts(c, kTTrunc);
+    SPAMM_HIP(c, launch_trunc(c->stream, in->G, P<int32_t>(in->slot), P<double>(in->norms) + level_offset(in->L),
                             tau * tau, P<int32_t>(m->slot), P<double>(m->norms) + level_offset(m->L), scratch->ptr(),
-                            sb, P<double>(result)));
+                              sb, P<double>(result)));
+  }
   st = pyramids(c, {P<double>(m->norms)}, {m->L});
   if (st != SPAMM_OK) return st;
   out = std::move(m);
@@ -297,6 +330,8 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   Ctx* c = &ctx->c;
   if (c->live_handles != 0) return fail(c, SPAMM_EINVAL, "handles still alive");
   hipStreamSynchronize(c->stream);
+  c->collect_timing();
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   if (c->host_stage) hipHostFree(c->host_stage);
   delete ctx;
   return SPAMM_OK;
@@ -307,6 +342,35 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream) {
   Ctx* c = &ctx->c;
   SPAMM_HIP(c, hipStreamSynchronize(c->stream));
   c->stream = static_cast<hipStream_t>(stream);
+  return SPAMM_OK;
+}
+
+spamm_status spamm_ctx_timing(spamm_ctx* ctx, int32_t enable, int32_t reset, spamm_timing* out) {
+  if (!ctx) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (out) {
+    SPAMM_HIP(c, c->collect_timing());
+    out->build_ms = c->t_ms[kTBuild];
+    out->trunc_ms = c->t_ms[kTTrunc];
+    out->prune_ms = c->t_ms[kTPrune];
+    out->gemm_ms = c->t_ms[kTGemm];
+    out->pyramid_ms = c->t_ms[kTPyr];
+    out->build_launches = c->t_cnt[kTBuild];
+    out->trunc_launches = c->t_cnt[kTTrunc];
+    out->prune_launches = c->t_cnt[kTPrune];
+    out->gemm_launches = c->t_cnt[kTGemm];
+    out->pyramid_launches = c->t_cnt[kTPyr];
+    out->gemm_flops = c->gemm_flops;
+  }
+  if (reset) {
+    SPAMM_HIP(c, c->collect_timing());
+    for (int k = 0; k < kTClasses; ++k) {
+      c->t_ms[k] = 0.0;
+      c->t_cnt[k] = 0;
+    }
+    c->gemm_flops = 0.0;
+  }
+  c->timing = enable != 0;
   return SPAMM_OK;
 }
 
@@ -335,10 +399,13 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   const size_t sb = scan_scratch_bytes(G2);
   ALLOC(scratch, sb, "scan scratch");
   int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
+  {
+  TimedScope ts(c, kTBuild);
   SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
   SPAMM_HIP(c, launch_build_scan_dense(c->stream, dense, n, ld, leaf, m->G, P<double>(m->norms) + level_offset(m->L),
                                        P<int32_t>(flag), P<int32_t>(nf)));
   SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  }
   struct {
     int32_t nf;
     int32_t pad[15];
@@ -351,6 +418,7 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   m->store = std::make_shared<Store>();
   st = alloc_store(c, *m->store, hb.total, leaf, stores);
   if (st != SPAMM_OK) return st;
+  TimedScope ts2(c, kTBuild);
   SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
   SPAMM_HIP(c, launch_copy_dense_leaves(c->stream, dense, n, ld, leaf, hb.total, P<int32_t>(m->store->keys),
                                         P<double>(m->store->f64), P<float>(m->store->f32),
@@ -378,6 +446,8 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   const size_t sb = scan_scratch_bytes(G2);
   ALLOC(scratch, sb, "scan scratch");
   int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
+  {
+  TimedScope ts(c, kTBuild);
   SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
   SPAMM_HIP(c, launch_fill_i32(c->stream, P<int32_t>(src), G2, -1));
   SPAMM_HIP(c, launch_blocks_scatter(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
@@ -385,6 +455,7 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   SPAMM_HIP(c, launch_blocks_scan(c->stream, n, leaf, m->G, data, P<int32_t>(src),
                                   P<double>(m->norms) + level_offset(m->L), P<int32_t>(flag), P<int32_t>(nf)));
   SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  }
   struct {
     int32_t err;
     int32_t pad[15];
@@ -400,6 +471,7 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   m->store = std::make_shared<Store>();
   st = alloc_store(c, *m->store, hb.total, leaf, stores);
   if (st != SPAMM_OK) return st;
+  TimedScope ts2(c, kTBuild);
   SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
   SPAMM_HIP(c, launch_copy_block_leaves(c->stream, n, leaf, hb.total, P<int32_t>(m->store->keys), P<int32_t>(src),
                                         data, P<double>(m->store->f64), P<float>(m->store->f32),
@@ -541,10 +613,13 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   ALLOC(totals, count * sizeof(ReqTotals), "totals");
   spamm_status st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
   if (st != SPAMM_OK) return st;
+  {
+  TimedScope ts(c, kTPrune);
   SPAMM_HIP(c, launch_prune_count(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(packed), P<double>(bnd_all),
                                   P<int32_t>(cand_all)));
   SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
   SPAMM_HIP(c, launch_gather_totals(c->stream, P<ReqDev>(reqd), count, P<int64_t>(scanned), P<ReqTotals>(totals)));
+  }
   std::vector<ReqTotals> ht(count);
   st = download(c, ht.data(), totals->ptr(), count * sizeof(ReqTotals));
   if (st != SPAMM_OK) return st;
@@ -629,14 +704,26 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   }
   RegionP wus, queue;
   ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
-  ALLOC(queue, 256, "queue counter");
+  ALLOC(queue, 1024, "queue counters");
   st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
   if (st != SPAMM_OK) return st;
-  SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned), P<double>(bnd_all),
-                                 P<int32_t>(cand_all), P<WorkUnit>(wus)));
+  {
+    TimedScope ts(c, kTPrune);
+    SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
+                                   P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus),
+                                   P<int32_t>(queue), int(launches.size())));
+  }
+  int qi = 0;
   for (auto& l : launches) {
+    int32_t* qptr = P<int32_t>(queue) + qi++;
+    if (l.second.second == 0) continue;
+    TimedScope ts(c, kTGemm);
+    if (c->timing) {
+      for (int r : groups[l.first]) c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs *
+                                                   double(ht[r].n_kept);
+    }
     SPAMM_HIP(c, launch_gemm(c->stream, l.first.first, l.first.second, P<ReqDev>(reqd), P<WorkUnit>(wus),
-                             l.second.first, l.second.second, P<int32_t>(queue), c->n_cu));
+                             l.second.first, l.second.second, qptr, c->n_cu));
   }
   {
     std::vector<double*> nv;

@@ -89,8 +89,23 @@ struct spamm_mat {
 
 namespace spamm {
 
+enum TimeClass { kTBuild = 0, kTTrunc, kTPrune, kTGemm, kTPyr, kTClasses };
+
 struct Ctx {
   int device = 0;
+  // event timing per kernel class
+  bool timing = false;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[kTClasses] = {0, 0, 0, 0, 0};
+  int64_t t_cnt[kTClasses] = {0, 0, 0, 0, 0};
+  double gemm_flops = 0.0;
+  hipEvent_t get_event();
+  hipError_t collect_timing();  // sync + fold pending pairs into totals
   hipStream_t stream = nullptr;
   Arena arena;
   std::string last_error;
@@ -102,6 +117,28 @@ struct Ctx {
   int live_handles = 0;
   RegionP alloc(size_t bytes);    // nullptr on exhaustion
   void* stage(size_t bytes);      // grow pinned staging if needed
+};
+
+// Records events around the launches of one kernel class while timing is on.
+struct TimedScope {
+  Ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  TimedScope(Ctx* ctx, int k) : c(ctx), cls(k) {
+    if (c->timing) {
+      a = c->get_event();
+      if (a) hipEventRecord(a, c->stream);
+    }
+  }
+  ~TimedScope() {
+    if (a) {
+      hipEvent_t b = c->get_event();
+      if (b) {
+        hipEventRecord(b, c->stream);
+        c->pending.push_back({cls, a, b});
+      }
+    }
+  }
 };
 
 // status helpers
@@ -234,8 +271,8 @@ hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq,
                                 const int64_t* scanned, ReqTotals* out);
 hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                              const int64_t* scanned, const double* bnd_all,
-                             const int32_t* cand_all, WorkUnit* wu);
-// gemm over work units [wu0, wu0 + nwu)
+                             const int32_t* cand_all, WorkUnit* wu, int32_t* queues, int nqueues);
+// gemm over work units [wu0, wu0 + nwu); *queue must be zero at launch
 hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
                        int64_t wu0, int64_t nwu, int32_t* queue, int n_cu);
 bool gemm_supported(int prec, int bs);

@@ -280,8 +280,6 @@ static hipError_t launch_one(hipStream_t s, const ReqDev* reqs, const WorkUnit* 
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<T, BS>, Cf::NT, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t grid = std::min<int64_t>(nwu, int64_t(n_cu) * per_cu);
-  e = launch_zero_i32(s, queue, 1);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_gemm<T, BS>), dim3(uint32_t(grid)), dim3(Cf::NT), 0, s, reqs, wu, wu0, nwu, queue);
   return hipGetLastError();
 }

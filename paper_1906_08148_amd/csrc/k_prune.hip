@@ -111,7 +111,9 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
                                                     const int64_t* __restrict__ scanned,
                                                     const double* __restrict__ bnd_all,
                                                     const int32_t* __restrict__ cand_all,
-                                                    WorkUnit* __restrict__ wu) {
+                                                    WorkUnit* __restrict__ wu, int32_t* __restrict__ queues,
+                                                    int nqueues) {
+  if (blockIdx.x == 0 && threadIdx.x < nqueues) queues[threadIdx.x] = 0;  // GEMM work queues
   const int64_t g = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (g >= total_c) return;
   const int r = find_req(reqs, nreq, g);
@@ -162,10 +164,11 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
 
 hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                              const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
-                             WorkUnit* wu) {
+                             WorkUnit* wu, int32_t* queues, int nqueues) {
+  if (nqueues > 256) return hipErrorInvalidValue;
   const int64_t blocks = (total_c + 3) / 4;
   hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, scanned,
-                     bnd_all, cand_all, wu);
+                     bnd_all, cand_all, wu, queues, nqueues);
   return hipGetLastError();
 }
 

@@ -61,6 +61,18 @@ class MatInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("build_ms", ctypes.c_double), ("trunc_ms", ctypes.c_double),
+                ("prune_ms", ctypes.c_double), ("gemm_ms", ctypes.c_double),
+                ("pyramid_ms", ctypes.c_double), ("build_launches", ctypes.c_int64),
+                ("trunc_launches", ctypes.c_int64), ("prune_launches", ctypes.c_int64),
+                ("gemm_launches", ctypes.c_int64), ("pyramid_launches", ctypes.c_int64),
+                ("gemm_flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 _SIGS = {
@@ -70,6 +82,8 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "spamm_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "spamm_ctx_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "spamm_ctx_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(Timing)]),
     "spamm_ctx_arena_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
                                             ctypes.POINTER(ctypes.c_size_t),
                                             ctypes.POINTER(ctypes.c_size_t)]),
@@ -190,6 +204,14 @@ class Context:
         u, f, l = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         self._check(_lib.spamm_ctx_arena_info(self.ptr, ctypes.byref(u), ctypes.byref(f), ctypes.byref(l)))
         return {"used": u.value, "free": f.value, "largest_free": l.value}
+
+    def timing(self, enable: bool = True, reset: bool = False, read: bool = True):
+        """Enable/disable per-kernel-class event timing; returns the totals
+        since the last reset (synchronises) when ``read``."""
+        out = Timing() if read else None
+        self._check(_lib.spamm_ctx_timing(self.ptr, int(enable), int(reset),
+                                          ctypes.byref(out) if read else None))
+        return out.as_dict() if read else None
 
     def set_stream(self, stream):
         self._check(_lib.spamm_ctx_set_stream(self.ptr, ctypes.c_void_p(stream.cuda_stream)))
