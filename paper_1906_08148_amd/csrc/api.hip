@@ -160,26 +160,44 @@ spamm_status new_matrix(Ctx* c, int64_t n, int bs, std::unique_ptr<spamm_mat>& o
   return SPAMM_OK;
 }
 
-// Row/column views for pruning, computed on first use as an operand.
-spamm_status ensure_prep(Ctx* c, spamm_mat* m) {
-  if (m->rm_sqrt) return SPAMM_OK;
-  const int64_t G2 = int64_t(m->G) * m->G;
-  RegionP a, b, d, e, r;
-  ALLOC(a, G2 * 8, "row view");
-  ALLOC(b, G2 * 4, "row slots");
-  ALLOC(d, G2 * 8, "column view");
-  ALLOC(e, G2 * 4, "column slots");
-  ALLOC(r, int64_t(4) * m->G * 4, "ranges");
-  const double* leaf = P<double>(m->norms) + level_offset(m->L);
+// Row/column views for pruning, computed on first use as an operand (all
+// matrices that lack them in one batched pass).
+spamm_status prep_many(Ctx* c, const std::vector<spamm_mat*>& mats) {
+  std::vector<PrepJob> jobs;
+  std::vector<spamm_mat*> todo;
+  int64_t total = 0, waves = 0;
+  for (spamm_mat* m : mats) {
+    if (m->rm_sqrt || std::find(todo.begin(), todo.end(), m) != todo.end()) continue;
+    const int64_t G2 = int64_t(m->G) * m->G;
+    ALLOC(m->rm_sqrt, G2 * 8, "row view");
+    ALLOC(m->rm_slot, G2 * 4, "row slots");
+    ALLOC(m->cm_sqrt, G2 * 8, "column view");
+    ALLOC(m->cm_slot, G2 * 4, "column slots");
+    ALLOC(m->ranges, int64_t(4) * m->G * 4, "ranges");
+    PrepJob j;
+    j.slot = P<int32_t>(m->slot);
+    j.leafnorm = P<double>(m->norms) + level_offset(m->L);
+    j.rm_sqrt = P<double>(m->rm_sqrt);
+    j.rm_slot = P<int32_t>(m->rm_slot);
+    j.cm_sqrt = P<double>(m->cm_sqrt);
+    j.cm_slot = P<int32_t>(m->cm_slot);
+    j.ranges = P<int32_t>(m->ranges);
+    j.base = total;
+    j.wbase = waves;
+    j.G = m->G;
+    j.pad_ = 0;
+    jobs.push_back(j);
+    todo.push_back(m);
+    total += G2;
+    waves += 2 * int64_t(m->G);
+  }
+  if (jobs.empty()) return SPAMM_OK;
+  RegionP jd;
+  ALLOC(jd, jobs.size() * sizeof(PrepJob), "prep jobs");
+  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PrepJob));
+  if (st != SPAMM_OK) return st;
   TimedScope ts(c, kTPrune);
-  SPAMM_HIP(c, launch_prep(c->stream, m->G, P<int32_t>(m->slot), leaf, P<double>(a), P<int32_t>(b), P<double>(d),
-                           P<int32_t>(e)));
-  SPAMM_HIP(c, launch_ranges(c->stream, m->G, P<double>(a), P<double>(d), P<int32_t>(r)));
-  m->rm_sqrt = a;
-  m->rm_slot = b;
-  m->cm_sqrt = d;
-  m->cm_slot = e;
-  m->ranges = r;
+  SPAMM_HIP(c, launch_prep_batch(c->stream, P<PrepJob>(jd), int(jobs.size()), total, waves));
   return SPAMM_OK;
 }
 
@@ -262,26 +280,55 @@ spamm_status finish_build(Ctx* c, std::unique_ptr<spamm_mat>& m, spamm_mat** out
   return SPAMM_OK;
 }
 
-spamm_status truncate_impl(Ctx* c, const spamm_mat* in, double tau, std::unique_ptr<spamm_mat>& out,
-                           RegionP& result) {
-  std::unique_ptr<spamm_mat> m;
-  spamm_status st = new_matrix(c, in->n, in->bs, m);
-  if (st != SPAMM_OK) return st;
-  m->store = in->store;
-  RegionP scratch;
-  const size_t sb = trunc_scratch_bytes(in->G);
+// Truncate several (matrix, tau) pairs with one set of launches.  Outputs
+// share leaf storage with their inputs; `result` holds 2 doubles per job
+// (dropped squared norm, dropped count) on the device.
+spamm_status truncate_many(Ctx* c, const std::vector<std::pair<const spamm_mat*, double>>& in,
+                           std::vector<std::unique_ptr<spamm_mat>>& out, RegionP& result) {
+  out.clear();
+  if (in.empty()) return SPAMM_OK;
+  ALLOC(result, in.size() * 16, "truncation results");
+  std::vector<TruncJob> jobs;
+  int64_t total = 0;
+  for (size_t t = 0; t < in.size(); ++t) {
+    const spamm_mat* a = in[t].first;
+    std::unique_ptr<spamm_mat> m;
+    spamm_status st = new_matrix(c, a->n, a->bs, m);
+    if (st != SPAMM_OK) return st;
+    m->store = a->store;
+    TruncJob j;
+    j.slot = P<int32_t>(a->slot);
+    j.leafnorm = P<double>(a->norms) + level_offset(a->L);
+    j.out_slot = P<int32_t>(m->slot);
+    j.out_norm = P<double>(m->norms) + level_offset(m->L);
+    j.result = P<double>(result) + 2 * t;
+    j.tau2 = in[t].second * in[t].second;
+    j.base = total;
+    j.G = a->G;
+    int kb = 1;
+    while ((int64_t(1) << kb) < int64_t(a->G) * a->G) ++kb;
+    j.key_bits_lo = kb;
+    jobs.push_back(j);
+    total += int64_t(a->G) * a->G;
+    out.push_back(std::move(m));
+  }
+  RegionP jd, scratch;
+  ALLOC(jd, jobs.size() * sizeof(TruncJob), "truncation jobs");
+  const size_t sb = trunc_batch_scratch_bytes(int(jobs.size()), total);
   ALLOC(scratch, sb, "truncation scratch");
-  ALLOC(result, 16, "truncation result");
+  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(TruncJob));
+  if (st != SPAMM_OK) return st;
   {
     TimedScope ts(c, kTTrunc);
-    SPAMM_HIP(c, launch_trunc(c->stream, in->G, P<int32_t>(in->slot), P<double>(in->norms) + level_offset(in->L),
-                            tau * tau, P<int32_t>(m->slot), P<double>(m->norms) + level_offset(m->L), scratch->ptr(),
-                              sb, P<double>(result)));
+    SPAMM_HIP(c, launch_trunc_batch(c->stream, P<TruncJob>(jd), int(jobs.size()), total, scratch->ptr(), sb));
   }
-  st = pyramids(c, {P<double>(m->norms)}, {m->L});
-  if (st != SPAMM_OK) return st;
-  out = std::move(m);
-  return SPAMM_OK;
+  std::vector<double*> nv;
+  std::vector<int> lv;
+  for (auto& m : out) {
+    nv.push_back(P<double>(m->norms));
+    lv.push_back(m->L);
+  }
+  return pyramids(c, nv, lv);
 }
 
 }  // namespace
@@ -452,7 +499,7 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   SPAMM_HIP(c, launch_fill_i32(c->stream, P<int32_t>(src), G2, -1));
   SPAMM_HIP(c, launch_blocks_scatter(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
                                      P<int32_t>(nf)));
-  SPAMM_HIP(c, launch_blocks_scan(c->stream, n, leaf, m->G, data, P<int32_t>(src),
+  SPAMM_HIP(c, launch_blocks_scan(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
                                   P<double>(m->norms) + level_offset(m->L), P<int32_t>(flag), P<int32_t>(nf)));
   SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
   }
@@ -485,17 +532,17 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   *out = nullptr;
   if (!in || in->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
   if (!tau_ok(tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
-  std::unique_ptr<spamm_mat> m;
+  std::vector<std::unique_ptr<spamm_mat>> ms;
   RegionP res;
-  spamm_status st = truncate_impl(c, in, tau, m, res);
+  spamm_status st = truncate_many(c, {{in, tau}}, ms, res);
   if (st != SPAMM_OK) return st;
   double hr[2];
   st = download(c, hr, res->ptr(), sizeof(hr));
   if (st != SPAMM_OK) return st;
   if (dropped_sq) *dropped_sq = hr[0];
-  m->nonnull = (in->nonnull >= 0) ? in->nonnull - int64_t(hr[1]) : -1;
+  ms[0]->nonnull = (in->nonnull >= 0) ? in->nonnull - int64_t(hr[1]) : -1;
   c->live_handles++;
-  *out = m.release();
+  *out = ms[0].release();
   return SPAMM_OK;
 }
 
@@ -525,42 +572,56 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     }
   }
 
-  // ---- truncations (shared within the batch per (matrix, tau))
-  std::map<std::pair<const spamm_mat*, uint64_t>, std::pair<std::unique_ptr<spamm_mat>, RegionP>> trunc;
-  std::vector<spamm_mat*> Au(count), Bu(count);
-  std::vector<const double*> trA(count, nullptr), trB(count, nullptr);
-  auto get_trunc = [&](const spamm_mat* m, double tau, spamm_mat*& o, const double*& res) -> spamm_status {
+  // ---- truncations (one per distinct (matrix, tau) in the batch, all at once)
+  std::map<std::pair<const spamm_mat*, uint64_t>, int> tindex;
+  std::vector<std::pair<const spamm_mat*, double>> tjobs;
+  auto tkey = [](const spamm_mat* m, double tau) {
     uint64_t bits;
     std::memcpy(&bits, &tau, 8);
-    auto key = std::make_pair(m, bits);
-    auto it = trunc.find(key);
-    if (it == trunc.end()) {
-      std::unique_ptr<spamm_mat> t;
-      RegionP rr;
-      spamm_status st = truncate_impl(c, m, tau, t, rr);
-      if (st != SPAMM_OK) return st;
-      it = trunc.emplace(key, std::make_pair(std::move(t), rr)).first;
-    }
-    o = it->second.first.get();
-    res = P<double>(it->second.second);
-    return SPAMM_OK;
+    return std::make_pair(m, bits);
   };
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    if (q.mode == SPAMM_SPAMM) continue;
+    for (const spamm_mat* m : {q.A, q.B}) {
+      auto k = tkey(m, q.tau);
+      if (!tindex.count(k)) {
+        tindex[k] = int(tjobs.size());
+        tjobs.push_back({m, q.tau});
+      }
+    }
+  }
+  std::vector<std::unique_ptr<spamm_mat>> tmats;
+  RegionP tres;
+  {
+    spamm_status st = truncate_many(c, tjobs, tmats, tres);
+    if (st != SPAMM_OK) return st;
+  }
+  std::vector<spamm_mat*> Au(count), Bu(count);
+  std::vector<const double*> trA(count, nullptr), trB(count, nullptr);
+  std::vector<spamm_mat*> operands;
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
     if (q.mode == SPAMM_SPAMM) {
       Au[r] = const_cast<spamm_mat*>(q.A);
       Bu[r] = const_cast<spamm_mat*>(q.B);
     } else {
-      spamm_status st = get_trunc(q.A, q.tau, Au[r], trA[r]);
-      if (st != SPAMM_OK) return st;
-      st = get_trunc(q.B, q.tau, Bu[r], trB[r]);
-      if (st != SPAMM_OK) return st;
+      const int ia = tindex[tkey(q.A, q.tau)], ib = tindex[tkey(q.B, q.tau)];
+      Au[r] = tmats[ia].get();
+      Bu[r] = tmats[ib].get();
+      trA[r] = P<double>(tres) + 2 * ia;
+      trB[r] = P<double>(tres) + 2 * ib;
     }
-    spamm_status st = ensure_prep(c, Au[r]);
+    operands.push_back(Au[r]);
+    operands.push_back(Bu[r]);
+  }
+  {
+    spamm_status st = prep_many(c, operands);
     if (st != SPAMM_OK) return st;
-    st = ensure_prep(c, Bu[r]);
-    if (st != SPAMM_OK) return st;
-    st = ensure_store(c, *Au[r]->store, store_for_prec(q.prec));
+  }
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    spamm_status st = ensure_store(c, *Au[r]->store, store_for_prec(q.prec));
     if (st != SPAMM_OK) return st;
     st = ensure_store(c, *Bu[r]->store, store_for_prec(q.prec));
     if (st != SPAMM_OK) return st;
@@ -572,7 +633,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
 
   // ---- descriptors and counting pass
   std::vector<ReqDev> rd(count);
-  int64_t total_c = 0;
+  int64_t total_c = 0, total_chunks = 0;
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
     ReqDev& d = rd[r];
@@ -600,7 +661,14 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     d.bs = q.A->bs;
     d.cbase = total_c;
     d.prec = q.prec;
+    d.rootA = P<double>(q.A->norms);
+    d.rootB = P<double>(q.B->norms);
+    d.rootAu = P<double>(Au[r]->norms);
+    d.truncA = trA[r];
+    d.truncB = trB[r];
+    d.stat_base = total_chunks;
     total_c += int64_t(d.G) * d.G;
+    total_chunks += (int64_t(d.G) * d.G + kStatChunk - 1) / kStatChunk;
   }
   RegionP reqd, packed, scanned, bnd_all, cand_all, scan_scr, totals;
   ALLOC(reqd, count * sizeof(ReqDev), "request table");
@@ -736,11 +804,13 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     if (st != SPAMM_OK) return st;
   }
 
-  // ---- statistics
+  // ---- statistics (one copy back for the whole batch)
   if (st_out) {
-    RegionP sd;
+    RegionP sd, part;
     ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
-    SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, P<ReqStatsDev>(sd)));
+    ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
+    SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, total_chunks, P<StatPartial>(part),
+                                  P<ReqStatsDev>(sd)));
     std::vector<ReqStatsDev> hs(count);
     st = download(c, hs.data(), sd->ptr(), count * sizeof(ReqStatsDev));
     if (st != SPAMM_OK) return st;
@@ -756,26 +826,11 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       o.B2 = q.mode == SPAMM_TRUNCMUL ? 0.0 : std::sqrt(hs[r].B2sq);
       o.trace = hs[r].trace;
       o.normC = std::sqrt(hs[r].normC_sq);
-      double roots[4] = {0, 0, 0, 0}, tr[4] = {0, 0, 0, 0};
-      st = download(c, &roots[0], q.A->norms->ptr(), 8);
-      if (st != SPAMM_OK) return st;
-      st = download(c, &roots[1], q.B->norms->ptr(), 8);
-      if (st != SPAMM_OK) return st;
-      st = download(c, &roots[2], Au[r]->norms->ptr(), 8);
-      if (st != SPAMM_OK) return st;
-      if (trA[r]) {
-        st = download(c, &tr[0], trA[r], 8);
-        if (st != SPAMM_OK) return st;
-      }
-      if (trB[r]) {
-        st = download(c, &tr[1], trB[r], 8);
-        if (st != SPAMM_OK) return st;
-      }
-      o.normA = std::sqrt(roots[0]);
-      o.normB = std::sqrt(roots[1]);
-      o.normA_used = std::sqrt(roots[2]);
-      o.dA = std::sqrt(tr[0]);
-      o.dB = std::sqrt(tr[1]);
+      o.normA = std::sqrt(hs[r].normA_sq);
+      o.normB = std::sqrt(hs[r].normB_sq);
+      o.normA_used = std::sqrt(hs[r].normAu_sq);
+      o.dA = std::sqrt(hs[r].dA_sq);
+      o.dB = std::sqrt(hs[r].dB_sq);
       if (q.mode == SPAMM_SPAMM) o.err_bound = o.B2;
       else if (q.mode == SPAMM_TRUNCMUL) o.err_bound = o.dA * o.normB + o.normA_used * o.dB;
       else o.err_bound = o.dA * o.normB + o.normA_used * o.dB + o.B2;

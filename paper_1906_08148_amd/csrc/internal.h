@@ -205,6 +205,41 @@ struct ReqDev {
   int64_t wu_base;        // first work unit of this request
   int32_t prec;
   int32_t use_ep;         // apply alpha/beta/D in the epilogue
+  // accounting inputs (roots of the pyramids, truncation results)
+  const double* rootA;
+  const double* rootB;
+  const double* rootAu;
+  const double* truncA;   // nullptr when A was not truncated
+  const double* truncB;
+  int64_t stat_base;      // first statistics chunk of this request
+};
+
+// One truncation inside a batch (leaf-block truncation with budget tau^2).
+struct TruncJob {
+  const int32_t* slot;     // input slot map (Morton)
+  const double* leafnorm;  // input leaf norms (Morton)
+  int32_t* out_slot;
+  double* out_norm;        // leaf level of the output pyramid
+  double* result;          // [0] dropped squared norm, [1] dropped count
+  double tau2;
+  int64_t base;            // first element in the batch's concatenated arrays
+  int32_t G;
+  int32_t key_bits_lo;     // bits of the Morton index in the sort key
+};
+
+// Row/column views of one matrix (see ensure_prep).
+struct PrepJob {
+  const int32_t* slot;
+  const double* leafnorm;
+  double* rm_sqrt;
+  int32_t* rm_slot;
+  double* cm_sqrt;
+  int32_t* cm_slot;
+  int32_t* ranges;
+  int64_t base;   // first element (G*G per job)
+  int64_t wbase;  // first wave of the range pass (2*G per job)
+  int32_t G;
+  int32_t pad_;
 };
 
 struct WorkUnit {
@@ -221,7 +256,15 @@ struct ReqTotals {
 // Per-request statistics reduced on the device.
 struct ReqStatsDev {
   double B1, B2sq, trace, normC_sq;
+  double normA_sq, normB_sq, normAu_sq, dA_sq, dB_sq;
   int64_t n_candidates;
+};
+
+constexpr int kStatChunk = 4096;  // C leaves per partial-statistics workgroup
+
+struct StatPartial {
+  double b1, b2;
+  int64_t cand;
   int64_t pad_;
 };
 
@@ -234,9 +277,9 @@ hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n
 hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
                                  const int32_t* coords, const double* data, int32_t* src_of,
                                  int32_t* errflags);
-hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, const double* data,
-                              const int32_t* src_of, double* leafnorm, int32_t* flag,
-                              int32_t* errflags);
+hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
+                              const int32_t* coords, const double* data, const int32_t* src_of,
+                              double* leafnorm, int32_t* flag, int32_t* errflags);
 // exclusive scan of int32 flags -> slot map (flag ? prefix : -1), total -> *total
 hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count,
                                  int32_t* slot, int64_t* total, void* scratch, size_t scratch_bytes);
@@ -253,17 +296,14 @@ hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nl
                                     uint16_t* bhi, uint16_t* blo);
 hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, const float* f32,
                                double* o64, float* o32, uint16_t* ohi, uint16_t* olo);
-hipError_t launch_prep(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
-                       double* rm_sqrt, int32_t* rm_slot, double* cm_sqrt, int32_t* cm_slot);
-hipError_t launch_ranges(hipStream_t s, int G, const double* rm_sqrt, const double* cm_sqrt,
-                         int32_t* ranges);
+hipError_t launch_prep_batch(hipStream_t s, const PrepJob* jobs_dev, int njobs, int64_t total,
+                             int64_t total_waves);
 hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
                           const std::vector<PyrJob>& jobs_host);
-// truncation
-hipError_t launch_trunc(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
-                        double tau2, int32_t* out_slot, double* out_leafnorm, void* scratch,
-                        size_t scratch_bytes, double* result_dev /* [0]=dropped_sq,[1]=count */);
-size_t trunc_scratch_bytes(int G);
+// truncation of several matrices at once (total = sum of G*G)
+hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs_dev, int njobs, int64_t total,
+                              void* scratch, size_t scratch_bytes);
+size_t trunc_batch_scratch_bytes(int njobs, int64_t total);
 // prune
 hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                               int64_t* packed, double* bnd_all, int32_t* cand_all);
@@ -278,7 +318,8 @@ hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, cons
 bool gemm_supported(int prec, int bs);
 hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
-hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, ReqStatsDev* out);
+hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,
+                            ReqStatsDev* out);
 hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
                            const double* f64, const float* f32, double* out, int64_t ld);
 hipError_t launch_decode_kept(hipStream_t s, int G, int64_t n_kept, const int64_t* off,

@@ -84,33 +84,43 @@ hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, const double* __restrict__ data,
+__global__ void k_blocks_zero(int64_t G2, double* __restrict__ leafnorm, int32_t* __restrict__ flag) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= G2) return;
+  leafnorm[m] = 0.0;
+  flag[m] = 0;
+}
+
+// One workgroup per listed block (the one that won its Morton slot).
+__global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, int64_t nblocks,
+                                                     const int32_t* __restrict__ coords,
+                                                     const double* __restrict__ data,
                                                      const int32_t* __restrict__ src_of,
                                                      double* __restrict__ leafnorm,
                                                      int32_t* __restrict__ flag,
                                                      int32_t* __restrict__ err) {
   __shared__ double red[4];
-  const uint32_t m = blockIdx.x;
-  const int32_t t = src_of[m];
+  const int64_t t = blockIdx.x;
+  const int64_t gmax = (n + bs - 1) / bs;
+  const int32_t I = coords[2 * t], J = coords[2 * t + 1];
+  if (I < 0 || J < 0 || I >= gmax || J >= gmax) return;
+  const uint32_t m = morton(uint32_t(I), uint32_t(J));
+  if (src_of[m] != int32_t(t)) return;
   double s = 0.0;
   int nz = 0, nf = 0, pad = 0;
-  if (t >= 0) {
-    uint32_t r, c;
-    demorton(m, r, c);
-    const int64_t rows = min<int64_t>(bs, n - int64_t(r) * bs);
-    const int64_t cols = min<int64_t>(bs, n - int64_t(c) * bs);
-    const double* blk = data + int64_t(t) * bs * bs;
-    for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-      const int rr = e / bs, cc = e % bs;
-      const double a = blk[e];
-      if (rr < rows && cc < cols) {
-        const double sq = a * a;
-        s += sq;
-        nz |= (a != 0.0);
-        nf |= !isfinite(a);
-      } else {
-        pad |= (a != 0.0);
-      }
+  const int64_t rows = min<int64_t>(bs, n - int64_t(I) * bs);
+  const int64_t cols = min<int64_t>(bs, n - int64_t(J) * bs);
+  const double* blk = data + t * bs * bs;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+    const int rr = e / bs, cc = e % bs;
+    const double a = blk[e];
+    if (rr < rows && cc < cols) {
+      const double sq = a * a;
+      s += sq;
+      nz |= (a != 0.0);
+      nf |= !isfinite(a);
+    } else {
+      pad |= (a != 0.0);
     }
   }
   s = block_sum_f64(s, red);
@@ -125,11 +135,15 @@ __global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, const do
   }
 }
 
-hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, const double* data,
-                              const int32_t* src_of, double* leafnorm, int32_t* flag,
+hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks, const int32_t* coords,
+                              const double* data, const int32_t* src_of, double* leafnorm, int32_t* flag,
                               int32_t* errflags) {
-  hipLaunchKernelGGL(k_blocks_scan, dim3(uint32_t(G) * uint32_t(G)), dim3(256), 0, s, n, bs, data,
-                     src_of, leafnorm, flag, errflags);
+  const int64_t G2 = int64_t(G) * G;
+  hipLaunchKernelGGL(k_blocks_zero, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G2, leafnorm, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nblocks == 0) return e;
+  hipLaunchKernelGGL(k_blocks_scan, dim3(uint32_t(nblocks)), dim3(256), 0, s, n, bs, nblocks, coords, data, src_of,
+                     leafnorm, flag, errflags);
   return hipGetLastError();
 }
 
@@ -241,40 +255,44 @@ hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, 
 // ---------------------------------------------------------------- pruning views
 
 // Row-major and column-major copies of sqrt(leaf norm) (-1 for null) and of
-// the slot map, so that pruning walks an A row and a B column contiguously.
-__global__ void k_prep(int G, const int32_t* __restrict__ slot, const double* __restrict__ leafnorm,
-                       double* __restrict__ rm_sqrt, int32_t* __restrict__ rm_slot,
-                       double* __restrict__ cm_sqrt, int32_t* __restrict__ cm_slot) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= int64_t(G) * G) return;
+// the slot map, so that pruning walks an A row and a B column contiguously;
+// then the non-null k range of every row and column (one wave each).  Both
+// passes cover all matrices of a batch.
+__device__ __forceinline__ int find_prep(const PrepJob* __restrict__ jobs, int njobs, int64_t g, bool waves) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((waves ? jobs[mid].wbase : jobs[mid].base) <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_prep(const PrepJob* __restrict__ jobs, int njobs, int64_t total) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const PrepJob& J = jobs[find_prep(jobs, njobs, g, false)];
+  const int64_t m = g - J.base;
+  const int G = J.G;
   uint32_t r, c;
   demorton(uint32_t(m), r, c);
-  const int32_t sl = slot[m];
-  const double v = sl >= 0 ? sqrt(leafnorm[m]) : -1.0;
-  rm_sqrt[int64_t(r) * G + c] = v;
-  rm_slot[int64_t(r) * G + c] = sl;
-  cm_sqrt[int64_t(c) * G + r] = v;
-  cm_slot[int64_t(c) * G + r] = sl;
+  const int32_t sl = J.slot[m];
+  const double v = sl >= 0 ? sqrt(J.leafnorm[m]) : -1.0;
+  J.rm_sqrt[int64_t(r) * G + c] = v;
+  J.rm_slot[int64_t(r) * G + c] = sl;
+  J.cm_sqrt[int64_t(c) * G + r] = v;
+  J.cm_slot[int64_t(c) * G + r] = sl;
 }
 
-hipError_t launch_prep(hipStream_t s, int G, const int32_t* slot, const double* leafnorm,
-                       double* rm_sqrt, int32_t* rm_slot, double* cm_sqrt, int32_t* cm_slot) {
-  const int64_t G2 = int64_t(G) * G;
-  hipLaunchKernelGGL(k_prep, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, slot, leafnorm,
-                     rm_sqrt, rm_slot, cm_sqrt, cm_slot);
-  return hipGetLastError();
-}
-
-// Non-null k range of every row (as left operand) and column (as right
-// operand): one wave per row/column.
-__global__ void __launch_bounds__(256) k_ranges(int G, const double* __restrict__ rm_sqrt,
-                                                const double* __restrict__ cm_sqrt,
-                                                int32_t* __restrict__ ranges) {
-  const int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (w >= 2 * G) return;
-  const bool is_col = w >= G;
-  const int idx = is_col ? w - G : w;
-  const double* v = (is_col ? cm_sqrt : rm_sqrt) + int64_t(idx) * G;
+__global__ void __launch_bounds__(256) k_ranges(const PrepJob* __restrict__ jobs, int njobs, int64_t total_waves) {
+  const int64_t w = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (w >= total_waves) return;
+  const PrepJob& J = jobs[find_prep(jobs, njobs, w, true)];
+  const int G = J.G;
+  const int64_t lw = w - J.wbase;
+  const bool is_col = lw >= G;
+  const int idx = int(is_col ? lw - G : lw);
+  const double* v = (is_col ? J.cm_sqrt : J.rm_sqrt) + int64_t(idx) * G;
   int lo = G, hi = -1;
   for (int k = lane_id(); k < G; k += kWave) {
     if (v[k] >= 0.0) {
@@ -288,16 +306,17 @@ __global__ void __launch_bounds__(256) k_ranges(int G, const double* __restrict_
     hi = max(hi, __shfl_down(hi, off, kWave));
   }
   if (lane_id() == 0) {
-    ranges[(is_col ? 2 : 0) * G + idx] = lo;
-    ranges[(is_col ? 3 : 1) * G + idx] = hi;
+    J.ranges[(is_col ? 2 : 0) * G + idx] = lo;
+    J.ranges[(is_col ? 3 : 1) * G + idx] = hi;
   }
 }
 
-hipError_t launch_ranges(hipStream_t s, int G, const double* rm_sqrt, const double* cm_sqrt,
-                         int32_t* ranges) {
-  const int waves = 2 * G;
-  hipLaunchKernelGGL(k_ranges, dim3(uint32_t((waves + 3) / 4)), dim3(256), 0, s, G, rm_sqrt, cm_sqrt,
-                     ranges);
+hipError_t launch_prep_batch(hipStream_t s, const PrepJob* jobs, int njobs, int64_t total, int64_t total_waves) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep, dim3(uint32_t((total + 255) / 256)), dim3(256), 0, s, jobs, njobs, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ranges, dim3(uint32_t((total_waves + 3) / 4)), dim3(256), 0, s, jobs, njobs, total_waves);
   return hipGetLastError();
 }
 

@@ -44,21 +44,45 @@ __device__ __forceinline__ Walk make_walk(const ReqDev& R, uint32_t i, uint32_t 
   return w;
 }
 
-__global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
-                                                     int64_t* __restrict__ packed, double* __restrict__ bnd_all,
-                                                     int32_t* __restrict__ cand_all) {
-  const int64_t g = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (g >= total_c) return;
-  const int r = find_req(reqs, nreq, g);
-  const ReqDev& R = reqs[r];
-  const uint32_t c = uint32_t(g - R.cbase);
-  uint32_t i, j;
-  demorton(c, i, j);
-  const Walk w = make_walk(R, i, j);
+// Each wave takes 64 consecutive C leaves (one per lane).  Every lane first
+// finds its request and intersects the k ranges of its A row and B column;
+// the wave then walks, 64 k at a time, only the leaves whose range is not
+// empty, so structurally empty leaves cost one coalesced pass.
+struct LaneLeaf {
+  int r;
+  uint32_t c, i, j;
+  Walk w;
+  bool valid;
+};
+
+__device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
+                                              int64_t g) {
+  LaneLeaf x;
+  x.valid = g < total_c;
+  x.r = 0;
+  x.c = x.i = x.j = 0;
+  x.w.lo = 1;
+  x.w.hi = 0;
+  x.w.rowA = x.w.colB = 0;
+  if (x.valid) {
+    x.r = find_req(reqs, nreq, g);
+    const ReqDev& R = reqs[x.r];
+    x.c = uint32_t(g - R.cbase);
+    demorton(x.c, x.i, x.j);
+    x.w = make_walk(R, x.i, x.j);
+  }
+  return x;
+}
+
+// Walk one C leaf with the whole wave: counts of kept and candidate k and
+// the sum of skipped norm products (lane partials, then a fixed tree).
+__device__ __forceinline__ void walk_count(const ReqDev& R, const Walk& w, int64_t& cnt, int64_t& cand,
+                                           double& skipped) {
   const double tau = R.tau;
   const bool use_norms = R.use_norms != 0;
-  int64_t cnt = 0, cand = 0;
-  double skipped = 0.0;
+  cnt = 0;
+  cand = 0;
+  double part = 0.0;
   for (int kb = w.lo; kb <= w.hi; kb += kWave) {
     const int k = kb + lane_id();
     double a = -1.0, b = -1.0;
@@ -71,21 +95,53 @@ __global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ 
     const bool keep = both && (!use_norms || p >= tau);
     cnt += popc64(ballot64(keep));
     cand += popc64(ballot64(both));
-    if (both && !keep) skipped += p;
+    if (both && !keep) part += p;
   }
-  skipped = wave_sum_f64(skipped);
-  if (lane_id() == 0) {
-    const bool dflag = R.slotD != nullptr && R.slotD[c] >= 0;
-    const int64_t flag = (cnt > 0 || dflag) ? 1 : 0;
-    packed[g] = (flag << kCntBits) | cnt;
-    bnd_all[g] = skipped;
-    cand_all[g] = int32_t(cand);
+  skipped = wave_sum_f64(part);
+}
+
+__global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
+                                                     int64_t* __restrict__ packed, double* __restrict__ bnd_all,
+                                                     int32_t* __restrict__ cand_all) {
+  const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+  if (g0 >= total_c) return;
+  const int64_t g = g0 + lane_id();
+  const LaneLeaf x = lane_leaf(reqs, nreq, total_c, g);
+  int64_t my_cnt = 0, my_cand = 0;
+  double my_skip = 0.0;
+  uint64_t todo = ballot64(x.valid && x.w.lo <= x.w.hi);
+  while (todo) {
+    const int b = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const int r = __shfl(x.r, b, kWave);
+    Walk w;
+    w.lo = __shfl(x.w.lo, b, kWave);
+    w.hi = __shfl(x.w.hi, b, kWave);
+    w.rowA = __shfl(x.w.rowA, b, kWave);
+    w.colB = __shfl(x.w.colB, b, kWave);
+    int64_t cnt, cand;
+    double skipped;
+    walk_count(reqs[r], w, cnt, cand, skipped);
+    if (lane_id() == b) {
+      my_cnt = cnt;
+      my_cand = cand;
+      my_skip = skipped;
+    }
+  }
+  if (x.valid) {
+    const ReqDev& R = reqs[x.r];
+    const bool dflag = R.slotD != nullptr && R.slotD[x.c] >= 0;
+    const int64_t flag = (my_cnt > 0 || dflag) ? 1 : 0;
+    packed[g] = (flag << kCntBits) | my_cnt;
+    bnd_all[g] = my_skip;
+    cand_all[g] = int32_t(my_cand);
   }
 }
 
 hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int64_t* packed,
                               double* bnd_all, int32_t* cand_all) {
-  const int64_t blocks = (total_c + 3) / 4;
+  const int64_t waves = (total_c + kWave - 1) / kWave;
+  const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, packed,
                      bnd_all, cand_all);
   return hipGetLastError();
@@ -114,51 +170,62 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
                                                     WorkUnit* __restrict__ wu, int32_t* __restrict__ queues,
                                                     int nqueues) {
   if (blockIdx.x == 0 && threadIdx.x < nqueues) queues[threadIdx.x] = 0;  // GEMM work queues
-  const int64_t g = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (g >= total_c) return;
-  const int r = find_req(reqs, nreq, g);
-  const ReqDev& R = reqs[r];
-  const uint32_t c = uint32_t(g - R.cbase);
-  const int64_t G2 = int64_t(R.G) * R.G;
-  const int64_t s0 = scanned[R.cbase], sg = scanned[g], s1 = scanned[g + 1];
-  const int64_t off = (sg & kCntMask) - (s0 & kCntMask);
-  const int64_t cnt = (s1 & kCntMask) - (sg & kCntMask);
-  const bool flag = ((s1 >> kCntBits) - (sg >> kCntBits)) != 0;
-  const int32_t cs = int32_t((sg >> kCntBits) - (s0 >> kCntBits));
-  uint32_t i, j;
-  demorton(c, i, j);
-  if (lane_id() == 0) {
-    R.off[c] = off;
-    if (c == G2 - 1) R.off[G2] = off + cnt;
-    R.cslot[c] = flag ? cs : -1;
-    R.bnd[c] = bnd_all[g];
-    R.ncand[c] = cand_all[g];
+  const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+  if (g0 >= total_c) return;
+  const int64_t g = g0 + lane_id();
+  const LaneLeaf x = lane_leaf(reqs, nreq, total_c, g);
+  int64_t off = 0, cnt = 0;
+  if (x.valid) {
+    const ReqDev& R = reqs[x.r];
+    const int64_t G2 = int64_t(R.G) * R.G;
+    const int64_t s0 = scanned[R.cbase], sg = scanned[g], s1 = scanned[g + 1];
+    off = (sg & kCntMask) - (s0 & kCntMask);
+    cnt = (s1 & kCntMask) - (sg & kCntMask);
+    const bool flag = ((s1 >> kCntBits) - (sg >> kCntBits)) != 0;
+    const int32_t cs = int32_t((sg >> kCntBits) - (s0 >> kCntBits));
+    R.off[x.c] = off;
+    if (x.c == G2 - 1) R.off[G2] = off + cnt;
+    R.cslot[x.c] = flag ? cs : -1;
+    R.bnd[x.c] = bnd_all[g];
+    R.ncand[x.c] = cand_all[g];
     if (flag) {
-      R.ckeys[cs] = int32_t(c);
-      wu[R.wu_base + cs] = WorkUnit{r, int32_t(c)};
+      R.ckeys[cs] = int32_t(x.c);
+      wu[R.wu_base + cs] = WorkUnit{x.r, int32_t(x.c)};
     } else {
-      R.cnorm[level_offset(R.L) + c] = 0.0;
+      R.cnorm[level_offset(R.L) + x.c] = 0.0;
     }
-    if (i == j) R.trace_part[i] = 0.0;
+    if (x.i == x.j) R.trace_part[x.i] = 0.0;
   }
-  if (cnt == 0) return;
-  const Walk w = make_walk(R, i, j);
-  const double tau = R.tau;
-  const bool use_norms = R.use_norms != 0;
-  int64_t pos = off;
-  for (int kb = w.lo; kb <= w.hi; kb += kWave) {
-    const int k = kb + lane_id();
-    double a = -1.0, b = -1.0;
-    if (k <= w.hi) {
-      a = R.A.rm_sqrt[w.rowA + k];
-      b = R.B.cm_sqrt[w.colB + k];
+  uint64_t todo = ballot64(x.valid && cnt > 0);
+  while (todo) {
+    const int b = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const int r = __shfl(x.r, b, kWave);
+    const ReqDev& R = reqs[r];
+    Walk w;
+    w.lo = __shfl(x.w.lo, b, kWave);
+    w.hi = __shfl(x.w.hi, b, kWave);
+    w.rowA = __shfl(x.w.rowA, b, kWave);
+    w.colB = __shfl(x.w.colB, b, kWave);
+    const int64_t base = __shfl(off, b, kWave);
+    const int64_t end = base + __shfl(cnt, b, kWave);
+    const double tau = R.tau;
+    const bool use_norms = R.use_norms != 0;
+    int64_t pos = base;
+    for (int kb = w.lo; kb <= w.hi; kb += kWave) {
+      const int k = kb + lane_id();
+      double a = -1.0, bb = -1.0;
+      if (k <= w.hi) {
+        a = R.A.rm_sqrt[w.rowA + k];
+        bb = R.B.cm_sqrt[w.colB + k];
+      }
+      const bool both = (a >= 0.0) && (bb >= 0.0);
+      const bool keep = both && (!use_norms || a * bb >= tau);
+      const uint64_t mask = ballot64(keep);
+      const int64_t at = pos + popc64(mask & lanemask_lt());
+      if (keep && at < end) R.pairs[at] = make_int2(R.A.rm_slot[w.rowA + k], R.B.cm_slot[w.colB + k]);
+      pos += popc64(mask);
     }
-    const bool both = (a >= 0.0) && (b >= 0.0);
-    const bool keep = both && (!use_norms || a * b >= tau);
-    const uint64_t mask = ballot64(keep);
-    const int64_t at = pos + popc64(mask & lanemask_lt());
-    if (keep && at < off + cnt) R.pairs[at] = make_int2(R.A.rm_slot[w.rowA + k], R.B.cm_slot[w.colB + k]);
-    pos += popc64(mask);
   }
 }
 
@@ -166,31 +233,44 @@ hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_
                              const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
                              WorkUnit* wu, int32_t* queues, int nqueues) {
   if (nqueues > 256) return hipErrorInvalidValue;
-  const int64_t blocks = (total_c + 3) / 4;
+  const int64_t waves = (total_c + kWave - 1) / kWave;
+  const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, scanned,
                      bnd_all, cand_all, wu, queues, nqueues);
   return hipGetLastError();
 }
 
-// Per-request accounting: skipped-product bound sums, candidates, trace and
-// ||C||^2, each reduced in one fixed order (one workgroup per request).
-__global__ void __launch_bounds__(256) k_req_stats(const ReqDev* __restrict__ reqs, ReqStatsDev* __restrict__ out) {
+// Per-request accounting, reduced in one fixed order: partial sums over
+// chunks of kStatChunk C leaves (one workgroup each), then one workgroup per
+// request adds its partials in chunk order with the trace parts and gathers
+// the pyramid roots and truncation results, so that one copy brings every
+// statistic to the host.
+__global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict__ reqs, int nreq,
+                                                       StatPartial* __restrict__ partial) {
   __shared__ double red[4];
   __shared__ int64_t ired[4];
-  const ReqDev& R = reqs[blockIdx.x];
+  int lo = 0, hi = nreq - 1;
+  const int64_t chunk = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (reqs[mid].stat_base <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  const ReqDev& R = reqs[lo];
   const int64_t G2 = int64_t(R.G) * R.G;
-  double b1 = 0.0, b2 = 0.0, tr = 0.0;
+  const int64_t c0 = (chunk - R.stat_base) * kStatChunk;
+  const int64_t c1 = min<int64_t>(G2, c0 + kStatChunk);
+  double b1 = 0.0, b2 = 0.0;
   int64_t cand = 0;
-  for (int64_t c = threadIdx.x; c < G2; c += blockDim.x) {
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     const double b = R.bnd[c];
     b1 += b;
-    b2 += b * b;
+    const double bb = b * b;
+    b2 += bb;
     cand += R.ncand[c];
   }
-  for (int64_t i = threadIdx.x; i < R.G; i += blockDim.x) tr += R.trace_part[i];
   b1 = block_sum_f64(b1, red);
   b2 = block_sum_f64(b2, red);
-  tr = block_sum_f64(tr, red);
   cand = wave_sum_i64(cand);
   __syncthreads();
   if (lane_id() == 0) ired[threadIdx.x / kWave] = cand;
@@ -198,17 +278,52 @@ __global__ void __launch_bounds__(256) k_req_stats(const ReqDev* __restrict__ re
   if (threadIdx.x == 0) {
     int64_t t = 0;
     for (int w = 0; w < 4; ++w) t += ired[w];
-    out[blockIdx.x].B1 = b1;
-    out[blockIdx.x].B2sq = b2;
-    out[blockIdx.x].trace = tr;
-    out[blockIdx.x].normC_sq = R.cnorm[0];
-    out[blockIdx.x].n_candidates = t;
+    partial[chunk].b1 = b1;
+    partial[chunk].b2 = b2;
+    partial[chunk].cand = t;
   }
 }
 
-hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, ReqStatsDev* out) {
+__global__ void __launch_bounds__(256) k_stats_final(const ReqDev* __restrict__ reqs,
+                                                     const StatPartial* __restrict__ partial,
+                                                     ReqStatsDev* __restrict__ out) {
+  __shared__ double red[4];
+  const ReqDev& R = reqs[blockIdx.x];
+  const int64_t G2 = int64_t(R.G) * R.G;
+  const int64_t nch = (G2 + kStatChunk - 1) / kStatChunk;
+  double tr = 0.0;
+  for (int64_t i = threadIdx.x; i < R.G; i += blockDim.x) tr += R.trace_part[i];
+  tr = block_sum_f64(tr, red);
+  if (threadIdx.x == 0) {
+    double b1 = 0.0, b2 = 0.0;
+    int64_t cand = 0;
+    for (int64_t q = 0; q < nch; ++q) {
+      b1 += partial[R.stat_base + q].b1;
+      b2 += partial[R.stat_base + q].b2;
+      cand += partial[R.stat_base + q].cand;
+    }
+    ReqStatsDev o;
+    o.B1 = b1;
+    o.B2sq = b2;
+    o.trace = tr;
+    o.normC_sq = R.cnorm[0];
+    o.normA_sq = *R.rootA;
+    o.normB_sq = *R.rootB;
+    o.normAu_sq = *R.rootAu;
+    o.dA_sq = R.truncA ? R.truncA[0] : 0.0;
+    o.dB_sq = R.truncB ? R.truncB[0] : 0.0;
+    o.n_candidates = cand;
+    out[blockIdx.x] = o;
+  }
+}
+
+hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,
+                            ReqStatsDev* out) {
   if (nreq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_req_stats, dim3(uint32_t(nreq)), dim3(256), 0, s, reqs, out);
+  hipLaunchKernelGGL(k_stats_partial, dim3(uint32_t(nchunks)), dim3(256), 0, s, reqs, nreq, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stats_final, dim3(uint32_t(nreq)), dim3(256), 0, s, reqs, partial, out);
   return hipGetLastError();
 }
 

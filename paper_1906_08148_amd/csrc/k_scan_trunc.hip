@@ -131,155 +131,229 @@ hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t cou
 // Order the non-null leaves by the key (bits of the squared norm s, Morton
 // index m) -- for s >= 0 the IEEE bit pattern orders like the value -- and
 // drop the longest prefix whose summed squared norm is <= tau^2.  Only leaves
-// with s <= tau^2 can be in that prefix.  Instead of sorting, the largest key
-// K with F(K) = sum{ s : key <= K } <= tau^2 is built bit by bit from the top;
-// F is evaluated in one fixed order (a thread's strided share, then a fixed
-// tree), so each addition only grows with K and F is monotone in K.
+// with s <= tau^2 can be in that prefix (candidates).  For each candidate x,
+// F(x) = sum of s_y over candidates y with key_y <= key_x, summed in one
+// fixed order (candidate index); each addition only grows with x's key, so F
+// is monotone in the key and {x : F(x) <= tau^2} is a prefix of the order.
+// Small candidate sets evaluate F(x) for every x from LDS; large ones build
+// the largest admissible key bit by bit (the same F, evaluated per trial key).
+// All jobs of a batch share one set of launches.
 
-__global__ void k_trunc_flag(int64_t G2, const int32_t* __restrict__ slot, const double* __restrict__ leafnorm,
-                             double tau2, int32_t* __restrict__ flag) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= G2) return;
-  flag[m] = (slot[m] >= 0 && leafnorm[m] <= tau2) ? 1 : 0;
+__device__ __forceinline__ int find_job(const TruncJob* __restrict__ jobs, int njobs, int64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].base <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
-
-__global__ void k_trunc_compact(int64_t G2, const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
-                                const double* __restrict__ leafnorm, double* __restrict__ cs,
-                                int32_t* __restrict__ cm) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= G2 || !flag[m]) return;
-  cs[pos[m]] = leafnorm[m];
-  cm[pos[m]] = int32_t(m);
-}
-
-constexpr int kSelThreads = 1024;
-constexpr int kSelLds = 4096;  // candidates cached in LDS when they fit
 
 __device__ __forceinline__ bool key_le(uint64_t sb, uint32_t m, uint64_t khi, uint32_t klo) {
   return sb < khi || (sb == khi && m <= klo);
 }
 
-__global__ void __launch_bounds__(kSelThreads) k_trunc_select(const int64_t* __restrict__ mc_ptr,
-                                                              const double* __restrict__ cs,
-                                                              const int32_t* __restrict__ cm, int key_bits_lo,
-                                                              double tau2, uint64_t* __restrict__ kout,
-                                                              double* __restrict__ result) {
+__global__ void k_trunc_flag(const TruncJob* __restrict__ jobs, int njobs, int64_t total, int32_t* __restrict__ flag) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const TruncJob& J = jobs[find_job(jobs, njobs, g)];
+  const int64_t m = g - J.base;
+  flag[g] = (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
+}
+
+__global__ void k_trunc_compact(const TruncJob* __restrict__ jobs, int njobs, int64_t total,
+                                const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                                double* __restrict__ cs, int32_t* __restrict__ cm) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total || !flag[g]) return;
+  const TruncJob& J = jobs[find_job(jobs, njobs, g)];
+  const int64_t m = g - J.base;
+  cs[pos[g]] = J.leafnorm[m];
+  cm[pos[g]] = int32_t(m);
+}
+
+constexpr int kSelThreads = 1024;
+constexpr int kSelLds = 4096;  // candidate sets up to this size use the all-pairs form
+
+__global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ pos,
+                                                              const double* __restrict__ cs_all,
+                                                              const int32_t* __restrict__ cm_all,
+                                                              uint64_t* __restrict__ kst) {
   __shared__ double red[kSelThreads / kWave];
+  __shared__ int64_t ired[kSelThreads / kWave];
   __shared__ double s_lds[kSelLds];
   __shared__ uint32_t m_lds[kSelLds];
-  const int64_t mc = *mc_ptr;
-  const bool cached = mc <= kSelLds;
-  if (cached) {
-    for (int64_t i = threadIdx.x; i < mc; i += kSelThreads) {
-      s_lds[i] = cs[i];
-      m_lds[i] = uint32_t(cm[i]);
-    }
-  }
-  __syncthreads();
+  __shared__ uint64_t best_hi[kSelThreads / kWave];
+  __shared__ uint32_t best_lo[kSelThreads / kWave];
+  const TruncJob& J = jobs[blockIdx.x];
+  const int64_t c0 = pos[J.base];
+  const int64_t mc = pos[J.base + int64_t(J.G) * J.G] - c0;
+  const double* cs = cs_all + c0;
+  const int32_t* cm = cm_all + c0;
+  const double tau2 = J.tau2;
   uint64_t khi = 0;
   uint32_t klo = 0;
-  for (int b = 63 + key_bits_lo; b >= 0; --b) {
-    uint64_t thi = khi;
-    uint32_t tlo = klo;
-    if (b >= key_bits_lo) thi |= (uint64_t(1) << (b - key_bits_lo));
-    else tlo |= (uint32_t(1) << b);
-    double part = 0.0;
-    for (int64_t i = threadIdx.x; i < mc; i += kSelThreads) {
-      const double s = cached ? s_lds[i] : cs[i];
-      const uint32_t m = cached ? m_lds[i] : uint32_t(cm[i]);
-      if (key_le(__double_as_longlong(s), m, thi, tlo)) part += s;
-    }
-    const double F = block_sum_f64(part, red);
-    if (F <= tau2) {
-      khi = thi;
-      klo = tlo;
+  double F = 0.0;
+  int64_t cnt = 0;
+  if (mc <= kSelLds) {
+    for (int64_t t = threadIdx.x; t < mc; t += kSelThreads) {
+      s_lds[t] = cs[t];
+      m_lds[t] = uint32_t(cm[t]);
     }
     __syncthreads();
-  }
-  // final dropped sum and count for K*
-  double part = 0.0;
-  int64_t cnt = 0;
-  for (int64_t i = threadIdx.x; i < mc; i += kSelThreads) {
-    const double s = cached ? s_lds[i] : cs[i];
-    const uint32_t m = cached ? m_lds[i] : uint32_t(cm[i]);
-    if (key_le(__double_as_longlong(s), m, khi, klo)) {
-      part += s;
-      ++cnt;
+    // every candidate: F(x) in candidate-index order
+    uint64_t my_hi = 0;
+    uint32_t my_lo = 0;
+    double my_F = 0.0;
+    int64_t my_cnt = 0;
+    bool any = false;
+    for (int64_t x = threadIdx.x; x < mc; x += kSelThreads) {
+      const uint64_t xh = __double_as_longlong(s_lds[x]);
+      const uint32_t xl = m_lds[x];
+      double f = 0.0;
+      for (int64_t y = 0; y < mc; ++y) {
+        const double sy = s_lds[y];
+        if (key_le(__double_as_longlong(sy), m_lds[y], xh, xl)) f += sy;
+      }
+      if (f <= tau2) {
+        ++my_cnt;
+        if (!any || !key_le(xh, xl, my_hi, my_lo)) {
+          my_hi = xh;
+          my_lo = xl;
+          my_F = f;
+        }
+        any = true;
+      }
     }
-  }
-  const double F = block_sum_f64(part, red);
-  __shared__ int64_t cred[kSelThreads / kWave];
-  cnt = wave_sum_i64(cnt);
-  if (lane_id() == 0) cred[threadIdx.x / kWave] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
+    // wave then block reduction of (max key, its F) and the count
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t oh = __shfl_down(my_hi, off, kWave);
+      const uint32_t ol = __shfl_down(my_lo, off, kWave);
+      const double of = __shfl_down(my_F, off, kWave);
+      const int oa = __shfl_down(int(any), off, kWave);
+      my_cnt += __shfl_down(my_cnt, off, kWave);
+      if (oa && (!any || !key_le(oh, ol, my_hi, my_lo))) {
+        my_hi = oh;
+        my_lo = ol;
+        my_F = of;
+        any = true;
+      }
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+      best_hi[w] = any ? my_hi : 0;
+      best_lo[w] = any ? my_lo : 0;
+      red[w] = any ? my_F : -1.0;
+      ired[w] = my_cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      bool found = false;
+      for (int q = 0; q < kSelThreads / kWave; ++q) {
+        cnt += ired[q];
+        if (red[q] >= 0.0 && (!found || !key_le(best_hi[q], best_lo[q], khi, klo))) {
+          khi = best_hi[q];
+          klo = best_lo[q];
+          F = red[q];
+          found = true;
+        }
+      }
+      if (!found) {  // nothing dropped: an empty prefix
+        khi = 0;
+        klo = 0;
+        F = 0.0;
+      }
+    }
+  } else {
+    for (int b = 63 + J.key_bits_lo; b >= 0; --b) {
+      uint64_t thi = khi;
+      uint32_t tlo = klo;
+      if (b >= J.key_bits_lo) thi |= (uint64_t(1) << (b - J.key_bits_lo));
+      else tlo |= (uint32_t(1) << b);
+      double part = 0.0;
+      for (int64_t i = threadIdx.x; i < mc; i += kSelThreads) {
+        const double sv = cs[i];
+        if (key_le(__double_as_longlong(sv), uint32_t(cm[i]), thi, tlo)) part += sv;
+      }
+      const double Ft = block_sum_f64(part, red);
+      if (Ft <= tau2) {
+        khi = thi;
+        klo = tlo;
+      }
+      __syncthreads();
+    }
+    double part = 0.0;
     int64_t c = 0;
-    for (int w = 0; w < kSelThreads / kWave; ++w) c += cred[w];
-    kout[0] = khi;
-    kout[1] = klo;
-    result[0] = F;
-    result[1] = double(c);
+    for (int64_t i = threadIdx.x; i < mc; i += kSelThreads) {
+      const double sv = cs[i];
+      if (key_le(__double_as_longlong(sv), uint32_t(cm[i]), khi, klo)) {
+        part += sv;
+        ++c;
+      }
+    }
+    F = block_sum_f64(part, red);
+    c = wave_sum_i64(c);
+    if (lane_id() == 0) ired[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int q = 0; q < kSelThreads / kWave; ++q) cnt += ired[q];
+  }
+  if (threadIdx.x == 0) {
+    // an empty drop set is encoded as "drop nothing" by a count of zero
+    kst[3 * blockIdx.x] = khi;
+    kst[3 * blockIdx.x + 1] = klo;
+    kst[3 * blockIdx.x + 2] = uint64_t(cnt);
+    J.result[0] = cnt ? F : 0.0;
+    J.result[1] = double(cnt);
   }
 }
 
-__global__ void k_trunc_apply(int64_t G2, const int32_t* __restrict__ slot, const double* __restrict__ leafnorm,
-                              const int32_t* __restrict__ flag, const uint64_t* __restrict__ kst,
-                              int32_t* __restrict__ out_slot, double* __restrict__ out_norm) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= G2) return;
-  const double s = leafnorm[m];
-  const bool drop = flag[m] && key_le(__double_as_longlong(s), uint32_t(m), kst[0], uint32_t(kst[1]));
-  out_slot[m] = drop ? -1 : slot[m];
-  out_norm[m] = drop ? 0.0 : s;
+__global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int64_t total,
+                              const int32_t* __restrict__ flag, const uint64_t* __restrict__ kst) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int j = find_job(jobs, njobs, g);
+  const TruncJob& J = jobs[j];
+  const int64_t m = g - J.base;
+  const double s = J.leafnorm[m];
+  const bool drop = flag[g] && kst[3 * j + 2] != 0 &&
+                    key_le(__double_as_longlong(s), uint32_t(m), kst[3 * j], uint32_t(kst[3 * j + 1]));
+  J.out_slot[m] = drop ? -1 : J.slot[m];
+  J.out_norm[m] = drop ? 0.0 : s;
 }
 
-size_t trunc_scratch_bytes(int G) {
-  const int64_t G2 = int64_t(G) * G;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return al(G2 * 4) + al((G2 + 1) * 8) + al(G2 * 8) + al(G2 * 4) + al(16) + al(scan_scratch_bytes(G2));
+static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t trunc_batch_scratch_bytes(int njobs, int64_t total) {
+  return al256(total * 4) + al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) +
+         al256(size_t(njobs) * 24) + al256(scan_scratch_bytes(total));
 }
 
-hipError_t launch_trunc(hipStream_t s, int G, const int32_t* slot, const double* leafnorm, double tau2,
-                        int32_t* out_slot, double* out_leafnorm, void* scratch, size_t scratch_bytes,
-                        double* result_dev) {
-  const int64_t G2 = int64_t(G) * G;
-  if (scratch_bytes < trunc_scratch_bytes(G)) return hipErrorInvalidValue;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, int64_t total, void* scratch,
+                              size_t scratch_bytes) {
+  if (njobs == 0) return hipSuccess;
+  if (scratch_bytes < trunc_batch_scratch_bytes(njobs, total)) return hipErrorInvalidValue;
   char* p = static_cast<char*>(scratch);
   int32_t* flag = reinterpret_cast<int32_t*>(p);
-  p += al(G2 * 4);
+  p += al256(total * 4);
   int64_t* pos = reinterpret_cast<int64_t*>(p);
-  p += al((G2 + 1) * 8);
+  p += al256((total + 1) * 8);
   double* cs = reinterpret_cast<double*>(p);
-  p += al(G2 * 8);
+  p += al256(total * 8);
   int32_t* cm = reinterpret_cast<int32_t*>(p);
-  p += al(G2 * 4);
+  p += al256(total * 4);
   uint64_t* kst = reinterpret_cast<uint64_t*>(p);
-  p += al(16);
-  const uint32_t nb = uint32_t((G2 + 255) / 256);
-  hipLaunchKernelGGL(k_trunc_flag, dim3(nb), dim3(256), 0, s, G2, slot, leafnorm, tau2, flag);
+  p += al256(size_t(njobs) * 24);
+  const uint32_t nb = uint32_t((total + 255) / 256);
+  hipLaunchKernelGGL(k_trunc_flag, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int32_t* dummy = nullptr;
-  (void)dummy;
-  // exclusive positions of the candidates; pos[G2] = candidate count
-  const int64_t nbs = std::max<int64_t>(1, (G2 + kScanTile - 1) / kScanTile);
-  int64_t* sums = reinterpret_cast<int64_t*>(p);
-  hipLaunchKernelGGL((k_scan_tiles<int32_t>), dim3(uint32_t(nbs)), dim3(kScanThreads), 0, s, flag, G2, sums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nbs, pos + G2);
-  hipLaunchKernelGGL((k_scan_apply<int32_t, 0>), dim3(uint32_t(nbs)), dim3(kScanThreads), 0, s, flag, G2, sums,
-                     pos, nullptr);
-  e = hipGetLastError();
+  e = scan_impl<int32_t, 0>(s, flag, total, pos, nullptr, pos + total, p, scan_scratch_bytes(total));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trunc_compact, dim3(nb), dim3(256), 0, s, G2, flag, pos, leafnorm, cs, cm);
-  int key_bits_lo = 1;
-  while ((int64_t(1) << key_bits_lo) < G2) ++key_bits_lo;
-  hipLaunchKernelGGL(k_trunc_select, dim3(1), dim3(kSelThreads), 0, s, pos + G2, cs, cm, key_bits_lo, tau2, kst,
-                     result_dev);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trunc_apply, dim3(nb), dim3(256), 0, s, G2, slot, leafnorm, flag, kst, out_slot,
-                     out_leafnorm);
+  hipLaunchKernelGGL(k_trunc_compact, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, pos, cs, cm);
+  hipLaunchKernelGGL(k_trunc_select, dim3(uint32_t(njobs)), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, kst);
+  hipLaunchKernelGGL(k_trunc_apply, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, kst);
   return hipGetLastError();
 }
 
