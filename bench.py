@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB on the device (a plain copy "
+                         "kernel of known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -240,6 +243,12 @@ def main():
     host = make_inputs()
     dev = gpu_inputs(host)
     ctx = spamm.Context(arena_bytes=16 << 30)
+    if args.copy_calibration_mb:
+        src = torch.ones(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     log("bench: FP32 steps")
     total32, lat32, flops32, tm32, stats32 = timed_steps(ctx, dev, spamm.F32, args.steps, args.warmup)

@@ -4,6 +4,7 @@
 // enqueues and reads back.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -364,6 +365,11 @@ spamm_status spamm_ctx_create(int device, void* arena, size_t arena_bytes, spamm
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     x->c.n_cu = cus;
+  if (const char* e = std::getenv("SPAMM_GEMM_SCHED")) {
+    const std::string v(e);
+    x->c.gemm_sched = v == "global" ? 1 : v == "rm" ? 2 : 0;
+  }
+  if (const char* e = std::getenv("SPAMM_GEMM_KERNEL")) x->c.gemm_wave = std::string(e) == "wave";
   if (!x->c.stage(size_t(1) << 20)) {
     delete x;
     return SPAMM_EDEVICE;
@@ -770,28 +776,86 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     }
     Cs[r] = std::move(C);
   }
-  RegionP wus, queue;
+  // per-XCD slice tables of each launch group: pre[x][k] = units of queue x
+  // before request k's slice, Q[x] = first unit of queue x (group-relative)
+  std::vector<int64_t> sched;
+  std::vector<size_t> sched_off;
+  for (auto& gk : groups) {
+    const auto& rs = gk.second;
+    const int nq = int(rs.size());
+    sched_off.push_back(sched.size());
+    std::vector<int64_t> pre(kGemmQueues * (nq + 1), 0), Q(kGemmQueues + 1, 0);
+    const int ns = c->gemm_sched == 2 ? 1 : kGemmQueues;  // slices per request
+    for (int x = 0; x < kGemmQueues; ++x) {
+      int64_t acc = 0;
+      for (int k = 0; k < nq; ++k) {
+        const int64_t cn = ht[rs[k]].c_nonnull;
+        pre[x * (nq + 1) + k] = acc;
+        if (x < ns) acc += cn * (x + 1) / ns - cn * x / ns;
+      }
+      pre[x * (nq + 1) + nq] = acc;
+      Q[x + 1] = Q[x] + acc;
+    }
+    // queue bounds for the GEMM: the per-XCD slices, or one shared queue
+    // (queue 0 spans every unit, the others start empty); the placement
+    // offsets Q stay the per-XCD ones in both cases
+    std::vector<int64_t> Qq(Q);
+    if (c->gemm_sched != 0)
+      for (int x = 1; x <= kGemmQueues; ++x) Qq[x] = Q[kGemmQueues];
+    sched.insert(sched.end(), pre.begin(), pre.end());
+    sched.insert(sched.end(), Q.begin(), Q.end());
+    sched.insert(sched.end(), Qq.begin(), Qq.end());
+  }
+  RegionP wus, queue, schedd;
   ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
   ALLOC(queue, 1024, "queue counters");
+  ALLOC(schedd, std::max<size_t>(sched.size(), 1) * 8, "schedule tables");
+  if (groups.size() * kGemmQueues > 256) return fail(c, SPAMM_EUNSUPPORTED, "too many precision/leaf groups");
+  st = upload(c, schedd->ptr(), sched.data(), sched.size() * 8);
+  if (st != SPAMM_OK) return st;
+  {
+    int gj = 0;
+    for (auto& gk : groups) {
+      for (size_t k = 0; k < gk.second.size(); ++k) {
+        ReqDev& d = rd[gk.second[k]];
+        d.wu_base = launches[gj].second.first;
+        d.sched = P<int64_t>(schedd) + sched_off[gj];
+        d.sched_k = int32_t(k);
+        d.sched_n = int32_t(gk.second.size());
+        d.nslices = c->gemm_sched == 2 ? 1 : kGemmQueues;
+      }
+      ++gj;
+    }
+  }
   st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
   if (st != SPAMM_OK) return st;
   {
     TimedScope ts(c, kTPrune);
     SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
                                    P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus),
-                                   P<int32_t>(queue), int(launches.size())));
+                                   P<int32_t>(queue), int(groups.size()) * kGemmQueues));
   }
-  int qi = 0;
-  for (auto& l : launches) {
-    int32_t* qptr = P<int32_t>(queue) + qi++;
-    if (l.second.second == 0) continue;
+  int gi = 0;
+  for (auto& gk : groups) {
+    const int64_t nwu = launches[gi].second.second;
+    int32_t* qptr = P<int32_t>(queue) + gi * kGemmQueues;
+    const int64_t nq = int64_t(gk.second.size());
+    const int64_t* Qp = P<int64_t>(schedd) + sched_off[gi] + kGemmQueues * (nq + 1) + (kGemmQueues + 1);
+    const WorkUnit* wbase = P<WorkUnit>(wus) + launches[gi].second.first;
+    ++gi;
+    if (nwu == 0) continue;
     TimedScope ts(c, kTGemm);
     if (c->timing) {
-      for (int r : groups[l.first]) c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs *
-                                                   double(ht[r].n_kept);
+      for (int r : gk.second)
+        c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
     }
-    SPAMM_HIP(c, launch_gemm(c->stream, l.first.first, l.first.second, P<ReqDev>(reqd), P<WorkUnit>(wus),
-                             l.second.first, l.second.second, qptr, c->n_cu));
+    if (c->gemm_wave && gemm_wave_supported(gk.first.first, gk.first.second)) {
+      SPAMM_HIP(c, launch_gemm_wave(c->stream, gk.first.first, gk.first.second, P<ReqDev>(reqd), wbase, Qp, nwu,
+                                    qptr, c->n_cu));
+    } else {
+      SPAMM_HIP(c, launch_gemm(c->stream, gk.first.first, gk.first.second, P<ReqDev>(reqd), wbase, Qp, nwu, qptr,
+                               c->n_cu));
+    }
   }
   {
     std::vector<double*> nv;

@@ -113,6 +113,8 @@ struct Ctx {
   void* host_stage = nullptr;
   size_t host_stage_bytes = 0;
   int n_cu = 256;
+  int gemm_sched = 0;     // 0: per-XCD queues, 1: one queue in XCD-major order, 2: one queue, request-major
+  bool gemm_wave = false;  // one-wave-per-leaf kernel (where it applies) instead of the LDS kernel
   std::map<uint64_t, int> tuned;  // reserved for autotune results
   int live_handles = 0;
   RegionP alloc(size_t bytes);    // nullptr on exhaustion
@@ -212,6 +214,13 @@ struct ReqDev {
   const double* truncA;   // nullptr when A was not truncated
   const double* truncB;
   int64_t stat_base;      // first statistics chunk of this request
+  // GEMM schedule: this request's group table (pre[8 * (n + 1)], then the
+  // placement offsets Q[9] of the per-XCD slices, then the queue bounds the
+  // GEMM pops from, 9 more) and its index k in the group; see k_gemm.hip
+  const int64_t* sched;
+  int32_t sched_k, sched_n;
+  int32_t nslices;        // slices per request in the placement (8 per-XCD, or 1)
+  int32_t pad2_;
 };
 
 // One truncation inside a batch (leaf-block truncation with budget tau^2).
@@ -244,7 +253,10 @@ struct PrepJob {
 
 struct WorkUnit {
   int32_t req;
-  int32_t c;  // Morton index of the C leaf
+  int32_t c;      // Morton index of the C leaf
+  int64_t pb;     // first product in the request's pair list
+  int32_t cnt;    // number of products
+  int32_t cslot;  // slot of the C leaf in C's store
 };
 
 // Per-request totals read back after the counting pass.
@@ -312,10 +324,15 @@ hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq,
 hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                              const int64_t* scanned, const double* bnd_all,
                              const int32_t* cand_all, WorkUnit* wu, int32_t* queues, int nqueues);
-// gemm over work units [wu0, wu0 + nwu); *queue must be zero at launch
+// GEMM over the work units of one (precision, leaf size) group, stored
+// XCD-major: queue x owns wu[Q[x] .. Q[x+1]); queues[0..8) must be zero.
+constexpr int kGemmQueues = 8;
 hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
-                       int64_t wu0, int64_t nwu, int32_t* queue, int n_cu);
+                       const int64_t* Q, int64_t nwu, int32_t* queues, int n_cu);
 bool gemm_supported(int prec, int bs);
+bool gemm_wave_supported(int prec, int bs);
+hipError_t launch_gemm_wave(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
+                            const int64_t* Q, int64_t nwu, int32_t* queues, int n_cu);
 hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
 hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,

@@ -6,7 +6,8 @@ namespace spamm {
 
 bool gemm_bf16_built() { return false; }
 
-hipError_t launch_gemm_bf16(hipStream_t, int, int, const ReqDev*, const WorkUnit*, int64_t, int64_t, int32_t*, int) {
+hipError_t launch_gemm_bf16(hipStream_t, int, int, const ReqDev*, const WorkUnit*, const int64_t*, int64_t, int32_t*,
+                            int) {
   return hipErrorNotSupported;
 }
 

@@ -57,6 +57,13 @@ struct LaneLeaf {
 
 __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
                                               int64_t g) {
+  // one scalar search per wave when its 64 leaves lie in one request
+  const int64_t g0 = g - lane_id();
+  const uint32_t g0lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(g0)));
+  const uint32_t g0hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(g0) >> 32));
+  const int64_t gw = int64_t((uint64_t(g0hi) << 32) | g0lo);
+  const int rw = find_req(reqs, nreq, gw);
+  const bool whole = reqs[rw].cbase + int64_t(reqs[rw].G) * reqs[rw].G >= gw + kWave;
   LaneLeaf x;
   x.valid = g < total_c;
   x.r = 0;
@@ -65,7 +72,7 @@ __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, i
   x.w.hi = 0;
   x.w.rowA = x.w.colB = 0;
   if (x.valid) {
-    x.r = find_req(reqs, nreq, g);
+    x.r = whole ? rw : find_req(reqs, nreq, g);
     const ReqDev& R = reqs[x.r];
     x.c = uint32_t(g - R.cbase);
     demorton(x.c, x.i, x.j);
@@ -190,7 +197,14 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
     R.ncand[x.c] = cand_all[g];
     if (flag) {
       R.ckeys[cs] = int32_t(x.c);
-      wu[R.wu_base + cs] = WorkUnit{x.r, int32_t(x.c)};
+      // XCD-major position: slice x of this request inside queue x
+      const int64_t cn = ((scanned[R.cbase + G2] >> kCntBits) - (s0 >> kCntBits));
+      const int n = R.sched_n, ns = R.nslices;
+      int q = 0;
+      while (q + 1 < ns && cn * (q + 1) / ns <= cs) ++q;
+      const int64_t* Q = R.sched + 8 * (n + 1);  // placement offsets of the slices
+      const int64_t at = Q[q] + R.sched[q * (n + 1) + R.sched_k] + (cs - cn * q / ns);
+      if (at >= 0 && at < Q[8]) wu[R.wu_base + at] = WorkUnit{x.r, int32_t(x.c), off, int32_t(cnt), cs};
     } else {
       R.cnorm[level_offset(R.L) + x.c] = 0.0;
     }

@@ -173,17 +173,49 @@ __global__ void k_trunc_compact(const TruncJob* __restrict__ jobs, int njobs, in
 }
 
 constexpr int kSelThreads = 1024;
-constexpr int kSelLds = 4096;  // candidate sets up to this size use the all-pairs form
+constexpr int kSelLds = 4096;   // candidate sets up to this size use the all-pairs form
+constexpr int kSelSplit = 16;   // workgroups per job in the all-pairs form
 
+// All-pairs form, part 1: workgroup (job, part) evaluates F(x) for the
+// candidates x = part, part + kSelSplit, ... of its job.
+__global__ void __launch_bounds__(kSelThreads) k_trunc_fx(const TruncJob* __restrict__ jobs,
+                                                          const int64_t* __restrict__ pos,
+                                                          const double* __restrict__ cs_all,
+                                                          const int32_t* __restrict__ cm_all,
+                                                          double* __restrict__ fx_all) {
+  __shared__ double s_lds[kSelLds];
+  __shared__ uint32_t m_lds[kSelLds];
+  const int job = blockIdx.x / kSelSplit, part = blockIdx.x % kSelSplit;
+  const TruncJob& J = jobs[job];
+  const int64_t c0 = pos[J.base];
+  const int64_t mc = pos[J.base + int64_t(J.G) * J.G] - c0;
+  if (mc > kSelLds || mc == 0) return;
+  for (int64_t t = threadIdx.x; t < mc; t += kSelThreads) {
+    s_lds[t] = cs_all[c0 + t];
+    m_lds[t] = uint32_t(cm_all[c0 + t]);
+  }
+  __syncthreads();
+  for (int64_t x = part + int64_t(threadIdx.x) * kSelSplit; x < mc; x += int64_t(kSelThreads) * kSelSplit) {
+    const uint64_t xh = __double_as_longlong(s_lds[x]);
+    const uint32_t xl = m_lds[x];
+    double f = 0.0;
+    for (int64_t y = 0; y < mc; ++y) {
+      const double sy = s_lds[y];
+      if (key_le(__double_as_longlong(sy), m_lds[y], xh, xl)) f += sy;
+    }
+    fx_all[c0 + x] = f;
+  }
+}
+
+// Part 2 (and the large form): one workgroup per job picks the drop set.
 __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __restrict__ jobs,
                                                               const int64_t* __restrict__ pos,
                                                               const double* __restrict__ cs_all,
                                                               const int32_t* __restrict__ cm_all,
+                                                              const double* __restrict__ fx_all,
                                                               uint64_t* __restrict__ kst) {
   __shared__ double red[kSelThreads / kWave];
   __shared__ int64_t ired[kSelThreads / kWave];
-  __shared__ double s_lds[kSelLds];
-  __shared__ uint32_t m_lds[kSelLds];
   __shared__ uint64_t best_hi[kSelThreads / kWave];
   __shared__ uint32_t best_lo[kSelThreads / kWave];
   const TruncJob& J = jobs[blockIdx.x];
@@ -197,26 +229,17 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
   double F = 0.0;
   int64_t cnt = 0;
   if (mc <= kSelLds) {
-    for (int64_t t = threadIdx.x; t < mc; t += kSelThreads) {
-      s_lds[t] = cs[t];
-      m_lds[t] = uint32_t(cm[t]);
-    }
-    __syncthreads();
-    // every candidate: F(x) in candidate-index order
+    // max key (and its F) over the candidates with F(x) <= tau^2, and their count
     uint64_t my_hi = 0;
     uint32_t my_lo = 0;
     double my_F = 0.0;
     int64_t my_cnt = 0;
     bool any = false;
     for (int64_t x = threadIdx.x; x < mc; x += kSelThreads) {
-      const uint64_t xh = __double_as_longlong(s_lds[x]);
-      const uint32_t xl = m_lds[x];
-      double f = 0.0;
-      for (int64_t y = 0; y < mc; ++y) {
-        const double sy = s_lds[y];
-        if (key_le(__double_as_longlong(sy), m_lds[y], xh, xl)) f += sy;
-      }
+      const double f = fx_all[c0 + x];
       if (f <= tau2) {
+        const uint64_t xh = __double_as_longlong(cs[x]);
+        const uint32_t xl = uint32_t(cm[x]);
         ++my_cnt;
         if (!any || !key_le(xh, xl, my_hi, my_lo)) {
           my_hi = xh;
@@ -226,7 +249,6 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
         any = true;
       }
     }
-    // wave then block reduction of (max key, its F) and the count
     for (int off = 32; off >= 1; off >>= 1) {
       const uint64_t oh = __shfl_down(my_hi, off, kWave);
       const uint32_t ol = __shfl_down(my_lo, off, kWave);
@@ -258,11 +280,6 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
           F = red[q];
           found = true;
         }
-      }
-      if (!found) {  // nothing dropped: an empty prefix
-        khi = 0;
-        klo = 0;
-        F = 0.0;
       }
     }
   } else {
@@ -300,7 +317,7 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
       for (int q = 0; q < kSelThreads / kWave; ++q) cnt += ired[q];
   }
   if (threadIdx.x == 0) {
-    // an empty drop set is encoded as "drop nothing" by a count of zero
+    // a count of zero means nothing is dropped
     kst[3 * blockIdx.x] = khi;
     kst[3 * blockIdx.x + 1] = klo;
     kst[3 * blockIdx.x + 2] = uint64_t(cnt);
@@ -326,7 +343,7 @@ __global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int6
 static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t trunc_batch_scratch_bytes(int njobs, int64_t total) {
-  return al256(total * 4) + al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) +
+  return al256(total * 4) + al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) + al256(total * 8) +
          al256(size_t(njobs) * 24) + al256(scan_scratch_bytes(total));
 }
 
@@ -343,6 +360,8 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   p += al256(total * 8);
   int32_t* cm = reinterpret_cast<int32_t*>(p);
   p += al256(total * 4);
+  double* fx = reinterpret_cast<double*>(p);
+  p += al256(total * 8);
   uint64_t* kst = reinterpret_cast<uint64_t*>(p);
   p += al256(size_t(njobs) * 24);
   const uint32_t nb = uint32_t((total + 255) / 256);
@@ -352,7 +371,8 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   e = scan_impl<int32_t, 0>(s, flag, total, pos, nullptr, pos + total, p, scan_scratch_bytes(total));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_trunc_compact, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, pos, cs, cm);
-  hipLaunchKernelGGL(k_trunc_select, dim3(uint32_t(njobs)), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, kst);
+  hipLaunchKernelGGL(k_trunc_fx, dim3(uint32_t(njobs) * kSelSplit), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx);
+  hipLaunchKernelGGL(k_trunc_select, dim3(uint32_t(njobs)), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx, kst);
   hipLaunchKernelGGL(k_trunc_apply, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, kst);
   return hipGetLastError();
 }

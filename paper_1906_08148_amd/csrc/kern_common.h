@@ -9,6 +9,22 @@ namespace spamm {
 
 constexpr int kWave = 64;
 
+// Pointers read from descriptor tables lose their address space, and the
+// compiler then emits flat loads, which also count against lgkmcnt: every
+// wait on an LDS read would then wait for outstanding global loads too.
+// These casts restore the global address space (and scalar loads where the
+// address is wave-uniform).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
 // Morton (Z-order) key of block (r, c): row bit above column bit, so the
 // four children of node m are 4m + 2a + b for (2r + a, 2c + b).
 __device__ __forceinline__ uint32_t spread_bits(uint32_t x) {

@@ -111,11 +111,14 @@ _SIGS = {
 }
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libspamm.so (after torch, so both share one HIP runtime)."""
+def load_library(path: str | None = None):
+    """Load libspamm.so (after torch, so both share one HIP runtime).  The
+    environment variable SPAMM_LIB may name another build of the library."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("SPAMM_LIB", LIB_PATH)
     import torch  # noqa: F401  (binds libamdhip64 first)
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
@@ -129,7 +132,7 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-def exported_symbols(path: str = LIB_PATH):
+def exported_symbols(path: str | None = None):
     lib = load_library(path)
     return {name for name in _SIGS if hasattr(lib, name)}
 

@@ -212,3 +212,50 @@ def test_config2_full(ctx):
             for mode in MODES:
                 for prec in (spamm.F64, spamm.F32):
                     check_product(ctx, M, M, T, T, tau, mode, prec, alias=True)
+
+
+def test_gemm_schedules_agree_bitwise():
+    """Per-XCD queues and one shared queue give bitwise the same C: each C
+    leaf is summed by one workgroup in the plan's order either way."""
+    import os
+    import torch
+    print("case: schedules", flush=True)
+    A = synth.DecaySpec("1d", 8192, 0.2, seed=2).dense()
+    res = {}
+    for mode in ("xcd", "global"):
+        os.environ["SPAMM_GEMM_SCHED"] = mode
+        try:
+            c = spamm.Context(arena_bytes=2 << 30)
+        finally:
+            del os.environ["SPAMM_GEMM_SCHED"]
+        M = c.build(dev(A), 64)
+        ps = c.multiply_batch([dict(A=M, B=M, tau=t, mode=m, prec=spamm.F32)
+                               for t in (1e-4, 1e-8) for m in MODES])
+        res[mode] = [c.to_dense(p.C).cpu() for p in ps]
+        for p in ps:
+            p.C.release()
+        M.release()
+        c.close()
+    for a, b in zip(res["xcd"], res["global"]):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("bs", [16, 32, 64])
+def test_wave_kernel_parity(bs):
+    """The one-wave-per-leaf GEMM (selected with SPAMM_GEMM_KERNEL=wave)
+    against the oracle, FP32 and FP64 where it applies."""
+    import os
+    print(f"case: wave kernel bs={bs}", flush=True)
+    os.environ["SPAMM_GEMM_KERNEL"] = "wave"
+    try:
+        c = spamm.Context(arena_bytes=1 << 30)
+    finally:
+        del os.environ["SPAMM_GEMM_KERNEL"]
+    A = synth.DecaySpec("1d", 1500, 0.3, seed=11).dense()
+    B = synth.DecaySpec("1d", 1500, 0.4, seed=12).dense()
+    TA, TB = O.build(A, bs), O.build(B, bs)
+    MA, MB = c.build(dev(A), bs), c.build(dev(B), bs)
+    for mode in MODES:
+        for prec in (spamm.F64, spamm.F32):
+            check_product(c, MA, MB, TA, TB, 1e-5, mode, prec)
+    c.close()
