@@ -35,7 +35,7 @@ SEED = 1
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
 GEMM_SOURCE = os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "k_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leaf_gemm_f32_bs64_config2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f32_leaf64_decay1d_n16384_batch18_traffic.json")
 
 
 def log(msg):
