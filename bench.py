@@ -84,14 +84,15 @@ def run_step(ctx, dev, prec, keep=False):
 
 
 def timed_steps(ctx, dev, prec, steps, warmup):
+    """Throughput and latency over `steps` steps with the library's event
+    timing off, then the same number of steps with it on for the per-phase
+    and per-launch kernel times (events add a little host work)."""
     import torch
     for _ in range(warmup):
         run_step(ctx, dev, prec)
     torch.cuda.synchronize()
-    ctx.timing(enable=True, reset=True)
     lat = []
     flops = 0.0
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s0 = time.perf_counter()
@@ -101,6 +102,10 @@ def timed_steps(ctx, dev, prec, steps, warmup):
         flops += sum(s["flops"] for s in stats)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    ctx.timing(enable=True, reset=True)
+    for _ in range(steps):
+        run_step(ctx, dev, prec)
+    torch.cuda.synchronize()
     tm = ctx.timing(enable=False, reset=True)
     return total, lat, flops, tm, stats
 
@@ -278,7 +283,7 @@ def main():
         "kept_products_per_step": int(sum(s["n_kept"] for s in stats32)),
         "phases_ms_per_step": {k: round(tm32[k + "_ms"] / args.steps, 4)
                                for k in ("build", "trunc", "prune", "gemm", "pyramid")},
-        "roofline": {"kernel": "k_gemm<float,64> (persistent MFMA leaf GEMM)", "bound": "mfma",
+        "roofline": {"kernel": "k_gemm<SPAMM_F32,64> (persistent MFMA leaf GEMM)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
                      "traffic": traffic_for(flops_per_launch),

@@ -71,7 +71,7 @@ size_t spamm_mat::device_bytes() const {
   for (auto* r : {&slot, &norms, &rm_sqrt, &rm_slot, &cm_sqrt, &cm_slot, &ranges, &plan_off, &plan_pairs, &plan_bnd})
     if (*r) b += (*r)->bytes;
   if (store) {
-    for (auto* r : {&store->keys, &store->f64, &store->f32, &store->bf16hi, &store->bf16lo})
+    for (auto* r : {&store->keys, &store->f64, &store->f32, &store->bf16, &store->bf16t})
       if (*r) b += (*r)->bytes;
   }
   return b;
@@ -108,24 +108,59 @@ spamm_status sync_stream(Ctx* c) {
   return SPAMM_OK;
 }
 
-// Wait until earlier uploads from the pinned staging buffer have been read.
-hipEvent_t g_stage_event = nullptr;
-
 spamm_status upload(Ctx* c, void* dev, const void* host, size_t bytes) {
   if (bytes == 0) return SPAMM_OK;
-  if (!g_stage_event) SPAMM_HIP(c, hipEventCreateWithFlags(&g_stage_event, hipEventDisableTiming));
-  SPAMM_HIP(c, hipEventSynchronize(g_stage_event));
-  void* st = c->stage(bytes);
-  if (!st) return fail(c, SPAMM_EDEVICE, "hipHostMalloc of staging buffer failed");
-  std::memcpy(st, host, bytes);
-  SPAMM_HIP(c, hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, c->stream));
-  SPAMM_HIP(c, hipEventRecord(g_stage_event, c->stream));
+  const size_t need = (bytes + 255) / 256 * 256;
+  if (need > c->up_bytes) {  // (re)allocate the ring once every copy out of it is done
+    SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& r : c->up_inflight) c->up_events.push_back(r.ev);
+    c->up_inflight.clear();
+    if (c->up_ring) SPAMM_HIP(c, hipHostFree(c->up_ring));
+    c->up_ring = nullptr;
+    c->up_bytes = 0;
+    const size_t want = std::max<size_t>(need, size_t(8) << 20);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess)
+      return fail(c, SPAMM_EDEVICE, "hipHostMalloc of the upload ring failed");
+    c->up_ring = static_cast<char*>(p);
+    c->up_bytes = want;
+    c->up_head = 0;
+  }
+  if (c->up_head + need > c->up_bytes) c->up_head = 0;
+  const size_t s = c->up_head, e = s + need;
+  // wait for the newest earlier copy that read any of [s, e); events on one
+  // stream complete in order, so every copy before it is done too
+  int last = -1;
+  for (int i = 0; i < int(c->up_inflight.size()); ++i) {
+    const auto& r = c->up_inflight[i];
+    if (r.s < e && s < r.e) last = i;
+  }
+  if (last >= 0) SPAMM_HIP(c, hipEventSynchronize(c->up_inflight[last].ev));
+  for (int i = 0; i <= last; ++i) {
+    c->up_events.push_back(c->up_inflight.front().ev);
+    c->up_inflight.pop_front();
+  }
+  while (!c->up_inflight.empty() && hipEventQuery(c->up_inflight.front().ev) == hipSuccess) {
+    c->up_events.push_back(c->up_inflight.front().ev);
+    c->up_inflight.pop_front();
+  }
+  std::memcpy(c->up_ring + s, host, bytes);
+  SPAMM_HIP(c, hipMemcpyAsync(dev, c->up_ring + s, bytes, hipMemcpyHostToDevice, c->stream));
+  hipEvent_t ev = nullptr;
+  if (!c->up_events.empty()) {
+    ev = c->up_events.back();
+    c->up_events.pop_back();
+  } else {
+    SPAMM_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  SPAMM_HIP(c, hipEventRecord(ev, c->stream));
+  c->up_inflight.push_back({s, e, ev});
+  c->up_head = e;
   return SPAMM_OK;
 }
 
 spamm_status download(Ctx* c, void* host, const void* dev, size_t bytes) {
   if (bytes == 0) return SPAMM_OK;
-  if (g_stage_event) SPAMM_HIP(c, hipEventSynchronize(g_stage_event));
   void* st = c->stage(bytes);
   if (!st) return fail(c, SPAMM_EDEVICE, "hipHostMalloc of staging buffer failed");
   SPAMM_HIP(c, hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -144,6 +179,13 @@ spamm_status nomem(Ctx* c, const char* what, size_t bytes) {
   do {                                                          \
     (var) = c->alloc(bytes);                                    \
     if (!(var)) return nomem(c, what, size_t(bytes));           \
+  } while (0)
+// leaf copies are aligned to their leaf size so that a leaf is one index
+// from the arena base
+#define ALLOC_LEAVES(var, nleaf, leaf_bytes, what)                                      \
+  do {                                                                                  \
+    (var) = c->alloc(size_t(std::max<int64_t>(nleaf, 1)) * (leaf_bytes), (leaf_bytes)); \
+    if (!(var)) return nomem(c, what, size_t(nleaf) * (leaf_bytes));                   \
   } while (0)
 
 // Handle skeleton with the per-level arrays (no leaf storage).
@@ -226,13 +268,13 @@ spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vect
 spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask) {
   s.nleaf = nleaf;
   s.bs = bs;
-  const int64_t e = nleaf * bs * bs;
+  const size_t e2 = size_t(bs) * bs;
   ALLOC(s.keys, std::max<int64_t>(nleaf, 1) * 4, "leaf keys");
-  if (mask & SPAMM_STORE_F64) ALLOC(s.f64, e * 8, "FP64 leaves");
-  if (mask & SPAMM_STORE_F32) ALLOC(s.f32, e * 4, "FP32 leaves");
+  if (mask & SPAMM_STORE_F64) ALLOC_LEAVES(s.f64, nleaf, e2 * 8, "FP64 leaves");
+  if (mask & SPAMM_STORE_F32) ALLOC_LEAVES(s.f32, nleaf, e2 * 4, "FP32 leaves");
   if (mask & SPAMM_STORE_BF16) {
-    ALLOC(s.bf16hi, e * 2, "BF16 hi leaves");
-    ALLOC(s.bf16lo, e * 2, "BF16 lo leaves");
+    ALLOC_LEAVES(s.bf16, nleaf, e2 * 4, "BF16 hi/lo leaves");
+    ALLOC_LEAVES(s.bf16t, nleaf, e2 * 4, "transposed BF16 hi/lo leaves");
   }
   return SPAMM_OK;
 }
@@ -242,23 +284,23 @@ spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask)
 spamm_status ensure_store(Ctx* c, Store& s, uint32_t need) {
   const uint32_t missing = need & ~s.mask();
   if (!missing) return SPAMM_OK;
-  const int64_t e = s.nleaf * s.bs * s.bs;
-  RegionP o64, o32, ohi, olo;
-  if (missing & SPAMM_STORE_F64) ALLOC(o64, e * 8, "FP64 leaves");
-  if (missing & SPAMM_STORE_F32) ALLOC(o32, e * 4, "FP32 leaves");
+  const size_t e2 = size_t(s.bs) * s.bs;
+  RegionP o64, o32, o16, o16t;
+  if (missing & SPAMM_STORE_F64) ALLOC_LEAVES(o64, s.nleaf, e2 * 8, "FP64 leaves");
+  if (missing & SPAMM_STORE_F32) ALLOC_LEAVES(o32, s.nleaf, e2 * 4, "FP32 leaves");
   if (missing & SPAMM_STORE_BF16) {
-    ALLOC(ohi, e * 2, "BF16 hi leaves");
-    ALLOC(olo, e * 2, "BF16 lo leaves");
+    ALLOC_LEAVES(o16, s.nleaf, e2 * 4, "BF16 hi/lo leaves");
+    ALLOC_LEAVES(o16t, s.nleaf, e2 * 4, "transposed BF16 hi/lo leaves");
   }
   if (!s.f64 && !s.f32) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 copy to derive from");
   TimedScope ts(c, kTBuild);
-  SPAMM_HIP(c, launch_derive_store(c->stream, e, P<double>(s.f64), s.f64 ? nullptr : P<float>(s.f32), P<double>(o64),
-                                   P<float>(o32), P<uint16_t>(ohi), P<uint16_t>(olo)));
+  SPAMM_HIP(c, launch_derive_store(c->stream, s.nleaf, s.bs, P<double>(s.f64), s.f64 ? nullptr : P<float>(s.f32),
+                                   P<double>(o64), P<float>(o32), P<uint16_t>(o16), P<uint16_t>(o16t)));
   if (o64) s.f64 = o64;
   if (o32) s.f32 = o32;
-  if (ohi) {
-    s.bf16hi = ohi;
-    s.bf16lo = olo;
+  if (o16) {
+    s.bf16 = o16;
+    s.bf16t = o16t;
   }
   return SPAMM_OK;
 }
@@ -365,11 +407,7 @@ spamm_status spamm_ctx_create(int device, void* arena, size_t arena_bytes, spamm
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     x->c.n_cu = cus;
-  if (const char* e = std::getenv("SPAMM_GEMM_SCHED")) {
-    const std::string v(e);
-    x->c.gemm_sched = v == "global" ? 1 : v == "rm" ? 2 : 0;
-  }
-  if (const char* e = std::getenv("SPAMM_GEMM_KERNEL")) x->c.gemm_wave = std::string(e) == "wave";
+  if (const char* e = std::getenv("SPAMM_GEMM_SCHED")) x->c.gemm_sched = std::string(e) == "rm" ? 1 : 0;
   if (!x->c.stage(size_t(1) << 20)) {
     delete x;
     return SPAMM_EDEVICE;
@@ -384,8 +422,11 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   if (c->live_handles != 0) return fail(c, SPAMM_EINVAL, "handles still alive");
   hipStreamSynchronize(c->stream);
   c->collect_timing();
-  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
-  if (c->host_stage) hipHostFree(c->host_stage);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  for (auto& r : c->up_inflight) (void)hipEventDestroy(r.ev);
+  for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
+  if (c->up_ring) (void)hipHostFree(c->up_ring);
+  if (c->host_stage) (void)hipHostFree(c->host_stage);
   delete ctx;
   return SPAMM_OK;
 }
@@ -475,7 +516,7 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
   SPAMM_HIP(c, launch_copy_dense_leaves(c->stream, dense, n, ld, leaf, hb.total, P<int32_t>(m->store->keys),
                                         P<double>(m->store->f64), P<float>(m->store->f32),
-                                        P<uint16_t>(m->store->bf16hi), P<uint16_t>(m->store->bf16lo)));
+                                        P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
   return finish_build(c, m, out);
 }
 
@@ -528,7 +569,7 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
   SPAMM_HIP(c, launch_copy_block_leaves(c->stream, n, leaf, hb.total, P<int32_t>(m->store->keys), P<int32_t>(src),
                                         data, P<double>(m->store->f64), P<float>(m->store->f32),
-                                        P<uint16_t>(m->store->bf16hi), P<uint16_t>(m->store->bf16lo)));
+                                        P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
   return finish_build(c, m, out);
 }
 
@@ -742,23 +783,40 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     d.ncand = P<int32_t>(cand_r[r]);
     d.trace_part = P<double>(trace_r[r]);
     d.cstore = q.prec == SPAMM_F64 ? C->store->f64->ptr() : C->store->f32->ptr();
+    // operands, pairs and C leaves as indices from the arena base
+    const char* base = c->arena.base();
     const Store& as = *Au[r]->store;
     const Store& bs = *Bu[r]->store;
+    const size_t e2 = size_t(q.A->bs) * q.A->bs;
+    const void *Ap, *Bp;
+    size_t lb;
     switch (q.prec) {
       case SPAMM_F64:
-        d.Astore = as.f64->ptr();
-        d.Bstore = bs.f64->ptr();
+        Ap = as.f64->ptr();
+        Bp = bs.f64->ptr();
+        lb = e2 * 8;
         break;
       case SPAMM_F32:
-        d.Astore = as.f32->ptr();
-        d.Bstore = bs.f32->ptr();
+        Ap = as.f32->ptr();
+        Bp = bs.f32->ptr();
+        lb = e2 * 4;
         break;
       default:
-        d.Astore = as.bf16hi->ptr();
-        d.Bstore = bs.bf16hi->ptr();
-        d.Astore_lo = as.bf16lo->ptr();
-        d.Bstore_lo = bs.bf16lo->ptr();
+        Ap = as.bf16->ptr();
+        Bp = bs.bf16t->ptr();
+        lb = e2 * 4;
     }
+    const size_t lc = e2 * (q.prec == SPAMM_F64 ? 8 : 4);
+    const size_t ao = static_cast<const char*>(Ap) - base, bo = static_cast<const char*>(Bp) - base;
+    const size_t co = static_cast<const char*>(d.cstore) - base, po = reinterpret_cast<const char*>(d.pairs) - base;
+    if (ao % lb || bo % lb || co % lc || po % 8) return fail(c, SPAMM_EDEVICE, "leaf store not aligned in the arena");
+    d.aoff = int64_t(ao / lb);
+    d.boff = int64_t(bo / lb);
+    d.cidx = int64_t(co / lc);
+    d.pairs_idx = int64_t(po / 8);
+    if (d.aoff + as.nleaf > INT32_MAX || d.boff + bs.nleaf > INT32_MAX || d.cidx + cn > INT32_MAX)
+      return fail(c, SPAMM_EUNSUPPORTED, "arena too large for 32-bit leaf indices at this leaf size");
+    C->plan_aoff = d.aoff;
     if (q.ep) {
       d.use_ep = 1;
       d.alpha = q.ep->alpha;
@@ -776,17 +834,17 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     }
     Cs[r] = std::move(C);
   }
-  // per-XCD slice tables of each launch group: pre[x][k] = units of queue x
-  // before request k's slice, Q[x] = first unit of queue x (group-relative)
+  // placement tables of each launch group: pre[x][k] = units of slice x
+  // before request k's part, Q[x] = first unit of slice x (group-relative)
   std::vector<int64_t> sched;
   std::vector<size_t> sched_off;
+  const int ns = c->gemm_sched == 1 ? 1 : kXcds;  // slices per request
   for (auto& gk : groups) {
     const auto& rs = gk.second;
     const int nq = int(rs.size());
     sched_off.push_back(sched.size());
-    std::vector<int64_t> pre(kGemmQueues * (nq + 1), 0), Q(kGemmQueues + 1, 0);
-    const int ns = c->gemm_sched == 2 ? 1 : kGemmQueues;  // slices per request
-    for (int x = 0; x < kGemmQueues; ++x) {
+    std::vector<int64_t> pre(kXcds * (nq + 1), 0), Q(kXcds + 1, 0);
+    for (int x = 0; x < kXcds; ++x) {
       int64_t acc = 0;
       for (int k = 0; k < nq; ++k) {
         const int64_t cn = ht[rs[k]].c_nonnull;
@@ -796,21 +854,34 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       pre[x * (nq + 1) + nq] = acc;
       Q[x + 1] = Q[x] + acc;
     }
-    // queue bounds for the GEMM: the per-XCD slices, or one shared queue
-    // (queue 0 spans every unit, the others start empty); the placement
-    // offsets Q stay the per-XCD ones in both cases
-    std::vector<int64_t> Qq(Q);
-    if (c->gemm_sched != 0)
-      for (int x = 1; x <= kGemmQueues; ++x) Qq[x] = Q[kGemmQueues];
     sched.insert(sched.end(), pre.begin(), pre.end());
     sched.insert(sched.end(), Q.begin(), Q.end());
-    sched.insert(sched.end(), Qq.begin(), Qq.end());
   }
-  RegionP wus, queue, schedd;
+  // workgroups per launch: the resident maximum, a multiple of 8 (one rank
+  // list per XCD)
+  std::vector<int> kxs;
+  int64_t start_total = 0, scan_need = 0;
+  {
+    int gi = 0;
+    for (auto& gk : groups) {
+      const int64_t nwu = launches[gi++].second.second;
+      const int64_t maxg = gemm_max_groups(gk.first.first, gk.first.second, c->n_cu);
+      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, nwu));
+      const int kx = int((want + kXcds - 1) / kXcds);
+      kxs.push_back(kx);
+      start_total += int64_t(kXcds) * kx + 1;
+      scan_need = std::max<int64_t>(scan_need, int64_t(scan_scratch_bytes(std::max<int64_t>(nwu, 1))));
+    }
+  }
+  RegionP wus, costs, prefix, starts, wn, wt, schedd, sscr;
   ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
-  ALLOC(queue, 1024, "queue counters");
-  ALLOC(schedd, std::max<size_t>(sched.size(), 1) * 8, "schedule tables");
-  if (groups.size() * kGemmQueues > 256) return fail(c, SPAMM_EUNSUPPORTED, "too many precision/leaf groups");
+  ALLOC(costs, std::max<int64_t>(wu_total, 1) * 8, "unit costs");
+  ALLOC(prefix, (wu_total + int64_t(groups.size())) * 8, "unit cost prefix");
+  ALLOC(starts, std::max<int64_t>(start_total, 1) * 8, "workgroup ranges");
+  ALLOC(wn, std::max<int64_t>(wu_total, 1) * 8, "unit norms");
+  ALLOC(wt, std::max<int64_t>(wu_total, 1) * 8, "unit diagonal sums");
+  ALLOC(schedd, std::max<size_t>(sched.size(), 1) * 8, "placement tables");
+  ALLOC(sscr, std::max<int64_t>(scan_need, 1), "scan scratch");
   st = upload(c, schedd->ptr(), sched.data(), sched.size() * 8);
   if (st != SPAMM_OK) return st;
   {
@@ -822,7 +893,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
         d.sched = P<int64_t>(schedd) + sched_off[gj];
         d.sched_k = int32_t(k);
         d.sched_n = int32_t(gk.second.size());
-        d.nslices = c->gemm_sched == 2 ? 1 : kGemmQueues;
+        d.nslices = ns;
       }
       ++gj;
     }
@@ -832,30 +903,45 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   {
     TimedScope ts(c, kTPrune);
     SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
-                                   P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus),
-                                   P<int32_t>(queue), int(groups.size()) * kGemmQueues));
+                                   P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus), P<int64_t>(costs)));
   }
-  int gi = 0;
-  for (auto& gk : groups) {
-    const int64_t nwu = launches[gi].second.second;
-    int32_t* qptr = P<int32_t>(queue) + gi * kGemmQueues;
-    const int64_t nq = int64_t(gk.second.size());
-    const int64_t* Qp = P<int64_t>(schedd) + sched_off[gi] + kGemmQueues * (nq + 1) + (kGemmQueues + 1);
-    const WorkUnit* wbase = P<WorkUnit>(wus) + launches[gi].second.first;
-    ++gi;
-    if (nwu == 0) continue;
-    TimedScope ts(c, kTGemm);
-    if (c->timing) {
-      for (int r : gk.second)
-        c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
+  {
+    int gi = 0;
+    int64_t soff = 0;
+    for (auto& gk : groups) {
+      const int64_t u0 = launches[gi].second.first, nwu = launches[gi].second.second;
+      const int kx = kxs[gi];
+      int64_t* pre = P<int64_t>(prefix) + u0 + gi;
+      int64_t* stg = P<int64_t>(starts) + soff;
+      soff += int64_t(kXcds) * kx + 1;
+      ++gi;
+      if (nwu == 0) continue;
+      {
+        TimedScope ts(c, kTPrune);
+        SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(costs) + u0, pre, nwu, sscr->ptr(), sscr->bytes));
+        SPAMM_HIP(c, launch_wg_ranges(c->stream, pre, nwu, kXcds * kx, stg));
+      }
+      GemmArgs ga;
+      ga.wu = P<WorkUnit>(wus) + u0;
+      ga.start = stg;
+      ga.reqs = P<ReqDev>(reqd);
+      ga.base = c->arena.base();
+      ga.wn = P<double>(wn) + u0;
+      ga.wt = P<double>(wt) + u0;
+      ga.kx = kx;
+      ga.pad_ = 0;
+      TimedScope ts(c, kTGemm);
+      if (c->timing) {
+        for (int r : gk.second)
+          c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
+      }
+      SPAMM_HIP(c, launch_gemm(c->stream, gk.first.first, gk.first.second, ga));
     }
-    if (c->gemm_wave && gemm_wave_supported(gk.first.first, gk.first.second)) {
-      SPAMM_HIP(c, launch_gemm_wave(c->stream, gk.first.first, gk.first.second, P<ReqDev>(reqd), wbase, Qp, nwu,
-                                    qptr, c->n_cu));
-    } else {
-      SPAMM_HIP(c, launch_gemm(c->stream, gk.first.first, gk.first.second, P<ReqDev>(reqd), wbase, Qp, nwu, qptr,
-                               c->n_cu));
-    }
+  }
+  {
+    TimedScope ts(c, kTPyr);
+    SPAMM_HIP(c, launch_unit_scatter(c->stream, P<ReqDev>(reqd), P<WorkUnit>(wus), wu_total, P<double>(wn),
+                                     P<double>(wt)));
   }
   {
     std::vector<double*> nv;
@@ -940,8 +1026,8 @@ spamm_status spamm_kept(spamm_ctx* ctx, const spamm_mat* C, int32_t* ijk, int64_
   if (C->n_kept == 0) return SPAMM_OK;
   RegionP tmp;
   ALLOC(tmp, C->n_kept * 12, "kept triples");
-  SPAMM_HIP(c, launch_decode_kept(c->stream, C->G, C->n_kept, P<int64_t>(C->plan_off), nullptr,
-                                  P<int2>(C->plan_pairs), P<int32_t>(C->plan_Astore->keys), nullptr, P<int32_t>(tmp)));
+  SPAMM_HIP(c, launch_decode_kept(c->stream, C->G, P<int64_t>(C->plan_off), P<int2>(C->plan_pairs), C->plan_aoff,
+                                  P<int32_t>(C->plan_Astore->keys), P<int32_t>(tmp)));
   return download(c, ijk, tmp->ptr(), C->n_kept * 12);
 }
 

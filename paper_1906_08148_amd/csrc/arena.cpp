@@ -64,9 +64,10 @@ Region::~Region() {
 
 void* Region::ptr() const { return ctx->arena.base() + off; }
 
-RegionP Ctx::alloc(size_t bytes) {
-  const size_t rounded = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-  const size_t off = arena.alloc(rounded, 256);
+RegionP Ctx::alloc(size_t bytes, size_t align) {
+  align = std::max<size_t>(align, 256);
+  const size_t rounded = (std::max<size_t>(bytes, 1) + align - 1) / align * align;
+  const size_t off = arena.alloc(rounded, align);
   if (off == SIZE_MAX) return nullptr;
   auto r = std::make_shared<Region>();
   r->ctx = this;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -54,10 +55,15 @@ struct Store {
   int64_t nleaf = 0;  // slots in the store
   int32_t bs = 0;
   RegionP keys;       // int32[nleaf]: Morton key of each stored leaf
-  RegionP f64, f32, bf16hi, bf16lo;
+  // f64 / f32: leaf s at s * bs^2, row-major.  bf16: leaf s holds the hi
+  // parts (bf16 of the FP32 value) then the lo parts (bf16 of the FP32
+  // remainder), bs^2 each, row-major; bf16t holds the same two blocks
+  // transposed (the B operand of a BF16 product reads its k index
+  // contiguously).  Every copy is aligned to its leaf size within the arena,
+  // so a leaf is addressed by one index from the arena base.
+  RegionP f64, f32, bf16, bf16t;
   uint32_t mask() const {
-    return (f64 ? SPAMM_STORE_F64 : 0u) | (f32 ? SPAMM_STORE_F32 : 0u) |
-           (bf16hi ? SPAMM_STORE_BF16 : 0u);
+    return (f64 ? SPAMM_STORE_F64 : 0u) | (f32 ? SPAMM_STORE_F32 : 0u) | (bf16 ? SPAMM_STORE_BF16 : 0u);
   }
 };
 using StoreP = std::shared_ptr<Store>;
@@ -80,9 +86,10 @@ struct spamm_mat {
   spamm::RegionP ranges;    // int32[4*G]: row_lo, row_hi, col_lo, col_hi
   // set on products only
   spamm::RegionP plan_off;  // int64[G*G+1] local offsets into plan_pairs
-  spamm::RegionP plan_pairs;// int2[n_kept]  (slotA, slotB)
+  spamm::RegionP plan_pairs;// int2[n_kept]  A and B leaf indices from the arena base
   spamm::RegionP plan_bnd;  // double[G*G] skipped bound b per C leaf
-  spamm::StoreP plan_Astore, plan_Bstore;  // keys decode k from slotA
+  spamm::StoreP plan_Astore, plan_Bstore;  // keys decode k from the A index
+  int64_t plan_aoff = 0;    // A store's first leaf index from the arena base
   int64_t n_kept = -1;
   size_t device_bytes() const;
 };
@@ -109,15 +116,25 @@ struct Ctx {
   hipStream_t stream = nullptr;
   Arena arena;
   std::string last_error;
-  // pinned host staging
+  // pinned host staging for read-backs
   void* host_stage = nullptr;
   size_t host_stage_bytes = 0;
+  // pinned upload ring: each upload takes the next region; a region is
+  // reused only after the copy that read it has completed (its event), so
+  // uploads do not wait for the stream to drain
+  struct UpRec {
+    size_t s, e;
+    hipEvent_t ev;
+  };
+  char* up_ring = nullptr;
+  size_t up_bytes = 0, up_head = 0;
+  std::deque<UpRec> up_inflight;
+  std::vector<hipEvent_t> up_events;
   int n_cu = 256;
-  int gemm_sched = 0;     // 0: per-XCD queues, 1: one queue in XCD-major order, 2: one queue, request-major
-  bool gemm_wave = false;  // one-wave-per-leaf kernel (where it applies) instead of the LDS kernel
+  int gemm_sched = 0;  // work-unit placement: 0 per-XCD Morton slices, 1 request-major
   std::map<uint64_t, int> tuned;  // reserved for autotune results
   int live_handles = 0;
-  RegionP alloc(size_t bytes);    // nullptr on exhaustion
+  RegionP alloc(size_t bytes, size_t align = 256);  // nullptr on exhaustion
   void* stage(size_t bytes);      // grow pinned staging if needed
 };
 
@@ -129,14 +146,14 @@ struct TimedScope {
   TimedScope(Ctx* ctx, int k) : c(ctx), cls(k) {
     if (c->timing) {
       a = c->get_event();
-      if (a) hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, c->stream);
     }
   }
   ~TimedScope() {
     if (a) {
       hipEvent_t b = c->get_event();
       if (b) {
-        hipEventRecord(b, c->stream);
+        (void)hipEventRecord(b, c->stream);
         c->pending.push_back({cls, a, b});
       }
     }
@@ -187,7 +204,7 @@ struct ReqDev {
   int32_t G, L, bs;
   int64_t cbase;          // first global C index of this request
   // outputs (set after sizing)
-  int2* pairs;
+  int2* pairs;            // A and B leaf indices from the arena base
   int64_t* off;           // G*G+1 local offsets
   int32_t* cslot;         // C slot map (Morton)
   int32_t* ckeys;         // C keys [c_nonnull]
@@ -196,15 +213,15 @@ struct ReqDev {
   int32_t* ncand;         // candidate count per C leaf
   double* trace_part;     // G entries (diagonal leaves)
   void* cstore;           // C leaf store (FP32 or FP64)
-  // GEMM operands in the request's precision
-  const void* Astore;
-  const void* Bstore;
-  const void* Astore_lo;  // split-BF16 lo parts
-  const void* Bstore_lo;
+  // GEMM operands in the request's precision: first leaf of A's and B's
+  // store as an index from the arena base (in leaves of the operand copy)
+  int64_t aoff, boff;
+  int64_t pairs_idx;      // pairs as an index from the arena base (8-byte units)
+  int64_t cidx;           // C store's first leaf as an index from the arena base
   const void* Dstore;
   const int32_t* Dslot;
   double alpha, beta;
-  int64_t wu_base;        // first work unit of this request
+  int64_t wu_base;        // first work unit of this request's launch group
   int32_t prec;
   int32_t use_ep;         // apply alpha/beta/D in the epilogue
   // accounting inputs (roots of the pyramids, truncation results)
@@ -214,9 +231,8 @@ struct ReqDev {
   const double* truncA;   // nullptr when A was not truncated
   const double* truncB;
   int64_t stat_base;      // first statistics chunk of this request
-  // GEMM schedule: this request's group table (pre[8 * (n + 1)], then the
-  // placement offsets Q[9] of the per-XCD slices, then the queue bounds the
-  // GEMM pops from, 9 more) and its index k in the group; see k_gemm.hip
+  // Work-unit placement: this request's group table (pre[8 * (n + 1)], then
+  // the offsets Q[9] of the 8 slices) and its index k in the group
   const int64_t* sched;
   int32_t sched_k, sched_n;
   int32_t nslices;        // slices per request in the placement (8 per-XCD, or 1)
@@ -251,12 +267,28 @@ struct PrepJob {
   int32_t pad_;
 };
 
+// One C leaf for the GEMM (24 bytes).
 struct WorkUnit {
-  int32_t req;
-  int32_t c;      // Morton index of the C leaf
-  int64_t pb;     // first product in the request's pair list
-  int32_t cnt;    // number of products
-  int32_t cslot;  // slot of the C leaf in C's store
+  int64_t pp;      // first product's pair, as an index from the arena base (8-byte units)
+  int32_t cnt;     // products (0: the leaf comes from the epilogue matrix alone)
+  int32_t cidx;    // C leaf as an index from the arena base (C leaves)
+  int32_t req;     // request
+  int32_t cflags;  // Morton index of the C leaf | kUnitEp when the epilogue applies alpha/beta/D
+};
+constexpr int32_t kUnitEp = int32_t(1) << 30;
+
+// Arguments of one GEMM launch: the work units of one (precision, leaf size)
+// group in placement order, split into contiguous ranges of equal cost, one
+// per workgroup.
+struct GemmArgs {
+  const WorkUnit* wu;
+  const int64_t* start;  // [nwg + 1]: range of workgroup rank r is [start[r], start[r+1])
+  const ReqDev* reqs;
+  const char* base;      // arena base
+  double* wn;            // per unit: FP64 squared Frobenius norm of the C leaf
+  double* wt;            // per unit: diagonal sum of the C leaf (diagonal leaves)
+  int32_t kx;            // workgroups per XCD (the grid is 8 * kx)
+  int32_t pad_;
 };
 
 // Per-request totals read back after the counting pass.
@@ -301,13 +333,13 @@ hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64
 hipError_t launch_slot_keys(hipStream_t s, const int32_t* slot, int64_t G2, int32_t* keys);
 hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                     int bs, int64_t nleaf, const int32_t* keys, double* f64,
-                                    float* f32, uint16_t* bhi, uint16_t* blo);
+                                    float* f32, uint16_t* b16, uint16_t* b16t);
 hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
                                     const int32_t* keys, const int32_t* src_of,
                                     const double* data, double* f64, float* f32,
-                                    uint16_t* bhi, uint16_t* blo);
-hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, const float* f32,
-                               double* o64, float* o32, uint16_t* ohi, uint16_t* olo);
+                                    uint16_t* b16, uint16_t* b16t);
+hipError_t launch_derive_store(hipStream_t s, int64_t nleaf, int bs, const double* f64, const float* f32,
+                               double* o64, float* o32, uint16_t* o16, uint16_t* o16t);
 hipError_t launch_prep_batch(hipStream_t s, const PrepJob* jobs_dev, int njobs, int64_t total,
                              int64_t total_waves);
 hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
@@ -321,26 +353,28 @@ hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64
                               int64_t* packed, double* bnd_all, int32_t* cand_all);
 hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq,
                                 const int64_t* scanned, ReqTotals* out);
+// writes the kept pairs, C's slot map and the work units (with their cost,
+// products + 1, for the range split) in placement order
 hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                              const int64_t* scanned, const double* bnd_all,
-                             const int32_t* cand_all, WorkUnit* wu, int32_t* queues, int nqueues);
-// GEMM over the work units of one (precision, leaf size) group, stored
-// XCD-major: queue x owns wu[Q[x] .. Q[x+1]); queues[0..8) must be zero.
-constexpr int kGemmQueues = 8;
-hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
-                       const int64_t* Q, int64_t nwu, int32_t* queues, int n_cu);
+                             const int32_t* cand_all, WorkUnit* wu, int64_t* cost);
+constexpr int kXcds = 8;  // slices of the placement: workgroup w runs on XCD w % 8
+// start[r] = first unit whose cost prefix reaches r / nwg of the total
+hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, int nwg, int64_t* start);
+// GEMM over the work units of one (precision, leaf size) group
+hipError_t launch_gemm(hipStream_t s, int prec, int bs, const GemmArgs& a);
+int gemm_max_groups(int prec, int bs, int n_cu);  // resident workgroups of the kernel on the device
 bool gemm_supported(int prec, int bs);
-bool gemm_wave_supported(int prec, int bs);
-hipError_t launch_gemm_wave(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
-                            const int64_t* Q, int64_t nwu, int32_t* queues, int n_cu);
+// leaf norms and trace parts of the units into each request's C pyramid
+hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu,
+                               const double* wn, const double* wt);
 hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
 hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,
                             ReqStatsDev* out);
 hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
                            const double* f64, const float* f32, double* out, int64_t ld);
-hipError_t launch_decode_kept(hipStream_t s, int G, int64_t n_kept, const int64_t* off,
-                              const int32_t* cslot_unused, const int2* pairs,
-                              const int32_t* akeys, const int32_t* bkeys, int32_t* ijk);
+hipError_t launch_decode_kept(hipStream_t s, int G, const int64_t* off, const int2* pairs, int64_t aoff,
+                              const int32_t* akeys, int32_t* ijk);
 
 }  // namespace spamm

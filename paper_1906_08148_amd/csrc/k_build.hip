@@ -169,86 +169,122 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-// Write element e of leaf slot `sl` in every requested copy.  The split-BF16
-// pair is hi = bf16(x32), lo = bf16(x32 - hi), with x32 the FP32 rounding.
-__device__ __forceinline__ void store_leaf_elem(int64_t idx, double a, double* f64, float* f32,
-                                                uint16_t* bhi, uint16_t* blo) {
-  if (f64) f64[idx] = a;
-  const float x = float(a);
-  if (f32) f32[idx] = x;
-  if (bhi) {
-    const uint16_t h = f32_to_bf16(x);
-    bhi[idx] = h;
-    blo[idx] = f32_to_bf16(x - bf16_to_f32(h));
+// One workgroup writes every requested copy of one leaf slot `sl` from the
+// leaf's FP64 values (get(e) for row-major element e).  The split-BF16 pair
+// is hi = bf16(x32), lo = bf16(x32 - hi) with x32 the FP32 rounding of the
+// value.  The transposed BF16 copy goes through a 64 x 64 LDS tile so its
+// stores stay coalesced.
+template <typename Get>
+__device__ __forceinline__ void write_leaf(int64_t sl, int bs, Get get, double* f64, float* f32, uint16_t* b16,
+                                           uint16_t* b16t) {
+  __shared__ uint32_t tile[64 * 65];
+  const int64_t e2 = int64_t(bs) * bs;
+  const int64_t base = sl * e2;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+    const double a = get(e);
+    if (f64) f64[base + e] = a;
+    const float x = float(a);
+    if (f32) f32[base + e] = x;
+    if (b16) {
+      const uint16_t h = f32_to_bf16(x);
+      b16[2 * base + e] = h;
+      b16[2 * base + e2 + e] = f32_to_bf16(x - bf16_to_f32(h));
+    }
   }
+  if (!b16t) return;
+  // transposed copy, 64 x 64 sub-tiles (one for bs <= 64)
+  const int ts = bs < 64 ? bs : 64;
+  for (int tr = 0; tr < bs; tr += ts)
+    for (int tc = 0; tc < bs; tc += ts) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < ts * ts; e += blockDim.x) {
+        const int r = e / ts, c = e % ts;
+        const float x = float(get((tr + r) * bs + tc + c));
+        const uint16_t h = f32_to_bf16(x);
+        const uint16_t l = f32_to_bf16(x - bf16_to_f32(h));
+        tile[r * 65 + c] = uint32_t(h) | (uint32_t(l) << 16);
+      }
+      __syncthreads();
+      // element (c, r) of the transposed leaf = element (r, c) of the leaf
+      for (int e = threadIdx.x; e < ts * ts; e += blockDim.x) {
+        const int c = e / ts, r = e % ts;
+        const uint32_t v = tile[r * 65 + c];
+        const int64_t o = int64_t(tc + c) * bs + tr + r;
+        b16t[2 * base + o] = uint16_t(v & 0xffffu);
+        b16t[2 * base + e2 + o] = uint16_t(v >> 16);
+      }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_copy_dense_leaves(const double* __restrict__ dense, int64_t n,
                                                            int64_t ld, int bs,
                                                            const int32_t* __restrict__ keys,
-                                                           double* f64, float* f32, uint16_t* bhi,
-                                                           uint16_t* blo) {
+                                                           double* f64, float* f32, uint16_t* b16,
+                                                           uint16_t* b16t) {
   const int64_t sl = blockIdx.x;
   uint32_t r, c;
   demorton(uint32_t(keys[sl]), r, c);
   const int64_t r0 = int64_t(r) * bs, c0 = int64_t(c) * bs;
   const int64_t rows = min<int64_t>(bs, n - r0), cols = min<int64_t>(bs, n - c0);
-  const int64_t base = sl * bs * bs;
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const int rr = e / bs, cc = e % bs;
-    const double a = (rr < rows && cc < cols) ? dense[(r0 + rr) * ld + c0 + cc] : 0.0;
-    store_leaf_elem(base + e, a, f64, f32, bhi, blo);
-  }
+  write_leaf(
+      sl, bs,
+      [&](int e) {
+        const int rr = e / bs, cc = e % bs;
+        return (rr < rows && cc < cols) ? dense[(r0 + rr) * ld + c0 + cc] : 0.0;
+      },
+      f64, f32, b16, b16t);
 }
 
 hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                     int bs, int64_t nleaf, const int32_t* keys, double* f64,
-                                    float* f32, uint16_t* bhi, uint16_t* blo) {
+                                    float* f32, uint16_t* b16, uint16_t* b16t) {
   if (nleaf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_dense_leaves, dim3(uint32_t(nleaf)), dim3(256), 0, s, dense, n, ld, bs,
-                     keys, f64, f32, bhi, blo);
+                     keys, f64, f32, b16, b16t);
   return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(256) k_copy_block_leaves(int bs, const int32_t* __restrict__ keys,
                                                            const int32_t* __restrict__ src_of,
                                                            const double* __restrict__ data,
-                                                           double* f64, float* f32, uint16_t* bhi,
-                                                           uint16_t* blo) {
+                                                           double* f64, float* f32, uint16_t* b16,
+                                                           uint16_t* b16t) {
   const int64_t sl = blockIdx.x;
   const int32_t t = src_of[keys[sl]];
   const double* blk = data + int64_t(t) * bs * bs;
-  const int64_t base = sl * bs * bs;
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) store_leaf_elem(base + e, blk[e], f64, f32, bhi, blo);
+  write_leaf(sl, bs, [&](int e) { return blk[e]; }, f64, f32, b16, b16t);
 }
 
 hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
                                     const int32_t* keys, const int32_t* src_of, const double* data,
-                                    double* f64, float* f32, uint16_t* bhi, uint16_t* blo) {
+                                    double* f64, float* f32, uint16_t* b16, uint16_t* b16t) {
   (void)n;
   if (nleaf == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_block_leaves, dim3(uint32_t(nleaf)), dim3(256), 0, s, bs, keys, src_of,
-                     data, f64, f32, bhi, blo);
+                     data, f64, f32, b16, b16t);
   return hipGetLastError();
 }
 
-// Derive missing compute copies from the best copy present (FP64 if any).
-__global__ void k_derive_store(int64_t count, const double* __restrict__ f64,
-                               const float* __restrict__ f32, double* o64, float* o32,
-                               uint16_t* ohi, uint16_t* olo) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const double a = f64 ? f64[i] : double(f32[i]);
-    store_leaf_elem(i, a, o64, o32, ohi, olo);
+// Derive missing copies of every leaf from the best copy present (FP64 if
+// any), one workgroup per leaf.
+__global__ void __launch_bounds__(256) k_derive_store(int64_t nleaf, int bs, const double* __restrict__ f64,
+                                                      const float* __restrict__ f32, double* o64, float* o32,
+                                                      uint16_t* o16, uint16_t* o16t) {
+  const int64_t e2 = int64_t(bs) * bs;
+  for (int64_t sl = blockIdx.x; sl < nleaf; sl += gridDim.x) {
+    const double* a64 = f64 ? f64 + sl * e2 : nullptr;
+    const float* a32 = f32 ? f32 + sl * e2 : nullptr;
+    write_leaf(sl, bs, [&](int e) { return a64 ? a64[e] : double(a32[e]); }, o64, o32, o16, o16t);
+    __syncthreads();  // the LDS tile is reused by the next leaf
   }
 }
 
-hipError_t launch_derive_store(hipStream_t s, int64_t count, const double* f64, const float* f32,
-                               double* o64, float* o32, uint16_t* ohi, uint16_t* olo) {
-  if (count == 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_derive_store, dim3(uint32_t(blocks)), dim3(256), 0, s, count, f64, f32, o64,
-                     o32, ohi, olo);
+hipError_t launch_derive_store(hipStream_t s, int64_t nleaf, int bs, const double* f64, const float* f32,
+                               double* o64, float* o32, uint16_t* o16, uint16_t* o16t) {
+  if (nleaf == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(nleaf, 65536);
+  hipLaunchKernelGGL(k_derive_store, dim3(uint32_t(blocks)), dim3(256), 0, s, nleaf, bs, f64, f32, o64, o32,
+                     o16, o16t);
   return hipGetLastError();
 }
 

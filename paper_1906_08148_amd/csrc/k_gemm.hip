@@ -2,25 +2,39 @@
 // every lowest-level product runs in one batch; Sec. 5.2 counts them as
 // 2*bs^3 flops each).
 //
-// One persistent launch serves every C leaf of every request in a batch.  A
-// workgroup pops C leaves from a device queue (the only atomic), and owns the
-// whole sum C_ij = sum_k A_ik B_kj: products are streamed in the plan's order
-// (k ascending) in k-panels through LDS and accumulated in MFMA registers, so
-// results are bitwise reproducible and independent of the batch they run in.
+// One persistent launch serves every C leaf of every request of a batch that
+// shares a precision and leaf size.  The work units (one per C leaf) sit in
+// placement order -- eight slices, each a Morton-contiguous part of every
+// request, so that the leaves one XCD works on share A rows and B columns in
+// its L2 -- and are split into contiguous ranges of equal cost (products + 1),
+// one per workgroup.  Workgroup w runs on XCD w % 8 and takes the range of
+// rank (w % 8) * kx + w / 8, so the ranks of an XCD cover its slice.  There
+// are no atomics: a workgroup owns the whole sum C_ij = sum_k A_ik B_kj of
+// each of its leaves, streamed in the plan's order (k ascending) through LDS
+// in k-panels and accumulated in MFMA registers, so results are bitwise
+// reproducible and independent of the batch they run in.
+//
+// Nothing in the inner loop waits on a dependent load: the unit records of
+// the range are held one per lane, 64 units per block (two blocks); the slot
+// pairs of the products are held one per lane, 64 per window, three windows
+// ahead; the next panel is loaded into registers while the current one is
+// multiplied, across unit boundaries too.  Pairs are leaf indices from the
+// arena base, so a product's operands need no request descriptor.
 //
 // Tiling (wave64, gfx950): the C leaf is split over a 2 x 2 grid of waves
-// (one wave for 16 x 16 leaves); each wave holds (BS/2)^2 accumulators as
-// 16 x 16 MFMA tiles (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64).  A
-// k-panel of A (BS x KP) is staged row-major with a 16-byte row pad; the
-// matching panel of B (KP x BS) row-major with an XOR column swizzle so the
-// four lane groups of an MFMA operand read different banks.  Lane group g of
-// a wave takes the panel's k = g*KP/4 + m, reading four consecutive k of A
-// with one 16-byte LDS load.  The next panel is prefetched into registers
-// while the current one is multiplied.
+// (one wave for 16 x 16 leaves).  MFMA tiles: v_mfma_f64_16x16x4f64 (FP64),
+// v_mfma_f32_32x32x2f32 (FP32; 16x16x4 where a wave's tile is 16 wide),
+// v_mfma_f32_32x32x16_bf16 / 16x16x32_bf16 (BF16; split-BF16 takes three
+// products per step, lo*hi + hi*lo + hi*hi, in FP32).  A k-panel of A (BS x KP)
+// is staged row-major with a 16-byte row pad.  For FP32/FP64 the k-panel of
+// B (KP x BS) is row-major with an XOR column swizzle so the lane groups of
+// an MFMA operand read different banks; for BF16 the B panel comes from the
+// transposed copy (k contiguous per column) and is laid out like A, so each
+// lane reads its eight k values with one 16-byte LDS load.
 //
-// The epilogue writes the C leaf, its FP64 squared Frobenius norm (leaf level
-// of C's pyramid) and, on diagonal leaves, the diagonal sum for the trace;
-// optionally C = alpha * AB + beta * D.
+// The epilogue writes the C leaf (FP64 for FP64 products, else FP32), the
+// leaf's FP64 squared Frobenius norm and, on diagonal leaves, its diagonal
+// sum, per unit; optionally C = alpha * AB + beta * D.
 #include <type_traits>
 
 #include "internal.h"
@@ -29,253 +43,359 @@
 namespace spamm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 
-template <typename T>
-struct Vec16;
-typedef float f32x4v __attribute__((ext_vector_type(4)));
-typedef double f64x2v __attribute__((ext_vector_type(2)));
-template <>
-struct Vec16<float> {
-  using type = f32x4v;
-  static constexpr int n = 4;
-};
-template <>
-struct Vec16<double> {
-  using type = f64x2v;
-  static constexpr int n = 2;
-};
-
-template <typename T, int BS>
+template <int P, int BS>
 struct GemmCfg {
+  static constexpr bool kBf = P == SPAMM_BF16 || P == SPAMM_BF16X3;
+  static constexpr int NH = P == SPAMM_BF16X3 ? 2 : 1;  // hi / lo halves staged
+  static constexpr int ES = P == SPAMM_F64 ? 8 : P == SPAMM_F32 ? 4 : 2;
+  using Out = typename std::conditional<P == SPAMM_F64, double, float>::type;
   static constexpr int NW = BS >= 32 ? 4 : 1;
   static constexpr int WM = BS >= 32 ? 2 : 1;
   static constexpr int WN = BS >= 32 ? 2 : 1;
   static constexpr int TILE_M = BS / WM, TILE_N = BS / WN;
-  // MFMA tile: 32 x 32 x 2 for FP32 when a wave's tile allows it (the faster
-  // FP32 form on gfx950), else 16 x 16 x 4
-  static constexpr int MT = (sizeof(T) == 4 && TILE_M % 32 == 0) ? 32 : 16;
-  static constexpr int NG = 64 / MT;       // lane groups = k slices of an MFMA
+  static constexpr int MT = (P != SPAMM_F64 && TILE_M % 32 == 0) ? 32 : 16;
+  static constexpr int NG = 64 / MT;      // lane groups
   static constexpr int AE = MT * MT / 64;  // accumulator registers per tile
   static constexpr int TM = TILE_M / MT, TN = TILE_N / MT;
-  static constexpr int KP = (BS >= 128 || (sizeof(T) == 8 && BS >= 64)) ? 32 : BS;
+  static constexpr int KP = P == SPAMM_F64    ? (BS >= 64 ? 32 : BS)
+                            : P == SPAMM_F32  ? (BS >= 128 ? 32 : BS)
+                            : P == SPAMM_BF16 ? (BS >= 128 ? 64 : BS)
+                                              : (BS >= 128 ? 32 : BS);
   static constexpr int NPANEL = BS / KP;
   static constexpr int NT = NW * 64;
-  static constexpr int VN = 16 / int(sizeof(T));
-  static constexpr int SA = KP + VN;
-  static constexpr int A_VECS = BS * KP / VN / NT;
-  static constexpr int B_VECS = KP * BS / VN / NT;
-  static constexpr int KG = KP / NG;       // k values of one lane group per panel
-  static_assert(A_VECS * VN * NT == BS * KP, "A panel must split evenly");
-  static_assert(B_VECS * VN * NT == KP * BS, "B panel must split evenly");
-  static_assert(KG % 4 == 0, "lane group takes k in fours");
+  static constexpr int VN = 16 / ES;  // elements per 16-byte vector
+  static constexpr int SA = KP + VN;  // padded row of an A (and BF16 B) panel
+  static constexpr int KG = KP / NG;  // k values of one lane group per panel
+  static constexpr int PV = BS * KP / VN;  // 16-byte vectors of one operand panel half
+  static constexpr int A_VECS = (NH * PV + NT - 1) / NT;  // per thread (the last may be partial)
+  static constexpr int B_VECS = A_VECS;
+  static constexpr bool PARTIAL = (NH * PV) % NT != 0;
+  static constexpr int A_LDS = NH * BS * SA * ES;               // bytes
+  static constexpr int B_LDS = kBf ? NH * BS * SA * ES : KP * BS * ES;
+  static constexpr int64_t LEAF_IN = int64_t(BS) * BS * (kBf ? 2 * ES : ES);  // bytes of a stored leaf
+  static constexpr int64_t LEAF_OUT = int64_t(BS) * BS * sizeof(Out);
+  static constexpr int VNO = 16 / int(sizeof(Out));
+  static constexpr int SC = BS + VNO;  // padded row of the staged C leaf
+  static constexpr bool STAGED = int64_t(BS) * SC * sizeof(Out) <= A_LDS + B_LDS;
+  static constexpr int LDS = A_LDS + B_LDS;
+  // resident workgroups per CU asked of the register allocator
+  static constexpr int MINB = (BS == 64 && P != SPAMM_F64) ? 3 : 1;
+  static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
 };
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-template <typename T, int MT>
+template <int P, int MT>
 struct AccSel {
-  using type = typename std::conditional<std::is_same<T, float>::value, f32x4, f64x4>::type;
+  using type = f32x4;
 };
 template <>
-struct AccSel<float, 32> {
+struct AccSel<SPAMM_F64, 16> {
+  using type = f64x4;
+};
+template <>
+struct AccSel<SPAMM_F32, 32> {
   using type = f32x16;
 };
-template <typename T, int BS>
-using Acc = typename AccSel<T, GemmCfg<T, BS>::MT>::type;
-
-template <typename T, int BS>
-__device__ __forceinline__ Acc<T, BS> mfma_step(T a, T b, Acc<T, BS> c) {
-  if constexpr (GemmCfg<T, BS>::MT == 32) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-  } else if constexpr (std::is_same<T, float>::value) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  } else {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-}
+template <>
+struct AccSel<SPAMM_BF16, 32> {
+  using type = f32x16;
+};
+template <>
+struct AccSel<SPAMM_BF16X3, 32> {
+  using type = f32x16;
+};
+template <int P, int BS>
+using Acc = typename AccSel<P, GemmCfg<P, BS>::MT>::type;
+template <int P, int BS>
+using AccTiles = Acc<P, BS>[GemmCfg<P, BS>::TM][GemmCfg<P, BS>::TN];
 
 // Row within an MFMA tile of accumulator register v held by lane group g:
-// f32 16x16x4: rows 4g..4g+3; f64 16x16x4: row 4v + g (interleaved);
-// f32 32x32x2: row 8(v/4) + 4g + v%4.
-template <typename T, int BS>
+// FP64 16x16x4: 4v + g (interleaved); FP32/BF16 16-wide: 4g + v;
+// FP32/BF16 32-wide: 8(v/4) + 4g + v%4.
+template <int P, int BS>
 __device__ __forceinline__ int acc_row(int g, int v) {
-  if constexpr (GemmCfg<T, BS>::MT == 32) return 8 * (v / 4) + 4 * g + (v % 4);
-  else if constexpr (std::is_same<T, float>::value) return 4 * g + v;
-  else return 4 * v + g;
+  if constexpr (GemmCfg<P, BS>::MT == 32) return 8 * (v / 4) + 4 * g + (v % 4);
+  else if constexpr (P == SPAMM_F64) return 4 * v + g;
+  else return 4 * g + v;
 }
 
-// B panel column swizzle: lane group g reads its k rows at column ^ swizzle,
-// so the groups of one MFMA operand hit different LDS banks.
-template <typename T, int BS>
+// FP32/FP64 B panel column swizzle of lane group g.
+template <int P, int BS>
 __device__ __forceinline__ int b_swizzle(int g) {
-  return (g * GemmCfg<T, BS>::MT) % BS;
+  return (g * GemmCfg<P, BS>::MT) % BS;
 }
 
-template <typename T>
-struct WuMeta {
-  const ReqDev* R;
-  const int2* pairs;
-  const T* Ast;
-  const T* Bst;
-  int64_t pb;
-  int64_t np;  // panels
-  int32_t c, cslot;
-  int32_t cnt;
-  int32_t la, lb;  // lane l holds the slots of product pb + 64 * window + l
+// ---------------------------------------------------------------- unit records
+
+// 64 unit records held one per lane.
+struct RecBlock {
+  int32_t pplo, pphi, cnt, cidx, req, cf;
 };
 
-// Fetch the slot pairs of products [pb + base, pb + base + 64) one per lane.
-template <typename T>
-__device__ __forceinline__ void fetch_pairs(WuMeta<T>& m, int64_t base) {
-  const int l = threadIdx.x & 63;
-  m.la = 0;
-  m.lb = 0;
-  if (base + l < m.cnt) {
-    const auto pp = as_global(reinterpret_cast<const int32_t*>(m.pairs + m.pb + base + l));
-    m.la = pp[0];
-    m.lb = pp[1];
+// Scalar copy of one unit.
+struct UnitS {
+  int64_t pp;
+  int32_t cnt, cidx, req, cf;
+};
+
+__device__ __forceinline__ RecBlock load_recs(const WorkUnit* __restrict__ wu, int64_t u, int64_t u1) {
+  RecBlock b;
+  b.pplo = b.pphi = b.cnt = b.cidx = b.req = b.cf = 0;
+  const int64_t x = u + (threadIdx.x & 63);
+  if (x < u1) {
+    const auto p = as_global(reinterpret_cast<const i32x2*>(wu + x));
+    const i32x2 v0 = p[0], v1 = p[1], v2 = p[2];
+    b.pplo = v0[0];
+    b.pphi = v0[1];
+    b.cnt = v1[0];
+    b.cidx = v1[1];
+    b.req = v2[0];
+    b.cf = v2[1];
   }
+  return b;
 }
 
-template <typename T, int BS>
-using ARegs = typename Vec16<T>::type[GemmCfg<T, BS>::A_VECS];
-template <typename T, int BS>
-using BRegs = typename Vec16<T>::type[GemmCfg<T, BS>::B_VECS];
+__device__ __forceinline__ UnitS unit_of(const RecBlock& b0, const RecBlock& b1, int64_t rel) {
+  const int l = int(rel & 63);
+  const bool first = rel < 64;
+#define SPAMM_PICK(f) (first ? __builtin_amdgcn_readlane(b0.f, l) : __builtin_amdgcn_readlane(b1.f, l))
+  UnitS u;
+  const uint32_t lo = uint32_t(SPAMM_PICK(pplo));
+  const uint32_t hi = uint32_t(SPAMM_PICK(pphi));
+  u.pp = int64_t((uint64_t(hi) << 32) | lo);
+  u.cnt = SPAMM_PICK(cnt);
+  u.cidx = SPAMM_PICK(cidx);
+  u.req = SPAMM_PICK(req);
+  u.cf = SPAMM_PICK(cf);
+#undef SPAMM_PICK
+  return u;
+}
 
-template <typename T, int BS>
-__device__ __forceinline__ void load_panel_at(ARegs<T, BS>& ra, BRegs<T, BS>& rb, int32_t sa, int32_t sb, int sub,
-                                              const T* __restrict__ Ast, const T* __restrict__ Bst, int tid) {
-  using Cf = GemmCfg<T, BS>;
-  using V = typename Vec16<T>::type;
-  const auto Ag = as_global(Ast + int64_t(sa) * BS * BS + sub * Cf::KP);
-  const auto Bg = as_global(Bst + int64_t(sb) * BS * BS + int64_t(sub) * Cf::KP * BS);
+// Leaf indices of 64 consecutive products of one unit, one product per lane.
+struct Win {
+  int32_t a, b;
+};
+
+__device__ __forceinline__ Win load_win(const char* __restrict__ base, const UnitS& u, int w, bool valid) {
+  Win x;
+  x.a = x.b = 0;
+  const int i = w * 64 + (threadIdx.x & 63);
+  if (valid && i < u.cnt) {
+    const i32x2 v = *as_global(reinterpret_cast<const i32x2*>(base) + (u.pp + i));
+    x.a = v[0];
+    x.b = v[1];
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------- panels
+
+template <int P, int BS>
+struct Panel {
+  u32x4 a[GemmCfg<P, BS>::A_VECS];
+  u32x4 b[GemmCfg<P, BS>::B_VECS];
+};
+
+// k-panel `sub` of product (leaf ia of A, leaf ib of B) into registers.
+template <int P, int BS>
+__device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restrict__ base, int32_t ia, int32_t ib,
+                                           int sub, int tid) {
+  using Cf = GemmCfg<P, BS>;
+  const char* A = base + int64_t(ia) * Cf::LEAF_IN;
+  const char* B = base + int64_t(ib) * Cf::LEAF_IN;
 #pragma unroll
   for (int t = 0; t < Cf::A_VECS; ++t) {
     const int v = tid + t * Cf::NT;
-    const int row = v / (Cf::KP / Cf::VN), cv = v % (Cf::KP / Cf::VN);
-    ra[t] = *reinterpret_cast<const __attribute__((address_space(1))) V*>(Ag + int64_t(row) * BS + cv * Cf::VN);
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    const int h = v / Cf::PV, vv = v % Cf::PV;
+    const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+    const uint32_t e = uint32_t(h * BS * BS + row * BS + sub * Cf::KP + cv * Cf::VN);  // uniform base + lane offset
+    r.a[t] = *as_global(reinterpret_cast<const u32x4*>(A + e * Cf::ES));
   }
 #pragma unroll
   for (int t = 0; t < Cf::B_VECS; ++t) {
     const int v = tid + t * Cf::NT;
-    const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
-    rb[t] = *reinterpret_cast<const __attribute__((address_space(1))) V*>(Bg + int64_t(kr) * BS + cv * Cf::VN);
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    uint32_t e;
+    if constexpr (Cf::kBf) {  // transposed copy: row = B column, k contiguous
+      const int h = v / Cf::PV, vv = v % Cf::PV;
+      const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+      e = uint32_t(h * BS * BS + row * BS + sub * Cf::KP + cv * Cf::VN);
+    } else {
+      const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
+      e = uint32_t((sub * Cf::KP + kr) * BS + cv * Cf::VN);
+    }
+    r.b[t] = *as_global(reinterpret_cast<const u32x4*>(B + e * Cf::ES));
   }
 }
 
-// Panel q of work unit m: product q / NPANEL of the unit, k-panel q % NPANEL.
-// The slot pair comes from the lane that holds it (readlane), so no load sits
-// between the barrier and the panel's global loads; units with more than 64
-// products refill the lane window every 64 products.
-template <typename T, int BS>
-__device__ __forceinline__ void load_panel(ARegs<T, BS>& ra, BRegs<T, BS>& rb, WuMeta<T>& m, int64_t q, int tid) {
-  using Cf = GemmCfg<T, BS>;
-  const int64_t p = q / Cf::NPANEL;
-  const int sub = int(q % Cf::NPANEL);
-  if (p >= 64 && (p & 63) == 0 && sub == 0) fetch_pairs(m, p);
-  const int lane = int(p & 63);
-  const int32_t sa = __builtin_amdgcn_readlane(m.la, lane);
-  const int32_t sb = __builtin_amdgcn_readlane(m.lb, lane);
-  load_panel_at<T, BS>(ra, rb, sa, sb, sub, m.Ast, m.Bst, tid);
-}
-
-template <typename T, int BS>
-__device__ __forceinline__ void store_panel(const ARegs<T, BS>& ra, const BRegs<T, BS>& rb, T* As, T* Bs,
-                                            int tid) {
-  using Cf = GemmCfg<T, BS>;
-  using V = typename Vec16<T>::type;
+template <int P, int BS>
+__device__ __forceinline__ void store_panel(const Panel<P, BS>& r, char* As, char* Bs, int tid) {
+  using Cf = GemmCfg<P, BS>;
 #pragma unroll
   for (int t = 0; t < Cf::A_VECS; ++t) {
     const int v = tid + t * Cf::NT;
-    const int row = v / (Cf::KP / Cf::VN), cv = v % (Cf::KP / Cf::VN);
-    *reinterpret_cast<V*>(As + row * Cf::SA + cv * Cf::VN) = ra[t];
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    const int h = v / Cf::PV, vv = v % Cf::PV;
+    const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+    *reinterpret_cast<u32x4*>(As + ((h * BS + row) * Cf::SA + cv * Cf::VN) * Cf::ES) = r.a[t];
   }
 #pragma unroll
   for (int t = 0; t < Cf::B_VECS; ++t) {
     const int v = tid + t * Cf::NT;
-    const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
-    const int sw = b_swizzle<T, BS>(kr / Cf::KG);
-    *reinterpret_cast<V*>(Bs + kr * BS + ((cv * Cf::VN) ^ sw)) = rb[t];
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    if constexpr (Cf::kBf) {
+      const int h = v / Cf::PV, vv = v % Cf::PV;
+      const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+      *reinterpret_cast<u32x4*>(Bs + ((h * BS + row) * Cf::SA + cv * Cf::VN) * Cf::ES) = r.b[t];
+    } else {
+      const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
+      const int sw = b_swizzle<P, BS>(kr / Cf::KG);
+      *reinterpret_cast<u32x4*>(Bs + (kr * BS + ((cv * Cf::VN) ^ sw)) * Cf::ES) = r.b[t];
+    }
   }
 }
 
-__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
-  return int64_t((uint64_t(hi) << 32) | lo);
-}
-
-// Wave-uniform description of one work unit (one C leaf).
-template <typename T, int BS>
-__device__ __forceinline__ WuMeta<T> load_meta(const ReqDev* __restrict__ reqs, const WorkUnit* __restrict__ wus,
-                                               int64_t w) {
-  WuMeta<T> m;
-  const auto ug = as_global(wus + w);
-  WorkUnit u;
-  u.req = ug->req;
-  u.c = ug->c;
-  u.pb = ug->pb;
-  u.cnt = ug->cnt;
-  u.cslot = ug->cslot;
-  m.R = reqs + u.req;
-  const auto Rg = as_global(m.R);
-  m.pairs = Rg->pairs;
-  m.Ast = static_cast<const T*>(Rg->Astore);
-  m.Bst = static_cast<const T*>(Rg->Bstore);
-  m.pb = u.pb;
-  m.np = int64_t(u.cnt) * GemmCfg<T, BS>::NPANEL;
-  m.c = u.c;
-  m.cslot = u.cslot;
-  m.cnt = u.cnt;
-  fetch_pairs(m, 0);
-  return m;
-}
-
-// LDS words needed to stage a C leaf for the vectorised epilogue store.
-template <typename T, int BS>
-struct EpiCfg {
-  using Cf = GemmCfg<T, BS>;
-  static constexpr int SC = BS + Cf::VN;
-  static constexpr int LDS_ELEMS = BS * Cf::SA + Cf::KP * BS;
-  static constexpr bool STAGED = BS * SC <= LDS_ELEMS;
-};
-
-template <typename T, int BS>
-__device__ __forceinline__ void epilogue(const WuMeta<T>& m, Acc<T, BS> (&acc)[GemmCfg<T, BS>::TM][GemmCfg<T, BS>::TN],
-                                         T* smem, double* red, int tid, int lane, int wave, int row0, int col0,
-                                         int li, int g) {
-  using Cf = GemmCfg<T, BS>;
-  using Ep = EpiCfg<T, BS>;
-  using V = typename Vec16<T>::type;
-  const ReqDev* R = m.R;
-  const auto Cl = as_global(static_cast<T*>(R->cstore) + int64_t(m.cslot) * BS * BS);
-  const T* Dl = nullptr;
-  const bool has_ep = R->use_ep != 0;
-  if (has_ep && R->Dslot != nullptr) {
-    const int32_t ds = R->Dslot[m.c];
-    if (ds >= 0) Dl = static_cast<const T*>(R->Dstore) + int64_t(ds) * BS * BS;
+// One k-panel into the accumulators.
+template <int P, int BS>
+__device__ __forceinline__ void compute_panel(AccTiles<P, BS>& acc, const char* As, const char* Bs, int row0, int col0, int li, int g) {
+  using Cf = GemmCfg<P, BS>;
+  if constexpr (Cf::kBf) {
+#pragma unroll
+    for (int s = 0; s < Cf::KG / 8; ++s) {
+      const int k0 = g * Cf::KG + 8 * s;
+      bf16x8 ah[Cf::TM], bh[Cf::TN], al[Cf::TM], bl[Cf::TN];
+#pragma unroll
+      for (int a = 0; a < Cf::TM; ++a) {
+        const int o = (row0 + a * Cf::MT + li) * Cf::SA + k0;
+        ah[a] = *reinterpret_cast<const bf16x8*>(As + o * 2);
+        if constexpr (Cf::NH == 2) al[a] = *reinterpret_cast<const bf16x8*>(As + (o + BS * Cf::SA) * 2);
+      }
+#pragma unroll
+      for (int b = 0; b < Cf::TN; ++b) {
+        const int o = (col0 + b * Cf::MT + li) * Cf::SA + k0;
+        bh[b] = *reinterpret_cast<const bf16x8*>(Bs + o * 2);
+        if constexpr (Cf::NH == 2) bl[b] = *reinterpret_cast<const bf16x8*>(Bs + (o + BS * Cf::SA) * 2);
+      }
+#pragma unroll
+      for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < Cf::TN; ++b) {
+          if constexpr (Cf::MT == 32) {
+            if constexpr (Cf::NH == 2) {
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            }
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          } else {
+            if constexpr (Cf::NH == 2) {
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            }
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+        }
+    }
+  } else {
+    using T = typename std::conditional<P == SPAMM_F64, double, float>::type;
+    const T* At = reinterpret_cast<const T*>(As);
+    const T* Bt = reinterpret_cast<const T*>(Bs);
+    const int swz = b_swizzle<P, BS>(g);
+#pragma unroll 2
+    for (int ch = 0; ch < Cf::KG / 4; ++ch) {
+      const int kk = g * Cf::KG + 4 * ch;
+      T av[Cf::TM][4];
+      T bv[Cf::TN][4];
+#pragma unroll
+      for (int a = 0; a < Cf::TM; ++a) {
+        const T* src = At + (row0 + a * Cf::MT + li) * Cf::SA + kk;
+        if constexpr (P == SPAMM_F32) {
+          const f32x4 x = *reinterpret_cast<const f32x4*>(src);
+          av[a][0] = x[0];
+          av[a][1] = x[1];
+          av[a][2] = x[2];
+          av[a][3] = x[3];
+        } else {
+          const f64x2 x0 = *reinterpret_cast<const f64x2*>(src);
+          const f64x2 x1 = *reinterpret_cast<const f64x2*>(src + 2);
+          av[a][0] = x0[0];
+          av[a][1] = x0[1];
+          av[a][2] = x1[0];
+          av[a][3] = x1[1];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < Cf::TN; ++b) {
+        const int col = (col0 + b * Cf::MT + li) ^ swz;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) bv[b][qq] = Bt[(kk + qq) * BS + col];
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+        for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+          for (int b = 0; b < Cf::TN; ++b) {
+            if constexpr (P == SPAMM_F64)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][qq], bv[b][qq], acc[a][b], 0, 0, 0);
+            else if constexpr (Cf::MT == 32)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a][qq], bv[b][qq], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][qq], bv[b][qq], acc[a][b], 0, 0, 0);
+          }
+    }
   }
-  const T alpha = T(R->alpha), beta = T(R->beta);
+}
+
+// ---------------------------------------------------------------- epilogue
+
+template <int P, int BS>
+__device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const UnitS& U, AccTiles<P, BS>& acc,
+                                         char* smem,
+                                         double* red, int tid, int lane, int wave, int row0, int col0, int li,
+                                         int g) {
+  using Cf = GemmCfg<P, BS>;
+  using Out = typename Cf::Out;
+  const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(U.cidx) * Cf::LEAF_OUT));
+  const uint32_t cm = uint32_t(U.cf & (kUnitEp - 1));
+  const bool has_ep = (U.cf & kUnitEp) != 0;
+  Out alpha = Out(1), beta = Out(0);
+  const Out* Dl = nullptr;
+  if (has_ep) {  // requests with an epilogue read their descriptor here only
+    const ReqDev* R = ga.reqs + U.req;
+    alpha = Out(R->alpha);
+    beta = Out(R->beta);
+    if (R->Dslot != nullptr) {
+      const int32_t ds = R->Dslot[cm];
+      if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * BS * BS;
+    }
+  }
   uint32_t ci, cj;
-  demorton(uint32_t(m.c), ci, cj);
+  demorton(cm, ci, cj);
+  Out* Cs = reinterpret_cast<Out*>(smem);
   double nsq = 0.0, tr = 0.0;
-  if constexpr (Ep::STAGED) __syncthreads();  // all waves are done reading the panel buffers
+  if constexpr (Cf::STAGED) __syncthreads();  // every wave is done reading the panel buffers
 #pragma unroll
   for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
     for (int b = 0; b < Cf::TN; ++b)
 #pragma unroll
       for (int v = 0; v < Cf::AE; ++v) {
-        const int row = row0 + a * Cf::MT + acc_row<T, BS>(g, v);
+        const int row = row0 + a * Cf::MT + acc_row<P, BS>(g, v);
         const int col = col0 + b * Cf::MT + li;
-        T val = acc[a][b][v];
+        Out val = Out(acc[a][b][v]);
         if (has_ep) {
-          const T prod = alpha * val;
-          const T dv = Dl ? beta * as_global(Dl)[row * BS + col] : T(0);
+          const Out prod = alpha * val;
+          const Out dv = Dl ? beta * as_global(Dl)[row * BS + col] : Out(0);
           val = prod + dv;
         }
-        if constexpr (Ep::STAGED) smem[row * Ep::SC + col] = val;
+        if constexpr (Cf::STAGED) Cs[row * Cf::SC + col] = val;
         else Cl[row * BS + col] = val;
         const double dval = double(val);
         const double sq = dval * dval;
@@ -289,14 +409,14 @@ __device__ __forceinline__ void epilogue(const WuMeta<T>& m, Acc<T, BS> (&acc)[G
     red[Cf::NW + wave] = tr;
   }
   __syncthreads();
-  if constexpr (Ep::STAGED) {
-    constexpr int NV = BS * BS / Cf::VN / Cf::NT;
+  if constexpr (Cf::STAGED) {
+    constexpr int NV = BS * BS / Cf::VNO / Cf::NT;
 #pragma unroll
     for (int t = 0; t < NV; ++t) {
       const int v = tid + t * Cf::NT;
-      const int row = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
-      *reinterpret_cast<__attribute__((address_space(1))) V*>(Cl + row * BS + cv * Cf::VN) =
-          *reinterpret_cast<const V*>(smem + row * Ep::SC + cv * Cf::VN);
+      const int row = v / (BS / Cf::VNO), cv = v % (BS / Cf::VNO);
+      *reinterpret_cast<__attribute__((address_space(1))) u32x4*>(Cl + row * BS + cv * Cf::VNO) =
+          *reinterpret_cast<const u32x4*>(Cs + row * Cf::SC + cv * Cf::VNO);
     }
   }
   if (tid == 0) {
@@ -305,41 +425,20 @@ __device__ __forceinline__ void epilogue(const WuMeta<T>& m, Acc<T, BS> (&acc)[G
       s += red[x];
       t += red[Cf::NW + x];
     }
-    as_global(R->cnorm)[level_offset(R->L) + m.c] = s;
-    if (ci == cj) as_global(R->trace_part)[ci] = t;
+    as_global(ga.wn)[u] = s;
+    if (ci == cj) as_global(ga.wt)[u] = t;
   }
 }
 
-// Work distribution: each of the kXcd queues serves one XCD (workgroup w
-// runs on XCD w % kXcd) and holds, for every request of the launch, the same
-// contiguous slice of its C leaves in Morton order, so neighbouring leaves --
-// which share A rows and B columns -- meet in one L2.  The units are stored
-// queue by queue (queue x owns wu[Q[x] .. Q[x+1])); a workgroup whose queue
-// is empty steals from the next queues in turn.
-constexpr int kXcd = 8;
+// ---------------------------------------------------------------- kernel
 
-__device__ __forceinline__ int64_t pop_unit(int32_t* __restrict__ queues, const int64_t* __restrict__ Q, int& q) {
-  for (int tries = 0; tries < kXcd; ++tries) {
-    const int64_t idx = atomicAdd(&queues[q], 1);
-    const auto Qg = as_global(Q);
-    if (idx < Qg[q + 1] - Qg[q]) return Qg[q] + idx;
-    q = (q + 1) % kXcd;
-  }
-  return -1;
-}
-
-template <typename T, int BS>
-__global__ void __launch_bounds__((GemmCfg<T, BS>::NT))
-    k_gemm(const ReqDev* __restrict__ reqs, const WorkUnit* __restrict__ wus, const int64_t* __restrict__ Q,
-           int32_t* __restrict__ queues) {
-  using Cf = GemmCfg<T, BS>;
-  using Ep = EpiCfg<T, BS>;
-  using V = typename Vec16<T>::type;
-  __shared__ __attribute__((aligned(16))) T smem[Ep::LDS_ELEMS];
-  T* const As = smem;
-  T* const Bs = smem + BS * Cf::SA;
+template <int P, int BS>
+__global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) k_gemm(const GemmArgs ga) {
+  using Cf = GemmCfg<P, BS>;
+  __shared__ __attribute__((aligned(16))) char smem[Cf::LDS];
   __shared__ double red[2 * Cf::NW];
-  __shared__ int64_t qsh[2];
+  char* const As = smem;
+  char* const Bs = smem + Cf::A_LDS;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -347,145 +446,208 @@ __global__ void __launch_bounds__((GemmCfg<T, BS>::NT))
   const int wr = wave / Cf::WN, wc = wave % Cf::WN;
   const int row0 = wr * Cf::TILE_M, col0 = wc * Cf::TILE_N;
   const int li = lane % Cf::MT, g = lane / Cf::MT;
-  const int swz = b_swizzle<T, BS>(g);
+  const char* const base = ga.base;
 
-  // Work units are taken one ahead: while unit `cur` is multiplied, the
-  // metadata and first panel of `nxt` are already being loaded.
-  int myq = int(blockIdx.x % kXcd);  // used by thread 0 only
-  if (tid == 0) {
-    qsh[0] = pop_unit(queues, Q, myq);
-    qsh[1] = qsh[0] < 0 ? -1 : pop_unit(queues, Q, myq);
-  }
-  __syncthreads();
-  int64_t cur = uniform_i64(qsh[0]), nxt = uniform_i64(qsh[1]);
-  if (cur < 0) return;
-  WuMeta<T> mc = load_meta<T, BS>(reqs, wus, cur);
-  V ra[Cf::A_VECS], rb[Cf::B_VECS];
-  if (mc.np > 0) load_panel<T, BS>(ra, rb, mc, 0, tid);
+  const int rank = int(blockIdx.x % kXcds) * ga.kx + int(blockIdx.x / kXcds);
+  const int64_t u0 = ga.start[rank], u1 = ga.start[rank + 1];
+  if (u0 >= u1) return;
+
+  // unit records [rb, rb + 128) in two lane-held blocks
+  int64_t rb = u0;
+  RecBlock b0 = load_recs(ga.wu, rb, u1);
+  RecBlock b1 = load_recs(ga.wu, rb + 64, u1);
+
+  // pair windows: W0 holds the window of the product being multiplied, W1
+  // and W2 the next two windows of the range (unit by unit, 64 products
+  // each; a unit without products has one empty window); (pu, pw) is W2's
+  int64_t cu = u0;
+  UnitS U = unit_of(b0, b1, 0);
+  Win W0 = load_win(base, U, 0, true);
+  int64_t pu = cu;
+  int pw = 0;
+  UnitS PU = U;
+  auto next_pos = [&]() {
+    if ((pw + 1) * 64 < PU.cnt) {
+      ++pw;
+    } else {
+      ++pu;
+      pw = 0;
+      if (pu < u1) PU = unit_of(b0, b1, pu - rb);
+    }
+  };
+  next_pos();
+  Win W1 = load_win(base, PU, pw, pu < u1);
+  next_pos();
+  Win W2 = load_win(base, PU, pw, pu < u1);
+
+  Panel<P, BS> pr;
+  if (U.cnt > 0)
+    load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
 
   for (;;) {
-    const bool has_next = nxt >= 0;
-    WuMeta<T> mn = mc;
-    if (has_next) mn = load_meta<T, BS>(reqs, wus, nxt);
-    // claim the unit after next now; its index is read at the end of this
-    // unit, so no wave waits on the atomic here
-    int32_t raw = 0;
-    if (tid == 0 && has_next) raw = atomicAdd(&queues[myq], 1);
+    const bool has_next = cu + 1 < u1;
+    int32_t next_cnt = 0;
+    if (has_next) next_cnt = unit_of(b0, b1, cu + 1 - rb).cnt;
 
-    Acc<T, BS> acc[Cf::TM][Cf::TN];
+    Acc<P, BS> acc[Cf::TM][Cf::TN];
 #pragma unroll
     for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
-      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<T, BS>{};
+      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, BS>{};
 
-    for (int64_t q = 0; q < mc.np; ++q) {
-      __syncthreads();
-      store_panel<T, BS>(ra, rb, As, Bs, tid);
-      __syncthreads();
-      if (q + 1 < mc.np) load_panel<T, BS>(ra, rb, mc, q + 1, tid);
-      else if (has_next && mn.np > 0) load_panel<T, BS>(ra, rb, mn, 0, tid);
-#pragma unroll
-      for (int ch = 0; ch < Cf::KG / 4; ++ch) {
-        const int kk = g * Cf::KG + 4 * ch;
-        T av[Cf::TM][4];
-        T bv[Cf::TN][4];
-#pragma unroll
-        for (int a = 0; a < Cf::TM; ++a) {
-          const T* src = As + (row0 + a * Cf::MT + li) * Cf::SA + kk;
-          if constexpr (std::is_same<T, float>::value) {
-            const f32x4v x = *reinterpret_cast<const f32x4v*>(src);
-            av[a][0] = x[0];
-            av[a][1] = x[1];
-            av[a][2] = x[2];
-            av[a][3] = x[3];
-          } else {
-            const f64x2v x0 = *reinterpret_cast<const f64x2v*>(src);
-            const f64x2v x1 = *reinterpret_cast<const f64x2v*>(src + 2);
-            av[a][0] = x0[0];
-            av[a][1] = x0[1];
-            av[a][2] = x1[0];
-            av[a][3] = x1[1];
-          }
+    for (int p = 0; p < U.cnt; ++p) {
+      for (int sub = 0; sub < Cf::NPANEL; ++sub) {
+        __syncthreads();
+        store_panel<P, BS>(pr, As, Bs, tid);
+        __syncthreads();
+        // next panel: same product, next product (this or the next window),
+        // or the first product of the next unit (the next window)
+        if (sub + 1 < Cf::NPANEL) {
+          load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63), __builtin_amdgcn_readlane(W0.b, p & 63),
+                            sub + 1, tid);
+        } else if (p + 1 < U.cnt) {
+          const int l = (p + 1) & 63;
+          const bool nw = l == 0;
+          const int32_t ia = nw ? __builtin_amdgcn_readlane(W1.a, 0) : __builtin_amdgcn_readlane(W0.a, l);
+          const int32_t ib = nw ? __builtin_amdgcn_readlane(W1.b, 0) : __builtin_amdgcn_readlane(W0.b, l);
+          load_panel<P, BS>(pr, base, ia, ib, 0, tid);
+        } else if (next_cnt > 0) {
+          load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W1.a, 0), __builtin_amdgcn_readlane(W1.b, 0), 0,
+                            tid);
         }
-#pragma unroll
-        for (int b = 0; b < Cf::TN; ++b) {
-          const int col = (col0 + b * Cf::MT + li) ^ swz;
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) bv[b][qq] = Bs[(kk + qq) * BS + col];
-        }
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-          for (int a = 0; a < Cf::TM; ++a)
-#pragma unroll
-            for (int b = 0; b < Cf::TN; ++b) acc[a][b] = mfma_step<T, BS>(av[a][qq], bv[b][qq], acc[a][b]);
+        compute_panel<P, BS>(acc, As, Bs, row0, col0, li, g);
+      }
+      if (((p + 1) & 63) == 0 && p + 1 < U.cnt) {  // into the unit's next window
+        W0 = W1;
+        W1 = W2;
+        next_pos();
+        W2 = load_win(base, PU, pw, pu < u1);
       }
     }
-    if (mc.np == 0 && has_next && mn.np > 0) load_panel<T, BS>(ra, rb, mn, 0, tid);
 
-    epilogue<T, BS>(mc, acc, smem, red, tid, lane, wave, row0, col0, li, g);
-
+    epilogue<P, BS>(ga, cu, U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
     if (!has_next) break;
-    if (tid == 0) {
-      const auto Qg = as_global(Q);
-      int64_t r = int64_t(raw) < Qg[myq + 1] - Qg[myq] ? Qg[myq] + raw : int64_t(-2);
-      if (r == -2) {
-        myq = (myq + 1) % kXcd;  // this queue is exhausted: steal from the others
-        r = pop_unit(queues, Q, myq);
-      }
-      qsh[1] = r;
+
+    const int32_t prev_cnt = U.cnt;
+    ++cu;
+    if (cu - rb == 64) {
+      rb += 64;
+      b0 = b1;
+      b1 = load_recs(ga.wu, rb + 64, u1);
     }
-    __syncthreads();  // qsh[1] is visible; epilogue LDS reads are done
-    cur = nxt;
-    nxt = uniform_i64(qsh[1]);
-    mc = mn;
+    U = unit_of(b0, b1, cu - rb);
+    W0 = W1;
+    W1 = W2;
+    next_pos();
+    W2 = load_win(base, PU, pw, pu < u1);
+    // the first panel of a unit that follows a unit without products was
+    // not prefetched
+    if (prev_cnt == 0 && U.cnt > 0)
+      load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
   }
 }
 
-template <typename T, int BS>
-static hipError_t launch_one(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, const int64_t* Q, int64_t nwu,
-                             int32_t* queues, int n_cu) {
-  using Cf = GemmCfg<T, BS>;
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<T, BS>, Cf::NT, 0);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  const int64_t grid = std::min<int64_t>(std::max<int64_t>(nwu, kXcd), int64_t(n_cu) * per_cu);
-  hipLaunchKernelGGL((k_gemm<T, BS>), dim3(uint32_t(grid)), dim3(Cf::NT), 0, s, reqs, wu, Q, queues);
+// ---------------------------------------------------------------- launch
+
+template <int P, int BS>
+static int max_groups(int n_cu) {
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS>, GemmCfg<P, BS>::NT, 0) != hipSuccess || v < 1)
+      v = 1;
+    per_cu = v;
+  }
+  return per_cu * n_cu;
+}
+
+template <int P, int BS>
+static hipError_t launch_one(hipStream_t s, const GemmArgs& a) {
+  hipLaunchKernelGGL((k_gemm<P, BS>), dim3(uint32_t(kXcds * a.kx)), dim3(GemmCfg<P, BS>::NT), 0, s, a);
   return hipGetLastError();
 }
 
-bool gemm_bf16_built();
-
 bool gemm_supported(int prec, int bs) {
-  if (prec != SPAMM_F64 && prec != SPAMM_F32 && prec != SPAMM_BF16 && prec != SPAMM_BF16X3) return false;
-  if ((prec == SPAMM_BF16 || prec == SPAMM_BF16X3) && !gemm_bf16_built()) return false;
-  return bs == 16 || bs == 32 || bs == 64 || bs == 128;
+  if (prec == SPAMM_F64 || prec == SPAMM_F32) return bs == 16 || bs == 32 || bs == 64 || bs == 128;
+  if (prec == SPAMM_BF16 || prec == SPAMM_BF16X3) return bs == 32 || bs == 64 || bs == 128;
+  return false;
 }
 
-hipError_t launch_gemm_bf16(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu,
-                            const int64_t* Q, int64_t nwu, int32_t* queues, int n_cu);
-
-hipError_t launch_gemm(hipStream_t s, int prec, int bs, const ReqDev* reqs, const WorkUnit* wu, const int64_t* Q,
-                       int64_t nwu, int32_t* queues, int n_cu) {
-  if (nwu == 0) return hipSuccess;
-  if (prec == SPAMM_F32) {
-    switch (bs) {
-      case 16: return launch_one<float, 16>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 32: return launch_one<float, 32>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 64: return launch_one<float, 64>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 128: return launch_one<float, 128>(s, reqs, wu, Q, nwu, queues, n_cu);
-    }
-  } else if (prec == SPAMM_F64) {
-    switch (bs) {
-      case 16: return launch_one<double, 16>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 32: return launch_one<double, 32>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 64: return launch_one<double, 64>(s, reqs, wu, Q, nwu, queues, n_cu);
-      case 128: return launch_one<double, 128>(s, reqs, wu, Q, nwu, queues, n_cu);
-    }
-  } else {
-    return launch_gemm_bf16(s, prec, bs, reqs, wu, Q, nwu, queues, n_cu);
+#define SPAMM_GEMM_DISPATCH(FN, ...)                                  \
+  switch (prec * 1000 + bs) {                                         \
+    case SPAMM_F64 * 1000 + 16: return FN<SPAMM_F64, 16>(__VA_ARGS__);    \
+    case SPAMM_F64 * 1000 + 32: return FN<SPAMM_F64, 32>(__VA_ARGS__);    \
+    case SPAMM_F64 * 1000 + 64: return FN<SPAMM_F64, 64>(__VA_ARGS__);    \
+    case SPAMM_F64 * 1000 + 128: return FN<SPAMM_F64, 128>(__VA_ARGS__);  \
+    case SPAMM_F32 * 1000 + 16: return FN<SPAMM_F32, 16>(__VA_ARGS__);    \
+    case SPAMM_F32 * 1000 + 32: return FN<SPAMM_F32, 32>(__VA_ARGS__);    \
+    case SPAMM_F32 * 1000 + 64: return FN<SPAMM_F32, 64>(__VA_ARGS__);    \
+    case SPAMM_F32 * 1000 + 128: return FN<SPAMM_F32, 128>(__VA_ARGS__);  \
+    case SPAMM_BF16 * 1000 + 32: return FN<SPAMM_BF16, 32>(__VA_ARGS__);  \
+    case SPAMM_BF16 * 1000 + 64: return FN<SPAMM_BF16, 64>(__VA_ARGS__);  \
+    case SPAMM_BF16 * 1000 + 128: return FN<SPAMM_BF16, 128>(__VA_ARGS__); \
+    case SPAMM_BF16X3 * 1000 + 32: return FN<SPAMM_BF16X3, 32>(__VA_ARGS__); \
+    case SPAMM_BF16X3 * 1000 + 64: return FN<SPAMM_BF16X3, 64>(__VA_ARGS__); \
+    case SPAMM_BF16X3 * 1000 + 128: return FN<SPAMM_BF16X3, 128>(__VA_ARGS__); \
+    default: break;                                                   \
   }
+
+int gemm_max_groups(int prec, int bs, int n_cu) {
+  SPAMM_GEMM_DISPATCH(max_groups, n_cu)
+  return n_cu;
+}
+
+hipError_t launch_gemm(hipStream_t s, int prec, int bs, const GemmArgs& a) {
+  SPAMM_GEMM_DISPATCH(launch_one, s, a)
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- schedule
+
+// Range starts: start[r] = first unit u with prefix[u] >= r * total / nwg
+// (prefix is the exclusive scan of the unit costs, prefix[nwu] = total).
+__global__ void k_wg_ranges(const int64_t* __restrict__ prefix, int64_t nwu, int nwg, int64_t* __restrict__ start) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > nwg) return;
+  const int64_t total = prefix[nwu];
+  if (r == 0 || r == nwg) {
+    start[r] = r == 0 ? 0 : nwu;
+    return;
+  }
+  const int64_t target = total / nwg * r + (total % nwg) * r / nwg;
+  int64_t lo = 0, hi = nwu;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (prefix[mid] >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  start[r] = lo;
+}
+
+hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, int nwg, int64_t* start) {
+  hipLaunchKernelGGL(k_wg_ranges, dim3(uint32_t((nwg + 1 + 255) / 256)), dim3(256), 0, s, prefix, nwu, nwg, start);
+  return hipGetLastError();
+}
+
+// Leaf norms (leaf level of C's pyramid) and diagonal sums of the units.
+__global__ void k_unit_scatter(const ReqDev* __restrict__ reqs, const WorkUnit* __restrict__ wu, int64_t nwu,
+                               const double* __restrict__ wn, const double* __restrict__ wt) {
+  const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (u >= nwu) return;
+  const WorkUnit w = wu[u];
+  const ReqDev& R = reqs[w.req];
+  const uint32_t cm = uint32_t(w.cflags & (kUnitEp - 1));
+  R.cnorm[level_offset(R.L) + cm] = wn[u];
+  uint32_t ci, cj;
+  demorton(cm, ci, cj);
+  if (ci == cj) R.trace_part[ci] = wt[u];
+}
+
+hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const double* wn,
+                               const double* wt) {
+  if (nwu == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_scatter, dim3(uint32_t((nwu + 255) / 256)), dim3(256), 0, s, reqs, wu, nwu, wn, wt);
+  return hipGetLastError();
 }
 
 }  // namespace spamm

@@ -8,8 +8,8 @@
 // the recursion of Alg. 1.
 //
 // Counting pass -> LDS-staged exclusive scan over all C leaves of the batch
-// (Morton order) -> fill pass writing the (slotA, slotB) pairs, the C slot
-// map and the GEMM work units.  No atomics: positions come from the scan, so
+// (Morton order) -> fill pass writing the pairs (A and B leaf indices from
+// the arena base), the C slot map and the GEMM work units.  No atomics: positions come from the scan, so
 // the lists are deterministic.
 #include "internal.h"
 #include "kern_common.h"
@@ -174,9 +174,7 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
                                                     const int64_t* __restrict__ scanned,
                                                     const double* __restrict__ bnd_all,
                                                     const int32_t* __restrict__ cand_all,
-                                                    WorkUnit* __restrict__ wu, int32_t* __restrict__ queues,
-                                                    int nqueues) {
-  if (blockIdx.x == 0 && threadIdx.x < nqueues) queues[threadIdx.x] = 0;  // GEMM work queues
+                                                    WorkUnit* __restrict__ wu, int64_t* __restrict__ cost) {
   const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
   if (g0 >= total_c) return;
   const int64_t g = g0 + lane_id();
@@ -197,14 +195,24 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
     R.ncand[x.c] = cand_all[g];
     if (flag) {
       R.ckeys[cs] = int32_t(x.c);
-      // XCD-major position: slice x of this request inside queue x
+      // placement: slice q of every request's C leaves (Morton order) goes to
+      // region q, which the workgroups of XCD q work through
       const int64_t cn = ((scanned[R.cbase + G2] >> kCntBits) - (s0 >> kCntBits));
       const int n = R.sched_n, ns = R.nslices;
       int q = 0;
       while (q + 1 < ns && cn * (q + 1) / ns <= cs) ++q;
-      const int64_t* Q = R.sched + 8 * (n + 1);  // placement offsets of the slices
+      const int64_t* Q = R.sched + kXcds * (n + 1);  // offsets of the slices
       const int64_t at = Q[q] + R.sched[q * (n + 1) + R.sched_k] + (cs - cn * q / ns);
-      if (at >= 0 && at < Q[8]) wu[R.wu_base + at] = WorkUnit{x.r, int32_t(x.c), off, int32_t(cnt), cs};
+      if (at >= 0 && at < Q[kXcds]) {
+        WorkUnit u;
+        u.pp = R.pairs_idx + off;
+        u.cnt = int32_t(cnt);
+        u.cidx = int32_t(R.cidx + cs);
+        u.req = x.r;
+        u.cflags = int32_t(x.c) | (R.use_ep ? kUnitEp : 0);
+        wu[R.wu_base + at] = u;
+        cost[R.wu_base + at] = cnt + 1;
+      }
     } else {
       R.cnorm[level_offset(R.L) + x.c] = 0.0;
     }
@@ -237,7 +245,8 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
       const bool keep = both && (!use_norms || a * bb >= tau);
       const uint64_t mask = ballot64(keep);
       const int64_t at = pos + popc64(mask & lanemask_lt());
-      if (keep && at < end) R.pairs[at] = make_int2(R.A.rm_slot[w.rowA + k], R.B.cm_slot[w.colB + k]);
+      if (keep && at < end)
+        R.pairs[at] = make_int2(int32_t(R.aoff + R.A.rm_slot[w.rowA + k]), int32_t(R.boff + R.B.cm_slot[w.colB + k]));
       pos += popc64(mask);
     }
   }
@@ -245,12 +254,11 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
 
 hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
                              const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
-                             WorkUnit* wu, int32_t* queues, int nqueues) {
-  if (nqueues > 256) return hipErrorInvalidValue;
+                             WorkUnit* wu, int64_t* cost) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
   const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, scanned,
-                     bnd_all, cand_all, wu, queues, nqueues);
+                     bnd_all, cand_all, wu, cost);
   return hipGetLastError();
 }
 
@@ -343,25 +351,25 @@ hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t
 
 // (I, K, J) triples of a product's plan, for parity checks.
 __global__ void k_decode_kept(int G, const int64_t* __restrict__ off, const int2* __restrict__ pairs,
-                              const int32_t* __restrict__ akeys, int32_t* __restrict__ ijk) {
+                              int64_t aoff, const int32_t* __restrict__ akeys, int32_t* __restrict__ ijk) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= int64_t(G) * G) return;
   uint32_t i, j;
   demorton(uint32_t(c), i, j);
   for (int64_t t = off[c]; t < off[c + 1]; ++t) {
     uint32_t ai, ak;
-    demorton(uint32_t(akeys[pairs[t].x]), ai, ak);
+    demorton(uint32_t(akeys[pairs[t].x - aoff]), ai, ak);
     ijk[3 * t] = int32_t(i);
     ijk[3 * t + 1] = int32_t(ak);
     ijk[3 * t + 2] = int32_t(j);
   }
 }
 
-hipError_t launch_decode_kept(hipStream_t s, int G, int64_t n_kept, const int64_t* off, const int32_t*,
-                              const int2* pairs, const int32_t* akeys, const int32_t*, int32_t* ijk) {
-  (void)n_kept;
+hipError_t launch_decode_kept(hipStream_t s, int G, const int64_t* off, const int2* pairs, int64_t aoff,
+                              const int32_t* akeys, int32_t* ijk) {
   const int64_t G2 = int64_t(G) * G;
-  hipLaunchKernelGGL(k_decode_kept, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, off, pairs, akeys, ijk);
+  hipLaunchKernelGGL(k_decode_kept, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, off, pairs, aoff, akeys,
+                     ijk);
   return hipGetLastError();
 }
 

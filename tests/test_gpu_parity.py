@@ -215,14 +215,15 @@ def test_config2_full(ctx):
 
 
 def test_gemm_schedules_agree_bitwise():
-    """Per-XCD queues and one shared queue give bitwise the same C: each C
-    leaf is summed by one workgroup in the plan's order either way."""
+    """Morton slices per XCD and request-major placement give bitwise the
+    same C: each C leaf is summed by one workgroup in the plan's order
+    either way."""
     import os
     import torch
     print("case: schedules", flush=True)
     A = synth.DecaySpec("1d", 8192, 0.2, seed=2).dense()
     res = {}
-    for mode in ("xcd", "global"):
+    for mode in ("xcd", "rm"):
         os.environ["SPAMM_GEMM_SCHED"] = mode
         try:
             c = spamm.Context(arena_bytes=2 << 30)
@@ -236,26 +237,67 @@ def test_gemm_schedules_agree_bitwise():
             p.C.release()
         M.release()
         c.close()
-    for a, b in zip(res["xcd"], res["global"]):
+    for a, b in zip(res["xcd"], res["rm"]):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("bs", [16, 32, 64])
-def test_wave_kernel_parity(bs):
-    """The one-wave-per-leaf GEMM (selected with SPAMM_GEMM_KERNEL=wave)
-    against the oracle, FP32 and FP64 where it applies."""
-    import os
-    print(f"case: wave kernel bs={bs}", flush=True)
-    os.environ["SPAMM_GEMM_KERNEL"] = "wave"
-    try:
-        c = spamm.Context(arena_bytes=1 << 30)
-    finally:
-        del os.environ["SPAMM_GEMM_KERNEL"]
-    A = synth.DecaySpec("1d", 1500, 0.3, seed=11).dense()
-    B = synth.DecaySpec("1d", 1500, 0.4, seed=12).dense()
+@pytest.mark.parametrize("n,bs,kind,tau", [
+    (1000, 32, "1d", 1e-5),
+    (2100, 64, "1d", 1e-6),
+    (700, 128, "3d", 1e-4),
+    (300, 32, "rand", 1e-2),
+])
+def test_bf16_and_split_bf16(ctx, n, bs, kind, tau):
+    """BF16 and split-BF16 products against the FP64 oracle (relative
+    Frobenius 1e-2 and 1e-5)."""
+    print(f"case: bf16 n={n} bs={bs} {kind}", flush=True)
+    if kind == "rand":
+        A = sparse_random(n, bs, 0.4, 13)
+        B = sparse_random(n, bs, 0.6, 14)
+    elif kind == "3d":
+        n = (n // 8) * 8
+        A = B = synth.DecaySpec("3d", n, 1.0, seed=7).dense()
+    else:
+        A = synth.DecaySpec("1d", n, 0.3, seed=8).dense()
+        B = synth.DecaySpec("1d", n, 0.4, seed=9).dense()
     TA, TB = O.build(A, bs), O.build(B, bs)
-    MA, MB = c.build(dev(A), bs), c.build(dev(B), bs)
+    MA, MB = ctx.build(dev(A), bs), ctx.build(dev(B), bs)
     for mode in MODES:
-        for prec in (spamm.F64, spamm.F32):
-            check_product(c, MA, MB, TA, TB, 1e-5, mode, prec)
-    c.close()
+        for prec in (spamm.BF16, spamm.BF16X3):
+            check_product(ctx, MA, MB, TA, TB, tau, mode, prec)
+
+
+def test_long_units_and_window_crossing(ctx):
+    """C leaves with 65 products (more than one 64-product window), ragged
+    tail, every precision."""
+    print("case: long units", flush=True)
+    A = sparse_random(1040, 16, 1.0, 21)
+    B = sparse_random(1040, 16, 1.0, 22)
+    TA, TB = O.build(A, 16), O.build(B, 16)
+    MA, MB = ctx.build(dev(A), 16), ctx.build(dev(B), 16)
+    for prec in (spamm.F64, spamm.F32):
+        check_product(ctx, MA, MB, TA, TB, 0.0, spamm.SPAMM, prec)
+    A = sparse_random(2100, 32, 1.0, 23)
+    TA = O.build(A, 32)
+    MA = ctx.build(dev(A), 32)
+    for prec in (spamm.F32, spamm.BF16X3):
+        check_product(ctx, MA, MA, TA, TA, 0.0, spamm.TRUNCMUL, prec, alias=True)
+
+
+def test_epilogue_with_leaves_from_d_only(ctx):
+    """C = alpha AB + beta D where many C leaves come from D alone (no
+    products), interleaved with product leaves."""
+    print("case: epilogue D-only leaves", flush=True)
+    A = synth.DecaySpec("1d", 1024, 2.0, seed=3).dense()  # narrow band
+    D = sparse_random(1024, 32, 0.5, 31)
+    TA = O.build(A, 32)
+    MA, MD = ctx.build(dev(A), 32), ctx.build(dev(D), 32)
+    for prec in (spamm.F64, spamm.F32, spamm.BF16X3):
+        p = ctx.multiply(MA, MA, 1e-9, mode=spamm.SPAMM, prec=prec, alpha=0.5, beta=-3.0, D=MD)
+        ref = O.multiply(TA, TA, 1e-9, O.SPAMM)
+        want = 0.5 * ref.C.to_dense() - 3.0 * D
+        C = ctx.to_dense(p.C).cpu().numpy()
+        assert rel_fro(C, want) <= TOL[prec]
+        d_only = (~ref.C.leaf_present) & O.build(D, 32).leaf_present
+        assert d_only.sum() > 50
+        assert p.C.info.nonnull == int((ref.C.leaf_present | O.build(D, 32).leaf_present).sum())
