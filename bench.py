@@ -34,6 +34,9 @@ MODE_NAMES = ("truncmul", "spamm", "hybrid")
 SEED = 1
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+# 3D decay workload: 4096 atoms (16^3 lattice, jitter 0.1) x 8 functions
+N3D, LEAF3D, ALPHA3D, TAU3D = 32768, 64, 1.0, 1e-6
 GEMM_SOURCE = os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "k_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f32_leaf64_decay1d_n16384_batch18_traffic.json")
 
@@ -108,6 +111,68 @@ def timed_steps(ctx, dev, prec, steps, warmup):
     torch.cuda.synchronize()
     tm = ctx.timing(enable=False, reset=True)
     return total, lat, flops, tm, stats
+
+
+def dense3d(steps):
+    """3D decay, n = 32768, leaf 64, tau = 1e-6, A = B: one multiply per
+    (scheme, precision), timed alone (warm), with the leaf-GEMM time from the
+    library's events and the relative difference from the FP64 product."""
+    import torch
+    import synth
+    from paper_1906_08148_amd import spamm
+    t0 = time.perf_counter()
+    A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).dense()
+    gen_s = time.perf_counter() - t0
+    ctx = spamm.Context(arena_bytes=64 << 30)
+    dA = torch.from_numpy(A).cuda()
+    del A
+    M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
+    torch.cuda.synchronize()
+    del dA
+    out = {"workload": f"3D decay n={N3D} (4096 atoms x 8 functions), alpha {ALPHA3D}, leaf {LEAF3D}, "
+                       f"tau {TAU3D}, A=B", "generate_s": round(gen_s, 1), "runs": {}}
+    peaks = {spamm.F64: FP64_MFMA_PEAK_TFLOPS, spamm.F32: FP32_MFMA_PEAK_TFLOPS,
+             spamm.BF16: BF16_MFMA_PEAK_TFLOPS, spamm.BF16X3: BF16_MFMA_PEAK_TFLOPS}
+    names = {spamm.F64: "f64", spamm.F32: "f32", spamm.BF16: "bf16", spamm.BF16X3: "bf16x3"}
+    for mode, mname in ((spamm.SPAMM, "spamm"), (spamm.HYBRID, "hybrid")):
+        ref = None
+        for prec in (spamm.F64, spamm.F32, spamm.BF16, spamm.BF16X3):
+            log(f"bench: 3D {mname} {names[prec]}")
+            p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)  # warm
+            p.C.release()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(steps):
+                ctx.timing(enable=True, reset=True)
+                s0 = time.perf_counter()
+                p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - s0)
+                tm = ctx.timing(enable=False, reset=True)
+                if _ + 1 < steps:
+                    p.C.release()
+            dt = sorted(ts)[len(ts) // 2]
+            st = p.stats
+            gemm_s = tm["gemm_ms"] / max(tm["gemm_launches"], 1) * 1e-3
+            rec = {"ms": round(dt * 1e3, 2), "gflops": round(st["flops"] / dt / 1e9, 1),
+                   "n_kept": int(st["n_kept"]), "gemm_ms": round(gemm_s * 1e3, 2),
+                   "gemm_tflops": round(st["flops"] / gemm_s / 1e12, 2),
+                   "gemm_frac": round(st["flops"] / gemm_s / 1e12 / peaks[prec], 4),
+                   "phases_ms": {k: round(tm[k + "_ms"], 2) for k in ("trunc", "prune", "gemm", "pyramid")}}
+            C = ctx.to_dense(p.C)
+            if prec == spamm.F64:
+                ref = C
+                rec["rel_err_vs_f64"] = 0.0
+            else:
+                rec["rel_err_vs_f64"] = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
+                del C
+            p.C.release()
+            out["runs"][f"{mname}/{names[prec]}"] = rec
+        del ref
+        torch.cuda.empty_cache()
+    M.release()
+    ctx.close()
+    return out
 
 
 def pct(xs, q):
@@ -233,6 +298,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D decay n=32768 section")
+    ap.add_argument("--steps-3d", type=int, default=3)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device (a plain copy "
                          "kernel of known traffic, to scale hardware byte counters)")
@@ -312,6 +379,9 @@ def main():
         }
         out["fixed_error"]["f32_over_f64"] = round(out["fixed_error"]["f32"]["multiplies_per_s"] /
                                                    out["fixed_error"]["f64"]["multiplies_per_s"], 3)
+    if not args.skip_extras and not args.no_3d:
+        log("bench: 3D decay n=32768")
+        out["dense3d"] = dense3d(args.steps_3d)
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)

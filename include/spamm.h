@@ -254,6 +254,16 @@ spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C,
 spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out,
                             int64_t ld);
 
+/* Copy `count` leaves (block row ij[2t], block column ij[2t+1], host int32)
+ * of a matrix into `out` (host, FP64, count * bs * bs values, leaf t
+ * row-major at t * bs * bs); null leaves give zeros, entries beyond n are the
+ * zero padding.  For checking a few blocks of a large result (Sec. 4.2
+ * layout: a leaf is one bs x bs block).  Synchronises.
+ * Errors: EINVAL (null pointer, count < 0, a coordinate outside the grid),
+ * ENOMEM, EDEVICE. */
+spamm_status spamm_leaves(spamm_ctx* ctx, const spamm_mat* m, const int32_t* ij,
+                          int64_t count, double* out);
+
 /* Describe a handle (host output). */
 spamm_status spamm_mat_info_get(const spamm_mat* m, spamm_mat_info* out);
 

@@ -425,15 +425,22 @@ def multiply(A: Tree, B: Tree, tau: float, mode: int, c_blocks=None) -> Result:
     c_present = np.zeros((G, G), dtype=bool)
     if len(kept):
         c_present[kept[:, 0], kept[:, 2]] = True
-    groups = {}
-    for I, K, J in kept:
-        groups.setdefault((int(I), int(J)), []).append(int(K))
-    for (I, J), ks in groups.items():
-        if want is not None and (I, J) not in want:
-            continue
+    rows = kept
+    if want is not None and len(kept):
+        wkeys = np.array([morton_key(I, J) for I, J in want], dtype=np.int64)
+        rows = kept[np.isin(morton_key(kept[:, 0], kept[:, 2]), wkeys)]
+    # kept is sorted by (Morton key of (I, J), K): each C leaf is one run
+    if len(rows):
+        rk = morton_key(rows[:, 0], rows[:, 2])
+        starts = np.flatnonzero(np.r_[True, rk[1:] != rk[:-1]])
+        ends = np.r_[starts[1:], len(rows)]
+    else:
+        starts = ends = np.zeros(0, dtype=np.int64)
+    for a, b in zip(starts, ends):
+        I, J = int(rows[a, 0]), int(rows[a, 2])
         acc = np.zeros((bs, bs), dtype=np.float64)
-        for K in ks:
-            acc = acc + Au.leaf(I, K) @ Bu.leaf(K, J)
+        for K in rows[a:b, 1]:
+            acc = acc + Au.leaf(I, int(K)) @ Bu.leaf(int(K), J)
         c_index[I, J] = len(c_list)
         c_list.append(acc)
     blocks = np.asarray(c_list, dtype=np.float64).reshape(-1, bs, bs)

@@ -1040,6 +1040,25 @@ spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C, double* out
   return download(c, out, C->plan_bnd->ptr(), G2 * 8);
 }
 
+spamm_status spamm_leaves(spamm_ctx* ctx, const spamm_mat* m, const int32_t* ij, int64_t count, double* out) {
+  if (!ctx || !m || (count > 0 && (!ij || !out)) || count < 0) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (count == 0) return SPAMM_OK;
+  for (int64_t t = 0; t < count; ++t)
+    if (ij[2 * t] < 0 || ij[2 * t] >= m->G || ij[2 * t + 1] < 0 || ij[2 * t + 1] >= m->G)
+      return fail(c, SPAMM_EINVAL, "leaf coordinate outside the grid");
+  const int64_t e2 = int64_t(m->bs) * m->bs;
+  RegionP dij, dout;
+  ALLOC(dij, count * 8, "leaf coordinates");
+  ALLOC(dout, count * e2 * 8, "gathered leaves");
+  spamm_status st = upload(c, dij->ptr(), ij, count * 8);
+  if (st != SPAMM_OK) return st;
+  const Store& s = *m->store;
+  SPAMM_HIP(c, launch_gather_leaves(c->stream, m->bs, count, P<int32_t>(m->slot), P<double>(s.f64),
+                                    s.f64 ? nullptr : P<float>(s.f32), P<int32_t>(dij), P<double>(dout)));
+  return download(c, out, dout->ptr(), count * e2 * 8);
+}
+
 spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out, int64_t ld) {
   if (!ctx || !m || !out) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;

@@ -453,6 +453,28 @@ hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_
   return hipGetLastError();
 }
 
+// Leaves (ij[2t], ij[2t+1]) of a matrix into out[t * bs^2 ...] as FP64.
+__global__ void __launch_bounds__(256) k_gather_leaves(int bs, const int32_t* __restrict__ slot,
+                                                       const double* __restrict__ f64,
+                                                       const float* __restrict__ f32,
+                                                       const int32_t* __restrict__ ij, double* out) {
+  const int64_t t = blockIdx.x;
+  const int32_t sl = slot[morton(uint32_t(ij[2 * t]), uint32_t(ij[2 * t + 1]))];
+  const int64_t e2 = int64_t(bs) * bs;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
+    double v = 0.0;
+    if (sl >= 0) v = f64 ? f64[sl * e2 + e] : double(f32[sl * e2 + e]);
+    out[t * e2 + e] = v;
+  }
+}
+
+hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int32_t* slot, const double* f64,
+                                const float* f32, const int32_t* ij, double* out) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_leaves, dim3(uint32_t(count)), dim3(256), 0, s, bs, slot, f64, f32, ij, out);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;

@@ -85,6 +85,11 @@ struct GemmCfg {
   static constexpr int SC = BS + VNO;  // padded row of the staged C leaf
   static constexpr bool STAGED = int64_t(BS) * SC * sizeof(Out) <= A_LDS + B_LDS;
   static constexpr int LDS = A_LDS + B_LDS;
+  // FP32 accumulation in two levels: each leaf product is summed in its own
+  // registers and then added to the leaf's total, so the rounding error of
+  // a C entry grows with sqrt(bs) + sqrt(products) rather than with the
+  // square root of all bs * products terms
+  static constexpr bool TWO_LEVEL = P != SPAMM_F64;
   // resident workgroups per CU asked of the register allocator
   static constexpr int MINB = (BS == 64 && P != SPAMM_F64) ? 3 : 1;
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
@@ -133,47 +138,36 @@ __device__ __forceinline__ int b_swizzle(int g) {
 
 // ---------------------------------------------------------------- unit records
 
-// 64 unit records held one per lane.
-struct RecBlock {
-  int32_t pplo, pphi, cnt, cidx, req, cf;
-};
-
 // Scalar copy of one unit.
 struct UnitS {
   int64_t pp;
   int32_t cnt, cidx, req, cf;
 };
 
-__device__ __forceinline__ RecBlock load_recs(const WorkUnit* __restrict__ wu, int64_t u, int64_t u1) {
-  RecBlock b;
-  b.pplo = b.pphi = b.cnt = b.cidx = b.req = b.cf = 0;
-  const int64_t x = u + (threadIdx.x & 63);
-  if (x < u1) {
-    const auto p = as_global(reinterpret_cast<const i32x2*>(wu + x));
-    const i32x2 v0 = p[0], v1 = p[1], v2 = p[2];
-    b.pplo = v0[0];
-    b.pphi = v0[1];
-    b.cnt = v1[0];
-    b.cidx = v1[1];
-    b.req = v2[0];
-    b.cf = v2[1];
+// Unit records live in a two-block LDS ring, 64 records per block: block
+// `blk` holds units [u, u + 64) of the range.  Records are copied 8 bytes per
+// thread (a record is three 8-byte words).
+typedef int32_t i32x2r __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stage_recs(i32x2r (*ring)[64 * 3], int blk, const WorkUnit* __restrict__ wu,
+                                           int64_t u, int64_t u1, int tid, int nt) {
+  for (int w = tid; w < 64 * 3; w += nt) {
+    const int64_t x = u + w / 3;
+    if (x < u1) ring[blk][w] = *as_global(reinterpret_cast<const i32x2r*>(wu + x) + (w % 3));
   }
-  return b;
 }
 
-__device__ __forceinline__ UnitS unit_of(const RecBlock& b0, const RecBlock& b1, int64_t rel) {
-  const int l = int(rel & 63);
-  const bool first = rel < 64;
-#define SPAMM_PICK(f) (first ? __builtin_amdgcn_readlane(b0.f, l) : __builtin_amdgcn_readlane(b1.f, l))
+__device__ __forceinline__ UnitS unit_of(const i32x2r (*ring)[64 * 3], int blk0, int64_t rel) {
+  const int b = (blk0 + (rel >= 64 ? 1 : 0)) & 1;
+  const int r = int(rel & 63);
+  const i32x2r v0 = ring[b][3 * r], v1 = ring[b][3 * r + 1], v2 = ring[b][3 * r + 2];
   UnitS u;
-  const uint32_t lo = uint32_t(SPAMM_PICK(pplo));
-  const uint32_t hi = uint32_t(SPAMM_PICK(pphi));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(v0[0]));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(v0[1]));
   u.pp = int64_t((uint64_t(hi) << 32) | lo);
-  u.cnt = SPAMM_PICK(cnt);
-  u.cidx = SPAMM_PICK(cidx);
-  u.req = SPAMM_PICK(req);
-  u.cf = SPAMM_PICK(cf);
-#undef SPAMM_PICK
+  u.cnt = __builtin_amdgcn_readfirstlane(v1[0]);
+  u.cidx = __builtin_amdgcn_readfirstlane(v1[1]);
+  u.req = __builtin_amdgcn_readfirstlane(v2[0]);
+  u.cf = __builtin_amdgcn_readfirstlane(v2[1]);
   return u;
 }
 
@@ -207,8 +201,10 @@ template <int P, int BS>
 __device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restrict__ base, int32_t ia, int32_t ib,
                                            int sub, int tid) {
   using Cf = GemmCfg<P, BS>;
-  const char* A = base + int64_t(ia) * Cf::LEAF_IN;
-  const char* B = base + int64_t(ib) * Cf::LEAF_IN;
+  // wave-uniform leaf base plus a 32-bit lane offset (global loads with a
+  // scalar base address)
+  const auto A = as_global(base + int64_t(ia) * Cf::LEAF_IN);
+  const auto B = as_global(base + int64_t(ib) * Cf::LEAF_IN);
 #pragma unroll
   for (int t = 0; t < Cf::A_VECS; ++t) {
     const int v = tid + t * Cf::NT;
@@ -216,7 +212,7 @@ __device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restri
     const int h = v / Cf::PV, vv = v % Cf::PV;
     const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
     const uint32_t e = uint32_t(h * BS * BS + row * BS + sub * Cf::KP + cv * Cf::VN);  // uniform base + lane offset
-    r.a[t] = *as_global(reinterpret_cast<const u32x4*>(A + e * Cf::ES));
+    r.a[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(A + uint32_t(e * Cf::ES));
   }
 #pragma unroll
   for (int t = 0; t < Cf::B_VECS; ++t) {
@@ -231,7 +227,7 @@ __device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restri
       const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
       e = uint32_t((sub * Cf::KP + kr) * BS + cv * Cf::VN);
     }
-    r.b[t] = *as_global(reinterpret_cast<const u32x4*>(B + e * Cf::ES));
+    r.b[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(B + uint32_t(e * Cf::ES));
   }
 }
 
@@ -452,16 +448,19 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
   const int64_t u0 = ga.start[rank], u1 = ga.start[rank + 1];
   if (u0 >= u1) return;
 
-  // unit records [rb, rb + 128) in two lane-held blocks
+  // unit records [rb, rb + 128) in the LDS ring (block blk0 first)
+  __shared__ i32x2r ring[2][64 * 3];
   int64_t rb = u0;
-  RecBlock b0 = load_recs(ga.wu, rb, u1);
-  RecBlock b1 = load_recs(ga.wu, rb + 64, u1);
+  int blk0 = 0;
+  stage_recs(ring, 0, ga.wu, rb, u1, tid, Cf::NT);
+  stage_recs(ring, 1, ga.wu, rb + 64, u1, tid, Cf::NT);
+  __syncthreads();
 
   // pair windows: W0 holds the window of the product being multiplied, W1
   // and W2 the next two windows of the range (unit by unit, 64 products
   // each; a unit without products has one empty window); (pu, pw) is W2's
   int64_t cu = u0;
-  UnitS U = unit_of(b0, b1, 0);
+  UnitS U = unit_of(ring, blk0, 0);
   Win W0 = load_win(base, U, 0, true);
   int64_t pu = cu;
   int pw = 0;
@@ -472,7 +471,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
     } else {
       ++pu;
       pw = 0;
-      if (pu < u1) PU = unit_of(b0, b1, pu - rb);
+      if (pu < u1) PU = unit_of(ring, blk0, pu - rb);
     }
   };
   next_pos();
@@ -487,13 +486,20 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
   for (;;) {
     const bool has_next = cu + 1 < u1;
     int32_t next_cnt = 0;
-    if (has_next) next_cnt = unit_of(b0, b1, cu + 1 - rb).cnt;
+    if (has_next) next_cnt = unit_of(ring, blk0, cu + 1 - rb).cnt;
 
     Acc<P, BS> acc[Cf::TM][Cf::TN];
+    Acc<P, BS> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
 #pragma unroll
     for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
       for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, BS>{};
+    if constexpr (Cf::TWO_LEVEL) {
+#pragma unroll
+      for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < Cf::TN; ++b) part[a][b] = Acc<P, BS>{};
+    }
 
     for (int p = 0; p < U.cnt; ++p) {
       for (int sub = 0; sub < Cf::NPANEL; ++sub) {
@@ -515,7 +521,20 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
           load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W1.a, 0), __builtin_amdgcn_readlane(W1.b, 0), 0,
                             tid);
         }
-        compute_panel<P, BS>(acc, As, Bs, row0, col0, li, g);
+        if constexpr (Cf::TWO_LEVEL) {
+          compute_panel<P, BS>(part, As, Bs, row0, col0, li, g);
+          if (sub + 1 == Cf::NPANEL) {  // the product's sum joins the leaf's total
+#pragma unroll
+            for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+              for (int b = 0; b < Cf::TN; ++b) {
+                acc[a][b] += part[a][b];
+                part[a][b] = Acc<P, BS>{};
+              }
+          }
+        } else {
+          compute_panel<P, BS>(acc, As, Bs, row0, col0, li, g);
+        }
       }
       if (((p + 1) & 63) == 0 && p + 1 < U.cnt) {  // into the unit's next window
         W0 = W1;
@@ -531,11 +550,13 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
     const int32_t prev_cnt = U.cnt;
     ++cu;
     if (cu - rb == 64) {
+      // units below cu are done: their block takes units [rb + 128, rb + 192),
+      // first read some 60 units (and as many barriers) later
       rb += 64;
-      b0 = b1;
-      b1 = load_recs(ga.wu, rb + 64, u1);
+      blk0 ^= 1;
+      stage_recs(ring, blk0 ^ 1, ga.wu, rb + 64, u1, tid, Cf::NT);
     }
-    U = unit_of(b0, b1, cu - rb);
+    U = unit_of(ring, blk0, cu - rb);
     W0 = W1;
     W1 = W2;
     next_pos();

@@ -106,6 +106,8 @@ _SIGS = {
     "spamm_skipped_bound": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
     "spamm_to_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "spamm_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p]),
     "spamm_mat_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MatInfo)]),
     "spamm_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -310,6 +312,15 @@ class Context:
         n = m.info.n
         out = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
+        return out
+
+    def leaves(self, m: Matrix, ij) -> np.ndarray:
+        """FP64 copies of the leaves at block coordinates ij (k, 2): (k, bs, bs)."""
+        ij = np.ascontiguousarray(np.asarray(ij, dtype=np.int32).reshape(-1, 2))
+        bs = m.info.leaf
+        out = np.zeros((len(ij), bs, bs), dtype=np.float64)
+        self._check(_lib.spamm_leaves(self.ptr, m.handle, ij.ctypes.data_as(ctypes.c_void_p), len(ij),
+                                      out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def __enter__(self):

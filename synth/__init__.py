@@ -30,6 +30,8 @@ always feeds the *same* generated bits to every consumer.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -119,15 +121,41 @@ class DecaySpec:
         j = np.arange(c0, c1, dtype=np.int64)[None, :]
         i, j = np.broadcast_arrays(i, j)
         u = uniform(self.seed, i, j, self.n)
-        a = (2.0 * u - 1.0) * np.exp(-self.alpha * self.distance(i, j))
+        if self.kind == "1d":
+            env = np.exp(-self.alpha * self.distance(i, j))
+        else:
+            # the envelope depends on the atom pair only: the same distance
+            # and exponential as per entry, evaluated once per atom pair
+            ai = np.arange(r0, r1, dtype=np.int64) // self.fpa
+            aj = np.arange(c0, c1, dtype=np.int64) // self.fpa
+            a0, b0 = ai[0], aj[0]
+            pa = self._pos[a0:ai[-1] + 1]
+            pb = self._pos[b0:aj[-1] + 1]
+            d = pa[:, None, :] - pb[None, :, :]
+            e_atoms = np.exp(-self.alpha * np.sqrt((d * d).sum(axis=-1)))
+            env = e_atoms[(ai - a0)[:, None], (aj - b0)[None, :]]
+        a = (2.0 * u - 1.0) * env
         a[np.abs(a) < TINY] = 0.0
         return a
 
     def dense(self) -> np.ndarray:
+        """The whole matrix; row blocks are generated on a thread pool (the
+        values do not depend on the split)."""
         out = np.empty((self.n, self.n), dtype=np.float64)
-        step = max(1, (1 << 22) // max(self.n, 1))
-        for r in range(0, self.n, step):
+        step = max(1, (1 << 21) // max(self.n, 1))
+        starts = list(range(0, self.n, step))
+
+        def fill(r):
             out[r:r + step] = self.block(r, r + step, 0, self.n)
+
+        workers = min(16, os.cpu_count() or 1, len(starts))
+        if workers <= 1:
+            for r in starts:
+                fill(r)
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(workers) as ex:
+                list(ex.map(fill, starts))
         return out
 
     def leaf_blocks(self, bs: int):

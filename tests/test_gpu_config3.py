@@ -1,0 +1,68 @@
+"""Full-size 3D decay parity: 4096 atoms x 8 functions (n = 32768), a_ij =
+(2u-1) exp(-dist), leaf 64, tau = 1e-6, the size the benchmark times.  The
+oracle's kept lists and accounting are complete; C is compared on sampled
+leaves (every diagonal leaf of a stride and random leaves), which the oracle
+computes one by one."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_1906_08148_amd import spamm
+
+from parity import TIE_BAND, TOL, compare_kept, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+N, LEAF, TAU, ALPHA = 32768, 64, 1e-6, 1.0
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    print("case: config3 generate", flush=True)
+    A = synth.DecaySpec("3d", N, ALPHA, seed=1).dense()
+    T = O.build(A, LEAF)
+    ctx = spamm.Context(arena_bytes=48 << 30)
+    print("case: config3 build", flush=True)
+    dA = torch.from_numpy(A).cuda()
+    M = ctx.build(dA, LEAF, stores=spamm.STORE_F32 | spamm.STORE_BF16)
+    del dA
+    torch.cuda.synchronize()
+    G = T.G
+    rng = np.random.default_rng(5)
+    diag = [(i, i) for i in range(0, G, 8)]
+    rand = [tuple(x) for x in rng.integers(0, G, size=(128, 2))]
+    sample = sorted(set(diag + rand))
+    yield ctx, M, T, A, sample
+    M.release()
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [spamm.SPAMM, spamm.HYBRID])
+def test_config3_kept_lists_and_sampled_leaves(setup, mode):
+    ctx, M, T, A, sample = setup
+    print(f"case: config3 mode={mode} oracle", flush=True)
+    ref = O.multiply(T, T, TAU, mode, c_blocks=sample)
+    ties = O.tie_triples(ref.A_used, ref.B_used, TAU, TIE_BAND)
+    want = np.stack([ref.C.leaf(I, J) if ref.C.index[I, J] >= 0 else np.zeros((LEAF, LEAF))
+                     for I, J in sample])
+    for prec in (spamm.F32, spamm.BF16, spamm.BF16X3):
+        print(f"case: config3 mode={mode} prec={prec}", flush=True)
+        p = ctx.multiply(M, M, TAU, mode=mode, prec=prec)
+        st = p.stats
+        if prec == spamm.F32:
+            ndiff = compare_kept(ctx.kept(p.C), ref.kept, ties, T.G)
+            assert st["n_kept"] == ref.stats["n_kept"] or ndiff > 0
+            if ndiff == 0 and not ref.stats["trunc_tie"]:
+                assert st["n_candidates"] == ref.stats["n_candidates"]
+                assert st["c_nonnull"] == ref.stats["c_nonnull"]
+                for k in ("B1", "B2", "dA", "dB"):
+                    assert abs(st[k] - ref.stats[k]) <= 1e-10 * max(abs(ref.stats[k]), 1e-300) + 1e-300, k
+        got = ctx.leaves(p.C, sample)
+        r = rel_fro(got, want)
+        print(f"  rel {r:.3e} kept {st['n_kept']}", flush=True)
+        assert r <= TOL[prec], f"prec {prec}: rel {r:.3e}"
+        p.C.release()
