@@ -175,6 +175,39 @@ def dense3d(steps):
     return out
 
 
+def purification(steps):
+    """20 trace-driven purification steps (X^2 or 2X - X^2, Hybrid, tau 1e-6)
+    on the 3D decay matrix n = 32768 scaled into [0, 1], FP64 and FP32 chains
+    side by side; per step the trace, products, time and ||X32 - X64||_F."""
+    import torch
+    import synth
+    from paper_1906_08148_amd import purify, spamm
+    A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).dense()
+    ctx = spamm.Context(arena_bytes=96 << 30)
+    dA = torch.from_numpy(A).cuda()
+    del A
+    X = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32)
+    torch.cuda.synchronize()
+    del dA
+    recs, diffs, (lo, hi) = purify.sp2(ctx, X, N3D / 2, TAU3D, steps, precs=(spamm.F64, spamm.F32))
+    X.release()
+    ctx.close()
+    out = {"workload": f"SP2 purification of the 3D decay matrix n={N3D}, leaf {LEAF3D}, hybrid, tau {TAU3D}, "
+                       f"n_occ = n/2, {steps} steps", "gershgorin": [lo, hi], "steps": []}
+    for k in range(steps):
+        r64, r32 = recs[spamm.F64][k], recs[spamm.F32][k]
+        out["steps"].append({"k": k, "trace64": round(r64.trace, 6), "trace32": round(r32.trace, 6),
+                             "branch64": r64.branch, "branch32": r32.branch,
+                             "kept64": r64.n_kept, "kept32": r32.n_kept,
+                             "ms64": round(r64.seconds * 1e3, 1), "ms32": round(r32.seconds * 1e3, 1),
+                             "gflops32": round(r32.flops / r32.seconds / 1e9, 1),
+                             "idempotency64": r64.idempotency, "x32_minus_x64": diffs[spamm.F32][k]})
+    t64 = sum(r.seconds for r in recs[spamm.F64])
+    t32 = sum(r.seconds for r in recs[spamm.F32])
+    out["total_s"] = {"f64": round(t64, 3), "f32": round(t32, 3)}
+    return out
+
+
 def pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -300,6 +333,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D decay n=32768 section")
     ap.add_argument("--steps-3d", type=int, default=3)
+    ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
+    ap.add_argument("--purify-steps", type=int, default=20)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device (a plain copy "
                          "kernel of known traffic, to scale hardware byte counters)")
@@ -382,6 +417,9 @@ def main():
     if not args.skip_extras and not args.no_3d:
         log("bench: 3D decay n=32768")
         out["dense3d"] = dense3d(args.steps_3d)
+    if not args.skip_extras and not args.no_purify:
+        log("bench: purification n=32768")
+        out["purification"] = purification(args.purify_steps)
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)

@@ -254,6 +254,15 @@ spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C,
 spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out,
                             int64_t ld);
 
+/* Gershgorin bounds of the spectrum of a square matrix: *lo = min over rows
+ * i < n of a_ii - sum_{j != i} |a_ij|, *hi = max of a_ii + sum_{j != i}
+ * |a_ij| (host doubles), from the FP64 leaf copy (FP32 when that is the only
+ * copy), in FP64.  Used to scale a matrix into [0, 1] before purification
+ * (the density-matrix purification the paper's introduction cites).
+ * Synchronises.  Errors: EINVAL, ENOMEM, EDEVICE. */
+spamm_status spamm_gershgorin(spamm_ctx* ctx, const spamm_mat* m, double* lo,
+                              double* hi);
+
 /* Copy `count` leaves (block row ij[2t], block column ij[2t+1], host int32)
  * of a matrix into `out` (host, FP64, count * bs * bs values, leaf t
  * row-major at t * bs * bs); null leaves give zeros, entries beyond n are the

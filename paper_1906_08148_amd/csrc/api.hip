@@ -1040,6 +1040,24 @@ spamm_status spamm_skipped_bound(spamm_ctx* ctx, const spamm_mat* C, double* out
   return download(c, out, C->plan_bnd->ptr(), G2 * 8);
 }
 
+spamm_status spamm_gershgorin(spamm_ctx* ctx, const spamm_mat* m, double* lo, double* hi) {
+  if (!ctx || !m || !lo || !hi) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  const Store& s = *m->store;
+  if (!s.f64 && !s.f32) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 leaf copy");
+  RegionP part, res;
+  ALLOC(part, int64_t(m->G) * 16, "Gershgorin partials");
+  ALLOC(res, 16, "Gershgorin bounds");
+  SPAMM_HIP(c, launch_gershgorin(c->stream, m->n, m->bs, m->G, P<int32_t>(m->slot), P<double>(s.f64),
+                                 s.f64 ? nullptr : P<float>(s.f32), P<double>(part), P<double>(res)));
+  double h[2];
+  spamm_status st = download(c, h, res->ptr(), 16);
+  if (st != SPAMM_OK) return st;
+  *lo = h[0];
+  *hi = h[1];
+  return SPAMM_OK;
+}
+
 spamm_status spamm_leaves(spamm_ctx* ctx, const spamm_mat* m, const int32_t* ij, int64_t count, double* out) {
   if (!ctx || !m || (count > 0 && (!ij || !out)) || count < 0) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;

@@ -369,6 +369,8 @@ bool gemm_supported(int prec, int bs);
 hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu,
                                const double* wn, const double* wt);
 hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
+hipError_t launch_gershgorin(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot, const double* f64,
+                             const float* f32, double* part, double* out);
 hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int32_t* slot, const double* f64,
                                 const float* f32, const int32_t* ij, double* out);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);

@@ -475,6 +475,79 @@ hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int3
   return hipGetLastError();
 }
 
+// Gershgorin discs, one workgroup per leaf row: every row i < n of the
+// leaf row gets lo_i = a_ii - sum_{j != i} |a_ij| and hi_i = a_ii + sum; the
+// workgroup keeps the min / max of its rows in part[2 * I], part[2 * I + 1]
+// (rows past n are padding and are skipped).
+__global__ void __launch_bounds__(256) k_gersh_rows(int64_t n, int bs, int G, const int32_t* __restrict__ slot,
+                                                    const double* __restrict__ f64, const float* __restrict__ f32,
+                                                    double* __restrict__ part) {
+  __shared__ double rad[256], dia[256];
+  __shared__ double mn[256], mx[256];
+  const int I = blockIdx.x;
+  const int tpr = blockDim.x / bs;  // threads per row (bs <= 256)
+  const int r = threadIdx.x % bs, q = threadIdx.x / bs;
+  const int64_t e2 = int64_t(bs) * bs;
+  double s = 0.0, d = 0.0;
+  for (int J = 0; J < G; ++J) {
+    const int32_t sl = slot[morton(uint32_t(I), uint32_t(J))];
+    if (sl < 0) continue;
+    for (int c = q; c < bs; c += tpr) {
+      const int64_t e = sl * e2 + int64_t(r) * bs + c;
+      const double v = f64 ? f64[e] : double(f32[e]);
+      if (J == I && c == r) d = v;
+      else s += fabs(v);
+    }
+  }
+  rad[threadIdx.x] = s;
+  dia[threadIdx.x] = d;
+  __syncthreads();
+  double lo = 1e308, hi = -1e308;
+  if (q == 0 && threadIdx.x < bs) {
+    double rs = 0.0, dd = 0.0;
+    for (int t = 0; t < tpr; ++t) {
+      rs += rad[r + t * bs];
+      dd += dia[r + t * bs];
+    }
+    if (int64_t(I) * bs + r < n) {
+      lo = dd - rs;
+      hi = dd + rs;
+    }
+  }
+  mn[threadIdx.x] = lo;
+  mx[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 1e308, b = -1e308;
+    for (int t = 0; t < bs; ++t) {
+      a = fmin(a, mn[t]);
+      b = fmax(b, mx[t]);
+    }
+    part[2 * I] = a;
+    part[2 * I + 1] = b;
+  }
+}
+
+__global__ void k_gersh_final(int G, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double a = 1e308, b = -1e308;
+  for (int I = 0; I < G; ++I) {
+    a = fmin(a, part[2 * I]);
+    b = fmax(b, part[2 * I + 1]);
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
+hipError_t launch_gershgorin(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot, const double* f64,
+                             const float* f32, double* part, double* out) {
+  hipLaunchKernelGGL(k_gersh_rows, dim3(uint32_t(G)), dim3(256), 0, s, n, bs, G, slot, f64, f32, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(64), 0, s, G, part, out);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;

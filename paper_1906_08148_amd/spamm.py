@@ -106,6 +106,8 @@ _SIGS = {
     "spamm_skipped_bound": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
     "spamm_to_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "spamm_gershgorin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "spamm_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_void_p]),
     "spamm_mat_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MatInfo)]),
@@ -313,6 +315,24 @@ class Context:
         out = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
         return out
+
+    def gershgorin(self, m: Matrix):
+        """(lo, hi) Gershgorin bounds of the spectrum, FP64."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.spamm_gershgorin(self.ptr, m.handle, ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
+
+    def identity(self, n: int, leaf: int, stores: int = STORE_F64 | STORE_F32) -> Matrix:
+        """The n x n identity as a quadtree (diagonal leaves only)."""
+        import torch
+        g = -(-n // leaf)
+        coords = torch.tensor([[i, i] for i in range(g)], dtype=torch.int32, device=f"cuda:{self.device}")
+        blk = np.zeros((g, leaf, leaf), dtype=np.float64)
+        for i in range(g):
+            m = min(leaf, n - i * leaf)
+            blk[i, np.arange(m), np.arange(m)] = 1.0
+        data = torch.from_numpy(blk).to(f"cuda:{self.device}")
+        return self.build_blocks(n, leaf, coords, data, stores=stores)
 
     def leaves(self, m: Matrix, ij) -> np.ndarray:
         """FP64 copies of the leaves at block coordinates ij (k, 2): (k, bs, bs)."""
