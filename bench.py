@@ -208,6 +208,47 @@ def purification(steps):
     return out
 
 
+def serving(n_requests, n_max, rates=(0.5, 0.8, 1.0, 1.2)):
+    """Served stream: the first `n_requests` requests with n <= n_max of the
+    seeded request pool (n in 2048..65536, 1D/3D decay, alpha, tau, scheme
+    drawn per request, FP32, A = B).  Capacity mu is measured alone (one lane, one request per
+    batch); then Poisson arrivals at rate x mu for each x, two lanes with
+    continuous batching and memory admission, fresh lanes (cold quadtree
+    caches) per run."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1906_08148_amd import serve
+    pool = [r for r in serve.request_pool(512) if r.mat.n <= n_max][:n_requests]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(4) as ex:
+        mats = list({r.mat: None for r in pool})
+        inputs = dict(zip(mats, ex.map(lambda m: serve.make_input(m, 64), mats)))
+    gen_s = time.perf_counter() - t0
+    lane_bytes = 60 << 30
+    srv = serve.Server(lanes=1, arena_bytes_per_lane=lane_bytes, max_batch=1, inputs=inputs)
+    t0 = time.perf_counter()
+    alone = serve.run_stream(srv.sched, pool, rate=0)
+    t_alone = time.perf_counter() - t0
+    srv.close()
+    torch.cuda.empty_cache()
+    mu = len(pool) / t_alone
+    out = {"workload": f"first {len(pool)} requests with n <= {n_max} of the seeded pool (n in 2048..65536 step "
+                       f"2048, 1D/3D decay, alpha U[0.2,1], tau 10^U[-8,-4], truncmul/spamm/hybrid, FP32, A=B)",
+           "generate_s": round(gen_s, 1), "alone": serve.summarize(alone, t_alone), "mu_per_s": mu,
+           "kinds": [f"{r.mat.kind}:{r.mat.n}" for r in pool], "runs": {}}
+    for x in rates:
+        log(f"bench: serving at {x} mu")
+        srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs)
+        res = serve.run_stream(srv.sched, pool, rate=x * mu, seed=11)
+        srv.close()
+        torch.cuda.empty_cache()
+        sm = serve.summarize(res)
+        sm["gflops_frac_of_fp32_peak"] = sm.get("gflops", 0.0) / 1e3 / FP32_MFMA_PEAK_TFLOPS
+        sm["batches"] = len(srv.sched.log)
+        out["runs"][str(x)] = sm
+    return out
+
+
 def pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -335,6 +376,8 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=3)
     ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
     ap.add_argument("--purify-steps", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the served stream (0: skip)")
+    ap.add_argument("--serve-nmax", type=int, default=32768, help="largest n of the served sample (pool: 65536)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device (a plain copy "
                          "kernel of known traffic, to scale hardware byte counters)")
@@ -420,6 +463,9 @@ def main():
     if not args.skip_extras and not args.no_purify:
         log("bench: purification n=32768")
         out["purification"] = purification(args.purify_steps)
+    if not args.skip_extras and args.serve_requests > 0:
+        log("bench: serving")
+        out["serving"] = serving(args.serve_requests, args.serve_nmax)
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)

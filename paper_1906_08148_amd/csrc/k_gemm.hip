@@ -572,13 +572,12 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
 
 template <int P, int BS>
 static int max_groups(int n_cu) {
-  static int per_cu = -1;
-  if (per_cu < 0) {
+  static const int per_cu = [] {  // thread-safe one-time query
     int v = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS>, GemmCfg<P, BS>::NT, 0) != hipSuccess || v < 1)
       v = 1;
-    per_cu = v;
-  }
+    return v;
+  }();
   return per_cu * n_cu;
 }
 
