@@ -128,7 +128,6 @@ def dense3d(steps):
     del A
     M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
     torch.cuda.synchronize()
-    del dA
     out = {"workload": f"3D decay n={N3D} (4096 atoms x 8 functions), alpha {ALPHA3D}, leaf {LEAF3D}, "
                        f"tau {TAU3D}, A=B", "generate_s": round(gen_s, 1), "runs": {}}
     peaks = {spamm.F64: FP64_MFMA_PEAK_TFLOPS, spamm.F32: FP32_MFMA_PEAK_TFLOPS,
@@ -171,6 +170,16 @@ def dense3d(steps):
         del ref
         torch.cuda.empty_cache()
     M.release()
+    # leaf size and MFMA tile picked by the autotuner (hybrid, FP32)
+    from paper_1906_08148_amd import autotune
+    log("bench: 3D autotune")
+    tuner = autotune.Tuner(ctx, leaves=(32, 64, 128), tiles=(0, 1), reps=2)
+    sig = autotune.signature("3d", N3D, ALPHA3D, TAU3D, spamm.HYBRID, spamm.F32)
+    best = tuner.tune(lambda leaf: ctx.build(dA, leaf, stores=spamm.STORE_F32), sig, TAU3D, spamm.HYBRID, spamm.F32)
+    out["autotune"] = {"leaf": best["leaf"], "tile": best["tile"],
+                       "table": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                                 for r in best["table"]]}
+    del dA
     ctx.close()
     return out
 

@@ -161,6 +161,28 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx);
 /* Change the stream later calls enqueue on. */
 spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
 
+/* Tunable behaviour of a context (spamm_ctx_set_option / get_option).
+ *  SPAMM_OPT_GEMM_TILE  0: 32 x 32 MFMA tiles for FP32 / BF16 leaf products
+ *                       where a wave's tile allows it (default); 1: 16 x 16.
+ *  SPAMM_OPT_PLACEMENT  0: each request's C leaves in eight Morton slices,
+ *                       one per XCD (default); 1: request after request.
+ *  SPAMM_OPT_GRAPH      0: launch the kernels of a batch one by one
+ *                       (default); 1: capture the kernels that follow the
+ *                       sizing read-back into one HIP graph per batch and
+ *                       launch that (an instantiated graph of the same shape
+ *                       is updated in place).  Ignored while event timing
+ *                       is on.
+ * All options give bitwise identical results.  Errors: EINVAL (unknown key
+ * or value). */
+typedef enum {
+  SPAMM_OPT_GEMM_TILE = 0,
+  SPAMM_OPT_PLACEMENT = 1,
+  SPAMM_OPT_GRAPH = 2
+} spamm_option;
+
+spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value);
+spamm_status spamm_ctx_get_option(const spamm_ctx* ctx, spamm_option key, int64_t* value);
+
 /* Arena occupancy in bytes (host outputs, any may be NULL). */
 spamm_status spamm_ctx_arena_info(const spamm_ctx* ctx, size_t* used,
                                   size_t* free_bytes, size_t* largest_free);

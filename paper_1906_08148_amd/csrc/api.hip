@@ -245,9 +245,12 @@ spamm_status prep_many(Ctx* c, const std::vector<spamm_mat*>& mats) {
 }
 
 // Pyramid over a set of matrices whose leaf level is filled.
-spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls) {
+// Pyramid jobs over a set of matrices whose leaf level is filled: the job
+// table is uploaded here, the launch is separate (it may be captured).
+spamm_status pyramids_prepare(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls, RegionP& jd,
+                              std::vector<PyrJob>& jobs) {
+  jobs.assign(norms.size(), PyrJob{});
   if (norms.empty()) return SPAMM_OK;
-  std::vector<PyrJob> jobs(norms.size());
   int64_t base = 0;
   for (size_t t = 0; t < norms.size(); ++t) {
     jobs[t].norms = norms[t];
@@ -256,13 +259,23 @@ spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vect
     jobs[t].block_base = base;
     base += int64_t(1) << (2 * (Ls[t] - jobs[t].sub_levels));
   }
-  RegionP jd;
   ALLOC(jd, jobs.size() * sizeof(PyrJob), "pyramid jobs");
-  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PyrJob));
-  if (st != SPAMM_OK) return st;
+  return upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PyrJob));
+}
+
+spamm_status pyramids_launch(Ctx* c, const RegionP& jd, const std::vector<PyrJob>& jobs) {
+  if (jobs.empty()) return SPAMM_OK;
   TimedScope ts(c, kTPyr);
   SPAMM_HIP(c, launch_pyramid(c->stream, P<PyrJob>(jd), int(jobs.size()), jobs));
   return SPAMM_OK;
+}
+
+spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls) {
+  RegionP jd;
+  std::vector<PyrJob> jobs;
+  spamm_status st = pyramids_prepare(c, norms, Ls, jd, jobs);
+  if (st != SPAMM_OK) return st;
+  return pyramids_launch(c, jd, jobs);
 }
 
 spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask) {
@@ -422,6 +435,8 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   if (c->live_handles != 0) return fail(c, SPAMM_EINVAL, "handles still alive");
   hipStreamSynchronize(c->stream);
   c->collect_timing();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (auto& r : c->up_inflight) (void)hipEventDestroy(r.ev);
   for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
@@ -429,6 +444,29 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   if (c->host_stage) (void)hipHostFree(c->host_stage);
   delete ctx;
   return SPAMM_OK;
+}
+
+spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value) {
+  if (!ctx) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (value != 0 && value != 1) return fail(c, SPAMM_EINVAL, "option value must be 0 or 1");
+  switch (key) {
+    case SPAMM_OPT_GEMM_TILE: c->gemm_tile = int(value); return SPAMM_OK;
+    case SPAMM_OPT_PLACEMENT: c->gemm_sched = int(value); return SPAMM_OK;
+    case SPAMM_OPT_GRAPH: c->use_graph = int(value); return SPAMM_OK;
+    default: return fail(c, SPAMM_EINVAL, "unknown option");
+  }
+}
+
+spamm_status spamm_ctx_get_option(const spamm_ctx* ctx, spamm_option key, int64_t* value) {
+  if (!ctx || !value) return SPAMM_EINVAL;
+  const Ctx* c = &ctx->c;
+  switch (key) {
+    case SPAMM_OPT_GEMM_TILE: *value = c->gemm_tile; return SPAMM_OK;
+    case SPAMM_OPT_PLACEMENT: *value = c->gemm_sched; return SPAMM_OK;
+    case SPAMM_OPT_GRAPH: *value = c->use_graph; return SPAMM_OK;
+    default: return SPAMM_EINVAL;
+  }
 }
 
 spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream) {
@@ -865,7 +903,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     int gi = 0;
     for (auto& gk : groups) {
       const int64_t nwu = launches[gi++].second.second;
-      const int64_t maxg = gemm_max_groups(gk.first.first, gk.first.second, c->n_cu);
+      const int64_t maxg = gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
       const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, nwu));
       const int kx = int((want + kXcds - 1) / kXcds);
       kxs.push_back(kx);
@@ -900,12 +938,30 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   }
   st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
   if (st != SPAMM_OK) return st;
+  // C pyramid jobs and statistics buffers are set up before the launches,
+  // which then need no host copies (they may be captured into one graph)
+  RegionP pyr_jd, sd, part;
+  std::vector<PyrJob> pyr_jobs;
   {
-    TimedScope ts(c, kTPrune);
-    SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
-                                   P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus), P<int64_t>(costs)));
+    std::vector<double*> nv;
+    std::vector<int> lv;
+    for (int r = 0; r < count; ++r) {
+      nv.push_back(P<double>(Cs[r]->norms));
+      lv.push_back(Cs[r]->L);
+    }
+    st = pyramids_prepare(c, nv, lv, pyr_jd, pyr_jobs);
+    if (st != SPAMM_OK) return st;
   }
-  {
+  if (st_out) {
+    ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
+    ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
+  }
+  auto post = [&]() -> spamm_status {
+    {
+      TimedScope ts(c, kTPrune);
+      SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
+                                     P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus), P<int64_t>(costs)));
+    }
     int gi = 0;
     int64_t soff = 0;
     for (auto& gk : groups) {
@@ -935,32 +991,61 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
         for (int r : gk.second)
           c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
       }
-      SPAMM_HIP(c, launch_gemm(c->stream, gk.first.first, gk.first.second, ga));
+      SPAMM_HIP(c, launch_gemm(c->stream, gk.first.first, gk.first.second, c->gemm_tile, ga));
     }
-  }
-  {
-    TimedScope ts(c, kTPyr);
-    SPAMM_HIP(c, launch_unit_scatter(c->stream, P<ReqDev>(reqd), P<WorkUnit>(wus), wu_total, P<double>(wn),
-                                     P<double>(wt)));
-  }
-  {
-    std::vector<double*> nv;
-    std::vector<int> lv;
-    for (int r = 0; r < count; ++r) {
-      nv.push_back(P<double>(Cs[r]->norms));
-      lv.push_back(Cs[r]->L);
+    {
+      TimedScope ts(c, kTPyr);
+      SPAMM_HIP(c, launch_unit_scatter(c->stream, P<ReqDev>(reqd), P<WorkUnit>(wus), wu_total, P<double>(wn),
+                                       P<double>(wt)));
     }
-    st = pyramids(c, nv, lv);
+    spamm_status s2 = pyramids_launch(c, pyr_jd, pyr_jobs);
+    if (s2 != SPAMM_OK) return s2;
+    if (st_out)
+      SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, total_chunks, P<StatPartial>(part),
+                                    P<ReqStatsDev>(sd)));
+    return SPAMM_OK;
+  };
+  if (c->use_graph && !c->timing) {
+    // one graph per batch; an instantiated graph of the same shape is
+    // updated in place instead of instantiated again
+    // recorded on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured) and launched on the caller's
+    if (!c->cap_stream) SPAMM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    SPAMM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    const spamm_status s1 = post();
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (s1 != SPAMM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return s1 != SPAMM_OK ? s1 : fail(c, SPAMM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (c->gexec) {
+      hipGraphNode_t bad = nullptr;
+      hipGraphExecUpdateResult res;
+      if (hipGraphExecUpdate(c->gexec, g, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
+    }
+    hipError_t e2 = hipSuccess;
+    if (!c->gexec) e2 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      c->gexec = nullptr;
+      return fail(c, SPAMM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    SPAMM_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    st = post();
     if (st != SPAMM_OK) return st;
   }
 
   // ---- statistics (one copy back for the whole batch)
   if (st_out) {
-    RegionP sd, part;
-    ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
-    ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
-    SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, total_chunks, P<StatPartial>(part),
-                                  P<ReqStatsDev>(sd)));
     std::vector<ReqStatsDev> hs(count);
     st = download(c, hs.data(), sd->ptr(), count * sizeof(ReqStatsDev));
     if (st != SPAMM_OK) return st;

@@ -132,6 +132,10 @@ struct Ctx {
   std::vector<hipEvent_t> up_events;
   int n_cu = 256;
   int gemm_sched = 0;  // work-unit placement: 0 per-XCD Morton slices, 1 request-major
+  int gemm_tile = 0;   // GEMM variant (MFMA tile shape), see launch_gemm
+  int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
+  hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
+  hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
   int live_handles = 0;
   RegionP alloc(size_t bytes, size_t align = 256);  // nullptr on exhaustion
@@ -362,8 +366,10 @@ constexpr int kXcds = 8;  // slices of the placement: workgroup w runs on XCD w 
 // start[r] = first unit whose cost prefix reaches r / nwg of the total
 hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, int nwg, int64_t* start);
 // GEMM over the work units of one (precision, leaf size) group
-hipError_t launch_gemm(hipStream_t s, int prec, int bs, const GemmArgs& a);
-int gemm_max_groups(int prec, int bs, int n_cu);  // resident workgroups of the kernel on the device
+// variant 0: 32 x 32 MFMA tiles for FP32 / BF16 where a wave's tile allows
+// it; variant 1: 16 x 16 tiles
+hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmArgs& a);
+int gemm_max_groups(int prec, int bs, int variant, int n_cu);  // resident workgroups of the kernel
 bool gemm_supported(int prec, int bs);
 // leaf norms and trace parts of the units into each request's C pyramid
 hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu,

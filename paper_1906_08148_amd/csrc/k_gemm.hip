@@ -50,7 +50,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 
-template <int P, int BS>
+template <int P, int BS, int V>
 struct GemmCfg {
   static constexpr bool kBf = P == SPAMM_BF16 || P == SPAMM_BF16X3;
   static constexpr int NH = P == SPAMM_BF16X3 ? 2 : 1;  // hi / lo halves staged
@@ -60,7 +60,9 @@ struct GemmCfg {
   static constexpr int WM = BS >= 32 ? 2 : 1;
   static constexpr int WN = BS >= 32 ? 2 : 1;
   static constexpr int TILE_M = BS / WM, TILE_N = BS / WN;
-  static constexpr int MT = (P != SPAMM_F64 && TILE_M % 32 == 0) ? 32 : 16;
+  // MFMA tile: 32 x 32 for FP32 / BF16 where a wave's tile allows it
+  // (variant 0), else 16 x 16 (variant 1, and always for FP64)
+  static constexpr int MT = (V == 0 && P != SPAMM_F64 && TILE_M % 32 == 0) ? 32 : 16;
   static constexpr int NG = 64 / MT;      // lane groups
   static constexpr int AE = MT * MT / 64;  // accumulator registers per tile
   static constexpr int TM = TILE_M / MT, TN = TILE_N / MT;
@@ -115,25 +117,25 @@ template <>
 struct AccSel<SPAMM_BF16X3, 32> {
   using type = f32x16;
 };
-template <int P, int BS>
-using Acc = typename AccSel<P, GemmCfg<P, BS>::MT>::type;
-template <int P, int BS>
-using AccTiles = Acc<P, BS>[GemmCfg<P, BS>::TM][GemmCfg<P, BS>::TN];
+template <int P, int BS, int V>
+using Acc = typename AccSel<P, GemmCfg<P, BS, V>::MT>::type;
+template <int P, int BS, int V>
+using AccTiles = Acc<P, BS, V>[GemmCfg<P, BS, V>::TM][GemmCfg<P, BS, V>::TN];
 
 // Row within an MFMA tile of accumulator register v held by lane group g:
 // FP64 16x16x4: 4v + g (interleaved); FP32/BF16 16-wide: 4g + v;
 // FP32/BF16 32-wide: 8(v/4) + 4g + v%4.
-template <int P, int BS>
+template <int P, int BS, int V>
 __device__ __forceinline__ int acc_row(int g, int v) {
-  if constexpr (GemmCfg<P, BS>::MT == 32) return 8 * (v / 4) + 4 * g + (v % 4);
+  if constexpr (GemmCfg<P, BS, V>::MT == 32) return 8 * (v / 4) + 4 * g + (v % 4);
   else if constexpr (P == SPAMM_F64) return 4 * v + g;
   else return 4 * g + v;
 }
 
 // FP32/FP64 B panel column swizzle of lane group g.
-template <int P, int BS>
+template <int P, int BS, int V>
 __device__ __forceinline__ int b_swizzle(int g) {
-  return (g * GemmCfg<P, BS>::MT) % BS;
+  return (g * GemmCfg<P, BS, V>::MT) % BS;
 }
 
 // ---------------------------------------------------------------- unit records
@@ -190,17 +192,17 @@ __device__ __forceinline__ Win load_win(const char* __restrict__ base, const Uni
 
 // ---------------------------------------------------------------- panels
 
-template <int P, int BS>
+template <int P, int BS, int V>
 struct Panel {
-  u32x4 a[GemmCfg<P, BS>::A_VECS];
-  u32x4 b[GemmCfg<P, BS>::B_VECS];
+  u32x4 a[GemmCfg<P, BS, V>::A_VECS];
+  u32x4 b[GemmCfg<P, BS, V>::B_VECS];
 };
 
 // k-panel `sub` of product (leaf ia of A, leaf ib of B) into registers.
-template <int P, int BS>
-__device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restrict__ base, int32_t ia, int32_t ib,
+template <int P, int BS, int V>
+__device__ __forceinline__ void load_panel(Panel<P, BS, V>& r, const char* __restrict__ base, int32_t ia, int32_t ib,
                                            int sub, int tid) {
-  using Cf = GemmCfg<P, BS>;
+  using Cf = GemmCfg<P, BS, V>;
   // wave-uniform leaf base plus a 32-bit lane offset (global loads with a
   // scalar base address)
   const auto A = as_global(base + int64_t(ia) * Cf::LEAF_IN);
@@ -231,9 +233,9 @@ __device__ __forceinline__ void load_panel(Panel<P, BS>& r, const char* __restri
   }
 }
 
-template <int P, int BS>
-__device__ __forceinline__ void store_panel(const Panel<P, BS>& r, char* As, char* Bs, int tid) {
-  using Cf = GemmCfg<P, BS>;
+template <int P, int BS, int V>
+__device__ __forceinline__ void store_panel(const Panel<P, BS, V>& r, char* As, char* Bs, int tid) {
+  using Cf = GemmCfg<P, BS, V>;
 #pragma unroll
   for (int t = 0; t < Cf::A_VECS; ++t) {
     const int v = tid + t * Cf::NT;
@@ -252,16 +254,16 @@ __device__ __forceinline__ void store_panel(const Panel<P, BS>& r, char* As, cha
       *reinterpret_cast<u32x4*>(Bs + ((h * BS + row) * Cf::SA + cv * Cf::VN) * Cf::ES) = r.b[t];
     } else {
       const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
-      const int sw = b_swizzle<P, BS>(kr / Cf::KG);
+      const int sw = b_swizzle<P, BS, V>(kr / Cf::KG);
       *reinterpret_cast<u32x4*>(Bs + (kr * BS + ((cv * Cf::VN) ^ sw)) * Cf::ES) = r.b[t];
     }
   }
 }
 
 // One k-panel into the accumulators.
-template <int P, int BS>
-__device__ __forceinline__ void compute_panel(AccTiles<P, BS>& acc, const char* As, const char* Bs, int row0, int col0, int li, int g) {
-  using Cf = GemmCfg<P, BS>;
+template <int P, int BS, int V>
+__device__ __forceinline__ void compute_panel(AccTiles<P, BS, V>& acc, const char* As, const char* Bs, int row0, int col0, int li, int g) {
+  using Cf = GemmCfg<P, BS, V>;
   if constexpr (Cf::kBf) {
 #pragma unroll
     for (int s = 0; s < Cf::KG / 8; ++s) {
@@ -302,7 +304,7 @@ __device__ __forceinline__ void compute_panel(AccTiles<P, BS>& acc, const char* 
     using T = typename std::conditional<P == SPAMM_F64, double, float>::type;
     const T* At = reinterpret_cast<const T*>(As);
     const T* Bt = reinterpret_cast<const T*>(Bs);
-    const int swz = b_swizzle<P, BS>(g);
+    const int swz = b_swizzle<P, BS, V>(g);
 #pragma unroll 2
     for (int ch = 0; ch < Cf::KG / 4; ++ch) {
       const int kk = g * Cf::KG + 4 * ch;
@@ -351,12 +353,12 @@ __device__ __forceinline__ void compute_panel(AccTiles<P, BS>& acc, const char* 
 
 // ---------------------------------------------------------------- epilogue
 
-template <int P, int BS>
-__device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const UnitS& U, AccTiles<P, BS>& acc,
+template <int P, int BS, int V>
+__device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const UnitS& U, AccTiles<P, BS, V>& acc,
                                          char* smem,
                                          double* red, int tid, int lane, int wave, int row0, int col0, int li,
                                          int g) {
-  using Cf = GemmCfg<P, BS>;
+  using Cf = GemmCfg<P, BS, V>;
   using Out = typename Cf::Out;
   const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(U.cidx) * Cf::LEAF_OUT));
   const uint32_t cm = uint32_t(U.cf & (kUnitEp - 1));
@@ -383,7 +385,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
     for (int b = 0; b < Cf::TN; ++b)
 #pragma unroll
       for (int v = 0; v < Cf::AE; ++v) {
-        const int row = row0 + a * Cf::MT + acc_row<P, BS>(g, v);
+        const int row = row0 + a * Cf::MT + acc_row<P, BS, V>(g, v);
         const int col = col0 + b * Cf::MT + li;
         Out val = Out(acc[a][b][v]);
         if (has_ep) {
@@ -428,9 +430,9 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
 
 // ---------------------------------------------------------------- kernel
 
-template <int P, int BS>
-__global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) k_gemm(const GemmArgs ga) {
-  using Cf = GemmCfg<P, BS>;
+template <int P, int BS, int V>
+__global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::MINB)) k_gemm(const GemmArgs ga) {
+  using Cf = GemmCfg<P, BS, V>;
   __shared__ __attribute__((aligned(16))) char smem[Cf::LDS];
   __shared__ double red[2 * Cf::NW];
   char* const As = smem;
@@ -479,61 +481,61 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
   next_pos();
   Win W2 = load_win(base, PU, pw, pu < u1);
 
-  Panel<P, BS> pr;
+  Panel<P, BS, V> pr;
   if (U.cnt > 0)
-    load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+    load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
 
   for (;;) {
     const bool has_next = cu + 1 < u1;
     int32_t next_cnt = 0;
     if (has_next) next_cnt = unit_of(ring, blk0, cu + 1 - rb).cnt;
 
-    Acc<P, BS> acc[Cf::TM][Cf::TN];
-    Acc<P, BS> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
+    Acc<P, BS, V> acc[Cf::TM][Cf::TN];
+    Acc<P, BS, V> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
 #pragma unroll
     for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
-      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, BS>{};
+      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, BS, V>{};
     if constexpr (Cf::TWO_LEVEL) {
 #pragma unroll
       for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
-        for (int b = 0; b < Cf::TN; ++b) part[a][b] = Acc<P, BS>{};
+        for (int b = 0; b < Cf::TN; ++b) part[a][b] = Acc<P, BS, V>{};
     }
 
     for (int p = 0; p < U.cnt; ++p) {
       for (int sub = 0; sub < Cf::NPANEL; ++sub) {
         __syncthreads();
-        store_panel<P, BS>(pr, As, Bs, tid);
+        store_panel<P, BS, V>(pr, As, Bs, tid);
         __syncthreads();
         // next panel: same product, next product (this or the next window),
         // or the first product of the next unit (the next window)
         if (sub + 1 < Cf::NPANEL) {
-          load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63), __builtin_amdgcn_readlane(W0.b, p & 63),
+          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63), __builtin_amdgcn_readlane(W0.b, p & 63),
                             sub + 1, tid);
         } else if (p + 1 < U.cnt) {
           const int l = (p + 1) & 63;
           const bool nw = l == 0;
           const int32_t ia = nw ? __builtin_amdgcn_readlane(W1.a, 0) : __builtin_amdgcn_readlane(W0.a, l);
           const int32_t ib = nw ? __builtin_amdgcn_readlane(W1.b, 0) : __builtin_amdgcn_readlane(W0.b, l);
-          load_panel<P, BS>(pr, base, ia, ib, 0, tid);
+          load_panel<P, BS, V>(pr, base, ia, ib, 0, tid);
         } else if (next_cnt > 0) {
-          load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W1.a, 0), __builtin_amdgcn_readlane(W1.b, 0), 0,
+          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0), __builtin_amdgcn_readlane(W1.b, 0), 0,
                             tid);
         }
         if constexpr (Cf::TWO_LEVEL) {
-          compute_panel<P, BS>(part, As, Bs, row0, col0, li, g);
+          compute_panel<P, BS, V>(part, As, Bs, row0, col0, li, g);
           if (sub + 1 == Cf::NPANEL) {  // the product's sum joins the leaf's total
 #pragma unroll
             for (int a = 0; a < Cf::TM; ++a)
 #pragma unroll
               for (int b = 0; b < Cf::TN; ++b) {
                 acc[a][b] += part[a][b];
-                part[a][b] = Acc<P, BS>{};
+                part[a][b] = Acc<P, BS, V>{};
               }
           }
         } else {
-          compute_panel<P, BS>(acc, As, Bs, row0, col0, li, g);
+          compute_panel<P, BS, V>(acc, As, Bs, row0, col0, li, g);
         }
       }
       if (((p + 1) & 63) == 0 && p + 1 < U.cnt) {  // into the unit's next window
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
       }
     }
 
-    epilogue<P, BS>(ga, cu, U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
+    epilogue<P, BS, V>(ga, cu, U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
     if (!has_next) break;
 
     const int32_t prev_cnt = U.cnt;
@@ -564,26 +566,26 @@ __global__ void __launch_bounds__((GemmCfg<P, BS>::NT), (GemmCfg<P, BS>::MINB)) 
     // the first panel of a unit that follows a unit without products was
     // not prefetched
     if (prev_cnt == 0 && U.cnt > 0)
-      load_panel<P, BS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+      load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
   }
 }
 
 // ---------------------------------------------------------------- launch
 
-template <int P, int BS>
+template <int P, int BS, int V>
 static int max_groups(int n_cu) {
   static const int per_cu = [] {  // thread-safe one-time query
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS>, GemmCfg<P, BS>::NT, 0) != hipSuccess || v < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS, V>, GemmCfg<P, BS, V>::NT, 0) != hipSuccess || v < 1)
       v = 1;
     return v;
   }();
   return per_cu * n_cu;
 }
 
-template <int P, int BS>
+template <int P, int BS, int V>
 static hipError_t launch_one(hipStream_t s, const GemmArgs& a) {
-  hipLaunchKernelGGL((k_gemm<P, BS>), dim3(uint32_t(kXcds * a.kx)), dim3(GemmCfg<P, BS>::NT), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<P, BS, V>), dim3(uint32_t(kXcds * a.kx)), dim3(GemmCfg<P, BS, V>::NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -593,33 +595,52 @@ bool gemm_supported(int prec, int bs) {
   return false;
 }
 
-#define SPAMM_GEMM_DISPATCH(FN, ...)                                  \
-  switch (prec * 1000 + bs) {                                         \
-    case SPAMM_F64 * 1000 + 16: return FN<SPAMM_F64, 16>(__VA_ARGS__);    \
-    case SPAMM_F64 * 1000 + 32: return FN<SPAMM_F64, 32>(__VA_ARGS__);    \
-    case SPAMM_F64 * 1000 + 64: return FN<SPAMM_F64, 64>(__VA_ARGS__);    \
-    case SPAMM_F64 * 1000 + 128: return FN<SPAMM_F64, 128>(__VA_ARGS__);  \
-    case SPAMM_F32 * 1000 + 16: return FN<SPAMM_F32, 16>(__VA_ARGS__);    \
-    case SPAMM_F32 * 1000 + 32: return FN<SPAMM_F32, 32>(__VA_ARGS__);    \
-    case SPAMM_F32 * 1000 + 64: return FN<SPAMM_F32, 64>(__VA_ARGS__);    \
-    case SPAMM_F32 * 1000 + 128: return FN<SPAMM_F32, 128>(__VA_ARGS__);  \
-    case SPAMM_BF16 * 1000 + 32: return FN<SPAMM_BF16, 32>(__VA_ARGS__);  \
-    case SPAMM_BF16 * 1000 + 64: return FN<SPAMM_BF16, 64>(__VA_ARGS__);  \
-    case SPAMM_BF16 * 1000 + 128: return FN<SPAMM_BF16, 128>(__VA_ARGS__); \
-    case SPAMM_BF16X3 * 1000 + 32: return FN<SPAMM_BF16X3, 32>(__VA_ARGS__); \
-    case SPAMM_BF16X3 * 1000 + 64: return FN<SPAMM_BF16X3, 64>(__VA_ARGS__); \
-    case SPAMM_BF16X3 * 1000 + 128: return FN<SPAMM_BF16X3, 128>(__VA_ARGS__); \
-    default: break;                                                   \
+// Runtime (precision, leaf, variant) -> kernel instance.
+template <int P, int V, typename F>
+static auto with_leaf(int bs, F&& f) {
+  switch (bs) {
+    case 16: if constexpr (P == SPAMM_F64 || P == SPAMM_F32) return f(std::integral_constant<int, 16>{}); else break;
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    default: break;
   }
-
-int gemm_max_groups(int prec, int bs, int n_cu) {
-  SPAMM_GEMM_DISPATCH(max_groups, n_cu)
-  return n_cu;
+  return f(std::integral_constant<int, 0>{});
 }
 
-hipError_t launch_gemm(hipStream_t s, int prec, int bs, const GemmArgs& a) {
-  SPAMM_GEMM_DISPATCH(launch_one, s, a)
-  return hipErrorInvalidValue;
+template <typename F>
+static auto dispatch(int prec, int bs, int variant, F&& f) {
+  auto go = [&](auto pc, auto vc) {
+    return with_leaf<decltype(pc)::value, decltype(vc)::value>(bs, [&](auto bc) { return f(pc, bc, vc); });
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  switch (prec) {
+    case SPAMM_F64: return go(std::integral_constant<int, SPAMM_F64>{}, I0{});
+    case SPAMM_F32:
+      return variant ? go(std::integral_constant<int, SPAMM_F32>{}, I1{}) : go(std::integral_constant<int, SPAMM_F32>{}, I0{});
+    case SPAMM_BF16:
+      return variant ? go(std::integral_constant<int, SPAMM_BF16>{}, I1{}) : go(std::integral_constant<int, SPAMM_BF16>{}, I0{});
+    default:
+      return variant ? go(std::integral_constant<int, SPAMM_BF16X3>{}, I1{})
+                     : go(std::integral_constant<int, SPAMM_BF16X3>{}, I0{});
+  }
+}
+
+int gemm_max_groups(int prec, int bs, int variant, int n_cu) {
+  if (!gemm_supported(prec, bs)) return n_cu;
+  return dispatch(prec, bs, variant, [&](auto pc, auto bc, auto vc) -> int {
+    if constexpr (decltype(bc)::value == 0) return n_cu;
+    else return max_groups<decltype(pc)::value, decltype(bc)::value, decltype(vc)::value>(n_cu);
+  });
+}
+
+hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmArgs& a) {
+  if (!gemm_supported(prec, bs)) return hipErrorInvalidValue;
+  return dispatch(prec, bs, variant, [&](auto pc, auto bc, auto vc) -> hipError_t {
+    if constexpr (decltype(bc)::value == 0) return hipErrorInvalidValue;
+    else return launch_one<decltype(pc)::value, decltype(bc)::value, decltype(vc)::value>(s, a);
+  });
 }
 
 // ---------------------------------------------------------------- schedule

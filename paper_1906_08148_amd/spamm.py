@@ -106,6 +106,8 @@ _SIGS = {
     "spamm_skipped_bound": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
     "spamm_to_dense": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "spamm_ctx_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
+    "spamm_ctx_get_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "spamm_gershgorin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
     "spamm_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -315,6 +317,18 @@ class Context:
         out = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
         self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
         return out
+
+    OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2}
+
+    def set_option(self, name: str, value: int):
+        """gemm_tile (0: 32x32 MFMA tiles, 1: 16x16), placement (0: XCD
+        slices, 1: request-major), graph (1: one captured graph per batch)."""
+        self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        self._check(_lib.spamm_ctx_get_option(self.ptr, self.OPTIONS[name], ctypes.byref(v)))
+        return v.value
 
     def gershgorin(self, m: Matrix):
         """(lo, hi) Gershgorin bounds of the spectrum, FP64."""

@@ -1,0 +1,84 @@
+"""Context options: captured-graph launches give bitwise the results of
+one-by-one launches, replay after replay with other work in between; the
+16 x 16 MFMA tile variant matches the oracle; the autotuner returns a
+working choice."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_1906_08148_amd import autotune, spamm
+
+from parity import check_product
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def batch(M1, M2):
+    return [dict(A=M1, B=M1, tau=1e-6, mode=spamm.HYBRID, prec=spamm.F32),
+            dict(A=M2, B=M2, tau=1e-5, mode=spamm.SPAMM, prec=spamm.F64),
+            dict(A=M1, B=M1, tau=1e-4, mode=spamm.TRUNCMUL, prec=spamm.BF16X3)]
+
+
+def test_graph_launch_equals_eager_over_replays():
+    import torch
+    print("case: graph replays", flush=True)
+    ctx = spamm.Context(arena_bytes=2 << 30)
+    M1 = ctx.build(dev(synth.DecaySpec("1d", 4096, 0.3, seed=2).dense()), 64)
+    M2 = ctx.build(dev(synth.DecaySpec("3d", 2048, 1.0, seed=3).dense()), 32)
+    eager = [ctx.to_dense(p.C) for p in ctx.multiply_batch(batch(M1, M2))]
+    other = [dict(A=M2, B=M2, tau=1e-7, mode=spamm.SPAMM, prec=spamm.F32)]
+    ctx.set_option("graph", 1)
+    assert ctx.get_option("graph") == 1
+    for rep in range(4):
+        ps = ctx.multiply_batch(batch(M1, M2))
+        for p, e in zip(ps, eager):
+            assert torch.equal(ctx.to_dense(p.C), e), rep
+            p.C.release()
+        # a batch of another shape (graph instantiated anew), then eager work
+        q = ctx.multiply_batch(other)[0]
+        ctx.set_option("graph", 0)
+        r = ctx.multiply_batch(other)[0]
+        assert torch.equal(ctx.to_dense(q.C), ctx.to_dense(r.C))
+        q.C.release()
+        r.C.release()
+        ctx.set_option("graph", 1)
+        torch.cuda.synchronize()
+    M1.release()
+    M2.release()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [spamm.F32, spamm.BF16, spamm.BF16X3])
+def test_tile_variant_parity(prec):
+    print(f"case: tile variant prec={prec}", flush=True)
+    ctx = spamm.Context(arena_bytes=1 << 30)
+    ctx.set_option("gemm_tile", 1)
+    A = synth.DecaySpec("1d", 2100, 0.3, seed=5).dense()
+    for bs in (32, 64, 128):
+        T = O.build(A, bs)
+        M = ctx.build(dev(A), bs)
+        for mode in (spamm.SPAMM, spamm.HYBRID):
+            check_product(ctx, M, M, T, T, 1e-6, mode, prec, alias=True)
+        M.release()
+    ctx.close()
+
+
+def test_autotuner_picks_a_candidate():
+    print("case: autotune", flush=True)
+    ctx = spamm.Context(arena_bytes=2 << 30)
+    sp = synth.DecaySpec("3d", 4096, 1.0, seed=4)
+    A = dev(sp.dense())
+    tuner = autotune.Tuner(ctx, leaves=(32, 64), tiles=(0, 1), reps=2)
+    sig = autotune.signature("3d", 4096, 1.0, 1e-6, spamm.HYBRID, spamm.F32)
+    best = tuner.tune(lambda leaf: ctx.build(A, leaf), sig, 1e-6, spamm.HYBRID, spamm.F32)
+    assert (best["leaf"], best["tile"]) in {(32, 0), (32, 1), (64, 0), (64, 1)}
+    assert len(best["table"]) == 4 and all(r["seconds"] > 0 for r in best["table"])
+    assert ctx.get_option("gemm_tile") == best["tile"]
+    assert tuner.tune(None, sig, 1e-6, spamm.HYBRID, spamm.F32) is best  # cached
+    ctx.close()
