@@ -172,12 +172,20 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       launch that (an instantiated graph of the same shape
  *                       is updated in place).  Ignored while event timing
  *                       is on.
+ *  SPAMM_OPT_UNIT_ORDER c in 1..1024: the C leaves an XCD works on are dealt
+ *                       round-robin over its workgroups in chunks of c
+ *                       consecutive leaves, so the workgroups move through
+ *                       the slice together (less L2 traffic); 0: each
+ *                       workgroup takes a contiguous range of equal cost;
+ *                       -1 (default): per launch, 1 when the C leaves average
+ *                       fewer than 16 products, else 0.
  * All options give bitwise identical results.  Errors: EINVAL (unknown key
  * or value). */
 typedef enum {
   SPAMM_OPT_GEMM_TILE = 0,
   SPAMM_OPT_PLACEMENT = 1,
-  SPAMM_OPT_GRAPH = 2
+  SPAMM_OPT_GRAPH = 2,
+  SPAMM_OPT_UNIT_ORDER = 3
 } spamm_option;
 
 spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value);

@@ -449,6 +449,11 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
 spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value) {
   if (!ctx) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;
+  if (key == SPAMM_OPT_UNIT_ORDER) {
+    if (value < -1 || value > 1024) return fail(c, SPAMM_EINVAL, "unit order: -1 (automatic) or chunk size 0..1024");
+    c->gemm_interleave = int(value);
+    return SPAMM_OK;
+  }
   if (value != 0 && value != 1) return fail(c, SPAMM_EINVAL, "option value must be 0 or 1");
   switch (key) {
     case SPAMM_OPT_GEMM_TILE: c->gemm_tile = int(value); return SPAMM_OK;
@@ -465,6 +470,7 @@ spamm_status spamm_ctx_get_option(const spamm_ctx* ctx, spamm_option key, int64_
     case SPAMM_OPT_GEMM_TILE: *value = c->gemm_tile; return SPAMM_OK;
     case SPAMM_OPT_PLACEMENT: *value = c->gemm_sched; return SPAMM_OK;
     case SPAMM_OPT_GRAPH: *value = c->use_graph; return SPAMM_OK;
+    case SPAMM_OPT_UNIT_ORDER: *value = c->gemm_interleave; return SPAMM_OK;
     default: return SPAMM_EINVAL;
   }
 }
@@ -985,7 +991,15 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       ga.wn = P<double>(wn) + u0;
       ga.wt = P<double>(wt) + u0;
       ga.kx = kx;
-      ga.pad_ = 0;
+      ga.interleave = c->gemm_interleave;
+      if (ga.interleave < 0) {
+        // short units (few products each): round-robin single units keep an
+        // XCD's workgroups close together in its slice; long units: contiguous
+        // ranges keep consecutive C leaves (shared A rows) in one workgroup
+        int64_t kept = 0;
+        for (int r : gk.second) kept += ht[r].n_kept;
+        ga.interleave = kept < 16 * nwu ? 1 : 0;
+      }
       TimedScope ts(c, kTGemm);
       if (c->timing) {
         for (int r : gk.second)

@@ -133,6 +133,8 @@ struct Ctx {
   int n_cu = 256;
   int gemm_sched = 0;  // work-unit placement: 0 per-XCD Morton slices, 1 request-major
   int gemm_tile = 0;   // GEMM variant (MFMA tile shape), see launch_gemm
+  int gemm_interleave = -1;  // GemmArgs::interleave (chunk of consecutive units, 0: contiguous ranges,
+                             // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
   hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
@@ -292,7 +294,8 @@ struct GemmArgs {
   double* wn;            // per unit: FP64 squared Frobenius norm of the C leaf
   double* wt;            // per unit: diagonal sum of the C leaf (diagonal leaves)
   int32_t kx;            // workgroups per XCD (the grid is 8 * kx)
-  int32_t pad_;
+  int32_t interleave;    // c > 0: an XCD's units [start[x*kx], start[(x+1)*kx]) dealt round-robin over its
+                         // workgroups in chunks of c; 0: workgroup rank r takes [start[r], start[r+1])
 };
 
 // Per-request totals read back after the counting pass.

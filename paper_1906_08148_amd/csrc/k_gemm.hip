@@ -67,7 +67,7 @@ struct GemmCfg {
   static constexpr int AE = MT * MT / 64;  // accumulator registers per tile
   static constexpr int TM = TILE_M / MT, TN = TILE_N / MT;
   static constexpr int KP = P == SPAMM_F64    ? (BS >= 64 ? 32 : BS)
-                            : P == SPAMM_F32  ? (BS >= 128 ? 32 : BS)
+                            : P == SPAMM_F32  ? (BS >= 64 ? 32 : BS)
                             : P == SPAMM_BF16 ? (BS >= 128 ? 64 : BS)
                                               : (BS >= 128 ? 32 : BS);
   static constexpr int NPANEL = BS / KP;
@@ -85,15 +85,19 @@ struct GemmCfg {
   static constexpr int64_t LEAF_OUT = int64_t(BS) * BS * sizeof(Out);
   static constexpr int VNO = 16 / int(sizeof(Out));
   static constexpr int SC = BS + VNO;  // padded row of the staged C leaf
-  static constexpr bool STAGED = int64_t(BS) * SC * sizeof(Out) <= A_LDS + B_LDS;
-  static constexpr int LDS = A_LDS + B_LDS;
+  // double-buffered panels: a panel is stored into the buffer the panel
+  // before last was read from, so one barrier per panel suffices
+  static constexpr bool DBUF = (P == SPAMM_F32 && BS == 64);
+  static constexpr int PANEL_LDS = A_LDS + B_LDS;
+  static constexpr int LDS = (DBUF ? 2 : 1) * PANEL_LDS;
+  static constexpr bool STAGED = int64_t(BS) * SC * sizeof(Out) <= LDS;
   // FP32 accumulation in two levels: each leaf product is summed in its own
   // registers and then added to the leaf's total, so the rounding error of
   // a C entry grows with sqrt(bs) + sqrt(products) rather than with the
   // square root of all bs * products terms
   static constexpr bool TWO_LEVEL = P != SPAMM_F64;
   // resident workgroups per CU asked of the register allocator
-  static constexpr int MINB = (BS == 64 && P != SPAMM_F64) ? 3 : 1;
+  static constexpr int MINB = (BS == 64 && P == SPAMM_F32) ? 4 : (BS == 64 && P != SPAMM_F64) ? 3 : 1;
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
 };
 
@@ -150,11 +154,18 @@ struct UnitS {
 // `blk` holds units [u, u + 64) of the range.  Records are copied 8 bytes per
 // thread (a record is three 8-byte words).
 typedef int32_t i32x2r __attribute__((ext_vector_type(2)));
+// The units a workgroup visits: visit t is unit ubase + (t / chunk) * cstride
+// + t % chunk (chunks of `chunk` consecutive units, `cstride` apart).
+struct Visits {
+  int64_t ubase, cstride, chunk, n;
+  __device__ __forceinline__ int64_t unit(int64_t t) const { return ubase + (t / chunk) * cstride + t % chunk; }
+};
+
 __device__ __forceinline__ void stage_recs(i32x2r (*ring)[64 * 3], int blk, const WorkUnit* __restrict__ wu,
-                                           int64_t u, int64_t u1, int tid, int nt) {
+                                           int64_t t0, const Visits& vs, int tid, int nt) {
   for (int w = tid; w < 64 * 3; w += nt) {
-    const int64_t x = u + w / 3;
-    if (x < u1) ring[blk][w] = *as_global(reinterpret_cast<const i32x2r*>(wu + x) + (w % 3));
+    const int64_t t = t0 + w / 3;
+    if (t < vs.n) ring[blk][w] = *as_global(reinterpret_cast<const i32x2r*>(wu + vs.unit(t)) + (w % 3));
   }
 }
 
@@ -426,6 +437,9 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
     as_global(ga.wn)[u] = s;
     if (ci == cj) as_global(ga.wt)[u] = t;
   }
+  // with double-buffered panels the next store is not preceded by a barrier:
+  // every wave must be done reading the staged leaf first
+  if constexpr (Cf::DBUF && Cf::STAGED) __syncthreads();
 }
 
 // ---------------------------------------------------------------- kernel
@@ -435,8 +449,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
   using Cf = GemmCfg<P, BS, V>;
   __shared__ __attribute__((aligned(16))) char smem[Cf::LDS];
   __shared__ double red[2 * Cf::NW];
-  char* const As = smem;
-  char* const Bs = smem + Cf::A_LDS;
+  int qg = 0;  // panels stored so far (picks the buffer when double-buffered)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -446,16 +459,34 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
   const int li = lane % Cf::MT, g = lane / Cf::MT;
   const char* const base = ga.base;
 
-  const int rank = int(blockIdx.x % kXcds) * ga.kx + int(blockIdx.x / kXcds);
-  const int64_t u0 = ga.start[rank], u1 = ga.start[rank + 1];
-  if (u0 >= u1) return;
+  // the units this workgroup visits (visit t = 0 .. u1 - 1)
+  const int xcd = int(blockIdx.x % kXcds), j = int(blockIdx.x / kXcds);
+  Visits vs;
+  if (ga.interleave > 0) {  // the XCD's share, dealt round-robin in chunks over its workgroups
+    const int64_t lo = ga.start[xcd * ga.kx], hi = ga.start[(xcd + 1) * ga.kx];
+    const int64_t c = ga.interleave, N = hi - lo, nch = (N + c - 1) / c;
+    const int64_t mine = j < nch ? (nch - j + ga.kx - 1) / ga.kx : 0;  // chunks j, j + kx, ...
+    vs.ubase = lo + int64_t(j) * c;
+    vs.cstride = int64_t(ga.kx) * c;
+    vs.chunk = c;
+    vs.n = mine * c;
+    if (mine > 0 && j + (mine - 1) * ga.kx == nch - 1 && N % c) vs.n -= c - N % c;  // the last chunk is partial
+  } else {  // a contiguous range of equal cost
+    const int rank = xcd * ga.kx + j;
+    vs.ubase = ga.start[rank];
+    vs.cstride = 0;
+    vs.chunk = int64_t(1) << 62;
+    vs.n = ga.start[rank + 1] - vs.ubase;
+  }
+  const int64_t u0 = 0, u1 = vs.n;
+  if (u1 <= 0) return;
 
-  // unit records [rb, rb + 128) in the LDS ring (block blk0 first)
+  // unit records of visits [rb, rb + 128) in the LDS ring (block blk0 first)
   __shared__ i32x2r ring[2][64 * 3];
   int64_t rb = u0;
   int blk0 = 0;
-  stage_recs(ring, 0, ga.wu, rb, u1, tid, Cf::NT);
-  stage_recs(ring, 1, ga.wu, rb + 64, u1, tid, Cf::NT);
+  stage_recs(ring, 0, ga.wu, rb, vs, tid, Cf::NT);
+  stage_recs(ring, 1, ga.wu, rb + 64, vs, tid, Cf::NT);
   __syncthreads();
 
   // pair windows: W0 holds the window of the product being multiplied, W1
@@ -505,7 +536,10 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
 
     for (int p = 0; p < U.cnt; ++p) {
       for (int sub = 0; sub < Cf::NPANEL; ++sub) {
-        __syncthreads();
+        char* const As = smem + (Cf::DBUF ? (qg & 1) * Cf::PANEL_LDS : 0);
+        char* const Bs = As + Cf::A_LDS;
+        ++qg;
+        if constexpr (!Cf::DBUF) __syncthreads();  // every wave is done with the previous panel
         store_panel<P, BS, V>(pr, As, Bs, tid);
         __syncthreads();
         // next panel: same product, next product (this or the next window),
@@ -546,7 +580,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
       }
     }
 
-    epilogue<P, BS, V>(ga, cu, U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
+    epilogue<P, BS, V>(ga, vs.unit(cu), U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
     if (!has_next) break;
 
     const int32_t prev_cnt = U.cnt;
@@ -556,7 +590,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
       // first read some 60 units (and as many barriers) later
       rb += 64;
       blk0 ^= 1;
-      stage_recs(ring, blk0 ^ 1, ga.wu, rb + 64, u1, tid, Cf::NT);
+      stage_recs(ring, blk0 ^ 1, ga.wu, rb + 64, vs, tid, Cf::NT);
     }
     U = unit_of(ring, blk0, cu - rb);
     W0 = W1;

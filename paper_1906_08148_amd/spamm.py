@@ -318,7 +318,7 @@ class Context:
         self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
         return out
 
-    OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2}
+    OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2, "unit_order": 3}  # unit_order: chunk size (0: contiguous ranges)
 
     def set_option(self, name: str, value: int):
         """gemm_tile (0: 32x32 MFMA tiles, 1: 16x16), placement (0: XCD

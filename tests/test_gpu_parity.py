@@ -215,20 +215,24 @@ def test_config2_full(ctx):
 
 
 def test_gemm_schedules_agree_bitwise():
-    """Morton slices per XCD and request-major placement give bitwise the
-    same C: each C leaf is summed by one workgroup in the plan's order
-    either way."""
+    """Morton slices per XCD, request-major placement, and round-robin or
+    contiguous unit ranges give bitwise the same C: each C leaf is summed by
+    one workgroup in the plan's order either way."""
     import os
     import torch
     print("case: schedules", flush=True)
     A = synth.DecaySpec("1d", 8192, 0.2, seed=2).dense()
     res = {}
-    for mode in ("xcd", "rm"):
-        os.environ["SPAMM_GEMM_SCHED"] = mode
+    for mode in ("xcd", "rm", "ranges", "chunk1", "chunk7"):
+        os.environ["SPAMM_GEMM_SCHED"] = "rm" if mode == "rm" else "xcd"
         try:
             c = spamm.Context(arena_bytes=2 << 30)
         finally:
             del os.environ["SPAMM_GEMM_SCHED"]
+        if mode == "ranges":
+            c.set_option("unit_order", 0)
+        elif mode.startswith("chunk"):
+            c.set_option("unit_order", int(mode[5:]))
         M = c.build(dev(A), 64)
         ps = c.multiply_batch([dict(A=M, B=M, tau=t, mode=m, prec=spamm.F32)
                                for t in (1e-4, 1e-8) for m in MODES])
@@ -237,8 +241,9 @@ def test_gemm_schedules_agree_bitwise():
             p.C.release()
         M.release()
         c.close()
-    for a, b in zip(res["xcd"], res["rm"]):
-        assert torch.equal(a, b)
+    for other in ("rm", "ranges", "chunk1", "chunk7"):
+        for a, b in zip(res["xcd"], res[other]):
+            assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("n,bs,kind,tau", [
