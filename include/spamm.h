@@ -179,8 +179,9 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       workgroup takes a contiguous range of equal cost;
  *                       -1 (default): per launch, 1 when the C leaves average
  *                       fewer than 16 products, else 0.
- * All options give bitwise identical results.  Errors: EINVAL (unknown key
- * or value). */
+ * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
+ * changes the order of the sums inside one MFMA (results stay within the
+ * precision's tolerance).  Errors: EINVAL (unknown key or value). */
 typedef enum {
   SPAMM_OPT_GEMM_TILE = 0,
   SPAMM_OPT_PLACEMENT = 1,
