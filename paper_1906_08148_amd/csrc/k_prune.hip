@@ -19,120 +19,169 @@ namespace spamm {
 constexpr int64_t kCntBits = 40;
 constexpr int64_t kCntMask = (int64_t(1) << kCntBits) - 1;
 
-__device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, int nreq, int64_t g) {
+// Requests' first global C index, cached in LDS by every workgroup (larger
+// batches search the descriptor table in memory).
+constexpr int kReqLds = 512;
+
+__device__ __forceinline__ void cache_cbase(const ReqDev* __restrict__ reqs, int nreq, int64_t* sc) {
+  for (int t = threadIdx.x; t < min(nreq, kReqLds); t += blockDim.x) sc[t] = reqs[t].cbase;
+  __syncthreads();
+}
+
+__device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, const int64_t* sc, int nreq, int64_t g) {
   int lo = 0, hi = nreq - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (reqs[mid].cbase <= g) lo = mid;
+    if ((nreq <= kReqLds ? sc[mid] : reqs[mid].cbase) <= g) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-struct Walk {
-  int64_t rowA, colB;  // offsets of row i in A's rm arrays, column j in B's cm arrays
-  int lo, hi;
-};
-
-__device__ __forceinline__ Walk make_walk(const ReqDev& R, uint32_t i, uint32_t j) {
-  Walk w;
-  const int G = R.G;
-  w.rowA = int64_t(i) * G;
-  w.colB = int64_t(j) * G;
-  w.lo = max(R.A.ranges[i], R.B.ranges[2 * G + j]);
-  w.hi = min(R.A.ranges[G + i], R.B.ranges[3 * G + j]);
-  return w;
-}
-
-// Each wave takes 64 consecutive C leaves (one per lane).  Every lane first
-// finds its request and intersects the k ranges of its A row and B column;
-// the wave then walks, 64 k at a time, only the leaves whose range is not
-// empty, so structurally empty leaves cost one coalesced pass.
+// Each wave takes 64 consecutive C leaves (one per lane).  Every lane finds
+// its request, intersects the k ranges of its A row and B column and keeps
+// the base addresses of that row and column in the row-major / column-major
+// prune views; the wave then walks the leaves whose range is not empty, four
+// at a time, 64 k per step, so the loads of four leaves are in flight
+// together.
 struct LaneLeaf {
   int r;
   uint32_t c, i, j;
-  Walk w;
+  int lo, hi;
+  const double* sa;  // sqrt norms of A's row i (index k)
+  const double* sb;  // sqrt norms of B's column j
+  const int32_t* la;  // slots of A's row i
+  const int32_t* lb;  // slots of B's column j
   bool valid;
 };
 
-__device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
-                                              int64_t g) {
-  // one scalar search per wave when its 64 leaves lie in one request
-  const int64_t g0 = g - lane_id();
-  const uint32_t g0lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(g0)));
-  const uint32_t g0hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(g0) >> 32));
-  const int64_t gw = int64_t((uint64_t(g0hi) << 32) | g0lo);
-  const int rw = find_req(reqs, nreq, gw);
-  const bool whole = reqs[rw].cbase + int64_t(reqs[rw].G) * reqs[rw].G >= gw + kWave;
+__device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, const int64_t* sc, int nreq,
+                                              int64_t total_c, int64_t g) {
   LaneLeaf x;
   x.valid = g < total_c;
   x.r = 0;
   x.c = x.i = x.j = 0;
-  x.w.lo = 1;
-  x.w.hi = 0;
-  x.w.rowA = x.w.colB = 0;
+  x.lo = 1;
+  x.hi = 0;
+  x.sa = x.sb = nullptr;
+  x.la = x.lb = nullptr;
   if (x.valid) {
-    x.r = whole ? rw : find_req(reqs, nreq, g);
+    x.r = find_req(reqs, sc, nreq, g);
     const ReqDev& R = reqs[x.r];
+    const int G = R.G;
     x.c = uint32_t(g - R.cbase);
     demorton(x.c, x.i, x.j);
-    x.w = make_walk(R, x.i, x.j);
+    x.lo = max(R.A.ranges[x.i], R.B.ranges[2 * G + x.j]);
+    x.hi = min(R.A.ranges[G + x.i], R.B.ranges[3 * G + x.j]);
+    x.sa = R.A.rm_sqrt + int64_t(x.i) * G;
+    x.sb = R.B.cm_sqrt + int64_t(x.j) * G;
+    x.la = R.A.rm_slot + int64_t(x.i) * G;
+    x.lb = R.B.cm_slot + int64_t(x.j) * G;
   }
   return x;
 }
 
-// Walk one C leaf with the whole wave: counts of kept and candidate k and
-// the sum of skipped norm products (lane partials, then a fixed tree).
-__device__ __forceinline__ void walk_count(const ReqDev& R, const Walk& w, int64_t& cnt, int64_t& cand,
-                                           double& skipped) {
-  const double tau = R.tau;
-  const bool use_norms = R.use_norms != 0;
-  cnt = 0;
-  cand = 0;
-  double part = 0.0;
-  for (int kb = w.lo; kb <= w.hi; kb += kWave) {
-    const int k = kb + lane_id();
-    double a = -1.0, b = -1.0;
-    if (k <= w.hi) {
-      a = R.A.rm_sqrt[w.rowA + k];
-      b = R.B.cm_sqrt[w.colB + k];
+__device__ __forceinline__ const double* lane_ptr(const double* p, int b) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(v), b), hi = __builtin_amdgcn_readlane(uint32_t(v >> 32), b);
+  return reinterpret_cast<const double*>((uint64_t(hi) << 32) | lo);
+}
+__device__ __forceinline__ const int32_t* lane_ptr(const int32_t* p, int b) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(v), b), hi = __builtin_amdgcn_readlane(uint32_t(v >> 32), b);
+  return reinterpret_cast<const int32_t*>((uint64_t(hi) << 32) | lo);
+}
+
+// One walk group: up to four leaves (lanes b[q]), their parameters read from
+// those lanes.
+struct Group {
+  int n;
+  int b[4];
+  int lo[4], hi[4];
+  const double* sa[4];
+  const double* sb[4];
+  double tau[4];
+  bool norms[4];
+};
+
+__device__ __forceinline__ Group take_group(uint64_t& todo, const LaneLeaf& x, const ReqDev* __restrict__ reqs) {
+  Group gr;
+  gr.n = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    gr.b[q] = 0;
+    gr.lo[q] = 1;
+    gr.hi[q] = 0;
+    gr.sa[q] = gr.sb[q] = nullptr;
+    gr.tau[q] = 0.0;
+    gr.norms[q] = false;
+    if (todo) {
+      const int b = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      gr.b[q] = b;
+      gr.lo[q] = __builtin_amdgcn_readlane(x.lo, b);
+      gr.hi[q] = __builtin_amdgcn_readlane(x.hi, b);
+      gr.sa[q] = lane_ptr(x.sa, b);
+      gr.sb[q] = lane_ptr(x.sb, b);
+      const int r = __builtin_amdgcn_readlane(x.r, b);
+      gr.tau[q] = reqs[r].tau;
+      gr.norms[q] = reqs[r].use_norms != 0;
+      gr.n = q + 1;
     }
-    const bool both = (a >= 0.0) && (b >= 0.0);
-    const double p = a * b;
-    const bool keep = both && (!use_norms || p >= tau);
-    cnt += popc64(ballot64(keep));
-    cand += popc64(ballot64(both));
-    if (both && !keep) part += p;
   }
-  skipped = wave_sum_f64(part);
+  return gr;
 }
 
 __global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
                                                      int64_t* __restrict__ packed, double* __restrict__ bnd_all,
                                                      int32_t* __restrict__ cand_all) {
+  __shared__ int64_t sc[kReqLds];
+  cache_cbase(reqs, nreq, sc);
   const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
   if (g0 >= total_c) return;
   const int64_t g = g0 + lane_id();
-  const LaneLeaf x = lane_leaf(reqs, nreq, total_c, g);
+  const LaneLeaf x = lane_leaf(reqs, sc, nreq, total_c, g);
   int64_t my_cnt = 0, my_cand = 0;
   double my_skip = 0.0;
-  uint64_t todo = ballot64(x.valid && x.w.lo <= x.w.hi);
+  uint64_t todo = ballot64(x.valid && x.lo <= x.hi);
   while (todo) {
-    const int b = __ffsll((unsigned long long)todo) - 1;
-    todo &= todo - 1;
-    const int r = __shfl(x.r, b, kWave);
-    Walk w;
-    w.lo = __shfl(x.w.lo, b, kWave);
-    w.hi = __shfl(x.w.hi, b, kWave);
-    w.rowA = __shfl(x.w.rowA, b, kWave);
-    w.colB = __shfl(x.w.colB, b, kWave);
-    int64_t cnt, cand;
-    double skipped;
-    walk_count(reqs[r], w, cnt, cand, skipped);
-    if (lane_id() == b) {
-      my_cnt = cnt;
-      my_cand = cand;
-      my_skip = skipped;
+    const Group gr = take_group(todo, x, reqs);
+    int64_t cnt[4] = {0, 0, 0, 0}, cand[4] = {0, 0, 0, 0};
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    int span = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) span = max(span, gr.hi[q] - gr.lo[q] + 1);
+    for (int kb = 0; kb < span; kb += kWave) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // all loads first
+        const int k = gr.lo[q] + kb + lane_id();
+        a[q] = -1.0;
+        bv[q] = -1.0;
+        if (q < gr.n && k <= gr.hi[q]) {
+          a[q] = gr.sa[q][k];
+          bv[q] = gr.sb[q][k];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool both = (a[q] >= 0.0) && (bv[q] >= 0.0);
+        const double pr = a[q] * bv[q];
+        const bool keep = both && (!gr.norms[q] || pr >= gr.tau[q]);
+        cnt[q] += popc64(ballot64(keep));
+        cand[q] += popc64(ballot64(both));
+        if (both && !keep) part[q] += pr;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q >= gr.n) break;
+      const double skipped = wave_sum_f64(part[q]);
+      if (lane_id() == gr.b[q]) {
+        my_cnt = cnt[q];
+        my_cand = cand[q];
+        my_skip = skipped;
+      }
     }
   }
   if (x.valid) {
@@ -175,10 +224,12 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
                                                     const double* __restrict__ bnd_all,
                                                     const int32_t* __restrict__ cand_all,
                                                     WorkUnit* __restrict__ wu, int64_t* __restrict__ cost) {
+  __shared__ int64_t sc[kReqLds];
+  cache_cbase(reqs, nreq, sc);
   const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
   if (g0 >= total_c) return;
   const int64_t g = g0 + lane_id();
-  const LaneLeaf x = lane_leaf(reqs, nreq, total_c, g);
+  const LaneLeaf x = lane_leaf(reqs, sc, nreq, total_c, g);
   int64_t off = 0, cnt = 0;
   if (x.valid) {
     const ReqDev& R = reqs[x.r];
@@ -220,34 +271,52 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
   }
   uint64_t todo = ballot64(x.valid && cnt > 0);
   while (todo) {
-    const int b = __ffsll((unsigned long long)todo) - 1;
-    todo &= todo - 1;
-    const int r = __shfl(x.r, b, kWave);
-    const ReqDev& R = reqs[r];
-    Walk w;
-    w.lo = __shfl(x.w.lo, b, kWave);
-    w.hi = __shfl(x.w.hi, b, kWave);
-    w.rowA = __shfl(x.w.rowA, b, kWave);
-    w.colB = __shfl(x.w.colB, b, kWave);
-    const int64_t base = __shfl(off, b, kWave);
-    const int64_t end = base + __shfl(cnt, b, kWave);
-    const double tau = R.tau;
-    const bool use_norms = R.use_norms != 0;
-    int64_t pos = base;
-    for (int kb = w.lo; kb <= w.hi; kb += kWave) {
-      const int k = kb + lane_id();
-      double a = -1.0, bb = -1.0;
-      if (k <= w.hi) {
-        a = R.A.rm_sqrt[w.rowA + k];
-        bb = R.B.cm_sqrt[w.colB + k];
+    const Group gr = take_group(todo, x, reqs);
+    int64_t pos[4], end[4];
+    const int32_t* la[4];
+    const int32_t* lb[4];
+    int64_t aoff[4], boff[4];
+    int2* out[4];
+    int span = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = gr.b[q];
+      pos[q] = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(off) >> 32), b))) << 32) |
+                       uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(off)), b)));
+      end[q] = pos[q] + __builtin_amdgcn_readlane(int32_t(cnt), b);
+      la[q] = lane_ptr(x.la, b);
+      lb[q] = lane_ptr(x.lb, b);
+      const int r = __builtin_amdgcn_readlane(x.r, b);
+      aoff[q] = reqs[r].aoff;
+      boff[q] = reqs[r].boff;
+      out[q] = reqs[r].pairs;
+      if (q < gr.n) span = max(span, gr.hi[q] - gr.lo[q] + 1);
+    }
+    for (int kb = 0; kb < span; kb += kWave) {
+      double a[4], bv[4];
+      int32_t sa[4], sb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // norms and slots of four leaves in flight together
+        const int k = gr.lo[q] + kb + lane_id();
+        a[q] = -1.0;
+        bv[q] = -1.0;
+        sa[q] = sb[q] = 0;
+        if (q < gr.n && k <= gr.hi[q]) {
+          a[q] = gr.sa[q][k];
+          bv[q] = gr.sb[q][k];
+          sa[q] = la[q][k];
+          sb[q] = lb[q][k];
+        }
       }
-      const bool both = (a >= 0.0) && (bb >= 0.0);
-      const bool keep = both && (!use_norms || a * bb >= tau);
-      const uint64_t mask = ballot64(keep);
-      const int64_t at = pos + popc64(mask & lanemask_lt());
-      if (keep && at < end)
-        R.pairs[at] = make_int2(int32_t(R.aoff + R.A.rm_slot[w.rowA + k]), int32_t(R.boff + R.B.cm_slot[w.colB + k]));
-      pos += popc64(mask);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool both = (a[q] >= 0.0) && (bv[q] >= 0.0);
+        const bool keep = both && (!gr.norms[q] || a[q] * bv[q] >= gr.tau[q]);
+        const uint64_t mask = ballot64(keep);
+        const int64_t at = pos[q] + popc64(mask & lanemask_lt());
+        if (keep && at < end[q]) out[q][at] = make_int2(int32_t(aoff[q] + sa[q]), int32_t(boff[q] + sb[q]));
+        pos[q] += popc64(mask);
+      }
     }
   }
 }
