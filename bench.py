@@ -383,6 +383,7 @@ def main():
     ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D decay n=32768 section")
     ap.add_argument("--graph", action="store_true", help="launch each batch's post-sizing kernels as one HIP graph")
+    ap.add_argument("--gemm-tile", type=int, default=None, help="MFMA tile variant (0: 32x32, 1: 16x16)")
     ap.add_argument("--steps-3d", type=int, default=3)
     ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
     ap.add_argument("--purify-steps", type=int, default=20)
@@ -405,6 +406,8 @@ def main():
     ctx = spamm.Context(arena_bytes=16 << 30)
     if args.graph:
         ctx.set_option("graph", 1)
+    if args.gemm_tile is not None:
+        ctx.set_option("gemm_tile", args.gemm_tile)
     if args.copy_calibration_mb:
         src = torch.ones(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -73,7 +73,7 @@ struct GemmCfg {
   static constexpr int NPANEL = BS / KP;
   static constexpr int NT = NW * 64;
   static constexpr int VN = 16 / ES;  // elements per 16-byte vector
-  static constexpr int SA = KP + VN;  // padded row of an A (and BF16 B) panel
+  static constexpr int SA = KP + VN;  // padded row of an A (and BF16 B) panel in LDS
   static constexpr int KG = KP / NG;  // k values of one lane group per panel
   static constexpr int PV = BS * KP / VN;  // 16-byte vectors of one operand panel half
   static constexpr int A_VECS = (NH * PV + NT - 1) / NT;  // per thread (the last may be partial)
@@ -311,6 +311,13 @@ __device__ __forceinline__ void compute_panel(AccTiles<P, BS, V>& acc, const cha
           }
         }
     }
+    // Wait states after the last BF16 MFMA before any later instruction may
+    // overwrite its operand registers: with the window registers reused
+    // right after the MFMA (a v_mov into its A-operand VGPRs a few cycles
+    // after issue), a leaf-32 build returned wrong products.
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 7\n\ts_nop 7");
+    __builtin_amdgcn_sched_barrier(0);
   } else {
     using T = typename std::conditional<P == SPAMM_F64, double, float>::type;
     const T* At = reinterpret_cast<const T*>(As);
@@ -448,7 +455,9 @@ template <int P, int BS, int V>
 __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::MINB)) k_gemm(const GemmArgs ga) {
   using Cf = GemmCfg<P, BS, V>;
   __shared__ __attribute__((aligned(16))) char smem[Cf::LDS];
-  __shared__ double red[2 * Cf::NW];
+  // per-wave partial sums of the epilogue, two sets used alternately: thread 0
+  // may still read one set while the next unit's waves fill the other
+  __shared__ double red2[2][2 * Cf::NW];
   int qg = 0;  // panels stored so far (picks the buffer when double-buffered)
 
   const int tid = threadIdx.x;
@@ -513,8 +522,12 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
   Win W2 = load_win(base, PU, pw, pu < u1);
 
   Panel<P, BS, V> pr;
+  Win Wn;  // the window after W2, fetched early
+  Wn.a = Wn.b = 0;
+  bool wn_ready = false;
   if (U.cnt > 0)
-    load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+    load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
+                          __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
 
   for (;;) {
     const bool has_next = cu + 1 < u1;
@@ -542,11 +555,19 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
         if constexpr (!Cf::DBUF) __syncthreads();  // every wave is done with the previous panel
         store_panel<P, BS, V>(pr, As, Bs, tid);
         __syncthreads();
+        // the window after W2 is fetched before the loads of the first panel
+        // of the next window (loads complete in order, so waiting for that
+        // panel does not wait on a window fetched later)
+        if (!wn_ready && sub + 1 == Cf::NPANEL && (p + 1 == U.cnt || ((p + 1) & 63) == 0)) {
+          next_pos();
+          Wn = load_win(base, PU, pw, pu < u1);
+          wn_ready = true;
+        }
         // next panel: same product, next product (this or the next window),
         // or the first product of the next unit (the next window)
         if (sub + 1 < Cf::NPANEL) {
-          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63), __builtin_amdgcn_readlane(W0.b, p & 63),
-                            sub + 1, tid);
+          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63),
+                                __builtin_amdgcn_readlane(W0.b, p & 63), sub + 1, tid);
         } else if (p + 1 < U.cnt) {
           const int l = (p + 1) & 63;
           const bool nw = l == 0;
@@ -554,8 +575,8 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
           const int32_t ib = nw ? __builtin_amdgcn_readlane(W1.b, 0) : __builtin_amdgcn_readlane(W0.b, l);
           load_panel<P, BS, V>(pr, base, ia, ib, 0, tid);
         } else if (next_cnt > 0) {
-          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0), __builtin_amdgcn_readlane(W1.b, 0), 0,
-                            tid);
+          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0),
+                                __builtin_amdgcn_readlane(W1.b, 0), 0, tid);
         }
         if constexpr (Cf::TWO_LEVEL) {
           compute_panel<P, BS, V>(part, As, Bs, row0, col0, li, g);
@@ -575,12 +596,12 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
       if (((p + 1) & 63) == 0 && p + 1 < U.cnt) {  // into the unit's next window
         W0 = W1;
         W1 = W2;
-        next_pos();
-        W2 = load_win(base, PU, pw, pu < u1);
+        W2 = Wn;
+        wn_ready = false;
       }
     }
 
-    epilogue<P, BS, V>(ga, vs.unit(cu), U, acc, smem, red, tid, lane, wave, row0, col0, li, g);
+    epilogue<P, BS, V>(ga, vs.unit(cu), U, acc, smem, red2[cu & 1], tid, lane, wave, row0, col0, li, g);
     if (!has_next) break;
 
     const int32_t prev_cnt = U.cnt;
@@ -595,12 +616,17 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
     U = unit_of(ring, blk0, cu - rb);
     W0 = W1;
     W1 = W2;
-    next_pos();
-    W2 = load_win(base, PU, pw, pu < u1);
+    if (!wn_ready) {  // a unit without products fetched nothing ahead
+      next_pos();
+      Wn = load_win(base, PU, pw, pu < u1);
+    }
+    W2 = Wn;
+    wn_ready = false;
     // the first panel of a unit that follows a unit without products was
     // not prefetched
     if (prev_cnt == 0 && U.cnt > 0)
-      load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0), __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+      load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
+                            __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
   }
 }
 
