@@ -11,6 +11,12 @@ constexpr int kErrCoord = 1, kErrDup = 2, kErrPad = 4;
 
 // ---------------------------------------------------------------- leaf scan
 
+// Leaf passes: thread t takes the elements t, t + 256, t + 512, ... of a leaf
+// (row-major), kLeafPass of them per pass with every load issued before the
+// first use.  The per-thread order is the same for every kernel below, so the
+// dense and the block-list builds give bitwise equal norms.
+constexpr int kLeafPass = 8;
+
 // One workgroup per leaf (Morton index = blockIdx): FP64 squared norm (each
 // thread sums its fixed strided share of the leaf, then a fixed tree), the
 // non-zero flag and the non-finite flag.  Reads the dense input once.
@@ -28,14 +34,24 @@ __global__ void __launch_bounds__(256) k_build_scan_dense(const double* __restri
   int nz = 0, nf = 0;
   if (r0 < n && c0 < n) {
     const int rows = int(min<int64_t>(bs, n - r0)), cols = int(min<int64_t>(bs, n - c0));
-    for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-      const int rr = e / bs, cc = e % bs;
-      if (rr < rows && cc < cols) {
-        const double a = dense[(r0 + rr) * ld + c0 + cc];
-        const double sq = a * a;
-        s += sq;
-        nz |= (a != 0.0);
-        nf |= !isfinite(a);
+    const int sh = __builtin_ctz(unsigned(bs)), e2 = bs * bs;
+    for (int base = 0; base < e2; base += kLeafPass * 256) {
+      double a[kLeafPass];
+#pragma unroll
+      for (int q = 0; q < kLeafPass; ++q) {  // all loads of the pass first
+        const int e = base + q * 256 + int(threadIdx.x);
+        const int rr = e >> sh, cc = e & (bs - 1);
+        a[q] = (e < e2 && rr < rows && cc < cols) ? dense[(r0 + rr) * ld + c0 + cc] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kLeafPass; ++q) {
+        const int e = base + q * 256 + int(threadIdx.x);
+        const int rr = e >> sh, cc = e & (bs - 1);
+        if (e < e2 && rr < rows && cc < cols) {
+          s += a[q] * a[q];
+          nz |= (a[q] != 0.0);
+          nf |= !isfinite(a[q]);
+        }
       }
     }
   }
@@ -111,16 +127,26 @@ __global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, int64_t 
   const int64_t rows = min<int64_t>(bs, n - int64_t(I) * bs);
   const int64_t cols = min<int64_t>(bs, n - int64_t(J) * bs);
   const double* blk = data + t * bs * bs;
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const int rr = e / bs, cc = e % bs;
-    const double a = blk[e];
-    if (rr < rows && cc < cols) {
-      const double sq = a * a;
-      s += sq;
-      nz |= (a != 0.0);
-      nf |= !isfinite(a);
-    } else {
-      pad |= (a != 0.0);
+  const int sh = __builtin_ctz(unsigned(bs)), e2 = bs * bs;
+  for (int base = 0; base < e2; base += kLeafPass * 256) {
+    double a[kLeafPass];
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {  // all loads of the pass first
+      const int e = base + q * 256 + int(threadIdx.x);
+      a[q] = e < e2 ? blk[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {
+      const int e = base + q * 256 + int(threadIdx.x);
+      const int rr = e >> sh, cc = e & (bs - 1);
+      if (e >= e2) continue;
+      if (rr < rows && cc < cols) {
+        s += a[q] * a[q];
+        nz |= (a[q] != 0.0);
+        nf |= !isfinite(a[q]);
+      } else {
+        pad |= (a[q] != 0.0);
+      }
     }
   }
   s = block_sum_f64(s, red);
@@ -180,15 +206,26 @@ __device__ __forceinline__ void write_leaf(int64_t sl, int bs, Get get, double* 
   __shared__ uint32_t tile[64 * 65];
   const int64_t e2 = int64_t(bs) * bs;
   const int64_t base = sl * e2;
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const double a = get(e);
-    if (f64) f64[base + e] = a;
-    const float x = float(a);
-    if (f32) f32[base + e] = x;
-    if (b16) {
-      const uint16_t h = f32_to_bf16(x);
-      b16[2 * base + e] = h;
-      b16[2 * base + e2 + e] = f32_to_bf16(x - bf16_to_f32(h));
+  for (int b0 = 0; b0 < e2; b0 += kLeafPass * 256) {
+    double av[kLeafPass];
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {  // all loads of the pass first
+      const int e = b0 + q * 256 + int(threadIdx.x);
+      av[q] = e < e2 ? get(e) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {
+      const int e = b0 + q * 256 + int(threadIdx.x);
+      if (e >= e2) continue;
+      const double a = av[q];
+      if (f64) f64[base + e] = a;
+      const float x = float(a);
+      if (f32) f32[base + e] = x;
+      if (b16) {
+        const uint16_t h = f32_to_bf16(x);
+        b16[2 * base + e] = h;
+        b16[2 * base + e2 + e] = f32_to_bf16(x - bf16_to_f32(h));
+      }
     }
   }
   if (!b16t) return;
@@ -226,10 +263,11 @@ __global__ void __launch_bounds__(256) k_copy_dense_leaves(const double* __restr
   demorton(uint32_t(keys[sl]), r, c);
   const int64_t r0 = int64_t(r) * bs, c0 = int64_t(c) * bs;
   const int64_t rows = min<int64_t>(bs, n - r0), cols = min<int64_t>(bs, n - c0);
+  const int sh = __builtin_ctz(unsigned(bs));
   write_leaf(
       sl, bs,
       [&](int e) {
-        const int rr = e / bs, cc = e % bs;
+        const int rr = e >> sh, cc = e & (bs - 1);
         return (rr < rows && cc < cols) ? dense[(r0 + rr) * ld + c0 + cc] : 0.0;
       },
       f64, f32, b16, b16t);

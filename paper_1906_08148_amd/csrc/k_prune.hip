@@ -1,16 +1,17 @@
 // Pruning: which leaf products are formed (Alg. 1's norm test with Alg. 2's
-// null rule).  For every C leaf (i, j) one wavefront walks the row i of A and
-// the column j of B over the k range where both have non-null leaves, 64 k at
-// a time, and keeps k when A_ik and B_kj are non-null and (SpAMM, Hybrid)
-// sqrt(s_ik) * sqrt(s_kj) >= tau in FP64.  Because a parent's squared norm is
-// a sum of non-negative terms, every ancestor of a kept triple passes the
-// same test, so this flat test selects exactly the leaf products reached by
-// the recursion of Alg. 1.
+// null rule).  For every C leaf (i, j) the k range where A's row i and B's
+// column j both have non-null leaves is walked, and k is kept when A_ik and
+// B_kj are non-null and (SpAMM, Hybrid) sqrt(s_ik) * sqrt(s_kj) >= tau in
+// FP64.  Because a parent's squared norm is a sum of non-negative terms,
+// every ancestor of a kept triple passes the same test, so this flat test
+// selects exactly the leaf products reached by the recursion of Alg. 1.
+// The skipped products of each C leaf are summed k ascending (the bound
+// b_ij of the error estimate).
 //
 // Counting pass -> LDS-staged exclusive scan over all C leaves of the batch
 // (Morton order) -> fill pass writing the pairs (A and B leaf indices from
-// the arena base), the C slot map and the GEMM work units.  No atomics: positions come from the scan, so
-// the lists are deterministic.
+// the arena base), the C slot map and the GEMM work units.  No atomics:
+// positions come from the scan, so the lists are deterministic.
 #include "internal.h"
 #include "kern_common.h"
 
@@ -41,9 +42,12 @@ __device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, const i
 // Each wave takes 64 consecutive C leaves (one per lane).  Every lane finds
 // its request, intersects the k ranges of its A row and B column and keeps
 // the base addresses of that row and column in the row-major / column-major
-// prune views; the wave then walks the leaves whose range is not empty, four
-// at a time, 64 k per step, so the loads of four leaves are in flight
-// together.
+// prune views.  The wave then lays the k ranges of its 64 leaves end to end
+// (a prefix sum of their lengths) and walks that flattened list with every
+// lane busy: element t belongs to the leaf whose segment holds t (a binary
+// search over the segment starts in LDS), and kPU elements per lane are
+// loaded before any is used, so one round trip to memory serves up to
+// kPU * 64 (leaf, k) candidates whatever the leaves' range lengths.
 struct LaneLeaf {
   int r;
   uint32_t c, i, j;
@@ -81,107 +85,124 @@ __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, c
   return x;
 }
 
-__device__ __forceinline__ const double* lane_ptr(const double* p, int b) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(v), b), hi = __builtin_amdgcn_readlane(uint32_t(v >> 32), b);
-  return reinterpret_cast<const double*>((uint64_t(hi) << 32) | lo);
+constexpr int kPU = 8;              // flattened elements per lane per window
+constexpr int kPW = kPU * kWave;    // window of the flattened list
+constexpr int kPWaves = 4;          // waves per workgroup
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(v, off, kWave);
+    if (l >= off) v += o;
+  }
+  return v;
 }
-__device__ __forceinline__ const int32_t* lane_ptr(const int32_t* p, int b) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(v), b), hi = __builtin_amdgcn_readlane(uint32_t(v >> 32), b);
-  return reinterpret_cast<const int32_t*>((uint64_t(hi) << 32) | lo);
+__device__ __forceinline__ int64_t wave_excl_scan_i64(int64_t v) {
+  const int l = lane_id();
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int64_t o = __shfl_up(x, off, kWave);
+    if (l >= off) x += o;
+  }
+  return x - v;
 }
 
-// One walk group: up to four leaves (lanes b[q]), their parameters read from
-// those lanes.
-struct Group {
-  int n;
-  int b[4];
-  int lo[4], hi[4];
-  const double* sa[4];
-  const double* sb[4];
-  double tau[4];
-  bool norms[4];
+// LDS written by some lanes of a wave and read by others of the same wave:
+// the workgroup-scope fences make the writes complete (lgkmcnt) and keep the
+// compiler from moving accesses across; no other wave touches the region.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Owner of flattened element t < T: the last lane whose segment starts at or
+// before t (lanes with empty segments share the next lane's start, so the
+// last such lane has a non-empty segment holding t).
+__device__ __forceinline__ int seg_owner(const int32_t* sst, int t) {
+  int b = 0;
+#pragma unroll
+  for (int st = 32; st >= 1; st >>= 1)
+    if (sst[b + st] <= t) b += st;
+  return b;
+}
+
+struct CountLds {
+  int32_t sst[kWave];
+  int32_t lo[kWave];
+  const double* sa[kWave];
+  const double* sb[kWave];
+  double tau[kWave];  // < 0: no norm test (Truncmul)
+  double v[kPW];      // skipped product sqrt(s_ik) sqrt(s_kj), else 0
+  uint8_t fl[kPW];    // bit 0: both leaves non-null, bit 1: kept
 };
 
-__device__ __forceinline__ Group take_group(uint64_t& todo, const LaneLeaf& x, const ReqDev* __restrict__ reqs) {
-  Group gr;
-  gr.n = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    gr.b[q] = 0;
-    gr.lo[q] = 1;
-    gr.hi[q] = 0;
-    gr.sa[q] = gr.sb[q] = nullptr;
-    gr.tau[q] = 0.0;
-    gr.norms[q] = false;
-    if (todo) {
-      const int b = __ffsll((unsigned long long)todo) - 1;
-      todo &= todo - 1;
-      gr.b[q] = b;
-      gr.lo[q] = __builtin_amdgcn_readlane(x.lo, b);
-      gr.hi[q] = __builtin_amdgcn_readlane(x.hi, b);
-      gr.sa[q] = lane_ptr(x.sa, b);
-      gr.sb[q] = lane_ptr(x.sb, b);
-      const int r = __builtin_amdgcn_readlane(x.r, b);
-      gr.tau[q] = reqs[r].tau;
-      gr.norms[q] = reqs[r].use_norms != 0;
-      gr.n = q + 1;
-    }
-  }
-  return gr;
-}
-
-__global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
-                                                     int64_t* __restrict__ packed, double* __restrict__ bnd_all,
-                                                     int32_t* __restrict__ cand_all) {
+__global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* __restrict__ reqs, int nreq,
+                                                                 int64_t total_c, int64_t* __restrict__ packed,
+                                                                 double* __restrict__ bnd_all,
+                                                                 int32_t* __restrict__ cand_all) {
   __shared__ int64_t sc[kReqLds];
+  __shared__ CountLds wl[kPWaves];
   cache_cbase(reqs, nreq, sc);
-  const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+  const int64_t g0 = (int64_t(blockIdx.x) * kPWaves + threadIdx.x / kWave) * kWave;
   if (g0 >= total_c) return;
-  const int64_t g = g0 + lane_id();
+  const int lane = lane_id();
+  const int64_t g = g0 + lane;
   const LaneLeaf x = lane_leaf(reqs, sc, nreq, total_c, g);
+  CountLds& L = wl[threadIdx.x / kWave];
+  const int span = (x.valid && x.lo <= x.hi) ? x.hi - x.lo + 1 : 0;
+  const int incl = wave_incl_scan_i32(span);
+  const int sst = incl - span;
+  const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
   int64_t my_cnt = 0, my_cand = 0;
   double my_skip = 0.0;
-  uint64_t todo = ballot64(x.valid && x.lo <= x.hi);
-  while (todo) {
-    const Group gr = take_group(todo, x, reqs);
-    int64_t cnt[4] = {0, 0, 0, 0}, cand[4] = {0, 0, 0, 0};
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    int span = 0;
+  if (T > 0) {
+    L.sst[lane] = sst;
+    L.lo[lane] = x.lo;
+    L.sa[lane] = x.sa;
+    L.sb[lane] = x.sb;
+    L.tau[lane] = (x.valid && reqs[x.r].use_norms) ? reqs[x.r].tau : -1.0;
+    wave_lds_sync();
+    for (int wb = 0; wb < T; wb += kPW) {
+      double a[kPU], bv[kPU];
+      int own[kPU];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) span = max(span, gr.hi[q] - gr.lo[q] + 1);
-    for (int kb = 0; kb < span; kb += kWave) {
-      double a[4], bv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {  // all loads first
-        const int k = gr.lo[q] + kb + lane_id();
-        a[q] = -1.0;
-        bv[q] = -1.0;
-        if (q < gr.n && k <= gr.hi[q]) {
-          a[q] = gr.sa[q][k];
-          bv[q] = gr.sb[q][k];
+      for (int u = 0; u < kPU; ++u) {  // all loads of the window first
+        const int t = wb + u * kWave + lane;
+        a[u] = bv[u] = -1.0;
+        own[u] = 0;
+        if (t < T) {
+          const int b = seg_owner(L.sst, t);
+          const int k = L.lo[b] + (t - L.sst[b]);
+          own[u] = b;
+          a[u] = as_global(L.sa[b])[k];
+          bv[u] = as_global(L.sb[b])[k];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool both = (a[q] >= 0.0) && (bv[q] >= 0.0);
-        const double pr = a[q] * bv[q];
-        const bool keep = both && (!gr.norms[q] || pr >= gr.tau[q]);
-        cnt[q] += popc64(ballot64(keep));
-        cand[q] += popc64(ballot64(both));
-        if (both && !keep) part[q] += pr;
+      for (int u = 0; u < kPU; ++u) {
+        const int t = wb + u * kWave + lane;
+        if (t < T) {
+          const double tau = L.tau[own[u]];
+          const bool both = (a[u] >= 0.0) && (bv[u] >= 0.0);
+          const double pr = a[u] * bv[u];
+          const bool keep = both && (tau < 0.0 || pr >= tau);
+          L.v[t - wb] = (both && !keep) ? pr : 0.0;
+          L.fl[t - wb] = uint8_t((both ? 1 : 0) | (keep ? 2 : 0));
+        }
       }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q >= gr.n) break;
-      const double skipped = wave_sum_f64(part[q]);
-      if (lane_id() == gr.b[q]) {
-        my_cnt = cnt[q];
-        my_cand = cand[q];
-        my_skip = skipped;
+      wave_lds_sync();
+      // each leaf adds its own part of the window, k ascending
+      const int s0 = max(sst, wb), s1 = min(sst + span, wb + kPW);
+      for (int t = s0; t < s1; ++t) {
+        const int f = L.fl[t - wb];
+        my_cand += f & 1;
+        my_cnt += f >> 1;
+        my_skip += L.v[t - wb];
       }
+      wave_lds_sync();
     }
   }
   if (x.valid) {
@@ -197,9 +218,9 @@ __global__ void __launch_bounds__(256) k_prune_count(const ReqDev* __restrict__ 
 hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int64_t* packed,
                               double* bnd_all, int32_t* cand_all) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
-  const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, packed,
-                     bnd_all, cand_all);
+  const int64_t blocks = (waves + kPWaves - 1) / kPWaves;
+  hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c,
+                     packed, bnd_all, cand_all);
   return hipGetLastError();
 }
 
@@ -219,16 +240,36 @@ hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, con
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c,
-                                                    const int64_t* __restrict__ scanned,
-                                                    const double* __restrict__ bnd_all,
-                                                    const int32_t* __restrict__ cand_all,
-                                                    WorkUnit* __restrict__ wu, int64_t* __restrict__ cost) {
+struct FillLds {
+  int32_t sst[kWave];
+  int32_t lo[kWave];
+  const double* sa[kWave];
+  const double* sb[kWave];
+  const int32_t* la[kWave];
+  const int32_t* lb[kWave];
+  int64_t delta[kWave];
+  int64_t beg[kWave];
+  int64_t end[kWave];
+  double tau[kWave];
+  int2* out[kWave];
+  int32_t aoff[kWave];
+  int32_t boff[kWave];
+};
+
+__global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __restrict__ reqs, int nreq,
+                                                                int64_t total_c,
+                                                                const int64_t* __restrict__ scanned,
+                                                                const double* __restrict__ bnd_all,
+                                                                const int32_t* __restrict__ cand_all,
+                                                                WorkUnit* __restrict__ wu,
+                                                                int64_t* __restrict__ cost) {
   __shared__ int64_t sc[kReqLds];
+  __shared__ FillLds wl[kPWaves];
   cache_cbase(reqs, nreq, sc);
-  const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+  const int64_t g0 = (int64_t(blockIdx.x) * kPWaves + threadIdx.x / kWave) * kWave;
   if (g0 >= total_c) return;
-  const int64_t g = g0 + lane_id();
+  const int lane = lane_id();
+  const int64_t g = g0 + lane;
   const LaneLeaf x = lane_leaf(reqs, sc, nreq, total_c, g);
   int64_t off = 0, cnt = 0;
   if (x.valid) {
@@ -269,54 +310,71 @@ __global__ void __launch_bounds__(256) k_prune_fill(const ReqDev* __restrict__ r
     }
     if (x.i == x.j) R.trace_part[x.i] = 0.0;
   }
-  uint64_t todo = ballot64(x.valid && cnt > 0);
-  while (todo) {
-    const Group gr = take_group(todo, x, reqs);
-    int64_t pos[4], end[4];
-    const int32_t* la[4];
-    const int32_t* lb[4];
-    int64_t aoff[4], boff[4];
-    int2* out[4];
-    int span = 0;
+  // the kept pairs of the wave's leaves, in flattened order; a running count
+  // of kept elements gives each its place: leaf b's pairs start at off_b,
+  // which is where the running count stands at b's segment start plus
+  // delta_b = off_b - (kept elements of the earlier leaves of this wave)
+  const int span = (x.valid && cnt > 0) ? x.hi - x.lo + 1 : 0;
+  const int incl = wave_incl_scan_i32(span);
+  const int sst = incl - span;
+  const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
+  if (T == 0) return;
+  FillLds& L = wl[threadIdx.x / kWave];
+  const int64_t before = wave_excl_scan_i64(span > 0 ? cnt : 0);
+  L.sst[lane] = sst;
+  L.lo[lane] = x.lo;
+  L.sa[lane] = x.sa;
+  L.sb[lane] = x.sb;
+  L.la[lane] = x.la;
+  L.lb[lane] = x.lb;
+  L.delta[lane] = off - before;
+  L.beg[lane] = off;
+  L.end[lane] = off + cnt;
+  if (span > 0) {
+    const ReqDev& R = reqs[x.r];
+    L.tau[lane] = R.use_norms ? R.tau : -1.0;
+    L.out[lane] = R.pairs;
+    L.aoff[lane] = int32_t(R.aoff);
+    L.boff[lane] = int32_t(R.boff);
+  }
+  wave_lds_sync();
+  int64_t run = 0;  // kept elements before the current row of 64
+  for (int wb = 0; wb < T; wb += kPW) {
+    double a[kPU], bv[kPU];
+    int32_t sa[kPU], sb[kPU];
+    int own[kPU];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = gr.b[q];
-      pos[q] = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(off) >> 32), b))) << 32) |
-                       uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(off)), b)));
-      end[q] = pos[q] + __builtin_amdgcn_readlane(int32_t(cnt), b);
-      la[q] = lane_ptr(x.la, b);
-      lb[q] = lane_ptr(x.lb, b);
-      const int r = __builtin_amdgcn_readlane(x.r, b);
-      aoff[q] = reqs[r].aoff;
-      boff[q] = reqs[r].boff;
-      out[q] = reqs[r].pairs;
-      if (q < gr.n) span = max(span, gr.hi[q] - gr.lo[q] + 1);
+    for (int u = 0; u < kPU; ++u) {  // norms and slots of the window in flight together
+      const int t = wb + u * kWave + lane;
+      a[u] = bv[u] = -1.0;
+      sa[u] = sb[u] = 0;
+      own[u] = 0;
+      if (t < T) {
+        const int b = seg_owner(L.sst, t);
+        const int k = L.lo[b] + (t - L.sst[b]);
+        own[u] = b;
+        a[u] = as_global(L.sa[b])[k];
+        bv[u] = as_global(L.sb[b])[k];
+        sa[u] = as_global(L.la[b])[k];
+        sb[u] = as_global(L.lb[b])[k];
+      }
     }
-    for (int kb = 0; kb < span; kb += kWave) {
-      double a[4], bv[4];
-      int32_t sa[4], sb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {  // norms and slots of four leaves in flight together
-        const int k = gr.lo[q] + kb + lane_id();
-        a[q] = -1.0;
-        bv[q] = -1.0;
-        sa[q] = sb[q] = 0;
-        if (q < gr.n && k <= gr.hi[q]) {
-          a[q] = gr.sa[q][k];
-          bv[q] = gr.sb[q][k];
-          sa[q] = la[q][k];
-          sb[q] = lb[q][k];
-        }
+    for (int u = 0; u < kPU; ++u) {
+      const int t = wb + u * kWave + lane;
+      bool keep = false;
+      int b = own[u];
+      if (t < T) {
+        const double tau = L.tau[b];
+        const bool both = (a[u] >= 0.0) && (bv[u] >= 0.0);
+        keep = both && (tau < 0.0 || a[u] * bv[u] >= tau);
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool both = (a[q] >= 0.0) && (bv[q] >= 0.0);
-        const bool keep = both && (!gr.norms[q] || a[q] * bv[q] >= gr.tau[q]);
-        const uint64_t mask = ballot64(keep);
-        const int64_t at = pos[q] + popc64(mask & lanemask_lt());
-        if (keep && at < end[q]) out[q][at] = make_int2(int32_t(aoff[q] + sa[q]), int32_t(boff[q] + sb[q]));
-        pos[q] += popc64(mask);
+      const uint64_t mask = ballot64(keep);
+      if (keep) {
+        const int64_t at = L.delta[b] + run + popc64(mask & lanemask_lt());
+        if (at >= L.beg[b] && at < L.end[b]) L.out[b][at] = make_int2(L.aoff[b] + sa[u], L.boff[b] + sb[u]);
       }
+      run += popc64(mask);
     }
   }
 }
@@ -325,8 +383,8 @@ hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_
                              const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
                              WorkUnit* wu, int64_t* cost) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
-  const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(256), 0, s, reqs, nreq, total_c, scanned,
+  const int64_t blocks = (waves + kPWaves - 1) / kPWaves;
+  hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c, scanned,
                      bnd_all, cand_all, wu, cost);
   return hipGetLastError();
 }

@@ -133,10 +133,13 @@ hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t cou
 // drop the longest prefix whose summed squared norm is <= tau^2.  Only leaves
 // with s <= tau^2 can be in that prefix (candidates).  For each candidate x,
 // F(x) = sum of s_y over candidates y with key_y <= key_x, summed in one
-// fixed order (candidate index); each addition only grows with x's key, so F
-// is monotone in the key and {x : F(x) <= tau^2} is a prefix of the order.
+// fixed order that does not depend on x (lane l of a wave adds the candidates
+// y = l, l + 64, ... in index order, then a fixed tree adds the 64 lane sums).
+// Rounding is monotone, so each addition only grows with x's key: F is
+// monotone in the key and {x : F(x) <= tau^2} is a prefix of the order.
 // Small candidate sets evaluate F(x) for every x from LDS; large ones build
-// the largest admissible key bit by bit (the same F, evaluated per trial key).
+// the largest admissible key bit by bit (F of each trial key summed in the
+// workgroup's own fixed order, again monotone in the key).
 // All jobs of a batch share one set of launches.
 
 __device__ __forceinline__ int find_job(const TruncJob* __restrict__ jobs, int njobs, int64_t g) {
@@ -176,8 +179,8 @@ constexpr int kSelThreads = 1024;
 constexpr int kSelLds = 4096;   // candidate sets up to this size use the all-pairs form
 constexpr int kSelSplit = 16;   // workgroups per job in the all-pairs form
 
-// All-pairs form, part 1: workgroup (job, part) evaluates F(x) for the
-// candidates x = part, part + kSelSplit, ... of its job.
+// All-pairs form, part 1: the waves of a job's kSelSplit workgroups take the
+// candidates x in turn; the lanes of a wave split the sum over y.
 __global__ void __launch_bounds__(kSelThreads) k_trunc_fx(const TruncJob* __restrict__ jobs,
                                                           const int64_t* __restrict__ pos,
                                                           const double* __restrict__ cs_all,
@@ -195,15 +198,19 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_fx(const TruncJob* __rest
     m_lds[t] = uint32_t(cm_all[c0 + t]);
   }
   __syncthreads();
-  for (int64_t x = part + int64_t(threadIdx.x) * kSelSplit; x < mc; x += int64_t(kSelThreads) * kSelSplit) {
+  constexpr int NW = kSelThreads / kWave;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  for (int64_t x = int64_t(part) * NW + w; x < mc; x += int64_t(kSelSplit) * NW) {
     const uint64_t xh = __double_as_longlong(s_lds[x]);
     const uint32_t xl = m_lds[x];
     double f = 0.0;
-    for (int64_t y = 0; y < mc; ++y) {
+#pragma unroll 4
+    for (int64_t y = lane; y < mc; y += kWave) {
       const double sy = s_lds[y];
       if (key_le(__double_as_longlong(sy), m_lds[y], xh, xl)) f += sy;
     }
-    fx_all[c0 + x] = f;
+    f = wave_sum_f64(f);
+    if (lane == 0) fx_all[c0 + x] = f;
   }
 }
 
