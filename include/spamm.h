@@ -253,7 +253,9 @@ spamm_status spamm_multiply(spamm_ctx* ctx, const spamm_mat* A,
  * persistent GEMM launch per (precision, leaf size).  C_out[r] and st_out[r]
  * (nullable array) receive request r's result; each equals what
  * spamm_multiply returns for that request alone, bit for bit.  On error no
- * C_out is allocated.  Same errors as spamm_multiply. */
+ * C_out is allocated.  Same errors as spamm_multiply; EUNSUPPORTED also when
+ * the batch is too large for one counting pass (the sum over requests of
+ * G^3, times the total number of C leaves G^2, reaches 2^62): split it. */
 spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count,
                                   const spamm_request* reqs,
                                   spamm_mat** C_out, spamm_stats* st_out);

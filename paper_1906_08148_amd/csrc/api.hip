@@ -188,6 +188,45 @@ spamm_status nomem(Ctx* c, const char* what, size_t bytes) {
     if (!(var)) return nomem(c, what, size_t(nleaf) * (leaf_bytes));                   \
   } while (0)
 
+// Descriptor tables gathered on the host and sent to the device in one copy
+// (one region, one transfer) before the launches that read them.
+// A table whose content depends on device addresses inside the set is
+// reserved first and written with put() once place() has allocated the set.
+struct TableSet {
+  std::vector<char> host;
+  RegionP dev;
+  size_t reserve(size_t bytes) {
+    const size_t o = (host.size() + 255) / 256 * 256;
+    host.resize(o + bytes);
+    return o;
+  }
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t o = reserve(v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(host.data() + o, v.data(), v.size() * sizeof(T));
+    return o;
+  }
+  template <typename T>
+  void put(size_t off, const std::vector<T>& v) {
+    if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+  }
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(static_cast<char*>(dev->ptr()) + off);
+  }
+};
+
+spamm_status place_tables(Ctx* c, TableSet& t) {
+  if (!t.dev) ALLOC(t.dev, std::max<size_t>(t.host.size(), 256), "descriptor tables");
+  return SPAMM_OK;
+}
+
+spamm_status send_tables(Ctx* c, TableSet& t) {
+  spamm_status st = place_tables(c, t);
+  if (st != SPAMM_OK) return st;
+  return upload(c, t.dev->ptr(), t.host.data(), t.host.size());
+}
+
 // Handle skeleton with the per-level arrays (no leaf storage).
 spamm_status new_matrix(Ctx* c, int64_t n, int bs, std::unique_ptr<spamm_mat>& out) {
   auto m = std::make_unique<spamm_mat>();
@@ -204,11 +243,15 @@ spamm_status new_matrix(Ctx* c, int64_t n, int bs, std::unique_ptr<spamm_mat>& o
 }
 
 // Row/column views for pruning, computed on first use as an operand (all
-// matrices that lack them in one batched pass).
-spamm_status prep_many(Ctx* c, const std::vector<spamm_mat*>& mats) {
+// matrices that lack them in one batched pass).  prep_plan allocates the
+// views and fills the job table; prep_launch runs it from the device copy.
+struct PrepPlan {
   std::vector<PrepJob> jobs;
-  std::vector<spamm_mat*> todo;
   int64_t total = 0, waves = 0;
+};
+
+spamm_status prep_plan(Ctx* c, const std::vector<spamm_mat*>& mats, PrepPlan& pp) {
+  std::vector<spamm_mat*> todo;
   for (spamm_mat* m : mats) {
     if (m->rm_sqrt || std::find(todo.begin(), todo.end(), m) != todo.end()) continue;
     const int64_t G2 = int64_t(m->G) * m->G;
@@ -225,32 +268,30 @@ spamm_status prep_many(Ctx* c, const std::vector<spamm_mat*>& mats) {
     j.cm_sqrt = P<double>(m->cm_sqrt);
     j.cm_slot = P<int32_t>(m->cm_slot);
     j.ranges = P<int32_t>(m->ranges);
-    j.base = total;
-    j.wbase = waves;
+    j.base = pp.total;
+    j.wbase = pp.waves;
     j.G = m->G;
     j.pad_ = 0;
-    jobs.push_back(j);
+    pp.jobs.push_back(j);
     todo.push_back(m);
-    total += G2;
-    waves += 2 * int64_t(m->G);
+    pp.total += G2;
+    pp.waves += 2 * int64_t(m->G);
   }
-  if (jobs.empty()) return SPAMM_OK;
-  RegionP jd;
-  ALLOC(jd, jobs.size() * sizeof(PrepJob), "prep jobs");
-  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PrepJob));
-  if (st != SPAMM_OK) return st;
-  TimedScope ts(c, kTPrune);
-  SPAMM_HIP(c, launch_prep_batch(c->stream, P<PrepJob>(jd), int(jobs.size()), total, waves));
   return SPAMM_OK;
 }
 
-// Pyramid over a set of matrices whose leaf level is filled.
-// Pyramid jobs over a set of matrices whose leaf level is filled: the job
-// table is uploaded here, the launch is separate (it may be captured).
-spamm_status pyramids_prepare(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls, RegionP& jd,
-                              std::vector<PyrJob>& jobs) {
-  jobs.assign(norms.size(), PyrJob{});
-  if (norms.empty()) return SPAMM_OK;
+spamm_status prep_launch(Ctx* c, const PrepJob* jd, const PrepPlan& pp) {
+  if (pp.jobs.empty()) return SPAMM_OK;
+  TimedScope ts(c, kTPrune);
+  SPAMM_HIP(c, launch_prep_batch(c->stream, jd, int(pp.jobs.size()), pp.total, pp.waves));
+  return SPAMM_OK;
+}
+
+// Pyramids over a set of matrices whose leaf level is filled: the job
+// table (pyramid_jobs) and its launch from a device copy (it may be
+// captured).
+std::vector<PyrJob> pyramid_jobs(const std::vector<double*>& norms, const std::vector<int>& Ls) {
+  std::vector<PyrJob> jobs(norms.size(), PyrJob{});
   int64_t base = 0;
   for (size_t t = 0; t < norms.size(); ++t) {
     jobs[t].norms = norms[t];
@@ -259,23 +300,14 @@ spamm_status pyramids_prepare(Ctx* c, const std::vector<double*>& norms, const s
     jobs[t].block_base = base;
     base += int64_t(1) << (2 * (Ls[t] - jobs[t].sub_levels));
   }
-  ALLOC(jd, jobs.size() * sizeof(PyrJob), "pyramid jobs");
-  return upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(PyrJob));
+  return jobs;
 }
 
-spamm_status pyramids_launch(Ctx* c, const RegionP& jd, const std::vector<PyrJob>& jobs) {
+spamm_status pyramids_launch(Ctx* c, const PyrJob* jd, const std::vector<PyrJob>& jobs) {
   if (jobs.empty()) return SPAMM_OK;
   TimedScope ts(c, kTPyr);
-  SPAMM_HIP(c, launch_pyramid(c->stream, P<PyrJob>(jd), int(jobs.size()), jobs));
+  SPAMM_HIP(c, launch_pyramid(c->stream, jd, int(jobs.size()), jobs));
   return SPAMM_OK;
-}
-
-spamm_status pyramids(Ctx* c, const std::vector<double*>& norms, const std::vector<int>& Ls) {
-  RegionP jd;
-  std::vector<PyrJob> jobs;
-  spamm_status st = pyramids_prepare(c, norms, Ls, jd, jobs);
-  if (st != SPAMM_OK) return st;
-  return pyramids_launch(c, jd, jobs);
 }
 
 spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask) {
@@ -328,8 +360,22 @@ uint32_t store_for_prec(int prec) {
 
 bool tau_ok(double t) { return std::isfinite(t) && t >= 0.0; }
 
-spamm_status finish_build(Ctx* c, std::unique_ptr<spamm_mat>& m, spamm_mat** out) {
-  spamm_status st = pyramids(c, {P<double>(m->norms)}, {m->L});
+// A build's pyramid job table is sent while its first kernels run (before
+// the build's read-back), so the copy costs no idle device time.
+struct BuildPyr {
+  TableSet t;
+  size_t off = 0;
+  std::vector<PyrJob> jobs;
+};
+
+spamm_status send_build_pyr(Ctx* c, const spamm_mat& m, BuildPyr& bp) {
+  bp.jobs = pyramid_jobs({P<double>(m.norms)}, {m.L});
+  bp.off = bp.t.add(bp.jobs);
+  return send_tables(c, bp.t);
+}
+
+spamm_status finish_build(Ctx* c, std::unique_ptr<spamm_mat>& m, spamm_mat** out, const BuildPyr& bp) {
+  spamm_status st = pyramids_launch(c, bp.t.at<PyrJob>(bp.off), bp.jobs);
   if (st != SPAMM_OK) return st;
   c->live_handles++;
   *out = m.release();
@@ -338,14 +384,22 @@ spamm_status finish_build(Ctx* c, std::unique_ptr<spamm_mat>& m, spamm_mat** out
 
 // Truncate several (matrix, tau) pairs with one set of launches.  Outputs
 // share leaf storage with their inputs; `result` holds 2 doubles per job
-// (dropped squared norm, dropped count) on the device.
-spamm_status truncate_many(Ctx* c, const std::vector<std::pair<const spamm_mat*, double>>& in,
-                           std::vector<std::unique_ptr<spamm_mat>>& out, RegionP& result) {
+// (dropped squared norm, dropped count) on the device.  trunc_plan creates
+// the outputs and the job tables (truncation, then the outputs' pyramids);
+// trunc_launch runs both from their device copies.
+struct TruncPlan {
+  std::vector<TruncJob> jobs;
+  std::vector<PyrJob> pyr;
+  int64_t total = 0;
+  RegionP scratch;
+  size_t sb = 0;
+};
+
+spamm_status trunc_plan(Ctx* c, const std::vector<std::pair<const spamm_mat*, double>>& in,
+                        std::vector<std::unique_ptr<spamm_mat>>& out, RegionP& result, TruncPlan& tp) {
   out.clear();
   if (in.empty()) return SPAMM_OK;
   ALLOC(result, in.size() * 16, "truncation results");
-  std::vector<TruncJob> jobs;
-  int64_t total = 0;
   for (size_t t = 0; t < in.size(); ++t) {
     const spamm_mat* a = in[t].first;
     std::unique_ptr<spamm_mat> m;
@@ -359,32 +413,34 @@ spamm_status truncate_many(Ctx* c, const std::vector<std::pair<const spamm_mat*,
     j.out_norm = P<double>(m->norms) + level_offset(m->L);
     j.result = P<double>(result) + 2 * t;
     j.tau2 = in[t].second * in[t].second;
-    j.base = total;
+    j.base = tp.total;
     j.G = a->G;
     int kb = 1;
     while ((int64_t(1) << kb) < int64_t(a->G) * a->G) ++kb;
     j.key_bits_lo = kb;
-    jobs.push_back(j);
-    total += int64_t(a->G) * a->G;
+    tp.jobs.push_back(j);
+    tp.total += int64_t(a->G) * a->G;
     out.push_back(std::move(m));
   }
-  RegionP jd, scratch;
-  ALLOC(jd, jobs.size() * sizeof(TruncJob), "truncation jobs");
-  const size_t sb = trunc_batch_scratch_bytes(int(jobs.size()), total);
-  ALLOC(scratch, sb, "truncation scratch");
-  spamm_status st = upload(c, jd->ptr(), jobs.data(), jobs.size() * sizeof(TruncJob));
-  if (st != SPAMM_OK) return st;
-  {
-    TimedScope ts(c, kTTrunc);
-    SPAMM_HIP(c, launch_trunc_batch(c->stream, P<TruncJob>(jd), int(jobs.size()), total, scratch->ptr(), sb));
-  }
+  tp.sb = trunc_batch_scratch_bytes(int(tp.jobs.size()), tp.total);
+  ALLOC(tp.scratch, tp.sb, "truncation scratch");
   std::vector<double*> nv;
   std::vector<int> lv;
   for (auto& m : out) {
     nv.push_back(P<double>(m->norms));
     lv.push_back(m->L);
   }
-  return pyramids(c, nv, lv);
+  tp.pyr = pyramid_jobs(nv, lv);
+  return SPAMM_OK;
+}
+
+spamm_status trunc_launch(Ctx* c, const TruncPlan& tp, const TruncJob* jd, const PyrJob* pd) {
+  if (tp.jobs.empty()) return SPAMM_OK;
+  {
+    TimedScope ts(c, kTTrunc);
+    SPAMM_HIP(c, launch_trunc_batch(c->stream, jd, int(tp.jobs.size()), tp.total, tp.scratch->ptr(), tp.sb));
+  }
+  return pyramids_launch(c, pd, tp.pyr);
 }
 
 }  // namespace
@@ -544,6 +600,9 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
                                        P<int32_t>(flag), P<int32_t>(nf)));
   SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
   }
+  BuildPyr bp;
+  st = send_build_pyr(c, *m, bp);
+  if (st != SPAMM_OK) return st;
   struct {
     int32_t nf;
     int32_t pad[15];
@@ -561,7 +620,7 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   SPAMM_HIP(c, launch_copy_dense_leaves(c->stream, dense, n, ld, leaf, hb.total, P<int32_t>(m->store->keys),
                                         P<double>(m->store->f64), P<float>(m->store->f32),
                                         P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
-  return finish_build(c, m, out);
+  return finish_build(c, m, out, bp);
 }
 
 spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t nblocks, const int32_t* coords,
@@ -594,6 +653,9 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
                                   P<double>(m->norms) + level_offset(m->L), P<int32_t>(flag), P<int32_t>(nf)));
   SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
   }
+  BuildPyr bp;
+  st = send_build_pyr(c, *m, bp);
+  if (st != SPAMM_OK) return st;
   struct {
     int32_t err;
     int32_t pad[15];
@@ -614,7 +676,7 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   SPAMM_HIP(c, launch_copy_block_leaves(c->stream, n, leaf, hb.total, P<int32_t>(m->store->keys), P<int32_t>(src),
                                         data, P<double>(m->store->f64), P<float>(m->store->f32),
                                         P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
-  return finish_build(c, m, out);
+  return finish_build(c, m, out, bp);
 }
 
 spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out, double* dropped_sq) {
@@ -625,7 +687,14 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   if (!tau_ok(tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
   std::vector<std::unique_ptr<spamm_mat>> ms;
   RegionP res;
-  spamm_status st = truncate_many(c, {{in, tau}}, ms, res);
+  TruncPlan tp;
+  spamm_status st = trunc_plan(c, {{in, tau}}, ms, res, tp);
+  if (st != SPAMM_OK) return st;
+  TableSet tabs;
+  const size_t oj = tabs.add(tp.jobs), op = tabs.add(tp.pyr);
+  st = send_tables(c, tabs);
+  if (st != SPAMM_OK) return st;
+  st = trunc_launch(c, tp, tabs.at<TruncJob>(oj), tabs.at<PyrJob>(op));
   if (st != SPAMM_OK) return st;
   double hr[2];
   st = download(c, hr, res->ptr(), sizeof(hr));
@@ -682,10 +751,13 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       }
     }
   }
+  // every table the launches up to the counting pass read is planned on the
+  // host first and sent in one copy
   std::vector<std::unique_ptr<spamm_mat>> tmats;
   RegionP tres;
+  TruncPlan tplan;
   {
-    spamm_status st = truncate_many(c, tjobs, tmats, tres);
+    spamm_status st = trunc_plan(c, tjobs, tmats, tres, tplan);
     if (st != SPAMM_OK) return st;
   }
   std::vector<spamm_mat*> Au(count), Bu(count);
@@ -706,8 +778,9 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     operands.push_back(Au[r]);
     operands.push_back(Bu[r]);
   }
+  PrepPlan pplan;
   {
-    spamm_status st = prep_many(c, operands);
+    spamm_status st = prep_plan(c, operands, pplan);
     if (st != SPAMM_OK) return st;
   }
   for (int r = 0; r < count; ++r) {
@@ -761,8 +834,19 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     total_c += int64_t(d.G) * d.G;
     total_chunks += (int64_t(d.G) * d.G + kStatChunk - 1) / kStatChunk;
   }
-  RegionP reqd, packed, scanned, bnd_all, cand_all, scan_scr, totals;
-  ALLOC(reqd, count * sizeof(ReqDev), "request table");
+  // packed counts: the kept count of a C leaf is at most G (one per k), so
+  // the batch's kept total is below sum G^3 and its non-null total at most
+  // total_c; both fields of the scanned int64 must fit
+  int cnt_bits = 1, c_bits = 1;
+  {
+    int64_t ub = 0;
+    for (int r = 0; r < count; ++r) ub += int64_t(rd[r].G) * rd[r].G * rd[r].G;
+    while ((int64_t(1) << cnt_bits) <= ub) ++cnt_bits;
+    while ((int64_t(1) << c_bits) <= total_c) ++c_bits;
+    if (cnt_bits + c_bits > 62)
+      return fail(c, SPAMM_EUNSUPPORTED, "batch too large for one counting pass; split it");
+  }
+  RegionP packed, scanned, bnd_all, cand_all, scan_scr, totals;
   ALLOC(packed, total_c * 8, "counts");
   ALLOC(scanned, (total_c + 1) * 8, "offsets");
   ALLOC(bnd_all, total_c * 8, "bounds");
@@ -770,14 +854,22 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   const size_t ssb = scan_scratch_bytes(total_c);
   ALLOC(scan_scr, ssb, "scan scratch");
   ALLOC(totals, count * sizeof(ReqTotals), "totals");
-  spamm_status st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
+  TableSet pre;
+  const size_t o_tj = pre.add(tplan.jobs), o_tp = pre.add(tplan.pyr), o_pj = pre.add(pplan.jobs),
+               o_rd = pre.add(rd);
+  spamm_status st = send_tables(c, pre);
+  if (st != SPAMM_OK) return st;
+  st = trunc_launch(c, tplan, pre.at<TruncJob>(o_tj), pre.at<PyrJob>(o_tp));
+  if (st != SPAMM_OK) return st;
+  st = prep_launch(c, pre.at<PrepJob>(o_pj), pplan);
   if (st != SPAMM_OK) return st;
   {
   TimedScope ts(c, kTPrune);
-  SPAMM_HIP(c, launch_prune_count(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(packed), P<double>(bnd_all),
+  const ReqDev* rd0 = pre.at<ReqDev>(o_rd);
+  SPAMM_HIP(c, launch_prune_count(c->stream, rd0, count, total_c, cnt_bits, P<int64_t>(packed), P<double>(bnd_all),
                                   P<int32_t>(cand_all)));
   SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
-  SPAMM_HIP(c, launch_gather_totals(c->stream, P<ReqDev>(reqd), count, P<int64_t>(scanned), P<ReqTotals>(totals)));
+  SPAMM_HIP(c, launch_gather_totals(c->stream, rd0, count, cnt_bits, P<int64_t>(scanned), P<ReqTotals>(totals)));
   }
   std::vector<ReqTotals> ht(count);
   st = download(c, ht.data(), totals->ptr(), count * sizeof(ReqTotals));
@@ -917,36 +1009,17 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       scan_need = std::max<int64_t>(scan_need, int64_t(scan_scratch_bytes(std::max<int64_t>(nwu, 1))));
     }
   }
-  RegionP wus, costs, prefix, starts, wn, wt, schedd, sscr;
+  RegionP wus, costs, prefix, starts, wn, wt, sscr;
   ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
   ALLOC(costs, std::max<int64_t>(wu_total, 1) * 8, "unit costs");
   ALLOC(prefix, (wu_total + int64_t(groups.size())) * 8, "unit cost prefix");
   ALLOC(starts, std::max<int64_t>(start_total, 1) * 8, "workgroup ranges");
   ALLOC(wn, std::max<int64_t>(wu_total, 1) * 8, "unit norms");
   ALLOC(wt, std::max<int64_t>(wu_total, 1) * 8, "unit diagonal sums");
-  ALLOC(schedd, std::max<size_t>(sched.size(), 1) * 8, "placement tables");
   ALLOC(sscr, std::max<int64_t>(scan_need, 1), "scan scratch");
-  st = upload(c, schedd->ptr(), sched.data(), sched.size() * 8);
-  if (st != SPAMM_OK) return st;
-  {
-    int gj = 0;
-    for (auto& gk : groups) {
-      for (size_t k = 0; k < gk.second.size(); ++k) {
-        ReqDev& d = rd[gk.second[k]];
-        d.wu_base = launches[gj].second.first;
-        d.sched = P<int64_t>(schedd) + sched_off[gj];
-        d.sched_k = int32_t(k);
-        d.sched_n = int32_t(gk.second.size());
-        d.nslices = ns;
-      }
-      ++gj;
-    }
-  }
-  st = upload(c, reqd->ptr(), rd.data(), count * sizeof(ReqDev));
-  if (st != SPAMM_OK) return st;
-  // C pyramid jobs and statistics buffers are set up before the launches,
-  // which then need no host copies (they may be captured into one graph)
-  RegionP pyr_jd, sd, part;
+  // placement tables, the completed request table and C's pyramid jobs:
+  // one copy, and the launches after it need no host copies (they may be
+  // captured into one graph)
   std::vector<PyrJob> pyr_jobs;
   {
     std::vector<double*> nv;
@@ -955,9 +1028,33 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       nv.push_back(P<double>(Cs[r]->norms));
       lv.push_back(Cs[r]->L);
     }
-    st = pyramids_prepare(c, nv, lv, pyr_jd, pyr_jobs);
-    if (st != SPAMM_OK) return st;
+    pyr_jobs = pyramid_jobs(nv, lv);
   }
+  TableSet postt;
+  const size_t o_sched = postt.add(sched), o_req = postt.reserve(count * sizeof(ReqDev)),
+               o_pyr = postt.add(pyr_jobs);
+  st = place_tables(c, postt);
+  if (st != SPAMM_OK) return st;
+  {
+    int gj = 0;
+    for (auto& gk : groups) {
+      for (size_t k = 0; k < gk.second.size(); ++k) {
+        ReqDev& d = rd[gk.second[k]];
+        d.wu_base = launches[gj].second.first;
+        d.sched = postt.at<int64_t>(o_sched) + sched_off[gj];
+        d.sched_k = int32_t(k);
+        d.sched_n = int32_t(gk.second.size());
+        d.nslices = ns;
+      }
+      ++gj;
+    }
+  }
+  postt.put(o_req, rd);
+  st = send_tables(c, postt);
+  if (st != SPAMM_OK) return st;
+  const ReqDev* reqd = postt.at<ReqDev>(o_req);
+  const PyrJob* pyr_jd = postt.at<PyrJob>(o_pyr);
+  RegionP sd, part;
   if (st_out) {
     ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
     ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
@@ -965,7 +1062,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   auto post = [&]() -> spamm_status {
     {
       TimedScope ts(c, kTPrune);
-      SPAMM_HIP(c, launch_prune_fill(c->stream, P<ReqDev>(reqd), count, total_c, P<int64_t>(scanned),
+      SPAMM_HIP(c, launch_prune_fill(c->stream, reqd, count, total_c, cnt_bits, P<int64_t>(scanned),
                                      P<double>(bnd_all), P<int32_t>(cand_all), P<WorkUnit>(wus), P<int64_t>(costs)));
     }
     int gi = 0;
@@ -986,7 +1083,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       GemmArgs ga;
       ga.wu = P<WorkUnit>(wus) + u0;
       ga.start = stg;
-      ga.reqs = P<ReqDev>(reqd);
+      ga.reqs = reqd;
       ga.base = c->arena.base();
       ga.wn = P<double>(wn) + u0;
       ga.wt = P<double>(wt) + u0;
@@ -1009,13 +1106,13 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     }
     {
       TimedScope ts(c, kTPyr);
-      SPAMM_HIP(c, launch_unit_scatter(c->stream, P<ReqDev>(reqd), P<WorkUnit>(wus), wu_total, P<double>(wn),
+      SPAMM_HIP(c, launch_unit_scatter(c->stream, reqd, P<WorkUnit>(wus), wu_total, P<double>(wn),
                                        P<double>(wt)));
     }
     spamm_status s2 = pyramids_launch(c, pyr_jd, pyr_jobs);
     if (s2 != SPAMM_OK) return s2;
     if (st_out)
-      SPAMM_HIP(c, launch_req_stats(c->stream, P<ReqDev>(reqd), count, total_chunks, P<StatPartial>(part),
+      SPAMM_HIP(c, launch_req_stats(c->stream, reqd, count, total_chunks, P<StatPartial>(part),
                                     P<ReqStatsDev>(sd)));
     return SPAMM_OK;
   };

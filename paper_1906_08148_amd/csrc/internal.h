@@ -355,14 +355,16 @@ hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
 hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs_dev, int njobs, int64_t total,
                               void* scratch, size_t scratch_bytes);
 size_t trunc_batch_scratch_bytes(int njobs, int64_t total);
-// prune
-hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+// prune.  The counting pass packs (C leaf non-null << cnt_bits) | kept count
+// per C leaf into one int64, so that one scan gives both prefixes; the host
+// picks cnt_bits per batch so that neither field can overflow.
+hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
                               int64_t* packed, double* bnd_all, int32_t* cand_all);
-hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq,
+hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, int cnt_bits,
                                 const int64_t* scanned, ReqTotals* out);
 // writes the kept pairs, C's slot map and the work units (with their cost,
 // products + 1, for the range split) in placement order
-hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
                              const int64_t* scanned, const double* bnd_all,
                              const int32_t* cand_all, WorkUnit* wu, int64_t* cost);
 constexpr int kXcds = 8;  // slices of the placement: workgroup w runs on XCD w % 8

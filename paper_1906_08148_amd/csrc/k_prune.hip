@@ -17,8 +17,7 @@
 
 namespace spamm {
 
-constexpr int64_t kCntBits = 40;
-constexpr int64_t kCntMask = (int64_t(1) << kCntBits) - 1;
+__device__ __forceinline__ int64_t cnt_mask(int cb) { return (int64_t(1) << cb) - 1; }
 
 // Requests' first global C index, cached in LDS by every workgroup (larger
 // batches search the descriptor table in memory).
@@ -140,7 +139,8 @@ struct CountLds {
 };
 
 __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* __restrict__ reqs, int nreq,
-                                                                 int64_t total_c, int64_t* __restrict__ packed,
+                                                                 int64_t total_c, int cb,
+                                                                 int64_t* __restrict__ packed,
                                                                  double* __restrict__ bnd_all,
                                                                  int32_t* __restrict__ cand_all) {
   __shared__ int64_t sc[kReqLds];
@@ -209,34 +209,35 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
     const ReqDev& R = reqs[x.r];
     const bool dflag = R.slotD != nullptr && R.slotD[x.c] >= 0;
     const int64_t flag = (my_cnt > 0 || dflag) ? 1 : 0;
-    packed[g] = (flag << kCntBits) | my_cnt;
+    packed[g] = (flag << cb) | my_cnt;
     bnd_all[g] = my_skip;
     cand_all[g] = int32_t(my_cand);
   }
 }
 
-hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int64_t* packed,
-                              double* bnd_all, int32_t* cand_all) {
+hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
+                              int64_t* packed, double* bnd_all, int32_t* cand_all) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
   const int64_t blocks = (waves + kPWaves - 1) / kPWaves;
   hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c,
-                     packed, bnd_all, cand_all);
+                     cnt_bits, packed, bnd_all, cand_all);
   return hipGetLastError();
 }
 
-__global__ void k_gather_totals(const ReqDev* __restrict__ reqs, int nreq, const int64_t* __restrict__ scanned,
-                                ReqTotals* __restrict__ out) {
+__global__ void k_gather_totals(const ReqDev* __restrict__ reqs, int nreq, int cb,
+                                const int64_t* __restrict__ scanned, ReqTotals* __restrict__ out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nreq) return;
   const ReqDev& R = reqs[r];
   const int64_t a = scanned[R.cbase], b = scanned[R.cbase + int64_t(R.G) * R.G];
-  out[r].n_kept = (b & kCntMask) - (a & kCntMask);
-  out[r].c_nonnull = (b >> kCntBits) - (a >> kCntBits);
+  out[r].n_kept = (b & cnt_mask(cb)) - (a & cnt_mask(cb));
+  out[r].c_nonnull = (b >> cb) - (a >> cb);
 }
 
-hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, const int64_t* scanned,
+hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, int cnt_bits, const int64_t* scanned,
                                 ReqTotals* out) {
-  hipLaunchKernelGGL(k_gather_totals, dim3(uint32_t((nreq + 63) / 64)), dim3(64), 0, s, reqs, nreq, scanned, out);
+  hipLaunchKernelGGL(k_gather_totals, dim3(uint32_t((nreq + 63) / 64)), dim3(64), 0, s, reqs, nreq, cnt_bits, scanned,
+                     out);
   return hipGetLastError();
 }
 
@@ -257,7 +258,7 @@ struct FillLds {
 };
 
 __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __restrict__ reqs, int nreq,
-                                                                int64_t total_c,
+                                                                int64_t total_c, int cb,
                                                                 const int64_t* __restrict__ scanned,
                                                                 const double* __restrict__ bnd_all,
                                                                 const int32_t* __restrict__ cand_all,
@@ -276,10 +277,11 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
     const ReqDev& R = reqs[x.r];
     const int64_t G2 = int64_t(R.G) * R.G;
     const int64_t s0 = scanned[R.cbase], sg = scanned[g], s1 = scanned[g + 1];
-    off = (sg & kCntMask) - (s0 & kCntMask);
-    cnt = (s1 & kCntMask) - (sg & kCntMask);
-    const bool flag = ((s1 >> kCntBits) - (sg >> kCntBits)) != 0;
-    const int32_t cs = int32_t((sg >> kCntBits) - (s0 >> kCntBits));
+    const int64_t cmk = cnt_mask(cb);
+    off = (sg & cmk) - (s0 & cmk);
+    cnt = (s1 & cmk) - (sg & cmk);
+    const bool flag = ((s1 >> cb) - (sg >> cb)) != 0;
+    const int32_t cs = int32_t((sg >> cb) - (s0 >> cb));
     R.off[x.c] = off;
     if (x.c == G2 - 1) R.off[G2] = off + cnt;
     R.cslot[x.c] = flag ? cs : -1;
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
       R.ckeys[cs] = int32_t(x.c);
       // placement: slice q of every request's C leaves (Morton order) goes to
       // region q, which the workgroups of XCD q work through
-      const int64_t cn = ((scanned[R.cbase + G2] >> kCntBits) - (s0 >> kCntBits));
+      const int64_t cn = ((scanned[R.cbase + G2] >> cb) - (s0 >> cb));
       const int n = R.sched_n, ns = R.nslices;
       int q = 0;
       while (q + 1 < ns && cn * (q + 1) / ns <= cs) ++q;
@@ -379,13 +381,13 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
   }
 }
 
-hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c,
+hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
                              const int64_t* scanned, const double* bnd_all, const int32_t* cand_all,
                              WorkUnit* wu, int64_t* cost) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
   const int64_t blocks = (waves + kPWaves - 1) / kPWaves;
-  hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c, scanned,
-                     bnd_all, cand_all, wu, cost);
+  hipLaunchKernelGGL(k_prune_fill, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c,
+                     cnt_bits, scanned, bnd_all, cand_all, wu, cost);
   return hipGetLastError();
 }
 

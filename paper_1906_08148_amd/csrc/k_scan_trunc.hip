@@ -6,6 +6,7 @@
 namespace spamm {
 
 constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
+constexpr int64_t kDirectTiles = 1024;  // up to this many tiles, two launches instead of three
 
 // ---------------------------------------------------------------- scan
 
@@ -64,13 +65,30 @@ __global__ void __launch_bounds__(1024) k_scan_top(int64_t* __restrict__ sums, i
   if (threadIdx.x == 0) *total = carry_sh;
 }
 
-// mode 0: out64[i] = exclusive prefix; mode 1: out32[i] = in[i] ? prefix : -1
-template <typename In, int Mode>
+// mode 0: out64[i] = exclusive prefix; mode 1: out32[i] = in[i] ? prefix : -1.
+// Direct (few tiles): each tile adds up the sums of the tiles before it
+// itself (integer sums, exact in any order) and the last tile writes the
+// total, so no separate pass over the tile sums is launched.
+template <typename In, int Mode, bool Direct>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restrict__ in, int64_t count,
                                                             const int64_t* __restrict__ offs,
                                                             int64_t* __restrict__ out64,
-                                                            int32_t* __restrict__ out32) {
+                                                            int32_t* __restrict__ out32,
+                                                            int64_t* __restrict__ total) {
   __shared__ int64_t wtot[kScanThreads / kWave];
+  __shared__ int64_t pre_sh[kScanThreads / kWave];
+  int64_t tile_pre = 0;
+  if constexpr (Direct) {
+    int64_t acc = 0;
+    for (int64_t j = threadIdx.x; j < int64_t(blockIdx.x); j += kScanThreads) acc += offs[j];
+    acc = wave_sum_i64(acc);
+    if (lane_id() == 0) pre_sh[threadIdx.x / kWave] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) tile_pre += pre_sh[w];
+  } else {
+    tile_pre = offs[blockIdx.x];
+  }
   const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
   int64_t vals[kScanItems];
   int64_t local = 0;
@@ -82,7 +100,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
   const int64_t inc = wave_incl_scan(local);
   if (lane_id() == kWave - 1) wtot[threadIdx.x / kWave] = inc;
   __syncthreads();
-  int64_t run = offs[blockIdx.x] + inc - local;
+  int64_t run = tile_pre + inc - local;
   for (int w = 0; w < int(threadIdx.x / kWave); ++w) run += wtot[w];
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + i;
@@ -92,6 +110,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
     }
     run += vals[i];
   }
+  if (Direct && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) *total = run;
 }
 
 size_t scan_scratch_bytes(int64_t count) {
@@ -108,11 +127,16 @@ static hipError_t scan_impl(hipStream_t s, const In* in, int64_t count, int64_t*
   hipLaunchKernelGGL((k_scan_tiles<In>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count, sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (nb <= kDirectTiles) {
+    hipLaunchKernelGGL((k_scan_apply<In, Mode, true>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
+                       sums, out64, out32, total);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_scan_apply<In, Mode>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
-                     sums, out64, out32);
+  hipLaunchKernelGGL((k_scan_apply<In, Mode, false>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
+                     sums, out64, out32, total);
   return hipGetLastError();
 }
 

@@ -117,6 +117,45 @@ def test_all_null_input(ctx):
     assert np.all(ctx.norms(M) == 0.0)
 
 
+def test_deepest_tree_and_batch_limit(ctx):
+    """The deepest quadtree (G = 2048, n = 131072 at leaf 64) with no leaves:
+    one multiply runs and forms nothing; a batch whose packed counts could
+    overflow one int64 is refused before any launch."""
+    import torch
+    print("case: empty G=2048, batch limit", flush=True)
+    e_c = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    e_d = torch.zeros((0, 64, 64), dtype=torch.float64, device="cuda")
+    M = ctx.build_blocks(131072, 64, e_c, e_d, stores=spamm.STORE_F32)
+    assert M.info.G == 2048 and M.info.nonnull == 0
+    p = ctx.multiply(M, M, 1e-6, mode=spamm.SPAMM, prec=spamm.F32)
+    assert p.stats["n_kept"] == 0 and p.stats["c_nonnull"] == 0
+    p.C.release()
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.multiply_batch([dict(A=M, B=M, tau=1e-6, mode=spamm.SPAMM, prec=spamm.F32)] * 16)
+    assert e.value.code == "EUNSUPPORTED"
+    M.release()
+
+
+def test_deepest_tree_with_leaves(ctx):
+    """G = 2048 with an upper bidiagonal of leaves whose norms span three
+    decades: the per-C-leaf scans run over 4 M entries (the multi-pass scan
+    path), and products, bounds and C must match the oracle."""
+    print("case: bidiagonal G=2048 leaf 64", flush=True)
+    rng = np.random.default_rng(11)
+    G, bs = 2048, 64
+    I = np.r_[np.arange(G), np.arange(G - 1)]
+    J = np.r_[np.arange(G), np.arange(1, G)]
+    coords = np.stack([I, J], axis=1).astype(np.int32)
+    scale = 10.0 ** rng.uniform(-3, 0, len(I))
+    data = rng.standard_normal((len(I), bs, bs)) * scale[:, None, None]
+    M = ctx.build_blocks(G * bs, bs, dev(coords), dev(data))
+    T = O.build_from_blocks(G * bs, bs, coords, data)
+    check_norms(ctx, M, T)
+    for mode in MODES:
+        check_product(ctx, M, M, T, T, 1.0, mode, spamm.F32, alias=True)
+    M.release()
+
+
 def test_truncation_drop_set(ctx):
     print("case: truncation", flush=True)
     A = synth.DecaySpec("1d", 4096, 0.2, seed=1).dense()
