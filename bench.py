@@ -74,7 +74,8 @@ def run_step(ctx, dev, prec, keep=False):
     """One pass of the whole path; returns (stats list, products or None)."""
     from paper_1906_08148_amd import spamm
     store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32
-    mats = {a: ctx.build_blocks(N, LEAF, c, d, stores=store) for a, (c, d) in dev.items()}
+    built = ctx.build_blocks_batch([(N, LEAF, c, d) for c, d in dev.values()], stores=store)
+    mats = dict(zip(dev.keys(), built))
     prods = ctx.multiply_batch(requests(mats, prec), stats=True)
     stats = [p.stats for p in prods]
     if keep:

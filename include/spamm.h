@@ -224,6 +224,28 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf,
                                 const double* data, uint32_t stores,
                                 spamm_mat** out);
 
+/* One list of leaf blocks for spamm_build_blocks_batch (the arguments of
+ * spamm_build_blocks). */
+typedef struct spamm_block_list {
+  int64_t n;
+  int32_t leaf;
+  uint32_t stores;
+  int64_t nblocks;
+  const int32_t* coords; /* device, 2 * nblocks */
+  const double* data;    /* device, nblocks * leaf * leaf */
+} spamm_block_list;
+
+/* spamm_build_blocks for `count` lists at once (Sec. 2; Sec. 4.2): each
+ * out[t] equals what spamm_build_blocks returns for lists[t], bit for bit,
+ * but the batch synchronises once for all lists and builds their norm
+ * pyramids in one launch.  The device inputs are read by kernels queued on
+ * the context's stream: keep them unchanged until that stream has passed
+ * this call.  On error (the first failing list's status) no out[t] is
+ * allocated.  Errors: EINVAL, ENONFINITE, ENOMEM, EDEVICE. */
+spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count,
+                                      const spamm_block_list* lists,
+                                      spamm_mat** out);
+
 /* Input truncation with a global Frobenius budget (Sec. 3; the leaf-block
  * form): order the non-null leaves by (squared norm, Morton key) and drop the
  * longest prefix whose summed squared norm is <= tau^2, so that

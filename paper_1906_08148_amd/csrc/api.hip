@@ -298,7 +298,9 @@ std::vector<PyrJob> pyramid_jobs(const std::vector<double*>& norms, const std::v
     jobs[t].L = Ls[t];
     jobs[t].sub_levels = std::min(Ls[t], 5);
     jobs[t].block_base = base;
-    base += int64_t(1) << (2 * (Ls[t] - jobs[t].sub_levels));
+    jobs[t].nsub = int32_t(int64_t(1) << (2 * (Ls[t] - jobs[t].sub_levels)));
+    jobs[t].pad_ = 0;
+    base += jobs[t].nsub;
   }
   return jobs;
 }
@@ -310,11 +312,13 @@ spamm_status pyramids_launch(Ctx* c, const PyrJob* jd, const std::vector<PyrJob>
   return SPAMM_OK;
 }
 
-spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask) {
+// keys: an already filled key region (at least nleaf entries) to adopt
+spamm_status alloc_store(Ctx* c, Store& s, int64_t nleaf, int bs, uint32_t mask, RegionP keys = nullptr) {
   s.nleaf = nleaf;
   s.bs = bs;
   const size_t e2 = size_t(bs) * bs;
-  ALLOC(s.keys, std::max<int64_t>(nleaf, 1) * 4, "leaf keys");
+  if (keys) s.keys = keys;
+  else ALLOC(s.keys, std::max<int64_t>(nleaf, 1) * 4, "leaf keys");
   if (mask & SPAMM_STORE_F64) ALLOC_LEAVES(s.f64, nleaf, e2 * 8, "FP64 leaves");
   if (mask & SPAMM_STORE_F32) ALLOC_LEAVES(s.f32, nleaf, e2 * 4, "FP32 leaves");
   if (mask & SPAMM_STORE_BF16) {
@@ -587,9 +591,10 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   spamm_status st = new_matrix(c, n, leaf, m);
   if (st != SPAMM_OK) return st;
   const int64_t G2 = int64_t(m->G) * m->G;
-  RegionP flag, total, scratch, nf;
+  RegionP flag, total, scratch, nf, keys;
   ALLOC(flag, G2 * 4, "flags");
   ALLOC(nf, 256, "flags");
+  ALLOC(keys, G2 * 4, "leaf keys");
   const size_t sb = scan_scratch_bytes(G2);
   ALLOC(scratch, sb, "scan scratch");
   int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
@@ -598,7 +603,8 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
   SPAMM_HIP(c, launch_build_scan_dense(c->stream, dense, n, ld, leaf, m->G, P<double>(m->norms) + level_offset(m->L),
                                        P<int32_t>(flag), P<int32_t>(nf)));
-  SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), P<int32_t>(keys), tot,
+                                     scratch->ptr(), sb));
   }
   BuildPyr bp;
   st = send_build_pyr(c, *m, bp);
@@ -613,70 +619,121 @@ spamm_status spamm_build(spamm_ctx* ctx, const double* dense, int64_t n, int64_t
   if (hb.nf) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input matrix");
   m->nonnull = hb.total;
   m->store = std::make_shared<Store>();
-  st = alloc_store(c, *m->store, hb.total, leaf, stores);
+  st = alloc_store(c, *m->store, hb.total, leaf, stores, keys);
   if (st != SPAMM_OK) return st;
   TimedScope ts2(c, kTBuild);
-  SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
   SPAMM_HIP(c, launch_copy_dense_leaves(c->stream, dense, n, ld, leaf, hb.total, P<int32_t>(m->store->keys),
                                         P<double>(m->store->f64), P<float>(m->store->f32),
                                         P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
   return finish_build(c, m, out, bp);
 }
 
-spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t nblocks, const int32_t* coords,
-                                const double* data, uint32_t stores, spamm_mat** out) {
-  if (!ctx || !out) return SPAMM_EINVAL;
+spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm_block_list* lists,
+                                      spamm_mat** out) {
+  if (!ctx) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;
-  *out = nullptr;
-  if (n < 1 || !leaf_ok(leaf) || nblocks < 0 || (nblocks > 0 && (!coords || !data)))
-    return fail(c, SPAMM_EINVAL, "bad build_blocks arguments");
-  if (stores == 0 || (stores & ~7u)) return fail(c, SPAMM_EINVAL, "bad store mask");
-  if (nblocks > INT32_MAX) return fail(c, SPAMM_EINVAL, "too many blocks");
-  std::unique_ptr<spamm_mat> m;
-  spamm_status st = new_matrix(c, n, leaf, m);
-  if (st != SPAMM_OK) return st;
-  const int64_t G2 = int64_t(m->G) * m->G;
-  RegionP flag, src, scratch, nf;
-  ALLOC(flag, G2 * 4, "flags");
-  ALLOC(src, G2 * 4, "block index");
-  ALLOC(nf, 256, "flags");
-  const size_t sb = scan_scratch_bytes(G2);
-  ALLOC(scratch, sb, "scan scratch");
-  int64_t* tot = reinterpret_cast<int64_t*>(static_cast<char*>(nf->ptr()) + 64);
-  {
-  TimedScope ts(c, kTBuild);
-  SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(nf), 4));
-  SPAMM_HIP(c, launch_fill_i32(c->stream, P<int32_t>(src), G2, -1));
-  SPAMM_HIP(c, launch_blocks_scatter(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
-                                     P<int32_t>(nf)));
-  SPAMM_HIP(c, launch_blocks_scan(c->stream, n, leaf, m->G, nblocks, coords, data, P<int32_t>(src),
-                                  P<double>(m->norms) + level_offset(m->L), P<int32_t>(flag), P<int32_t>(nf)));
-  SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag), G2, P<int32_t>(m->slot), tot, scratch->ptr(), sb));
+  if (count < 0 || (count > 0 && (!lists || !out))) return fail(c, SPAMM_EINVAL, "bad build_blocks arguments");
+  for (int t = 0; t < count; ++t) out[t] = nullptr;
+  for (int t = 0; t < count; ++t) {
+    const spamm_block_list& b = lists[t];
+    if (b.n < 1 || !leaf_ok(b.leaf) || b.nblocks < 0 || (b.nblocks > 0 && (!b.coords || !b.data)))
+      return fail(c, SPAMM_EINVAL, "bad build_blocks arguments");
+    if (b.stores == 0 || (b.stores & ~7u)) return fail(c, SPAMM_EINVAL, "bad store mask");
+    if (b.nblocks > INT32_MAX) return fail(c, SPAMM_EINVAL, "too many blocks");
   }
-  BuildPyr bp;
-  st = send_build_pyr(c, *m, bp);
-  if (st != SPAMM_OK) return st;
-  struct {
+  if (count == 0) return SPAMM_OK;
+  // per list: leaf norms, null flags, slots and keys; one read-back of every
+  // list's error bits and leaf count; then the leaf copies and one pyramid
+  // launch for all lists
+  struct Hdr {
     int32_t err;
     int32_t pad[15];
     int64_t total;
-  } hb;
-  st = download(c, &hb, nf->ptr(), sizeof(hb));
+    int64_t pad2[7];
+  };
+  static_assert(sizeof(Hdr) == 128, "one header per list");
+  std::vector<std::unique_ptr<spamm_mat>> ms(count);
+  std::vector<RegionP> src(count), keys(count);
+  RegionP hdr;
+  ALLOC(hdr, int64_t(count) * sizeof(Hdr), "build headers");
+  {
+    std::vector<RegionP> flag(count), scratch(count);
+    for (int t = 0; t < count; ++t) {
+      const spamm_block_list& b = lists[t];
+      spamm_status st = new_matrix(c, b.n, b.leaf, ms[t]);
+      if (st != SPAMM_OK) return st;
+      spamm_mat* m = ms[t].get();
+      const int64_t G2 = int64_t(m->G) * m->G;
+      ALLOC(flag[t], G2 * 4, "flags");
+      ALLOC(src[t], G2 * 4, "block index");
+      ALLOC(keys[t], std::max<int64_t>(1, std::min<int64_t>(b.nblocks, G2)) * 4, "leaf keys");  // >= non-null
+      const size_t sb = scan_scratch_bytes(G2);
+      ALLOC(scratch[t], sb, "scan scratch");
+      Hdr* h = P<Hdr>(hdr) + t;
+      TimedScope ts(c, kTBuild);
+      double* leafnorm = P<double>(m->norms) + level_offset(m->L);
+      SPAMM_HIP(c, launch_blocks_init(c->stream, G2, P<int32_t>(src[t]), leafnorm, P<int32_t>(flag[t]), &h->err));
+      SPAMM_HIP(c, launch_blocks_scatter(c->stream, b.n, b.leaf, m->G, b.nblocks, b.coords, b.data,
+                                         P<int32_t>(src[t]), &h->err));
+      SPAMM_HIP(c, launch_blocks_scan(c->stream, b.n, b.leaf, m->G, b.nblocks, b.coords, b.data, P<int32_t>(src[t]),
+                                      leafnorm, P<int32_t>(flag[t]), &h->err));
+      SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag[t]), G2, P<int32_t>(m->slot), P<int32_t>(keys[t]),
+                                         &h->total, scratch[t]->ptr(), sb));
+    }
+  }
+  // the pyramid job table goes out while those kernels run
+  TableSet pt;
+  std::vector<PyrJob> pjobs;
+  {
+    std::vector<double*> nv;
+    std::vector<int> lv;
+    for (auto& m : ms) {
+      nv.push_back(P<double>(m->norms));
+      lv.push_back(m->L);
+    }
+    pjobs = pyramid_jobs(nv, lv);
+  }
+  const size_t po = pt.add(pjobs);
+  spamm_status st = send_tables(c, pt);
   if (st != SPAMM_OK) return st;
-  if (hb.err & 1) return fail(c, SPAMM_EINVAL, "block coordinate outside the matrix");
-  if (hb.err & 2) return fail(c, SPAMM_EINVAL, "block coordinate listed twice");
-  if (hb.err & 4) return fail(c, SPAMM_EINVAL, "non-zero entry past row/column n");
-  if (hb.err & 8) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input blocks");
-  m->nonnull = hb.total;
-  m->store = std::make_shared<Store>();
-  st = alloc_store(c, *m->store, hb.total, leaf, stores);
+  std::vector<Hdr> hb(count);
+  st = download(c, hb.data(), hdr->ptr(), int64_t(count) * sizeof(Hdr));
   if (st != SPAMM_OK) return st;
-  TimedScope ts2(c, kTBuild);
-  SPAMM_HIP(c, launch_slot_keys(c->stream, P<int32_t>(m->slot), G2, P<int32_t>(m->store->keys)));
-  SPAMM_HIP(c, launch_copy_block_leaves(c->stream, n, leaf, hb.total, P<int32_t>(m->store->keys), P<int32_t>(src),
-                                        data, P<double>(m->store->f64), P<float>(m->store->f32),
-                                        P<uint16_t>(m->store->bf16), P<uint16_t>(m->store->bf16t)));
-  return finish_build(c, m, out, bp);
+  for (int t = 0; t < count; ++t) {
+    const int32_t e = hb[t].err;
+    if (e & 1) return fail(c, SPAMM_EINVAL, "block coordinate outside the matrix");
+    if (e & 2) return fail(c, SPAMM_EINVAL, "block coordinate listed twice");
+    if (e & 4) return fail(c, SPAMM_EINVAL, "non-zero entry past row/column n");
+    if (e & 8) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input blocks");
+  }
+  for (int t = 0; t < count; ++t) {
+    const spamm_block_list& b = lists[t];
+    spamm_mat* m = ms[t].get();
+    m->nonnull = hb[t].total;
+    m->store = std::make_shared<Store>();
+    st = alloc_store(c, *m->store, hb[t].total, b.leaf, b.stores, keys[t]);
+    if (st != SPAMM_OK) return st;
+    TimedScope ts2(c, kTBuild);
+    SPAMM_HIP(c, launch_copy_block_leaves(c->stream, b.n, b.leaf, hb[t].total, P<int32_t>(m->store->keys),
+                                          P<int32_t>(src[t]), b.data, P<double>(m->store->f64),
+                                          P<float>(m->store->f32), P<uint16_t>(m->store->bf16),
+                                          P<uint16_t>(m->store->bf16t)));
+  }
+  st = pyramids_launch(c, pt.at<PyrJob>(po), pjobs);
+  if (st != SPAMM_OK) return st;
+  for (int t = 0; t < count; ++t) {
+    c->live_handles++;
+    out[t] = ms[t].release();
+  }
+  return SPAMM_OK;
+}
+
+spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t nblocks, const int32_t* coords,
+                                const double* data, uint32_t stores, spamm_mat** out) {
+  if (!ctx || !out) return SPAMM_EINVAL;
+  *out = nullptr;
+  const spamm_block_list b{n, leaf, stores, nblocks, coords, data};
+  return spamm_build_blocks_batch(ctx, 1, &b, out);
 }
 
 spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out, double* dropped_sq) {

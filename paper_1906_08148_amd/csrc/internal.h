@@ -199,6 +199,8 @@ struct PyrJob {
   int32_t L;
   int32_t sub_levels;   // levels reduced inside one subtree workgroup
   int64_t block_base;   // first workgroup index of this job
+  int32_t nsub;         // subtree workgroups of this job
+  int32_t pad_;
 };
 
 // One multiply request inside a batch.
@@ -328,16 +330,19 @@ hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n
 hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
                                  const int32_t* coords, const double* data, int32_t* src_of,
                                  int32_t* errflags);
+// src_of[] = -1, leafnorm[] = 0, flag[] = 0 over G2 entries and err[0..3] = 0
+hipError_t launch_blocks_init(hipStream_t s, int64_t G2, int32_t* src_of, double* leafnorm, int32_t* flag,
+                              int32_t* err);
 hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
                               const int32_t* coords, const double* data, const int32_t* src_of,
                               double* leafnorm, int32_t* flag, int32_t* errflags);
-// exclusive scan of int32 flags -> slot map (flag ? prefix : -1), total -> *total
-hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count,
-                                 int32_t* slot, int64_t* total, void* scratch, size_t scratch_bytes);
+// exclusive scan of int32 flags -> slot map (flag ? prefix : -1) and its
+// inverse keys[slot] = index (keys may be null), total -> *total
+hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot,
+                                 int32_t* keys, int64_t* total, void* scratch, size_t scratch_bytes);
 size_t scan_scratch_bytes(int64_t count);
 hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t count,
                            void* scratch, size_t scratch_bytes);  // exclusive, out[count] = total
-hipError_t launch_slot_keys(hipStream_t s, const int32_t* slot, int64_t G2, int32_t* keys);
 hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                     int bs, int64_t nleaf, const int32_t* keys, double* f64,
                                     float* f32, uint16_t* b16, uint16_t* b16t);

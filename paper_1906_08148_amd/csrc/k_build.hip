@@ -100,11 +100,21 @@ hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_
   return hipGetLastError();
 }
 
-__global__ void k_blocks_zero(int64_t G2, double* __restrict__ leafnorm, int32_t* __restrict__ flag) {
+__global__ void k_blocks_init(int64_t G2, int32_t* __restrict__ src_of, double* __restrict__ leafnorm,
+                              int32_t* __restrict__ flag, int32_t* __restrict__ err) {
   const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m < 4) err[m] = 0;
   if (m >= G2) return;
+  src_of[m] = -1;
   leafnorm[m] = 0.0;
   flag[m] = 0;
+}
+
+hipError_t launch_blocks_init(hipStream_t s, int64_t G2, int32_t* src_of, double* leafnorm, int32_t* flag,
+                              int32_t* err) {
+  hipLaunchKernelGGL(k_blocks_init, dim3(uint32_t((std::max<int64_t>(G2, 4) + 255) / 256)), dim3(256), 0, s, G2,
+                     src_of, leafnorm, flag, err);
+  return hipGetLastError();
 }
 
 // One workgroup per listed block (the one that won its Morton slot).
@@ -164,10 +174,8 @@ __global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, int64_t 
 hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks, const int32_t* coords,
                               const double* data, const int32_t* src_of, double* leafnorm, int32_t* flag,
                               int32_t* errflags) {
-  const int64_t G2 = int64_t(G) * G;
-  hipLaunchKernelGGL(k_blocks_zero, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G2, leafnorm, flag);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nblocks == 0) return e;
+  (void)G;
+  if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_blocks_scan, dim3(uint32_t(nblocks)), dim3(256), 0, s, n, bs, nblocks, coords, data, src_of,
                      leafnorm, flag, errflags);
   return hipGetLastError();
@@ -175,17 +183,6 @@ hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t n
 
 // ---------------------------------------------------------------- compaction
 
-__global__ void k_slot_keys(const int32_t* __restrict__ slot, int64_t G2, int32_t* __restrict__ keys) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= G2) return;
-  const int32_t sl = slot[m];
-  if (sl >= 0) keys[sl] = int32_t(m);
-}
-
-hipError_t launch_slot_keys(hipStream_t s, const int32_t* slot, int64_t G2, int32_t* keys) {
-  hipLaunchKernelGGL(k_slot_keys, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, slot, G2, keys);
-  return hipGetLastError();
-}
 
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
@@ -342,34 +339,38 @@ __device__ __forceinline__ int find_prep(const PrepJob* __restrict__ jobs, int n
   return lo;
 }
 
-__global__ void k_prep(const PrepJob* __restrict__ jobs, int njobs, int64_t total) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const PrepJob& J = jobs[find_prep(jobs, njobs, g, false)];
-  const int64_t m = g - J.base;
-  const int G = J.G;
-  uint32_t r, c;
-  demorton(uint32_t(m), r, c);
-  const int32_t sl = J.slot[m];
-  const double v = sl >= 0 ? sqrt(J.leafnorm[m]) : -1.0;
-  J.rm_sqrt[int64_t(r) * G + c] = v;
-  J.rm_slot[int64_t(r) * G + c] = sl;
-  J.cm_sqrt[int64_t(c) * G + r] = v;
-  J.cm_slot[int64_t(c) * G + r] = sl;
-}
-
-__global__ void __launch_bounds__(256) k_ranges(const PrepJob* __restrict__ jobs, int njobs, int64_t total_waves) {
-  const int64_t w = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+// One launch: the first nb_prep workgroups write the row-major and
+// column-major views (one entry per thread); the others find, one wave per
+// row or column, the k range of its non-null leaves from the slot map.
+__global__ void __launch_bounds__(256) k_prep(const PrepJob* __restrict__ jobs, int njobs, int64_t total,
+                                              int64_t total_waves, int64_t nb_prep) {
+  if (int64_t(blockIdx.x) < nb_prep) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const PrepJob& J = jobs[find_prep(jobs, njobs, g, false)];
+    const int64_t m = g - J.base;
+    const int G = J.G;
+    uint32_t r, c;
+    demorton(uint32_t(m), r, c);
+    const int32_t sl = J.slot[m];
+    const double v = sl >= 0 ? sqrt(J.leafnorm[m]) : -1.0;
+    J.rm_sqrt[int64_t(r) * G + c] = v;
+    J.rm_slot[int64_t(r) * G + c] = sl;
+    J.cm_sqrt[int64_t(c) * G + r] = v;
+    J.cm_slot[int64_t(c) * G + r] = sl;
+    return;
+  }
+  const int64_t w = (int64_t(blockIdx.x) - nb_prep) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (w >= total_waves) return;
   const PrepJob& J = jobs[find_prep(jobs, njobs, w, true)];
   const int G = J.G;
   const int64_t lw = w - J.wbase;
   const bool is_col = lw >= G;
-  const int idx = int(is_col ? lw - G : lw);
-  const double* v = (is_col ? J.cm_sqrt : J.rm_sqrt) + int64_t(idx) * G;
+  const uint32_t idx = uint32_t(is_col ? lw - G : lw);
   int lo = G, hi = -1;
   for (int k = lane_id(); k < G; k += kWave) {
-    if (v[k] >= 0.0) {
+    const uint32_t m = is_col ? morton(uint32_t(k), idx) : morton(idx, uint32_t(k));
+    if (J.slot[m] >= 0) {
       lo = min(lo, k);
       hi = max(hi, k);
     }
@@ -387,10 +388,9 @@ __global__ void __launch_bounds__(256) k_ranges(const PrepJob* __restrict__ jobs
 
 hipError_t launch_prep_batch(hipStream_t s, const PrepJob* jobs, int njobs, int64_t total, int64_t total_waves) {
   if (njobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(uint32_t((total + 255) / 256)), dim3(256), 0, s, jobs, njobs, total);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ranges, dim3(uint32_t((total_waves + 3) / 4)), dim3(256), 0, s, jobs, njobs, total_waves);
+  const int64_t nb_prep = (total + 255) / 256, nb_rng = (total_waves + 3) / 4;
+  hipLaunchKernelGGL(k_prep, dim3(uint32_t(nb_prep + nb_rng)), dim3(256), 0, s, jobs, njobs, total, total_waves,
+                     nb_prep);
   return hipGetLastError();
 }
 
@@ -449,14 +449,21 @@ __global__ void __launch_bounds__(256) k_pyr_top(const PyrJob* __restrict__ jobs
   pyr_reduce_lds(lds, top, job.norms, top, 0);
 }
 
-hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs,
-                          const std::vector<PyrJob>& jobs_host) {
+// Subtrees of sub_levels levels, one workgroup each, then the levels above
+// them, one workgroup per job (a second launch: a cross-workgroup handoff
+// inside one launch would need device-scope fences, which write back the
+// XCD's L2 and cost more than the launch).
+hipError_t launch_pyramid(hipStream_t s, const PyrJob* jobs_dev, int njobs, const std::vector<PyrJob>& jobs_host) {
   if (njobs == 0) return hipSuccess;
   int64_t blocks = 0;
-  for (auto& jb : jobs_host) blocks += int64_t(1) << (2 * (jb.L - jb.sub_levels));
+  bool any_top = false;
+  for (auto& jb : jobs_host) {
+    blocks += jb.nsub;
+    any_top |= jb.L > jb.sub_levels;
+  }
   hipLaunchKernelGGL(k_pyr_sub, dim3(uint32_t(blocks)), dim3(256), 0, s, jobs_dev, njobs);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !any_top) return e;
   hipLaunchKernelGGL(k_pyr_top, dim3(uint32_t(njobs)), dim3(256), 0, s, jobs_dev);
   return hipGetLastError();
 }

@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(1024) k_scan_top(int64_t* __restrict__ sums, i
   if (threadIdx.x == 0) *total = carry_sh;
 }
 
-// mode 0: out64[i] = exclusive prefix; mode 1: out32[i] = in[i] ? prefix : -1.
+// mode 0: out64[i] = exclusive prefix; mode 1: out32[i] = in[i] ? prefix : -1
+// and, with keys, keys[prefix] = i for the flagged i (the inverse map).
 // Direct (few tiles): each tile adds up the sums of the tiles before it
 // itself (integer sums, exact in any order) and the last tile writes the
 // total, so no separate pass over the tile sums is launched.
@@ -74,6 +75,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
                                                             const int64_t* __restrict__ offs,
                                                             int64_t* __restrict__ out64,
                                                             int32_t* __restrict__ out32,
+                                                            int32_t* __restrict__ keys,
                                                             int64_t* __restrict__ total) {
   __shared__ int64_t wtot[kScanThreads / kWave];
   __shared__ int64_t pre_sh[kScanThreads / kWave];
@@ -105,8 +107,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + i;
     if (idx < count) {
-      if (Mode == 0) out64[idx] = run;
-      else out32[idx] = vals[i] ? int32_t(run) : -1;
+      if (Mode == 0) {
+        out64[idx] = run;
+      } else {
+        out32[idx] = vals[i] ? int32_t(run) : -1;
+        if (keys && vals[i]) keys[run] = int32_t(idx);
+      }
     }
     run += vals[i];
   }
@@ -120,7 +126,7 @@ size_t scan_scratch_bytes(int64_t count) {
 
 template <typename In, int Mode>
 static hipError_t scan_impl(hipStream_t s, const In* in, int64_t count, int64_t* out64, int32_t* out32,
-                            int64_t* total, void* scratch, size_t scratch_bytes) {
+                            int32_t* keys, int64_t* total, void* scratch, size_t scratch_bytes) {
   const int64_t nb = std::max<int64_t>(1, (count + kScanTile - 1) / kScanTile);
   if (scratch_bytes < size_t(nb * sizeof(int64_t))) return hipErrorInvalidValue;
   int64_t* sums = static_cast<int64_t*>(scratch);
@@ -129,25 +135,25 @@ static hipError_t scan_impl(hipStream_t s, const In* in, int64_t count, int64_t*
   if (e != hipSuccess) return e;
   if (nb <= kDirectTiles) {
     hipLaunchKernelGGL((k_scan_apply<In, Mode, true>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
-                       sums, out64, out32, total);
+                       sums, out64, out32, keys, total);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_scan_apply<In, Mode, false>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
-                     sums, out64, out32, total);
+                     sums, out64, out32, keys, total);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t count, void* scratch,
                            size_t scratch_bytes) {
-  return scan_impl<int64_t, 0>(s, in, count, out, nullptr, out + count, scratch, scratch_bytes);
+  return scan_impl<int64_t, 0>(s, in, count, out, nullptr, nullptr, out + count, scratch, scratch_bytes);
 }
 
-hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot,
+hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot, int32_t* keys,
                                  int64_t* total, void* scratch, size_t scratch_bytes) {
-  return scan_impl<int32_t, 1>(s, flag, count, nullptr, slot, total, scratch, scratch_bytes);
+  return scan_impl<int32_t, 1>(s, flag, count, nullptr, slot, keys, total, scratch, scratch_bytes);
 }
 
 // ---------------------------------------------------------------- truncation
@@ -399,7 +405,7 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   hipLaunchKernelGGL(k_trunc_flag, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan_impl<int32_t, 0>(s, flag, total, pos, nullptr, pos + total, p, scan_scratch_bytes(total));
+  e = scan_impl<int32_t, 0>(s, flag, total, pos, nullptr, nullptr, pos + total, p, scan_scratch_bytes(total));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_trunc_compact, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, pos, cs, cm);
   hipLaunchKernelGGL(k_trunc_fx, dim3(uint32_t(njobs) * kSelSplit), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx);

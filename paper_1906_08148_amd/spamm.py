@@ -45,6 +45,18 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# The same two records as numpy dtypes (C layout), so that a whole batch is
+# marshalled with one array conversion instead of per-field ctypes access.
+STATS_DTYPE = np.dtype([(k, np.int64 if t is ctypes.c_int64 else np.float64) for k, t in Stats._fields_])
+REQUEST_DTYPE = np.dtype([("A", np.uintp), ("B", np.uintp), ("tau", np.float64), ("mode", np.int32),
+                          ("prec", np.int32), ("ep", np.uintp)], align=True)
+
+
+class BlockList(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("leaf", ctypes.c_int32), ("stores", ctypes.c_uint32),
+                ("nblocks", ctypes.c_int64), ("coords", ctypes.c_void_p), ("data", ctypes.c_void_p)]
+
+
 class Epilogue(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("D", ctypes.c_void_p)]
 
@@ -52,6 +64,9 @@ class Epilogue(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("tau", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("prec", ctypes.c_int32), ("ep", ctypes.c_void_p)]
+
+
+assert REQUEST_DTYPE.itemsize == ctypes.sizeof(Request) and STATS_DTYPE.itemsize == ctypes.sizeof(Stats)
 
 
 class MatInfo(ctypes.Structure):
@@ -97,8 +112,10 @@ _SIGS = {
     "spamm_multiply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]),
-    "spamm_multiply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Request),
-                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]),
+    "spamm_build_blocks_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.POINTER(ctypes.c_void_p)]),
+    "spamm_multiply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
     "spamm_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "spamm_kept": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -171,6 +188,11 @@ class Matrix:
                 self.release()
         except Exception:
             pass
+
+
+def _hval(m: Matrix) -> int:
+    """The handle's address (0 for a released matrix, which the library rejects)."""
+    return (m.handle.value or 0) if m.handle is not None else 0
 
 
 @dataclass
@@ -247,6 +269,21 @@ class Context:
                                             ctypes.byref(out)))
         return Matrix(self, out.value)
 
+    def build_blocks_batch(self, lists, stores: int = STORE_F64 | STORE_F32):
+        """Several block-list builds with one synchronisation: `lists` holds
+        (n, leaf, coords, data) tuples as for build_blocks."""
+        import torch
+        k = len(lists)
+        arr = (BlockList * k)()
+        for i, (n, leaf, coords, data) in enumerate(lists):
+            assert coords.dtype == torch.int32 and coords.is_cuda and coords.is_contiguous()
+            assert data.dtype == torch.float64 and data.is_cuda and data.is_contiguous()
+            m = coords.shape[0]
+            arr[i] = BlockList(n, leaf, stores, m, coords.data_ptr() if m else 0, data.data_ptr() if m else 0)
+        outs = (ctypes.c_void_p * k)()
+        self._check(_lib.spamm_build_blocks_batch(self.ptr, k, arr, outs))
+        return [Matrix(self, outs[i]) for i in range(k)]
+
     # ---- truncation / multiply
     def truncate(self, m: Matrix, tau: float):
         out = ctypes.c_void_p()
@@ -261,31 +298,28 @@ class Context:
 
     def multiply_batch(self, reqs, stats: bool = True):
         n = len(reqs)
-        arr = (Request * n)()
-        eps = []
-        for i, r in enumerate(reqs):
+        rows = []
+        eps = []  # epilogue records stay alive until the call returns
+        for r in reqs:
             mode = MODES.get(r.get("mode"), r.get("mode", SPAMM))
             prec = PRECS.get(r.get("prec"), r.get("prec", F32))
-            arr[i].A = r["A"].handle
-            arr[i].B = r["B"].handle
-            arr[i].tau = float(r["tau"])
-            arr[i].mode = int(mode)
-            arr[i].prec = int(prec)
+            ep = 0
             if r.get("alpha") is not None or r.get("beta") is not None or r.get("D") is not None:
-                ep = Epilogue(1.0 if r.get("alpha") is None else float(r["alpha"]),
-                              0.0 if r.get("beta") is None else float(r["beta"]),
-                              r["D"].handle if r.get("D") is not None else None)
-                eps.append(ep)
-                arr[i].ep = ctypes.cast(ctypes.pointer(ep), ctypes.c_void_p)
-            else:
-                arr[i].ep = None
+                e = Epilogue(1.0 if r.get("alpha") is None else float(r["alpha"]),
+                             0.0 if r.get("beta") is None else float(r["beta"]),
+                             r["D"].handle if r.get("D") is not None else None)
+                eps.append(e)
+                ep = ctypes.addressof(e)
+            rows.append((_hval(r["A"]), _hval(r["B"]), float(r["tau"]), int(mode), int(prec), ep))
+        arr = np.array(rows, dtype=REQUEST_DTYPE)
         outs = (ctypes.c_void_p * n)()
-        st = (Stats * n)() if stats else None
-        self._check(_lib.spamm_multiply_batch(self.ptr, n, arr, outs, st))
-        res = []
-        for i in range(n):
-            res.append(Product(Matrix(self, outs[i]), st[i].as_dict() if stats else None))
-        return res
+        st = np.zeros(n, dtype=STATS_DTYPE) if stats else None
+        self._check(_lib.spamm_multiply_batch(self.ptr, n, arr.ctypes.data_as(ctypes.c_void_p), outs,
+                                              st.ctypes.data_as(ctypes.c_void_p) if stats else None))
+        if not stats:
+            return [Product(Matrix(self, outs[i]), None) for i in range(n)]
+        names = STATS_DTYPE.names
+        return [Product(Matrix(self, outs[i]), dict(zip(names, row))) for i, row in enumerate(st.tolist())]
 
     # ---- read-back
     def norms(self, m: Matrix, level: int = -1) -> np.ndarray:

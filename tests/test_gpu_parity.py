@@ -91,6 +91,30 @@ def test_block_list_build_matches_dense_build(ctx):
         check_product(ctx, Mb, Mb, T, T, 1e-6, mode, spamm.F32, alias=True)
 
 
+def test_block_list_batch_build(ctx):
+    """Several lists in one call give the same matrices, bit for bit, as one
+    call per list; an error in any list fails the whole call."""
+    import torch
+    print("case: batched block build", flush=True)
+    lists = []
+    for n, bs, a, seed in ((3000, 64, 0.2, 3), (2048, 32, 0.5, 4), (700, 16, 0.3, 5)):
+        c, d = synth.DecaySpec("1d", n, a, seed=seed).leaf_blocks(bs)
+        lists.append((n, bs, dev(c.astype(np.int32)), dev(d)))
+    Ms = ctx.build_blocks_batch(lists)
+    for (n, bs, c, d), M in zip(lists, Ms):
+        S = ctx.build_blocks(n, bs, c, d)
+        assert M.info.nonnull == S.info.nonnull and M.info.G == S.info.G
+        assert np.array_equal(ctx.norms(M), ctx.norms(S))
+        assert torch.equal(ctx.to_dense(M), ctx.to_dense(S))
+        S.release()
+        M.release()
+    dup = lists[1][2].clone()
+    dup[1] = dup[0]
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.build_blocks_batch([lists[0], (lists[1][0], lists[1][1], dup, lists[1][3])])
+    assert e.value.code == "EINVAL"
+
+
 def test_tau_zero_and_huge(ctx):
     print("case: tau 0 / huge", flush=True)
     A = sparse_random(400, 32, 0.4, 8)
