@@ -37,6 +37,28 @@ void* Ctx::stage(size_t bytes) {
   return host_stage;
 }
 
+bool Ctx::results(size_t bytes) {
+  if (bytes <= res_bytes) return true;
+  if (res_host) {  // kernels of earlier calls may still write the old buffer
+    if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    (void)hipHostFree(res_host);
+  }
+  res_host = res_dev = nullptr;
+  res_bytes = 0;
+  const size_t want = std::max<size_t>((bytes + 4095) / 4096 * 4096, size_t(1) << 20);
+  void* h = nullptr;
+  if (hipHostMalloc(&h, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return false;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+    (void)hipHostFree(h);
+    return false;
+  }
+  res_host = static_cast<char*>(h);
+  res_dev = static_cast<char*>(d);
+  res_bytes = want;
+  return true;
+}
+
 hipEvent_t Ctx::get_event() {
   if (!event_pool.empty()) {
     hipEvent_t e = event_pool.back();
@@ -502,6 +524,7 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
   if (c->up_ring) (void)hipHostFree(c->up_ring);
   if (c->host_stage) (void)hipHostFree(c->host_stage);
+  if (c->res_host) (void)hipHostFree(c->res_host);
   delete ctx;
   return SPAMM_OK;
 }
@@ -903,14 +926,19 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     if (cnt_bits + c_bits > 62)
       return fail(c, SPAMM_EUNSUPPORTED, "batch too large for one counting pass; split it");
   }
-  RegionP packed, scanned, bnd_all, cand_all, scan_scr, totals;
+  // per-request totals and statistics come back through mapped host memory
+  const size_t res_tot = (size_t(count) * sizeof(ReqTotals) + 255) / 256 * 256;
+  if (!c->results(res_tot + size_t(count) * sizeof(ReqStatsDev)))
+    return fail(c, SPAMM_EDEVICE, "hipHostMalloc of the result buffer failed");
+  ReqTotals* totals_h = reinterpret_cast<ReqTotals*>(c->res_host);
+  ReqTotals* totals_d = reinterpret_cast<ReqTotals*>(c->res_dev);
+  RegionP packed, scanned, bnd_all, cand_all, scan_scr;
   ALLOC(packed, total_c * 8, "counts");
   ALLOC(scanned, (total_c + 1) * 8, "offsets");
   ALLOC(bnd_all, total_c * 8, "bounds");
   ALLOC(cand_all, total_c * 4, "candidates");
   const size_t ssb = scan_scratch_bytes(total_c);
   ALLOC(scan_scr, ssb, "scan scratch");
-  ALLOC(totals, count * sizeof(ReqTotals), "totals");
   TableSet pre;
   const size_t o_tj = pre.add(tplan.jobs), o_tp = pre.add(tplan.pyr), o_pj = pre.add(pplan.jobs),
                o_rd = pre.add(rd);
@@ -926,11 +954,10 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   SPAMM_HIP(c, launch_prune_count(c->stream, rd0, count, total_c, cnt_bits, P<int64_t>(packed), P<double>(bnd_all),
                                   P<int32_t>(cand_all)));
   SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
-  SPAMM_HIP(c, launch_gather_totals(c->stream, rd0, count, cnt_bits, P<int64_t>(scanned), P<ReqTotals>(totals)));
+  SPAMM_HIP(c, launch_gather_totals(c->stream, rd0, count, cnt_bits, P<int64_t>(scanned), totals_d));
   }
-  std::vector<ReqTotals> ht(count);
-  st = download(c, ht.data(), totals->ptr(), count * sizeof(ReqTotals));
-  if (st != SPAMM_OK) return st;
+  SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+  const std::vector<ReqTotals> ht(totals_h, totals_h + count);
 
   // ---- allocate results; work units grouped by (precision, leaf size)
   std::vector<std::unique_ptr<spamm_mat>> Cs(count);
@@ -1111,11 +1138,10 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   if (st != SPAMM_OK) return st;
   const ReqDev* reqd = postt.at<ReqDev>(o_req);
   const PyrJob* pyr_jd = postt.at<PyrJob>(o_pyr);
-  RegionP sd, part;
-  if (st_out) {
-    ALLOC(sd, count * sizeof(ReqStatsDev), "stats");
-    ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
-  }
+  RegionP part;
+  ReqStatsDev* sd_dev = reinterpret_cast<ReqStatsDev*>(c->res_dev + res_tot);
+  const ReqStatsDev* sd_host = reinterpret_cast<const ReqStatsDev*>(c->res_host + res_tot);
+  if (st_out) ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
   auto post = [&]() -> spamm_status {
     {
       TimedScope ts(c, kTPrune);
@@ -1170,7 +1196,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     if (s2 != SPAMM_OK) return s2;
     if (st_out)
       SPAMM_HIP(c, launch_req_stats(c->stream, reqd, count, total_chunks, P<StatPartial>(part),
-                                    P<ReqStatsDev>(sd)));
+                                    sd_dev));
     return SPAMM_OK;
   };
   if (c->use_graph && !c->timing) {
@@ -1212,11 +1238,10 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     if (st != SPAMM_OK) return st;
   }
 
-  // ---- statistics (one copy back for the whole batch)
+  // ---- statistics (written by the kernel into mapped host memory)
   if (st_out) {
-    std::vector<ReqStatsDev> hs(count);
-    st = download(c, hs.data(), sd->ptr(), count * sizeof(ReqStatsDev));
-    if (st != SPAMM_OK) return st;
+    SPAMM_HIP(c, hipStreamSynchronize(c->stream));
+    const std::vector<ReqStatsDev> hs(sd_host, sd_host + count);
     for (int r = 0; r < count; ++r) {
       const spamm_request& q = reqs[r];
       spamm_stats& o = st_out[r];

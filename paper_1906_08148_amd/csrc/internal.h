@@ -140,8 +140,14 @@ struct Ctx {
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
   int live_handles = 0;
+  // results that kernels write straight into host memory (mapped pinned,
+  // coherent): read by the host after a stream synchronisation
+  char* res_host = nullptr;
+  char* res_dev = nullptr;
+  size_t res_bytes = 0;
   RegionP alloc(size_t bytes, size_t align = 256);  // nullptr on exhaustion
   void* stage(size_t bytes);      // grow pinned staging if needed
+  bool results(size_t bytes);     // res_* holds at least `bytes` (synchronises to grow)
 };
 
 // Records events around the launches of one kernel class while timing is on.

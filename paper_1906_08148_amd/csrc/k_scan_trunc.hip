@@ -10,15 +10,27 @@ constexpr int64_t kDirectTiles = 1024;  // up to this many tiles, two launches i
 
 // ---------------------------------------------------------------- scan
 
+// Scan inputs are read through a source functor (element i -> int64 value)
+// and every element's exclusive prefix may also go to a sink functor, so that
+// a producer or a consumer pass can ride along with the scan's own launches.
 template <typename In>
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const In* __restrict__ in, int64_t count,
+struct ArraySrc {
+  const In* p;
+  __device__ int64_t operator()(int64_t i) const { return int64_t(p[i]); }
+};
+struct NoSink {
+  __device__ void operator()(int64_t, int64_t, int64_t) const {}
+};
+
+template <typename Src>
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const Src src, int64_t count,
                                                             int64_t* __restrict__ sums) {
   __shared__ int64_t red[kScanThreads / kWave];
   const int64_t base = int64_t(blockIdx.x) * kScanTile;
   int64_t v = 0;
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + int64_t(i) * kScanThreads + threadIdx.x;
-    if (idx < count) v += int64_t(in[idx]);
+    if (idx < count) v += src(idx);
   }
   v = wave_sum_i64(v);
   if (lane_id() == 0) red[threadIdx.x / kWave] = v;
@@ -70,13 +82,13 @@ __global__ void __launch_bounds__(1024) k_scan_top(int64_t* __restrict__ sums, i
 // Direct (few tiles): each tile adds up the sums of the tiles before it
 // itself (integer sums, exact in any order) and the last tile writes the
 // total, so no separate pass over the tile sums is launched.
-template <typename In, int Mode, bool Direct>
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restrict__ in, int64_t count,
+template <typename Src, int Mode, bool Direct, typename Sink>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const Src src, int64_t count,
                                                             const int64_t* __restrict__ offs,
                                                             int64_t* __restrict__ out64,
                                                             int32_t* __restrict__ out32,
                                                             int32_t* __restrict__ keys,
-                                                            int64_t* __restrict__ total) {
+                                                            int64_t* __restrict__ total, const Sink sink) {
   __shared__ int64_t wtot[kScanThreads / kWave];
   __shared__ int64_t pre_sh[kScanThreads / kWave];
   int64_t tile_pre = 0;
@@ -96,7 +108,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
   int64_t local = 0;
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t idx = base + i;
-    vals[i] = idx < count ? int64_t(in[idx]) : 0;
+    vals[i] = idx < count ? src(idx) : 0;
     local += vals[i];
   }
   const int64_t inc = wave_incl_scan(local);
@@ -113,6 +125,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const In* __restric
         out32[idx] = vals[i] ? int32_t(run) : -1;
         if (keys && vals[i]) keys[run] = int32_t(idx);
       }
+      sink(idx, vals[i], run);
     }
     run += vals[i];
   }
@@ -124,36 +137,37 @@ size_t scan_scratch_bytes(int64_t count) {
   return size_t((nb + 1) * sizeof(int64_t) + 256);
 }
 
-template <typename In, int Mode>
-static hipError_t scan_impl(hipStream_t s, const In* in, int64_t count, int64_t* out64, int32_t* out32,
-                            int32_t* keys, int64_t* total, void* scratch, size_t scratch_bytes) {
+template <int Mode, typename Src, typename Sink = NoSink>
+static hipError_t scan_impl(hipStream_t s, const Src in, int64_t count, int64_t* out64, int32_t* out32,
+                            int32_t* keys, int64_t* total, void* scratch, size_t scratch_bytes,
+                            const Sink sink = Sink()) {
   const int64_t nb = std::max<int64_t>(1, (count + kScanTile - 1) / kScanTile);
   if (scratch_bytes < size_t(nb * sizeof(int64_t))) return hipErrorInvalidValue;
   int64_t* sums = static_cast<int64_t*>(scratch);
-  hipLaunchKernelGGL((k_scan_tiles<In>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count, sums);
+  hipLaunchKernelGGL((k_scan_tiles<Src>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count, sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nb <= kDirectTiles) {
-    hipLaunchKernelGGL((k_scan_apply<In, Mode, true>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
-                       sums, out64, out32, keys, total);
+    hipLaunchKernelGGL((k_scan_apply<Src, Mode, true, Sink>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in,
+                       count, sums, out64, out32, keys, total, sink);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_scan_apply<In, Mode, false>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in, count,
-                     sums, out64, out32, keys, total);
+  hipLaunchKernelGGL((k_scan_apply<Src, Mode, false, Sink>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in,
+                     count, sums, out64, out32, keys, total, sink);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64_t count, void* scratch,
                            size_t scratch_bytes) {
-  return scan_impl<int64_t, 0>(s, in, count, out, nullptr, nullptr, out + count, scratch, scratch_bytes);
+  return scan_impl<0>(s, ArraySrc<int64_t>{in}, count, out, nullptr, nullptr, out + count, scratch, scratch_bytes);
 }
 
 hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot, int32_t* keys,
                                  int64_t* total, void* scratch, size_t scratch_bytes) {
-  return scan_impl<int32_t, 1>(s, flag, count, nullptr, slot, keys, total, scratch, scratch_bytes);
+  return scan_impl<1>(s, ArraySrc<int32_t>{flag}, count, nullptr, slot, keys, total, scratch, scratch_bytes);
 }
 
 // ---------------------------------------------------------------- truncation
@@ -186,24 +200,30 @@ __device__ __forceinline__ bool key_le(uint64_t sb, uint32_t m, uint64_t khi, ui
   return sb < khi || (sb == khi && m <= klo);
 }
 
-__global__ void k_trunc_flag(const TruncJob* __restrict__ jobs, int njobs, int64_t total, int32_t* __restrict__ flag) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const TruncJob& J = jobs[find_job(jobs, njobs, g)];
-  const int64_t m = g - J.base;
-  flag[g] = (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
-}
-
-__global__ void k_trunc_compact(const TruncJob* __restrict__ jobs, int njobs, int64_t total,
-                                const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
-                                double* __restrict__ cs, int32_t* __restrict__ cm) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= total || !flag[g]) return;
-  const TruncJob& J = jobs[find_job(jobs, njobs, g)];
-  const int64_t m = g - J.base;
-  cs[pos[g]] = J.leafnorm[m];
-  cm[pos[g]] = int32_t(m);
-}
+// Candidates (non-null leaves with s <= tau^2), counted by the scan's source
+// and compacted into (s, Morton index) lists by its sink.
+struct TruncFlagSrc {
+  const TruncJob* jobs;
+  int njobs;
+  __device__ int64_t operator()(int64_t g) const {
+    const TruncJob& J = jobs[find_job(jobs, njobs, g)];
+    const int64_t m = g - J.base;
+    return (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
+  }
+};
+struct TruncCompactSink {
+  const TruncJob* jobs;
+  int njobs;
+  double* cs;
+  int32_t* cm;
+  __device__ void operator()(int64_t g, int64_t v, int64_t pos) const {
+    if (!v) return;
+    const TruncJob& J = jobs[find_job(jobs, njobs, g)];
+    const int64_t m = g - J.base;
+    cs[pos] = J.leafnorm[m];
+    cm[pos] = int32_t(m);
+  }
+};
 
 constexpr int kSelThreads = 1024;
 constexpr int kSelLds = 4096;   // candidate sets up to this size use the all-pairs form
@@ -364,14 +384,15 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
 }
 
 __global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int64_t total,
-                              const int32_t* __restrict__ flag, const uint64_t* __restrict__ kst) {
+                              const uint64_t* __restrict__ kst) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int j = find_job(jobs, njobs, g);
   const TruncJob& J = jobs[j];
   const int64_t m = g - J.base;
   const double s = J.leafnorm[m];
-  const bool drop = flag[g] && kst[3 * j + 2] != 0 &&
+  const bool cand = J.slot[m] >= 0 && s <= J.tau2;
+  const bool drop = cand && kst[3 * j + 2] != 0 &&
                     key_le(__double_as_longlong(s), uint32_t(m), kst[3 * j], uint32_t(kst[3 * j + 1]));
   J.out_slot[m] = drop ? -1 : J.slot[m];
   J.out_norm[m] = drop ? 0.0 : s;
@@ -380,7 +401,7 @@ __global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int6
 static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t trunc_batch_scratch_bytes(int njobs, int64_t total) {
-  return al256(total * 4) + al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) + al256(total * 8) +
+  return al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) + al256(total * 8) +
          al256(size_t(njobs) * 24) + al256(scan_scratch_bytes(total));
 }
 
@@ -389,8 +410,6 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   if (njobs == 0) return hipSuccess;
   if (scratch_bytes < trunc_batch_scratch_bytes(njobs, total)) return hipErrorInvalidValue;
   char* p = static_cast<char*>(scratch);
-  int32_t* flag = reinterpret_cast<int32_t*>(p);
-  p += al256(total * 4);
   int64_t* pos = reinterpret_cast<int64_t*>(p);
   p += al256((total + 1) * 8);
   double* cs = reinterpret_cast<double*>(p);
@@ -402,15 +421,12 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   uint64_t* kst = reinterpret_cast<uint64_t*>(p);
   p += al256(size_t(njobs) * 24);
   const uint32_t nb = uint32_t((total + 255) / 256);
-  hipLaunchKernelGGL(k_trunc_flag, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag);
-  hipError_t e = hipGetLastError();
+  hipError_t e = scan_impl<0>(s, TruncFlagSrc{jobs, njobs}, total, pos, nullptr, nullptr, pos + total, p,
+                              scan_scratch_bytes(total), TruncCompactSink{jobs, njobs, cs, cm});
   if (e != hipSuccess) return e;
-  e = scan_impl<int32_t, 0>(s, flag, total, pos, nullptr, nullptr, pos + total, p, scan_scratch_bytes(total));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trunc_compact, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, pos, cs, cm);
   hipLaunchKernelGGL(k_trunc_fx, dim3(uint32_t(njobs) * kSelSplit), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx);
   hipLaunchKernelGGL(k_trunc_select, dim3(uint32_t(njobs)), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx, kst);
-  hipLaunchKernelGGL(k_trunc_apply, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag, kst);
+  hipLaunchKernelGGL(k_trunc_apply, dim3(nb), dim3(256), 0, s, jobs, njobs, total, kst);
   return hipGetLastError();
 }
 
