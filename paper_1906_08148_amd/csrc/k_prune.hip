@@ -46,7 +46,13 @@ __device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, const i
 // lane busy: element t belongs to the leaf whose segment holds t (a binary
 // search over the segment starts in LDS), and kPU elements per lane are
 // loaded before any is used, so one round trip to memory serves up to
-// kPU * 64 (leaf, k) candidates whatever the leaves' range lengths.
+// kPU * 64 (leaf, k) candidates whatever the leaves' range lengths.  In the
+// counting pass a wave whose longest range exceeds kLongSpan instead lets
+// every lane walk its own leaf: the ranges are then long enough to keep the
+// lanes busy, and a window of the flattened list would hold only one or two
+// leaves, whose k-ordered sums would fall to one or two lanes.  Both walks
+// add each leaf's terms k ascending, so they give the same bits.  The fill
+// pass (no sums) always walks the flattened list, whose writes coalesce.
 struct LaneLeaf {
   int r;
   uint32_t c, i, j;
@@ -84,6 +90,7 @@ __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, c
   return x;
 }
 
+constexpr int kLongSpan = 64;       // waves whose longest k range exceeds this walk one leaf per lane
 constexpr int kPU = 8;              // flattened elements per lane per window
 constexpr int kPW = kPU * kWave;    // window of the flattened list
 constexpr int kPWaves = 4;          // waves per workgroup
@@ -106,6 +113,12 @@ __device__ __forceinline__ int64_t wave_excl_scan_i64(int64_t v) {
     if (l >= off) x += o;
   }
   return x - v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+  return v;
 }
 
 // LDS written by some lanes of a wave and read by others of the same wave:
@@ -158,7 +171,34 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
   const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
   int64_t my_cnt = 0, my_cand = 0;
   double my_skip = 0.0;
-  if (T > 0) {
+  const int maxspan = wave_max_i32(span);
+  if (maxspan > kLongSpan) {
+    // long ranges: every lane walks its own leaf, k ascending, with eight
+    // k values' loads in flight (the same order and arithmetic as below)
+    const double tau = (x.valid && reqs[x.r].use_norms) ? reqs[x.r].tau : -1.0;
+    for (int k0 = 0; k0 < maxspan; k0 += 8) {
+      double a[8], bv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = bv[q] = -1.0;
+        if (k0 + q < span) {
+          a[q] = as_global(x.sa)[x.lo + k0 + q];
+          bv[q] = as_global(x.sb)[x.lo + k0 + q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (k0 + q < span) {
+          const bool both = (a[q] >= 0.0) && (bv[q] >= 0.0);
+          const double pr = a[q] * bv[q];
+          const bool keep = both && (tau < 0.0 || pr >= tau);
+          my_cand += both ? 1 : 0;
+          my_cnt += keep ? 1 : 0;
+          my_skip += (both && !keep) ? pr : 0.0;
+        }
+      }
+    }
+  } else if (T > 0) {
     L.sst[lane] = sst;
     L.lo[lane] = x.lo;
     L.sa[lane] = x.sa;
@@ -194,13 +234,31 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
         }
       }
       wave_lds_sync();
-      // each leaf adds its own part of the window, k ascending
-      const int s0 = max(sst, wb), s1 = min(sst + span, wb + kPW);
-      for (int t = s0; t < s1; ++t) {
-        const int f = L.fl[t - wb];
+      // each leaf adds its own part of the window, k ascending; eight LDS
+      // reads are issued before their additions (long ranges leave a
+      // window to one or two lanes)
+      const int s0 = max(sst, wb) - wb, s1 = min(sst + span, wb + kPW) - wb;
+      int t = s0;
+      for (; t + 8 <= s1; t += 8) {
+        double v[8];
+        int f[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          v[q] = L.v[t + q];
+          f[q] = L.fl[t + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          my_cand += f[q] & 1;
+          my_cnt += f[q] >> 1;
+          my_skip += v[q];
+        }
+      }
+      for (; t < s1; ++t) {
+        const int f = L.fl[t];
         my_cand += f & 1;
         my_cnt += f >> 1;
-        my_skip += L.v[t - wb];
+        my_skip += L.v[t];
       }
       wave_lds_sync();
     }
