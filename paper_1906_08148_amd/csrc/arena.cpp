@@ -1,4 +1,5 @@
-// First-fit sub-allocator over the caller's device arena.
+// Sub-allocator over the caller's device arena: first-fit ranges with an
+// exact-size cache in front.
 #include <algorithm>
 #include <cstdint>
 
@@ -11,12 +12,17 @@ void Arena::init(char* base, size_t bytes) {
   size_ = bytes;
   used_ = 0;
   free_.clear();
+  cache_.clear();
   free_[0] = bytes;
 }
 
-size_t Arena::alloc(size_t bytes, size_t align) {
-  if (bytes == 0) bytes = align;
-  bytes = (bytes + align - 1) / align * align;
+static uint64_t cache_key(size_t bytes, size_t align) {
+  int la = 0;
+  while ((size_t(1) << la) < align) ++la;
+  return (uint64_t(bytes) << 6) | uint64_t(la);
+}
+
+size_t Arena::fit(size_t bytes, size_t align) const {
   for (auto it = free_.begin(); it != free_.end(); ++it) {
     const size_t off = it->first, len = it->second;
     const size_t start = (off + align - 1) / align * align;
@@ -26,40 +32,70 @@ size_t Arena::alloc(size_t bytes, size_t align) {
     if (lead) free_[off] = lead;
     const size_t tail = len - lead - bytes;
     if (tail) free_[start + bytes] = tail;
-    used_ += bytes;
     return start;
   }
   return SIZE_MAX;
 }
 
-void Arena::release(size_t off, size_t bytes) {
+size_t Arena::alloc(size_t bytes, size_t align) {
+  if (bytes == 0) bytes = align;
+  bytes = (bytes + align - 1) / align * align;
+  auto c = cache_.find(cache_key(bytes, align));
+  if (c != cache_.end() && !c->second.empty()) {
+    const size_t off = c->second.back();
+    c->second.pop_back();
+    used_ += bytes;
+    return off;
+  }
+  size_t off = fit(bytes, align);
+  if (off == SIZE_MAX && !cache_.empty()) {
+    trim();
+    off = fit(bytes, align);
+  }
+  if (off != SIZE_MAX) used_ += bytes;
+  return off;
+}
+
+void Arena::release(size_t off, size_t bytes, size_t align) {
   if (bytes == 0) return;
   used_ -= bytes;
-  auto next = free_.lower_bound(off);
-  size_t start = off, len = bytes;
-  if (next != free_.begin()) {
-    auto prev = std::prev(next);
-    if (prev->first + prev->second == off) {
-      start = prev->first;
-      len += prev->second;
-      free_.erase(prev);
+  cache_[cache_key(bytes, align)].push_back(off);
+}
+
+// Return every cached range to the range map, merging neighbours.
+void Arena::trim() const {
+  for (auto& kv : cache_) {
+    const size_t bytes = size_t(kv.first >> 6);
+    for (const size_t off : kv.second) {
+      auto next = free_.lower_bound(off);
+      size_t start = off, len = bytes;
+      if (next != free_.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+          start = prev->first;
+          len += prev->second;
+          free_.erase(prev);
+        }
+      }
+      if (next != free_.end() && next->first == off + bytes) {
+        len += next->second;
+        free_.erase(next);
+      }
+      free_[start] = len;
     }
   }
-  if (next != free_.end() && next->first == off + bytes) {
-    len += next->second;
-    free_.erase(next);
-  }
-  free_[start] = len;
+  cache_.clear();
 }
 
 size_t Arena::largest_free() const {
+  trim();
   size_t best = 0;
   for (auto& kv : free_) best = std::max(best, kv.second);
   return best;
 }
 
 Region::~Region() {
-  if (ctx) ctx->arena.release(off, bytes);
+  if (ctx) ctx->arena.release(off, bytes, align);
 }
 
 void* Region::ptr() const { return ctx->arena.base() + off; }
@@ -73,6 +109,7 @@ RegionP Ctx::alloc(size_t bytes, size_t align) {
   r->ctx = this;
   r->off = off;
   r->bytes = rounded;
+  r->align = align;
   return r;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -20,12 +21,18 @@ namespace spamm {
 // First-fit sub-allocator over one caller-owned device buffer.  Free ranges
 // are kept in an ordered map and coalesced on release.  All reuse is ordered
 // on the context's single stream.
+// First-fit ranges over the caller's buffer, with an exact-size cache in
+// front: a released range waits in the bucket of its (size, alignment) and
+// the next request of that shape takes it back in O(1) (the multiply and
+// build calls repeat their shapes from batch to batch).  The buckets return
+// to the coalescing range map when a request finds no fit, and before the
+// largest free range is reported.
 class Arena {
  public:
   void init(char* base, size_t bytes);
   // Returns offset or SIZE_MAX when no range fits.
   size_t alloc(size_t bytes, size_t align = 256);
-  void release(size_t off, size_t bytes);
+  void release(size_t off, size_t bytes, size_t align);
   size_t used() const { return used_; }
   size_t size() const { return size_; }
   size_t free_bytes() const { return size_ - used_; }
@@ -33,10 +40,13 @@ class Arena {
   char* base() const { return base_; }
 
  private:
+  size_t fit(size_t bytes, size_t align) const;  // first-fit in the range map
+  void trim() const;                              // buckets back into the range map
   char* base_ = nullptr;
   size_t size_ = 0;
   size_t used_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> length
+  mutable std::map<size_t, size_t> free_;  // offset -> length
+  mutable std::unordered_map<uint64_t, std::vector<size_t>> cache_;  // (size, log2 align) -> offsets
 };
 
 struct Ctx;
@@ -44,7 +54,7 @@ struct Ctx;
 // One arena allocation; freed when the last shared owner drops it.
 struct Region {
   Ctx* ctx = nullptr;
-  size_t off = 0, bytes = 0;
+  size_t off = 0, bytes = 0, align = 256;
   ~Region();
   void* ptr() const;
 };
