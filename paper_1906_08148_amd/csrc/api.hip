@@ -28,7 +28,7 @@ spamm_status fail(Ctx* c, spamm_status s, const std::string& msg) {
 
 void* Ctx::stage(size_t bytes) {
   if (bytes <= host_stage_bytes) return host_stage;
-  if (host_stage) hipHostFree(host_stage);
+  if (host_stage) (void)hipHostFree(host_stage);
   host_stage = nullptr;
   host_stage_bytes = 0;
   size_t want = std::max<size_t>(bytes, size_t(1) << 20);
@@ -515,8 +515,8 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx) {
   if (!ctx) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;
   if (c->live_handles != 0) return fail(c, SPAMM_EINVAL, "handles still alive");
-  hipStreamSynchronize(c->stream);
-  c->collect_timing();
+  (void)hipStreamSynchronize(c->stream);
+  (void)c->collect_timing();
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -665,9 +665,12 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     if (b.nblocks > INT32_MAX) return fail(c, SPAMM_EINVAL, "too many blocks");
   }
   if (count == 0) return SPAMM_OK;
-  // per list: leaf norms, null flags, slots and keys; one read-back of every
-  // list's error bits and leaf count; then the leaf copies and one pyramid
-  // launch for all lists
+  // Every list's leaf store is allocated for min(nblocks, G^2) leaves (an
+  // upper bound of its non-null leaves) before any launch.  Norms, flags
+  // and slots of all lists go out as one set of launches; one read-back
+  // returns every list's error bits and leaf count; the leaf copies and the
+  // pyramids are queued after it (they read the counts on the device) and
+  // run while the caller goes on.
   struct Hdr {
     int32_t err;
     int32_t pad[15];
@@ -676,36 +679,54 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
   };
   static_assert(sizeof(Hdr) == 128, "one header per list");
   std::vector<std::unique_ptr<spamm_mat>> ms(count);
-  std::vector<RegionP> src(count), keys(count);
+  std::vector<RegionP> src(count);
+  std::vector<BuildJob> jobs(count);
   RegionP hdr;
   ALLOC(hdr, int64_t(count) * sizeof(Hdr), "build headers");
-  {
-    std::vector<RegionP> flag(count), scratch(count);
-    for (int t = 0; t < count; ++t) {
-      const spamm_block_list& b = lists[t];
-      spamm_status st = new_matrix(c, b.n, b.leaf, ms[t]);
-      if (st != SPAMM_OK) return st;
-      spamm_mat* m = ms[t].get();
-      const int64_t G2 = int64_t(m->G) * m->G;
-      ALLOC(flag[t], G2 * 4, "flags");
-      ALLOC(src[t], G2 * 4, "block index");
-      ALLOC(keys[t], std::max<int64_t>(1, std::min<int64_t>(b.nblocks, G2)) * 4, "leaf keys");  // >= non-null
-      const size_t sb = scan_scratch_bytes(G2);
-      ALLOC(scratch[t], sb, "scan scratch");
-      Hdr* h = P<Hdr>(hdr) + t;
-      TimedScope ts(c, kTBuild);
-      double* leafnorm = P<double>(m->norms) + level_offset(m->L);
-      SPAMM_HIP(c, launch_blocks_init(c->stream, G2, P<int32_t>(src[t]), leafnorm, P<int32_t>(flag[t]), &h->err));
-      SPAMM_HIP(c, launch_blocks_scatter(c->stream, b.n, b.leaf, m->G, b.nblocks, b.coords, b.data,
-                                         P<int32_t>(src[t]), &h->err));
-      SPAMM_HIP(c, launch_blocks_scan(c->stream, b.n, b.leaf, m->G, b.nblocks, b.coords, b.data, P<int32_t>(src[t]),
-                                      leafnorm, P<int32_t>(flag[t]), &h->err));
-      SPAMM_HIP(c, launch_flags_to_slots(c->stream, P<int32_t>(flag[t]), G2, P<int32_t>(m->slot), P<int32_t>(keys[t]),
-                                         &h->total, scratch[t]->ptr(), sb));
-    }
+  int64_t flags_total = 0, blocks_total = 0, cap_total = 0;
+  for (int t = 0; t < count; ++t) {
+    const spamm_block_list& b = lists[t];
+    spamm_status st = new_matrix(c, b.n, b.leaf, ms[t]);
+    if (st != SPAMM_OK) return st;
+    spamm_mat* m = ms[t].get();
+    const int64_t G2 = int64_t(m->G) * m->G;
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(b.nblocks, G2));
+    ALLOC(src[t], G2 * 4, "block index");
+    m->store = std::make_shared<Store>();
+    st = alloc_store(c, *m->store, cap, b.leaf, b.stores);
+    if (st != SPAMM_OK) return st;
+    BuildJob& J = jobs[t];
+    std::memset(&J, 0, sizeof(J));
+    J.n = b.n;
+    J.bs = b.leaf;
+    J.G = m->G;
+    J.nblocks = b.nblocks;
+    J.coords = b.coords;
+    J.data = b.data;
+    J.src_of = P<int32_t>(src[t]);
+    J.leafnorm = P<double>(m->norms) + level_offset(m->L);
+    J.slot = P<int32_t>(m->slot);
+    J.keys = P<int32_t>(m->store->keys);
+    J.err = &(P<Hdr>(hdr) + t)->err;
+    J.total = &(P<Hdr>(hdr) + t)->total;
+    J.f64 = P<double>(m->store->f64);
+    J.f32 = P<float>(m->store->f32);
+    J.b16 = P<uint16_t>(m->store->bf16);
+    J.b16t = P<uint16_t>(m->store->bf16t);
+    J.g2_base = flags_total;
+    J.blk_base = blocks_total;
+    J.leaf_base = cap_total;
+    J.tile_base = flags_total / kBuildTile;
+    flags_total += (G2 + kBuildTile - 1) / kBuildTile * kBuildTile;
+    blocks_total += b.nblocks;
+    cap_total += cap;
   }
-  // the pyramid job table goes out while those kernels run
-  TableSet pt;
+  if (blocks_total > INT32_MAX || cap_total > INT32_MAX)
+    return fail(c, SPAMM_EINVAL, "too many blocks in one build call");
+  RegionP flags, scratch;
+  ALLOC(flags, flags_total * 4, "flags");
+  const size_t sb = build_batch_scratch_bytes(flags_total);
+  ALLOC(scratch, sb, "scan scratch");
   std::vector<PyrJob> pjobs;
   {
     std::vector<double*> nv;
@@ -716,9 +737,15 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     }
     pjobs = pyramid_jobs(nv, lv);
   }
-  const size_t po = pt.add(pjobs);
-  spamm_status st = send_tables(c, pt);
+  TableSet tabs;
+  const size_t oj = tabs.add(jobs), po = tabs.add(pjobs);
+  spamm_status st = send_tables(c, tabs);
   if (st != SPAMM_OK) return st;
+  {
+    TimedScope ts(c, kTBuild);
+    SPAMM_HIP(c, launch_build_batch(c->stream, tabs.at<BuildJob>(oj), count, P<int32_t>(flags), flags_total,
+                                    blocks_total, cap_total, scratch->ptr(), sb));
+  }
   std::vector<Hdr> hb(count);
   st = download(c, hb.data(), hdr->ptr(), int64_t(count) * sizeof(Hdr));
   if (st != SPAMM_OK) return st;
@@ -729,22 +756,15 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     if (e & 4) return fail(c, SPAMM_EINVAL, "non-zero entry past row/column n");
     if (e & 8) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input blocks");
   }
-  for (int t = 0; t < count; ++t) {
-    const spamm_block_list& b = lists[t];
-    spamm_mat* m = ms[t].get();
-    m->nonnull = hb[t].total;
-    m->store = std::make_shared<Store>();
-    st = alloc_store(c, *m->store, hb[t].total, b.leaf, b.stores, keys[t]);
-    if (st != SPAMM_OK) return st;
-    TimedScope ts2(c, kTBuild);
-    SPAMM_HIP(c, launch_copy_block_leaves(c->stream, b.n, b.leaf, hb[t].total, P<int32_t>(m->store->keys),
-                                          P<int32_t>(src[t]), b.data, P<double>(m->store->f64),
-                                          P<float>(m->store->f32), P<uint16_t>(m->store->bf16),
-                                          P<uint16_t>(m->store->bf16t)));
+  {
+    TimedScope ts(c, kTBuild);
+    SPAMM_HIP(c, launch_build_copies(c->stream, tabs.at<BuildJob>(oj), count, cap_total));
   }
-  st = pyramids_launch(c, pt.at<PyrJob>(po), pjobs);
+  st = pyramids_launch(c, tabs.at<PyrJob>(po), pjobs);
   if (st != SPAMM_OK) return st;
   for (int t = 0; t < count; ++t) {
+    ms[t]->nonnull = hb[t].total;
+    ms[t]->store->nleaf = hb[t].total;  // leaves in use (the copies hold up to min(nblocks, G^2))
     c->live_handles++;
     out[t] = ms[t].release();
   }

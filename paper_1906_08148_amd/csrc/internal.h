@@ -343,15 +343,41 @@ struct StatPartial {
 hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                    int bs, int G, double* leafnorm, int32_t* flag,
                                    int32_t* nonfinite);
-hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
-                                 const int32_t* coords, const double* data, int32_t* src_of,
-                                 int32_t* errflags);
-// src_of[] = -1, leafnorm[] = 0, flag[] = 0 over G2 entries and err[0..3] = 0
-hipError_t launch_blocks_init(hipStream_t s, int64_t G2, int32_t* src_of, double* leafnorm, int32_t* flag,
-                              int32_t* err);
-hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
-                              const int32_t* coords, const double* data, const int32_t* src_of,
-                              double* leafnorm, int32_t* flag, int32_t* errflags);
+// One block list of a batched build (device table).  The batch's flags are
+// one array in which every list's G*G entries start on a scan tile; blocks
+// and leaf slots are numbered through the batch.
+struct BuildJob {
+  int64_t n;
+  int32_t bs, G;
+  int64_t nblocks;
+  const int32_t* coords;
+  const double* data;
+  int32_t* src_of;    // G*G: index of the block placed at each Morton slot
+  double* leafnorm;   // leaf level of the norm pyramid
+  int32_t* slot;      // slot map
+  int32_t* keys;      // Morton key of each leaf slot (capacity cap)
+  int32_t* err;       // four error words
+  int64_t* total;     // non-null leaves, written by the slot scan
+  double* f64;        // leaf copies, capacity cap (null when not kept)
+  float* f32;
+  uint16_t* b16;
+  uint16_t* b16t;
+  int64_t g2_base;    // first flag of this list in the batch's flag array
+  int64_t blk_base;   // first block of this list in the batch
+  int64_t leaf_base;  // first leaf slot of this list in the batch (cap slots each)
+  int64_t tile_base;  // first scan tile of this list
+};
+constexpr int64_t kBuildTile = 2048;  // flag entries per scan tile (each list starts on one)
+// init, scatter, leaf norms and flags, slot scan (slots, keys, totals): one
+// launch each for all lists of the batch; then the leaf copies (each list's
+// count read on the device)
+hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int32_t* flags, int64_t flags_total,
+                              int64_t blocks_total, int64_t cap_total, void* scratch, size_t scratch_bytes);
+hipError_t launch_build_copies(hipStream_t s, const BuildJob* jobs, int njobs, int64_t cap_total);
+size_t build_batch_scratch_bytes(int64_t flags_total);
+// slot scan of a batched build (segmented by list)
+hipError_t launch_build_slots(hipStream_t s, const BuildJob* jobs, int njobs, const int32_t* flags,
+                              int64_t flags_total, void* scratch, size_t scratch_bytes);
 // exclusive scan of int32 flags -> slot map (flag ? prefix : -1) and its
 // inverse keys[slot] = index (keys may be null), total -> *total
 hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot,
@@ -362,10 +388,6 @@ hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64
 hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                     int bs, int64_t nleaf, const int32_t* keys, double* f64,
                                     float* f32, uint16_t* b16, uint16_t* b16t);
-hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
-                                    const int32_t* keys, const int32_t* src_of,
-                                    const double* data, double* f64, float* f32,
-                                    uint16_t* b16, uint16_t* b16t);
 hipError_t launch_derive_store(hipStream_t s, int64_t nleaf, int bs, const double* f64, const float* f32,
                                double* o64, float* o32, uint16_t* o16, uint16_t* o16t);
 hipError_t launch_prep_batch(hipStream_t s, const PrepJob* jobs_dev, int njobs, int64_t total,

@@ -73,75 +73,76 @@ hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n
   return hipGetLastError();
 }
 
-// Block list: place block t at its Morton slot; flag bad and duplicate coords.
-__global__ void k_blocks_scatter(int64_t n, int bs, int64_t nblocks, const int32_t* __restrict__ coords,
-                                 int32_t* __restrict__ src_of, int32_t* __restrict__ err) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nblocks) return;
-  const int64_t gmax = (n + bs - 1) / bs;
-  const int32_t I = coords[2 * t], J = coords[2 * t + 1];
-  if (I < 0 || J < 0 || I >= gmax || J >= gmax) {
-    atomicOr(err, kErrCoord);
+// ---------------------------------------------------------------- batched block lists
+
+// The lists of one build call, each kernel over all of them; a thread or
+// workgroup finds its list by the list's first index (flags, blocks or leaf
+// slots of the batch).
+template <int Field>
+__device__ __forceinline__ int find_bjob(const BuildJob* __restrict__ jobs, int njobs, int64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = Field == 0 ? jobs[mid].g2_base : Field == 1 ? jobs[mid].blk_base : jobs[mid].leaf_base;
+    if (b <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_build_init_b(const BuildJob* __restrict__ jobs, int njobs, int32_t* __restrict__ flags,
+                               int64_t flags_total) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= flags_total) return;
+  flags[g] = 0;
+  const BuildJob& J = jobs[find_bjob<0>(jobs, njobs, g)];
+  const int64_t m = g - J.g2_base;
+  if (m < 4) J.err[m] = 0;
+  if (m < int64_t(J.G) * J.G) {
+    J.src_of[m] = -1;
+    J.leafnorm[m] = 0.0;
+  }
+}
+
+__global__ void k_blocks_scatter_b(const BuildJob* __restrict__ jobs, int njobs, int64_t blocks_total) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= blocks_total) return;
+  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, g)];
+  const int64_t t = g - J.blk_base;
+  const int64_t gmax = (J.n + J.bs - 1) / J.bs;
+  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
+  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) {
+    atomicOr(J.err, kErrCoord);
     return;
   }
-  const uint32_t m = morton(uint32_t(I), uint32_t(J));
-  const int32_t old = atomicCAS(&src_of[m], -1, int32_t(t));
-  if (old != -1) atomicOr(err, kErrDup);
+  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
+  const int32_t old = atomicCAS(&J.src_of[m], -1, int32_t(t));
+  if (old != -1) atomicOr(J.err, kErrDup);
 }
 
-hipError_t launch_blocks_scatter(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks,
-                                 const int32_t* coords, const double* data, int32_t* src_of,
-                                 int32_t* errflags) {
-  (void)G;
-  (void)data;
-  if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_blocks_scatter, dim3(uint32_t((nblocks + 255) / 256)), dim3(256), 0, s, n,
-                     bs, nblocks, coords, src_of, errflags);
-  return hipGetLastError();
-}
-
-__global__ void k_blocks_init(int64_t G2, int32_t* __restrict__ src_of, double* __restrict__ leafnorm,
-                              int32_t* __restrict__ flag, int32_t* __restrict__ err) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m < 4) err[m] = 0;
-  if (m >= G2) return;
-  src_of[m] = -1;
-  leafnorm[m] = 0.0;
-  flag[m] = 0;
-}
-
-hipError_t launch_blocks_init(hipStream_t s, int64_t G2, int32_t* src_of, double* leafnorm, int32_t* flag,
-                              int32_t* err) {
-  hipLaunchKernelGGL(k_blocks_init, dim3(uint32_t((std::max<int64_t>(G2, 4) + 255) / 256)), dim3(256), 0, s, G2,
-                     src_of, leafnorm, flag, err);
-  return hipGetLastError();
-}
-
-// One workgroup per listed block (the one that won its Morton slot).
-__global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, int64_t nblocks,
-                                                     const int32_t* __restrict__ coords,
-                                                     const double* __restrict__ data,
-                                                     const int32_t* __restrict__ src_of,
-                                                     double* __restrict__ leafnorm,
-                                                     int32_t* __restrict__ flag,
-                                                     int32_t* __restrict__ err) {
+// One workgroup per block of the batch: the leaf-pass order of k_blocks_scan.
+__global__ void __launch_bounds__(256) k_blocks_scan_b(const BuildJob* __restrict__ jobs, int njobs,
+                                                       int32_t* __restrict__ flags) {
   __shared__ double red[4];
-  const int64_t t = blockIdx.x;
+  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, blockIdx.x)];
+  const int64_t t = int64_t(blockIdx.x) - J.blk_base;
+  const int bs = J.bs;
+  const int64_t n = J.n;
   const int64_t gmax = (n + bs - 1) / bs;
-  const int32_t I = coords[2 * t], J = coords[2 * t + 1];
-  if (I < 0 || J < 0 || I >= gmax || J >= gmax) return;
-  const uint32_t m = morton(uint32_t(I), uint32_t(J));
-  if (src_of[m] != int32_t(t)) return;
+  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
+  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) return;
+  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
+  if (J.src_of[m] != int32_t(t)) return;
   double s = 0.0;
   int nz = 0, nf = 0, pad = 0;
   const int64_t rows = min<int64_t>(bs, n - int64_t(I) * bs);
-  const int64_t cols = min<int64_t>(bs, n - int64_t(J) * bs);
-  const double* blk = data + t * bs * bs;
+  const int64_t cols = min<int64_t>(bs, n - int64_t(Jc) * bs);
+  const double* blk = J.data + t * bs * bs;
   const int sh = __builtin_ctz(unsigned(bs)), e2 = bs * bs;
   for (int base = 0; base < e2; base += kLeafPass * 256) {
     double a[kLeafPass];
 #pragma unroll
-    for (int q = 0; q < kLeafPass; ++q) {  // all loads of the pass first
+    for (int q = 0; q < kLeafPass; ++q) {
       const int e = base + q * 256 + int(threadIdx.x);
       a[q] = e < e2 ? blk[e] : 0.0;
     }
@@ -164,21 +165,11 @@ __global__ void __launch_bounds__(256) k_blocks_scan(int64_t n, int bs, int64_t 
   nf = __syncthreads_or(nf);
   pad = __syncthreads_or(pad);
   if (threadIdx.x == 0) {
-    leafnorm[m] = nz ? s : 0.0;
-    flag[m] = nz;
-    if (nf) atomicOr(err, 8);
-    if (pad) atomicOr(err, kErrPad);
+    J.leafnorm[m] = nz ? s : 0.0;
+    flags[J.g2_base + m] = nz;
+    if (nf) atomicOr(J.err, 8);
+    if (pad) atomicOr(J.err, kErrPad);
   }
-}
-
-hipError_t launch_blocks_scan(hipStream_t s, int64_t n, int bs, int G, int64_t nblocks, const int32_t* coords,
-                              const double* data, const int32_t* src_of, double* leafnorm, int32_t* flag,
-                              int32_t* errflags) {
-  (void)G;
-  if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_blocks_scan, dim3(uint32_t(nblocks)), dim3(256), 0, s, n, bs, nblocks, coords, data, src_of,
-                     leafnorm, flag, errflags);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- compaction
@@ -279,24 +270,40 @@ hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t 
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_copy_block_leaves(int bs, const int32_t* __restrict__ keys,
-                                                           const int32_t* __restrict__ src_of,
-                                                           const double* __restrict__ data,
-                                                           double* f64, float* f32, uint16_t* b16,
-                                                           uint16_t* b16t) {
-  const int64_t sl = blockIdx.x;
-  const int32_t t = src_of[keys[sl]];
-  const double* blk = data + int64_t(t) * bs * bs;
-  write_leaf(sl, bs, [&](int e) { return blk[e]; }, f64, f32, b16, b16t);
+// One workgroup per leaf slot of the batch (each list has cap slots); slots
+// at or past the list's leaf count (read from the slot scan) do nothing, so
+// the launch needs no count from the host.
+__global__ void __launch_bounds__(256) k_copy_block_leaves_b(const BuildJob* __restrict__ jobs, int njobs) {
+  const BuildJob& J = jobs[find_bjob<2>(jobs, njobs, blockIdx.x)];
+  const int64_t sl = int64_t(blockIdx.x) - J.leaf_base;
+  if (sl >= *J.total) return;
+  const int32_t t = J.src_of[J.keys[sl]];
+  const double* blk = J.data + int64_t(t) * J.bs * J.bs;
+  write_leaf(sl, J.bs, [&](int e) { return blk[e]; }, J.f64, J.f32, J.b16, J.b16t);
 }
 
-hipError_t launch_copy_block_leaves(hipStream_t s, int64_t n, int bs, int64_t nleaf,
-                                    const int32_t* keys, const int32_t* src_of, const double* data,
-                                    double* f64, float* f32, uint16_t* b16, uint16_t* b16t) {
-  (void)n;
-  if (nleaf == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_block_leaves, dim3(uint32_t(nleaf)), dim3(256), 0, s, bs, keys, src_of,
-                     data, f64, f32, b16, b16t);
+size_t build_batch_scratch_bytes(int64_t flags_total) { return scan_scratch_bytes(flags_total); }
+
+hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int32_t* flags, int64_t flags_total,
+                              int64_t blocks_total, int64_t cap_total, void* scratch, size_t scratch_bytes) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_init_b, dim3(uint32_t((flags_total + 255) / 256)), dim3(256), 0, s, jobs, njobs, flags,
+                     flags_total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (blocks_total > 0) {
+    hipLaunchKernelGGL(k_blocks_scatter_b, dim3(uint32_t((blocks_total + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                       blocks_total);
+    hipLaunchKernelGGL(k_blocks_scan_b, dim3(uint32_t(blocks_total)), dim3(256), 0, s, jobs, njobs, flags);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_build_slots(s, jobs, njobs, flags, flags_total, scratch, scratch_bytes);
+}
+
+hipError_t launch_build_copies(hipStream_t s, const BuildJob* jobs, int njobs, int64_t cap_total) {
+  if (njobs == 0 || cap_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_block_leaves_b, dim3(uint32_t(cap_total)), dim3(256), 0, s, jobs, njobs);
   return hipGetLastError();
 }
 

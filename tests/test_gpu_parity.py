@@ -108,6 +108,18 @@ def test_block_list_batch_build(ctx):
         assert torch.equal(ctx.to_dense(M), ctx.to_dense(S))
         S.release()
         M.release()
+    # an empty G = 2048 list first: the batch's slot scan takes the
+    # three-launch path, and the small list's prefixes restart on its tile
+    e_c = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    e_d = torch.zeros((0, 64, 64), dtype=torch.float64, device="cuda")
+    big, small = ctx.build_blocks_batch([(131072, 64, e_c, e_d), lists[0]])
+    S = ctx.build_blocks(*lists[0])
+    assert big.info.nonnull == 0 and big.info.G == 2048
+    assert small.info.nonnull == S.info.nonnull
+    assert np.array_equal(ctx.norms(small), ctx.norms(S))
+    assert torch.equal(ctx.to_dense(small), ctx.to_dense(S))
+    for M in (big, small, S):
+        M.release()
     dup = lists[1][2].clone()
     dup[1] = dup[0]
     with pytest.raises(spamm.SpammError) as e:
