@@ -665,12 +665,11 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     if (b.nblocks > INT32_MAX) return fail(c, SPAMM_EINVAL, "too many blocks");
   }
   if (count == 0) return SPAMM_OK;
-  // Every list's leaf store is allocated for min(nblocks, G^2) leaves (an
-  // upper bound of its non-null leaves) before any launch.  Norms, flags
-  // and slots of all lists go out as one set of launches; one read-back
-  // returns every list's error bits and leaf count; the leaf copies and the
-  // pyramids are queued after it (they read the counts on the device) and
-  // run while the caller goes on.
+  // Every list's leaf store has one slot per listed block (block t is leaf
+  // slot t), so one pass over the blocks computes the norms and null flags
+  // and writes the slot map, the keys and the leaf copies: one set of
+  // launches for all lists, one read-back of every list's error bits and
+  // leaf count, and the pyramids queued after it.
   struct Hdr {
     int32_t err;
     int32_t pad[15];
@@ -683,17 +682,16 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
   std::vector<BuildJob> jobs(count);
   RegionP hdr;
   ALLOC(hdr, int64_t(count) * sizeof(Hdr), "build headers");
-  int64_t flags_total = 0, blocks_total = 0, cap_total = 0;
+  int64_t g2_total = 0, blocks_total = 0;
   for (int t = 0; t < count; ++t) {
     const spamm_block_list& b = lists[t];
     spamm_status st = new_matrix(c, b.n, b.leaf, ms[t]);
     if (st != SPAMM_OK) return st;
     spamm_mat* m = ms[t].get();
     const int64_t G2 = int64_t(m->G) * m->G;
-    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(b.nblocks, G2));
     ALLOC(src[t], G2 * 4, "block index");
     m->store = std::make_shared<Store>();
-    st = alloc_store(c, *m->store, cap, b.leaf, b.stores);
+    st = alloc_store(c, *m->store, std::max<int64_t>(b.nblocks, 1), b.leaf, b.stores);
     if (st != SPAMM_OK) return st;
     BuildJob& J = jobs[t];
     std::memset(&J, 0, sizeof(J));
@@ -713,20 +711,13 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     J.f32 = P<float>(m->store->f32);
     J.b16 = P<uint16_t>(m->store->bf16);
     J.b16t = P<uint16_t>(m->store->bf16t);
-    J.g2_base = flags_total;
+    J.g2_base = g2_total;
     J.blk_base = blocks_total;
-    J.leaf_base = cap_total;
-    J.tile_base = flags_total / kBuildTile;
-    flags_total += (G2 + kBuildTile - 1) / kBuildTile * kBuildTile;
+    g2_total += G2;
     blocks_total += b.nblocks;
-    cap_total += cap;
   }
-  if (blocks_total > INT32_MAX || cap_total > INT32_MAX)
+  if (blocks_total > INT32_MAX || g2_total > INT32_MAX)
     return fail(c, SPAMM_EINVAL, "too many blocks in one build call");
-  RegionP flags, scratch;
-  ALLOC(flags, flags_total * 4, "flags");
-  const size_t sb = build_batch_scratch_bytes(flags_total);
-  ALLOC(scratch, sb, "scan scratch");
   std::vector<PyrJob> pjobs;
   {
     std::vector<double*> nv;
@@ -743,8 +734,7 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
   if (st != SPAMM_OK) return st;
   {
     TimedScope ts(c, kTBuild);
-    SPAMM_HIP(c, launch_build_batch(c->stream, tabs.at<BuildJob>(oj), count, P<int32_t>(flags), flags_total,
-                                    blocks_total, cap_total, scratch->ptr(), sb));
+    SPAMM_HIP(c, launch_build_batch(c->stream, tabs.at<BuildJob>(oj), count, g2_total, blocks_total));
   }
   std::vector<Hdr> hb(count);
   st = download(c, hb.data(), hdr->ptr(), int64_t(count) * sizeof(Hdr));
@@ -756,15 +746,10 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count, const spamm
     if (e & 4) return fail(c, SPAMM_EINVAL, "non-zero entry past row/column n");
     if (e & 8) return fail(c, SPAMM_ENONFINITE, "NaN or Inf in the input blocks");
   }
-  {
-    TimedScope ts(c, kTBuild);
-    SPAMM_HIP(c, launch_build_copies(c->stream, tabs.at<BuildJob>(oj), count, cap_total));
-  }
   st = pyramids_launch(c, tabs.at<PyrJob>(po), pjobs);
   if (st != SPAMM_OK) return st;
   for (int t = 0; t < count; ++t) {
     ms[t]->nonnull = hb[t].total;
-    ms[t]->store->nleaf = hb[t].total;  // leaves in use (the copies hold up to min(nblocks, G^2))
     c->live_handles++;
     out[t] = ms[t].release();
   }

@@ -343,9 +343,10 @@ struct StatPartial {
 hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n, int64_t ld,
                                    int bs, int G, double* leafnorm, int32_t* flag,
                                    int32_t* nonfinite);
-// One block list of a batched build (device table).  The batch's flags are
-// one array in which every list's G*G entries start on a scan tile; blocks
-// and leaf slots are numbered through the batch.
+// One block list of a batched build (device table).  G*G entries and
+// blocks are numbered through the batch.  A list's leaf store has one slot
+// per listed block (block t -> slot t); slots of all-zero or rejected
+// blocks stay unused.
 struct BuildJob {
   int64_t n;
   int32_t bs, G;
@@ -355,29 +356,20 @@ struct BuildJob {
   int32_t* src_of;    // G*G: index of the block placed at each Morton slot
   double* leafnorm;   // leaf level of the norm pyramid
   int32_t* slot;      // slot map
-  int32_t* keys;      // Morton key of each leaf slot (capacity cap)
+  int32_t* keys;      // Morton key of each leaf slot
   int32_t* err;       // four error words
-  int64_t* total;     // non-null leaves, written by the slot scan
-  double* f64;        // leaf copies, capacity cap (null when not kept)
+  int64_t* total;     // non-null leaves
+  double* f64;        // leaf copies (null when not kept)
   float* f32;
   uint16_t* b16;
   uint16_t* b16t;
-  int64_t g2_base;    // first flag of this list in the batch's flag array
+  int64_t g2_base;    // first G*G entry of this list in the batch
   int64_t blk_base;   // first block of this list in the batch
-  int64_t leaf_base;  // first leaf slot of this list in the batch (cap slots each)
-  int64_t tile_base;  // first scan tile of this list
 };
-constexpr int64_t kBuildTile = 2048;  // flag entries per scan tile (each list starts on one)
-// init, scatter, leaf norms and flags, slot scan (slots, keys, totals): one
-// launch each for all lists of the batch; then the leaf copies (each list's
-// count read on the device)
-hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int32_t* flags, int64_t flags_total,
-                              int64_t blocks_total, int64_t cap_total, void* scratch, size_t scratch_bytes);
-hipError_t launch_build_copies(hipStream_t s, const BuildJob* jobs, int njobs, int64_t cap_total);
-size_t build_batch_scratch_bytes(int64_t flags_total);
-// slot scan of a batched build (segmented by list)
-hipError_t launch_build_slots(hipStream_t s, const BuildJob* jobs, int njobs, const int32_t* flags,
-                              int64_t flags_total, void* scratch, size_t scratch_bytes);
+// init, scatter, then one pass over the blocks (norms, null flags, slot
+// map, keys, leaf copies, counts): one launch each for all lists
+hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int64_t g2_total,
+                              int64_t blocks_total);
 // exclusive scan of int32 flags -> slot map (flag ? prefix : -1) and its
 // inverse keys[slot] = index (keys may be null), total -> *total
 hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot,

@@ -73,108 +73,6 @@ hipError_t launch_build_scan_dense(hipStream_t s, const double* dense, int64_t n
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- batched block lists
-
-// The lists of one build call, each kernel over all of them; a thread or
-// workgroup finds its list by the list's first index (flags, blocks or leaf
-// slots of the batch).
-template <int Field>
-__device__ __forceinline__ int find_bjob(const BuildJob* __restrict__ jobs, int njobs, int64_t g) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int64_t b = Field == 0 ? jobs[mid].g2_base : Field == 1 ? jobs[mid].blk_base : jobs[mid].leaf_base;
-    if (b <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ void k_build_init_b(const BuildJob* __restrict__ jobs, int njobs, int32_t* __restrict__ flags,
-                               int64_t flags_total) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= flags_total) return;
-  flags[g] = 0;
-  const BuildJob& J = jobs[find_bjob<0>(jobs, njobs, g)];
-  const int64_t m = g - J.g2_base;
-  if (m < 4) J.err[m] = 0;
-  if (m < int64_t(J.G) * J.G) {
-    J.src_of[m] = -1;
-    J.leafnorm[m] = 0.0;
-  }
-}
-
-__global__ void k_blocks_scatter_b(const BuildJob* __restrict__ jobs, int njobs, int64_t blocks_total) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= blocks_total) return;
-  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, g)];
-  const int64_t t = g - J.blk_base;
-  const int64_t gmax = (J.n + J.bs - 1) / J.bs;
-  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
-  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) {
-    atomicOr(J.err, kErrCoord);
-    return;
-  }
-  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
-  const int32_t old = atomicCAS(&J.src_of[m], -1, int32_t(t));
-  if (old != -1) atomicOr(J.err, kErrDup);
-}
-
-// One workgroup per block of the batch: the leaf-pass order of k_blocks_scan.
-__global__ void __launch_bounds__(256) k_blocks_scan_b(const BuildJob* __restrict__ jobs, int njobs,
-                                                       int32_t* __restrict__ flags) {
-  __shared__ double red[4];
-  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, blockIdx.x)];
-  const int64_t t = int64_t(blockIdx.x) - J.blk_base;
-  const int bs = J.bs;
-  const int64_t n = J.n;
-  const int64_t gmax = (n + bs - 1) / bs;
-  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
-  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) return;
-  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
-  if (J.src_of[m] != int32_t(t)) return;
-  double s = 0.0;
-  int nz = 0, nf = 0, pad = 0;
-  const int64_t rows = min<int64_t>(bs, n - int64_t(I) * bs);
-  const int64_t cols = min<int64_t>(bs, n - int64_t(Jc) * bs);
-  const double* blk = J.data + t * bs * bs;
-  const int sh = __builtin_ctz(unsigned(bs)), e2 = bs * bs;
-  for (int base = 0; base < e2; base += kLeafPass * 256) {
-    double a[kLeafPass];
-#pragma unroll
-    for (int q = 0; q < kLeafPass; ++q) {
-      const int e = base + q * 256 + int(threadIdx.x);
-      a[q] = e < e2 ? blk[e] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kLeafPass; ++q) {
-      const int e = base + q * 256 + int(threadIdx.x);
-      const int rr = e >> sh, cc = e & (bs - 1);
-      if (e >= e2) continue;
-      if (rr < rows && cc < cols) {
-        s += a[q] * a[q];
-        nz |= (a[q] != 0.0);
-        nf |= !isfinite(a[q]);
-      } else {
-        pad |= (a[q] != 0.0);
-      }
-    }
-  }
-  s = block_sum_f64(s, red);
-  nz = __syncthreads_or(nz);
-  nf = __syncthreads_or(nf);
-  pad = __syncthreads_or(pad);
-  if (threadIdx.x == 0) {
-    J.leafnorm[m] = nz ? s : 0.0;
-    flags[J.g2_base + m] = nz;
-    if (nf) atomicOr(J.err, 8);
-    if (pad) atomicOr(J.err, kErrPad);
-  }
-}
-
-// ---------------------------------------------------------------- compaction
-
-
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -241,6 +139,115 @@ __device__ __forceinline__ void write_leaf(int64_t sl, int bs, Get get, double* 
     }
 }
 
+// ---------------------------------------------------------------- batched block lists
+
+// The lists of one build call, each kernel over all of them; a thread or
+// workgroup finds its list by the list's first index (G*G entries or blocks
+// of the batch).
+template <int Field>
+__device__ __forceinline__ int find_bjob(const BuildJob* __restrict__ jobs, int njobs, int64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t b = Field == 0 ? jobs[mid].g2_base : jobs[mid].blk_base;
+    if (b <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_build_init_b(const BuildJob* __restrict__ jobs, int njobs, int64_t g2_total) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= g2_total) return;
+  const BuildJob& J = jobs[find_bjob<0>(jobs, njobs, g)];
+  const int64_t m = g - J.g2_base;
+  if (m < 4) J.err[m] = 0;
+  if (m == 0) *J.total = 0;
+  J.src_of[m] = -1;
+  J.slot[m] = -1;
+  J.leafnorm[m] = 0.0;
+}
+
+__global__ void k_blocks_scatter_b(const BuildJob* __restrict__ jobs, int njobs, int64_t blocks_total) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= blocks_total) return;
+  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, g)];
+  const int64_t t = g - J.blk_base;
+  const int64_t gmax = (J.n + J.bs - 1) / J.bs;
+  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
+  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) {
+    atomicOr(J.err, kErrCoord);
+    return;
+  }
+  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
+  const int32_t old = atomicCAS(&J.src_of[m], -1, int32_t(t));
+  if (old != -1) atomicOr(J.err, kErrDup);
+}
+
+// One workgroup per block of the batch.  The block that won its Morton slot
+// gets its squared norm (the leaf-pass order of k_build_scan_dense, so both
+// builds give the same bits) and, when it is not all zero, becomes leaf slot
+// t of its list: slot map, key, leaf copies (read again from L2) and one
+// count.  A list's store therefore has a slot per listed block, in list
+// order; slots of zero or rejected blocks stay unused.
+__global__ void __launch_bounds__(256) k_blocks_scan_b(const BuildJob* __restrict__ jobs, int njobs) {
+  __shared__ double red[4];
+  const BuildJob& J = jobs[find_bjob<1>(jobs, njobs, blockIdx.x)];
+  const int64_t t = int64_t(blockIdx.x) - J.blk_base;
+  const int bs = J.bs;
+  const int64_t n = J.n;
+  const int64_t gmax = (n + bs - 1) / bs;
+  const int32_t I = J.coords[2 * t], Jc = J.coords[2 * t + 1];
+  if (I < 0 || Jc < 0 || I >= gmax || Jc >= gmax) return;
+  const uint32_t m = morton(uint32_t(I), uint32_t(Jc));
+  if (J.src_of[m] != int32_t(t)) return;
+  double s = 0.0;
+  int nz = 0, nf = 0, pad = 0;
+  const int64_t rows = min<int64_t>(bs, n - int64_t(I) * bs);
+  const int64_t cols = min<int64_t>(bs, n - int64_t(Jc) * bs);
+  const double* blk = J.data + t * bs * bs;
+  const int sh = __builtin_ctz(unsigned(bs)), e2 = bs * bs;
+  for (int base = 0; base < e2; base += kLeafPass * 256) {
+    double a[kLeafPass];
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {
+      const int e = base + q * 256 + int(threadIdx.x);
+      a[q] = e < e2 ? blk[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kLeafPass; ++q) {
+      const int e = base + q * 256 + int(threadIdx.x);
+      const int rr = e >> sh, cc = e & (bs - 1);
+      if (e >= e2) continue;
+      if (rr < rows && cc < cols) {
+        s += a[q] * a[q];
+        nz |= (a[q] != 0.0);
+        nf |= !isfinite(a[q]);
+      } else {
+        pad |= (a[q] != 0.0);
+      }
+    }
+  }
+  s = block_sum_f64(s, red);
+  nz = __syncthreads_or(nz);
+  nf = __syncthreads_or(nf);
+  pad = __syncthreads_or(pad);
+  if (threadIdx.x == 0) {
+    J.leafnorm[m] = nz ? s : 0.0;
+    if (nz) {
+      J.slot[m] = int32_t(t);
+      J.keys[t] = int32_t(m);
+      atomicAdd(reinterpret_cast<unsigned long long*>(J.total), 1ull);
+    }
+    if (nf) atomicOr(J.err, 8);
+    if (pad) atomicOr(J.err, kErrPad);
+  }
+  if (nz) write_leaf(t, bs, [&](int e) { return blk[e]; }, J.f64, J.f32, J.b16, J.b16t);
+}
+
+// ---------------------------------------------------------------- compaction
+
+
 __global__ void __launch_bounds__(256) k_copy_dense_leaves(const double* __restrict__ dense, int64_t n,
                                                            int64_t ld, int bs,
                                                            const int32_t* __restrict__ keys,
@@ -270,40 +277,15 @@ hipError_t launch_copy_dense_leaves(hipStream_t s, const double* dense, int64_t 
   return hipGetLastError();
 }
 
-// One workgroup per leaf slot of the batch (each list has cap slots); slots
-// at or past the list's leaf count (read from the slot scan) do nothing, so
-// the launch needs no count from the host.
-__global__ void __launch_bounds__(256) k_copy_block_leaves_b(const BuildJob* __restrict__ jobs, int njobs) {
-  const BuildJob& J = jobs[find_bjob<2>(jobs, njobs, blockIdx.x)];
-  const int64_t sl = int64_t(blockIdx.x) - J.leaf_base;
-  if (sl >= *J.total) return;
-  const int32_t t = J.src_of[J.keys[sl]];
-  const double* blk = J.data + int64_t(t) * J.bs * J.bs;
-  write_leaf(sl, J.bs, [&](int e) { return blk[e]; }, J.f64, J.f32, J.b16, J.b16t);
-}
-
-size_t build_batch_scratch_bytes(int64_t flags_total) { return scan_scratch_bytes(flags_total); }
-
-hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int32_t* flags, int64_t flags_total,
-                              int64_t blocks_total, int64_t cap_total, void* scratch, size_t scratch_bytes) {
+hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, int64_t g2_total,
+                              int64_t blocks_total) {
   if (njobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_init_b, dim3(uint32_t((flags_total + 255) / 256)), dim3(256), 0, s, jobs, njobs, flags,
-                     flags_total);
+  hipLaunchKernelGGL(k_build_init_b, dim3(uint32_t((g2_total + 255) / 256)), dim3(256), 0, s, jobs, njobs, g2_total);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (blocks_total > 0) {
-    hipLaunchKernelGGL(k_blocks_scatter_b, dim3(uint32_t((blocks_total + 255) / 256)), dim3(256), 0, s, jobs, njobs,
-                       blocks_total);
-    hipLaunchKernelGGL(k_blocks_scan_b, dim3(uint32_t(blocks_total)), dim3(256), 0, s, jobs, njobs, flags);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return launch_build_slots(s, jobs, njobs, flags, flags_total, scratch, scratch_bytes);
-}
-
-hipError_t launch_build_copies(hipStream_t s, const BuildJob* jobs, int njobs, int64_t cap_total) {
-  if (njobs == 0 || cap_total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_block_leaves_b, dim3(uint32_t(cap_total)), dim3(256), 0, s, jobs, njobs);
+  if (e != hipSuccess || blocks_total == 0) return e;
+  hipLaunchKernelGGL(k_blocks_scatter_b, dim3(uint32_t((blocks_total + 255) / 256)), dim3(256), 0, s, jobs, njobs,
+                     blocks_total);
+  hipLaunchKernelGGL(k_blocks_scan_b, dim3(uint32_t(blocks_total)), dim3(256), 0, s, jobs, njobs);
   return hipGetLastError();
 }
 

@@ -21,10 +21,6 @@ struct ArraySrc {
 struct NoSink {
   __device__ void operator()(int64_t, int64_t, int64_t) const {}
 };
-// First tile of the segment that holds a tile (prefixes restart there).
-struct NoSeg {
-  __device__ int64_t operator()(int64_t) const { return 0; }
-};
 
 template <typename Src>
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const Src src, int64_t count,
@@ -86,28 +82,26 @@ __global__ void __launch_bounds__(1024) k_scan_top(int64_t* __restrict__ sums, i
 // Direct (few tiles): each tile adds up the sums of the tiles before it
 // itself (integer sums, exact in any order) and the last tile writes the
 // total, so no separate pass over the tile sums is launched.
-template <typename Src, int Mode, bool Direct, typename Sink, typename Seg>
+template <typename Src, int Mode, bool Direct, typename Sink>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const Src src, int64_t count,
                                                             const int64_t* __restrict__ offs,
                                                             int64_t* __restrict__ out64,
                                                             int32_t* __restrict__ out32,
                                                             int32_t* __restrict__ keys,
-                                                            int64_t* __restrict__ total, const Sink sink,
-                                                            const Seg seg) {
+                                                            int64_t* __restrict__ total, const Sink sink) {
   __shared__ int64_t wtot[kScanThreads / kWave];
   __shared__ int64_t pre_sh[kScanThreads / kWave];
   int64_t tile_pre = 0;
-  const int64_t first = seg(blockIdx.x);
   if constexpr (Direct) {
     int64_t acc = 0;
-    for (int64_t j = first + threadIdx.x; j < int64_t(blockIdx.x); j += kScanThreads) acc += offs[j];
+    for (int64_t j = threadIdx.x; j < int64_t(blockIdx.x); j += kScanThreads) acc += offs[j];
     acc = wave_sum_i64(acc);
     if (lane_id() == 0) pre_sh[threadIdx.x / kWave] = acc;
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < kScanThreads / kWave; ++w) tile_pre += pre_sh[w];
   } else {
-    tile_pre = offs[blockIdx.x] - (first > 0 ? offs[first] : 0);
+    tile_pre = offs[blockIdx.x];
   }
   const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
   int64_t vals[kScanItems];
@@ -143,10 +137,10 @@ size_t scan_scratch_bytes(int64_t count) {
   return size_t((nb + 1) * sizeof(int64_t) + 256);
 }
 
-template <int Mode, typename Src, typename Sink = NoSink, typename Seg = NoSeg>
+template <int Mode, typename Src, typename Sink = NoSink>
 static hipError_t scan_impl(hipStream_t s, const Src in, int64_t count, int64_t* out64, int32_t* out32,
                             int32_t* keys, int64_t* total, void* scratch, size_t scratch_bytes,
-                            const Sink sink = Sink(), const Seg seg = Seg()) {
+                            const Sink sink = Sink()) {
   const int64_t nb = std::max<int64_t>(1, (count + kScanTile - 1) / kScanTile);
   if (scratch_bytes < size_t(nb * sizeof(int64_t))) return hipErrorInvalidValue;
   int64_t* sums = static_cast<int64_t*>(scratch);
@@ -154,15 +148,15 @@ static hipError_t scan_impl(hipStream_t s, const Src in, int64_t count, int64_t*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nb <= kDirectTiles) {
-    hipLaunchKernelGGL((k_scan_apply<Src, Mode, true, Sink, Seg>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s,
-                       in, count, sums, out64, out32, keys, total, sink, seg);
+    hipLaunchKernelGGL((k_scan_apply<Src, Mode, true, Sink>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s,
+                       in, count, sums, out64, out32, keys, total, sink);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, sums, nb, total);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_scan_apply<Src, Mode, false, Sink, Seg>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in,
-                     count, sums, out64, out32, keys, total, sink, seg);
+  hipLaunchKernelGGL((k_scan_apply<Src, Mode, false, Sink>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, in,
+                     count, sums, out64, out32, keys, total, sink);
   return hipGetLastError();
 }
 
@@ -174,47 +168,6 @@ hipError_t launch_scan_i64(hipStream_t s, const int64_t* in, int64_t* out, int64
 hipError_t launch_flags_to_slots(hipStream_t s, const int32_t* flag, int64_t count, int32_t* slot, int32_t* keys,
                                  int64_t* total, void* scratch, size_t scratch_bytes) {
   return scan_impl<1>(s, ArraySrc<int32_t>{flag}, count, nullptr, slot, keys, total, scratch, scratch_bytes);
-}
-
-// ---------------------------------------------------------------- batched build slots
-
-__device__ __forceinline__ int find_build_job(const BuildJob* __restrict__ jobs, int njobs, int64_t g) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].g2_base <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Each list's slot map (flag ? prefix : -1), its keys and its leaf count,
-// with prefixes that restart at every list's first tile.
-struct BuildSlotSink {
-  const BuildJob* jobs;
-  int njobs;
-  __device__ void operator()(int64_t g, int64_t v, int64_t pos) const {
-    const BuildJob& J = jobs[find_build_job(jobs, njobs, g)];
-    const int64_t m = g - J.g2_base, G2 = int64_t(J.G) * J.G;
-    if (m >= G2) return;  // tile padding
-    J.slot[m] = v ? int32_t(pos) : -1;
-    if (v) J.keys[pos] = int32_t(m);
-    if (m == G2 - 1) *J.total = pos + v;
-  }
-};
-struct BuildSeg {
-  const BuildJob* jobs;
-  int njobs;
-  __device__ int64_t operator()(int64_t tile) const {
-    return jobs[find_build_job(jobs, njobs, tile * kScanTile)].tile_base;
-  }
-};
-
-hipError_t launch_build_slots(hipStream_t s, const BuildJob* jobs, int njobs, const int32_t* flags,
-                              int64_t flags_total, void* scratch, size_t scratch_bytes) {
-  static_assert(kBuildTile == kScanTile, "lists start on scan tiles");
-  return scan_impl<0>(s, ArraySrc<int32_t>{flags}, flags_total, nullptr, nullptr, nullptr, nullptr, scratch,
-                      scratch_bytes, BuildSlotSink{jobs, njobs}, BuildSeg{jobs, njobs});
 }
 
 // ---------------------------------------------------------------- truncation
@@ -247,17 +200,17 @@ __device__ __forceinline__ bool key_le(uint64_t sb, uint32_t m, uint64_t khi, ui
   return sb < khi || (sb == khi && m <= klo);
 }
 
-// Candidates (non-null leaves with s <= tau^2), counted by the scan's source
-// and compacted into (s, Morton index) lists by its sink.
-struct TruncFlagSrc {
-  const TruncJob* jobs;
-  int njobs;
-  __device__ int64_t operator()(int64_t g) const {
-    const TruncJob& J = jobs[find_job(jobs, njobs, g)];
-    const int64_t m = g - J.base;
-    return (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
-  }
-};
+// Candidates (non-null leaves with s <= tau^2) are flagged, scanned, and
+// compacted into (s, Morton index) lists by the scan's sink, which looks up
+// the job of flagged entries only.
+__global__ void k_trunc_flag(const TruncJob* __restrict__ jobs, int njobs, int64_t total, int32_t* __restrict__ flag) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const TruncJob& J = jobs[find_job(jobs, njobs, g)];
+  const int64_t m = g - J.base;
+  flag[g] = (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
+}
+
 struct TruncCompactSink {
   const TruncJob* jobs;
   int njobs;
@@ -448,7 +401,7 @@ __global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int6
 static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t trunc_batch_scratch_bytes(int njobs, int64_t total) {
-  return al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) + al256(total * 8) +
+  return al256(total * 4) + al256((total + 1) * 8) + al256(total * 8) + al256(total * 4) + al256(total * 8) +
          al256(size_t(njobs) * 24) + al256(scan_scratch_bytes(total));
 }
 
@@ -457,6 +410,8 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   if (njobs == 0) return hipSuccess;
   if (scratch_bytes < trunc_batch_scratch_bytes(njobs, total)) return hipErrorInvalidValue;
   char* p = static_cast<char*>(scratch);
+  int32_t* flag = reinterpret_cast<int32_t*>(p);
+  p += al256(total * 4);
   int64_t* pos = reinterpret_cast<int64_t*>(p);
   p += al256((total + 1) * 8);
   double* cs = reinterpret_cast<double*>(p);
@@ -468,8 +423,11 @@ hipError_t launch_trunc_batch(hipStream_t s, const TruncJob* jobs, int njobs, in
   uint64_t* kst = reinterpret_cast<uint64_t*>(p);
   p += al256(size_t(njobs) * 24);
   const uint32_t nb = uint32_t((total + 255) / 256);
-  hipError_t e = scan_impl<0>(s, TruncFlagSrc{jobs, njobs}, total, pos, nullptr, nullptr, pos + total, p,
-                              scan_scratch_bytes(total), TruncCompactSink{jobs, njobs, cs, cm});
+  hipLaunchKernelGGL(k_trunc_flag, dim3(nb), dim3(256), 0, s, jobs, njobs, total, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_impl<0>(s, ArraySrc<int32_t>{flag}, total, pos, nullptr, nullptr, pos + total, p,
+                   scan_scratch_bytes(total), TruncCompactSink{jobs, njobs, cs, cm});
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_trunc_fx, dim3(uint32_t(njobs) * kSelSplit), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx);
   hipLaunchKernelGGL(k_trunc_select, dim3(uint32_t(njobs)), dim3(kSelThreads), 0, s, jobs, pos, cs, cm, fx, kst);

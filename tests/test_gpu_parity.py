@@ -108,8 +108,8 @@ def test_block_list_batch_build(ctx):
         assert torch.equal(ctx.to_dense(M), ctx.to_dense(S))
         S.release()
         M.release()
-    # an empty G = 2048 list first: the batch's slot scan takes the
-    # three-launch path, and the small list's prefixes restart on its tile
+    # an empty G = 2048 list beside a small one (lists of very different
+    # sizes in one call)
     e_c = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
     e_d = torch.zeros((0, 64, 64), dtype=torch.float64, device="cuda")
     big, small = ctx.build_blocks_batch([(131072, 64, e_c, e_d), lists[0]])
