@@ -961,12 +961,28 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
   SPAMM_HIP(c, launch_gather_totals(c->stream, rd0, count, cnt_bits, P<int64_t>(scanned), totals_d));
   }
+  // the parts of every C whose size does not depend on the counts are set up
+  // while the counting pass runs
+  std::vector<std::unique_ptr<spamm_mat>> Cs(count);
+  std::vector<RegionP> cand_r(count), trace_r(count);
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    st = new_matrix(c, q.A->n, q.A->bs, Cs[r]);
+    if (st != SPAMM_OK) return st;
+    spamm_mat* C = Cs[r].get();
+    const int64_t G2 = int64_t(C->G) * C->G;
+    ALLOC(C->plan_off, (G2 + 1) * 8, "plan offsets");
+    ALLOC(C->plan_bnd, G2 * 8, "skipped bounds");
+    ALLOC(cand_r[r], G2 * 4, "candidate counts");
+    ALLOC(trace_r[r], int64_t(C->G) * 8, "trace parts");
+    C->store = std::make_shared<Store>();
+    C->plan_Astore = Au[r]->store;
+    C->plan_Bstore = Bu[r]->store;
+  }
   SPAMM_HIP(c, hipStreamSynchronize(c->stream));
   const std::vector<ReqTotals> ht(totals_h, totals_h + count);
 
   // ---- allocate results; work units grouped by (precision, leaf size)
-  std::vector<std::unique_ptr<spamm_mat>> Cs(count);
-  std::vector<RegionP> cand_r(count), trace_r(count);
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < count; ++r) groups[{reqs[r].prec, reqs[r].A->bs}].push_back(r);
   int64_t wu_total = 0;
@@ -982,23 +998,13 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
     ReqDev& d = rd[r];
-    std::unique_ptr<spamm_mat> C;
-    st = new_matrix(c, q.A->n, q.A->bs, C);
-    if (st != SPAMM_OK) return st;
-    const int64_t G2 = int64_t(C->G) * C->G;
+    spamm_mat* C = Cs[r].get();
     const int64_t nk = ht[r].n_kept, cn = ht[r].c_nonnull;
     C->nonnull = cn;
     C->n_kept = nk;
-    C->store = std::make_shared<Store>();
     st = alloc_store(c, *C->store, cn, C->bs, q.prec == SPAMM_F64 ? SPAMM_STORE_F64 : SPAMM_STORE_F32);
     if (st != SPAMM_OK) return st;
-    ALLOC(C->plan_off, (G2 + 1) * 8, "plan offsets");
     ALLOC(C->plan_pairs, std::max<int64_t>(nk, 1) * 8, "plan pairs");
-    ALLOC(C->plan_bnd, G2 * 8, "skipped bounds");
-    ALLOC(cand_r[r], G2 * 4, "candidate counts");
-    ALLOC(trace_r[r], int64_t(C->G) * 8, "trace parts");
-    C->plan_Astore = Au[r]->store;
-    C->plan_Bstore = Bu[r]->store;
     d.pairs = P<int2>(C->plan_pairs);
     d.off = P<int64_t>(C->plan_off);
     d.cslot = P<int32_t>(C->slot);
@@ -1057,7 +1063,6 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       d.alpha = 1.0;
       d.beta = 0.0;
     }
-    Cs[r] = std::move(C);
   }
   // placement tables of each launch group: pre[x][k] = units of slice x
   // before request k's part, Q[x] = first unit of slice x (group-relative)
