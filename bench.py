@@ -361,15 +361,15 @@ def cpu_baseline(host, min_s=10.0):
                       f"NumPy FP64, one BLAS thread"}
 
 
-def traffic_for(flops_per_launch):
+def traffic_for(tile):
     """HBM bytes per GEMM launch from the committed rocprofv3 counter summary,
-    only when it was taken on the current kernel source."""
+    only when it was taken on the current kernel source and tile variant."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
     src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != src:
+    if rec.get("kernel_source_sha256") != src or rec.get("kernel") != f"void spamm::k_gemm<1, 64, {tile}>":
         return None
     return rec.get("bytes_per_launch")
 
@@ -422,6 +422,7 @@ def main():
     gemm_per_launch_ms = tm32["gemm_ms"] / max(tm32["gemm_launches"], 1)
     flops_per_launch = tm32["gemm_flops"] / max(tm32["gemm_launches"], 1)
     achieved = flops_per_launch / (gemm_per_launch_ms * 1e-3) / 1e12
+    tile = ctx.get_option("gemm_tile")
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -444,10 +445,11 @@ def main():
         "kept_products_per_step": int(sum(s["n_kept"] for s in stats32)),
         "phases_ms_per_step": {k: round(tm32[k + "_ms"] / args.steps, 4)
                                for k in ("build", "trunc", "prune", "gemm", "pyramid")},
-        "roofline": {"kernel": "k_gemm<SPAMM_F32,64> (persistent MFMA leaf GEMM)", "bound": "mfma",
+        "roofline": {"kernel": f"k_gemm<SPAMM_F32,64,{tile}> (persistent MFMA leaf GEMM, "
+                               f"{'16x16' if tile else '32x32'} MFMA tiles)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": traffic_for(flops_per_launch),
+                     "traffic": traffic_for(tile),
                      "flops_per_launch": flops_per_launch, "ms_per_launch": round(gemm_per_launch_ms, 5)},
     }
     if not args.skip_extras:

@@ -162,8 +162,9 @@ spamm_status spamm_ctx_destroy(spamm_ctx* ctx);
 spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
 
 /* Tunable behaviour of a context (spamm_ctx_set_option / get_option).
- *  SPAMM_OPT_GEMM_TILE  0: 32 x 32 MFMA tiles for FP32 / BF16 leaf products
- *                       where a wave's tile allows it (default); 1: 16 x 16.
+ *  SPAMM_OPT_GEMM_TILE  1: 16 x 16 MFMA tiles (default); 0: 32 x 32 tiles
+ *                       for FP32 / BF16 leaf products where a wave's tile
+ *                       allows it.  FP64 always takes 16 x 16.
  *  SPAMM_OPT_PLACEMENT  0: each request's C leaves in eight Morton slices,
  *                       one per XCD (default); 1: request after request.
  *  SPAMM_OPT_GRAPH      0: launch the kernels of a batch one by one

@@ -142,7 +142,7 @@ struct Ctx {
   std::vector<hipEvent_t> up_events;
   int n_cu = 256;
   int gemm_sched = 0;  // work-unit placement: 0 per-XCD Morton slices, 1 request-major
-  int gemm_tile = 0;   // GEMM variant (MFMA tile shape), see launch_gemm
+  int gemm_tile = 1;   // GEMM variant (MFMA tile shape), see launch_gemm
   int gemm_interleave = -1;  // GemmArgs::interleave (chunk of consecutive units, 0: contiguous ranges,
                              // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph

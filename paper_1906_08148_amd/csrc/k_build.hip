@@ -1,6 +1,7 @@
 // Build-time kernels: leaf norms and null flags (Sec. 2, Sec. 4.2, Sec. 4.4),
-// compaction into the Morton-ordered leaf store, derived compute copies, the
-// row/column views used by pruning, and the squared-norm pyramid.
+// compaction into the leaf store (Morton order for a dense input, list order
+// for a block list), derived compute copies, the row/column views used by
+// pruning, and the squared-norm pyramid.
 #include "internal.h"
 #include "kern_common.h"
 

@@ -23,8 +23,9 @@
 //
 // Tiling (wave64, gfx950): the C leaf is split over a 2 x 2 grid of waves
 // (one wave for 16 x 16 leaves).  MFMA tiles: v_mfma_f64_16x16x4f64 (FP64),
-// v_mfma_f32_32x32x2f32 (FP32; 16x16x4 where a wave's tile is 16 wide),
-// v_mfma_f32_32x32x16_bf16 / 16x16x32_bf16 (BF16; split-BF16 takes three
+// v_mfma_f32_16x16x4f32 (FP32, variant 1) or 32x32x2f32 (variant 0, where a
+// wave's tile is 32 wide), v_mfma_f32_16x16x32_bf16 / 32x32x16_bf16 (BF16,
+// the same two variants; split-BF16 takes three
 // products per step, lo*hi + hi*lo + hi*hi, in FP32).  A k-panel of A (BS x KP)
 // is staged row-major with a 16-byte row pad.  For FP32/FP64 the k-panel of
 // B (KP x BS) is row-major with an XOR column swizzle so the lane groups of

@@ -355,7 +355,7 @@ class Context:
     OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2, "unit_order": 3}  # unit_order: chunk size (0: contiguous ranges)
 
     def set_option(self, name: str, value: int):
-        """gemm_tile (0: 32x32 MFMA tiles, 1: 16x16), placement (0: XCD
+        """gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
         slices, 1: request-major), graph (1: one captured graph per batch)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 

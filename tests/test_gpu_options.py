@@ -58,7 +58,8 @@ def test_graph_launch_equals_eager_over_replays():
 def test_tile_variant_parity(prec):
     print(f"case: tile variant prec={prec}", flush=True)
     ctx = spamm.Context(arena_bytes=1 << 30)
-    ctx.set_option("gemm_tile", 1)
+    assert ctx.get_option("gemm_tile") == 1  # the default; the other parity tests run it
+    ctx.set_option("gemm_tile", 0)
     A = synth.DecaySpec("1d", 2100, 0.3, seed=5).dense()
     for bs in (32, 64, 128):
         T = O.build(A, bs)
