@@ -979,8 +979,17 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     C->plan_Astore = Au[r]->store;
     C->plan_Bstore = Bu[r]->store;
   }
+  RegionP part;
+  if (st_out) ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
   SPAMM_HIP(c, hipStreamSynchronize(c->stream));
   const std::vector<ReqTotals> ht(totals_h, totals_h + count);
+  // the partial statistics need only the counting pass: they run while the
+  // host lays out the results
+  if (st_out) {
+    TimedScope ts(c, kTPrune);
+    SPAMM_HIP(c, launch_stats_partial(c->stream, pre.at<ReqDev>(o_rd), count, total_chunks, P<double>(bnd_all),
+                                      P<int32_t>(cand_all), P<StatPartial>(part)));
+  }
 
   // ---- allocate results; work units grouped by (precision, leaf size)
   std::map<std::pair<int, int>, std::vector<int>> groups;
@@ -1148,10 +1157,8 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   if (st != SPAMM_OK) return st;
   const ReqDev* reqd = postt.at<ReqDev>(o_req);
   const PyrJob* pyr_jd = postt.at<PyrJob>(o_pyr);
-  RegionP part;
   ReqStatsDev* sd_dev = reinterpret_cast<ReqStatsDev*>(c->res_dev + res_tot);
   const ReqStatsDev* sd_host = reinterpret_cast<const ReqStatsDev*>(c->res_host + res_tot);
-  if (st_out) ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
   auto post = [&]() -> spamm_status {
     {
       TimedScope ts(c, kTPrune);
@@ -1204,9 +1211,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     }
     spamm_status s2 = pyramids_launch(c, pyr_jd, pyr_jobs);
     if (s2 != SPAMM_OK) return s2;
-    if (st_out)
-      SPAMM_HIP(c, launch_req_stats(c->stream, reqd, count, total_chunks, P<StatPartial>(part),
-                                    sd_dev));
+    if (st_out) SPAMM_HIP(c, launch_stats_final(c->stream, reqd, count, P<StatPartial>(part), sd_dev));
     return SPAMM_OK;
   };
   if (c->use_graph && !c->timing) {

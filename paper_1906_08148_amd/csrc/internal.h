@@ -420,8 +420,10 @@ hipError_t launch_gershgorin(hipStream_t s, int64_t n, int bs, int G, const int3
 hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int32_t* slot, const double* f64,
                                 const float* f32, const int32_t* ij, double* out);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
-hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,
-                            ReqStatsDev* out);
+hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
+                                const double* bnd_all, const int32_t* cand_all, StatPartial* partial);
+hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const StatPartial* partial,
+                              ReqStatsDev* out);
 hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
                            const double* f64, const float* f32, double* out, int64_t ld);
 hipError_t launch_decode_kept(hipStream_t s, int G, const int64_t* off, const int2* pairs, int64_t aoff,

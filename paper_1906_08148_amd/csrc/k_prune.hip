@@ -453,8 +453,12 @@ hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_
 // chunks of kStatChunk C leaves (one workgroup each), then one workgroup per
 // request adds its partials in chunk order with the trace parts and gathers
 // the pyramid roots and truncation results, so that one copy brings every
-// statistic to the host.
+// statistic to the host.  The partial sums read the batch-wide skipped bounds
+// and candidate counts of the counting pass (C leaf c of a request at cbase +
+// c), so they can run before the fill pass.
 __global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict__ reqs, int nreq,
+                                                       const double* __restrict__ bnd_all,
+                                                       const int32_t* __restrict__ cand_all,
                                                        StatPartial* __restrict__ partial) {
   __shared__ double red[4];
   __shared__ int64_t ired[4];
@@ -471,12 +475,14 @@ __global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict_
   const int64_t c1 = min<int64_t>(G2, c0 + kStatChunk);
   double b1 = 0.0, b2 = 0.0;
   int64_t cand = 0;
+  const double* bnd = bnd_all + R.cbase;
+  const int32_t* ncand = cand_all + R.cbase;
   for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-    const double b = R.bnd[c];
+    const double b = bnd[c];
     b1 += b;
     const double bb = b * b;
     b2 += bb;
-    cand += R.ncand[c];
+    cand += ncand[c];
   }
   b1 = block_sum_f64(b1, red);
   b2 = block_sum_f64(b2, red);
@@ -526,12 +532,17 @@ __global__ void __launch_bounds__(256) k_stats_final(const ReqDev* __restrict__ 
   }
 }
 
-hipError_t launch_req_stats(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks, StatPartial* partial,
-                            ReqStatsDev* out) {
+hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
+                                const double* bnd_all, const int32_t* cand_all, StatPartial* partial) {
+  if (nreq == 0 || nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stats_partial, dim3(uint32_t(nchunks)), dim3(256), 0, s, reqs, nreq, bnd_all, cand_all,
+                     partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const StatPartial* partial,
+                              ReqStatsDev* out) {
   if (nreq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stats_partial, dim3(uint32_t(nchunks)), dim3(256), 0, s, reqs, nreq, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_stats_final, dim3(uint32_t(nreq)), dim3(256), 0, s, reqs, partial, out);
   return hipGetLastError();
 }
