@@ -472,6 +472,81 @@ def multiply(A: Tree, B: Tree, tau: float, mode: int, c_blocks=None) -> Result:
     return Result(C, kept, Au, Bu, bnd, stats)
 
 
+# Unit roundoffs: FP64, FP32 and BF16 (8 significand bits, round to nearest).
+U64, U32, U16 = 2.0 ** -53, 2.0 ** -24, 2.0 ** -8
+# Compute precisions of the leaf products: FP64 inputs and sums; FP32 inputs
+# and sums; BF16 inputs (the FP32 value rounded to BF16) with FP32 sums;
+# split BF16 (x ~ hi + lo, both BF16, products hi*hi + hi*lo + lo*hi) with
+# FP32 sums.
+P_F64, P_F32, P_BF16, P_BF16X3 = "f64", "f32", "bf16", "bf16x3"
+
+
+def gamma(n: float, u: float) -> float:
+    """gamma_n = n u / (1 - n u): the classical bound on the relative error
+    accumulated by n roundings (Higham, Accuracy and Stability of Numerical
+    Algorithms, Lemma 3.1)."""
+    return n * u / (1.0 - n * u)
+
+
+def rounding_coefficient(prec: str, bs: int, m: int) -> float:
+    """c such that every entry of the computed sum of m leaf products of
+    order bs differs from the exact sum of those products by at most
+    c * (sum_k |A_ik| |B_kj|) entry-wise.
+
+    Two parts: the representation error of the inputs in the compute
+    precision (e_in, for a product of two represented values) and the
+    roundings of the sum (gamma over the longest chain of roundings an entry
+    goes through: one product rounding, bs - 1 additions inside a leaf
+    product, three times that for split BF16, and m additions across
+    products), scaled by the size of the represented inputs (mag).  This is
+    a bound we define for the output accounting; the paper gives none.
+    """
+    if prec == P_F64:
+        e_in, mag, u, depth = 0.0, 1.0, U64, bs + m + 1
+    elif prec == P_F32:
+        e = U32  # FP64 -> FP32
+        e_in, mag, u, depth = 2.0 * e + e * e, (1.0 + e) ** 2, U32, bs + m + 1
+    elif prec == P_BF16:
+        e = U32 + U16 * (1.0 + U32)  # FP64 -> FP32 -> BF16
+        e_in, mag, u, depth = 2.0 * e + e * e, (1.0 + e) ** 2, U32, bs + m + 1
+    elif prec == P_BF16X3:
+        e3 = U32 + U16 * U16 * (1.0 + U32)  # |hi + lo - x| <= e3 |x|
+        el = (1.0 + U16) * U16 * (1.0 + U32)  # |lo| <= el |x|
+        h = (1.0 + U16) * (1.0 + U32) + el  # |hi| + |lo| <= h |x|
+        # (hi_a + lo_a)(hi_b + lo_b) - lo_a lo_b against a b
+        e_in, mag, u, depth = 2.0 * e3 + e3 * e3 + el * el, h * h, U32, 3 * bs + m + 1
+    else:
+        raise ValueError("unknown precision")
+    return e_in + gamma(depth, u) * mag
+
+
+def precision_bound(res: "Result", prec: str) -> float:
+    """Bound on ||C_computed - C_kept||_F, where C_kept is the exact sum of the
+    kept products and C_computed the same sum formed in precision `prec`.
+
+    Per C leaf (I, J) with m kept products: ||E_IJ||_F <= c(m) * sum over
+    kept K (ascending) of ||A_IK||_F ||B_KJ||_F, since the Frobenius norm of
+    |A||B| is at most ||A||_F ||B||_F; the leaves are disjoint, so the
+    squares add.  Uses the operands actually multiplied.
+    """
+    Au, Bu, kept = res.A_used, res.B_used, res.kept
+    G, bs = Au.G, Au.bs
+    total = 0.0
+    if len(kept) == 0:
+        return 0.0
+    key = morton_key(kept[:, 0], kept[:, 2])
+    starts = np.flatnonzero(np.r_[True, key[1:] != key[:-1]])
+    ends = np.r_[starts[1:], len(kept)]
+    for a, b in zip(starts, ends):
+        s = 0.0
+        for t in range(a, b):  # k ascending
+            I, K, J = int(kept[t, 0]), int(kept[t, 1]), int(kept[t, 2])
+            s += math.sqrt(Au.leaf_sq[I, K]) * math.sqrt(Bu.leaf_sq[K, J])
+        e = rounding_coefficient(prec, bs, int(b - a)) * s
+        total += e * e
+    return math.sqrt(total)
+
+
 def exact_product(A_dense: np.ndarray, B_dense: np.ndarray) -> np.ndarray:
     """The untruncated product, the reference for the error E (Thms 1-3)."""
     return np.asarray(A_dense, dtype=np.float64) @ np.asarray(B_dense, dtype=np.float64)

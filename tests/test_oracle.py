@@ -471,3 +471,99 @@ def test_error_trends_in_n_and_tau():
         # element-wise O(tau): max |E_ij| / tau stays bounded
         emax = [np.max(np.abs(ex - O.multiply(T, T, t, m).C.to_dense())) / t for t in taus[::3]]
         assert max(emax) < 10.0
+
+
+# ---------------------------------------------------------------- rounding bound
+#
+# The bound of ``precision_bound`` covers the rounding of the kept products
+# formed in a lower precision.  It is pinned by forming those products the
+# way each precision does (inputs rounded, sums in FP32) and measuring the
+# error against the exact sum of the same products, and by invariants.
+
+def _bf16(x32):
+    """Round float32 values to BF16 (nearest, ties to even), as float32."""
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _formed(res, prec):
+    """C leaves of res summed over kept K ascending, each product and sum in
+    the arithmetic of `prec` (NumPy float32 stands in for the FP32 MFMA)."""
+    Au, Bu, kept = res.A_used, res.B_used, res.kept
+    out = {}
+    for I, K, J in kept:
+        a, b = Au.leaf(int(I), int(K)), Bu.leaf(int(K), int(J))
+        a32, b32 = a.astype(np.float32), b.astype(np.float32)
+        if prec == O.P_F32:
+            part = a32 @ b32
+        elif prec == O.P_BF16:
+            part = _bf16(a32) @ _bf16(b32)
+        else:
+            ha, hb = _bf16(a32), _bf16(b32)
+            la, lb = _bf16(a32 - ha), _bf16(b32 - hb)
+            part = (la @ hb + ha @ lb) + ha @ hb
+        key = (int(I), int(J))
+        out[key] = part if key not in out else (out[key] + part).astype(np.float32)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("kind,alpha,bs", [("1d", 0.15, 8), ("3d", 1.0, 16)])
+def test_rounding_bound_holds_for_formed_products(prec, kind, alpha, bs):
+    n = 256 if kind == "1d" else 192
+    A = synth.DecaySpec(kind, n, alpha, seed=11).dense()
+    T = O.build(A, bs)
+    for mode, tau in ((O.SPAMM, 1e-5), (O.HYBRID, 1e-7), (O.TRUNCMUL, 0.0)):
+        res = O.multiply(T, T, tau, mode)
+        formed = _formed(res, prec)
+        err2 = 0.0
+        for (I, J), c in formed.items():
+            ref = res.C.leaf(I, J)
+            err2 += float(np.sum((c.astype(np.float64) - ref) ** 2))
+        bound = O.precision_bound(res, prec)
+        # the FP64 oracle's own rounding is covered by the FP64 bound
+        assert math.sqrt(err2) <= bound + O.precision_bound(res, O.P_F64), (mode, math.sqrt(err2), bound)
+        assert math.sqrt(err2) > 0.0
+
+
+def test_rounding_bound_fp64_against_exact_rationals():
+    from fractions import Fraction
+    A = synth.DecaySpec("1d", 24, 0.4, seed=3).dense()
+    T = O.build(A, 4)
+    res = O.multiply(T, T, 1e-3, O.SPAMM)
+    err2 = Fraction(0)
+    by_leaf = {}
+    for I, K, J in res.kept:
+        by_leaf.setdefault((int(I), int(J)), []).append(int(K))
+    for (I, J), ks in by_leaf.items():
+        exact = [[Fraction(0)] * 4 for _ in range(4)]
+        for K in ks:
+            a, b = T.leaf(I, K), T.leaf(K, J)
+            for r in range(4):
+                for c in range(4):
+                    exact[r][c] += sum(Fraction(float(a[r, q])) * Fraction(float(b[q, c])) for q in range(4))
+        got = res.C.leaf(I, J)
+        for r in range(4):
+            for c in range(4):
+                err2 += (Fraction(float(got[r, c])) - exact[r][c]) ** 2
+    assert float(err2) ** 0.5 <= O.precision_bound(res, O.P_F64)
+
+
+def test_rounding_bound_invariants():
+    A = synth.DecaySpec("1d", 128, 0.3, seed=5).dense()
+    T = O.build(A, 8)
+    res = O.multiply(T, T, 1e-6, O.SPAMM)
+    b = {p: O.precision_bound(res, p) for p in (O.P_F64, O.P_F32, O.P_BF16X3, O.P_BF16)}
+    # finer arithmetic, smaller bound
+    assert 0.0 < b[O.P_F64] < b[O.P_F32] < b[O.P_BF16X3] < b[O.P_BF16]
+    # linear in the operands' scale: scaling A by 2^5 scales every product
+    # norm, and the bound, by exactly 2^5
+    T2 = O.build(A * 32.0, 8)
+    res2 = O.multiply(T2, T2, 1e-6 * 1024.0, O.SPAMM)
+    assert np.array_equal(res2.kept, res.kept)
+    assert O.precision_bound(res2, O.P_F32) == 1024.0 * b[O.P_F32]
+    # more products per C leaf, larger coefficient; nothing kept, zero bound
+    assert O.rounding_coefficient(O.P_F32, 8, 10) > O.rounding_coefficient(O.P_F32, 8, 1)
+    empty = O.multiply(T, T, 1e9, O.SPAMM)
+    assert len(empty.kept) == 0 and O.precision_bound(empty, O.P_F32) == 0.0
