@@ -97,6 +97,16 @@ typedef struct spamm_stats {
   double err_bound;     /* bound on ||A B - C||_F from the terms above       */
   double trace;         /* trace of C (sum of diagonal-leaf diagonals)       */
   double normC;         /* ||C||_F                                           */
+  double prec_bound;    /* bound on ||C - C_kept||_F from rounding, where
+                           C_kept is the exact sum of the kept products: per
+                           C leaf with m kept products of order bs, c(m) times
+                           the sum of their ||A_ik||_F ||B_kj||_F, with c(m) =
+                           e_in + gamma_n mag for the compute precision (input
+                           representation error e_in, n = bs + m + 1 roundings,
+                           3 bs + m + 1 for split BF16); root-sum-square over
+                           C leaves.  Covers the product before an epilogue.
+                           The total error against A B is at most err_bound +
+                           prec_bound.                                       */
 } spamm_stats;
 
 /* Optional epilogue: C = alpha * (approximate A B) + beta * D, with D a

@@ -525,26 +525,23 @@ def precision_bound(res: "Result", prec: str) -> float:
     kept products and C_computed the same sum formed in precision `prec`.
 
     Per C leaf (I, J) with m kept products: ||E_IJ||_F <= c(m) * sum over
-    kept K (ascending) of ||A_IK||_F ||B_KJ||_F, since the Frobenius norm of
-    |A||B| is at most ||A||_F ||B||_F; the leaves are disjoint, so the
-    squares add.  Uses the operands actually multiplied.
+    kept K of ||A_IK||_F ||B_KJ||_F, since the Frobenius norm of |A||B| is
+    at most ||A||_F ||B||_F; the leaves are disjoint, so the squares add.
+    Uses the operands actually multiplied.
     """
     Au, Bu, kept = res.A_used, res.B_used, res.kept
-    G, bs = Au.G, Au.bs
-    total = 0.0
     if len(kept) == 0:
         return 0.0
-    key = morton_key(kept[:, 0], kept[:, 2])
+    I, K, J = kept[:, 0], kept[:, 1], kept[:, 2]
+    key = morton_key(I, J)  # kept is grouped by C leaf
     starts = np.flatnonzero(np.r_[True, key[1:] != key[:-1]])
-    ends = np.r_[starts[1:], len(kept)]
-    for a, b in zip(starts, ends):
-        s = 0.0
-        for t in range(a, b):  # k ascending
-            I, K, J = int(kept[t, 0]), int(kept[t, 1]), int(kept[t, 2])
-            s += math.sqrt(Au.leaf_sq[I, K]) * math.sqrt(Bu.leaf_sq[K, J])
-        e = rounding_coefficient(prec, bs, int(b - a)) * s
-        total += e * e
-    return math.sqrt(total)
+    m = np.diff(np.r_[starts, len(kept)])
+    prod = np.sqrt(Au.leaf_sq[I, K]) * np.sqrt(Bu.leaf_sq[K, J])
+    per_leaf = np.add.reduceat(prod, starts)
+    ms, inv = np.unique(m, return_inverse=True)
+    coef = np.array([rounding_coefficient(prec, Au.bs, int(x)) for x in ms])[inv]
+    e = coef * per_leaf
+    return math.sqrt(float(np.sum(e * e)))
 
 
 def exact_product(A_dense: np.ndarray, B_dense: np.ndarray) -> np.ndarray:

@@ -937,11 +937,12 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
     return fail(c, SPAMM_EDEVICE, "hipHostMalloc of the result buffer failed");
   ReqTotals* totals_h = reinterpret_cast<ReqTotals*>(c->res_host);
   ReqTotals* totals_d = reinterpret_cast<ReqTotals*>(c->res_dev);
-  RegionP packed, scanned, bnd_all, cand_all, scan_scr;
+  RegionP packed, scanned, bnd_all, cand_all, pb_all, scan_scr;
   ALLOC(packed, total_c * 8, "counts");
   ALLOC(scanned, (total_c + 1) * 8, "offsets");
   ALLOC(bnd_all, total_c * 8, "bounds");
   ALLOC(cand_all, total_c * 4, "candidates");
+  ALLOC(pb_all, total_c * 8, "rounding bounds");
   const size_t ssb = scan_scratch_bytes(total_c);
   ALLOC(scan_scr, ssb, "scan scratch");
   TableSet pre;
@@ -957,7 +958,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   TimedScope ts(c, kTPrune);
   const ReqDev* rd0 = pre.at<ReqDev>(o_rd);
   SPAMM_HIP(c, launch_prune_count(c->stream, rd0, count, total_c, cnt_bits, P<int64_t>(packed), P<double>(bnd_all),
-                                  P<int32_t>(cand_all)));
+                                  P<int32_t>(cand_all), P<double>(pb_all)));
   SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(packed), P<int64_t>(scanned), total_c, scan_scr->ptr(), ssb));
   SPAMM_HIP(c, launch_gather_totals(c->stream, rd0, count, cnt_bits, P<int64_t>(scanned), totals_d));
   }
@@ -988,7 +989,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
   if (st_out) {
     TimedScope ts(c, kTPrune);
     SPAMM_HIP(c, launch_stats_partial(c->stream, pre.at<ReqDev>(o_rd), count, total_chunks, P<double>(bnd_all),
-                                      P<int32_t>(cand_all), P<StatPartial>(part)));
+                                      P<int32_t>(cand_all), P<double>(pb_all), P<StatPartial>(part)));
   }
 
   // ---- allocate results; work units grouped by (precision, leaf size)
@@ -1274,6 +1275,7 @@ spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_req
       o.normA_used = std::sqrt(hs[r].normAu_sq);
       o.dA = std::sqrt(hs[r].dA_sq);
       o.dB = std::sqrt(hs[r].dB_sq);
+      o.prec_bound = std::sqrt(hs[r].pb_sq);
       if (q.mode == SPAMM_SPAMM) o.err_bound = o.B2;
       else if (q.mode == SPAMM_TRUNCMUL) o.err_bound = o.dA * o.normB + o.normA_used * o.dB;
       else o.err_bound = o.dA * o.normB + o.normA_used * o.dB + o.B2;

@@ -326,15 +326,15 @@ struct ReqTotals {
 struct ReqStatsDev {
   double B1, B2sq, trace, normC_sq;
   double normA_sq, normB_sq, normAu_sq, dA_sq, dB_sq;
+  double pb_sq;  // squared rounding bound of the kept products
   int64_t n_candidates;
 };
 
 constexpr int kStatChunk = 4096;  // C leaves per partial-statistics workgroup
 
 struct StatPartial {
-  double b1, b2;
+  double b1, b2, pb;
   int64_t cand;
-  int64_t pad_;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -394,7 +394,7 @@ size_t trunc_batch_scratch_bytes(int njobs, int64_t total);
 // per C leaf into one int64, so that one scan gives both prefixes; the host
 // picks cnt_bits per batch so that neither field can overflow.
 hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
-                              int64_t* packed, double* bnd_all, int32_t* cand_all);
+                              int64_t* packed, double* bnd_all, int32_t* cand_all, double* pb_all);
 hipError_t launch_gather_totals(hipStream_t s, const ReqDev* reqs, int nreq, int cnt_bits,
                                 const int64_t* scanned, ReqTotals* out);
 // writes the kept pairs, C's slot map and the work units (with their cost,
@@ -421,7 +421,8 @@ hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int3
                                 const float* f32, const int32_t* ij, double* out);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
 hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
-                                const double* bnd_all, const int32_t* cand_all, StatPartial* partial);
+                                const double* bnd_all, const int32_t* cand_all, const double* pb_all,
+                                StatPartial* partial);
 hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const StatPartial* partial,
                               ReqStatsDev* out);
 hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,

@@ -151,11 +151,47 @@ struct CountLds {
   uint8_t fl[kPW];    // bit 0: both leaves non-null, bit 1: kept
 };
 
+// Rounding coefficient of one C leaf summed from m kept products of order bs
+// in precision prec: every entry of the computed sum lies within c * sum_k
+// |A_ik| |B_kj| of the exact sum of those products.  c = e_in + gamma_n *
+// mag: e_in bounds the representation error of the inputs in the compute
+// precision (for a product of two inputs), gamma_n = n u / (1 - n u) the
+// roundings of the sum along its longest chain (one product rounding, the
+// bs - 1 additions of a leaf product, three times that for split BF16, and
+// m additions across products), mag the size of the represented inputs.
+__device__ double rounding_coef(int prec, int bs, int64_t m) {
+  const double u64 = 0x1p-53, u32 = 0x1p-24, u16 = 0x1p-8;
+  double e_in, mag, u, depth;
+  if (prec == SPAMM_F64) {
+    e_in = 0.0;
+    mag = 1.0;
+    u = u64;
+    depth = double(bs + m + 1);
+  } else if (prec == SPAMM_F32 || prec == SPAMM_BF16) {
+    const double e = prec == SPAMM_F32 ? u32 : u32 + u16 * (1.0 + u32);  // FP64 -> FP32 (-> BF16)
+    e_in = 2.0 * e + e * e;
+    mag = (1.0 + e) * (1.0 + e);
+    u = u32;
+    depth = double(bs + m + 1);
+  } else {
+    const double e3 = u32 + u16 * u16 * (1.0 + u32);    // |hi + lo - x| <= e3 |x|
+    const double el = (1.0 + u16) * u16 * (1.0 + u32);  // |lo| <= el |x|
+    const double h = (1.0 + u16) * (1.0 + u32) + el;    // |hi| + |lo| <= h |x|
+    e_in = 2.0 * e3 + e3 * e3 + el * el;                // lo_a lo_b is not formed
+    mag = h * h;
+    u = u32;
+    depth = double(3 * bs + m + 1);
+  }
+  const double nu = depth * u;
+  return e_in + nu / (1.0 - nu) * mag;
+}
+
 __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* __restrict__ reqs, int nreq,
                                                                  int64_t total_c, int cb,
                                                                  int64_t* __restrict__ packed,
                                                                  double* __restrict__ bnd_all,
-                                                                 int32_t* __restrict__ cand_all) {
+                                                                 int32_t* __restrict__ cand_all,
+                                                                 double* __restrict__ pb_all) {
   __shared__ int64_t sc[kReqLds];
   __shared__ CountLds wl[kPWaves];
   cache_cbase(reqs, nreq, sc);
@@ -170,7 +206,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
   const int sst = incl - span;
   const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
   int64_t my_cnt = 0, my_cand = 0;
-  double my_skip = 0.0;
+  double my_skip = 0.0, my_kept = 0.0;  // skipped and kept norm products
   const int maxspan = wave_max_i32(span);
   if (maxspan > kLongSpan) {
     // long ranges: every lane walks its own leaf, k ascending, with eight
@@ -195,6 +231,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
           my_cand += both ? 1 : 0;
           my_cnt += keep ? 1 : 0;
           my_skip += (both && !keep) ? pr : 0.0;
+          my_kept += keep ? pr : 0.0;
         }
       }
     }
@@ -229,7 +266,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
           const bool both = (a[u] >= 0.0) && (bv[u] >= 0.0);
           const double pr = a[u] * bv[u];
           const bool keep = both && (tau < 0.0 || pr >= tau);
-          L.v[t - wb] = (both && !keep) ? pr : 0.0;
+          L.v[t - wb] = both ? pr : 0.0;
           L.fl[t - wb] = uint8_t((both ? 1 : 0) | (keep ? 2 : 0));
         }
       }
@@ -251,14 +288,17 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
         for (int q = 0; q < 8; ++q) {
           my_cand += f[q] & 1;
           my_cnt += f[q] >> 1;
-          my_skip += v[q];
+          my_skip += (f[q] & 2) ? 0.0 : v[q];
+          my_kept += (f[q] & 2) ? v[q] : 0.0;
         }
       }
       for (; t < s1; ++t) {
         const int f = L.fl[t];
+        const double v = L.v[t];
         my_cand += f & 1;
         my_cnt += f >> 1;
-        my_skip += L.v[t];
+        my_skip += (f & 2) ? 0.0 : v;
+        my_kept += (f & 2) ? v : 0.0;
       }
       wave_lds_sync();
     }
@@ -270,15 +310,16 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
     packed[g] = (flag << cb) | my_cnt;
     bnd_all[g] = my_skip;
     cand_all[g] = int32_t(my_cand);
+    pb_all[g] = rounding_coef(R.prec, R.bs, my_cnt) * my_kept;
   }
 }
 
 hipError_t launch_prune_count(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c, int cnt_bits,
-                              int64_t* packed, double* bnd_all, int32_t* cand_all) {
+                              int64_t* packed, double* bnd_all, int32_t* cand_all, double* pb_all) {
   const int64_t waves = (total_c + kWave - 1) / kWave;
   const int64_t blocks = (waves + kPWaves - 1) / kPWaves;
   hipLaunchKernelGGL(k_prune_count, dim3(uint32_t(blocks)), dim3(kPWaves * kWave), 0, s, reqs, nreq, total_c,
-                     cnt_bits, packed, bnd_all, cand_all);
+                     cnt_bits, packed, bnd_all, cand_all, pb_all);
   return hipGetLastError();
 }
 
@@ -459,6 +500,7 @@ hipError_t launch_prune_fill(hipStream_t s, const ReqDev* reqs, int nreq, int64_
 __global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict__ reqs, int nreq,
                                                        const double* __restrict__ bnd_all,
                                                        const int32_t* __restrict__ cand_all,
+                                                       const double* __restrict__ pb_all,
                                                        StatPartial* __restrict__ partial) {
   __shared__ double red[4];
   __shared__ int64_t ired[4];
@@ -473,19 +515,24 @@ __global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict_
   const int64_t G2 = int64_t(R.G) * R.G;
   const int64_t c0 = (chunk - R.stat_base) * kStatChunk;
   const int64_t c1 = min<int64_t>(G2, c0 + kStatChunk);
-  double b1 = 0.0, b2 = 0.0;
+  double b1 = 0.0, b2 = 0.0, b3 = 0.0;
   int64_t cand = 0;
   const double* bnd = bnd_all + R.cbase;
   const int32_t* ncand = cand_all + R.cbase;
+  const double* pb = pb_all + R.cbase;
   for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     const double b = bnd[c];
     b1 += b;
     const double bb = b * b;
     b2 += bb;
+    const double e = pb[c];
+    const double ee = e * e;
+    b3 += ee;
     cand += ncand[c];
   }
   b1 = block_sum_f64(b1, red);
   b2 = block_sum_f64(b2, red);
+  b3 = block_sum_f64(b3, red);
   cand = wave_sum_i64(cand);
   __syncthreads();
   if (lane_id() == 0) ired[threadIdx.x / kWave] = cand;
@@ -495,6 +542,7 @@ __global__ void __launch_bounds__(256) k_stats_partial(const ReqDev* __restrict_
     for (int w = 0; w < 4; ++w) t += ired[w];
     partial[chunk].b1 = b1;
     partial[chunk].b2 = b2;
+    partial[chunk].pb = b3;
     partial[chunk].cand = t;
   }
 }
@@ -510,11 +558,12 @@ __global__ void __launch_bounds__(256) k_stats_final(const ReqDev* __restrict__ 
   for (int64_t i = threadIdx.x; i < R.G; i += blockDim.x) tr += R.trace_part[i];
   tr = block_sum_f64(tr, red);
   if (threadIdx.x == 0) {
-    double b1 = 0.0, b2 = 0.0;
+    double b1 = 0.0, b2 = 0.0, b3 = 0.0;
     int64_t cand = 0;
     for (int64_t q = 0; q < nch; ++q) {
       b1 += partial[R.stat_base + q].b1;
       b2 += partial[R.stat_base + q].b2;
+      b3 += partial[R.stat_base + q].pb;
       cand += partial[R.stat_base + q].cand;
     }
     ReqStatsDev o;
@@ -527,16 +576,18 @@ __global__ void __launch_bounds__(256) k_stats_final(const ReqDev* __restrict__ 
     o.normAu_sq = *R.rootAu;
     o.dA_sq = R.truncA ? R.truncA[0] : 0.0;
     o.dB_sq = R.truncB ? R.truncB[0] : 0.0;
+    o.pb_sq = b3;
     o.n_candidates = cand;
     out[blockIdx.x] = o;
   }
 }
 
 hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
-                                const double* bnd_all, const int32_t* cand_all, StatPartial* partial) {
+                                const double* bnd_all, const int32_t* cand_all, const double* pb_all,
+                                StatPartial* partial) {
   if (nreq == 0 || nchunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_stats_partial, dim3(uint32_t(nchunks)), dim3(256), 0, s, reqs, nreq, bnd_all, cand_all,
-                     partial);
+                     pb_all, partial);
   return hipGetLastError();
 }
 

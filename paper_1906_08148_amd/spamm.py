@@ -39,7 +39,8 @@ class Stats(ctypes.Structure):
                 ("dA", ctypes.c_double), ("dB", ctypes.c_double),
                 ("normA", ctypes.c_double), ("normB", ctypes.c_double),
                 ("normA_used", ctypes.c_double), ("err_bound", ctypes.c_double),
-                ("trace", ctypes.c_double), ("normC", ctypes.c_double)]
+                ("trace", ctypes.c_double), ("normC", ctypes.c_double),
+                ("prec_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

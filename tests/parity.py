@@ -5,6 +5,7 @@ import oracle as O
 from paper_1906_08148_amd import spamm
 
 TOL = {spamm.F64: 1e-12, spamm.F32: 1e-5, spamm.BF16: 1e-2, spamm.BF16X3: 1e-5}
+PREC_NAME = {spamm.F64: O.P_F64, spamm.F32: O.P_F32, spamm.BF16: O.P_BF16, spamm.BF16X3: O.P_BF16X3}
 TIE_BAND = 1e-12
 
 
@@ -81,4 +82,10 @@ def check_product(ctx, A_h, B_h, TA, TB, tau, mode, prec, A_dense=None, alias=Fa
             assert abs(st[k] - ref.stats[k]) <= 1e-10 * max(abs(ref.stats[k]), 1e-300) + 1e-300, k
         if ref.stats["err_bound"] > 0:
             assert abs(st["err_bound"] - ref.stats["err_bound"]) <= 1e-10 * ref.stats["err_bound"]
+        # the rounding bound: the same quantity as the oracle's, and above the
+        # measured difference (the oracle's own FP64 rounding added)
+        pb = O.precision_bound(ref, PREC_NAME[prec])
+        assert abs(st["prec_bound"] - pb) <= 1e-10 * pb, (st["prec_bound"], pb)
+        assert r * ref.C.fro() <= st["prec_bound"] + O.precision_bound(ref, O.P_F64), \
+            (r * ref.C.fro(), st["prec_bound"])
     return p, ref
