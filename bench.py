@@ -287,7 +287,8 @@ def errors(ctx, dev, host, prec):
                 C = ctx.to_dense(prods[i].C)
                 err = float(torch.linalg.norm(C - exact))
                 out.append(dict(alpha=a, tau=t, mode=m, err=err, sigma=1e-5 * nA * nA,
-                                n_kept=stats[i]["n_kept"], bound=stats[i]["err_bound"]))
+                                n_kept=stats[i]["n_kept"], bound=stats[i]["err_bound"],
+                                prec_bound=stats[i]["prec_bound"]))
                 i += 1
                 del C
         del A, exact
@@ -471,7 +472,9 @@ def main():
             "sigma": "1e-5 * ||A||_F * ||B||_F",
             "f32": fixed_error_rate(ctx, dev, spamm.F32, e32, 20),
             "f64": fixed_error_rate(ctx, dev, spamm.F64, e64, 20),
-            "errors_f32": [{k: e[k] for k in ("alpha", "tau", "mode", "err", "bound")} for e in e32],
+            # err <= bound + prec_bound: the approximation and the FP32 rounding
+            "errors_f32": [{k: e[k] for k in ("alpha", "tau", "mode", "err", "bound", "prec_bound")}
+                           for e in e32],
         }
         out["fixed_error"]["f32_over_f64"] = round(out["fixed_error"]["f32"]["multiplies_per_s"] /
                                                    out["fixed_error"]["f64"]["multiplies_per_s"], 3)
