@@ -107,6 +107,9 @@ typedef struct spamm_stats {
                            C leaves.  Covers the product before an epilogue.
                            The total error against A B is at most err_bound +
                            prec_bound.                                       */
+  double val_err;       /* ||C - C_FP64||_F, C_FP64 the same kept products in
+                           FP64, measured when SPAMM_OPT_VALIDATE is on;
+                           -1 when it is off                                 */
 } spamm_stats;
 
 /* Optional epilogue: C = alpha * (approximate A B) + beta * D, with D a
@@ -190,6 +193,13 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       workgroup takes a contiguous range of equal cost;
  *                       -1 (default): per launch, 1 when the C leaves average
  *                       fewer than 16 products, else 0.
+ *  SPAMM_OPT_VALIDATE   0 (default): spamm_stats.val_err = -1; 1: every
+ *                       product that is not FP64 runs beside an FP64 twin
+ *                       (same operands, tau, mode and epilogue) in the same
+ *                       batch, and val_err = ||C - C_FP64||_F over the same
+ *                       kept products (0 for FP64 products).  Needs the FP64
+ *                       copy of A and B (EUNSUPPORTED otherwise); costs the
+ *                       FP64 products and one synchronisation.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
  * changes the order of the sums inside one MFMA (results stay within the
  * precision's tolerance).  Errors: EINVAL (unknown key or value). */
@@ -197,7 +207,8 @@ typedef enum {
   SPAMM_OPT_GEMM_TILE = 0,
   SPAMM_OPT_PLACEMENT = 1,
   SPAMM_OPT_GRAPH = 2,
-  SPAMM_OPT_UNIT_ORDER = 3
+  SPAMM_OPT_UNIT_ORDER = 3,
+  SPAMM_OPT_VALIDATE = 4
 } spamm_option;
 
 spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value);

@@ -542,6 +542,7 @@ spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t valu
     case SPAMM_OPT_GEMM_TILE: c->gemm_tile = int(value); return SPAMM_OK;
     case SPAMM_OPT_PLACEMENT: c->gemm_sched = int(value); return SPAMM_OK;
     case SPAMM_OPT_GRAPH: c->use_graph = int(value); return SPAMM_OK;
+    case SPAMM_OPT_VALIDATE: c->validate = int(value); return SPAMM_OK;
     default: return fail(c, SPAMM_EINVAL, "unknown option");
   }
 }
@@ -554,6 +555,7 @@ spamm_status spamm_ctx_get_option(const spamm_ctx* ctx, spamm_option key, int64_
     case SPAMM_OPT_PLACEMENT: *value = c->gemm_sched; return SPAMM_OK;
     case SPAMM_OPT_GRAPH: *value = c->use_graph; return SPAMM_OK;
     case SPAMM_OPT_UNIT_ORDER: *value = c->gemm_interleave; return SPAMM_OK;
+    case SPAMM_OPT_VALIDATE: *value = c->validate; return SPAMM_OK;
     default: return SPAMM_EINVAL;
   }
 }
@@ -791,10 +793,102 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   return SPAMM_OK;
 }
 
+static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* reqs, spamm_mat** C_out,
+                                  spamm_stats* st_out);
+
+// With validation on, every product that is not FP64 gets an FP64 twin (same
+// operands, tau, mode and epilogue) in the same batch.  The twin shares the
+// truncations and the norm tests, so it keeps the same products and its C
+// holds the same non-null leaves in the same slots; the two C stores are
+// then compared leaf slot by leaf slot and the twin is released.
 spamm_status spamm_multiply_batch(spamm_ctx* ctx, int32_t count, const spamm_request* reqs, spamm_mat** C_out,
                                   spamm_stats* st_out) {
   if (!ctx) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;
+  if (!c->validate || count <= 0 || !reqs || !C_out) {
+    const spamm_status st = multiply_core(c, count, reqs, C_out, st_out);
+    if (st == SPAMM_OK && st_out)
+      for (int r = 0; r < count; ++r) st_out[r].val_err = -1.0;
+    return st;
+  }
+  for (int r = 0; r < count; ++r) C_out[r] = nullptr;
+  std::vector<spamm_request> all(reqs, reqs + count);
+  std::vector<int> twin(count, -1);
+  for (int r = 0; r < count; ++r) {
+    const spamm_request& q = reqs[r];
+    if (q.prec == SPAMM_F64 || !q.A || !q.B || q.A->ctx != c || q.B->ctx != c) continue;  // core checks handles
+    if (!q.A->store || !q.A->store->f64 || !q.B->store || !q.B->store->f64)
+      return fail(c, SPAMM_EUNSUPPORTED, "validation needs the FP64 copy of A and B");
+    twin[r] = int(all.size());
+    spamm_request t = q;
+    t.prec = SPAMM_F64;
+    all.push_back(t);
+  }
+  const int total = int(all.size());
+  std::vector<spamm_mat*> Cs(total, nullptr);
+  std::vector<spamm_stats> sts(total);
+  spamm_status st = multiply_core(c, total, all.data(), Cs.data(), st_out ? sts.data() : nullptr);
+  if (st != SPAMM_OK) return st;
+  auto release_all = [&]() {
+    for (spamm_mat* m : Cs) (void)spamm_release(ctx, m);
+  };
+  std::vector<ValJob> jobs;
+  std::vector<int> job_of(count, -1);
+  int64_t nchunks = 0;
+  for (int r = 0; r < count; ++r) {
+    if (twin[r] < 0) continue;
+    const spamm_mat* C = Cs[r];
+    const spamm_mat* T = Cs[twin[r]];
+    if (C->nonnull != T->nonnull) {
+      release_all();
+      return fail(c, SPAMM_EDEVICE, "validation twin kept different products");
+    }
+    ValJob j;
+    j.c32 = C->nonnull ? P<float>(C->store->f32) : nullptr;
+    j.c64 = T->nonnull ? P<double>(T->store->f64) : nullptr;
+    j.nelem = C->nonnull * int64_t(C->bs) * C->bs;
+    j.chunk_base = nchunks;
+    nchunks += (j.nelem + kValChunk - 1) / kValChunk;
+    job_of[r] = int(jobs.size());
+    jobs.push_back(j);
+  }
+  if (!jobs.empty()) {
+    TableSet tabs;
+    const size_t oj = tabs.add(jobs);
+    RegionP part = c->alloc(size_t(std::max<int64_t>(nchunks, 1)) * 8);
+    if (!part) {
+      release_all();
+      return nomem(c, "validation partial sums", size_t(std::max<int64_t>(nchunks, 1)) * 8);
+    }
+    st = send_tables(c, tabs);
+    if (st == SPAMM_OK && !c->results(jobs.size() * sizeof(double)))
+      st = fail(c, SPAMM_EDEVICE, "mapped results buffer");
+    if (st == SPAMM_OK) {
+      const hipError_t e = launch_validate(c->stream, tabs.at<ValJob>(oj), int(jobs.size()), nchunks,
+                                           P<double>(part), reinterpret_cast<double*>(c->res_dev));
+      if (e != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        st = fail(c, SPAMM_EDEVICE, std::string("validation: ") + hipGetErrorString(hipGetLastError()));
+    }
+    if (st != SPAMM_OK) {
+      release_all();
+      return st;
+    }
+  }
+  const double* vsq = reinterpret_cast<const double*>(c->res_host);
+  for (int r = 0; r < count; ++r) {
+    C_out[r] = Cs[r];
+    Cs[r] = nullptr;
+    if (st_out) {
+      st_out[r] = sts[r];
+      st_out[r].val_err = twin[r] < 0 ? 0.0 : std::sqrt(vsq[job_of[r]]);
+    }
+  }
+  release_all();  // the twins
+  return SPAMM_OK;
+}
+
+static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* reqs, spamm_mat** C_out,
+                                  spamm_stats* st_out) {
   if (count < 0 || (count > 0 && (!reqs || !C_out))) return fail(c, SPAMM_EINVAL, "bad batch arguments");
   for (int r = 0; r < count; ++r) C_out[r] = nullptr;
   if (count == 0) return SPAMM_OK;

@@ -146,6 +146,7 @@ struct Ctx {
   int gemm_interleave = -1;  // GemmArgs::interleave (chunk of consecutive units, 0: contiguous ranges,
                              // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
+  int validate = 0;    // measure every lower-precision product against an FP64 twin
   hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
@@ -332,6 +333,16 @@ struct ReqStatsDev {
 
 constexpr int kStatChunk = 4096;  // C leaves per partial-statistics workgroup
 
+// Validation of one product against its FP64 twin: both C stores hold the
+// same non-null leaves in the same slots (same kept products).
+struct ValJob {
+  const float* c32;   // the product's C store (FP32)
+  const double* c64;  // the twin's C store (FP64)
+  int64_t nelem;      // non-null leaves x bs^2
+  int64_t chunk_base; // first chunk of this job in the partial sums
+};
+constexpr int64_t kValChunk = 65536;  // elements per partial sum
+
 struct StatPartial {
   double b1, b2, pb;
   int64_t cand;
@@ -425,6 +436,9 @@ hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int
                                 StatPartial* partial);
 hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const StatPartial* partial,
                               ReqStatsDev* out);
+// out[j] = ||c32 - c64||_F^2 of job j (partial: one double per chunk)
+hipError_t launch_validate(hipStream_t s, const ValJob* jobs, int njobs, int64_t nchunks, double* partial,
+                           double* out);
 hipError_t launch_to_dense(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot,
                            const double* f64, const float* f32, double* out, int64_t ld);
 hipError_t launch_decode_kept(hipStream_t s, int G, const int64_t* off, const int2* pairs, int64_t aoff,

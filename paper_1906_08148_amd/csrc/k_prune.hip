@@ -598,6 +598,55 @@ hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const
   return hipGetLastError();
 }
 
+// Squared Frobenius difference of a product's C and its FP64 twin's, in one
+// fixed order: partial sums over chunks of kValChunk elements (one
+// workgroup each), then each job adds its chunks in order.
+__global__ void __launch_bounds__(256) k_val_partial(const ValJob* __restrict__ jobs, int njobs,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[4];
+  int lo = 0, hi = njobs - 1;
+  const int64_t chunk = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].chunk_base <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  const ValJob& J = jobs[lo];
+  const int64_t e0 = (chunk - J.chunk_base) * kValChunk;
+  const int64_t e1 = min<int64_t>(J.nelem, e0 + kValChunk);
+  double s = 0.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const double d = double(J.c32[e]) - J.c64[e];
+    const double dd = d * d;
+    s += dd;
+  }
+  s = block_sum_f64(s, red);
+  if (threadIdx.x == 0) partial[chunk] = s;
+}
+
+__global__ void k_val_final(const ValJob* __restrict__ jobs, int njobs, int64_t nchunks,
+                            const double* __restrict__ partial, double* __restrict__ out) {
+  const int j = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= njobs) return;
+  const int64_t end = j + 1 < njobs ? jobs[j + 1].chunk_base : nchunks;
+  double s = 0.0;
+  for (int64_t q = jobs[j].chunk_base; q < end; ++q) s += partial[q];
+  out[j] = s;
+}
+
+hipError_t launch_validate(hipStream_t s, const ValJob* jobs, int njobs, int64_t nchunks, double* partial,
+                           double* out) {
+  if (njobs == 0) return hipSuccess;
+  if (nchunks > 0) {
+    hipLaunchKernelGGL(k_val_partial, dim3(uint32_t(nchunks)), dim3(256), 0, s, jobs, njobs, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_val_final, dim3(uint32_t((njobs + 63) / 64)), dim3(64), 0, s, jobs, njobs, nchunks, partial,
+                     out);
+  return hipGetLastError();
+}
+
 // (I, K, J) triples of a product's plan, for parity checks.
 __global__ void k_decode_kept(int G, const int64_t* __restrict__ off, const int2* __restrict__ pairs,
                               int64_t aoff, const int32_t* __restrict__ akeys, int32_t* __restrict__ ijk) {

@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
                 ("normA", ctypes.c_double), ("normB", ctypes.c_double),
                 ("normA_used", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("trace", ctypes.c_double), ("normC", ctypes.c_double),
-                ("prec_bound", ctypes.c_double)]
+                ("prec_bound", ctypes.c_double), ("val_err", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -353,10 +353,12 @@ class Context:
         self._check(_lib.spamm_to_dense(self.ptr, m.handle, ctypes.c_void_p(out.data_ptr()), n))
         return out
 
-    OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2, "unit_order": 3}  # unit_order: chunk size (0: contiguous ranges)
+    OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2, "unit_order": 3,  # unit_order: chunk size (0: contiguous ranges)
+               "validate": 4}
 
     def set_option(self, name: str, value: int):
-        """gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
+        """validate (1: measure ||C - C_FP64||_F into stats["val_err"]),
+        gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
         slices, 1: request-major), graph (1: one captured graph per batch)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 

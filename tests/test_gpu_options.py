@@ -1,7 +1,7 @@
 """Context options: captured-graph launches give bitwise the results of
 one-by-one launches, replay after replay with other work in between; the
 16 x 16 MFMA tile variant matches the oracle; the autotuner returns a
-working choice."""
+working choice; validation measures each product against its FP64 twin."""
 import numpy as np
 import pytest
 
@@ -9,7 +9,7 @@ import oracle as O
 import synth
 from paper_1906_08148_amd import autotune, spamm
 
-from parity import check_product
+from parity import check_product, compare_kept, TIE_BAND
 
 pytestmark = pytest.mark.gpu
 
@@ -82,4 +82,50 @@ def test_autotuner_picks_a_candidate():
     assert len(best["table"]) == 4 and all(r["seconds"] > 0 for r in best["table"])
     assert ctx.get_option("gemm_tile") == best["tile"]
     assert tuner.tune(None, sig, 1e-6, spamm.HYBRID, spamm.F32) is best  # cached
+    ctx.close()
+
+
+def test_validation_against_fp64_twin():
+    print("case: validation", flush=True)
+    ctx = spamm.Context(arena_bytes=1 << 30)
+    A = synth.DecaySpec("1d", 1500, 0.3, seed=7).dense()
+    T = O.build(A, 32)
+    M = ctx.build(dev(A), 32)
+    reqs = [dict(A=M, B=M, tau=1e-6, mode=m, prec=p)
+            for m in (spamm.SPAMM, spamm.HYBRID) for p in (spamm.F32, spamm.BF16, spamm.BF16X3, spamm.F64)]
+    for pr in ctx.multiply_batch(reqs):  # builds and caches M's prune views
+        pr.C.release()
+    base = ctx.arena_info()["used"]
+    ctx.set_option("validate", 1)
+    assert ctx.get_option("validate") == 1
+    prods = ctx.multiply_batch(reqs)
+    for q, pr in zip(reqs, prods):
+        st = pr.stats
+        if q["prec"] == spamm.F64:
+            assert st["val_err"] == 0.0
+            continue
+        ref = O.multiply(T, T, q["tau"], q["mode"])
+        ties = O.tie_triples(ref.A_used, ref.B_used, q["tau"], TIE_BAND)
+        if compare_kept(ctx.kept(pr.C), ref.kept, ties, T.G) or ref.stats["trunc_tie"]:
+            continue
+        d = float(np.linalg.norm(ctx.to_dense(pr.C).cpu().numpy() - ref.C.to_dense()))
+        # the twin and the oracle differ only by FP64 rounding
+        assert abs(st["val_err"] - d) <= 2.0 * O.precision_bound(ref, O.P_F64), (st["val_err"], d)
+        assert 0.0 < st["val_err"] <= st["prec_bound"]
+    for pr in prods:
+        pr.C.release()
+    # the twins were released with the call
+    assert ctx.arena_info()["used"] == base
+    ctx.set_option("validate", 0)
+    p = ctx.multiply(M, M, 1e-6, prec=spamm.F32)
+    assert p.stats["val_err"] == -1.0
+    p.C.release()
+    # operands without the FP64 copy cannot be validated
+    M32 = ctx.build(dev(A), 32, stores=spamm.STORE_F32)
+    ctx.set_option("validate", 1)
+    with pytest.raises(spamm.SpammError) as e:
+        ctx.multiply(M32, M32, 1e-6, prec=spamm.F32)
+    assert e.value.code == "EUNSUPPORTED"
+    M32.release()
+    M.release()
     ctx.close()
