@@ -277,6 +277,20 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count,
 spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau,
                             spamm_mat** out, double* dropped_sq);
 
+/* Element-wise input truncation, the truncated matrix of Thm. 1 (Sec. 3):
+ * every entry with |a_ij| < tau becomes zero, so each dropped entry is below
+ * tau.  A leaf with no non-zero entry left becomes null; the others keep
+ * their slots in a new store holding the same copies as `in`, written again
+ * from the thresholded FP64 values, and the norm pyramid is rebuilt.
+ * `dropped_sq` (host, nullable) receives the squared Frobenius norm of the
+ * dropped entries (FP64, summed in a fixed order).  Multiplying two such
+ * results with tau = 0 in SPAMM_TRUNCMUL mode gives the element-wise
+ * Truncmul product of the theorem.  Needs the FP64 copy of `in`
+ * (EUNSUPPORTED otherwise).  Synchronises once.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+spamm_status spamm_truncate_elementwise(spamm_ctx* ctx, const spamm_mat* in, double tau,
+                                        spamm_mat** out, double* dropped_sq);
+
 /* C ~= A B (Alg. 1 with the null rule of Alg. 2; the mode selects Truncmul,
  * SpAMM or Hybrid).  A leaf triple (i,k,j) is formed when A_ik and B_kj are
  * non-null and, for SpAMM/Hybrid, sqrt(s_ik) * sqrt(s_kj) >= tau in FP64.

@@ -793,6 +793,67 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   return SPAMM_OK;
 }
 
+spamm_status spamm_truncate_elementwise(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out,
+                                        double* dropped_sq) {
+  if (!ctx || !out) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  *out = nullptr;
+  if (!in || in->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
+  if (!tau_ok(tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
+  if (!in->store || !in->store->f64)
+    return fail(c, SPAMM_EUNSUPPORTED, "element-wise truncation needs the FP64 copy of the matrix");
+  std::unique_ptr<spamm_mat> m;
+  spamm_status st = new_matrix(c, in->n, in->bs, m);
+  if (st != SPAMM_OK) return st;
+  m->store = std::make_shared<Store>();
+  // same slots as the input, so the keys are shared (they never change)
+  st = alloc_store(c, *m->store, in->store->nleaf, in->bs, in->store->mask(), in->store->keys);
+  if (st != SPAMM_OK) return st;
+  const int64_t G2 = int64_t(m->G) * m->G;
+  RegionP dropped, part, hdr;
+  ALLOC(dropped, G2 * 8, "dropped norms");
+  ALLOC(part, ((G2 + 4095) / 4096) * 8, "partial sums");
+  ALLOC(hdr, 16, "count and total");
+  ElemTruncJob j;
+  j.G = m->G;
+  j.bs = m->bs;
+  j.tau = tau;
+  j.in_slot = P<int32_t>(in->slot);
+  j.in_f64 = P<double>(in->store->f64);
+  j.slot = P<int32_t>(m->slot);
+  j.leafnorm = P<double>(m->norms) + level_offset(m->L);
+  j.dropped = P<double>(dropped);
+  j.count = P<int64_t>(hdr);
+  j.f64 = P<double>(m->store->f64);
+  j.f32 = P<float>(m->store->f32);
+  j.b16 = P<uint16_t>(m->store->bf16);
+  j.b16t = P<uint16_t>(m->store->bf16t);
+  SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(hdr), 2));
+  {
+    TimedScope ts(c, kTTrunc);
+    SPAMM_HIP(c, launch_trunc_elem(c->stream, j));
+    SPAMM_HIP(c, launch_sum_f64(c->stream, P<double>(dropped), G2, P<double>(part), P<double>(hdr) + 1));
+  }
+  const std::vector<PyrJob> pj = pyramid_jobs({P<double>(m->norms)}, {m->L});
+  TableSet tabs;
+  const size_t po = tabs.add(pj);
+  st = send_tables(c, tabs);
+  if (st != SPAMM_OK) return st;
+  st = pyramids_launch(c, tabs.at<PyrJob>(po), pj);
+  if (st != SPAMM_OK) return st;
+  struct {
+    int64_t count;
+    double dropped;
+  } h;
+  st = download(c, &h, hdr->ptr(), sizeof(h));
+  if (st != SPAMM_OK) return st;
+  if (dropped_sq) *dropped_sq = h.dropped;
+  m->nonnull = h.count;
+  c->live_handles++;
+  *out = m.release();
+  return SPAMM_OK;
+}
+
 static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* reqs, spamm_mat** C_out,
                                   spamm_stats* st_out);
 

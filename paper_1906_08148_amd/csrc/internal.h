@@ -431,6 +431,24 @@ hipError_t launch_gershgorin(hipStream_t s, int64_t n, int bs, int G, const int3
 hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int32_t* slot, const double* f64,
                                 const float* f32, const int32_t* ij, double* out);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t value);
+// Element-wise truncation of one matrix into a new store with the same slots.
+struct ElemTruncJob {
+  int G, bs;
+  double tau;
+  const int32_t* in_slot;
+  const double* in_f64;
+  int32_t* slot;      // new slot map (G*G)
+  double* leafnorm;   // new leaf level of the pyramid (G*G)
+  double* dropped;    // squared norm of the dropped entries per leaf (G*G)
+  int64_t* count;     // non-null leaves of the result (starts at zero)
+  double* f64;
+  float* f32;
+  uint16_t* b16;
+  uint16_t* b16t;
+};
+hipError_t launch_trunc_elem(hipStream_t s, const ElemTruncJob& job);
+// *out = v[0] + ... + v[n-1] in a fixed order (partial: (n + 4095) / 4096)
+hipError_t launch_sum_f64(hipStream_t s, const double* v, int64_t n, double* partial, double* out);
 hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
                                 const double* bnd_all, const int32_t* cand_all, const double* pb_all,
                                 StatPartial* partial);

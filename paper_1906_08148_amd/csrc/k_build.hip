@@ -290,6 +290,100 @@ hipError_t launch_build_batch(hipStream_t s, const BuildJob* jobs, int njobs, in
   return hipGetLastError();
 }
 
+// Element-wise truncation (the truncated matrix of Thm. 1): every entry with
+// |a| < tau becomes zero.  One workgroup per leaf, over the slot map: the
+// kept entries' squared norm and the dropped entries' squared norm in FP64, a
+// leaf with no non-zero entry left becomes null, and the others keep their
+// slot in a new store of the same size, with every copy written again.
+__global__ void __launch_bounds__(256) k_trunc_elem(const ElemTruncJob J) {
+  __shared__ double red[4];
+  const int64_t G2 = int64_t(J.G) * J.G;
+  const int bs = J.bs, e2 = bs * bs;
+  const double tau = J.tau;
+  for (int64_t m = blockIdx.x; m < G2; m += gridDim.x) {
+    const int32_t t = J.in_slot[m];  // uniform over the workgroup
+    if (t < 0) {
+      if (threadIdx.x == 0) {
+        J.slot[m] = -1;
+        J.leafnorm[m] = 0.0;
+        J.dropped[m] = 0.0;
+      }
+      continue;
+    }
+    const double* src = J.in_f64 + int64_t(t) * e2;
+    double s = 0.0, d = 0.0;
+    int nz = 0;
+    for (int base = 0; base < e2; base += kLeafPass * 256) {
+      double a[kLeafPass];
+#pragma unroll
+      for (int q = 0; q < kLeafPass; ++q) {
+        const int e = base + q * 256 + int(threadIdx.x);
+        a[q] = e < e2 ? src[e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kLeafPass; ++q) {
+        const double x = a[q];
+        const double xx = x * x;
+        if (fabs(x) < tau) {
+          d += xx;
+        } else {
+          s += xx;
+          nz |= (x != 0.0);
+        }
+      }
+    }
+    s = block_sum_f64(s, red);
+    d = block_sum_f64(d, red);
+    nz = __syncthreads_or(nz);
+    if (threadIdx.x == 0) {
+      J.leafnorm[m] = nz ? s : 0.0;
+      J.slot[m] = nz ? t : -1;
+      J.dropped[m] = d;
+      if (nz) atomicAdd(reinterpret_cast<unsigned long long*>(J.count), 1ull);
+    }
+    if (nz)
+      write_leaf(t, bs, [&](int e) { const double x = src[e]; return fabs(x) < tau ? 0.0 : x; }, J.f64, J.f32,
+                 J.b16, J.b16t);
+    __syncthreads();  // red and the LDS tile are reused by the next leaf
+  }
+}
+
+hipError_t launch_trunc_elem(hipStream_t s, const ElemTruncJob& job) {
+  const int64_t G2 = int64_t(job.G) * job.G;
+  hipLaunchKernelGGL(k_trunc_elem, dim3(uint32_t(G2 < 65536 ? G2 : 65536)), dim3(256), 0, s, job);
+  return hipGetLastError();
+}
+
+// Sum of n doubles in one fixed order: chunks of 4096 (one workgroup each),
+// then the chunk sums in order.
+__global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ v, int64_t n,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int64_t c0 = int64_t(blockIdx.x) * 4096, c1 = min<int64_t>(n, c0 + 4096);
+  double s = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) s += v[i];
+  s = block_sum_f64(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_sum_final(const double* __restrict__ partial, int64_t nchunks, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t q = 0; q < nchunks; ++q) s += partial[q];
+  *out = s;
+}
+
+hipError_t launch_sum_f64(hipStream_t s, const double* v, int64_t n, double* partial, double* out) {
+  const int64_t nchunks = (n + 4095) / 4096;
+  if (nchunks > 0) {
+    hipLaunchKernelGGL(k_sum_chunks, dim3(uint32_t(nchunks)), dim3(256), 0, s, v, n, partial);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, partial, nchunks, out);
+  return hipGetLastError();
+}
+
 // Derive missing copies of every leaf from the best copy present (FP64 if
 // any), one workgroup per leaf.
 __global__ void __launch_bounds__(256) k_derive_store(int64_t nleaf, int bs, const double* __restrict__ f64,

@@ -110,6 +110,8 @@ _SIGS = {
                                           ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     "spamm_truncate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
+    "spamm_truncate_elementwise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
     "spamm_multiply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Stats)]),
@@ -290,6 +292,14 @@ class Context:
         out = ctypes.c_void_p()
         dropped = ctypes.c_double()
         self._check(_lib.spamm_truncate(self.ptr, m.handle, tau, ctypes.byref(out), ctypes.byref(dropped)))
+        return Matrix(self, out.value), dropped.value
+
+    def truncate_elementwise(self, m: Matrix, tau: float):
+        """Zero every entry with |a| < tau (Thm. 1); returns (matrix, dropped squared norm)."""
+        out = ctypes.c_void_p()
+        dropped = ctypes.c_double()
+        self._check(_lib.spamm_truncate_elementwise(self.ptr, m.handle, tau, ctypes.byref(out),
+                                                    ctypes.byref(dropped)))
         return Matrix(self, out.value), dropped.value
 
     def multiply(self, A: Matrix, B: Matrix, tau: float, mode=SPAMM, prec=F32,

@@ -567,3 +567,17 @@ def test_rounding_bound_invariants():
     assert O.rounding_coefficient(O.P_F32, 8, 10) > O.rounding_coefficient(O.P_F32, 8, 1)
     empty = O.multiply(T, T, 1e9, O.SPAMM)
     assert len(empty.kept) == 0 and O.precision_bound(empty, O.P_F32) == 0.0
+
+
+def test_elementwise_truncmul_error_grows_like_sqrt_n():
+    """Thm. 1 with the element-wise truncated matrix: a fixed number of
+    entries per row falls below tau on a 1D decay matrix, so ||E||_F grows
+    like n^{1/2} (the paper's Truncmul trend, Sec. 5), unlike the
+    leaf-level budget, whose error does not grow with n."""
+    ns = [256, 512, 1024, 2048]
+    errs = []
+    for n in ns:
+        A = synth.DecaySpec("1d", n, 0.3, seed=1).dense()
+        At = O.truncate_elementwise(A, 1e-6)
+        errs.append(float(np.linalg.norm(O.exact_product(At, At) - O.exact_product(A, A))))
+    assert 0.4 <= _slope(ns, errs) <= 0.7
