@@ -185,6 +185,106 @@ def dense3d(steps):
     return out
 
 
+def paper_workloads():
+    """The paper's own synthetic workloads (Sec. 5), in FP64 as there.
+
+    Model problem: 1D decay n = 4e4, alpha = 0.005, A = B.  For each leaf size
+    and method, the largest tau on the grid 1e-4 ... 1e-12 whose product has
+    ||A A - C||_F <= sigma = 1e-6; its kept products (the paper's gemm calls)
+    and multiply time with the norms precomputed, as there.  Truncmul runs in
+    both readings: the leaf-level budget and the element-wise truncation of
+    Thm. 1 (the truncation is not timed, like the norms).
+
+    Leaf-library sweep: 2048 x 2048 matrices of random uniform blocks at fill
+    0.1 ... 1.0, every product formed (Truncmul at tau = 0); kept-product
+    GFLOP/s of batches of 32 multiplies."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1906_08148_amd import spamm
+    n, alpha, sigma = 40000, 0.005, 1e-6
+    t0 = time.perf_counter()
+    A = synth.DecaySpec("1d", n, alpha, seed=SEED).dense()
+    gen_s = time.perf_counter() - t0
+    dA = torch.from_numpy(A).cuda()
+    del A
+    exact = dA @ dA
+    ctx = spamm.Context(arena_bytes=80 << 30)
+    modes = {"truncmul": spamm.TRUNCMUL, "spamm": spamm.SPAMM, "hybrid": spamm.HYBRID}
+    model = {"workload": f"1D decay n={n}, alpha {alpha}, A=B, FP64, sigma {sigma}",
+             "generate_s": round(gen_s, 1), "rows": []}
+    for leaf in (32, 64, 128):
+        M = ctx.build(dA, leaf, stores=spamm.STORE_F64)
+        ctx.multiply(M, M, 1e-4, mode=spamm.SPAMM, prec=spamm.F64).C.release()  # prune views
+        base = None
+        for name in ("truncmul", "truncmul_elementwise", "spamm", "hybrid"):
+            best = {"leaf": leaf, "method": name, "tau": None}
+            for k in range(4, 13):
+                tau = 10.0 ** -k
+                log(f"bench: model problem leaf {leaf} {name} tau 1e-{k}")
+                Mt = None
+                if name == "truncmul_elementwise":
+                    Mt, _ = ctx.truncate_elementwise(M, tau)
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                if Mt is not None:
+                    p = ctx.multiply(Mt, Mt, 0.0, mode=spamm.TRUNCMUL, prec=spamm.F64)
+                else:
+                    p = ctx.multiply(M, M, tau, mode=modes[name], prec=spamm.F64)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - s0
+                err = float(torch.linalg.norm(ctx.to_dense(p.C) - exact))
+                kept = int(p.stats["n_kept"])
+                p.C.release()
+                if Mt is not None:
+                    Mt.release()
+                if err <= sigma:
+                    best = {"leaf": leaf, "method": name, "tau": tau, "n_kept": kept, "ms": round(dt * 1e3, 2),
+                            "err": err, "gflops": round(2.0 * leaf ** 3 * kept / dt / 1e9, 1)}
+                    break
+            if name == "truncmul" and best["tau"] is not None:
+                base = best
+            if base is not None and best["tau"] is not None:
+                best["kept_vs_truncmul"] = round(best["n_kept"] / base["n_kept"], 3)
+                best["time_vs_truncmul"] = round(best["ms"] / base["ms"], 3)
+            model["rows"].append(best)
+            torch.cuda.empty_cache()
+        M.release()
+    del exact, dA
+    torch.cuda.empty_cache()
+    sweep = {"workload": "2048 x 2048 random uniform blocks, FP64, every product (Truncmul, tau 0), "
+                         "batches of 32 multiplies", "rows": []}
+    for leaf in (32, 64, 128):
+        for fill in (0.1, 0.3, 0.5, 0.7, 1.0):
+            log(f"bench: leaf library leaf {leaf} fill {fill}")
+            mats = []
+            for seed in (SEED, SEED + 1):
+                coords, data = synth.random_blocks(seed, 2048, leaf, fill)
+                mats.append(ctx.build_blocks(2048, leaf, torch.from_numpy(coords.astype(np.int32)).cuda(),
+                                             torch.from_numpy(np.ascontiguousarray(data)).cuda(),
+                                             stores=spamm.STORE_F64))
+            reqs = [dict(A=mats[0], B=mats[1], tau=0.0, mode=spamm.TRUNCMUL, prec=spamm.F64)] * 32
+            for p in ctx.multiply_batch(reqs):
+                p.C.release()
+            ts, flops = [], 0.0
+            for _ in range(5):
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                prods = ctx.multiply_batch(reqs)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - s0)
+                flops = sum(p.stats["flops"] for p in prods)
+                for p in prods:
+                    p.C.release()
+            dt = sorted(ts)[len(ts) // 2]
+            sweep["rows"].append({"leaf": leaf, "fill": fill, "gflops": round(flops / dt / 1e9, 1),
+                                  "frac_of_fp64_peak": round(flops / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)})
+            for m in mats:
+                m.release()
+    ctx.close()
+    return {"model_problem": model, "leaf_library": sweep}
+
+
 def purification(steps):
     """20 trace-driven purification steps (X^2 or 2X - X^2, Hybrid, tau 1e-6)
     on the 3D decay matrix n = 32768 scaled into [0, 1], FP64 and FP32 chains
@@ -388,6 +488,8 @@ def main():
     ap.add_argument("--gemm-tile", type=int, default=None, help="MFMA tile variant (0: 32x32, 1: 16x16)")
     ap.add_argument("--steps-3d", type=int, default=3)
     ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
+    ap.add_argument("--paper-workloads", action="store_true",
+                    help="also run the paper's model problem and leaf-library sweep (FP64; a few minutes)")
     ap.add_argument("--purify-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=16, help="requests of the served stream (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=32768, help="largest n of the served sample (pool: 65536)")
@@ -487,6 +589,9 @@ def main():
     if not args.skip_extras and args.serve_requests > 0:
         log("bench: serving")
         out["serving"] = serving(args.serve_requests, args.serve_nmax)
+    if args.paper_workloads:
+        log("bench: the paper's model problem and leaf-library sweep")
+        out["paper_workloads"] = paper_workloads()
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
