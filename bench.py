@@ -114,6 +114,33 @@ def timed_steps(ctx, dev, prec, steps, warmup):
     return total, lat, flops, tm, stats
 
 
+def multiply_only(ctx, dev, prec, steps, warmup):
+    """The same 18 multiplies with both matrices built once beforehand: the
+    norms are precomputed, the paper's timing convention (Sec. 5)."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32
+    built = ctx.build_blocks_batch([(N, LEAF, c, d) for c, d in dev.values()], stores=store)
+    mats = dict(zip(dev.keys(), built))
+    reqs = requests(mats, prec)
+    for _ in range(warmup):
+        for p in ctx.multiply_batch(reqs):
+            p.C.release()
+    torch.cuda.synchronize()
+    flops = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prods = ctx.multiply_batch(reqs)
+        flops += sum(p.stats["flops"] for p in prods)
+        for p in prods:
+            p.C.release()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    for m in mats.values():
+        m.release()
+    return {"ms_per_step": round(total / steps * 1e3, 4), "gflops": round(flops / total / 1e9, 3)}
+
+
 def dense3d(steps):
     """3D decay, n = 32768, leaf 64, tau = 1e-6, A = B: one multiply per
     (scheme, precision), timed alone (warm), with the leaf-GEMM time from the
@@ -548,6 +575,8 @@ def main():
         "kept_products_per_step": int(sum(s["n_kept"] for s in stats32)),
         "phases_ms_per_step": {k: round(tm32[k + "_ms"] / args.steps, 4)
                                for k in ("build", "trunc", "prune", "gemm", "pyramid")},
+        # the same multiplies with the matrices (and their norms) built once
+        "norms_precomputed": multiply_only(ctx, dev, spamm.F32, args.steps, args.warmup),
         "roofline": {"kernel": f"k_gemm<SPAMM_F32,64,{tile}> (persistent MFMA leaf GEMM, "
                                f"{'16x16' if tile else '32x32'} MFMA tiles)", "bound": "mfma",
                      "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
