@@ -129,3 +129,31 @@ def test_validation_against_fp64_twin():
     M32.release()
     M.release()
     ctx.close()
+
+
+def test_validation_with_epilogue_and_mixed_leaves():
+    """The FP64 twin carries the request's epilogue (C = alpha A B + beta D),
+    and twins of different leaf sizes share one batch: val_err equals the
+    difference from the same request computed in FP64 on its own."""
+    import torch
+    print("case: validation epilogue", flush=True)
+    ctx = spamm.Context(arena_bytes=1 << 30)
+    A = synth.DecaySpec("1d", 1200, 0.4, seed=3).dense()
+    M32, M64 = ctx.build(dev(A), 32), ctx.build(dev(A), 64)
+    reqs = [dict(A=M32, B=M32, tau=1e-7, mode=spamm.HYBRID, prec=spamm.F32, alpha=-1.0, beta=2.0, D=M32),
+            dict(A=M64, B=M64, tau=1e-6, mode=spamm.SPAMM, prec=spamm.BF16X3, alpha=0.5, beta=-3.0, D=M64),
+            dict(A=M64, B=M64, tau=1e-6, mode=spamm.TRUNCMUL, prec=spamm.F32)]
+    ctx.set_option("validate", 1)
+    prods = ctx.multiply_batch(reqs)
+    ctx.set_option("validate", 0)
+    for q, pr in zip(reqs, prods):
+        ref = ctx.multiply_batch([dict(q, prec=spamm.F64)])[0]
+        d = float(torch.linalg.norm(ctx.to_dense(pr.C) - ctx.to_dense(ref.C)))
+        # the twin is the same FP64 computation: bitwise the same C
+        assert pr.stats["val_err"] == pytest.approx(d, rel=1e-12, abs=1e-300), (pr.stats["val_err"], d)
+        assert pr.stats["val_err"] > 0.0
+        ref.C.release()
+        pr.C.release()
+    M32.release()
+    M64.release()
+    ctx.close()
