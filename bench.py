@@ -525,8 +525,8 @@ def main():
                          "kernel of known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU (sharding across GPUs is designed, not "
+                                   "implemented); --gpus must be 1", "n_gpus": args.gpus}))
         return 2
     import torch
     from paper_1906_08148_amd import spamm
