@@ -482,11 +482,36 @@ def cpu_baseline(host, min_s=10.0):
         if time.perf_counter() - t0 >= min_s:
             break
     dt = time.perf_counter() - t0
+    # one more step, timed phase by phase: the leaf trees with their norms,
+    # the truncations, the kept lists, and the rest of each multiply (C
+    # accumulation and accounting)
+    ph = {"build_and_norms": 0.0, "truncation": 0.0, "kept_list": 0.0, "c_and_accounting": 0.0}
+    for a in ALPHAS:
+        coords, data = host[a]
+        s0 = time.perf_counter()
+        tree = O.build_from_blocks(N, LEAF, coords, data)
+        ph["build_and_norms"] += time.perf_counter() - s0
+        for t in TAUS:
+            s0 = time.perf_counter()
+            tr = O.truncate(tree, t).tree
+            ph["truncation"] += 2 * (time.perf_counter() - s0)  # Truncmul and Hybrid each truncate
+            s0 = time.perf_counter()
+            for Tu, use in ((tr, False), (tree, True), (tr, True)):
+                O.kept_flat(Tu, Tu, t, use)
+            kept_s = time.perf_counter() - s0
+            ph["kept_list"] += kept_s
+            s0 = time.perf_counter()
+            for mi in (O.TRUNCMUL, O.SPAMM, O.HYBRID):
+                O.multiply(tree, tree, t, mi)
+            ph["c_and_accounting"] += time.perf_counter() - s0 - kept_s
+    ph["c_and_accounting"] -= ph["truncation"]
     if limiter is not None:
         limiter.unregister()
     return {"value": round(flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} whole step(s): both builds and all 18 multiplies, {dt:.1f} s, "
-                      f"NumPy FP64, one BLAS thread"}
+                      f"NumPy FP64, one BLAS thread",
+            "host_cores": os.cpu_count(),
+            "phases_s_per_step": {k: round(v, 4) for k, v in ph.items()}}
 
 
 def traffic_for(tile):
