@@ -61,7 +61,15 @@ typedef enum spamm_status {
 typedef enum spamm_mode {
   SPAMM_TRUNCMUL = 0, /* truncate A and B, form every non-null leaf product   */
   SPAMM_SPAMM = 1,    /* form leaf products with ||A_ik||_F ||B_kj||_F >= tau */
-  SPAMM_HYBRID = 2    /* SPAMM on A and B truncated with the same tau         */
+  SPAMM_HYBRID = 2,   /* SPAMM on A and B truncated with the same tau         */
+  SPAMM_SPAMM_SYM = 3 /* SPAMM for the square of a symmetric A (B = A, the
+                         same handle, no epilogue).  The kept set is then
+                         symmetric, so only the products of C leaves (I, J)
+                         with I <= J are formed and each leaf below the
+                         diagonal is written as the transpose of its mirror
+                         (n_kept and flops count the formed products; the
+                         kept list holds the upper ones).  The caller
+                         asserts that A is symmetric.                      */
 } spamm_mode;
 
 /* Arithmetic of the leaf products.  The norms, the tau tests and all error

@@ -960,7 +960,9 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     if (!q.A || !q.B || q.A->ctx != c || q.B->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
     if (q.A->n != q.B->n || q.A->bs != q.B->bs) return fail(c, SPAMM_ESHAPE, "A and B differ in n or leaf size");
     if (!tau_ok(q.tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
-    if (q.mode < 0 || q.mode > 2) return fail(c, SPAMM_EINVAL, "bad mode");
+    if (q.mode < 0 || q.mode > 3) return fail(c, SPAMM_EINVAL, "bad mode");
+    if (q.mode == SPAMM_SPAMM_SYM && (q.A != q.B || q.ep))
+      return fail(c, SPAMM_EINVAL, "the symmetric square needs B = A (the same handle) and no epilogue");
     if (q.prec < 0 || q.prec > 3) return fail(c, SPAMM_EINVAL, "bad precision");
     if (!gemm_supported(q.prec, q.A->bs)) return fail(c, SPAMM_EUNSUPPORTED, "precision/leaf size not built");
     if (q.ep) {
@@ -982,7 +984,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   };
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
-    if (q.mode == SPAMM_SPAMM) continue;
+    if (q.mode == SPAMM_SPAMM || q.mode == SPAMM_SPAMM_SYM) continue;
     for (const spamm_mat* m : {q.A, q.B}) {
       auto k = tkey(m, q.tau);
       if (!tindex.count(k)) {
@@ -1005,7 +1007,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   std::vector<spamm_mat*> operands;
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
-    if (q.mode == SPAMM_SPAMM) {
+    if (q.mode == SPAMM_SPAMM || q.mode == SPAMM_SPAMM_SYM) {
       Au[r] = const_cast<spamm_mat*>(q.A);
       Bu[r] = const_cast<spamm_mat*>(q.B);
     } else {
@@ -1038,6 +1040,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   // ---- descriptors and counting pass
   std::vector<ReqDev> rd(count);
   int64_t total_c = 0, total_chunks = 0;
+  bool any_sym = false;
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
     ReqDev& d = rd[r];
@@ -1060,6 +1063,8 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     d.slotD = (q.ep && q.ep->D) ? P<int32_t>(q.ep->D->slot) : nullptr;
     d.tau = q.tau;
     d.use_norms = q.mode != SPAMM_TRUNCMUL;
+    d.sym = q.mode == SPAMM_SPAMM_SYM;
+    any_sym = any_sym || d.sym;
     d.G = q.A->G;
     d.L = q.A->L;
     d.bs = q.A->bs;
@@ -1364,6 +1369,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       TimedScope ts(c, kTPyr);
       SPAMM_HIP(c, launch_unit_scatter(c->stream, reqd, P<WorkUnit>(wus), wu_total, P<double>(wn),
                                        P<double>(wt)));
+      if (any_sym) SPAMM_HIP(c, launch_mirror(c->stream, reqd, count, total_c));
     }
     spamm_status s2 = pyramids_launch(c, pyr_jd, pyr_jobs);
     if (s2 != SPAMM_OK) return s2;
@@ -1431,7 +1437,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       o.dA = std::sqrt(hs[r].dA_sq);
       o.dB = std::sqrt(hs[r].dB_sq);
       o.prec_bound = std::sqrt(hs[r].pb_sq);
-      if (q.mode == SPAMM_SPAMM) o.err_bound = o.B2;
+      if (q.mode == SPAMM_SPAMM || q.mode == SPAMM_SPAMM_SYM) o.err_bound = o.B2;
       else if (q.mode == SPAMM_TRUNCMUL) o.err_bound = o.dA * o.normB + o.normA_used * o.dB;
       else o.err_bound = o.dA * o.normB + o.normA_used * o.dB + o.B2;
     }

@@ -261,7 +261,7 @@ struct ReqDev {
   const int64_t* sched;
   int32_t sched_k, sched_n;
   int32_t nslices;        // slices per request in the placement (8 per-XCD, or 1)
-  int32_t pad2_;
+  int32_t sym;            // symmetric square: C leaves below the diagonal are mirrored
 };
 
 // One truncation inside a batch (leaf-block truncation with budget tau^2).
@@ -449,6 +449,9 @@ struct ElemTruncJob {
 hipError_t launch_trunc_elem(hipStream_t s, const ElemTruncJob& job);
 // *out = v[0] + ... + v[n-1] in a fixed order (partial: (n + 4095) / 4096)
 hipError_t launch_sum_f64(hipStream_t s, const double* v, int64_t n, double* partial, double* out);
+// Symmetric squares: every C leaf below the diagonal of a request with sym
+// set becomes the transpose of its mirror, with the mirror's norm.
+hipError_t launch_mirror(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c);
 hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
                                 const double* bnd_all, const int32_t* cand_all, const double* pb_all,
                                 StatPartial* partial);

@@ -307,7 +307,10 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
     const ReqDev& R = reqs[x.r];
     const bool dflag = R.slotD != nullptr && R.slotD[x.c] >= 0;
     const int64_t flag = (my_cnt > 0 || dflag) ? 1 : 0;
-    packed[g] = (flag << cb) | my_cnt;
+    // a symmetric square forms no product below the diagonal: those leaves
+    // are written from their mirrors (they keep their slot, bounds and counts)
+    const int64_t formed = (R.sym && x.i > x.j) ? 0 : my_cnt;
+    packed[g] = (flag << cb) | formed;
     bnd_all[g] = my_skip;
     cand_all[g] = int32_t(my_cand);
     pb_all[g] = rounding_coef(R.prec, R.bs, my_cnt) * my_kept;
@@ -595,6 +598,68 @@ hipError_t launch_stats_final(hipStream_t s, const ReqDev* reqs, int nreq, const
                               ReqStatsDev* out) {
   if (nreq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_stats_final, dim3(uint32_t(nreq)), dim3(256), 0, s, reqs, partial, out);
+  return hipGetLastError();
+}
+
+// Symmetric squares (A = A^T, C = A A): the kept set is symmetric, because
+// the norm product of (I, K, J) equals that of (J, K, I), and C_IJ = C_JI^T.
+// Each non-null leaf below the diagonal is written as the transpose of its
+// mirror through a 64 x 64 LDS tile, and takes the mirror's squared norm
+// before the pyramid is summed.
+template <typename T>
+__device__ __forceinline__ void mirror_leaf(const T* __restrict__ src, T* __restrict__ dst, int bs, T* tile) {
+  const int ts = bs < 64 ? bs : 64;
+  for (int tr = 0; tr < bs; tr += ts)
+    for (int tc = 0; tc < bs; tc += ts) {
+      __syncthreads();
+      // tile(r, c) = src(tc + r, tr + c); dst(tr + r, tc + c) = tile(c, r)
+      for (int e = threadIdx.x; e < ts * ts; e += blockDim.x) {
+        const int r = e / ts, c = e % ts;
+        tile[r * (ts + 1) + c] = src[(tc + r) * bs + tr + c];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < ts * ts; e += blockDim.x) {
+        const int r = e / ts, c = e % ts;
+        dst[(tr + r) * bs + tc + c] = tile[c * (ts + 1) + r];
+      }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mirror(const ReqDev* __restrict__ reqs, int nreq, int64_t total_c) {
+  __shared__ double tile[64 * 65];
+  for (int64_t g = blockIdx.x; g < total_c; g += gridDim.x) {  // uniform over the workgroup
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].cbase <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const ReqDev& R = reqs[lo];
+    if (!R.sym) continue;
+    const uint32_t m = uint32_t(g - R.cbase);
+    uint32_t I, J;
+    demorton(m, I, J);
+    if (I <= J) continue;
+    const uint32_t m2 = morton(J, I);
+    const int32_t sd = R.cslot[m], ss = R.cslot[m2];
+    if (sd < 0 || ss < 0) continue;  // a null mirror only if A was not symmetric
+    const int64_t e2 = int64_t(R.bs) * R.bs;
+    const int64_t lv = level_offset(R.L);
+    if (threadIdx.x == 0) R.cnorm[lv + m] = R.cnorm[lv + m2];
+    if (R.prec == SPAMM_F64) {
+      const double* c = static_cast<const double*>(R.cstore);
+      mirror_leaf(c + ss * e2, static_cast<double*>(R.cstore) + sd * e2, R.bs, tile);
+    } else {
+      const float* c = static_cast<const float*>(R.cstore);
+      mirror_leaf(c + ss * e2, static_cast<float*>(R.cstore) + sd * e2, R.bs, reinterpret_cast<float*>(tile));
+    }
+  }
+}
+
+hipError_t launch_mirror(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c) {
+  if (nreq == 0 || total_c == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror, dim3(uint32_t(total_c < 16384 ? total_c : 16384)), dim3(256), 0, s, reqs, nreq,
+                     total_c);
   return hipGetLastError();
 }
 
