@@ -161,9 +161,10 @@ def dense3d(steps):
     peaks = {spamm.F64: FP64_MFMA_PEAK_TFLOPS, spamm.F32: FP32_MFMA_PEAK_TFLOPS,
              spamm.BF16: BF16_MFMA_PEAK_TFLOPS, spamm.BF16X3: BF16_MFMA_PEAK_TFLOPS}
     names = {spamm.F64: "f64", spamm.F32: "f32", spamm.BF16: "bf16", spamm.BF16X3: "bf16x3"}
-    for mode, mname in ((spamm.SPAMM, "spamm"), (spamm.HYBRID, "hybrid")):
+    for mode, mname in ((spamm.SPAMM, "spamm"), (spamm.HYBRID, "hybrid"), (spamm.SPAMM_SYM, "spamm_sym")):
         ref = None
-        for prec in (spamm.F64, spamm.F32, spamm.BF16, spamm.BF16X3):
+        for prec in ((spamm.F64, spamm.F32) if mode == spamm.SPAMM_SYM else
+                     (spamm.F64, spamm.F32, spamm.BF16, spamm.BF16X3)):
             log(f"bench: 3D {mname} {names[prec]}")
             p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)  # warm
             p.C.release()
