@@ -1,0 +1,32 @@
+"""The device-arena sub-allocator is host code: compile it with a small
+driver (tests/arena_check.cpp) and run seeded random allocate/release
+sequences against its invariants (alignment, no overlap, usage, refusals only
+when no aligned gap fits, full coalescing at the end)."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("arena") / "arena_check")
+    cmd = [HIPCC, "-std=c++17", "-O1", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_1906_08148_amd", "csrc"),
+           os.path.join(ROOT, "tests", "arena_check.cpp"),
+           os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "arena.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_arena_invariants(checker, seed):
+    r = subprocess.run([checker, str(seed), "100000"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
