@@ -579,6 +579,10 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
           load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0),
                                 __builtin_amdgcn_readlane(W1.b, 0), 0, tid);
         }
+        // the panel's MFMAs run at raised wave priority, so that a wave with
+        // MFMA work ready is issued ahead of the waves of other workgroups
+        // on the SIMD that are storing panels, loading or in an epilogue
+        __builtin_amdgcn_s_setprio(1);
         if constexpr (Cf::TWO_LEVEL) {
           compute_panel<P, BS, V>(part, As, Bs, row0, col0, li, g);
           if (sub + 1 == Cf::NPANEL) {  // the product's sum joins the leaf's total
@@ -593,6 +597,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
         } else {
           compute_panel<P, BS, V>(acc, As, Bs, row0, col0, li, g);
         }
+        __builtin_amdgcn_s_setprio(0);
       }
       if (((p + 1) & 63) == 0 && p + 1 < U.cnt) {  // into the unit's next window
         W0 = W1;
