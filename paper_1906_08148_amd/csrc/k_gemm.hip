@@ -553,6 +553,11 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
         char* const As = smem + (Cf::DBUF ? (qg & 1) * Cf::PANEL_LDS : 0);
         char* const Bs = As + Cf::A_LDS;
         ++qg;
+        // wave priorities: the panel's MFMAs 2, its store and the prefetch
+        // loads 1, everything else (the epilogue's C writes) 0, so that of
+        // the four workgroups on a SIMD the one with MFMA work ready issues
+        // first and the next panels are staged ahead of epilogue traffic
+        __builtin_amdgcn_s_setprio(1);
         if constexpr (!Cf::DBUF) __syncthreads();  // every wave is done with the previous panel
         store_panel<P, BS, V>(pr, As, Bs, tid);
         __syncthreads();
@@ -579,10 +584,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
           load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0),
                                 __builtin_amdgcn_readlane(W1.b, 0), 0, tid);
         }
-        // the panel's MFMAs run at raised wave priority, so that a wave with
-        // MFMA work ready is issued ahead of the waves of other workgroups
-        // on the SIMD that are storing panels, loading or in an epilogue
-        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_s_setprio(2);
         if constexpr (Cf::TWO_LEVEL) {
           compute_panel<P, BS, V>(part, As, Bs, row0, col0, li, g);
           if (sub + 1 == Cf::NPANEL) {  // the product's sum joins the leaf's total
