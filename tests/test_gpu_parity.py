@@ -383,20 +383,20 @@ def test_epilogue_with_leaves_from_d_only(ctx):
         assert p.C.info.nonnull == int((ref.C.leaf_present | O.build(D, 32).leaf_present).sum())
 
 
-def _fuzz_cases(count=24, seed=2024):
+def _fuzz_cases(count=24, seed=2024, leaves=(16, 32, 64), precs=(spamm.F64, spamm.F32), first=0):
     """Seeded random small cases: n in [1, 300] (mostly not a multiple of the
-    leaf, so grids are padded and tails ragged), leaf 16/32/64, 1D decay or
-    random blocks, tau = 0 or 10^U[-8, 0], every mode, FP64 or FP32, A = B
-    aliased or not."""
+    leaf, so grids are padded and tails ragged), the given leaf sizes, 1D
+    decay or random blocks, tau = 0 or 10^U[-8, 0], every mode, the given
+    precisions, A = B aliased or not."""
     rng = np.random.default_rng(seed)
     cases = []
-    for i in range(count):
+    for i in range(first, first + count):
         n = int(rng.integers(1, 301))
-        bs = int(rng.choice([16, 32, 64]))
+        bs = int(rng.choice(leaves))
         kind = "rand" if rng.random() < 0.4 else "1d"
         tau = 0.0 if rng.random() < 0.15 else float(10.0 ** rng.uniform(-8, 0))
         mode = int(rng.integers(0, 3))
-        prec = int(rng.choice([spamm.F64, spamm.F32]))
+        prec = int(rng.choice(precs))
         alias = bool(rng.random() < 0.5)
         cases.append((i, n, bs, kind, tau, mode, prec, alias, float(rng.uniform(0.05, 1.0))))
     return cases
@@ -408,7 +408,8 @@ def _fuzz_matrix(kind, n, bs, a, seed):
     return synth.DecaySpec("1d", n, a, seed=seed).dense()
 
 
-@pytest.mark.parametrize("case", _fuzz_cases(), ids=lambda c: f"fuzz{c[0]}")
+@pytest.mark.parametrize("case", _fuzz_cases() + _fuzz_cases(12, 2025, (32, 64), (spamm.BF16, spamm.BF16X3), 24),
+                         ids=lambda c: f"fuzz{c[0]}")
 def test_fuzz_small_random(ctx, case):
     i, n, bs, kind, tau, mode, prec, alias, a = case
     print(f"case: fuzz{i} n={n} leaf={bs} {kind} tau={tau:.2e} mode={mode} prec={prec} alias={alias}", flush=True)
