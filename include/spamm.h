@@ -53,7 +53,9 @@ typedef enum spamm_status {
   SPAMM_ESHAPE = 2,       /* A and B (or D) differ in n or leaf size           */
   SPAMM_ENOMEM = 3,       /* the arena cannot hold the result                 */
   SPAMM_ENONFINITE = 4,   /* NaN or Inf in an input matrix                    */
-  SPAMM_EUNSUPPORTED = 5, /* requested precision/leaf combination not built   */
+  SPAMM_EUNSUPPORTED = 5, /* not supported: precision/leaf combination not
+                             built, a needed FP64 copy absent, or a batch too
+                             large for one counting pass                     */
   SPAMM_EDEVICE = 6       /* a HIP call failed (message in spamm_last_error)  */
 } spamm_status;
 
