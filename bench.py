@@ -635,6 +635,8 @@ def main():
         }
         out["fixed_error"]["f32_over_f64"] = round(out["fixed_error"]["f32"]["multiplies_per_s"] /
                                                    out["fixed_error"]["f64"]["multiplies_per_s"], 3)
+        # every FP32 error within the approximation bound plus the rounding bound
+        out["fixed_error"]["bounds_hold"] = all(e["err"] <= e["bound"] + e["prec_bound"] for e in e32)
     if not args.skip_extras and not args.no_3d:
         log("bench: 3D decay n=32768")
         out["dense3d"] = dense3d(args.steps_3d)
