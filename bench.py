@@ -430,7 +430,7 @@ def errors(ctx, dev, host, prec):
 
 def fixed_error_rate(ctx, dev, prec, errs, reps):
     """Multiplies/s for the largest tau meeting ||E||_F <= 1e-5 ||A||_F^2 per
-    (alpha, scheme), matrices prebuilt (norms precomputed, as in Sec. 5.2)."""
+    (alpha, scheme), matrices prebuilt (norms precomputed, as in Sec. 5.3)."""
     import torch
     from paper_1906_08148_amd import spamm
     store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32

@@ -97,7 +97,7 @@ typedef struct spamm_stats {
   int64_t n_kept;       /* leaf products formed                              */
   int64_t n_candidates; /* leaf triples with both operands non-null          */
   int64_t c_nonnull;    /* non-null leaves of C                              */
-  double flops;         /* 2 * bs^3 * n_kept (Sec. 5.2 flop count)           */
+  double flops;         /* 2 * bs^3 * n_kept (Sec. 5.3 flop count)           */
   double B1;            /* sum over C leaves of b_ij, where b_ij is the sum of
                            ||A_ik||_F ||B_kj||_F over skipped non-null k     */
   double B2;            /* (sum of b_ij^2)^(1/2) >= ||E_SpAMM||_F             */

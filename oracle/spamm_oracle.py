@@ -383,7 +383,7 @@ def multiply(A: Tree, B: Tree, tau: float, mode: int, c_blocks=None) -> Result:
     """C ~= A B by Truncmul, SpAMM or Hybrid.
 
     Truncmul multiplies the truncated inputs and forms every non-null product
-    (Sec. 5.2 notes that no gemm is skipped); SpAMM forms the products that
+    (Sec. 5.3 notes that no gemm is skipped); SpAMM forms the products that
     pass Alg. 1's norm test; Hybrid applies SpAMM to the inputs truncated with
     the same tau.  ``c_blocks`` (optional list of (I, J)) limits which C leaves
     are computed numerically; structure and accounting are always complete.

@@ -1,5 +1,5 @@
 // Batched leaf products (Sec. 4.4: the output structure is built first, then
-// every lowest-level product runs in one batch; Sec. 5.2 counts them as
+// every lowest-level product runs in one batch; Sec. 5.3 counts them as
 // 2*bs^3 flops each).
 //
 // One persistent launch serves every C leaf of every request of a batch that

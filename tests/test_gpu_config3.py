@@ -1,8 +1,13 @@
 """Full-size 3D decay parity: 4096 atoms x 8 functions (n = 32768), a_ij =
-(2u-1) exp(-dist), leaf 64, tau = 1e-6, the size the benchmark times.  The
-oracle's kept lists and accounting are complete; C is compared on sampled
-leaves (every diagonal leaf of a stride and random leaves), which the oracle
-computes one by one."""
+(2u-1) exp(-dist), leaf 64, tau = 1e-6, the size the benchmark times.
+
+The oracle's kept lists and accounting are complete: the GPU's kept list
+must equal it triple for triple (this input has no triple inside the tie
+band and no truncation tie, which the test asserts), and so must the
+candidate count, C's non-null leaves, every skipped bound b_IJ, B1, B2, the
+truncation terms, the error bound and the rounding bound.  C is compared on
+sampled leaves (every eighth diagonal leaf and 128 random leaves), which the
+oracle computes one by one, in FP64, FP32, BF16 and split BF16."""
 import numpy as np
 import pytest
 
@@ -10,7 +15,7 @@ import oracle as O
 import synth
 from paper_1906_08148_amd import spamm
 
-from parity import TIE_BAND, TOL, compare_kept, rel_fro
+from parity import PREC_NAME, TIE_BAND, TOL, compare_kept, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -24,45 +29,55 @@ def setup():
         pytest.skip("needs a GPU")
     print("case: config3 generate", flush=True)
     A = synth.DecaySpec("3d", N, ALPHA, seed=1).dense()
+    print("case: config3 oracle build", flush=True)
     T = O.build(A, LEAF)
-    ctx = spamm.Context(arena_bytes=48 << 30)
+    ctx = spamm.Context(arena_bytes=64 << 30)
     print("case: config3 build", flush=True)
     dA = torch.from_numpy(A).cuda()
-    M = ctx.build(dA, LEAF, stores=spamm.STORE_F32 | spamm.STORE_BF16)
+    M = ctx.build(dA, LEAF, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
     del dA
     torch.cuda.synchronize()
     G = T.G
     rng = np.random.default_rng(5)
     diag = [(i, i) for i in range(0, G, 8)]
-    rand = [tuple(x) for x in rng.integers(0, G, size=(128, 2))]
+    rand = [tuple(int(v) for v in x) for x in rng.integers(0, G, size=(128, 2))]
     sample = sorted(set(diag + rand))
-    yield ctx, M, T, A, sample
+    yield ctx, M, T, sample
     M.release()
     ctx.close()
 
 
 @pytest.mark.parametrize("mode", [spamm.SPAMM, spamm.HYBRID])
-def test_config3_kept_lists_and_sampled_leaves(setup, mode):
-    ctx, M, T, A, sample = setup
+def test_config3_kept_lists_accounting_and_sampled_leaves(setup, mode):
+    ctx, M, T, sample = setup
     print(f"case: config3 mode={mode} oracle", flush=True)
     ref = O.multiply(T, T, TAU, mode, c_blocks=sample)
     ties = O.tie_triples(ref.A_used, ref.B_used, TAU, TIE_BAND)
+    assert len(ties) == 0 and not ref.stats["trunc_tie"]
     want = np.stack([ref.C.leaf(I, J) if ref.C.index[I, J] >= 0 else np.zeros((LEAF, LEAF))
                      for I, J in sample])
-    for prec in (spamm.F32, spamm.BF16, spamm.BF16X3):
+    bnd_ref = ref.skipped_bound
+    for prec in (spamm.F64, spamm.F32, spamm.BF16, spamm.BF16X3):
         print(f"case: config3 mode={mode} prec={prec}", flush=True)
         p = ctx.multiply(M, M, TAU, mode=mode, prec=prec)
         st = p.stats
-        if prec == spamm.F32:
-            ndiff = compare_kept(ctx.kept(p.C), ref.kept, ties, T.G)
-            assert st["n_kept"] == ref.stats["n_kept"] or ndiff > 0
-            if ndiff == 0 and not ref.stats["trunc_tie"]:
-                assert st["n_candidates"] == ref.stats["n_candidates"]
-                assert st["c_nonnull"] == ref.stats["c_nonnull"]
-                for k in ("B1", "B2", "dA", "dB"):
-                    assert abs(st[k] - ref.stats[k]) <= 1e-10 * max(abs(ref.stats[k]), 1e-300) + 1e-300, k
+        if prec == spamm.F64:  # the list is the same in every precision; read it once
+            assert compare_kept(ctx.kept(p.C), ref.kept, ties, T.G) == 0
+        assert st["n_kept"] == ref.stats["n_kept"]
+        assert st["n_candidates"] == ref.stats["n_candidates"]
+        assert st["c_nonnull"] == ref.stats["c_nonnull"]
+        for k in ("B1", "B2", "dA", "dB"):
+            assert abs(st[k] - ref.stats[k]) <= 1e-10 * max(abs(ref.stats[k]), 1e-300) + 1e-300, k
+        assert abs(st["err_bound"] - ref.stats["err_bound"]) <= 1e-10 * ref.stats["err_bound"]
+        bnd = spamm.morton_order_to_grid(ctx.skipped_bound(p.C), T.L)
+        assert np.all(np.abs(bnd - bnd_ref) <= 1e-13 * bnd_ref)
+        pb = O.precision_bound(ref, PREC_NAME[prec])
+        assert abs(st["prec_bound"] - pb) <= 1e-10 * pb
         got = ctx.leaves(p.C, sample)
         r = rel_fro(got, want)
         print(f"  rel {r:.3e} kept {st['n_kept']}", flush=True)
         assert r <= TOL[prec], f"prec {prec}: rel {r:.3e}"
+        # the measured error of the sampled leaves stays within the rounding
+        # bound of the whole product (the bound covers every leaf)
+        assert float(np.linalg.norm(got - want)) <= st["prec_bound"] + O.precision_bound(ref, O.P_F64)
         p.C.release()

@@ -106,8 +106,8 @@ def test_validation_against_fp64_twin():
             continue
         ref = O.multiply(T, T, q["tau"], q["mode"])
         ties = O.tie_triples(ref.A_used, ref.B_used, q["tau"], TIE_BAND)
-        if compare_kept(ctx.kept(pr.C), ref.kept, ties, T.G) or ref.stats["trunc_tie"]:
-            continue
+        # no tie on this input: the kept lists are identical
+        assert compare_kept(ctx.kept(pr.C), ref.kept, ties, T.G) == 0 and not ref.stats["trunc_tie"]
         d = float(np.linalg.norm(ctx.to_dense(pr.C).cpu().numpy() - ref.C.to_dense()))
         # the twin and the oracle differ only by FP64 rounding
         assert abs(st["val_err"] - d) <= 2.0 * O.precision_bound(ref, O.P_F64), (st["val_err"], d)

@@ -200,8 +200,8 @@ def test_truncation_drop_set(ctx):
     for tau in (1e-8, 1e-6, 1e-4, 1e-2):
         Mt, dropped = ctx.truncate(M, tau)
         tr = O.truncate(T, tau)
-        if tr.tie:
-            continue
+        # no tie at this boundary, so the drop set is unique
+        assert not tr.tie
         assert Mt.info.nonnull == tr.tree.nonnull_count()
         assert abs(dropped - tr.dropped_sq) <= 1e-12 * max(tr.dropped_sq, 1e-300)
         check_norms(ctx, Mt, tr.tree)
@@ -419,7 +419,9 @@ def test_fuzz_small_random(ctx, case):
     TB = TA if alias else O.build(B, bs)
     MA = ctx.build(dev(A), bs)
     MB = MA if alias else ctx.build(dev(B), bs)
-    check_product(ctx, MA, MB, TA, TB, tau, mode, prec, alias=alias)
+    # random thresholds may land a product inside the tie band: then the
+    # agreeing C leaves are still compared
+    check_product(ctx, MA, MB, TA, TB, tau, mode, prec, alias=alias, expect_full=False)
     if not alias:
         MB.release()
     MA.release()

@@ -1,8 +1,12 @@
-"""Purification chain on the device against the oracle's chain: 3D decay
-n = 2048 (256 atoms x 8 functions), leaf 64, Hybrid, tau = 1e-6, 20 SP2
-steps, n_occ = n / 2.  The FP64 chain follows the oracle step by step
-(trace, branch, products formed, iterate); the FP32 chain stays close to
-the FP64 one."""
+"""Purification chain on the device against the oracle's chain: 3D decay,
+leaf 64, Hybrid, tau = 1e-6, 20 SP2 steps, n_occ = n / 2.
+
+* n = 2048 (256 atoms) and n = 4096 (512 atoms, an 8^3 cube): the FP64
+  chain follows the oracle step by step (trace, branch, products formed,
+  iterate); the FP32 chain stays close to the FP64 one.
+* n = 32768 (the 16^3 cube): the first step, against the oracle's first
+  step -- scaling bounds, branch, kept list triple for triple, the step's
+  accounting and sampled leaves of X_1."""
 import numpy as np
 import pytest
 
@@ -11,28 +15,30 @@ import synth
 from oracle import purify as PU
 from paper_1906_08148_amd import purify, spamm
 
-from parity import rel_fro
+from parity import TIE_BAND, compare_kept, rel_fro
 
 pytestmark = pytest.mark.gpu
 
-N, LEAF, TAU, STEPS = 2048, 64, 1e-6, 20
+LEAF, TAU, STEPS = 64, 1e-6, 20
 
 
-def test_sp2_chain_matches_oracle():
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_sp2_chain_matches_oracle(n):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("needs a GPU")
-    print("case: purification n=2048", flush=True)
-    A = synth.DecaySpec("3d", N, 1.0, seed=1).dense()
-    ref, (lo_r, hi_r) = PU.sp2_chain(A, LEAF, N / 2, TAU, STEPS, O.HYBRID)
-    ctx = spamm.Context(arena_bytes=4 << 30)
+    print(f"case: purification n={n} oracle chain", flush=True)
+    A = synth.DecaySpec("3d", n, 1.0, seed=1).dense()
+    ref, (lo_r, hi_r) = PU.sp2_chain(A, LEAF, n / 2, TAU, STEPS, O.HYBRID)
+    print(f"case: purification n={n} device chains", flush=True)
+    ctx = spamm.Context(arena_bytes=8 << 30)
     X = ctx.build(torch.from_numpy(A).cuda(), LEAF)
-    ident = ctx.identity(N, LEAF)
+    ident = ctx.identity(n, LEAF)
     X0, tr0, lo, hi = purify.scale_unit(ctx, X, ident)
     assert abs(lo - lo_r) <= 1e-12 * abs(lo_r) and abs(hi - hi_r) <= 1e-12 * abs(hi_r)
     X064 = ctx.multiply(X0, ident, 0.0, mode=spamm.SPAMM, prec=spamm.F64).C
-    c64 = purify.Chain(ctx, X0, tr0, N / 2, TAU, spamm.F64)
-    c32 = purify.Chain(ctx, X064, tr0, N / 2, TAU, spamm.F32)
+    c64 = purify.Chain(ctx, X0, tr0, n / 2, TAU, spamm.F64)
+    c32 = purify.Chain(ctx, X064, tr0, n / 2, TAU, spamm.F32)
     for k in range(STEPS):
         s64 = c64.step(ident)
         s32 = c32.step(ident)
@@ -48,5 +54,60 @@ def test_sp2_chain_matches_oracle():
               f"fp64 rel {e:.2e} fp32-fp64 rel {d:.2e} idem {s64.idempotency:.3e}", flush=True)
         assert d <= 1e-3, (k, d)
     for m in (c64.X, c32.X, ident, X):
+        m.release()
+    ctx.close()
+
+
+def test_sp2_first_step_full_size():
+    """n = 32768: the oracle runs the scaling and step 1 with its kept list
+    and accounting in full and the iterate on sampled leaves."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    n = 32768
+    print("case: purification n=32768 step 1 oracle", flush=True)
+    A = synth.DecaySpec("3d", n, 1.0, seed=1).dense()
+    X0r, lo_r, hi_r = PU.scale_unit(A)
+    T0 = O.build(X0r, LEAF)
+    G = T0.G
+    rng = np.random.default_rng(17)
+    sample = sorted({(i, i) for i in range(0, G, 16)} |
+                    {tuple(int(v) for v in x) for x in rng.integers(0, G, size=(64, 2))})
+    ref = O.multiply(T0, T0, TAU, O.HYBRID, c_blocks=sample)
+    ties = O.tie_triples(ref.A_used, ref.B_used, TAU, TIE_BAND)
+    tr0 = float(np.trace(X0r))
+    branch_r = 0 if tr0 > n / 2 else 1
+    print("case: purification n=32768 step 1 device", flush=True)
+    ctx = spamm.Context(arena_bytes=64 << 30)
+    dA = torch.from_numpy(A).cuda()
+    X = ctx.build(dA, LEAF, stores=spamm.STORE_F64)
+    del dA
+    ident = ctx.identity(n, LEAF, stores=spamm.STORE_F64)
+    X0, tr0g, lo, hi = purify.scale_unit(ctx, X, ident)
+    assert abs(lo - lo_r) <= 1e-12 * abs(lo_r) and abs(hi - hi_r) <= 1e-12 * abs(hi_r)
+    assert abs(tr0g - tr0) <= 1e-10 * abs(tr0)
+    X0_leaves = ctx.leaves(X0, sample)
+    c64 = purify.Chain(ctx, X0, tr0g, n / 2, TAU, spamm.F64)
+    s = c64.step(ident)
+    assert s.branch == branch_r
+    # X_0 is formed in a different order on the two sides, so its leaf
+    # norms may differ in the last bits: only tie-band triples may differ
+    ndiff = compare_kept(ctx.kept(c64.X), ref.kept, ties, G)
+    assert not ref.stats["trunc_tie"]
+    if ndiff == 0:
+        assert s.n_kept == ref.stats["n_kept"]
+        assert s.stats["c_nonnull"] == ref.stats["c_nonnull"]
+    assert s.stats["n_candidates"] == ref.stats["n_candidates"]
+    assert abs(s.stats["err_bound"] - ref.stats["err_bound"]) <= 1e-10 * ref.stats["err_bound"]
+    want = np.stack([ref.C.leaf(I, J) if ref.C.index[I, J] >= 0 else np.zeros((LEAF, LEAF))
+                     for I, J in sample])
+    if branch_r == 1:
+        want = 2.0 * X0_leaves - want
+    got = ctx.leaves(c64.X, sample)
+    r = rel_fro(got, want)
+    print(f"  step 1: branch {s.branch} kept {s.n_kept} ties {len(ties)} differing {ndiff} "
+          f"sampled rel {r:.3e}", flush=True)
+    assert r <= 1e-12
+    for m in (c64.X, ident, X):
         m.release()
     ctx.close()
