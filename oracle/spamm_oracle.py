@@ -70,7 +70,8 @@ def morton_key(I, J):
     I = np.asarray(I, dtype=np.int64)
     J = np.asarray(J, dtype=np.int64)
     key = np.zeros(np.broadcast(I, J).shape, dtype=np.int64)
-    for b in range(31):
+    top = int(max(I.max(initial=0), J.max(initial=0)))
+    for b in range(top.bit_length()):  # higher bits of I and J are zero
         key |= ((I >> b) & 1) << (2 * b + 1)
         key |= ((J >> b) & 1) << (2 * b)
     return key
@@ -164,8 +165,24 @@ def build(dense: np.ndarray, bs: int) -> Tree:
     full = np.zeros((G * bs, G * bs), dtype=np.float64)
     full[:n, :n] = dense
     leafs4 = full.reshape(G, bs, G, bs).transpose(0, 2, 1, 3)
-    coords = [(I, J) for I in range(G) for J in range(G)]
-    return _from_leaves(n, bs, G, L, coords, (leafs4[I, J] for I, J in coords))
+    # the leaves in row-major (I, J) order, all-zero ones null, as
+    # _from_leaves does for a list; each leaf's squared norm is the sum of
+    # its own bs * bs squares, as there
+    leafs4 = np.ascontiguousarray(leafs4)
+    del full
+    present = np.any(leafs4 != 0, axis=(2, 3))
+    store = leafs4[present]
+    del leafs4
+    index = np.full((G, G), -1, dtype=np.int64)
+    index[present] = np.arange(len(store))
+    sqs = np.empty(len(store), dtype=np.float64)
+    for c0 in range(0, len(store), 4096):  # in chunks: small temporaries
+        blk = store[c0:c0 + 4096]
+        sqs[c0:c0 + 4096] = np.sum(blk * blk, axis=(1, 2))
+    leaf_sq = np.zeros((G, G), dtype=np.float64)
+    leaf_sq[present] = sqs
+    sq, pres = pyramid(leaf_sq, present)
+    return Tree(n, bs, G, L, index, store.reshape(-1, bs, bs), sq, pres)
 
 
 def build_from_blocks(n: int, bs: int, coords: np.ndarray, data: np.ndarray) -> Tree:
@@ -255,7 +272,9 @@ def truncate(t: Tree, tau: float) -> Truncation:
     b0 = float(Fraction(acc, 1 << 1074))
     b1 = float(Fraction(nxt_sum, 1 << 1074)) if r < len(order) else math.inf
     band = 1e-12 * tau2
-    tie = abs(b0 - tau2) <= band or (r < len(order) and abs(b1 - tau2) <= band)
+    # a dropped prefix of zero squared norm (nothing dropped, or only leaves
+    # whose squares underflow) is summed exactly on every side: no tie there
+    tie = (b0 > 0.0 and abs(b0 - tau2) <= band) or (r < len(order) and abs(b1 - tau2) <= band)
     # equal-norm run straddling the boundary also counts as a tie
     if 0 < r < len(order) and s[order[r - 1]] == s[order[r]]:
         tie = True
@@ -309,7 +328,7 @@ def _decode_sorted(keys_list, G) -> np.ndarray:
     m = keys // G
     I = np.zeros_like(m)
     J = np.zeros_like(m)
-    for b in range(31):
+    for b in range((G - 1).bit_length()):  # coordinates are below G
         I |= ((m >> (2 * b + 1)) & 1) << b
         J |= ((m >> (2 * b)) & 1) << b
     return np.stack([I, K, J], axis=1)

@@ -271,3 +271,46 @@ def test_skipped_bound_zero_for_truncmul_and_tau_zero():
     assert not O.multiply(T, T, 1e-3, O.TRUNCMUL).skipped_bound.any()
     r = O.multiply(T, T, 0.0, O.SPAMM)
     assert not r.skipped_bound.any() and r.stats["B1"] == 0.0
+
+
+# ---------------------------------------------------------------- dense build
+
+@pytest.mark.parametrize("kind,n,bs", [("3d", 1024, 64), ("1d", 1000, 32), ("1d", 77, 16), ("1d", 5, 8)])
+def test_dense_build_equals_block_list_of_every_leaf(kind, n, bs):
+    """``build`` (whole-array form) against ``build_from_blocks`` with every
+    leaf listed (one leaf at a time): the same null map, leaves, slots and
+    norms, bit for bit."""
+    A = synth.DecaySpec(kind, n, 0.7, seed=2).dense()
+    A[:bs, :bs] = 0.0  # one all-zero leaf inside the matrix
+    g = -(-n // bs)
+    coords = np.array([(I, J) for I in range(g) for J in range(g)])
+    data = np.zeros((len(coords), bs, bs))
+    for t, (I, J) in enumerate(coords):
+        blk = A[I * bs:(I + 1) * bs, J * bs:(J + 1) * bs]
+        data[t, :blk.shape[0], :blk.shape[1]] = blk
+    T, Tb = O.build(A, bs), O.build_from_blocks(n, bs, coords, data)
+    _same_tree(T, Tb)
+    assert np.array_equal(T.index, Tb.index)
+    assert not T.leaf_present[0, 0] or n <= bs and not np.any(A)
+
+
+# ---------------------------------------------------------------- truncation ties
+
+def test_truncation_tie_only_where_rounding_can_move_the_boundary():
+    """tau = 0 drops nothing and the empty prefix is summed exactly: no tie.
+    A boundary sum equal to tau^2 after real additions is a tie."""
+    # distinct leaf norms (a symmetric matrix would pair them up, and an
+    # equal-norm pair split by the boundary is a tie of its own)
+    A = synth.dense_from_blocks(256, 32, *synth.random_blocks(5, 256, 32, 0.6))
+    A *= np.random.default_rng(2).uniform(0.5, 2.0, size=A.shape)
+    T = O.build(A, 32)
+    tr = O.truncate(T, 0.0)
+    assert len(tr.dropped) == 0 and not tr.tie
+    # tau^2 within rounding of the smallest leaf's squared norm: whether
+    # that leaf goes depends on the last bit of a sum -> tie
+    s_min = float(T.leaf_sq[T.leaf_present].min())
+    tr = O.truncate(T, math.sqrt(s_min))
+    assert len(tr.dropped) in (0, 1) and tr.tie
+    # well clear of it on either side: no tie
+    assert not O.truncate(T, math.sqrt(s_min) * (1 - 1e-9)).tie
+    assert not O.truncate(T, math.sqrt(s_min) * (1 + 1e-9)).tie
