@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the approximate-product hot path on one MI355X.
 
-Workload (one "step"): the 1D-decay sweep n = 16384, leaf 64,
-a_ij = (2u - 1) exp(-alpha |i - j|), alpha in {0.2, 0.5}, tau in {1e-4, 1e-6,
-1e-8}, schemes Truncmul / SpAMM / Hybrid, A = B.  A step builds both matrices
-from their device-resident leaf-block lists (norms, null map, pyramid), then
-runs the 18 multiplies as one batch: truncation, pruning, one persistent
-leaf-GEMM launch, C pyramids and the FP64 accounting.  The headline value is
-kept-leaf GFLOP/s (2 * 64^3 per formed leaf product) in FP32-MFMA mode; the
-same step in FP64 mode is reported beside it.
+Headline workload (one "step"): the 3D decay matrix n = 32768 (4096 atoms
+on a 16^3 lattice, jitter 0.1, x 8 basis functions), a_ij = (2u - 1)
+exp(-dist), leaf 64, tau = 1e-6, A = B.  A step builds the quadtree from the
+dense FP64 matrix already in HBM (leaf norms, null map, pyramid, leaf
+copies), then runs the combined scheme (Hybrid: leaf-level truncation of
+both operands, pruning, the persistent leaf-GEMM launch, C's pyramid and the
+FP64 accounting) with FP64 leaf products, the paper's arithmetic.  The
+headline value is kept-leaf GFLOP/s (2 * 64^3 per formed leaf product, the
+flop count of Sec. 5.3) over whole steps.
+
+Beside it: the same step in FP32, BF16 and split BF16 (leaf-GEMM rate and
+error against the FP64 product), multiplies/s at a fixed error
+||A A - C||_F <= 1e-5 ||A||_F ||B||_F per precision (Sec. 5.3's
+target-accuracy comparison), the 1D batch of 18 multiplies (n = 16384),
+the purification chain, the served stream and the oracle timed on the host.
 
 Prints one JSON line (see the repository's measurement notes for fields).
 """
@@ -37,8 +44,12 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 # 3D decay workload: 4096 atoms (16^3 lattice, jitter 0.1) x 8 functions
 N3D, LEAF3D, ALPHA3D, TAU3D = 32768, 64, 1.0, 1e-6
+SIGMA_REL = 1e-5  # fixed error: ||A A - C||_F <= SIGMA_REL ||A||_F ||B||_F
+TAU_GRID = tuple(10.0 ** -k for k in range(0, 9))  # 1 ... 1e-8, decades
 GEMM_SOURCE = os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "k_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f32_leaf64_decay1d_n16384_batch18_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f64_leaf64_decay3d_n32768_hybrid_traffic.json")
+PREC_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16x3"}
+PEAKS = {0: FP64_MFMA_PEAK_TFLOPS, 1: FP32_MFMA_PEAK_TFLOPS, 2: BF16_MFMA_PEAK_TFLOPS, 3: BF16_MFMA_PEAK_TFLOPS}
 
 
 def log(msg):
@@ -141,75 +152,210 @@ def multiply_only(ctx, dev, prec, steps, warmup):
     return {"ms_per_step": round(total / steps * 1e3, 4), "gflops": round(flops / total / 1e9, 3)}
 
 
-def dense3d(steps):
-    """3D decay, n = 32768, leaf 64, tau = 1e-6, A = B: one multiply per
-    (scheme, precision), timed alone (warm), with the leaf-GEMM time from the
-    library's events and the relative difference from the FP64 product."""
-    import torch
-    import synth
+def store_for(prec):
     from paper_1906_08148_amd import spamm
-    t0 = time.perf_counter()
-    A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).dense()
-    gen_s = time.perf_counter() - t0
-    ctx = spamm.Context(arena_bytes=64 << 30)
-    dA = torch.from_numpy(A).cuda()
-    del A
-    M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
+    return {spamm.F64: spamm.STORE_F64, spamm.F32: spamm.STORE_F32}.get(prec, spamm.STORE_BF16)
+
+
+def config3_steps(ctx, dA, prec, steps, warmup, mode=None, keep_last=False):
+    """`steps` whole steps of the 3D workload in precision `prec`: build from
+    the dense matrix in HBM, then one multiply (Hybrid by default) with its
+    statistics.  The library's HIP events (recorded on the stream the
+    kernels run on) are on during the timed steps, so the per-kernel-class
+    times come from the timed region itself."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    mode = spamm.HYBRID if mode is None else mode
+
+    def one():
+        M = ctx.build(dA, LEAF3D, stores=store_for(prec))
+        p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)
+        return M, p
+
+    for _ in range(warmup):
+        M, p = one()
+        p.C.release()
+        M.release()
     torch.cuda.synchronize()
-    out = {"workload": f"3D decay n={N3D} (4096 atoms x 8 functions), alpha {ALPHA3D}, leaf {LEAF3D}, "
-                       f"tau {TAU3D}, A=B", "generate_s": round(gen_s, 1), "runs": {}}
-    peaks = {spamm.F64: FP64_MFMA_PEAK_TFLOPS, spamm.F32: FP32_MFMA_PEAK_TFLOPS,
-             spamm.BF16: BF16_MFMA_PEAK_TFLOPS, spamm.BF16X3: BF16_MFMA_PEAK_TFLOPS}
-    names = {spamm.F64: "f64", spamm.F32: "f32", spamm.BF16: "bf16", spamm.BF16X3: "bf16x3"}
-    for mode, mname in ((spamm.SPAMM, "spamm"), (spamm.HYBRID, "hybrid"), (spamm.SPAMM_SYM, "spamm_sym")):
-        ref = None
-        for prec in ((spamm.F64, spamm.F32) if mode == spamm.SPAMM_SYM else
-                     (spamm.F64, spamm.F32, spamm.BF16, spamm.BF16X3)):
-            log(f"bench: 3D {mname} {names[prec]}")
-            p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)  # warm
+    ctx.timing(enable=True, reset=True)
+    lat, flops, last = [], 0.0, None
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s0 = time.perf_counter()
+        M, p = one()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        flops += p.stats["flops"]
+        M.release()
+        if keep_last and k + 1 == steps:
+            last = p
+        else:
             p.C.release()
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(steps):
-                ctx.timing(enable=True, reset=True)
-                s0 = time.perf_counter()
-                p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - s0)
-                tm = ctx.timing(enable=False, reset=True)
-                if _ + 1 < steps:
-                    p.C.release()
-            dt = sorted(ts)[len(ts) // 2]
-            st = p.stats
-            gemm_s = tm["gemm_ms"] / max(tm["gemm_launches"], 1) * 1e-3
-            rec = {"ms": round(dt * 1e3, 2), "gflops": round(st["flops"] / dt / 1e9, 1),
-                   "n_kept": int(st["n_kept"]), "gemm_ms": round(gemm_s * 1e3, 2),
-                   "gemm_tflops": round(st["flops"] / gemm_s / 1e12, 2),
-                   "gemm_frac": round(st["flops"] / gemm_s / 1e12 / peaks[prec], 4),
-                   "phases_ms": {k: round(tm[k + "_ms"], 2) for k in ("trunc", "prune", "gemm", "pyramid")}}
-            C = ctx.to_dense(p.C)
-            if prec == spamm.F64:
-                ref = C
-                rec["rel_err_vs_f64"] = 0.0
-            else:
-                rec["rel_err_vs_f64"] = float(torch.linalg.norm(C - ref) / torch.linalg.norm(ref))
-                del C
-            p.C.release()
-            out["runs"][f"{mname}/{names[prec]}"] = rec
-        del ref
-        torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    tm = ctx.timing(enable=False, reset=True)
+    g_ms = tm["gemm_ms"] / max(tm["gemm_launches"], 1)
+    g_fl = tm["gemm_flops"] / max(tm["gemm_launches"], 1)
+    return dict(total=total, lat=lat, flops=flops, tm=tm, stats=p.stats, gemm_ms=g_ms, gemm_flops=g_fl,
+                gemm_tflops=g_fl / (g_ms * 1e-3) / 1e12, last=last)
+
+
+def multiply_only_3d(ctx, dA, prec, steps, mode=None):
+    """The same multiply with the quadtree built once beforehand: norms
+    precomputed, the paper's timing convention (Sec. 5.3)."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    mode = spamm.HYBRID if mode is None else mode
+    M = ctx.build(dA, LEAF3D, stores=store_for(prec))
+    ctx.multiply(M, M, TAU3D, mode=mode, prec=prec).C.release()
+    torch.cuda.synchronize()
+    flops = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec, stats=False)
+        p.C.release()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)
+    flops = p.stats["flops"] * steps
+    p.C.release()
     M.release()
-    # leaf size and MFMA tile picked by the autotuner (hybrid, FP32)
-    from paper_1906_08148_amd import autotune
-    log("bench: 3D autotune")
-    tuner = autotune.Tuner(ctx, leaves=(32, 64, 128), tiles=(0, 1), reps=2)
-    sig = autotune.signature("3d", N3D, ALPHA3D, TAU3D, spamm.HYBRID, spamm.F32)
-    best = tuner.tune(lambda leaf: ctx.build(dA, leaf, stores=spamm.STORE_F32), sig, TAU3D, spamm.HYBRID, spamm.F32)
-    out["autotune"] = {"leaf": best["leaf"], "tile": best["tile"],
-                       "table": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-                                 for r in best["table"]]}
-    del dA
-    ctx.close()
+    return {"ms_per_multiply": round(total / steps * 1e3, 3), "gflops": round(flops / total / 1e9, 1),
+            "multiplies_per_s": round(steps / total, 3)}
+
+
+def config3_precisions(ctx, dA, steps, C64):
+    """FP32, BF16 and split BF16 on the same step: whole-step and leaf-GEMM
+    rates, the GEMM's fraction of its precision's MFMA peak, and
+    ||C - C_FP64||_F / ||C_FP64||_F against the FP64 product."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    out = {}
+    nref = float(torch.linalg.norm(C64))
+    for prec in (spamm.F32, spamm.BF16X3, spamm.BF16):
+        log(f"bench: 3D hybrid {PREC_NAMES[prec]}")
+        r = config3_steps(ctx, dA, prec, steps, 1, keep_last=True)
+        C = ctx.to_dense(r["last"].C)
+        rel = float(torch.linalg.norm(C - C64)) / nref
+        del C
+        r["last"].C.release()
+        out[PREC_NAMES[prec]] = {
+            "ms_per_step": round(r["total"] / steps * 1e3, 2),
+            "gflops": round(r["flops"] / r["total"] / 1e9, 1),
+            "gemm_ms": round(r["gemm_ms"], 3), "gemm_tflops": round(r["gemm_tflops"], 2),
+            "gemm_frac_of_peak": round(r["gemm_tflops"] / PEAKS[prec], 4), "peak_tflops": PEAKS[prec],
+            "rel_err_vs_f64": rel, "prec_bound": r["stats"]["prec_bound"],
+            "phases_ms_per_step": {k: round(r["tm"][k + "_ms"] / steps, 3)
+                                   for k in ("build", "trunc", "prune", "gemm", "pyramid")}}
+        torch.cuda.empty_cache()
+    return out
+
+
+def fixed_error_3d(ctx, dA, reps=3):
+    """Sec. 5.3's comparison at a target accuracy: for each precision, the
+    largest tau on the decade grid 1 ... 1e-8 whose Hybrid product has
+    ||A A - C||_F <= sigma = 1e-5 ||A||_F ||B||_F (the exact product A A in
+    FP64 by the vendor GEMM, an independent reference), then multiplies/s at
+    that tau with the quadtree built once (norms precomputed).  BF16 alone
+    stays above sigma at every tau: its rounding error exceeds the budget."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    exact = dA @ dA
+    nA = float(torch.linalg.norm(dA))
+    sigma = SIGMA_REL * nA * nA
+    M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
+    out = {"sigma": sigma, "sigma_rel": SIGMA_REL, "mode": "hybrid", "tau_grid": list(TAU_GRID), "precisions": {}}
+    for prec in (spamm.F64, spamm.F32, spamm.BF16X3, spamm.BF16):
+        tried = []
+        chosen = None
+        for tau in TAU_GRID:
+            p = ctx.multiply(M, M, tau, mode=spamm.HYBRID, prec=prec)
+            err = float(torch.linalg.norm(ctx.to_dense(p.C) - exact))
+            tried.append({"tau": tau, "err": err, "n_kept": int(p.stats["n_kept"]),
+                          "bound": p.stats["err_bound"] + p.stats["prec_bound"]})
+            p.C.release()
+            if err <= sigma:
+                chosen = tau
+                break
+            # the error has reached the precision's rounding floor: smaller
+            # tau cannot help
+            if len(tried) >= 3 and err > 0.5 * tried[-2]["err"] and tau <= 1e-4:
+                break
+        rec = {"tau": chosen, "tried": tried}
+        if chosen is not None:
+            ctx.multiply(M, M, chosen, mode=spamm.HYBRID, prec=prec, stats=False).C.release()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.multiply(M, M, chosen, mode=spamm.HYBRID, prec=prec, stats=False).C.release()
+            torch.cuda.synchronize()
+            rec["multiplies_per_s"] = round(reps / (time.perf_counter() - t0), 3)
+        out["precisions"][PREC_NAMES[prec]] = rec
+        log(f"bench: fixed error {PREC_NAMES[prec]}: tau {chosen}")
+    M.release()
+    del exact
+    torch.cuda.empty_cache()
+    P = out["precisions"]
+    if P["f32"].get("multiplies_per_s") and P["f64"].get("multiplies_per_s"):
+        out["f32_over_f64"] = round(P["f32"]["multiplies_per_s"] / P["f64"]["multiplies_per_s"], 3)
+    return out
+
+
+def symmetric_3d(ctx, dA, C64):
+    """The square of the symmetric 3D matrix with only the C leaves on and
+    above the diagonal formed (each leaf below is its mirror's transpose),
+    against the full product: time and agreement."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    out = {}
+    M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32)
+    nref = float(torch.linalg.norm(C64))
+    for name, mode in (("spamm_sym", spamm.SPAMM_SYM), ("hybrid_sym", getattr(spamm, "HYBRID_SYM", None))):
+        if mode is None:
+            continue
+        for prec in (spamm.F64, spamm.F32):
+            ctx.multiply(M, M, TAU3D, mode=mode, prec=prec).C.release()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = ctx.multiply(M, M, TAU3D, mode=mode, prec=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec = {"ms": round(dt * 1e3, 2), "n_kept_formed": int(p.stats["n_kept"])}
+            if mode != spamm.SPAMM_SYM:
+                rec["rel_diff_vs_full_hybrid_f64"] = float(torch.linalg.norm(ctx.to_dense(p.C) - C64)) / nref
+            p.C.release()
+            out[f"{name}/{PREC_NAMES[prec]}"] = rec
+    M.release()
+    return out
+
+
+def autotune_3d(ctx, dA):
+    """Leaf size (32 ... 256) and MFMA tile picked by the autotuner for the 3D
+    workload (Hybrid, tau 1e-6) per precision, among the candidates whose
+    error meets sigma = 1e-5 ||A||_F^2: by the library's guaranteed bound,
+    and by the error measured against the exact product."""
+    import torch
+    from paper_1906_08148_amd import autotune, spamm
+    out = {}
+    exact = dA @ dA
+    budget = SIGMA_REL * float(torch.linalg.norm(dA)) ** 2
+    tuner = autotune.Tuner(ctx, leaves=(32, 64, 128, 256), tiles=(0, 1), reps=1)
+    measured = lambda c, p: float(torch.linalg.norm(c.to_dense(p.C) - exact))
+    for prec in (spamm.F32, spamm.BF16X3, spamm.BF16):
+        for how, fn in (("bound", None), ("measured", measured)):
+            if how == "bound" and prec != spamm.F32:
+                continue  # the BF16 rounding bounds are above sigma at every leaf size
+            log(f"bench: 3D autotune {PREC_NAMES[prec]} ({how} error)")
+            sig = autotune.signature("3d", N3D, ALPHA3D, TAU3D, spamm.HYBRID, prec) + (how,)
+            best = tuner.tune(lambda leaf: ctx.build(dA, leaf, stores=store_for(prec)), sig,
+                              TAU3D, spamm.HYBRID, prec, budget=budget, error_fn=fn)
+            out[f"{PREC_NAMES[prec]}/{how}"] = {
+                "leaf": best["leaf"], "tile": best["tile"], "budget": budget,
+                "table": [{k: (round(v, 6) if isinstance(v, float) and k == "seconds" else v) for k, v in r.items()}
+                          for r in best["table"]]}
+            torch.cuda.empty_cache()
+    del exact
+    ctx.set_option("gemm_tile", 1)
     return out
 
 
@@ -241,7 +387,7 @@ def paper_workloads():
     modes = {"truncmul": spamm.TRUNCMUL, "spamm": spamm.SPAMM, "hybrid": spamm.HYBRID}
     model = {"workload": f"1D decay n={n}, alpha {alpha}, A=B, FP64, sigma {sigma}",
              "generate_s": round(gen_s, 1), "rows": []}
-    for leaf in (32, 64, 128):
+    for leaf in (32, 64, 128, 256):
         M = ctx.build(dA, leaf, stores=spamm.STORE_F64)
         ctx.multiply(M, M, 1e-4, mode=spamm.SPAMM, prec=spamm.F64).C.release()  # prune views
         base = None
@@ -282,7 +428,7 @@ def paper_workloads():
     torch.cuda.empty_cache()
     sweep = {"workload": "2048 x 2048 random uniform blocks, FP64, every product (Truncmul, tau 0), "
                          "batches of 32 multiplies", "rows": []}
-    for leaf in (32, 64, 128):
+    for leaf in (32, 64, 128, 256):
         for fill in (0.1, 0.3, 0.5, 0.7, 1.0):
             log(f"bench: leaf library leaf {leaf} fill {fill}")
             mats = []
@@ -313,10 +459,11 @@ def paper_workloads():
     return {"model_problem": model, "leaf_library": sweep}
 
 
-def purification(steps):
-    """20 trace-driven purification steps (X^2 or 2X - X^2, Hybrid, tau 1e-6)
-    on the 3D decay matrix n = 32768 scaled into [0, 1], FP64 and FP32 chains
-    side by side; per step the trace, products, time and ||X32 - X64||_F."""
+def purification(steps, mode=None):
+    """20 trace-driven purification steps (X^2 or 2X - X^2, tau 1e-6, the
+    symmetric square of Hybrid by default: the iterates are symmetric) on the
+    3D decay matrix n = 32768 scaled into [0, 1], FP64 and FP32 chains side
+    by side; per step the trace, products, time and ||X32 - X64||_F."""
     import torch
     import synth
     from paper_1906_08148_amd import purify, spamm
@@ -327,11 +474,13 @@ def purification(steps):
     X = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32)
     torch.cuda.synchronize()
     del dA
-    recs, diffs, (lo, hi) = purify.sp2(ctx, X, N3D / 2, TAU3D, steps, precs=(spamm.F64, spamm.F32))
+    mode = spamm.HYBRID_SYM if mode is None else mode
+    recs, diffs, (lo, hi) = purify.sp2(ctx, X, N3D / 2, TAU3D, steps, precs=(spamm.F64, spamm.F32), mode=mode)
     X.release()
     ctx.close()
-    out = {"workload": f"SP2 purification of the 3D decay matrix n={N3D}, leaf {LEAF3D}, hybrid, tau {TAU3D}, "
-                       f"n_occ = n/2, {steps} steps", "gershgorin": [lo, hi], "steps": []}
+    out = {"workload": f"SP2 purification of the 3D decay matrix n={N3D}, leaf {LEAF3D}, "
+                       f"{'hybrid_sym' if mode == spamm.HYBRID_SYM else 'hybrid'}, tau {TAU3D}, n_occ = n/2, "
+                       f"{steps} steps", "gershgorin": [lo, hi], "steps": []}
     for k in range(steps):
         r64, r32 = recs[spamm.F64][k], recs[spamm.F32][k]
         out["steps"].append({"k": k, "trace64": round(r64.trace, 6), "trace32": round(r32.trace, 6),
@@ -346,13 +495,14 @@ def purification(steps):
     return out
 
 
-def serving(n_requests, n_max, rates=(0.5, 0.8, 1.0, 1.2)):
+def serving(n_requests, n_max, rates=(0.5, 1.0, 2.0, 4.0)):
     """Served stream: the first `n_requests` requests with n <= n_max of the
     seeded request pool (n in 2048..65536, 1D/3D decay, alpha, tau, scheme
-    drawn per request, FP32, A = B).  Capacity mu is measured alone (one lane, one request per
-    batch); then Poisson arrivals at rate x mu for each x, two lanes with
-    continuous batching and memory admission, fresh lanes (cold quadtree
-    caches) per run."""
+    drawn per request, FP32, A = B).  Capacity mu is measured alone (one
+    lane, one request per batch); then Poisson arrivals at rate x mu for
+    each x, two lanes with continuous batching and memory admission, fresh
+    lanes (cold quadtree caches) per run.  At 2 mu the same stream also runs
+    with each batch's post-sizing kernels launched as one HIP graph."""
     import torch
     from concurrent.futures import ThreadPoolExecutor
     from paper_1906_08148_amd import serve
@@ -373,17 +523,20 @@ def serving(n_requests, n_max, rates=(0.5, 0.8, 1.0, 1.2)):
     out = {"workload": f"first {len(pool)} requests with n <= {n_max} of the seeded pool (n in 2048..65536 step "
                        f"2048, 1D/3D decay, alpha U[0.2,1], tau 10^U[-8,-4], truncmul/spamm/hybrid, FP32, A=B)",
            "generate_s": round(gen_s, 1), "alone": serve.summarize(alone, t_alone), "mu_per_s": mu,
+           "n_max_served": max(r.mat.n for r in pool),
            "kinds": [f"{r.mat.kind}:{r.mat.n}" for r in pool], "runs": {}}
-    for x in rates:
-        log(f"bench: serving at {x} mu")
-        srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs)
+    for x, graph in [(x, False) for x in rates] + [(2.0, True)]:
+        log(f"bench: serving at {x} mu{' (graph)' if graph else ''}")
+        srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs, graph=graph)
         res = serve.run_stream(srv.sched, pool, rate=x * mu, seed=11)
         srv.close()
         torch.cuda.empty_cache()
         sm = serve.summarize(res)
         sm["gflops_frac_of_fp32_peak"] = sm.get("gflops", 0.0) / 1e3 / FP32_MFMA_PEAK_TFLOPS
         sm["batches"] = len(srv.sched.log)
-        out["runs"][str(x)] = sm
+        sm["largest_batch"] = max((len(b[2]) for b in srv.sched.log), default=0)
+        sm["over_alone_capacity"] = round(sm.get("multiplies_per_s", 0.0) / mu, 3)
+        out["runs"][f"{x}{'_graph' if graph else ''}"] = sm
     return out
 
 
@@ -396,156 +549,108 @@ def pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def errors(ctx, dev, host, prec):
-    """||C - A A||_F of every request against the FP64 dense product (torch
-    FP64 GEMM as an independent reference), outside the timed region."""
-    import numpy as np
-    import torch
+def cpu_baseline_3d(sample_n=8192, one_thread=True):
+    """The oracle as it stands on a bounded sample of the 3D workload: the
+    leading sample_n x sample_n principal sub-matrix of the same matrix (the
+    first sample_n / 8 atoms of the Morton order, a box of the same
+    lattice), leaf 64, tau 1e-6, Hybrid, the whole oracle multiply (tree and
+    norms, truncation, kept list, every C leaf, accounting), NumPy FP64 with
+    BLAS on every core the host gives it; then again with one BLAS thread."""
+    import oracle as O
     import synth
-    stats, prods, mats = run_step(ctx, dev, prec, keep=True)
-    out = []
-    i = 0
-    for a in ALPHAS:
-        coords, data = host[a]
-        A = torch.from_numpy(synth.dense_from_blocks(N, LEAF, coords, data)).cuda()
-        exact = A @ A
-        nA = float(torch.linalg.norm(A))
-        for t in TAUS:
-            for m in MODE_NAMES:
-                C = ctx.to_dense(prods[i].C)
-                err = float(torch.linalg.norm(C - exact))
-                out.append(dict(alpha=a, tau=t, mode=m, err=err, sigma=1e-5 * nA * nA,
-                                n_kept=stats[i]["n_kept"], bound=stats[i]["err_bound"],
-                                prec_bound=stats[i]["prec_bound"]))
-                i += 1
-                del C
-        del A, exact
-    for p in prods:
-        p.C.release()
-    for m in mats.values():
-        m.release()
-    torch.cuda.empty_cache()
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_info = threadpool_limits = None
+    A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).block(0, sample_n, 0, sample_n)
+
+    def run():
+        ph = {}
+        t0 = time.perf_counter()
+        T = O.build(A, LEAF3D)
+        ph["tree_and_norms"] = time.perf_counter() - t0
+        s0 = time.perf_counter()
+        r = O.multiply(T, T, TAU3D, O.HYBRID)
+        ph["multiply"] = time.perf_counter() - s0
+        return time.perf_counter() - t0, r.stats["flops"], ph
+
+    dt, flops, ph = run()
+    blas = None
+    if threadpool_info is not None:
+        blas = sum(p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas") or None
+    out = {"value": round(flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": blas or 1, "kind": "oracle",
+           "sample": f"leading {sample_n} x {sample_n} principal block of the 3D decay matrix (first "
+                     f"{sample_n // 8} atoms), leaf {LEAF3D}, tau {TAU3D}, Hybrid: the whole oracle multiply "
+                     f"({dt:.1f} s, {flops:.3e} kept-leaf flops), NumPy FP64; cores = BLAS threads "
+                     f"(Python-level work is one thread)",
+           "host_cores": os.cpu_count(), "seconds": round(dt, 2),
+           "phases_s": {k: round(v, 3) for k, v in ph.items()}}
+    if one_thread and threadpool_limits is not None:
+        with threadpool_limits(1):
+            dt1, fl1, _ = run()
+        out["one_thread"] = {"value": round(fl1 / dt1 / 1e9, 4), "seconds": round(dt1, 2)}
     return out
 
 
-def fixed_error_rate(ctx, dev, prec, errs, reps):
-    """Multiplies/s for the largest tau meeting ||E||_F <= 1e-5 ||A||_F^2 per
-    (alpha, scheme), matrices prebuilt (norms precomputed, as in Sec. 5.3)."""
-    import torch
-    from paper_1906_08148_amd import spamm
-    store = spamm.STORE_F64 if prec == spamm.F64 else spamm.STORE_F32
-    mats = {a: ctx.build_blocks(N, LEAF, c, d, stores=store) for a, (c, d) in dev.items()}
-    chosen = []
-    for a in ALPHAS:
-        for mi, m in enumerate(MODE_NAMES):
-            ok = [e for e in errs if e["alpha"] == a and e["mode"] == m and e["err"] <= e["sigma"]]
-            if ok:
-                best = max(ok, key=lambda e: e["tau"])
-                chosen.append(dict(alpha=a, mode=m, tau=best["tau"], err=best["err"], mi=mi))
-    reqs = [dict(A=mats[c["alpha"]], B=mats[c["alpha"]], tau=c["tau"], mode=c["mi"], prec=prec) for c in chosen]
-    for _ in range(2):
-        for p in ctx.multiply_batch(reqs, stats=False):
-            p.C.release()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for p in ctx.multiply_batch(reqs, stats=False):
-            p.C.release()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for m in mats.values():
-        m.release()
-    return dict(multiplies_per_s=len(reqs) * reps / dt,
-                chosen=[{k: c[k] for k in ("alpha", "mode", "tau", "err")} for c in chosen])
-
-
-def cpu_baseline(host, min_s=10.0):
-    """The oracle as it stands, with one BLAS thread, on whole steps of the
-    same workload (both builds and all 18 multiplies), repeated until at
-    least ``min_s`` seconds of CPU work have run."""
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    t0 = time.perf_counter()
-    flops = 0.0
-    steps = 0
-    while True:
-        for a in ALPHAS:
-            coords, data = host[a]
-            tree = O.build_from_blocks(N, LEAF, coords, data)
-            for t in TAUS:
-                for mi in (O.TRUNCMUL, O.SPAMM, O.HYBRID):
-                    flops += O.multiply(tree, tree, t, mi).stats["flops"]
-        steps += 1
-        if time.perf_counter() - t0 >= min_s:
-            break
-    dt = time.perf_counter() - t0
-    # one more step, timed phase by phase: the leaf trees with their norms,
-    # the truncations, the kept lists, and the rest of each multiply (C
-    # accumulation and accounting)
-    ph = {"build_and_norms": 0.0, "truncation": 0.0, "kept_list": 0.0, "c_and_accounting": 0.0}
-    for a in ALPHAS:
-        coords, data = host[a]
-        s0 = time.perf_counter()
-        tree = O.build_from_blocks(N, LEAF, coords, data)
-        ph["build_and_norms"] += time.perf_counter() - s0
-        for t in TAUS:
-            s0 = time.perf_counter()
-            tr = O.truncate(tree, t).tree
-            ph["truncation"] += 2 * (time.perf_counter() - s0)  # Truncmul and Hybrid each truncate
-            s0 = time.perf_counter()
-            for Tu, use in ((tr, False), (tree, True), (tr, True)):
-                O.kept_flat(Tu, Tu, t, use)
-            kept_s = time.perf_counter() - s0
-            ph["kept_list"] += kept_s
-            s0 = time.perf_counter()
-            for mi in (O.TRUNCMUL, O.SPAMM, O.HYBRID):
-                O.multiply(tree, tree, t, mi)
-            ph["c_and_accounting"] += time.perf_counter() - s0 - kept_s
-    ph["c_and_accounting"] -= ph["truncation"]
-    if limiter is not None:
-        limiter.unregister()
-    return {"value": round(flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} whole step(s): both builds and all 18 multiplies, {dt:.1f} s, "
-                      f"NumPy FP64, one BLAS thread",
-            "host_cores": os.cpu_count(),
-            "phases_s_per_step": {k: round(v, 4) for k, v in ph.items()}}
-
-
-def traffic_for(tile):
+def traffic_for(kernel_name):
     """HBM bytes per GEMM launch from the committed rocprofv3 counter summary,
-    only when it was taken on the current kernel source and tile variant."""
+    only when it was taken on the current kernel source and this kernel."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
     src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != src or rec.get("kernel") != f"void spamm::k_gemm<1, 64, {tile}>":
+    if rec.get("kernel_source_sha256") != src or rec.get("kernel") != kernel_name:
         return None
     return rec.get("bytes_per_launch")
+
+
+def batch_1d(ctx, steps, warmup):
+    """The 1D batch: 18 multiplies of n = 16384 (alpha x tau x scheme) built
+    from leaf-block lists, FP32 and FP64, one batch per step."""
+    from paper_1906_08148_amd import spamm
+    host = make_inputs()
+    dev = gpu_inputs(host)
+    out = {"workload": "1D decay n=16384 leaf 64, alpha {0.2,0.5} x tau {1e-4,1e-6,1e-8} x "
+                       "{truncmul,spamm,hybrid}, A=B, built from leaf-block lists; 18 multiplies per step, one batch"}
+    for prec in (spamm.F32, spamm.F64):
+        total, lat, flops, tm, stats = timed_steps(ctx, dev, prec, steps, warmup)
+        g = tm["gemm_ms"] / max(tm["gemm_launches"], 1)
+        fl = tm["gemm_flops"] / max(tm["gemm_launches"], 1)
+        out[PREC_NAMES[prec]] = {
+            "gflops": round(flops / total / 1e9, 1), "ms_per_step": round(total / steps * 1e3, 4),
+            "multiplies_per_s": round(len(stats) * steps / total, 1),
+            "latency_ms": {"p50": round(pct(lat, 0.5) * 1e3, 4), "p99": round(pct(lat, 0.99) * 1e3, 4)},
+            "gemm_tflops": round(fl / (g * 1e-3) / 1e12, 2),
+            "gemm_frac_of_peak": round(fl / (g * 1e-3) / 1e12 / PEAKS[prec], 4),
+            "phases_ms_per_step": {k: round(tm[k + "_ms"] / steps, 4)
+                                   for k in ("build", "trunc", "prune", "gemm", "pyramid")},
+            "norms_precomputed": multiply_only(ctx, dev, prec, steps, warmup)}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--skip-extras", action="store_true", help="only the timed FP32 steps (profiling)")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D decay n=32768 section")
+    ap.add_argument("--cpu-sample-n", type=int, default=8192, help="size of the oracle's sample (principal block)")
+    ap.add_argument("--skip-extras", action="store_true", help="only the timed headline steps (profiling)")
+    ap.add_argument("--prec", default="f64", choices=sorted(PREC_NAMES.values()),
+                    help="precision of the timed steps (profiling the other GEMMs)")
     ap.add_argument("--graph", action="store_true", help="launch each batch's post-sizing kernels as one HIP graph")
     ap.add_argument("--gemm-tile", type=int, default=None, help="MFMA tile variant (0: 32x32, 1: 16x16)")
-    ap.add_argument("--steps-3d", type=int, default=3)
+    ap.add_argument("--steps-1d", type=int, default=20)
+    ap.add_argument("--no-1d", action="store_true", help="skip the 1D batch section")
     ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner section")
     ap.add_argument("--paper-workloads", action="store_true",
                     help="also run the paper's model problem and leaf-library sweep (FP64; a few minutes)")
     ap.add_argument("--purify-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=16, help="requests of the served stream (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the served stream (0: skip)")
     ap.add_argument("--serve-nmax", type=int, default=32768, help="largest n of the served sample (pool: 65536)")
+    ap.add_argument("--serving-only", action="store_true", help="only the served stream (its own JSON line)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB on the device (a plain copy "
                          "kernel of known traffic, to scale hardware byte counters)")
@@ -555,12 +660,20 @@ def main():
                                    "implemented); --gpus must be 1", "n_gpus": args.gpus}))
         return 2
     import torch
+    import synth
     from paper_1906_08148_amd import spamm
 
-    log("bench: generating inputs")
-    host = make_inputs()
-    dev = gpu_inputs(host)
-    ctx = spamm.Context(arena_bytes=16 << 30)
+    if args.serving_only:
+        print(json.dumps({"serving": serving(args.serve_requests, args.serve_nmax)}))
+        return 0
+    prec = spamm.PRECS[args.prec]
+    log("bench: generating the 3D decay matrix n=32768")
+    t0 = time.perf_counter()
+    A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).dense()
+    gen_s = time.perf_counter() - t0
+    dA = torch.from_numpy(A).cuda()
+    del A
+    ctx = spamm.Context(arena_bytes=64 << 30)
     if args.graph:
         ctx.set_option("graph", 1)
     if args.gemm_tile is not None:
@@ -572,87 +685,81 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    log("bench: FP32 steps")
-    total32, lat32, flops32, tm32, stats32 = timed_steps(ctx, dev, spamm.F32, args.steps, args.warmup)
-    value = flops32 / total32 / 1e9
-    gemm_per_launch_ms = tm32["gemm_ms"] / max(tm32["gemm_launches"], 1)
-    flops_per_launch = tm32["gemm_flops"] / max(tm32["gemm_launches"], 1)
-    achieved = flops_per_launch / (gemm_per_launch_ms * 1e-3) / 1e12
+    log(f"bench: 3D hybrid {args.prec} steps")
+    r = config3_steps(ctx, dA, prec, args.steps, args.warmup, keep_last=not args.skip_extras)
     tile = ctx.get_option("gemm_tile")
+    kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}>"
+    st = r["stats"]
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(r["flops"] / r["total"] / 1e9, 3),
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(total32 / args.steps * 1e3, 4),
+        "ms_per_step": round(r["total"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": "1D decay n=16384 leaf 64, alpha {0.2,0.5} x tau {1e-4,1e-6,1e-8} x "
-                               "{truncmul,spamm,hybrid}, A=B, built from leaf-block lists; 18 multiplies "
-                               "per step, one batch",
-                   "n": N, "leaf": LEAF, "multiplies_per_step": len(stats32), "seed": SEED},
-        "multiplies_per_s": round(len(stats32) * args.steps / total32, 2),
-        "latency_ms": {"p50": round(pct(lat32, 0.5) * 1e3, 4), "p99": round(pct(lat32, 0.99) * 1e3, 4)},
-        "kept_products_per_step": int(sum(s["n_kept"] for s in stats32)),
-        "phases_ms_per_step": {k: round(tm32[k + "_ms"] / args.steps, 4)
+        "config": {"workload": f"3D decay n={N3D} (4096 atoms on a 16^3 lattice x 8 functions), a_ij = (2u-1) "
+                               f"exp(-dist), leaf {LEAF3D}, tau {TAU3D}, A=B; one step = build from the dense "
+                               f"FP64 matrix in HBM + one Hybrid multiply ({args.prec} leaf products)",
+                   "n": N3D, "leaf": LEAF3D, "tau": TAU3D, "mode": "hybrid", "seed": SEED},
+        "multiplies_per_s": round(args.steps / r["total"], 3),
+        "latency_ms": {"p50": round(pct(r["lat"], 0.5) * 1e3, 3), "p99": round(pct(r["lat"], 0.99) * 1e3, 3)},
+        "kept_products_per_step": int(st["n_kept"]),
+        "stats": {k: st[k] for k in ("n_candidates", "c_nonnull", "err_bound", "prec_bound", "dA", "B2")},
+        "phases_ms_per_step": {k: round(r["tm"][k + "_ms"] / args.steps, 3)
                                for k in ("build", "trunc", "prune", "gemm", "pyramid")},
-        # the same multiplies with the matrices (and their norms) built once
-        "norms_precomputed": multiply_only(ctx, dev, spamm.F32, args.steps, args.warmup),
-        "roofline": {"kernel": f"k_gemm<SPAMM_F32,64,{tile}> (persistent MFMA leaf GEMM, "
-                               f"{'16x16' if tile else '32x32'} MFMA tiles)", "bound": "mfma",
-                     "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": traffic_for(tile),
-                     "flops_per_launch": flops_per_launch, "ms_per_launch": round(gemm_per_launch_ms, 5)},
+        "generate_s": round(gen_s, 1),
+        "roofline": {"kernel": f"k_gemm<{args.prec.upper()},{LEAF3D}> (persistent MFMA leaf GEMM)",
+                     "bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": PEAKS[prec],
+                     "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / PEAKS[prec], 4),
+                     "traffic": traffic_for(kname), "flops_per_launch": r["gemm_flops"],
+                     "ms_per_launch": round(r["gemm_ms"], 4)},
     }
+    C64 = None
+    if r["last"] is not None:
+        C64 = ctx.to_dense(r["last"].C)
+        r["last"].C.release()
     if not args.skip_extras:
-        log("bench: FP64 steps")
-        total64, lat64, flops64, tm64, _ = timed_steps(ctx, dev, spamm.F64, args.steps, args.warmup)
-        g64 = tm64["gemm_ms"] / max(tm64["gemm_launches"], 1)
-        f64l = tm64["gemm_flops"] / max(tm64["gemm_launches"], 1)
-        out["f64"] = {"value": round(flops64 / total64 / 1e9, 3), "unit": "GFLOP/s",
-                      "ms_per_step": round(total64 / args.steps * 1e3, 4),
-                      "multiplies_per_s": round(18 * args.steps / total64, 2),
-                      "latency_ms": {"p50": round(pct(lat64, 0.5) * 1e3, 4),
-                                     "p99": round(pct(lat64, 0.99) * 1e3, 4)},
-                      "gemm_tflops": round(f64l / (g64 * 1e-3) / 1e12, 3),
-                      "gemm_frac_of_fp64_peak": round(f64l / (g64 * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)}
-        log("bench: errors and fixed-error rates")
-        e32 = errors(ctx, dev, host, spamm.F32)
-        e64 = errors(ctx, dev, host, spamm.F64)
-        out["fixed_error"] = {
-            "sigma": "1e-5 * ||A||_F * ||B||_F",
-            "f32": fixed_error_rate(ctx, dev, spamm.F32, e32, 20),
-            "f64": fixed_error_rate(ctx, dev, spamm.F64, e64, 20),
-            # err <= bound + prec_bound: the approximation and the FP32 rounding
-            "errors_f32": [{k: e[k] for k in ("alpha", "tau", "mode", "err", "bound", "prec_bound")}
-                           for e in e32],
-        }
-        out["fixed_error"]["f32_over_f64"] = round(out["fixed_error"]["f32"]["multiplies_per_s"] /
-                                                   out["fixed_error"]["f64"]["multiplies_per_s"], 3)
-        # every FP32 error within the approximation bound plus the rounding bound
-        out["fixed_error"]["bounds_hold"] = all(e["err"] <= e["bound"] + e["prec_bound"] for e in e32)
-    if not args.skip_extras and not args.no_3d:
-        log("bench: 3D decay n=32768")
-        out["dense3d"] = dense3d(args.steps_3d)
-    if not args.skip_extras and not args.no_purify:
-        log("bench: purification n=32768")
-        out["purification"] = purification(args.purify_steps)
-    if not args.skip_extras and args.serve_requests > 0:
-        log("bench: serving")
-        out["serving"] = serving(args.serve_requests, args.serve_nmax)
-    if args.paper_workloads:
-        log("bench: the paper's model problem and leaf-library sweep")
-        out["paper_workloads"] = paper_workloads()
+        log("bench: 3D multiply with norms precomputed")
+        out["norms_precomputed"] = multiply_only_3d(ctx, dA, prec, args.steps)
+        if prec == spamm.F64:
+            out["precisions"] = config3_precisions(ctx, dA, max(2, args.steps // 2), C64)
+            log("bench: 3D symmetric square")
+            out["symmetric"] = symmetric_3d(ctx, dA, C64)
+        del C64
+        torch.cuda.empty_cache()
+        log("bench: 3D fixed error")
+        out["fixed_error"] = fixed_error_3d(ctx, dA)
+        if not args.no_autotune:
+            out["autotune"] = autotune_3d(ctx, dA)
+        ctx.close()
+        del dA
+        torch.cuda.empty_cache()
+        ctx = spamm.Context(arena_bytes=16 << 30)
+        if not args.no_1d:
+            log("bench: 1D batch")
+            out["batch_1d"] = batch_1d(ctx, args.steps_1d, 5)
+        ctx.close()
+        ctx = None
+        if not args.no_purify:
+            log("bench: purification n=32768")
+            out["purification"] = purification(args.purify_steps)
+        if args.serve_requests > 0:
+            log("bench: serving")
+            out["serving"] = serving(args.serve_requests, args.serve_nmax)
+        if args.paper_workloads:
+            log("bench: the paper's model problem and leaf-library sweep")
+            out["paper_workloads"] = paper_workloads()
+    if ctx is not None:
+        ctx.close()
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
-    ctx.close()
+        out["cpu_baseline"] = cpu_baseline_3d(args.cpu_sample_n)
     print(json.dumps(out))
     return 0
 

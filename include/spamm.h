@@ -49,7 +49,8 @@ extern "C" {
 typedef enum spamm_status {
   SPAMM_OK = 0,
   SPAMM_EINVAL = 1,       /* bad argument: tau < 0 / NaN / Inf, n < 1, ld < n,
-                             leaf not in {16,32,64,128}, NULL pointer, ...   */
+                             leaf not in {16,32,64,128,256}, NULL pointer,
+                             ...                                              */
   SPAMM_ESHAPE = 2,       /* A and B (or D) differ in n or leaf size           */
   SPAMM_ENOMEM = 3,       /* the arena cannot hold the result                 */
   SPAMM_ENONFINITE = 4,   /* NaN or Inf in an input matrix                    */
@@ -64,14 +65,23 @@ typedef enum spamm_mode {
   SPAMM_TRUNCMUL = 0, /* truncate A and B, form every non-null leaf product   */
   SPAMM_SPAMM = 1,    /* form leaf products with ||A_ik||_F ||B_kj||_F >= tau */
   SPAMM_HYBRID = 2,   /* SPAMM on A and B truncated with the same tau         */
-  SPAMM_SPAMM_SYM = 3 /* SPAMM for the square of a symmetric A (B = A, the
-                         same handle, no epilogue).  The kept set is then
-                         symmetric, so only the products of C leaves (I, J)
-                         with I <= J are formed and each leaf below the
-                         diagonal is written as the transpose of its mirror
-                         (n_kept and flops count the formed products; the
-                         kept list holds the upper ones).  The caller
-                         asserts that A is symmetric.                      */
+  SPAMM_SPAMM_SYM = 3, /* SPAMM for the square of a symmetric A (B = A, the
+                          same handle; an epilogue matrix D must be symmetric
+                          too).  C = A A is symmetric, so only the C leaves
+                          (I, J) with I <= J are decided by the norm test and
+                          formed; each leaf below the diagonal takes its
+                          mirror's decision, skipped bound and norm and is
+                          written as the transpose of its mirror (n_kept and
+                          flops count the formed products; the kept list
+                          holds them).  If A's null map (or D's) is not
+                          symmetric, every C leaf is formed as in SPAMM.
+                          The caller asserts that A (and D) are symmetric. */
+  SPAMM_HYBRID_SYM = 4 /* the same for Hybrid: A is truncated as in HYBRID;
+                          if the truncated null map is symmetric, the upper
+                          C leaves are formed and mirrored as above, else
+                          (the truncation boundary split a mirror pair) the
+                          full Hybrid product is formed.  The check runs on
+                          the device; no extra synchronisation.            */
 } spamm_mode;
 
 /* Arithmetic of the leaf products.  The norms, the tau tests and all error

@@ -33,16 +33,19 @@ def scale_unit(A: np.ndarray):
     return X0, lo, hi
 
 
-def sp2_chain(A: np.ndarray, bs: int, n_occ: float, tau: float, steps: int, mode: int = O.HYBRID):
+def sp2_chain(A: np.ndarray, bs: int, n_occ: float, tau: float, steps: int, mode: int = O.HYBRID,
+              sym: bool = False):
     """Run `steps` SP2 steps on A scaled into [0, 1].  Each record holds the
     trace the decision used, the branch (0: X^2, 1: 2X - X^2), the number of
-    leaf products formed and the new iterate (dense FP64)."""
+    leaf products formed and the new iterate (dense FP64).  With `sym` every
+    square is the symmetric square (``multiply_symmetric``): the iterates
+    stay exactly symmetric."""
     X, lo, hi = scale_unit(A)
     out = []
     for _ in range(steps):
         T = O.build(X, bs)
         tr = float(np.trace(X))
-        r = O.multiply(T, T, tau, mode)
+        r = O.multiply_symmetric(T, tau, mode) if sym else O.multiply(T, T, tau, mode)
         X2 = r.C.to_dense()
         if tr > n_occ:
             Xn, branch = X2, 0

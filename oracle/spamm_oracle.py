@@ -282,6 +282,58 @@ def truncate(t: Tree, tau: float) -> Truncation:
     return Truncation(with_leaves_dropped(t, drop_mask), dropped, b0, (b0, b1), tie)
 
 
+def truncate_pairs(t: Tree, tau: float) -> Truncation:
+    """Leaf-block truncation of a symmetric matrix in mirror pairs, with the
+    same global budget tau (a reading for the symmetric square; the paper's
+    truncation is Sec. 3's, it does not exploit symmetry).
+
+    Each leaf (I, K) with I < K forms a pair with (K, I) of weight
+    w = s_IK + s_KI (FP64 sum), each diagonal leaf is a pair of its own with
+    w = s_II; pairs with a non-null leaf are ordered by (w, Morton key of
+    (I, K)) and the longest prefix whose exact summed squared norms stay
+    <= tau^2 is dropped, both leaves of a pair together.  The result is
+    symmetric whenever the input's null map is, and ||A - A~||_F <= tau."""
+    if not (tau >= 0.0) or math.isinf(tau):
+        raise ValueError("tau must be finite and >= 0")
+    pres, sq = t.leaf_present, t.leaf_sq
+    I, K = np.nonzero(np.triu(pres | pres.T))
+    w = np.where(I == K, sq[I, K], sq[I, K] + sq[K, I])
+    keys = morton_key(I, K)
+    order = np.lexsort((keys, w))
+    tnum, tden = float(tau).as_integer_ratio()
+    limit_lhs_scale = tden * tden
+    limit_rhs = tnum * tnum * (1 << 1074)
+
+    def exact(i, k):
+        e = _exact_scaled(sq[i, k])
+        return e if i == k else e + _exact_scaled(sq[k, i])
+
+    acc = 0
+    r = 0
+    for idx in order:
+        nxt = acc + exact(I[idx], K[idx])
+        if nxt * limit_lhs_scale <= limit_rhs:
+            acc = nxt
+            r += 1
+        else:
+            break
+    nxt_sum = acc + (exact(I[order[r]], K[order[r]]) if r < len(order) else 0)
+    drop_mask = np.zeros_like(t.index, dtype=bool)
+    d = order[:r]
+    drop_mask[I[d], K[d]] = True
+    drop_mask[K[d], I[d]] = True
+    drop_mask &= pres
+    tau2 = float(tau) * float(tau)
+    b0 = float(Fraction(acc, 1 << 1074))
+    b1 = float(Fraction(nxt_sum, 1 << 1074)) if r < len(order) else math.inf
+    band = 1e-12 * tau2
+    tie = (b0 > 0.0 and abs(b0 - tau2) <= band) or (r < len(order) and abs(b1 - tau2) <= band)
+    if 0 < r < len(order) and w[order[r - 1]] == w[order[r]]:
+        tie = True
+    dI, dJ = np.nonzero(drop_mask)
+    return Truncation(with_leaves_dropped(t, drop_mask), np.stack([dI, dJ], axis=1), b0, (b0, b1), tie)
+
+
 def truncate_elementwise(dense: np.ndarray, tau: float) -> np.ndarray:
     """Eq. (truncated_matrices): zero every entry with |a_ij| < tau."""
     out = np.array(dense, dtype=np.float64, copy=True)
@@ -489,6 +541,72 @@ def multiply(A: Tree, B: Tree, tau: float, mode: int, c_blocks=None) -> Result:
         err_bound=bound, trunc_tie=(tieA or tieB),
     )
     return Result(C, kept, Au, Bu, bnd, stats)
+
+
+def multiply_symmetric(A: Tree, tau: float, mode: int, c_blocks=None) -> Result:
+    """The square of a symmetric A formed on the upper triangle of C.
+
+    A reading the paper leaves open (it does not exploit symmetry, Sec. 5.4):
+    for A = A^T the product A A is symmetric, and the leaf triple (I, K, J)
+    pairs with (J, K, I), whose norm product is the same up to the rounding
+    of the two leaf norms.  Hybrid truncates A in mirror pairs
+    (``truncate_pairs``), so the truncated operand stays symmetric.  The
+    norm test decides the C leaves with I <= J; each leaf below the
+    diagonal takes its mirror's decision and is the transpose of its
+    mirror, with the mirror's skipped bound.  When the operand's null map is
+    not symmetric all the same (A itself was not), every C leaf is formed
+    by its own test instead.  The kept list holds the formed products: the
+    upper ones, or all of them in that fallback."""
+    if mode not in (SPAMM, HYBRID):
+        raise ValueError("symmetric square: SpAMM or Hybrid")
+    want = None
+    if c_blocks is not None:  # the requested leaves and their mirrors
+        want = sorted({(int(a), int(b)) for a, b in c_blocks} | {(int(b), int(a)) for a, b in c_blocks})
+    if mode == HYBRID:
+        tr = truncate_pairs(A, tau)
+        full = multiply(tr.tree, tr.tree, tau, SPAMM, c_blocks=want)
+        dA = math.sqrt(tr.dropped_sq)
+        full.stats.update(mode=HYBRID, dA=dA, dB=dA, normA=A.fro(), normB=A.fro(), trunc_tie=tr.tie,
+                          err_bound=dA * A.fro() + tr.tree.fro() * dA + full.stats["B2"])
+    else:
+        full = multiply(A, A, tau, SPAMM, c_blocks=want)
+    Au = full.A_used
+    pres = Au.leaf_present
+    if not np.array_equal(pres, pres.T):
+        full.stats["sym_fallback"] = True
+        return full
+    G = A.G
+    kept = full.kept[full.kept[:, 0] <= full.kept[:, 2]]
+    bnd = full.skipped_bound.copy()
+    lower = np.tril_indices(G, -1)
+    bnd[lower] = full.skipped_bound.T[lower]
+    c_present = full.C.leaf_present.copy()
+    c_present[lower] = full.C.leaf_present.T[lower]
+    c_index = np.full((G, G), -1, dtype=np.int64)
+    blocks = []
+    for I, J in zip(*np.nonzero(c_present)):
+        a, b = (I, J) if I <= J else (J, I)
+        if full.C.index[a, b] < 0:
+            continue  # a leaf not computed (outside c_blocks)
+        src = full.C.leaf(a, b) if I <= J else full.C.leaf(a, b).T
+        c_index[I, J] = len(blocks)
+        blocks.append(np.array(src))
+    bs = A.bs
+    blocks = np.asarray(blocks, dtype=np.float64).reshape(-1, bs, bs)
+    c_sq = np.zeros((G, G), dtype=np.float64)
+    for I, J in zip(*np.nonzero(c_index >= 0)):
+        b = blocks[c_index[I, J]]
+        c_sq[I, J] = np.sum(b * b)
+    sq, pr = pyramid(c_sq, c_present)
+    C = Tree(A.n, bs, G, A.L, c_index, blocks, sq, pr)
+    stats = dict(full.stats)
+    B2 = math.sqrt(float(np.sum(bnd * bnd)))
+    dA, normB, normAu = stats["dA"], stats["normB"], Au.fro()
+    stats.update(n_kept=int(len(kept)), flops=2.0 * bs ** 3 * len(kept), c_nonnull=int(c_present.sum()),
+                 B1=float(np.sum(bnd)), B2=B2, sym_fallback=False,
+                 err_bound=B2 if mode == SPAMM else dA * normB + normAu * dA + B2)
+    # the rounding bound of a mirrored leaf is its mirror's (same products)
+    return Result(C, kept, Au, Au, bnd, stats)
 
 
 # Unit roundoffs: FP64, FP32 and BF16 (8 significand bits, round to nearest).

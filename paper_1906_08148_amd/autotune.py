@@ -2,11 +2,19 @@
 
 The leaf size trades pruning resolution against per-product efficiency: a
 smaller leaf skips more negligible work (finer norm tests) but each product
-is a smaller matrix multiply.  The GEMM tile variant (32 x 32 or 16 x 16
-MFMA tiles for FP32 / BF16) changes the register budget and the issue
-pattern of the leaf GEMM.  The tuner times the full multiply (prune + GEMM +
-epilogue) for every candidate on the device and keeps the fastest; choices
-are cached per workload signature and can be saved as JSON.
+is a smaller matrix multiply.  A different leaf also changes which products
+are kept, and so the error of the result at the same tau (the paper picks a
+different tau per block size for the same accuracy, Sec. 5.3).  The GEMM
+tile variant (32 x 32 or 16 x 16 MFMA tiles for FP32 / BF16) changes the
+register budget and the issue pattern of the leaf GEMM.
+
+For every candidate the tuner times the full multiply (prune + GEMM +
+epilogue) on the device and takes its error: by default the library's
+guaranteed bound on ||A B - C||_F (the approximation bound plus the
+rounding bound of the compute precision), or a measured error when the
+caller gives a function for it.  Candidates whose error exceeds the
+request's budget are rejected; the fastest of the rest wins.  Choices are
+cached per workload signature and can be saved as JSON.
 """
 import json
 import math
@@ -39,50 +47,74 @@ def _time_multiply(ctx, M, tau, mode, prec, reps):
     return sorted(ts)[len(ts) // 2], stats
 
 
-def choose(candidates, measure):
-    """Run `measure(leaf, tile) -> seconds` over the candidates and return
-    (best (leaf, tile), table).  Pure selection logic (testable without a
-    device)."""
+def choose(candidates, measure, budget=None):
+    """Run `measure(leaf, tile) -> (seconds, error)` over the candidates and
+    return (best (leaf, tile) or None, table).  A candidate whose error is
+    above `budget` (None: no budget) is rejected whatever its time; the
+    fastest admissible one wins, ties going to the smaller leaf, then tile.
+    None when no candidate meets the budget.  Pure selection logic
+    (testable without a device)."""
     table = []
     for leaf, tile in candidates:
-        t = measure(leaf, tile)
-        table.append({"leaf": leaf, "tile": tile, "seconds": t})
-    best = min(table, key=lambda r: (r["seconds"], r["leaf"], r["tile"]))
+        t, err = measure(leaf, tile)
+        ok = budget is None or (err is not None and err <= budget)
+        table.append({"leaf": leaf, "tile": tile, "seconds": t, "error": err, "admissible": ok})
+    admissible = [r for r in table if r["admissible"]]
+    if not admissible:
+        return None, table
+    best = min(admissible, key=lambda r: (r["seconds"], r["leaf"], r["tile"]))
     return (best["leaf"], best["tile"]), table
 
 
 class Tuner:
-    def __init__(self, ctx: S.Context, leaves=(32, 64, 128), tiles=(0, 1), reps=3):
+    def __init__(self, ctx: S.Context, leaves=(32, 64, 128, 256), tiles=(0, 1), reps=3):
         self.ctx, self.leaves, self.tiles, self.reps = ctx, leaves, tiles, reps
         self.cache = {}
 
-    def tune(self, make_matrix, sig, tau, mode, prec):
+    def tune(self, make_matrix, sig, tau, mode, prec, budget=None, error_fn=None):
         """`make_matrix(leaf)` builds the workload's matrix in this context.
-        Returns {"leaf", "tile", "table"}; sets the context's tile option."""
-        if sig in self.cache:
-            best = self.cache[sig]
-            self.ctx.set_option("gemm_tile", best["tile"])
+        `budget` bounds ||A B - C||_F; each candidate's error is
+        error_fn(ctx, product) when given, else the product's err_bound +
+        prec_bound.  Returns {"leaf", "tile", "table"} (leaf and tile None
+        when no candidate meets the budget); sets the context's tile option
+        to the winner's."""
+        key = (sig, budget)
+        if key in self.cache:
+            best = self.cache[key]
+            if best["tile"] is not None:
+                self.ctx.set_option("gemm_tile", best["tile"])
             return best
         tiles = self.tiles if prec != S.F64 else (0,)
         built = {}
         extra = {}
 
         def measure(leaf, tile):
-            if leaf not in built:
+            if leaf not in built:  # one leaf size resident at a time (candidates go leaf by leaf)
+                for M in built.values():
+                    M.release()
+                built.clear()
                 built[leaf] = make_matrix(leaf)
             self.ctx.set_option("gemm_tile", tile)
             t, st = _time_multiply(self.ctx, built[leaf], tau, mode, prec, self.reps)
+            if error_fn is not None:
+                p = self.ctx.multiply(built[leaf], built[leaf], tau, mode=mode, prec=prec)
+                err = float(error_fn(self.ctx, p))
+                p.C.release()
+            else:
+                err = float(st["err_bound"] + st["prec_bound"])
             extra[(leaf, tile)] = {"n_kept": int(st["n_kept"]), "flops": float(st["flops"])}
-            return t
+            return t, err
 
-        (leaf, tile), table = choose([(l, t) for l in self.leaves for t in tiles], measure)
+        pick, table = choose([(l, t) for l in self.leaves for t in tiles], measure, budget)
         for r in table:
             r.update(extra[(r["leaf"], r["tile"])])
         for M in built.values():
             M.release()
-        self.ctx.set_option("gemm_tile", tile)
-        best = {"leaf": leaf, "tile": tile, "table": table}
-        self.cache[sig] = best
+        leaf, tile = pick if pick is not None else (None, None)
+        if tile is not None:
+            self.ctx.set_option("gemm_tile", tile)
+        best = {"leaf": leaf, "tile": tile, "table": table, "budget": budget}
+        self.cache[key] = best
         return best
 
     def save(self, path):

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -103,7 +104,7 @@ namespace {
 
 constexpr int kMaxL = 11;  // G <= 2048
 
-bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128; }
+bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || bs == 256; }
 
 void grid_of(int64_t n, int bs, int& G, int& L) {
   const int64_t g = (n + bs - 1) / bs;
@@ -421,13 +422,19 @@ struct TruncPlan {
   size_t sb = 0;
 };
 
-spamm_status trunc_plan(Ctx* c, const std::vector<std::pair<const spamm_mat*, double>>& in,
-                        std::vector<std::unique_ptr<spamm_mat>>& out, RegionP& result, TruncPlan& tp) {
+struct TruncIn {
+  const spamm_mat* m;
+  double tau;
+  bool pairs;  // mirror-pair truncation (the symmetric square)
+};
+
+spamm_status trunc_plan(Ctx* c, const std::vector<TruncIn>& in, std::vector<std::unique_ptr<spamm_mat>>& out,
+                        RegionP& result, TruncPlan& tp) {
   out.clear();
   if (in.empty()) return SPAMM_OK;
   ALLOC(result, in.size() * 16, "truncation results");
   for (size_t t = 0; t < in.size(); ++t) {
-    const spamm_mat* a = in[t].first;
+    const spamm_mat* a = in[t].m;
     std::unique_ptr<spamm_mat> m;
     spamm_status st = new_matrix(c, a->n, a->bs, m);
     if (st != SPAMM_OK) return st;
@@ -438,7 +445,8 @@ spamm_status trunc_plan(Ctx* c, const std::vector<std::pair<const spamm_mat*, do
     j.out_slot = P<int32_t>(m->slot);
     j.out_norm = P<double>(m->norms) + level_offset(m->L);
     j.result = P<double>(result) + 2 * t;
-    j.tau2 = in[t].second * in[t].second;
+    j.tau2 = in[t].tau * in[t].tau;
+    j.pairs = in[t].pairs ? 1 : 0;
     j.base = tp.total;
     j.G = a->G;
     int kb = 1;
@@ -775,7 +783,7 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   std::vector<std::unique_ptr<spamm_mat>> ms;
   RegionP res;
   TruncPlan tp;
-  spamm_status st = trunc_plan(c, {{in, tau}}, ms, res, tp);
+  spamm_status st = trunc_plan(c, {{in, tau, false}}, ms, res, tp);
   if (st != SPAMM_OK) return st;
   TableSet tabs;
   const size_t oj = tabs.add(tp.jobs), op = tabs.add(tp.pyr);
@@ -960,11 +968,13 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     if (!q.A || !q.B || q.A->ctx != c || q.B->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
     if (q.A->n != q.B->n || q.A->bs != q.B->bs) return fail(c, SPAMM_ESHAPE, "A and B differ in n or leaf size");
     if (!tau_ok(q.tau)) return fail(c, SPAMM_EINVAL, "tau must be finite and >= 0");
-    if (q.mode < 0 || q.mode > 3) return fail(c, SPAMM_EINVAL, "bad mode");
-    if (q.mode == SPAMM_SPAMM_SYM && (q.A != q.B || q.ep))
-      return fail(c, SPAMM_EINVAL, "the symmetric square needs B = A (the same handle) and no epilogue");
+    if (q.mode < 0 || q.mode > 4) return fail(c, SPAMM_EINVAL, "bad mode");
+    if ((q.mode == SPAMM_SPAMM_SYM || q.mode == SPAMM_HYBRID_SYM) && q.A != q.B)
+      return fail(c, SPAMM_EINVAL, "the symmetric square needs B = A (the same handle)");
     if (q.prec < 0 || q.prec > 3) return fail(c, SPAMM_EINVAL, "bad precision");
     if (!gemm_supported(q.prec, q.A->bs)) return fail(c, SPAMM_EUNSUPPORTED, "precision/leaf size not built");
+    if (q.A->G > (1 << (kUnitTileShift / 2)))
+      return fail(c, SPAMM_EUNSUPPORTED, "more than 16384 leaf rows");
     if (q.ep) {
       if (q.ep->D && (q.ep->D->ctx != c)) return fail(c, SPAMM_EINVAL, "bad epilogue matrix");
       if (q.ep->D && (q.ep->D->n != q.A->n || q.ep->D->bs != q.A->bs))
@@ -975,21 +985,23 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   }
 
   // ---- truncations (one per distinct (matrix, tau) in the batch, all at once)
-  std::map<std::pair<const spamm_mat*, uint64_t>, int> tindex;
-  std::vector<std::pair<const spamm_mat*, double>> tjobs;
-  auto tkey = [](const spamm_mat* m, double tau) {
+  // one truncation per distinct (matrix, tau, pair form)
+  std::map<std::tuple<const spamm_mat*, uint64_t, bool>, int> tindex;
+  std::vector<TruncIn> tjobs;
+  auto tkey = [](const spamm_mat* m, double tau, bool pairs) {
     uint64_t bits;
     std::memcpy(&bits, &tau, 8);
-    return std::make_pair(m, bits);
+    return std::make_tuple(m, bits, pairs);
   };
   for (int r = 0; r < count; ++r) {
     const spamm_request& q = reqs[r];
-    if (q.mode == SPAMM_SPAMM || q.mode == SPAMM_SPAMM_SYM) continue;
+    if (q.mode == SPAMM_SPAMM || q.mode == SPAMM_SPAMM_SYM) continue;  // no truncation
+    const bool pairs = q.mode == SPAMM_HYBRID_SYM;
     for (const spamm_mat* m : {q.A, q.B}) {
-      auto k = tkey(m, q.tau);
+      auto k = tkey(m, q.tau, pairs);
       if (!tindex.count(k)) {
         tindex[k] = int(tjobs.size());
-        tjobs.push_back({m, q.tau});
+        tjobs.push_back({m, q.tau, pairs});
       }
     }
   }
@@ -1011,7 +1023,8 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       Au[r] = const_cast<spamm_mat*>(q.A);
       Bu[r] = const_cast<spamm_mat*>(q.B);
     } else {
-      const int ia = tindex[tkey(q.A, q.tau)], ib = tindex[tkey(q.B, q.tau)];
+      const bool pairs = q.mode == SPAMM_HYBRID_SYM;
+      const int ia = tindex[tkey(q.A, q.tau, pairs)], ib = tindex[tkey(q.B, q.tau, pairs)];
       Au[r] = tmats[ia].get();
       Bu[r] = tmats[ib].get();
       trA[r] = P<double>(tres) + 2 * ia;
@@ -1063,7 +1076,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     d.slotD = (q.ep && q.ep->D) ? P<int32_t>(q.ep->D->slot) : nullptr;
     d.tau = q.tau;
     d.use_norms = q.mode != SPAMM_TRUNCMUL;
-    d.sym = q.mode == SPAMM_SPAMM_SYM;
+    d.sym = q.mode == SPAMM_SPAMM_SYM || q.mode == SPAMM_HYBRID_SYM;
     any_sym = any_sym || d.sym;
     d.G = q.A->G;
     d.L = q.A->L;
@@ -1105,6 +1118,13 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   ALLOC(pb_all, total_c * 8, "rounding bounds");
   const size_t ssb = scan_scratch_bytes(total_c);
   ALLOC(scan_scr, ssb, "scan scratch");
+  // symmetric squares: one flag per request, set on the device when the
+  // operand's (or D's) null map is not symmetric
+  RegionP symflags;
+  if (any_sym) {
+    ALLOC(symflags, int64_t(count) * 4, "symmetry flags");
+    for (int r = 0; r < count; ++r) rd[r].asym = P<int32_t>(symflags) + r;
+  }
   TableSet pre;
   const size_t o_tj = pre.add(tplan.jobs), o_tp = pre.add(tplan.pyr), o_pj = pre.add(pplan.jobs),
                o_rd = pre.add(rd);
@@ -1116,6 +1136,12 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   if (st != SPAMM_OK) return st;
   {
   TimedScope ts(c, kTPrune);
+  if (any_sym) {  // after the truncations, before the counting pass reads the flags
+    SPAMM_HIP(c, launch_zero_i32(c->stream, P<int32_t>(symflags), count));
+    for (int r = 0; r < count; ++r)
+      if (rd[r].sym)
+        SPAMM_HIP(c, launch_sym_check(c->stream, rd[r].G, rd[r].A.slot, rd[r].slotD, P<int32_t>(symflags) + r));
+  }
   const ReqDev* rd0 = pre.at<ReqDev>(o_rd);
   SPAMM_HIP(c, launch_prune_count(c->stream, rd0, count, total_c, cnt_bits, P<int64_t>(packed), P<double>(bnd_all),
                                   P<int32_t>(cand_all), P<double>(pb_all)));
@@ -1161,7 +1187,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     const int64_t start = wu_total;
     for (int r : gk.second) {
       rd[r].wu_base = wu_total;
-      wu_total += ht[r].c_nonnull;
+      wu_total += ht[r].c_nonnull * gemm_unit_tiles(gk.first.second);
     }
     launches.push_back({gk.first, {start, wu_total - start}});
   }

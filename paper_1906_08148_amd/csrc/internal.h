@@ -262,6 +262,8 @@ struct ReqDev {
   int32_t sched_k, sched_n;
   int32_t nslices;        // slices per request in the placement (8 per-XCD, or 1)
   int32_t sym;            // symmetric square: C leaves below the diagonal are mirrored
+  const int32_t* asym;    // symmetric square: nonzero when the operand's (or D's) null
+                          // map is not symmetric (every C leaf is then formed)
 };
 
 // One truncation inside a batch (leaf-block truncation with budget tau^2).
@@ -270,11 +272,12 @@ struct TruncJob {
   const double* leafnorm;  // input leaf norms (Morton)
   int32_t* out_slot;
   double* out_norm;        // leaf level of the output pyramid
-  double* result;          // [0] dropped squared norm, [1] dropped count
+  double* result;          // [0] dropped squared norm, [1] dropped count (leaves; pairs in the pair form)
   double tau2;
   int64_t base;            // first element in the batch's concatenated arrays
   int32_t G;
   int32_t key_bits_lo;     // bits of the Morton index in the sort key
+  int32_t pairs;           // truncate in mirror pairs (I, K) + (K, I), keyed by the upper leaf
 };
 
 // Row/column views of one matrix (see ensure_prep).
@@ -301,6 +304,12 @@ struct WorkUnit {
   int32_t cflags;  // Morton index of the C leaf | kUnitEp when the epilogue applies alpha/beta/D
 };
 constexpr int32_t kUnitEp = int32_t(1) << 30;
+// Bits 28-29 of cflags: the unit's tile of a C leaf split into tiles (256
+// leaves: 2 x 2 tiles of 128, tile = 2 * tile row + tile column); the
+// Morton index sits below bit 28, so G <= 16384.
+constexpr int kUnitTileShift = 28;
+constexpr int32_t kUnitMorton = (int32_t(1) << kUnitTileShift) - 1;
+__host__ __device__ inline int unit_tile(int32_t cflags) { return (cflags >> kUnitTileShift) & 3; }
 
 // Arguments of one GEMM launch: the work units of one (precision, leaf size)
 // group in placement order, split into contiguous ranges of equal cost, one
@@ -422,6 +431,7 @@ hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, i
 hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmArgs& a);
 int gemm_max_groups(int prec, int bs, int variant, int n_cu);  // resident workgroups of the kernel
 bool gemm_supported(int prec, int bs);
+int gemm_unit_tiles(int bs);  // work units per C leaf (4 for 256 leaves, else 1)
 // leaf norms and trace parts of the units into each request's C pyramid
 hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu,
                                const double* wn, const double* wt);
@@ -452,6 +462,9 @@ hipError_t launch_sum_f64(hipStream_t s, const double* v, int64_t n, double* par
 // Symmetric squares: every C leaf below the diagonal of a request with sym
 // set becomes the transpose of its mirror, with the mirror's norm.
 hipError_t launch_mirror(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c);
+// flag |= 1 if the null map of slot (or of slotD, nullable) is not symmetric;
+// the flag must be zero before
+hipError_t launch_sym_check(hipStream_t s, int G, const int32_t* slot, const int32_t* slotD, int32_t* flag);
 hipError_t launch_stats_partial(hipStream_t s, const ReqDev* reqs, int nreq, int64_t nchunks,
                                 const double* bnd_all, const int32_t* cand_all, const double* pb_all,
                                 StatPartial* partial);

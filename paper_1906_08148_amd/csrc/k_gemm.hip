@@ -36,6 +36,11 @@
 // The epilogue writes the C leaf (FP64 for FP64 products, else FP32), the
 // leaf's FP64 squared Frobenius norm and, on diagonal leaves, its diagonal
 // sum, per unit; optionally C = alpha * AB + beta * D.
+//
+// Leaves of 256 (LS) are stored row-major like every other leaf size; their
+// C leaf is split into 2 x 2 tiles of 128 (BS), one work unit each, so the
+// 128-tile kernel runs them with a row stride of 256 and k running over all
+// 256 columns of A (and rows of B) of a product.
 #include <type_traits>
 
 #include "internal.h"
@@ -51,7 +56,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 
-template <int P, int BS, int V>
+template <int P, int BS, int V, int LS = BS>
 struct GemmCfg {
   static constexpr bool kBf = P == SPAMM_BF16 || P == SPAMM_BF16X3;
   static constexpr int NH = P == SPAMM_BF16X3 ? 2 : 1;  // hi / lo halves staged
@@ -71,7 +76,8 @@ struct GemmCfg {
                             : P == SPAMM_F32  ? (BS >= 64 ? 32 : BS)
                             : P == SPAMM_BF16 ? (BS >= 128 ? 64 : BS)
                                               : (BS >= 128 ? 32 : BS);
-  static constexpr int NPANEL = BS / KP;
+  static constexpr int NSUB = LS / BS;    // tiles per side of a C leaf
+  static constexpr int NPANEL = LS / KP;  // k-panels of one product
   static constexpr int NT = NW * 64;
   static constexpr int VN = 16 / ES;  // elements per 16-byte vector
   static constexpr int SA = KP + VN;  // padded row of an A (and BF16 B) panel in LDS
@@ -82,13 +88,13 @@ struct GemmCfg {
   static constexpr bool PARTIAL = (NH * PV) % NT != 0;
   static constexpr int A_LDS = NH * BS * SA * ES;               // bytes
   static constexpr int B_LDS = kBf ? NH * BS * SA * ES : KP * BS * ES;
-  static constexpr int64_t LEAF_IN = int64_t(BS) * BS * (kBf ? 2 * ES : ES);  // bytes of a stored leaf
-  static constexpr int64_t LEAF_OUT = int64_t(BS) * BS * sizeof(Out);
+  static constexpr int64_t LEAF_IN = int64_t(LS) * LS * (kBf ? 2 * ES : ES);  // bytes of a stored leaf
+  static constexpr int64_t LEAF_OUT = int64_t(LS) * LS * sizeof(Out);
   static constexpr int VNO = 16 / int(sizeof(Out));
   static constexpr int SC = BS + VNO;  // padded row of the staged C leaf
   // double-buffered panels: a panel is stored into the buffer the panel
   // before last was read from, so one barrier per panel suffices
-  static constexpr bool DBUF = (P == SPAMM_F32 && BS == 64);
+  static constexpr bool DBUF = (P == SPAMM_F32 && BS == 64 && LS == 64);
   static constexpr int PANEL_LDS = A_LDS + B_LDS;
   static constexpr int LDS = (DBUF ? 2 : 1) * PANEL_LDS;
   static constexpr bool STAGED = int64_t(BS) * SC * sizeof(Out) <= LDS;
@@ -100,6 +106,7 @@ struct GemmCfg {
   // resident workgroups per CU asked of the register allocator
   static constexpr int MINB = (BS == 64 && P == SPAMM_F32) ? 4 : (BS == 64 && P != SPAMM_F64) ? 3 : 1;
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
+  static_assert(LS % BS == 0 && LS % KP == 0 && NSUB <= 2, "tiles of a leaf");
 };
 
 template <int P, int MT>
@@ -210,11 +217,13 @@ struct Panel {
   u32x4 b[GemmCfg<P, BS, V>::B_VECS];
 };
 
-// k-panel `sub` of product (leaf ia of A, leaf ib of B) into registers.
-template <int P, int BS, int V>
+// k-panel `sub` of product (leaf ia of A, leaf ib of B) into registers; the
+// unit's tile of C starts at row r0, column c0 of the leaf (0 unless the
+// leaf holds several tiles).
+template <int P, int BS, int V, int LS>
 __device__ __forceinline__ void load_panel(Panel<P, BS, V>& r, const char* __restrict__ base, int32_t ia, int32_t ib,
-                                           int sub, int tid) {
-  using Cf = GemmCfg<P, BS, V>;
+                                           int sub, int r0, int c0, int tid) {
+  using Cf = GemmCfg<P, BS, V, LS>;
   // wave-uniform leaf base plus a 32-bit lane offset (global loads with a
   // scalar base address)
   const auto A = as_global(base + int64_t(ia) * Cf::LEAF_IN);
@@ -225,7 +234,7 @@ __device__ __forceinline__ void load_panel(Panel<P, BS, V>& r, const char* __res
     if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
     const int h = v / Cf::PV, vv = v % Cf::PV;
     const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
-    const uint32_t e = uint32_t(h * BS * BS + row * BS + sub * Cf::KP + cv * Cf::VN);  // uniform base + lane offset
+    const uint32_t e = uint32_t(h * LS * LS + (r0 + row) * LS + sub * Cf::KP + cv * Cf::VN);  // uniform base + lane offset
     r.a[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(A + uint32_t(e * Cf::ES));
   }
 #pragma unroll
@@ -236,10 +245,10 @@ __device__ __forceinline__ void load_panel(Panel<P, BS, V>& r, const char* __res
     if constexpr (Cf::kBf) {  // transposed copy: row = B column, k contiguous
       const int h = v / Cf::PV, vv = v % Cf::PV;
       const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
-      e = uint32_t(h * BS * BS + row * BS + sub * Cf::KP + cv * Cf::VN);
+      e = uint32_t(h * LS * LS + (c0 + row) * LS + sub * Cf::KP + cv * Cf::VN);
     } else {
       const int kr = v / (BS / Cf::VN), cv = v % (BS / Cf::VN);
-      e = uint32_t((sub * Cf::KP + kr) * BS + cv * Cf::VN);
+      e = uint32_t((sub * Cf::KP + kr) * LS + c0 + cv * Cf::VN);
     }
     r.b[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(B + uint32_t(e * Cf::ES));
   }
@@ -372,15 +381,18 @@ __device__ __forceinline__ void compute_panel(AccTiles<P, BS, V>& acc, const cha
 
 // ---------------------------------------------------------------- epilogue
 
-template <int P, int BS, int V>
+template <int P, int BS, int V, int LS>
 __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const UnitS& U, AccTiles<P, BS, V>& acc,
                                          char* smem,
                                          double* red, int tid, int lane, int wave, int row0, int col0, int li,
                                          int g) {
-  using Cf = GemmCfg<P, BS, V>;
+  using Cf = GemmCfg<P, BS, V, LS>;
   using Out = typename Cf::Out;
-  const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(U.cidx) * Cf::LEAF_OUT));
-  const uint32_t cm = uint32_t(U.cf & (kUnitEp - 1));
+  // the unit's tile of the C leaf (the whole leaf unless LS > BS)
+  const int tile = unit_tile(U.cf), tr0 = (tile / Cf::NSUB) * BS, tc0 = (tile % Cf::NSUB) * BS;
+  const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(U.cidx) * Cf::LEAF_OUT) +
+                            tr0 * LS + tc0);
+  const uint32_t cm = uint32_t(U.cf & kUnitMorton);
   const bool has_ep = (U.cf & kUnitEp) != 0;
   Out alpha = Out(1), beta = Out(0);
   const Out* Dl = nullptr;
@@ -390,7 +402,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
     beta = Out(R->beta);
     if (R->Dslot != nullptr) {
       const int32_t ds = R->Dslot[cm];
-      if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * BS * BS;
+      if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * LS * LS + tr0 * LS + tc0;
     }
   }
   uint32_t ci, cj;
@@ -409,11 +421,11 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
         Out val = Out(acc[a][b][v]);
         if (has_ep) {
           const Out prod = alpha * val;
-          const Out dv = Dl ? beta * as_global(Dl)[row * BS + col] : Out(0);
+          const Out dv = Dl ? beta * as_global(Dl)[row * LS + col] : Out(0);
           val = prod + dv;
         }
         if constexpr (Cf::STAGED) Cs[row * Cf::SC + col] = val;
-        else Cl[row * BS + col] = val;
+        else Cl[row * LS + col] = val;
         const double dval = double(val);
         const double sq = dval * dval;
         nsq += sq;
@@ -432,7 +444,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
     for (int t = 0; t < NV; ++t) {
       const int v = tid + t * Cf::NT;
       const int row = v / (BS / Cf::VNO), cv = v % (BS / Cf::VNO);
-      *reinterpret_cast<__attribute__((address_space(1))) u32x4*>(Cl + row * BS + cv * Cf::VNO) =
+      *reinterpret_cast<__attribute__((address_space(1))) u32x4*>(Cl + row * LS + cv * Cf::VNO) =
           *reinterpret_cast<const u32x4*>(Cs + row * Cf::SC + cv * Cf::VNO);
     }
   }
@@ -443,7 +455,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
       t += red[Cf::NW + x];
     }
     as_global(ga.wn)[u] = s;
-    if (ci == cj) as_global(ga.wt)[u] = t;
+    if (ci == cj && tr0 == tc0) as_global(ga.wt)[u] = t;  // a tile on the leaf's diagonal
   }
   // with double-buffered panels the next store is not preceded by a barrier:
   // every wave must be done reading the staged leaf first
@@ -452,9 +464,9 @@ __device__ __forceinline__ void epilogue(const GemmArgs& ga, int64_t u, const Un
 
 // ---------------------------------------------------------------- kernel
 
-template <int P, int BS, int V>
-__global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::MINB)) k_gemm(const GemmArgs ga) {
-  using Cf = GemmCfg<P, BS, V>;
+template <int P, int BS, int V, int LS>
+__global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V, LS>::MINB)) k_gemm(const GemmArgs ga) {
+  using Cf = GemmCfg<P, BS, V, LS>;
   __shared__ __attribute__((aligned(16))) char smem[Cf::LDS];
   // per-wave partial sums of the epilogue, two sets used alternately: thread 0
   // may still read one set while the next unit's waves fill the other
@@ -526,14 +538,22 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
   Win Wn;  // the window after W2, fetched early
   Wn.a = Wn.b = 0;
   bool wn_ready = false;
+  // the current unit's tile within its C leaf (row and column offsets)
+  int ur0 = (unit_tile(U.cf) / Cf::NSUB) * BS, uc0 = (unit_tile(U.cf) % Cf::NSUB) * BS;
   if (U.cnt > 0)
-    load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
-                          __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+    load_panel<P, BS, V, LS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
+                              __builtin_amdgcn_readlane(W0.b, 0), 0, ur0, uc0, tid);
 
   for (;;) {
     const bool has_next = cu + 1 < u1;
     int32_t next_cnt = 0;
-    if (has_next) next_cnt = unit_of(ring, blk0, cu + 1 - rb).cnt;
+    int nr0 = 0, nc0 = 0;
+    if (has_next) {
+      const UnitS NU = unit_of(ring, blk0, cu + 1 - rb);
+      next_cnt = NU.cnt;
+      nr0 = (unit_tile(NU.cf) / Cf::NSUB) * BS;
+      nc0 = (unit_tile(NU.cf) % Cf::NSUB) * BS;
+    }
 
     Acc<P, BS, V> acc[Cf::TM][Cf::TN];
     Acc<P, BS, V> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
@@ -572,17 +592,17 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
         // next panel: same product, next product (this or the next window),
         // or the first product of the next unit (the next window)
         if (sub + 1 < Cf::NPANEL) {
-          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63),
-                                __builtin_amdgcn_readlane(W0.b, p & 63), sub + 1, tid);
+          load_panel<P, BS, V, LS>(pr, base, __builtin_amdgcn_readlane(W0.a, p & 63),
+                                    __builtin_amdgcn_readlane(W0.b, p & 63), sub + 1, ur0, uc0, tid);
         } else if (p + 1 < U.cnt) {
           const int l = (p + 1) & 63;
           const bool nw = l == 0;
           const int32_t ia = nw ? __builtin_amdgcn_readlane(W1.a, 0) : __builtin_amdgcn_readlane(W0.a, l);
           const int32_t ib = nw ? __builtin_amdgcn_readlane(W1.b, 0) : __builtin_amdgcn_readlane(W0.b, l);
-          load_panel<P, BS, V>(pr, base, ia, ib, 0, tid);
+          load_panel<P, BS, V, LS>(pr, base, ia, ib, 0, ur0, uc0, tid);
         } else if (next_cnt > 0) {
-          load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W1.a, 0),
-                                __builtin_amdgcn_readlane(W1.b, 0), 0, tid);
+          load_panel<P, BS, V, LS>(pr, base, __builtin_amdgcn_readlane(W1.a, 0),
+                                    __builtin_amdgcn_readlane(W1.b, 0), 0, nr0, nc0, tid);
         }
         __builtin_amdgcn_s_setprio(2);
         if constexpr (Cf::TWO_LEVEL) {
@@ -609,7 +629,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
       }
     }
 
-    epilogue<P, BS, V>(ga, vs.unit(cu), U, acc, smem, red2[cu & 1], tid, lane, wave, row0, col0, li, g);
+    epilogue<P, BS, V, LS>(ga, vs.unit(cu), U, acc, smem, red2[cu & 1], tid, lane, wave, row0, col0, li, g);
     if (!has_next) break;
 
     const int32_t prev_cnt = U.cnt;
@@ -622,6 +642,8 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
       stage_recs(ring, blk0 ^ 1, ga.wu, rb + 64, vs, tid, Cf::NT);
     }
     U = unit_of(ring, blk0, cu - rb);
+    ur0 = nr0;
+    uc0 = nc0;
     W0 = W1;
     W1 = W2;
     if (!wn_ready) {  // a unit without products fetched nothing ahead
@@ -633,53 +655,64 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V>::NT), (GemmCfg<P, BS, V>::M
     // the first panel of a unit that follows a unit without products was
     // not prefetched
     if (prev_cnt == 0 && U.cnt > 0)
-      load_panel<P, BS, V>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
-                            __builtin_amdgcn_readlane(W0.b, 0), 0, tid);
+      load_panel<P, BS, V, LS>(pr, base, __builtin_amdgcn_readlane(W0.a, 0),
+                                __builtin_amdgcn_readlane(W0.b, 0), 0, ur0, uc0, tid);
   }
 }
 
 // ---------------------------------------------------------------- launch
 
-template <int P, int BS, int V>
+template <int P, int BS, int V, int LS>
 static int max_groups(int n_cu) {
   static const int per_cu = [] {  // thread-safe one-time query
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS, V>, GemmCfg<P, BS, V>::NT, 0) != hipSuccess || v < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm<P, BS, V, LS>, GemmCfg<P, BS, V, LS>::NT, 0) !=
+            hipSuccess ||
+        v < 1)
       v = 1;
     return v;
   }();
   return per_cu * n_cu;
 }
 
-template <int P, int BS, int V>
+template <int P, int BS, int V, int LS>
 static hipError_t launch_one(hipStream_t s, const GemmArgs& a) {
-  hipLaunchKernelGGL((k_gemm<P, BS, V>), dim3(uint32_t(kXcds * a.kx)), dim3(GemmCfg<P, BS, V>::NT), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<P, BS, V, LS>), dim3(uint32_t(kXcds * a.kx)), dim3(GemmCfg<P, BS, V, LS>::NT), 0, s,
+                     a);
   return hipGetLastError();
 }
 
 bool gemm_supported(int prec, int bs) {
-  if (prec == SPAMM_F64 || prec == SPAMM_F32) return bs == 16 || bs == 32 || bs == 64 || bs == 128;
-  if (prec == SPAMM_BF16 || prec == SPAMM_BF16X3) return bs == 32 || bs == 64 || bs == 128;
+  if (prec == SPAMM_F64 || prec == SPAMM_F32) return bs == 16 || bs == 32 || bs == 64 || bs == 128 || bs == 256;
+  if (prec == SPAMM_BF16 || prec == SPAMM_BF16X3) return bs == 32 || bs == 64 || bs == 128 || bs == 256;
   return false;
 }
 
-// Runtime (precision, leaf, variant) -> kernel instance.
+// Work units per C leaf: one, or four 128 x 128 tiles of a 256 leaf.
+int gemm_unit_tiles(int bs) { return bs == 256 ? 4 : 1; }
+
+// Runtime (precision, leaf, variant) -> kernel instance; f receives the
+// C tile side and the leaf side (equal below 256).
 template <int P, int V, typename F>
 static auto with_leaf(int bs, F&& f) {
+  using std::integral_constant;
   switch (bs) {
-    case 16: if constexpr (P == SPAMM_F64 || P == SPAMM_F32) return f(std::integral_constant<int, 16>{}); else break;
-    case 32: return f(std::integral_constant<int, 32>{});
-    case 64: return f(std::integral_constant<int, 64>{});
-    case 128: return f(std::integral_constant<int, 128>{});
+    case 16:
+      if constexpr (P == SPAMM_F64 || P == SPAMM_F32) return f(integral_constant<int, 16>{}, integral_constant<int, 16>{});
+      else break;
+    case 32: return f(integral_constant<int, 32>{}, integral_constant<int, 32>{});
+    case 64: return f(integral_constant<int, 64>{}, integral_constant<int, 64>{});
+    case 128: return f(integral_constant<int, 128>{}, integral_constant<int, 128>{});
+    case 256: return f(integral_constant<int, 128>{}, integral_constant<int, 256>{});
     default: break;
   }
-  return f(std::integral_constant<int, 0>{});
+  return f(integral_constant<int, 0>{}, integral_constant<int, 0>{});
 }
 
 template <typename F>
 static auto dispatch(int prec, int bs, int variant, F&& f) {
   auto go = [&](auto pc, auto vc) {
-    return with_leaf<decltype(pc)::value, decltype(vc)::value>(bs, [&](auto bc) { return f(pc, bc, vc); });
+    return with_leaf<decltype(pc)::value, decltype(vc)::value>(bs, [&](auto tc, auto lc) { return f(pc, tc, vc, lc); });
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -697,17 +730,17 @@ static auto dispatch(int prec, int bs, int variant, F&& f) {
 
 int gemm_max_groups(int prec, int bs, int variant, int n_cu) {
   if (!gemm_supported(prec, bs)) return n_cu;
-  return dispatch(prec, bs, variant, [&](auto pc, auto bc, auto vc) -> int {
-    if constexpr (decltype(bc)::value == 0) return n_cu;
-    else return max_groups<decltype(pc)::value, decltype(bc)::value, decltype(vc)::value>(n_cu);
+  return dispatch(prec, bs, variant, [&](auto pc, auto tc, auto vc, auto lc) -> int {
+    if constexpr (decltype(tc)::value == 0) return n_cu;
+    else return max_groups<decltype(pc)::value, decltype(tc)::value, decltype(vc)::value, decltype(lc)::value>(n_cu);
   });
 }
 
 hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmArgs& a) {
   if (!gemm_supported(prec, bs)) return hipErrorInvalidValue;
-  return dispatch(prec, bs, variant, [&](auto pc, auto bc, auto vc) -> hipError_t {
-    if constexpr (decltype(bc)::value == 0) return hipErrorInvalidValue;
-    else return launch_one<decltype(pc)::value, decltype(bc)::value, decltype(vc)::value>(s, a);
+  return dispatch(prec, bs, variant, [&](auto pc, auto tc, auto vc, auto lc) -> hipError_t {
+    if constexpr (decltype(tc)::value == 0) return hipErrorInvalidValue;
+    else return launch_one<decltype(pc)::value, decltype(tc)::value, decltype(vc)::value, decltype(lc)::value>(s, a);
   });
 }
 
@@ -738,18 +771,29 @@ hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, i
   return hipGetLastError();
 }
 
-// Leaf norms (leaf level of C's pyramid) and diagonal sums of the units.
+// Leaf norms (leaf level of C's pyramid) and diagonal sums of the units.  A
+// leaf split into tiles has its units next to each other (tile 0 first):
+// the unit of tile 0 adds the tiles' squared norms, and the diagonal sums of
+// the tiles on the leaf's diagonal, in tile order.
 __global__ void k_unit_scatter(const ReqDev* __restrict__ reqs, const WorkUnit* __restrict__ wu, int64_t nwu,
                                const double* __restrict__ wn, const double* __restrict__ wt) {
   const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (u >= nwu) return;
   const WorkUnit w = wu[u];
+  if (unit_tile(w.cflags) != 0) return;
   const ReqDev& R = reqs[w.req];
-  const uint32_t cm = uint32_t(w.cflags & (kUnitEp - 1));
-  R.cnorm[level_offset(R.L) + cm] = wn[u];
+  const int nt = R.bs == 256 ? 2 : 1;  // tiles per side
+  const uint32_t cm = uint32_t(w.cflags & kUnitMorton);
+  double s = 0.0;
+  for (int t = 0; t < nt * nt; ++t) s += wn[u + t];
+  R.cnorm[level_offset(R.L) + cm] = s;
   uint32_t ci, cj;
   demorton(cm, ci, cj);
-  if (ci == cj) R.trace_part[ci] = wt[u];
+  if (ci == cj) {
+    double d = 0.0;
+    for (int t = 0; t < nt; ++t) d += wt[u + t * nt + t];
+    R.trace_part[ci] = d;
+  }
 }
 
 hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const double* wn,

@@ -56,6 +56,7 @@ __device__ __forceinline__ int find_req(const ReqDev* __restrict__ reqs, const i
 struct LaneLeaf {
   int r;
   uint32_t c, i, j;
+  bool mirror;  // a symmetric square's leaf below the diagonal: walks its mirror (j, i)
   int lo, hi;
   const double* sa;  // sqrt norms of A's row i (index k)
   const double* sb;  // sqrt norms of B's column j
@@ -70,6 +71,7 @@ __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, c
   x.valid = g < total_c;
   x.r = 0;
   x.c = x.i = x.j = 0;
+  x.mirror = false;
   x.lo = 1;
   x.hi = 0;
   x.sa = x.sb = nullptr;
@@ -80,12 +82,16 @@ __device__ __forceinline__ LaneLeaf lane_leaf(const ReqDev* __restrict__ reqs, c
     const int G = R.G;
     x.c = uint32_t(g - R.cbase);
     demorton(x.c, x.i, x.j);
-    x.lo = max(R.A.ranges[x.i], R.B.ranges[2 * G + x.j]);
-    x.hi = min(R.A.ranges[G + x.i], R.B.ranges[3 * G + x.j]);
-    x.sa = R.A.rm_sqrt + int64_t(x.i) * G;
-    x.sb = R.B.cm_sqrt + int64_t(x.j) * G;
-    x.la = R.A.rm_slot + int64_t(x.i) * G;
-    x.lb = R.B.cm_slot + int64_t(x.j) * G;
+    // a symmetric square decides a leaf below the diagonal as its mirror:
+    // the same walk, so the same counts, bounds and kept set (transposed)
+    x.mirror = R.sym && x.i > x.j && *R.asym == 0;
+    const uint32_t wi = x.mirror ? x.j : x.i, wj = x.mirror ? x.i : x.j;
+    x.lo = max(R.A.ranges[wi], R.B.ranges[2 * G + wj]);
+    x.hi = min(R.A.ranges[G + wi], R.B.ranges[3 * G + wj]);
+    x.sa = R.A.rm_sqrt + int64_t(wi) * G;
+    x.sb = R.B.cm_sqrt + int64_t(wj) * G;
+    x.la = R.A.rm_slot + int64_t(wi) * G;
+    x.lb = R.B.cm_slot + int64_t(wj) * G;
   }
   return x;
 }
@@ -309,7 +315,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_count(const ReqDev* _
     const int64_t flag = (my_cnt > 0 || dflag) ? 1 : 0;
     // a symmetric square forms no product below the diagonal: those leaves
     // are written from their mirrors (they keep their slot, bounds and counts)
-    const int64_t formed = (R.sym && x.i > x.j) ? 0 : my_cnt;
+    const int64_t formed = x.mirror ? 0 : my_cnt;
     packed[g] = (flag << cb) | formed;
     bnd_all[g] = my_skip;
     cand_all[g] = int32_t(my_cand);
@@ -400,14 +406,18 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
       const int64_t* Q = R.sched + kXcds * (n + 1);  // offsets of the slices
       const int64_t at = Q[q] + R.sched[q * (n + 1) + R.sched_k] + (cs - cn * q / ns);
       if (at >= 0 && at < Q[kXcds]) {
+        // a 256 leaf is four 128 x 128 tiles, one unit each, side by side
+        const int nt = R.bs == 256 ? 4 : 1;
         WorkUnit u;
         u.pp = R.pairs_idx + off;
         u.cnt = int32_t(cnt);
         u.cidx = int32_t(R.cidx + cs);
         u.req = x.r;
-        u.cflags = int32_t(x.c) | (R.use_ep ? kUnitEp : 0);
-        wu[R.wu_base + at] = u;
-        cost[R.wu_base + at] = cnt + 1;
+        for (int t = 0; t < nt; ++t) {
+          u.cflags = int32_t(x.c) | (R.use_ep ? kUnitEp : 0) | (t << kUnitTileShift);
+          wu[R.wu_base + at * nt + t] = u;
+          cost[R.wu_base + at * nt + t] = cnt + 1;
+        }
       }
     } else {
       R.cnorm[level_offset(R.L) + x.c] = 0.0;
@@ -635,14 +645,14 @@ __global__ void __launch_bounds__(256) k_mirror(const ReqDev* __restrict__ reqs,
       else hi = mid - 1;
     }
     const ReqDev& R = reqs[lo];
-    if (!R.sym) continue;
+    if (!R.sym || *R.asym != 0) continue;  // not a symmetric square, or formed in full
     const uint32_t m = uint32_t(g - R.cbase);
     uint32_t I, J;
     demorton(m, I, J);
     if (I <= J) continue;
     const uint32_t m2 = morton(J, I);
     const int32_t sd = R.cslot[m], ss = R.cslot[m2];
-    if (sd < 0 || ss < 0) continue;  // a null mirror only if A was not symmetric
+    if (sd < 0 || ss < 0) continue;  // both null: the lower leaf took its mirror's decision
     const int64_t e2 = int64_t(R.bs) * R.bs;
     const int64_t lv = level_offset(R.L);
     if (threadIdx.x == 0) R.cnorm[lv + m] = R.cnorm[lv + m2];
@@ -654,6 +664,31 @@ __global__ void __launch_bounds__(256) k_mirror(const ReqDev* __restrict__ reqs,
       mirror_leaf(c + ss * e2, static_cast<float*>(R.cstore) + sd * e2, R.bs, reinterpret_cast<float*>(tile));
     }
   }
+}
+
+// Symmetry of a null map (and of the epilogue matrix's): one thread per
+// leaf (I, K) with I < K compares it with (K, I); a wave with a mismatch
+// sets the flag.
+__global__ void k_sym_check(int G, const int32_t* __restrict__ slot, const int32_t* __restrict__ slotD,
+                            int32_t* __restrict__ flag) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (m < int64_t(G) * G) {
+    uint32_t I, K;
+    demorton(uint32_t(m), I, K);
+    if (I < K) {
+      const uint32_t t = morton(K, I);
+      bad = (slot[m] >= 0) != (slot[t] >= 0);
+      if (slotD) bad = bad || ((slotD[m] >= 0) != (slotD[t] >= 0));
+    }
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_sym_check(hipStream_t s, int G, const int32_t* slot, const int32_t* slotD, int32_t* flag) {
+  const int64_t G2 = int64_t(G) * G;
+  hipLaunchKernelGGL(k_sym_check, dim3(uint32_t((G2 + 255) / 256)), dim3(256), 0, s, G, slot, slotD, flag);
+  return hipGetLastError();
 }
 
 hipError_t launch_mirror(hipStream_t s, const ReqDev* reqs, int nreq, int64_t total_c) {

@@ -200,15 +200,48 @@ __device__ __forceinline__ bool key_le(uint64_t sb, uint32_t m, uint64_t khi, ui
   return sb < khi || (sb == khi && m <= klo);
 }
 
-// Candidates (non-null leaves with s <= tau^2) are flagged, scanned, and
-// compacted into (s, Morton index) lists by the scan's sink, which looks up
-// the job of flagged entries only.
+// The unit a leaf is truncated with: itself, or in the mirror-pair form its
+// pair, represented by the leaf on or above the diagonal (rep), with weight
+// s_rep + s_mirror (s of a null leaf is 0; a diagonal leaf is alone).
+struct TruncUnit {
+  uint32_t rep;
+  double w;
+  bool present;
+};
+
+__device__ __forceinline__ TruncUnit trunc_unit(const TruncJob& J, uint32_t m) {
+  TruncUnit u;
+  if (!J.pairs) {
+    u.rep = m;
+    u.present = J.slot[m] >= 0;
+    u.w = J.leafnorm[m];
+    return u;
+  }
+  uint32_t i, k;
+  demorton(m, i, k);
+  const uint32_t hi = i <= k ? m : morton(k, i), lo = morton(i <= k ? k : i, i <= k ? i : k);
+  u.rep = hi;
+  if (hi == lo) {
+    u.present = J.slot[hi] >= 0;
+    u.w = J.leafnorm[hi];
+  } else {
+    u.present = J.slot[hi] >= 0 || J.slot[lo] >= 0;
+    u.w = J.leafnorm[hi] + J.leafnorm[lo];
+  }
+  return u;
+}
+
+// Candidates (units with a non-null leaf and weight <= tau^2) are flagged,
+// scanned, and compacted into (weight, Morton index) lists by the scan's
+// sink, which looks up the job of flagged entries only.  In the pair form
+// only the representative leaf of a pair is a candidate.
 __global__ void k_trunc_flag(const TruncJob* __restrict__ jobs, int njobs, int64_t total, int32_t* __restrict__ flag) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const TruncJob& J = jobs[find_job(jobs, njobs, g)];
-  const int64_t m = g - J.base;
-  flag[g] = (J.slot[m] >= 0 && J.leafnorm[m] <= J.tau2) ? 1 : 0;
+  const uint32_t m = uint32_t(g - J.base);
+  const TruncUnit u = trunc_unit(J, m);
+  flag[g] = (u.rep == m && u.present && u.w <= J.tau2) ? 1 : 0;
 }
 
 struct TruncCompactSink {
@@ -219,8 +252,8 @@ struct TruncCompactSink {
   __device__ void operator()(int64_t g, int64_t v, int64_t pos) const {
     if (!v) return;
     const TruncJob& J = jobs[find_job(jobs, njobs, g)];
-    const int64_t m = g - J.base;
-    cs[pos] = J.leafnorm[m];
+    const uint32_t m = uint32_t(g - J.base);
+    cs[pos] = trunc_unit(J, m).w;
     cm[pos] = int32_t(m);
   }
 };
@@ -391,9 +424,11 @@ __global__ void k_trunc_apply(const TruncJob* __restrict__ jobs, int njobs, int6
   const TruncJob& J = jobs[j];
   const int64_t m = g - J.base;
   const double s = J.leafnorm[m];
-  const bool cand = J.slot[m] >= 0 && s <= J.tau2;
+  // a leaf goes with its unit (itself, or its mirror pair)
+  const TruncUnit u = trunc_unit(J, uint32_t(m));
+  const bool cand = u.present && u.w <= J.tau2;
   const bool drop = cand && kst[3 * j + 2] != 0 &&
-                    key_le(__double_as_longlong(s), uint32_t(m), kst[3 * j], uint32_t(kst[3 * j + 1]));
+                    key_le(__double_as_longlong(u.w), u.rep, kst[3 * j], uint32_t(kst[3 * j + 1]));
   J.out_slot[m] = drop ? -1 : J.slot[m];
   J.out_norm[m] = drop ? 0.0 : s;
 }

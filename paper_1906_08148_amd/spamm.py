@@ -16,10 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libspamm.so")
 
-TRUNCMUL, SPAMM, HYBRID, SPAMM_SYM = 0, 1, 2, 3
+TRUNCMUL, SPAMM, HYBRID, SPAMM_SYM, HYBRID_SYM = 0, 1, 2, 3, 4
 F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 STORE_F64, STORE_F32, STORE_BF16 = 1, 2, 4
-MODES = {"truncmul": TRUNCMUL, "spamm": SPAMM, "hybrid": HYBRID, "spamm_sym": SPAMM_SYM}
+MODES = {"truncmul": TRUNCMUL, "spamm": SPAMM, "hybrid": HYBRID, "spamm_sym": SPAMM_SYM, "hybrid_sym": HYBRID_SYM}
 PRECS = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "ENONFINITE",
           5: "EUNSUPPORTED", 6: "EDEVICE"}

@@ -47,15 +47,16 @@ def test_config1_all_modes(ctx):
             check_product(ctx, M, M, T, T, 1e-6, mode, prec, alias=True)
 
 
-@pytest.mark.parametrize("n,bs,kind,alpha,tau", [
-    (1000, 32, "1d", 0.3, 1e-5),      # ragged tail, not a power of two
-    (300, 16, "rand", 0.3, 1e-2),     # random sparse blocks
-    (2100, 64, "1d", 0.2, 1e-6),      # several tiles + ragged
-    (700, 128, "3d", 1.0, 1e-4),      # 3D decay, big leaves
-    (17, 16, "1d", 0.5, 1e-3),        # G = 2 with a 1-row tail
-    (20, 32, "1d", 0.5, 1e-3),        # single leaf (L = 0)
+@pytest.mark.parametrize("n,bs,kind,alpha,tau,full", [
+    (1000, 32, "1d", 0.3, 2e-5, True),    # ragged tail, not a power of two
+    (1000, 32, "1d", 0.3, 1e-5, False),   # the same with a tie at B's truncation boundary
+    (300, 16, "rand", 0.3, 1e-2, True),   # random sparse blocks
+    (2100, 64, "1d", 0.2, 1e-6, True),    # several tiles + ragged
+    (700, 128, "3d", 1.0, 1e-4, True),    # 3D decay, big leaves
+    (17, 16, "1d", 0.5, 1e-3, True),      # G = 2 with a 1-row tail
+    (20, 32, "1d", 0.5, 1e-3, True),      # single leaf (L = 0)
 ])
-def test_shapes_and_leaf_sizes(ctx, n, bs, kind, alpha, tau):
+def test_shapes_and_leaf_sizes(ctx, n, bs, kind, alpha, tau, full):
     print(f"case: n={n} bs={bs} {kind}", flush=True)
     if kind == "rand":
         A = sparse_random(n, bs, alpha, 3)
@@ -72,7 +73,7 @@ def test_shapes_and_leaf_sizes(ctx, n, bs, kind, alpha, tau):
     check_norms(ctx, MA, TA)
     for mode in MODES:
         for prec in (spamm.F64, spamm.F32):
-            check_product(ctx, MA, MB, TA, TB, tau, mode, prec)
+            check_product(ctx, MA, MB, TA, TB, tau, mode, prec, expect_full=full or mode == spamm.SPAMM)
 
 
 def test_block_list_build_matches_dense_build(ctx):

@@ -314,3 +314,138 @@ def test_truncation_tie_only_where_rounding_can_move_the_boundary():
     # well clear of it on either side: no tie
     assert not O.truncate(T, math.sqrt(s_min) * (1 - 1e-9)).tie
     assert not O.truncate(T, math.sqrt(s_min) * (1 + 1e-9)).tie
+
+
+# ---------------------------------------------------------------- symmetric square
+
+def _brute_pair_truncate(A, bs, tau):
+    """Independent mirror-pair truncation: loop-computed leaf norms, pairs
+    (I <= K) of weight s_IK + s_KI, bit-loop Morton keys, greedy drop with
+    exactly rounded running sums (math.fsum of the leaf norms)."""
+    n = A.shape[0]
+    g = -(-n // bs)
+
+    def sq(I, K):
+        blk = A[I * bs:(I + 1) * bs, K * bs:(K + 1) * bs]
+        v = 0.0
+        for x in blk.ravel():
+            v += x * x
+        return v, bool(np.any(blk != 0))
+
+    pairs = []
+    for I in range(g):
+        for K in range(I, g):
+            (a, na), (b, nb) = sq(I, K), sq(K, I)
+            if not (na or nb):
+                continue
+            key = 0
+            for bit in range(16):
+                key |= ((I >> bit) & 1) << (2 * bit + 1) | ((K >> bit) & 1) << (2 * bit)
+            terms = [a] if I == K else [a, b]
+            pairs.append((a if I == K else a + b, key, I, K, terms))
+    pairs.sort(key=lambda p: (p[0], p[1]))
+    out = A.copy()
+    taken = []
+    for w, key, I, K, terms in pairs:
+        if math.fsum(taken + terms) <= tau * tau:
+            taken += terms
+            out[I * bs:(I + 1) * bs, K * bs:(K + 1) * bs] = 0.0
+            out[K * bs:(K + 1) * bs, I * bs:(I + 1) * bs] = 0.0
+        else:
+            break
+    return out
+
+
+@pytest.mark.parametrize("kind,n,alpha,bs", [("1d", 96, 0.3, 8), ("3d", 128, 1.0, 16), ("1d", 200, 0.05, 8)])
+def test_pair_truncation_brute_force_and_invariants(kind, n, alpha, bs):
+    A = synth.DecaySpec(kind, n, alpha, seed=11).dense()
+    T = O.build(A, bs)
+    for tau in (1e-8, 1e-5, 1e-3, 1e-1, 1.0):
+        tr = O.truncate_pairs(T, tau)
+        At = tr.tree.to_dense()
+        assert np.array_equal(At, _brute_pair_truncate(A, bs, tau))
+        # symmetric, within budget, and maximal: the next pair would break it
+        assert np.array_equal(At, At.T)
+        assert np.linalg.norm(A - At) <= tau * (1 + 1e-12)
+        assert math.sqrt(tr.dropped_sq) <= tau * (1 + 1e-15)
+        if tr.boundary_sq[1] < math.inf:
+            assert tr.boundary_sq[1] > tau * tau or tr.tie
+
+
+@pytest.mark.parametrize("mode", [O.SPAMM, O.HYBRID])
+@pytest.mark.parametrize("kind,n,alpha,bs,tau", [("1d", 300, 0.2, 16, 1e-6), ("3d", 256, 1.0, 16, 1e-3),
+                                                 ("1d", 200, 0.05, 8, 1e-2)])
+def test_symmetric_square_reading(mode, kind, n, alpha, bs, tau):
+    """Upper C leaves as the norm test decides them on the (pair-truncated)
+    operand, each lower leaf the exact transpose of its mirror with the
+    mirror's bound; against a loop over the upper leaves and the full
+    product of the same operand."""
+    A = synth.DecaySpec(kind, n, alpha, seed=6).dense()
+    assert np.array_equal(A, A.T)
+    T = O.build(A, bs)
+    Au = O.truncate_pairs(T, tau).tree if mode == O.HYBRID else T
+    full = O.multiply(Au, Au, tau, O.SPAMM)
+    sym = O.multiply_symmetric(T, tau, mode)
+    assert not sym.stats["sym_fallback"]
+    assert np.array_equal(sym.A_used.index >= 0, Au.index >= 0)
+    want = []
+    for I in range(T.G):
+        for J in range(I, T.G):
+            for K in range(T.G):
+                if Au.leaf_present[I, K] and Au.leaf_present[K, J] and \
+                        math.sqrt(Au.leaf_sq[I, K]) * math.sqrt(Au.leaf_sq[K, J]) >= tau:
+                    want.append((I, K, J))
+    assert {tuple(t) for t in sym.kept.tolist()} == set(want)
+    assert sym.stats["n_kept"] == len(want)
+    for I in range(T.G):
+        for J in range(T.G):
+            assert sym.C.leaf_present[I, J] == sym.C.leaf_present[J, I]
+            if sym.C.leaf_present[I, J]:
+                if I <= J:
+                    acc = np.zeros((bs, bs))
+                    for (i, k, j) in want:
+                        if (i, j) == (I, J):
+                            acc = acc + Au.leaf(I, k) @ Au.leaf(k, J)
+                    assert np.array_equal(sym.C.leaf(I, J), acc)
+                else:
+                    assert np.array_equal(sym.C.leaf(I, J), sym.C.leaf(J, I).T)
+            assert sym.skipped_bound[I, J] == sym.skipped_bound[min(I, J), max(I, J)]
+    Cf, Cs = full.C.to_dense(), sym.C.to_dense()
+    assert np.linalg.norm(Cs - Cf) <= 1e-14 * max(np.linalg.norm(Cf), 1e-300)
+    assert np.array_equal(Cs, Cs.T)
+    if mode == O.HYBRID:  # Thm. 3's terms with the pair truncation's dA
+        dA = sym.stats["dA"]
+        assert dA <= tau and abs(dA - np.linalg.norm(A - Au.to_dense())) <= 1e-12 * max(dA, 1e-300) + 1e-300
+
+
+def test_pair_truncation_keeps_mirror_pairs_together():
+    """Leaves (0, 1) and (1, 0) have exactly equal norms and tau^2 lies between
+    one and two of them: the leaf-by-leaf truncation drops (0, 1) alone,
+    the pair truncation neither (their weight 0.5 is above 0.3)."""
+    bs = 4
+    A = np.zeros((8, 8))
+    A[0:4, 0:4] = np.eye(4) * 2.0
+    A[4:8, 4:8] = np.eye(4) * 3.0
+    A[0, 4] = A[4, 0] = 0.5          # s = 0.25 for both off-diagonal leaves
+    T = O.build(A, bs)
+    tau = math.sqrt(0.3)
+    assert [tuple(x) for x in O.truncate(T, tau).dropped.tolist()] == [(0, 1)]
+    assert len(O.truncate_pairs(T, tau).dropped) == 0
+    assert {tuple(x) for x in O.truncate_pairs(T, math.sqrt(0.5)).dropped.tolist()} == {(0, 1), (1, 0)}
+
+
+def test_symmetric_square_falls_back_when_the_null_map_is_not_symmetric():
+    """A whose leaf (0, 1) is non-null and (1, 0) null: the mirror
+    decisions would be wrong, so every C leaf is formed by its own test."""
+    bs = 4
+    A = np.zeros((8, 8))
+    A[0:4, 0:4] = np.eye(4) * 2.0
+    A[4:8, 4:8] = np.eye(4) * 3.0
+    A[0, 4] = 0.5
+    T = O.build(A, bs)
+    for mode in (O.SPAMM, O.HYBRID):
+        sym = O.multiply_symmetric(T, 1e-9, mode)
+        full = O.multiply(T, T, 1e-9, O.SPAMM)
+        assert sym.stats["sym_fallback"]
+        assert np.array_equal(sym.kept, full.kept)
+        assert np.array_equal(sym.C.to_dense(), full.C.to_dense())
