@@ -374,6 +374,23 @@ spamm_status spamm_to_dense(spamm_ctx* ctx, const spamm_mat* m, double* out,
 spamm_status spamm_gershgorin(spamm_ctx* ctx, const spamm_mat* m, double* lo,
                               double* hi);
 
+/* spamm_gershgorin for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The same bounds, computed by the same kernels, are written
+ * stream-ordered to the caller's device buffer bounds[0] = lo, bounds[1] =
+ * hi (two doubles); nothing is synchronised and nothing is allocated: the
+ * per-leaf-row partial bounds live in a static device array of 1024 leaf
+ * rows (16 KiB per device, held until the process ends), so m must have
+ * G <= 1024 leaf rows (n <= 1024 * leaf; EUNSUPPORTED otherwise, before
+ * any launch).  Every
+ * call on one device shares that array: calls that overlap on one device
+ * (other streams or contexts, other threads) race and must be ordered by
+ * the caller.  Errors: EINVAL (NULL argument, foreign handle), EUNSUPPORTED
+ * (no FP64/FP32 copy, G > 1024), EDEVICE (launch failure, scratch address
+ * not found at context creation). */
+spamm_status spamm_gershgorin_static(spamm_ctx* ctx, const spamm_mat* m,
+                                     double* bounds);
+
 /* Copy `count` leaves (block row ij[2t], block column ij[2t+1], host int32)
  * of a matrix into `out` (host, FP64, count * bs * bs values, leaf t
  * row-major at t * bs * bs); null leaves give zeros, entries beyond n are the

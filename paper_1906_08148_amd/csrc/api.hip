@@ -503,6 +503,8 @@ spamm_status spamm_ctx_create(int device, void* arena, size_t arena_bytes, spamm
     return SPAMM_EINVAL;
   *out = nullptr;
   if (hipSetDevice(device) != hipSuccess) return SPAMM_EDEVICE;
+  // the static scratch of spamm_gershgorin_static, once per device
+  if (noalloc_setup(device) != hipSuccess) return SPAMM_EDEVICE;
   auto* x = new spamm_ctx;
   x->c.device = device;
   x->c.stream = static_cast<hipStream_t>(stream);
@@ -1537,6 +1539,23 @@ spamm_status spamm_gershgorin(spamm_ctx* ctx, const spamm_mat* m, double* lo, do
   if (st != SPAMM_OK) return st;
   *lo = h[0];
   *hi = h[1];
+  return SPAMM_OK;
+}
+
+spamm_status spamm_gershgorin_static(spamm_ctx* ctx, const spamm_mat* m, double* bounds) {
+  if (!ctx || !m || !bounds) return SPAMM_EINVAL;
+  Ctx* c = &ctx->c;
+  if (m->ctx != c) return fail(c, SPAMM_EINVAL, "bad matrix handle");
+  if (!m->store || (!m->store->f64 && !m->store->f32)) return fail(c, SPAMM_EUNSUPPORTED, "no FP64/FP32 leaf copy");
+  if (m->G > kGershStaticRows)
+    return fail(c, SPAMM_EUNSUPPORTED, "more leaf rows than the static scratch holds (1024)");
+  double* part = noalloc_scratch(c->device);
+  if (!part) return fail(c, SPAMM_EDEVICE, "static scratch not set up on this device");
+  // every partial in [0, 2 G) is written by the row kernel before the final
+  // kernel reads it, so nothing left by an earlier call needs clearing
+  const Store& s = *m->store;
+  SPAMM_HIP(c, launch_gershgorin(c->stream, m->n, m->bs, m->G, P<int32_t>(m->slot), P<double>(s.f64),
+                                 s.f64 ? nullptr : P<float>(s.f32), part, bounds));
   return SPAMM_OK;
 }
 

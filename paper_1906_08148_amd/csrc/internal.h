@@ -436,6 +436,14 @@ int gemm_unit_tiles(int bs);  // work units per C leaf (4 for 256 leaves, else 1
 hipError_t launch_unit_scatter(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu,
                                const double* wn, const double* wt);
 hipError_t launch_zero_i32(hipStream_t s, int32_t* p, int64_t count);
+// The entry point that allocates nothing keeps its scratch in a static
+// device array of this many leaf rows (noalloc.hip); noalloc_setup looks up
+// the array's address on `device` (which must be current) once, and
+// noalloc_scratch returns it (nullptr before setup).
+constexpr int kGershStaticRows = 1024;
+hipError_t noalloc_setup(int device);
+double* noalloc_scratch(int device);
+
 hipError_t launch_gershgorin(hipStream_t s, int64_t n, int bs, int G, const int32_t* slot, const double* f64,
                              const float* f32, double* part, double* out);
 hipError_t launch_gather_leaves(hipStream_t s, int bs, int64_t count, const int32_t* slot, const double* f64,

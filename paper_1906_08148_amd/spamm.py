@@ -130,6 +130,7 @@ _SIGS = {
     "spamm_ctx_get_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "spamm_gershgorin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
+    "spamm_gershgorin_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "spamm_leaves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_void_p]),
     "spamm_mat_info_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MatInfo)]),
@@ -382,6 +383,13 @@ class Context:
         lo, hi = ctypes.c_double(), ctypes.c_double()
         self._check(_lib.spamm_gershgorin(self.ptr, m.handle, ctypes.byref(lo), ctypes.byref(hi)))
         return lo.value, hi.value
+
+    def gershgorin_static(self, m: Matrix, bounds):
+        """Gershgorin bounds written into the device tensor `bounds` (two
+        float64 values, lo then hi), stream-ordered, with no allocation."""
+        import torch
+        assert bounds.dtype == torch.float64 and bounds.is_cuda and bounds.numel() >= 2 and bounds.is_contiguous()
+        self._check(_lib.spamm_gershgorin_static(self.ptr, m.handle, ctypes.c_void_p(bounds.data_ptr())))
 
     def identity(self, n: int, leaf: int, stores: int = STORE_F64 | STORE_F32) -> Matrix:
         """The n x n identity as a quadtree (diagonal leaves only)."""
