@@ -518,6 +518,7 @@ def serving(n_requests, n_max, rates=(0.5, 1.0, 2.0, 4.0)):
     alone = serve.run_stream(srv.sched, pool, rate=0)
     t_alone = time.perf_counter() - t0
     srv.close()
+    del srv
     torch.cuda.empty_cache()
     mu = len(pool) / t_alone
     out = {"workload": f"first {len(pool)} requests with n <= {n_max} of the seeded pool (n in 2048..65536 step "
@@ -530,11 +531,13 @@ def serving(n_requests, n_max, rates=(0.5, 1.0, 2.0, 4.0)):
         srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs, graph=graph)
         res = serve.run_stream(srv.sched, pool, rate=x * mu, seed=11)
         srv.close()
+        log_ = list(srv.sched.log)
+        del srv
         torch.cuda.empty_cache()
         sm = serve.summarize(res)
         sm["gflops_frac_of_fp32_peak"] = sm.get("gflops", 0.0) / 1e3 / FP32_MFMA_PEAK_TFLOPS
-        sm["batches"] = len(srv.sched.log)
-        sm["largest_batch"] = max((len(b[2]) for b in srv.sched.log), default=0)
+        sm["batches"] = len(log_)
+        sm["largest_batch"] = max((len(b[2]) for b in log_), default=0)
         sm["over_alone_capacity"] = round(sm.get("multiplies_per_s", 0.0) / mu, 3)
         out["runs"][f"{x}{'_graph' if graph else ''}"] = sm
     return out
@@ -688,7 +691,7 @@ def main():
     log(f"bench: 3D hybrid {args.prec} steps")
     r = config3_steps(ctx, dA, prec, args.steps, args.warmup, keep_last=not args.skip_extras)
     tile = ctx.get_option("gemm_tile")
-    kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}>"
+    kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}, {LEAF3D}>"
     st = r["stats"]
     out = {
         "metric": METRIC,

@@ -232,8 +232,12 @@ class Context:
         if self.ptr is not None:
             import gc
             gc.collect()
-            _lib.spamm_ctx_destroy(self.ptr)
+            st = _lib.spamm_ctx_destroy(self.ptr)
             self.ptr = None
+            if st == 0:
+                # the context synchronised its stream and is gone: the arena
+                # goes back to torch now, not when this object is collected
+                self.arena = None
 
     def arena_info(self):
         u, f, l = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
