@@ -220,15 +220,26 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       kept products (0 for FP64 products).  Needs the FP64
  *                       copy of A and B (EUNSUPPORTED otherwise); costs the
  *                       FP64 products and one synchronisation.
+ *  SPAMM_OPT_GEMM_QUAD  0 (default): every C leaf of a leaf-64 product is
+ *                       one work unit of the leaf GEMM; 1: the C leaves that
+ *                       are children of one quadtree node (up to four) run in
+ *                       one workgroup over the merged k order of their
+ *                       products, so that every A and B leaf staged serves
+ *                       both children of its row or column half (half the
+ *                       operand reads when all four keep a k).  Each C leaf
+ *                       still sums its own products k ascending.  Other leaf
+ *                       sizes ignore it.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
- * changes the order of the sums inside one MFMA (results stay within the
- * precision's tolerance).  Errors: EINVAL (unknown key or value). */
+ * and GEMM_QUAD change the order of the sums inside one MFMA or one k-panel
+ * (results stay within the precision's tolerance).  Errors: EINVAL (unknown
+ * key or value). */
 typedef enum {
   SPAMM_OPT_GEMM_TILE = 0,
   SPAMM_OPT_PLACEMENT = 1,
   SPAMM_OPT_GRAPH = 2,
   SPAMM_OPT_UNIT_ORDER = 3,
-  SPAMM_OPT_VALIDATE = 4
+  SPAMM_OPT_VALIDATE = 4,
+  SPAMM_OPT_GEMM_QUAD = 5
 } spamm_option;
 
 spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t value);

@@ -106,6 +106,9 @@ constexpr int kMaxL = 11;  // G <= 2048
 
 bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || bs == 256; }
 
+// Launch groups whose products run in quads of sibling C leaves.
+bool quad_group(const Ctx* c, int prec, int bs) { return c->gemm_quad && gemm_quad_supported(prec, bs); }
+
 void grid_of(int64_t n, int bs, int& G, int& L) {
   const int64_t g = (n + bs - 1) / bs;
   G = 1;
@@ -553,6 +556,7 @@ spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t valu
     case SPAMM_OPT_PLACEMENT: c->gemm_sched = int(value); return SPAMM_OK;
     case SPAMM_OPT_GRAPH: c->use_graph = int(value); return SPAMM_OK;
     case SPAMM_OPT_VALIDATE: c->validate = int(value); return SPAMM_OK;
+    case SPAMM_OPT_GEMM_QUAD: c->gemm_quad = int(value); return SPAMM_OK;
     default: return fail(c, SPAMM_EINVAL, "unknown option");
   }
 }
@@ -566,6 +570,7 @@ spamm_status spamm_ctx_get_option(const spamm_ctx* ctx, spamm_option key, int64_
     case SPAMM_OPT_GRAPH: *value = c->use_graph; return SPAMM_OK;
     case SPAMM_OPT_UNIT_ORDER: *value = c->gemm_interleave; return SPAMM_OK;
     case SPAMM_OPT_VALIDATE: *value = c->validate; return SPAMM_OK;
+    case SPAMM_OPT_GEMM_QUAD: *value = c->gemm_quad; return SPAMM_OK;
     default: return SPAMM_EINVAL;
   }
 }
@@ -1184,6 +1189,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < count; ++r) groups[{reqs[r].prec, reqs[r].A->bs}].push_back(r);
   int64_t wu_total = 0;
+  std::vector<RegionP> quad_keep;  // per-request k arrays of the quad groups
   std::vector<std::pair<std::pair<int, int>, std::pair<int64_t, int64_t>>> launches;
   for (auto& gk : groups) {
     const int64_t start = wu_total;
@@ -1204,6 +1210,14 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     if (st != SPAMM_OK) return st;
     ALLOC(C->plan_pairs, std::max<int64_t>(nk, 1) * 8, "plan pairs");
     d.pairs = P<int2>(C->plan_pairs);
+    d.pk = nullptr;
+    d.qbase = 0;
+    if (quad_group(c, q.prec, q.A->bs)) {  // the k of every pair, for the quads' merged order
+      RegionP pkr;
+      ALLOC(pkr, std::max<int64_t>(nk, 1) * 4, "plan k");
+      d.pk = P<int32_t>(pkr);
+      quad_keep.push_back(std::move(pkr));
+    }
     d.off = P<int64_t>(C->plan_off);
     d.cslot = P<int32_t>(C->slot);
     d.ckeys = P<int32_t>(C->store->keys);
@@ -1293,8 +1307,11 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     int gi = 0;
     for (auto& gk : groups) {
       const int64_t nwu = launches[gi++].second.second;
-      const int64_t maxg = gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
-      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, nwu));
+      const bool quad = quad_group(c, gk.first.first, gk.first.second);
+      const int64_t maxg = quad ? gemm_quad_max_groups(gk.first.first, c->gemm_tile, c->n_cu)
+                                : gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
+      // quads: at least a quarter of the units
+      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, quad ? (nwu + 3) / 4 : nwu));
       const int kx = int((want + kXcds - 1) / kXcds);
       kxs.push_back(kx);
       start_total += int64_t(kXcds) * kx + 1;
@@ -1309,6 +1326,33 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   ALLOC(wn, std::max<int64_t>(wu_total, 1) * 8, "unit norms");
   ALLOC(wt, std::max<int64_t>(wu_total, 1) * 8, "unit diagonal sums");
   ALLOC(sscr, std::max<int64_t>(scan_need, 1), "scan scratch");
+  // quad plans: per quad group, flags, quad positions, step counts and
+  // offsets, the quads' cost prefix (int64), the quad records and the steps
+  RegionP q_i64, q_rec, q_steps, q_mask;
+  std::vector<std::array<int64_t, 3>> q_off;  // per group: int64, record and step offsets
+  {
+    int64_t n64 = 0, nrec = 0, nst = 0;
+    int gi = 0;
+    for (auto& gk : groups) {
+      const int64_t nwu = launches[gi++].second.second;
+      q_off.push_back({n64, nrec, nst});
+      if (!quad_group(c, gk.first.first, gk.first.second)) continue;
+      int64_t kept = 0;
+      for (int r : gk.second) {  // a request's steps sit where its products do
+        rd[r].qbase = kept;
+        kept += ht[r].n_kept;
+      }
+      n64 += 4 * nwu + 2;
+      nrec += nwu;
+      nst += kept;
+    }
+    if (n64 > 0) {
+      ALLOC(q_i64, n64 * 8, "quad plan");
+      ALLOC(q_rec, std::max<int64_t>(nrec, 1) * sizeof(QuadUnit), "quad records");
+      ALLOC(q_steps, std::max<int64_t>(nst, 1) * 16, "quad steps");
+      ALLOC(q_mask, std::max<int64_t>(nst, 1), "quad step children");
+    }
+  }
   // placement tables, the completed request table and C's pyramid jobs:
   // one copy, and the launches after it need no host copies (they may be
   // captured into one graph)
@@ -1364,12 +1408,52 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       soff += int64_t(kXcds) * kx + 1;
       ++gi;
       if (nwu == 0) continue;
+      if (quad_group(c, gk.first.first, gk.first.second)) {
+        const auto& qo = q_off[gi - 1];
+        int64_t* flag = P<int64_t>(q_i64) + qo[0];
+        int64_t* qpos = flag + nwu;        // nwu + 1
+        int64_t* qcost = qpos + nwu + 1;   // nwu (zero beyond the last quad)
+        int64_t* qpre = qcost + nwu;       // nwu + 1
+        QuadUnit* qu = P<QuadUnit>(q_rec) + qo[1];
+        int4* steps = P<int4>(q_steps) + qo[2];
+        uint8_t* smask = P<uint8_t>(q_mask) + qo[2];
+        const WorkUnit* wu = P<WorkUnit>(wus) + u0;
+        {
+          TimedScope ts(c, kTPrune);
+          SPAMM_HIP(c, launch_quad_mark(c->stream, wu, nwu, flag));
+          SPAMM_HIP(c, launch_scan_i64(c->stream, flag, qpos, nwu, sscr->ptr(), sscr->bytes));
+          SPAMM_HIP(c, launch_zero_i32(c->stream, reinterpret_cast<int32_t*>(qcost), 2 * nwu));
+          SPAMM_HIP(c, launch_quad_plan(c->stream, reqd, wu, nwu, flag, qpos, qu, qcost, steps, smask));
+          SPAMM_HIP(c, launch_scan_i64(c->stream, qcost, qpre, nwu, sscr->ptr(), sscr->bytes));
+          SPAMM_HIP(c, launch_wg_ranges(c->stream, qpre, nwu, kXcds * kx, stg));
+        }
+        GemmArgs ga{};
+        ga.wu = wu;
+        ga.start = stg;
+        ga.reqs = reqd;
+        ga.base = c->arena.base();
+        ga.wn = P<double>(wn) + u0;
+        ga.wt = P<double>(wt) + u0;
+        ga.kx = kx;
+        ga.interleave = 0;
+        ga.qu = qu;
+        ga.steps = steps;
+        ga.smask = smask;
+        ga.nq = qpos + nwu;
+        TimedScope ts(c, kTGemm);
+        if (c->timing) {
+          for (int r : gk.second)
+            c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
+        }
+        SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, c->gemm_tile, ga));
+        continue;
+      }
       {
         TimedScope ts(c, kTPrune);
         SPAMM_HIP(c, launch_scan_i64(c->stream, P<int64_t>(costs) + u0, pre, nwu, sscr->ptr(), sscr->bytes));
         SPAMM_HIP(c, launch_wg_ranges(c->stream, pre, nwu, kXcds * kx, stg));
       }
-      GemmArgs ga;
+      GemmArgs ga{};
       ga.wu = P<WorkUnit>(wus) + u0;
       ga.start = stg;
       ga.reqs = reqd;

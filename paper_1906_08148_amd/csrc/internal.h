@@ -147,6 +147,7 @@ struct Ctx {
                              // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
   int validate = 0;    // measure every lower-precision product against an FP64 twin
+  int gemm_quad = 0;   // leaf-64 products in quads of sibling C leaves (k_gemm_quad)
   hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
@@ -264,6 +265,8 @@ struct ReqDev {
   int32_t sym;            // symmetric square: C leaves below the diagonal are mirrored
   const int32_t* asym;    // symmetric square: nonzero when the operand's (or D's) null
                           // map is not symmetric (every C leaf is then formed)
+  int32_t* pk;            // k of every kept pair (nullptr: not needed), beside `pairs`
+  int64_t qbase;          // quads: the request's first step in its group's step array
 };
 
 // One truncation inside a batch (leaf-block truncation with budget tau^2).
@@ -311,6 +314,19 @@ constexpr int kUnitTileShift = 28;
 constexpr int32_t kUnitMorton = (int32_t(1) << kUnitTileShift) - 1;
 __host__ __device__ inline int unit_tile(int32_t cflags) { return (cflags >> kUnitTileShift) & 3; }
 
+// A quad: the non-null C leaves of one parent node of one request (up to
+// four siblings, consecutive work units), run by one workgroup with one wave
+// per child over the merged k order of the children's products, so that an
+// A leaf serves both children of its row and a B leaf both of its column.
+struct QuadUnit {
+  int64_t sp;      // first merged step (index into the step arrays)
+  int32_t ns;      // merged steps
+  int32_t u0;      // first work unit of the quad (launch-group relative)
+  int32_t cmask;   // bit c: child c (2 * row half + column half) is present
+  int32_t req;     // request
+};
+static_assert(sizeof(QuadUnit) == 24, "a quad record is three 8-byte words");
+
 // Arguments of one GEMM launch: the work units of one (precision, leaf size)
 // group in placement order, split into contiguous ranges of equal cost, one
 // per workgroup.
@@ -324,6 +340,13 @@ struct GemmArgs {
   int32_t kx;            // workgroups per XCD (the grid is 8 * kx)
   int32_t interleave;    // c > 0: an XCD's units [start[x*kx], start[(x+1)*kx]) dealt round-robin over its
                          // workgroups in chunks of c; 0: workgroup rank r takes [start[r], start[r+1])
+  // quad launches: the quads, and per merged step the A leaves of the two
+  // row halves and the B leaves of the two column halves (-1: not needed)
+  // and the children that take part (bit c)
+  const QuadUnit* qu;
+  const int4* steps;
+  const uint8_t* smask;
+  const int64_t* nq;     // number of quads (device)
 };
 
 // Per-request totals read back after the counting pass.
@@ -429,6 +452,15 @@ hipError_t launch_wg_ranges(hipStream_t s, const int64_t* prefix, int64_t nwu, i
 // variant 0: 32 x 32 MFMA tiles for FP32 / BF16 where a wave's tile allows
 // it; variant 1: 16 x 16 tiles
 hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmArgs& a);
+// Quads of 64-leaves (see QuadUnit): the quad kernel, its occupancy, and the
+// plan: quad starts, then per quad its record, merged steps and cost
+// (steps + 1, by quad index).
+bool gemm_quad_supported(int prec, int bs);
+int gemm_quad_max_groups(int prec, int variant, int n_cu);
+hipError_t launch_gemm_quad(hipStream_t s, int prec, int variant, const GemmArgs& a);
+hipError_t launch_quad_mark(hipStream_t s, const WorkUnit* wu, int64_t nwu, int64_t* flag);
+hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
+                            const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask);
 int gemm_max_groups(int prec, int bs, int variant, int n_cu);  // resident workgroups of the kernel
 bool gemm_supported(int prec, int bs);
 int gemm_unit_tiles(int bs);  // work units per C leaf (4 for 256 leaves, else 1)

@@ -660,6 +660,362 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V
   }
 }
 
+// ---------------------------------------------------------------- quads
+
+// A quad (four sibling 64-leaves of C, see k_quad.hip) runs on the 128-tile
+// configuration: wave (r, c) of the 2 x 2 grid owns child 2r + c, the A
+// panel stacks the A leaves of the two row halves and the B panel puts the B
+// leaves of the two column halves side by side, so each staged leaf serves
+// both children of its row (column).  A merged step is one k: the waves of
+// the children that keep it multiply, the others wait at the barriers.  Each
+// child's sum runs over its own products k ascending, in the same panels and
+// MFMA order as a quad with only that child.
+
+// Scalar copy of one quad record.
+struct QuadS {
+  int64_t sp;
+  int32_t ns, u0, cmask, req;
+};
+
+__device__ __forceinline__ QuadS quad_of(const i32x2r (*ring)[64 * 3], int blk0, int64_t rel) {
+  const int b = (blk0 + (rel >= 64 ? 1 : 0)) & 1;
+  const int r = int(rel & 63);
+  const i32x2r v0 = ring[b][3 * r], v1 = ring[b][3 * r + 1], v2 = ring[b][3 * r + 2];
+  QuadS q;
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(v0[0]));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(v0[1]));
+  q.sp = int64_t((uint64_t(hi) << 32) | lo);
+  q.ns = __builtin_amdgcn_readfirstlane(v1[0]);
+  q.u0 = __builtin_amdgcn_readfirstlane(v1[1]);
+  q.cmask = __builtin_amdgcn_readfirstlane(v2[0]);
+  q.req = __builtin_amdgcn_readfirstlane(v2[1]);
+  return q;
+}
+
+// Operand leaves and children of 64 consecutive steps, one step per lane.
+struct Win4 {
+  int32_t a0, a1, b0, b1, m;
+};
+
+__device__ __forceinline__ Win4 load_win4(const GemmArgs& ga, const QuadS& q, int w, bool valid) {
+  Win4 x;
+  x.a0 = x.a1 = x.b0 = x.b1 = -1;
+  x.m = 0;
+  const int i = w * 64 + (threadIdx.x & 63);
+  if (valid && i < q.ns) {
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 v = *as_global(reinterpret_cast<const i32x4*>(ga.steps) + (q.sp + i));
+    x.a0 = v[0];
+    x.a1 = v[1];
+    x.b0 = v[2];
+    x.b1 = v[3];
+    x.m = int32_t(*as_global(ga.smask + (q.sp + i)));
+  }
+  return x;
+}
+
+// The operand leaves of step l of a window (wave-uniform).
+struct Step4 {
+  int32_t a0, a1, b0, b1, m;
+};
+
+__device__ __forceinline__ Step4 step_at(const Win4& w, int l) {
+  Step4 s;
+  s.a0 = __builtin_amdgcn_readlane(w.a0, l);
+  s.a1 = __builtin_amdgcn_readlane(w.a1, l);
+  s.b0 = __builtin_amdgcn_readlane(w.b0, l);
+  s.b1 = __builtin_amdgcn_readlane(w.b1, l);
+  s.m = __builtin_amdgcn_readlane(w.m, l);
+  return s;
+}
+
+// k-panel `sub` of a step into registers: rows of the A panel below 64 come
+// from the row-half-0 leaf, the others from the row-half-1 leaf; columns of
+// the B panel likewise by column half.  Leaves no child of the step needs
+// (-1) are not loaded.
+template <int P, int V>
+__device__ __forceinline__ void load_panel_quad(Panel<P, 128, V>& r, const char* __restrict__ base, const Step4& st,
+                                                int sub, int tid) {
+  using Cf = GemmCfg<P, 128, V>;
+  constexpr int64_t LEAF = int64_t(64) * 64 * (Cf::kBf ? 2 * Cf::ES : Cf::ES);
+  const int32_t sa0 = st.a0, sa1 = st.a1, sb0 = st.b0, sb1 = st.b1;  // values, not a select of addresses
+#pragma unroll
+  for (int t = 0; t < Cf::A_VECS; ++t) {
+    const int v = tid + t * Cf::NT;
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    const int h = v / Cf::PV, vv = v % Cf::PV;
+    const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+    const int32_t leaf = row < 64 ? sa0 : sa1;
+    if (leaf < 0) continue;
+    const int64_t e = h * 64 * 64 + (row & 63) * 64 + sub * Cf::KP + cv * Cf::VN;
+    const auto L = as_global(base + int64_t(leaf) * LEAF);
+    r.a[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(L + e * Cf::ES);
+  }
+#pragma unroll
+  for (int t = 0; t < Cf::B_VECS; ++t) {
+    const int v = tid + t * Cf::NT;
+    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+    int32_t leaf;
+    int64_t e;
+    if constexpr (Cf::kBf) {  // transposed copy: row = B column, k contiguous
+      const int h = v / Cf::PV, vv = v % Cf::PV;
+      const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
+      leaf = row < 64 ? sb0 : sb1;
+      e = h * 64 * 64 + (row & 63) * 64 + sub * Cf::KP + cv * Cf::VN;
+    } else {
+      const int kr = v / (128 / Cf::VN), col = (v % (128 / Cf::VN)) * Cf::VN;
+      leaf = col < 64 ? sb0 : sb1;
+      e = (sub * Cf::KP + kr) * 64 + (col & 63);
+    }
+    if (leaf < 0) continue;
+    const auto L = as_global(base + int64_t(leaf) * LEAF);
+    r.b[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(L + e * Cf::ES);
+  }
+}
+
+// Every present child's C leaf from its wave's accumulators: C (optionally
+// alpha * AB + beta * D), its FP64 squared norm and, on a diagonal leaf, its
+// diagonal sum, for that child's work unit.
+template <int P, int V>
+__device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q, AccTiles<P, 128, V>& acc,
+                                              int lane, int child, int li, int g) {
+  using Cf = GemmCfg<P, 128, V>;
+  using Out = typename Cf::Out;
+  if (((q.cmask >> child) & 1) == 0) return;
+  const int64_t u = int64_t(q.u0) + __builtin_popcount(uint32_t(q.cmask) & ((1u << child) - 1u));
+  const WorkUnit W = ga.wu[u];
+  const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(W.cidx) * 64 * 64 * sizeof(Out)));
+  const uint32_t cm = uint32_t(W.cflags & kUnitMorton);
+  const bool has_ep = (W.cflags & kUnitEp) != 0;
+  Out alpha = Out(1), beta = Out(0);
+  const Out* Dl = nullptr;
+  if (has_ep) {
+    const ReqDev* R = ga.reqs + W.req;
+    alpha = Out(R->alpha);
+    beta = Out(R->beta);
+    if (R->Dslot != nullptr) {
+      const int32_t ds = R->Dslot[cm];
+      if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * 64 * 64;
+    }
+  }
+  uint32_t ci, cj;
+  demorton(cm, ci, cj);
+  double nsq = 0.0, tr = 0.0;
+#pragma unroll
+  for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+    for (int b = 0; b < Cf::TN; ++b)
+#pragma unroll
+      for (int v = 0; v < Cf::AE; ++v) {
+        const int row = a * Cf::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
+        const int col = b * Cf::MT + li;
+        Out val = Out(acc[a][b][v]);
+        if (has_ep) {
+          const Out prod = alpha * val;
+          const Out dv = Dl ? beta * as_global(Dl)[row * 64 + col] : Out(0);
+          val = prod + dv;
+        }
+        Cl[row * 64 + col] = val;
+        const double dval = double(val);
+        const double sq = dval * dval;
+        nsq += sq;
+        if (row == col) tr += dval;
+      }
+  nsq = wave_sum_f64(nsq);
+  tr = wave_sum_f64(tr);
+  if (lane == 0) {
+    as_global(ga.wn)[u] = nsq;
+    if (ci == cj) as_global(ga.wt)[u] = tr;
+  }
+}
+
+template <int P, int V>
+__global__ void __launch_bounds__(256, 1) k_gemm_quad(const GemmArgs ga) {
+  using Cf = GemmCfg<P, 128, V>;
+  constexpr int NPANEL = 64 / Cf::KP;  // k-panels of one 64-leaf product
+  __shared__ __attribute__((aligned(16))) char smem[Cf::PANEL_LDS];
+  char* const As = smem;
+  char* const Bs = smem + Cf::A_LDS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave / Cf::WN, wc = wave % Cf::WN;
+  const int child = 2 * wr + wc;  // the C leaf this wave owns in every quad
+  const int row0 = wr * Cf::TILE_M, col0 = wc * Cf::TILE_N;
+  const int li = lane % Cf::MT, g = lane / Cf::MT;
+  const char* const base = ga.base;
+
+  // this workgroup's contiguous range of quads (the last range is cut at
+  // the number of quads, known on the device only)
+  const int xcd = int(blockIdx.x % kXcds), j = int(blockIdx.x / kXcds);
+  const int rank = xcd * ga.kx + j;
+  const int64_t nq = *ga.nq;
+  Visits vs;
+  vs.ubase = ga.start[rank];
+  vs.cstride = 0;
+  vs.chunk = int64_t(1) << 62;
+  vs.n = min(ga.start[rank + 1], nq) - vs.ubase;
+  const int64_t u1 = vs.n;
+  if (u1 <= 0) return;
+
+  __shared__ i32x2r ring[2][64 * 3];
+  const WorkUnit* recs = reinterpret_cast<const WorkUnit*>(ga.qu);
+  int64_t rb = 0;
+  int blk0 = 0;
+  stage_recs(ring, 0, recs, rb, vs, tid, Cf::NT);
+  stage_recs(ring, 1, recs, rb + 64, vs, tid, Cf::NT);
+  __syncthreads();
+
+  // W0: the window of the current step; W1: the window after it (the
+  // quad's next, or the next quad's first); (pu, pw) is W1's position
+  int64_t cu = 0;
+  QuadS U = quad_of(ring, blk0, 0);
+  Win4 W0 = load_win4(ga, U, 0, true);
+  int64_t pu = 0;
+  int pw = 0;
+  QuadS PU = U;
+  auto next_pos = [&]() {
+    if ((pw + 1) * 64 < PU.ns) {
+      ++pw;
+    } else {
+      ++pu;
+      pw = 0;
+      if (pu < u1) PU = quad_of(ring, blk0, pu - rb);
+    }
+  };
+  next_pos();
+  Win4 W1 = load_win4(ga, PU, pw, pu < u1);
+
+  Panel<P, 128, V> pr;
+  if (U.ns > 0) load_panel_quad<P, V>(pr, base, step_at(W0, 0), 0, tid);
+
+  for (;;) {
+    const bool has_next = cu + 1 < u1;
+    int32_t next_ns = 0;
+    if (has_next) next_ns = quad_of(ring, blk0, cu + 1 - rb).ns;
+
+    Acc<P, 128, V> acc[Cf::TM][Cf::TN];
+    Acc<P, 128, V> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
+#pragma unroll
+    for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, 128, V>{};
+    if constexpr (Cf::TWO_LEVEL) {
+#pragma unroll
+      for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < Cf::TN; ++b) part[a][b] = Acc<P, 128, V>{};
+    }
+
+    for (int p = 0; p < U.ns; ++p) {
+      const bool mine = (__builtin_amdgcn_readlane(W0.m, p & 63) >> child) & 1;
+      for (int sub = 0; sub < NPANEL; ++sub) {
+        __builtin_amdgcn_s_setprio(1);
+        __syncthreads();  // every wave is done with the previous panel
+        store_panel<P, 128, V>(pr, As, Bs, tid);
+        __syncthreads();
+        // next panel: same step, next step (this or the next window), or
+        // the first step of the next quad (the next window)
+        if (sub + 1 < NPANEL) {
+          load_panel_quad<P, V>(pr, base, step_at(W0, p & 63), sub + 1, tid);
+        } else if (p + 1 < U.ns) {
+          const int l = (p + 1) & 63;
+          load_panel_quad<P, V>(pr, base, l == 0 ? step_at(W1, 0) : step_at(W0, l), 0, tid);
+        } else if (next_ns > 0) {
+          load_panel_quad<P, V>(pr, base, step_at(W1, 0), 0, tid);
+        }
+        __builtin_amdgcn_s_setprio(2);
+        if (mine) {
+          if constexpr (Cf::TWO_LEVEL) {
+            compute_panel<P, 128, V>(part, As, Bs, row0, col0, li, g);
+            if (sub + 1 == NPANEL) {  // the product's sum joins the leaf's total
+#pragma unroll
+              for (int a = 0; a < Cf::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < Cf::TN; ++b) {
+                  acc[a][b] += part[a][b];
+                  part[a][b] = Acc<P, 128, V>{};
+                }
+            }
+          } else {
+            compute_panel<P, 128, V>(acc, As, Bs, row0, col0, li, g);
+          }
+        }
+        __builtin_amdgcn_s_setprio(0);
+      }
+      if (((p + 1) & 63) == 0 && p + 1 < U.ns) {  // into the quad's next window
+        W0 = W1;
+        next_pos();
+        W1 = load_win4(ga, PU, pw, pu < u1);
+      }
+    }
+
+    epilogue_quad<P, V>(ga, U, acc, lane, child, li, g);
+    if (!has_next) break;
+
+    const int32_t prev_ns = U.ns;
+    ++cu;
+    if (cu - rb == 64) {
+      // quads below cu are done: their block takes quads [rb + 128, rb + 192)
+      // (quads without steps pass no barrier, hence the two here)
+      __syncthreads();
+      rb += 64;
+      blk0 ^= 1;
+      stage_recs(ring, blk0 ^ 1, recs, rb + 64, vs, tid, Cf::NT);
+      __syncthreads();
+    }
+    U = quad_of(ring, blk0, cu - rb);
+    W0 = W1;
+    next_pos();
+    W1 = load_win4(ga, PU, pw, pu < u1);
+    // the first panel of a quad after a quad without steps was not prefetched
+    if (prev_ns == 0 && U.ns > 0) load_panel_quad<P, V>(pr, base, step_at(W0, 0), 0, tid);
+  }
+}
+
+template <int P, int V>
+static int max_groups_quad(int n_cu) {
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, 256, 0) != hipSuccess || v < 1) v = 1;
+    return v;
+  }();
+  return per_cu * n_cu;
+}
+
+bool gemm_quad_supported(int prec, int bs) { return bs == 64 && prec >= SPAMM_F64 && prec <= SPAMM_BF16X3; }
+
+template <typename F>
+static auto dispatch_quad(int prec, int variant, F&& f) {
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  switch (prec) {
+    case SPAMM_F64: return f(std::integral_constant<int, SPAMM_F64>{}, I0{});
+    case SPAMM_F32:
+      return variant ? f(std::integral_constant<int, SPAMM_F32>{}, I1{}) : f(std::integral_constant<int, SPAMM_F32>{}, I0{});
+    case SPAMM_BF16:
+      return variant ? f(std::integral_constant<int, SPAMM_BF16>{}, I1{}) : f(std::integral_constant<int, SPAMM_BF16>{}, I0{});
+    default:
+      return variant ? f(std::integral_constant<int, SPAMM_BF16X3>{}, I1{})
+                     : f(std::integral_constant<int, SPAMM_BF16X3>{}, I0{});
+  }
+}
+
+int gemm_quad_max_groups(int prec, int variant, int n_cu) {
+  return dispatch_quad(prec, variant, [&](auto pc, auto vc) -> int {
+    return max_groups_quad<decltype(pc)::value, decltype(vc)::value>(n_cu);
+  });
+}
+
+hipError_t launch_gemm_quad(hipStream_t s, int prec, int variant, const GemmArgs& a) {
+  return dispatch_quad(prec, variant, [&](auto pc, auto vc) -> hipError_t {
+    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)), dim3(256),
+                       0, s, a);
+    return hipGetLastError();
+  });
+}
+
 // ---------------------------------------------------------------- launch
 
 template <int P, int BS, int V, int LS>

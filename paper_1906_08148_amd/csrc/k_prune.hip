@@ -361,6 +361,7 @@ struct FillLds {
   int64_t end[kWave];
   double tau[kWave];
   int2* out[kWave];
+  int32_t* pk[kWave];  // k of each pair, or nullptr
   int32_t aoff[kWave];
   int32_t boff[kWave];
 };
@@ -448,6 +449,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
     const ReqDev& R = reqs[x.r];
     L.tau[lane] = R.use_norms ? R.tau : -1.0;
     L.out[lane] = R.pairs;
+    L.pk[lane] = R.pk;
     L.aoff[lane] = int32_t(R.aoff);
     L.boff[lane] = int32_t(R.boff);
   }
@@ -455,7 +457,7 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
   int64_t run = 0;  // kept elements before the current row of 64
   for (int wb = 0; wb < T; wb += kPW) {
     double a[kPU], bv[kPU];
-    int32_t sa[kPU], sb[kPU];
+    int32_t sa[kPU], sb[kPU], kk[kPU];
     int own[kPU];
 #pragma unroll
     for (int u = 0; u < kPU; ++u) {  // norms and slots of the window in flight together
@@ -463,10 +465,12 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
       a[u] = bv[u] = -1.0;
       sa[u] = sb[u] = 0;
       own[u] = 0;
+      kk[u] = 0;
       if (t < T) {
         const int b = seg_owner(L.sst, t);
         const int k = L.lo[b] + (t - L.sst[b]);
         own[u] = b;
+        kk[u] = k;
         a[u] = as_global(L.sa[b])[k];
         bv[u] = as_global(L.sb[b])[k];
         sa[u] = as_global(L.la[b])[k];
@@ -486,7 +490,10 @@ __global__ void __launch_bounds__(kPWaves * kWave) k_prune_fill(const ReqDev* __
       const uint64_t mask = ballot64(keep);
       if (keep) {
         const int64_t at = L.delta[b] + run + popc64(mask & lanemask_lt());
-        if (at >= L.beg[b] && at < L.end[b]) L.out[b][at] = make_int2(L.aoff[b] + sa[u], L.boff[b] + sb[u]);
+        if (at >= L.beg[b] && at < L.end[b]) {
+          L.out[b][at] = make_int2(L.aoff[b] + sa[u], L.boff[b] + sb[u]);
+          if (L.pk[b]) L.pk[b][at] = kk[u];
+        }
       }
       run += popc64(mask);
     }

@@ -369,12 +369,13 @@ class Context:
         return out
 
     OPTIONS = {"gemm_tile": 0, "placement": 1, "graph": 2, "unit_order": 3,  # unit_order: chunk size (0: contiguous ranges)
-               "validate": 4}
+               "validate": 4, "gemm_quad": 5}
 
     def set_option(self, name: str, value: int):
         """validate (1: measure ||C - C_FP64||_F into stats["val_err"]),
         gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
-        slices, 1: request-major), graph (1: one captured graph per batch)."""
+        slices, 1: request-major), graph (1: one captured graph per batch),
+        gemm_quad (1: leaf-64 products in quads of sibling C leaves)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 
     def get_option(self, name: str) -> int:

@@ -8,7 +8,7 @@ passes.  A build that let a VALU move overwrite the A operand 7 issue slots
 after an 8-pass MFMA returned wrong products, so every group of BF16 MFMAs
 ends with 16 wait states.  This test compiles the GEMM source for gfx950
 (device assembly of this repository's own code, on the CPU) and checks, for
-every BF16 and split-BF16 kernel, that no VALU instruction writes a VGPR
+every BF16 and split-BF16 kernel (one-leaf and quad), that no VALU instruction writes a VGPR
 read as A or B by an MFMA fewer than 16 wait states after that MFMA issued.
 (LDS and memory loads write their VGPRs only when the data returns, after
 the LDS or memory latency: the split-BF16 leaf-32 kernel issues an LDS read
@@ -46,7 +46,7 @@ def asm(tmp_path_factory):
 
 
 def _kernels(text, prec):
-    for m in re.finditer(rf"^(_ZN5spamm6k_gemmILi{prec}E\w+):", text, re.M):
+    for m in re.finditer(rf"^(_ZN5spamm(?:6k_gemm|11k_gemm_quad)ILi{prec}E\w+):", text, re.M):
         end = text.index(".Lfunc_end", m.end())
         yield m.group(1), [l.strip() for l in text[m.end():end].splitlines()
                            if l.strip() and not l.strip().startswith((";", ".", "/"))]
