@@ -47,9 +47,20 @@ N3D, LEAF3D, ALPHA3D, TAU3D = 32768, 64, 1.0, 1e-6
 SIGMA_REL = 1e-5  # fixed error: ||A A - C||_F <= SIGMA_REL ||A||_F ||B||_F
 TAU_GRID = tuple(10.0 ** -k for k in range(0, 9))  # 1 ... 1e-8, decades
 GEMM_SOURCE = os.path.join(ROOT, "paper_1906_08148_amd", "csrc", "k_gemm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gemm_f64_leaf64_decay3d_n32768_hybrid_traffic.json")
+TRAFFIC_GLOB = os.path.join(ROOT, "profiles", "*_decay3d_n32768_hybrid_traffic.json")
 PREC_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16x3"}
 PEAKS = {0: FP64_MFMA_PEAK_TFLOPS, 1: FP32_MFMA_PEAK_TFLOPS, 2: BF16_MFMA_PEAK_TFLOPS, 3: BF16_MFMA_PEAK_TFLOPS}
+
+
+CTX_OPTIONS = {}  # options every context of the run is given (--gemm-tile, --gemm-quad)
+
+
+def new_context(arena_bytes):
+    from paper_1906_08148_amd import spamm
+    ctx = spamm.Context(arena_bytes=arena_bytes)
+    for k, v in CTX_OPTIONS.items():
+        ctx.set_option(k, v)
+    return ctx
 
 
 def log(msg):
@@ -251,6 +262,39 @@ def config3_precisions(ctx, dA, steps, C64):
     return out
 
 
+def quad_comparison(ctx, dA, reps=2):
+    """The 3D multiply (norms precomputed) in every precision on the two leaf
+    GEMMs: quads of sibling C leaves (the default) and one C leaf per work
+    unit; leaf-GEMM time per launch from the library's HIP events."""
+    import torch
+    from paper_1906_08148_amd import spamm
+    M = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32 | spamm.STORE_BF16)
+    default = ctx.get_option("gemm_quad")
+    out = {}
+    for prec in (spamm.F64, spamm.F32, spamm.BF16X3, spamm.BF16):
+        row = {}
+        for quad in (0, 1):
+            ctx.set_option("gemm_quad", quad)
+            ctx.multiply(M, M, TAU3D, mode=spamm.HYBRID, prec=prec, stats=False).C.release()
+            torch.cuda.synchronize()
+            ctx.timing(enable=True, reset=True)
+            for _ in range(reps):
+                ctx.multiply(M, M, TAU3D, mode=spamm.HYBRID, prec=prec, stats=False).C.release()
+            torch.cuda.synchronize()
+            tm = ctx.timing(enable=False, reset=True)
+            g_ms = tm["gemm_ms"] / max(tm["gemm_launches"], 1)
+            g_fl = tm["gemm_flops"] / max(tm["gemm_launches"], 1)
+            row["quad" if quad else "one_leaf"] = {"gemm_ms": round(g_ms, 3),
+                                                   "gemm_tflops": round(g_fl / (g_ms * 1e-3) / 1e12, 2),
+                                                   "plan_ms": round(tm["prune_ms"] / reps, 3)}
+        row["gemm_speedup"] = round(row["one_leaf"]["gemm_ms"] / row["quad"]["gemm_ms"], 3)
+        out[PREC_NAMES[prec]] = row
+    ctx.set_option("gemm_quad", default)
+    M.release()
+    torch.cuda.empty_cache()
+    return out
+
+
 def fixed_error_3d(ctx, dA, reps=3):
     """Sec. 5.3's comparison at a target accuracy: for each precision, the
     largest tau on the decade grid 1 ... 1e-8 whose Hybrid product has
@@ -383,7 +427,7 @@ def paper_workloads():
     dA = torch.from_numpy(A).cuda()
     del A
     exact = dA @ dA
-    ctx = spamm.Context(arena_bytes=80 << 30)
+    ctx = new_context(80 << 30)
     modes = {"truncmul": spamm.TRUNCMUL, "spamm": spamm.SPAMM, "hybrid": spamm.HYBRID}
     model = {"workload": f"1D decay n={n}, alpha {alpha}, A=B, FP64, sigma {sigma}",
              "generate_s": round(gen_s, 1), "rows": []}
@@ -468,7 +512,7 @@ def purification(steps, mode=None):
     import synth
     from paper_1906_08148_amd import purify, spamm
     A = synth.DecaySpec("3d", N3D, ALPHA3D, seed=SEED).dense()
-    ctx = spamm.Context(arena_bytes=96 << 30)
+    ctx = new_context(96 << 30)
     dA = torch.from_numpy(A).cuda()
     del A
     X = ctx.build(dA, LEAF3D, stores=spamm.STORE_F64 | spamm.STORE_F32)
@@ -513,7 +557,7 @@ def serving(n_requests, n_max, rates=(0.5, 1.0, 2.0, 4.0)):
         inputs = dict(zip(mats, ex.map(lambda m: serve.make_input(m, 64), mats)))
     gen_s = time.perf_counter() - t0
     lane_bytes = 60 << 30
-    srv = serve.Server(lanes=1, arena_bytes_per_lane=lane_bytes, max_batch=1, inputs=inputs)
+    srv = serve.Server(lanes=1, arena_bytes_per_lane=lane_bytes, max_batch=1, inputs=inputs, options=CTX_OPTIONS)
     t0 = time.perf_counter()
     alone = serve.run_stream(srv.sched, pool, rate=0)
     t_alone = time.perf_counter() - t0
@@ -528,7 +572,8 @@ def serving(n_requests, n_max, rates=(0.5, 1.0, 2.0, 4.0)):
            "kinds": [f"{r.mat.kind}:{r.mat.n}" for r in pool], "runs": {}}
     for x, graph in [(x, False) for x in rates] + [(2.0, True)]:
         log(f"bench: serving at {x} mu{' (graph)' if graph else ''}")
-        srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs, graph=graph)
+        srv = serve.Server(lanes=2, arena_bytes_per_lane=lane_bytes, max_batch=16, inputs=inputs, graph=graph,
+                           options=CTX_OPTIONS)
         res = serve.run_stream(srv.sched, pool, rate=x * mu, seed=11)
         srv.close()
         log_ = list(srv.sched.log)
@@ -596,16 +641,18 @@ def cpu_baseline_3d(sample_n=8192, one_thread=True):
 
 
 def traffic_for(kernel_name):
-    """HBM bytes per GEMM launch from the committed rocprofv3 counter summary,
-    only when it was taken on the current kernel source and this kernel."""
-    try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except Exception:
-        return None
+    """HBM bytes per GEMM launch from the committed rocprofv3 counter summary
+    of this kernel, only when it was taken on the current kernel source."""
+    import glob
     src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != src or rec.get("kernel") != kernel_name:
-        return None
-    return rec.get("bytes_per_launch")
+    for f in sorted(glob.glob(TRAFFIC_GLOB)):
+        try:
+            rec = json.load(open(f))
+        except Exception:
+            continue
+        if rec.get("kernel") == kernel_name and rec.get("kernel_source_sha256") == src:
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def batch_1d(ctx, steps, warmup):
@@ -644,6 +691,9 @@ def main():
                     help="precision of the timed steps (profiling the other GEMMs)")
     ap.add_argument("--graph", action="store_true", help="launch each batch's post-sizing kernels as one HIP graph")
     ap.add_argument("--gemm-tile", type=int, default=None, help="MFMA tile variant (0: 32x32, 1: 16x16)")
+    ap.add_argument("--gemm-quad", type=int, default=None, choices=(0, 1),
+                    help="leaf-64 products in quads of sibling C leaves (1, the library default) or one C leaf "
+                         "per work unit (0)")
     ap.add_argument("--steps-1d", type=int, default=20)
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D batch section")
     ap.add_argument("--no-purify", action="store_true", help="skip the purification section")
@@ -666,6 +716,10 @@ def main():
     import synth
     from paper_1906_08148_amd import spamm
 
+    if args.gemm_tile is not None:
+        CTX_OPTIONS["gemm_tile"] = args.gemm_tile
+    if args.gemm_quad is not None:
+        CTX_OPTIONS["gemm_quad"] = args.gemm_quad
     if args.serving_only:
         print(json.dumps({"serving": serving(args.serve_requests, args.serve_nmax)}))
         return 0
@@ -676,11 +730,9 @@ def main():
     gen_s = time.perf_counter() - t0
     dA = torch.from_numpy(A).cuda()
     del A
-    ctx = spamm.Context(arena_bytes=64 << 30)
+    ctx = new_context(64 << 30)
     if args.graph:
         ctx.set_option("graph", 1)
-    if args.gemm_tile is not None:
-        ctx.set_option("gemm_tile", args.gemm_tile)
     if args.copy_calibration_mb:
         src = torch.ones(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -691,7 +743,11 @@ def main():
     log(f"bench: 3D hybrid {args.prec} steps")
     r = config3_steps(ctx, dA, prec, args.steps, args.warmup, keep_last=not args.skip_extras)
     tile = ctx.get_option("gemm_tile")
-    kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}, {LEAF3D}>"
+    quad = ctx.get_option("gemm_quad")
+    if quad:
+        kname = f"void spamm::k_gemm_quad<{prec}, {0 if prec == spamm.F64 else 1}>"
+    else:
+        kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}, {LEAF3D}>"
     st = r["stats"]
     out = {
         "metric": METRIC,
@@ -717,7 +773,9 @@ def main():
         "phases_ms_per_step": {k: round(r["tm"][k + "_ms"] / args.steps, 3)
                                for k in ("build", "trunc", "prune", "gemm", "pyramid")},
         "generate_s": round(gen_s, 1),
-        "roofline": {"kernel": f"k_gemm<{args.prec.upper()},{LEAF3D}> (persistent MFMA leaf GEMM)",
+        "roofline": {"kernel": (f"k_gemm_quad<{args.prec.upper()}> (quads of sibling 64-leaves, pipelined MFMA "
+                               f"leaf GEMM)" if quad else
+                               f"k_gemm<{args.prec.upper()},{LEAF3D}> (persistent MFMA leaf GEMM)"),
                      "bound": "mfma", "achieved": round(r["gemm_tflops"], 3), "peak": PEAKS[prec],
                      "unit": "TFLOP/s", "frac": round(r["gemm_tflops"] / PEAKS[prec], 4),
                      "traffic": traffic_for(kname), "flops_per_launch": r["gemm_flops"],
@@ -736,6 +794,8 @@ def main():
             out["symmetric"] = symmetric_3d(ctx, dA, C64)
         del C64
         torch.cuda.empty_cache()
+        log("bench: 3D quads vs one leaf per work unit")
+        out["quad_vs_one_leaf"] = quad_comparison(ctx, dA)
         log("bench: 3D fixed error")
         out["fixed_error"] = fixed_error_3d(ctx, dA)
         if not args.no_autotune:
@@ -743,7 +803,7 @@ def main():
         ctx.close()
         del dA
         torch.cuda.empty_cache()
-        ctx = spamm.Context(arena_bytes=16 << 30)
+        ctx = new_context(16 << 30)
         if not args.no_1d:
             log("bench: 1D batch")
             out["batch_1d"] = batch_1d(ctx, args.steps_1d, 5)

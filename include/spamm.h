@@ -220,15 +220,16 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       kept products (0 for FP64 products).  Needs the FP64
  *                       copy of A and B (EUNSUPPORTED otherwise); costs the
  *                       FP64 products and one synchronisation.
- *  SPAMM_OPT_GEMM_QUAD  0 (default): every C leaf of a leaf-64 product is
- *                       one work unit of the leaf GEMM; 1: the C leaves that
- *                       are children of one quadtree node (up to four) run in
- *                       one workgroup over the merged k order of their
+ *  SPAMM_OPT_GEMM_QUAD  1 (default): the C leaves of a leaf-64 product
+ *                       that are children of one quadtree node (up to four)
+ *                       run in one workgroup over the merged k order of their
  *                       products, so that every A and B leaf staged serves
  *                       both children of its row or column half (half the
- *                       operand reads when all four keep a k).  Each C leaf
- *                       still sums its own products k ascending.  Other leaf
- *                       sizes ignore it.
+ *                       operand reads when all four keep a k); each C leaf
+ *                       still sums its own products k ascending.  Quads take
+ *                       16 x 16 MFMA tiles whatever GEMM_TILE says.  0: every
+ *                       C leaf is one work unit of the one-leaf GEMM.  Other
+ *                       leaf sizes ignore the option.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
  * and GEMM_QUAD change the order of the sums inside one MFMA or one k-panel
  * (results stay within the precision's tolerance).  Errors: EINVAL (unknown

@@ -1308,7 +1308,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     for (auto& gk : groups) {
       const int64_t nwu = launches[gi++].second.second;
       const bool quad = quad_group(c, gk.first.first, gk.first.second);
-      const int64_t maxg = quad ? gemm_quad_max_groups(gk.first.first, c->gemm_tile, c->n_cu)
+      const int64_t maxg = quad ? gemm_quad_max_groups(gk.first.first, c->n_cu)
                                 : gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
       // quads: at least a quarter of the units
       const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, quad ? (nwu + 3) / 4 : nwu));
@@ -1445,7 +1445,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
           for (int r : gk.second)
             c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
         }
-        SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, c->gemm_tile, ga));
+        SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, ga));
         continue;
       }
       {

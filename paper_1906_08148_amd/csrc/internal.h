@@ -147,7 +147,7 @@ struct Ctx {
                              // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
   int validate = 0;    // measure every lower-precision product against an FP64 twin
-  int gemm_quad = 0;   // leaf-64 products in quads of sibling C leaves (k_gemm_quad)
+  int gemm_quad = 1;   // leaf-64 products in quads of sibling C leaves (k_gemm_quad)
   hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
@@ -456,8 +456,8 @@ hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmA
 // plan: quad starts, then per quad its record, merged steps and cost
 // (steps + 1, by quad index).
 bool gemm_quad_supported(int prec, int bs);
-int gemm_quad_max_groups(int prec, int variant, int n_cu);
-hipError_t launch_gemm_quad(hipStream_t s, int prec, int variant, const GemmArgs& a);
+int gemm_quad_max_groups(int prec, int n_cu);
+hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a);
 hipError_t launch_quad_mark(hipStream_t s, const WorkUnit* wu, int64_t nwu, int64_t* flag);
 hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
                             const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask);

@@ -662,34 +662,92 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V
 
 // ---------------------------------------------------------------- quads
 
-// A quad (four sibling 64-leaves of C, see k_quad.hip) runs on the 128-tile
-// configuration: wave (r, c) of the 2 x 2 grid owns child 2r + c, the A
-// panel stacks the A leaves of the two row halves and the B panel puts the B
-// leaves of the two column halves side by side, so each staged leaf serves
-// both children of its row (column).  A merged step is one k: the waves of
-// the children that keep it multiply, the others wait at the barriers.  Each
-// child's sum runs over its own products k ascending, in the same panels and
-// MFMA order as a quad with only that child.
+// A quad (four sibling 64-leaves of C, see k_quad.hip) runs on a 128 x 128
+// tile: the A panel stacks the A leaves of the two row halves and the B
+// panel puts the B leaves of the two column halves side by side, so each
+// staged leaf serves both children of its row (column).  Eight waves, two
+// per child: wave w owns columns 32 (w % 2) .. + 31 of child w / 2 (2 * row
+// half + column half), so two waves share each SIMD and one's MFMAs run
+// while the other waits.  A merged step is one k: the waves of the
+// children that keep it add the product to their C leaf, the others only
+// take part in the barriers.  Each child sums its own products k
+// ascending, in the same panels and MFMA order whatever its siblings keep.
+//
+// Panels move from memory to LDS by direct loads (global_load_lds, 16 bytes
+// per lane, no registers) into a ring of four stages, three panels ahead of
+// the one being multiplied: a panel's loads wait on the memory latency
+// while the three before it are multiplied.  Every panel is the same number
+// of load instructions per wave (a leaf no child of the step needs is
+// replaced by its partner's), so the wait for a panel is a fixed count of
+// later loads.  A stage is 16 KiB of A and 16 KiB of B.  A row of the A
+// part (and of transposed BF16 B) is the panel's k of one row, its 16-byte
+// chunks XOR-swizzled by row so that the operand reads of consecutive rows
+// fall on different banks; FP32 / FP64 B is k-major, one 64-column block
+// per B leaf, its columns swizzled by lane group.  Each load instruction
+// reads one leaf: a scalar leaf address plus a fixed per-lane offset.
 
-// Scalar copy of one quad record.
+template <int P, int V>
+struct QuadCfg {
+  using G = GemmCfg<P, 128, V>;
+  static constexpr bool kBf = G::kBf;
+  static constexpr int NH = G::NH, ES = G::ES, MT = G::MT, NG = G::NG, AE = G::AE;
+  static constexpr bool TWO_LEVEL = G::TWO_LEVEL;
+  static constexpr int NW = 8, NT = NW * 64;         // two waves per child
+  static constexpr int TILE_M = 64, TILE_N = 32;     // a wave's part of its child
+  static constexpr int TM = TILE_M / MT, TN = TILE_N / MT;
+  static constexpr int PART = 16384;                 // bytes of the A (or B) part of a stage
+  static constexpr int KP = PART / (128 * ES * NH);  // k per panel: 64 BF16, 32 BF16X3 / FP32, 16 FP64
+  static constexpr int NP = 64 / KP;                 // panels per 64-leaf product
+  static constexpr int KG = KP / NG;                 // k of one lane group per panel
+  static constexpr int RB = KP * ES;                 // bytes of an A row (or a transposed B row)
+  static constexpr int CH = RB / 16;                 // 16-byte chunks per row
+  static constexpr int VN = 16 / ES;                 // elements per chunk
+  static constexpr int STAGE = 2 * PART;
+  static constexpr int NSTAGE = 4;
+  // panels multiplied between two barriers: FP32 / FP64 take two (a longer
+  // run of MFMAs per barrier, the next two panels loading meanwhile), the
+  // BF16 forms one (three panels loading ahead)
+  static constexpr int GP = (P == SPAMM_F64 || P == SPAMM_F32) ? 2 : 1;
+  static constexpr int VPT = PART / 1024 / NW;       // 1 KiB load blocks of a part per wave
+  static constexpr int LOADS = 2 * VPT;              // load instructions per wave per panel
+  static constexpr int64_t LEAF = int64_t(64) * 64 * (kBf ? 2 * ES : ES);  // bytes of a stored 64-leaf
+  static_assert(CH >= 1 && CH <= 8 && 8 % CH == 0, "row chunks");
+  static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
+  static_assert(VPT * NW * 1024 == PART, "whole load blocks per part");
+  static_assert(MT == 16, "quads take 16 x 16 MFMA tiles");
+  static_assert(NP % GP == 0 && NSTAGE % GP == 0, "panel groups within a product");
+};
+
+template <int P, int V>
+using QAcc = Acc<P, 128, V>[QuadCfg<P, V>::TM][QuadCfg<P, V>::TN];
+
+// Physical chunk of logical chunk kc in row R of an A (or transposed B)
+// part: 8 consecutive rows take 8 different 16-byte bank groups.
+template <int CH>
+__device__ __forceinline__ int qswz(int R) {
+  return (R / (8 / CH)) % CH;
+}
+
+// Scalar copy of one quad record (global memory, the range's quad q).
 struct QuadS {
   int64_t sp;
   int32_t ns, u0, cmask, req;
 };
 
-__device__ __forceinline__ QuadS quad_of(const i32x2r (*ring)[64 * 3], int blk0, int64_t rel) {
-  const int b = (blk0 + (rel >= 64 ? 1 : 0)) & 1;
-  const int r = int(rel & 63);
-  const i32x2r v0 = ring[b][3 * r], v1 = ring[b][3 * r + 1], v2 = ring[b][3 * r + 2];
-  QuadS q;
-  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(v0[0]));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(v0[1]));
-  q.sp = int64_t((uint64_t(hi) << 32) | lo);
-  q.ns = __builtin_amdgcn_readfirstlane(v1[0]);
-  q.u0 = __builtin_amdgcn_readfirstlane(v1[1]);
-  q.cmask = __builtin_amdgcn_readfirstlane(v2[0]);
-  q.req = __builtin_amdgcn_readfirstlane(v2[1]);
-  return q;
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  return int64_t((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int32_t(uint64_t(v) >> 32)))) << 32) |
+                 uint32_t(__builtin_amdgcn_readfirstlane(int32_t(uint64_t(v) & 0xffffffffu))));
+}
+
+__device__ __forceinline__ QuadS quad_at(const GemmArgs& ga, int64_t q) {
+  const QuadUnit* p = ga.qu + q;
+  QuadS r;
+  r.sp = uniform64(p->sp);
+  r.ns = __builtin_amdgcn_readfirstlane(p->ns);
+  r.u0 = __builtin_amdgcn_readfirstlane(p->u0);
+  r.cmask = __builtin_amdgcn_readfirstlane(p->cmask);
+  r.req = __builtin_amdgcn_readfirstlane(p->req);
+  return r;
 }
 
 // Operand leaves and children of 64 consecutive steps, one step per lane.
@@ -697,280 +755,454 @@ struct Win4 {
   int32_t a0, a1, b0, b1, m;
 };
 
-__device__ __forceinline__ Win4 load_win4(const GemmArgs& ga, const QuadS& q, int w, bool valid) {
+__device__ __forceinline__ Win4 load_win4(const GemmArgs& ga, int64_t sp, int32_t ns, int w, bool valid) {
+  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
   Win4 x;
   x.a0 = x.a1 = x.b0 = x.b1 = -1;
   x.m = 0;
   const int i = w * 64 + (threadIdx.x & 63);
-  if (valid && i < q.ns) {
-    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-    const i32x4 v = *as_global(reinterpret_cast<const i32x4*>(ga.steps) + (q.sp + i));
+  if (valid && i < ns) {
+    const i32x4 v = *as_global(reinterpret_cast<const i32x4*>(ga.steps) + (sp + i));
     x.a0 = v[0];
     x.a1 = v[1];
     x.b0 = v[2];
     x.b1 = v[3];
-    x.m = int32_t(*as_global(ga.smask + (q.sp + i)));
+    x.m = int32_t(*as_global(ga.smask + (sp + i)));
   }
   return x;
 }
 
-// The operand leaves of step l of a window (wave-uniform).
-struct Step4 {
-  int32_t a0, a1, b0, b1, m;
+// Per-lane byte offsets (within a leaf, panel 0) of the wave's load blocks.
+template <int P, int V>
+struct QuadOffs {
+  uint32_t a[QuadCfg<P, V>::VPT], b[QuadCfg<P, V>::VPT];
 };
 
-__device__ __forceinline__ Step4 step_at(const Win4& w, int l) {
-  Step4 s;
-  s.a0 = __builtin_amdgcn_readlane(w.a0, l);
-  s.a1 = __builtin_amdgcn_readlane(w.a1, l);
-  s.b0 = __builtin_amdgcn_readlane(w.b0, l);
-  s.b1 = __builtin_amdgcn_readlane(w.b1, l);
-  s.m = __builtin_amdgcn_readlane(w.m, l);
-  return s;
+template <int P, int V>
+__device__ __forceinline__ QuadOffs<P, V> quad_offsets(int wave, int lane) {
+  using Q = QuadCfg<P, V>;
+  QuadOffs<P, V> o;
+#pragma unroll
+  for (int i = 0; i < Q::VPT; ++i) {
+    const int q = (i * Q::NW + wave) * 64 + lane;  // chunk of the part
+    {
+      const int R = q / Q::CH, phys = q % Q::CH;
+      const int h = R / 128, r = R % 128;
+      const int kc = phys ^ qswz<Q::CH>(R);
+      o.a[i] = uint32_t((h * 4096 + (r & 63) * 64 + kc * Q::VN) * Q::ES);
+    }
+    if constexpr (Q::kBf) {  // transposed copy: a row is a B column, k contiguous
+      const int R = q / Q::CH, phys = q % Q::CH;
+      const int h = R / 128, r = R % 128;
+      const int kc = phys ^ qswz<Q::CH>(R);
+      o.b[i] = uint32_t((h * 4096 + (r & 63) * 64 + kc * Q::VN) * Q::ES);
+    } else {  // k-major: one 64-column block per leaf, row kr of 64 columns
+      const int qh = q % (Q::KP * 64 / Q::VN);
+      const int kr = qh / (64 / Q::VN), pc = (qh % (64 / Q::VN)) * Q::VN;
+      const int col = pc ^ (((kr / Q::KG) * Q::MT) % 64);
+      o.b[i] = uint32_t((kr * 64 + col) * Q::ES);
+    }
+  }
+  return o;
 }
 
-// k-panel `sub` of a step into registers: rows of the A panel below 64 come
-// from the row-half-0 leaf, the others from the row-half-1 leaf; columns of
-// the B panel likewise by column half.  Leaves no child of the step needs
-// (-1) are not loaded.
+// Direct loads of k-panel `sub` of a step (leaves a0 / a1 of the A row
+// halves, b0 / b1 of the B column halves) into stage `st`.
 template <int P, int V>
-__device__ __forceinline__ void load_panel_quad(Panel<P, 128, V>& r, const char* __restrict__ base, const Step4& st,
-                                                int sub, int tid) {
-  using Cf = GemmCfg<P, 128, V>;
-  constexpr int64_t LEAF = int64_t(64) * 64 * (Cf::kBf ? 2 * Cf::ES : Cf::ES);
-  const int32_t sa0 = st.a0, sa1 = st.a1, sb0 = st.b0, sb1 = st.b1;  // values, not a select of addresses
+__device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ base, const QuadOffs<P, V>& o,
+                                            int32_t a0, int32_t a1, int32_t b0, int32_t b1, int sub, int wave) {
+  using Q = QuadCfg<P, V>;
+  if (a0 < 0) a0 = a1;  // a leaf no child needs: load the partner's instead
+  if (a1 < 0) a1 = a0;
+  if (b0 < 0) b0 = b1;
+  if (b1 < 0) b1 = b0;
 #pragma unroll
-  for (int t = 0; t < Cf::A_VECS; ++t) {
-    const int v = tid + t * Cf::NT;
-    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
-    const int h = v / Cf::PV, vv = v % Cf::PV;
-    const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
-    const int32_t leaf = row < 64 ? sa0 : sa1;
-    if (leaf < 0) continue;
-    const int64_t e = h * 64 * 64 + (row & 63) * 64 + sub * Cf::KP + cv * Cf::VN;
-    const auto L = as_global(base + int64_t(leaf) * LEAF);
-    r.a[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(L + e * Cf::ES);
+  for (int i = 0; i < Q::VPT; ++i) {
+    const int blk = i * Q::NW + wave;  // 1 KiB block of the part (wave-uniform)
+    // an A block's rows lie in one row half
+    const int32_t leaf = ((blk * 64 / Q::CH) % 128) < 64 ? a0 : a1;
+    const auto L = as_global(base + int64_t(leaf) * Q::LEAF + sub * (Q::KP * Q::ES));
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.a[i]),
+                                     (__attribute__((address_space(3))) void*)(st + blk * 1024), 16, 0, 0);
   }
 #pragma unroll
-  for (int t = 0; t < Cf::B_VECS; ++t) {
-    const int v = tid + t * Cf::NT;
-    if (Cf::PARTIAL && v >= Cf::NH * Cf::PV) break;
+  for (int i = 0; i < Q::VPT; ++i) {
+    const int blk = i * Q::NW + wave;
     int32_t leaf;
-    int64_t e;
-    if constexpr (Cf::kBf) {  // transposed copy: row = B column, k contiguous
-      const int h = v / Cf::PV, vv = v % Cf::PV;
-      const int row = vv / (Cf::KP / Cf::VN), cv = vv % (Cf::KP / Cf::VN);
-      leaf = row < 64 ? sb0 : sb1;
-      e = h * 64 * 64 + (row & 63) * 64 + sub * Cf::KP + cv * Cf::VN;
+    int64_t so;
+    if constexpr (Q::kBf) {
+      leaf = ((blk * 64 / Q::CH) % 128) < 64 ? b0 : b1;
+      so = sub * (Q::KP * Q::ES);
     } else {
-      const int kr = v / (128 / Cf::VN), col = (v % (128 / Cf::VN)) * Cf::VN;
-      leaf = col < 64 ? sb0 : sb1;
-      e = (sub * Cf::KP + kr) * 64 + (col & 63);
+      leaf = blk < 8 ? b0 : b1;  // blocks 0-7: the left B leaf, 8-15: the right
+      so = int64_t(sub) * Q::KP * 64 * Q::ES;
     }
-    if (leaf < 0) continue;
-    const auto L = as_global(base + int64_t(leaf) * LEAF);
-    r.b[t] = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(L + e * Cf::ES);
+    const auto L = as_global(base + int64_t(leaf) * Q::LEAF + so);
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.b[i]),
+                                     (__attribute__((address_space(3))) void*)(st + Q::PART + blk * 1024), 16, 0, 0);
   }
 }
 
-// Every present child's C leaf from its wave's accumulators: C (optionally
-// alpha * AB + beta * D), its FP64 squared norm and, on a diagonal leaf, its
-// diagonal sum, for that child's work unit.
-template <int P, int V>
-__device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q, AccTiles<P, 128, V>& acc,
-                                              int lane, int child, int li, int g) {
-  using Cf = GemmCfg<P, 128, V>;
-  using Out = typename Cf::Out;
-  if (((q.cmask >> child) & 1) == 0) return;
-  const int64_t u = int64_t(q.u0) + __builtin_popcount(uint32_t(q.cmask) & ((1u << child) - 1u));
-  const WorkUnit W = ga.wu[u];
-  const auto Cl = as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(W.cidx) * 64 * 64 * sizeof(Out)));
-  const uint32_t cm = uint32_t(W.cflags & kUnitMorton);
-  const bool has_ep = (W.cflags & kUnitEp) != 0;
-  Out alpha = Out(1), beta = Out(0);
-  const Out* Dl = nullptr;
-  if (has_ep) {
-    const ReqDev* R = ga.reqs + W.req;
-    alpha = Out(R->alpha);
-    beta = Out(R->beta);
-    if (R->Dslot != nullptr) {
-      const int32_t ds = R->Dslot[cm];
-      if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * 64 * 64;
-    }
+// Wait until at most n of this wave's loads are outstanding (the loads of
+// the panels issued after the one wanted).
+__device__ __forceinline__ void wait_loads(int n) {
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
   }
-  uint32_t ci, cj;
-  demorton(cm, ci, cj);
-  double nsq = 0.0, tr = 0.0;
+}
+
+// Workgroup barrier that orders LDS accesses at the compiler level only
+// (the direct loads it waits for were counted explicitly).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// One k-panel of the stage at As / Bs into the accumulators of the wave's
+// tile (rows row0.., columns col0.. of the 128 x 128 quad).  FP64: with
+// `keep` false the A operand is zero, so the accumulators do not change
+// (every staged leaf is finite: builds refuse NaN and Inf).
+template <int P, int V>
+__device__ __forceinline__ void compute_quad_panel(QAcc<P, V>& acc, const char* As, const char* Bs, int row0,
+                                                   int col0, int li, int g, bool keep = true) {
+  using Q = QuadCfg<P, V>;
+  if constexpr (Q::kBf) {
 #pragma unroll
-  for (int a = 0; a < Cf::TM; ++a)
+    for (int s = 0; s < Q::KG / 8; ++s) {
+      const int kc = (g * Q::KG + 8 * s) / 8;
+      bf16x8 ah[Q::TM], bh[Q::TN], al[Q::TM], bl[Q::TN];
 #pragma unroll
-    for (int b = 0; b < Cf::TN; ++b)
-#pragma unroll
-      for (int v = 0; v < Cf::AE; ++v) {
-        const int row = a * Cf::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
-        const int col = b * Cf::MT + li;
-        Out val = Out(acc[a][b][v]);
-        if (has_ep) {
-          const Out prod = alpha * val;
-          const Out dv = Dl ? beta * as_global(Dl)[row * 64 + col] : Out(0);
-          val = prod + dv;
-        }
-        Cl[row * 64 + col] = val;
-        const double dval = double(val);
-        const double sq = dval * dval;
-        nsq += sq;
-        if (row == col) tr += dval;
+      for (int a = 0; a < Q::TM; ++a) {
+        const int R = row0 + a * Q::MT + li;
+        const int o = R * Q::RB + ((kc ^ qswz<Q::CH>(R)) << 4);
+        ah[a] = *reinterpret_cast<const bf16x8*>(As + o);
+        if constexpr (Q::NH == 2) al[a] = *reinterpret_cast<const bf16x8*>(As + 128 * Q::RB + o);
       }
-  nsq = wave_sum_f64(nsq);
-  tr = wave_sum_f64(tr);
-  if (lane == 0) {
-    as_global(ga.wn)[u] = nsq;
-    if (ci == cj) as_global(ga.wt)[u] = tr;
+#pragma unroll
+      for (int b = 0; b < Q::TN; ++b) {
+        const int R = col0 + b * Q::MT + li;
+        const int o = R * Q::RB + ((kc ^ qswz<Q::CH>(R)) << 4);
+        bh[b] = *reinterpret_cast<const bf16x8*>(Bs + o);
+        if constexpr (Q::NH == 2) bl[b] = *reinterpret_cast<const bf16x8*>(Bs + 128 * Q::RB + o);
+      }
+#pragma unroll
+      for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < Q::TN; ++b) {
+          if constexpr (Q::NH == 2) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          }
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    // the BF16 operand-read wait states (as in compute_panel)
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 7\n\ts_nop 7");
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    using T = typename std::conditional<P == SPAMM_F64, double, float>::type;
+    const T* Bt = reinterpret_cast<const T*>(Bs);
+    const int swz = (g * Q::MT) % 64;
+#pragma unroll 2
+    for (int ch = 0; ch < Q::KG / 4; ++ch) {
+      const int kk = g * Q::KG + 4 * ch;
+      T av[Q::TM][4];
+      T bv[Q::TN][4];
+#pragma unroll
+      for (int a = 0; a < Q::TM; ++a) {
+        const int R = row0 + a * Q::MT + li;
+        if constexpr (P == SPAMM_F32) {
+          const int o = R * Q::RB + (((kk / 4) ^ qswz<Q::CH>(R)) << 4);
+          const f32x4 x = *reinterpret_cast<const f32x4*>(As + o);
+          av[a][0] = x[0];
+          av[a][1] = x[1];
+          av[a][2] = x[2];
+          av[a][3] = x[3];
+        } else {
+          const int o0 = R * Q::RB + (((kk / 2) ^ qswz<Q::CH>(R)) << 4);
+          const int o1 = R * Q::RB + (((kk / 2 + 1) ^ qswz<Q::CH>(R)) << 4);
+          const f64x2 x0 = *reinterpret_cast<const f64x2*>(As + o0);
+          const f64x2 x1 = *reinterpret_cast<const f64x2*>(As + o1);
+          av[a][0] = keep ? x0[0] : 0.0;
+          av[a][1] = keep ? x0[1] : 0.0;
+          av[a][2] = keep ? x1[0] : 0.0;
+          av[a][3] = keep ? x1[1] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < Q::TN; ++b) {
+        const int c = col0 + b * Q::MT + li;  // column of the quad
+        const T* blk = Bt + (c >> 6) * (Q::KP * 64);
+        const int cc = (c & 63) ^ swz;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) bv[b][qq] = blk[(kk + qq) * 64 + cc];
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+        for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+          for (int b = 0; b < Q::TN; ++b) {
+            if constexpr (P == SPAMM_F64)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][qq], bv[b][qq], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][qq], bv[b][qq], acc[a][b], 0, 0, 0);
+          }
+    }
+  }
+}
+
+// The C leaves of a quad from the waves' accumulators: C (optionally
+// alpha * AB + beta * D), its FP64 squared norm and, on a diagonal leaf, its
+// diagonal sum, for the child's work unit.  Called by every wave at the same
+// point (it holds a workgroup barrier); red: 2 * 8 partial sums.
+template <int P, int V>
+__device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q, QAcc<P, V>& acc, double* red,
+                                              int wave, int lane, int child, int ccol0, int li, int g) {
+  using Q = QuadCfg<P, V>;
+  using Out = typename GemmCfg<P, 128, V>::Out;
+  const bool present = (q.cmask >> child) & 1;
+  const int64_t u = int64_t(q.u0) + __builtin_popcount(uint32_t(q.cmask) & ((1u << child) - 1u));
+  uint32_t ci = 0, cj = 0;
+  if (present) {
+    const WorkUnit W = ga.wu[u];
+    const auto Cl =
+        as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(W.cidx) * 64 * 64 * sizeof(Out)));
+    const uint32_t cm = uint32_t(W.cflags & kUnitMorton);
+    const bool has_ep = (W.cflags & kUnitEp) != 0;
+    Out alpha = Out(1), beta = Out(0);
+    const Out* Dl = nullptr;
+    if (has_ep) {
+      const ReqDev* R = ga.reqs + W.req;
+      alpha = Out(R->alpha);
+      beta = Out(R->beta);
+      if (R->Dslot != nullptr) {
+        const int32_t ds = R->Dslot[cm];
+        if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * 64 * 64;
+      }
+    }
+    demorton(cm, ci, cj);
+    double nsq = 0.0, tr = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+      for (int b = 0; b < Q::TN; ++b)
+#pragma unroll
+        for (int v = 0; v < Q::AE; ++v) {
+          const int row = a * Q::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
+          const int col = ccol0 + b * Q::MT + li;
+          Out val = Out(acc[a][b][v]);
+          if (has_ep) {
+            const Out prod = alpha * val;
+            const Out dv = Dl ? beta * as_global(Dl)[row * 64 + col] : Out(0);
+            val = prod + dv;
+          }
+          Cl[row * 64 + col] = val;
+          const double dval = double(val);
+          nsq += dval * dval;
+          if (row == col) tr += dval;
+        }
+    nsq = wave_sum_f64(nsq);
+    tr = wave_sum_f64(tr);
+    if (lane == 0) {
+      red[wave] = nsq;
+      red[Q::NW + wave] = tr;
+    }
+  }
+  __syncthreads();
+  if (present && (wave & 1) == 0 && lane == 0) {  // the child's two halves, left first
+    as_global(ga.wn)[u] = red[wave] + red[wave + 1];
+    if (ci == cj) as_global(ga.wt)[u] = red[Q::NW + wave] + red[Q::NW + wave + 1];
   }
 }
 
 template <int P, int V>
-__global__ void __launch_bounds__(256, 1) k_gemm_quad(const GemmArgs ga) {
-  using Cf = GemmCfg<P, 128, V>;
-  constexpr int NPANEL = 64 / Cf::KP;  // k-panels of one 64-leaf product
-  __shared__ __attribute__((aligned(16))) char smem[Cf::PANEL_LDS];
-  char* const As = smem;
-  char* const Bs = smem + Cf::A_LDS;
+__global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
+  using Q = QuadCfg<P, V>;
+  __shared__ __attribute__((aligned(1024))) char smem[Q::NSTAGE * Q::STAGE];
+  // partial norm and diagonal sums of the epilogue, two sets used in turn
+  __shared__ double red2[2][2 * Q::NW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave / Cf::WN, wc = wave % Cf::WN;
-  const int child = 2 * wr + wc;  // the C leaf this wave owns in every quad
-  const int row0 = wr * Cf::TILE_M, col0 = wc * Cf::TILE_N;
-  const int li = lane % Cf::MT, g = lane / Cf::MT;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int child = wave >> 1;  // the C leaf (2 * row half + column half) this wave works on
+  const int ccol0 = (wave & 1) * Q::TILE_N;                        // the wave's columns in the child
+  const int row0 = (child >> 1) * 64, col0 = (child & 1) * 64 + ccol0;  // ... and in the quad
+  const int li = lane % Q::MT, g = lane / Q::MT;
   const char* const base = ga.base;
+  const QuadOffs<P, V> offs = quad_offsets<P, V>(wave, lane);
 
   // this workgroup's contiguous range of quads (the last range is cut at
   // the number of quads, known on the device only)
   const int xcd = int(blockIdx.x % kXcds), j = int(blockIdx.x / kXcds);
   const int rank = xcd * ga.kx + j;
   const int64_t nq = *ga.nq;
-  Visits vs;
-  vs.ubase = ga.start[rank];
-  vs.cstride = 0;
-  vs.chunk = int64_t(1) << 62;
-  vs.n = min(ga.start[rank + 1], nq) - vs.ubase;
-  const int64_t u1 = vs.n;
+  const int64_t q0 = ga.start[rank];
+  const int64_t u1 = min(ga.start[rank + 1], nq) - q0;  // quads q0 .. q0 + u1 - 1
   if (u1 <= 0) return;
+  const GemmArgs* gp = &ga;
+  auto rec = [&](int64_t q) { return quad_at(*gp, q0 + q); };
 
-  __shared__ i32x2r ring[2][64 * 3];
-  const WorkUnit* recs = reinterpret_cast<const WorkUnit*>(ga.qu);
-  int64_t rb = 0;
-  int blk0 = 0;
-  stage_recs(ring, 0, recs, rb, vs, tid, Cf::NT);
-  stage_recs(ring, 1, recs, rb + 64, vs, tid, Cf::NT);
-  __syncthreads();
-
-  // W0: the window of the current step; W1: the window after it (the
-  // quad's next, or the next quad's first); (pu, pw) is W1's position
-  int64_t cu = 0;
-  QuadS U = quad_of(ring, blk0, 0);
-  Win4 W0 = load_win4(ga, U, 0, true);
-  int64_t pu = 0;
+  // loader: quad lq (with steps), step ls, panel lsub; WL holds the window of
+  // step ls, WN the window after it, at (pq, pw)
+  int64_t lq = 0;
+  QuadS LQ = rec(0);
+  while (LQ.ns == 0 && ++lq < u1) LQ = rec(lq);
+  bool lmore = lq < u1;
+  int32_t ls = 0;
+  int lsub = 0;
+  Win4 WL = load_win4(ga, LQ.sp, LQ.ns, 0, lmore);
+  int64_t pq = lq;
   int pw = 0;
-  QuadS PU = U;
-  auto next_pos = [&]() {
-    if ((pw + 1) * 64 < PU.ns) {
+  QuadS PQ = LQ;
+  auto next_win = [&]() {  // (pq, pw) to the next window of a quad with steps
+    if ((pw + 1) * 64 < PQ.ns) {
       ++pw;
     } else {
-      ++pu;
       pw = 0;
-      if (pu < u1) PU = quad_of(ring, blk0, pu - rb);
+      do {
+        ++pq;
+        if (pq < u1) PQ = rec(pq);
+      } while (pq < u1 && PQ.ns == 0);
+    }
+    pq = uniform64(pq);
+    pw = __builtin_amdgcn_readfirstlane(pw);
+  };
+  if (lmore) next_win();
+  Win4 WN = load_win4(ga, PQ.sp, PQ.ns, pw, lmore && pq < u1);
+
+  // per panel in flight (up to four, one byte each, oldest lowest): bits 0-3
+  // the children that keep the step, bit 4 last panel of the step
+  uint32_t fifo = 0;
+  int ahead = 0, ist = 0, cst = 0;  // panels in flight, next stage to fill, stage to multiply
+  auto issue = [&]() {
+    const int l = ls & 63;
+    const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
+    const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
+    const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
+    issue_panel<P, V>(smem + ist * Q::STAGE, base, offs, a0, a1, b0, b1, lsub, wave);
+    const bool last_sub = lsub + 1 == Q::NP;
+    fifo |= (m | (last_sub ? 16u : 0u)) << (8 * ahead);
+    ++ahead;
+    ist = (ist + 1) % Q::NSTAGE;
+    if (!last_sub) {
+      ++lsub;
+    } else {
+      lsub = 0;
+      ++ls;
+      if (ls == LQ.ns) {  // the next quad with steps: its first window is WN
+        lq = pq;
+        LQ = PQ;
+        ls = 0;
+        lmore = lq < u1;
+        WL = WN;
+        if (lmore) {
+          next_win();
+          WN = load_win4(*gp, PQ.sp, PQ.ns, pw, pq < u1);
+        }
+      } else if ((ls & 63) == 0) {  // the quad's next window
+        WL = WN;
+        next_win();
+        WN = load_win4(*gp, PQ.sp, PQ.ns, pw, pq < u1);
+      }
     }
   };
-  next_pos();
-  Win4 W1 = load_win4(ga, PU, pw, pu < u1);
 
-  Panel<P, 128, V> pr;
-  if (U.ns > 0) load_panel_quad<P, V>(pr, base, step_at(W0, 0), 0, tid);
-
-  for (;;) {
-    const bool has_next = cu + 1 < u1;
-    int32_t next_ns = 0;
-    if (has_next) next_ns = quad_of(ring, blk0, cu + 1 - rb).ns;
-
-    Acc<P, 128, V> acc[Cf::TM][Cf::TN];
-    Acc<P, 128, V> part[Cf::TWO_LEVEL ? Cf::TM : 1][Cf::TWO_LEVEL ? Cf::TN : 1];
+  Acc<P, 128, V> acc[Q::TM][Q::TN];
+  Acc<P, 128, V> part[Q::TWO_LEVEL ? Q::TM : 1][Q::TWO_LEVEL ? Q::TN : 1];
+  auto clear = [&]() {
 #pragma unroll
-    for (int a = 0; a < Cf::TM; ++a)
+    for (int a = 0; a < Q::TM; ++a)
 #pragma unroll
-      for (int b = 0; b < Cf::TN; ++b) acc[a][b] = Acc<P, 128, V>{};
-    if constexpr (Cf::TWO_LEVEL) {
+      for (int b = 0; b < Q::TN; ++b) acc[a][b] = Acc<P, 128, V>{};
+    if constexpr (Q::TWO_LEVEL) {
 #pragma unroll
-      for (int a = 0; a < Cf::TM; ++a)
+      for (int a = 0; a < Q::TM; ++a)
 #pragma unroll
-        for (int b = 0; b < Cf::TN; ++b) part[a][b] = Acc<P, 128, V>{};
+        for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
     }
+  };
+  clear();
 
-    for (int p = 0; p < U.ns; ++p) {
-      const bool mine = (__builtin_amdgcn_readlane(W0.m, p & 63) >> child) & 1;
-      for (int sub = 0; sub < NPANEL; ++sub) {
-        __builtin_amdgcn_s_setprio(1);
-        __syncthreads();  // every wave is done with the previous panel
-        store_panel<P, 128, V>(pr, As, Bs, tid);
-        __syncthreads();
-        // next panel: same step, next step (this or the next window), or
-        // the first step of the next quad (the next window)
-        if (sub + 1 < NPANEL) {
-          load_panel_quad<P, V>(pr, base, step_at(W0, p & 63), sub + 1, tid);
-        } else if (p + 1 < U.ns) {
-          const int l = (p + 1) & 63;
-          load_panel_quad<P, V>(pr, base, l == 0 ? step_at(W1, 0) : step_at(W0, l), 0, tid);
-        } else if (next_ns > 0) {
-          load_panel_quad<P, V>(pr, base, step_at(W1, 0), 0, tid);
-        }
-        __builtin_amdgcn_s_setprio(2);
-        if (mine) {
-          if constexpr (Cf::TWO_LEVEL) {
-            compute_panel<P, 128, V>(part, As, Bs, row0, col0, li, g);
-            if (sub + 1 == NPANEL) {  // the product's sum joins the leaf's total
+  // quads without steps (C from the epilogue alone, zero products) up to the
+  // next quad with steps
+  int64_t cq = 0;
+  auto flush_empty = [&]() {
+    while (cq < u1) {
+      const QuadS E = rec(cq);
+      if (E.ns != 0) break;
+      epilogue_quad<P, V>(*gp, E, acc, red2[cq & 1], wave, lane, child, ccol0, li, g);
+      ++cq;
+    }
+  };
+  flush_empty();
+
+  for (int i = 0; i < Q::NSTAGE - Q::GP && lmore; ++i) issue();
+  // the quads with steps in order, each over its panels (the loader issued
+  // exactly these panels in this order), GP panels per barrier
+  while (cq < u1) {
+    const QuadS C = rec(cq);
+    const int32_t npan = C.ns * Q::NP;
+    for (int32_t p = 0; p < npan; p += Q::GP) {
+      // loop state is wave-uniform: keep it in scalar registers
+      ahead = __builtin_amdgcn_readfirstlane(ahead);
+      fifo = uint32_t(__builtin_amdgcn_readfirstlane(int32_t(fifo)));
+      ist = __builtin_amdgcn_readfirstlane(ist);
+      cst = __builtin_amdgcn_readfirstlane(cst);
+      ls = __builtin_amdgcn_readfirstlane(ls);
+      lsub = __builtin_amdgcn_readfirstlane(lsub);
+      lmore = __builtin_amdgcn_readfirstlane(int32_t(lmore)) != 0;
+      wait_loads((ahead - Q::GP) * Q::LOADS);  // this wave's loads of the oldest GP panels are in LDS
+      lds_barrier();                            // every wave's are, and the stages multiplied last are free
+      uint32_t meta[Q::GP];
+      int st[Q::GP];
 #pragma unroll
-              for (int a = 0; a < Cf::TM; ++a)
+      for (int k = 0; k < Q::GP; ++k) {  // the oldest panels leave the queue
+        meta[k] = fifo & 0xffu;
+        fifo >>= 8;
+        st[k] = cst;
+        cst = (cst + 1) % Q::NSTAGE;
+      }
+      ahead -= Q::GP;
 #pragma unroll
-                for (int b = 0; b < Cf::TN; ++b) {
-                  acc[a][b] += part[a][b];
-                  part[a][b] = Acc<P, 128, V>{};
-                }
+      for (int k = 0; k < Q::GP; ++k)
+        if (lmore) issue();  // into the stages multiplied last
+#pragma unroll
+      for (int k = 0; k < Q::GP; ++k) {
+        const char* As = smem + st[k] * Q::STAGE;
+        const char* Bs = As + Q::PART;
+        const bool mine = (meta[k] >> child) & 1u;
+        if constexpr (Q::TWO_LEVEL) {
+          // every wave multiplies every panel into its product sum; a wave
+          // whose child does not keep the step drops that sum instead
+          compute_quad_panel<P, V>(part, As, Bs, row0, col0, li, g);
+          if (meta[k] & 16u) {  // the product's sum joins the leaf's total
+            if (mine) {
+#pragma unroll
+              for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < Q::TN; ++b) acc[a][b] += part[a][b];
             }
-          } else {
-            compute_panel<P, 128, V>(acc, As, Bs, row0, col0, li, g);
+#pragma unroll
+            for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+              for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
           }
+        } else {  // FP64: one level, a wave whose child does not keep the step multiplies zeros
+          compute_quad_panel<P, V>(acc, As, Bs, row0, col0, li, g, mine);
         }
-        __builtin_amdgcn_s_setprio(0);
-      }
-      if (((p + 1) & 63) == 0 && p + 1 < U.ns) {  // into the quad's next window
-        W0 = W1;
-        next_pos();
-        W1 = load_win4(ga, PU, pw, pu < u1);
       }
     }
-
-    epilogue_quad<P, V>(ga, U, acc, lane, child, li, g);
-    if (!has_next) break;
-
-    const int32_t prev_ns = U.ns;
-    ++cu;
-    if (cu - rb == 64) {
-      // quads below cu are done: their block takes quads [rb + 128, rb + 192)
-      // (quads without steps pass no barrier, hence the two here)
-      __syncthreads();
-      rb += 64;
-      blk0 ^= 1;
-      stage_recs(ring, blk0 ^ 1, recs, rb + 64, vs, tid, Cf::NT);
-      __syncthreads();
-    }
-    U = quad_of(ring, blk0, cu - rb);
-    W0 = W1;
-    next_pos();
-    W1 = load_win4(ga, PU, pw, pu < u1);
-    // the first panel of a quad after a quad without steps was not prefetched
-    if (prev_ns == 0 && U.ns > 0) load_panel_quad<P, V>(pr, base, step_at(W0, 0), 0, tid);
+    epilogue_quad<P, V>(ga, C, acc, red2[cq & 1], wave, lane, child, ccol0, li, g);
+    clear();
+    ++cq;
+    flush_empty();
   }
 }
 
@@ -978,7 +1210,7 @@ template <int P, int V>
 static int max_groups_quad(int n_cu) {
   static const int per_cu = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, 256, 0) != hipSuccess || v < 1) v = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, 512, 0) != hipSuccess || v < 1) v = 1;
     return v;
   }();
   return per_cu * n_cu;
@@ -986,31 +1218,29 @@ static int max_groups_quad(int n_cu) {
 
 bool gemm_quad_supported(int prec, int bs) { return bs == 64 && prec >= SPAMM_F64 && prec <= SPAMM_BF16X3; }
 
+// Quads take 16 x 16 MFMA tiles in every precision (the 32 x 32 variant
+// needs more registers than the pipelined kernel leaves).
 template <typename F>
-static auto dispatch_quad(int prec, int variant, F&& f) {
+static auto dispatch_quad(int prec, F&& f) {
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
   switch (prec) {
     case SPAMM_F64: return f(std::integral_constant<int, SPAMM_F64>{}, I0{});
-    case SPAMM_F32:
-      return variant ? f(std::integral_constant<int, SPAMM_F32>{}, I1{}) : f(std::integral_constant<int, SPAMM_F32>{}, I0{});
-    case SPAMM_BF16:
-      return variant ? f(std::integral_constant<int, SPAMM_BF16>{}, I1{}) : f(std::integral_constant<int, SPAMM_BF16>{}, I0{});
-    default:
-      return variant ? f(std::integral_constant<int, SPAMM_BF16X3>{}, I1{})
-                     : f(std::integral_constant<int, SPAMM_BF16X3>{}, I0{});
+    case SPAMM_F32: return f(std::integral_constant<int, SPAMM_F32>{}, I1{});
+    case SPAMM_BF16: return f(std::integral_constant<int, SPAMM_BF16>{}, I1{});
+    default: return f(std::integral_constant<int, SPAMM_BF16X3>{}, I1{});
   }
 }
 
-int gemm_quad_max_groups(int prec, int variant, int n_cu) {
-  return dispatch_quad(prec, variant, [&](auto pc, auto vc) -> int {
+int gemm_quad_max_groups(int prec, int n_cu) {
+  return dispatch_quad(prec, [&](auto pc, auto vc) -> int {
     return max_groups_quad<decltype(pc)::value, decltype(vc)::value>(n_cu);
   });
 }
 
-hipError_t launch_gemm_quad(hipStream_t s, int prec, int variant, const GemmArgs& a) {
-  return dispatch_quad(prec, variant, [&](auto pc, auto vc) -> hipError_t {
-    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)), dim3(256),
+hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a) {
+  return dispatch_quad(prec, [&](auto pc, auto vc) -> hipError_t {
+    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)), dim3(512),
                        0, s, a);
     return hipGetLastError();
   });

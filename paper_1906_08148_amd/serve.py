@@ -224,12 +224,14 @@ class GpuLane:
     cache of built quadtrees.  `inputs` maps a MatrixSpec to its host input
     (make_input) or is None to generate on demand."""
 
-    def __init__(self, arena_bytes, device=0, inputs=None, keep_C=False, graph=False):
+    def __init__(self, arena_bytes, device=0, inputs=None, keep_C=False, graph=False, options=None):
         import torch
         from . import spamm as S
         self.S = S
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = S.Context(arena_bytes=arena_bytes, device=device, stream=self.stream)
+        for k, v in (options or {}).items():  # context options (spamm.Context.set_option)
+            self.ctx.set_option(k, v)
         if graph:  # each batch's kernels after the sizing read-back as one HIP graph
             self.ctx.set_option("graph", 1)
         self.budget = arena_bytes
@@ -309,8 +311,8 @@ class Server:
     """Continuous-batching server over `lanes` GPU lanes."""
 
     def __init__(self, lanes=2, arena_bytes_per_lane=32 << 30, max_batch=16, device=0, inputs=None,
-                 keep_C=False, graph=False):
-        self.lanes = [GpuLane(arena_bytes_per_lane, device, inputs, keep_C, graph) for _ in range(lanes)]
+                 keep_C=False, graph=False, options=None):
+        self.lanes = [GpuLane(arena_bytes_per_lane, device, inputs, keep_C, graph, options) for _ in range(lanes)]
         self.sched = Scheduler(self.lanes, max_batch=max_batch)
 
     def submit(self, spec: RequestSpec, t_arrive=None):

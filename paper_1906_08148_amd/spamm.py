@@ -375,7 +375,8 @@ class Context:
         """validate (1: measure ||C - C_FP64||_F into stats["val_err"]),
         gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
         slices, 1: request-major), graph (1: one captured graph per batch),
-        gemm_quad (1: leaf-64 products in quads of sibling C leaves)."""
+        gemm_quad (1, the default: leaf-64 products in quads of sibling C
+        leaves; 0: one C leaf per work unit)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 
     def get_option(self, name: str) -> int:

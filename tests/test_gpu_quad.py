@@ -1,6 +1,6 @@
-"""Quads of sibling C leaves (leaf 64, option gemm_quad): the leaf GEMM that
-runs the up to four children of a quadtree node of C in one workgroup over
-the merged k order of their products.  Checked against the CPU oracle in
+"""Quads of sibling C leaves (leaf 64, option gemm_quad, on by default):
+the leaf GEMM that runs the up to four children of a quadtree node of C in
+one workgroup over the merged k order of their products.  Checked against the CPU oracle in
 every scheme and precision (ragged tails, banded matrices whose quads have
 one to four children, 3D decay with partial pruning), against the one-leaf
 path, for repeatability, batches, C leaves from D alone, the symmetric
@@ -46,9 +46,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("quad", [1, 0])
 @pytest.mark.parametrize("n,kind,alpha,tau,modes", CASES)
-def test_quad_matches_the_oracle(ctx, n, kind, alpha, tau, modes):
-    print(f"case: quad n={n} {kind} alpha={alpha} tau={tau}", flush=True)
+def test_quad_matches_the_oracle(ctx, n, kind, alpha, tau, modes, quad):
+    """Quads (the default) and the one-leaf GEMM, against the oracle."""
+    print(f"case: quad={quad} n={n} {kind} alpha={alpha} tau={tau}", flush=True)
+    ctx.set_option("gemm_quad", quad)
     A = synth.DecaySpec(kind, n, alpha, seed=3).dense()
     B = A if kind == "3d" else synth.DecaySpec(kind, n, alpha * 1.5, seed=4).dense()
     TA = O.build(A, 64)
@@ -59,6 +62,7 @@ def test_quad_matches_the_oracle(ctx, n, kind, alpha, tau, modes):
         for prec in PRECS:
             p, _, _ = check_product(ctx, MA, MB, TA, TB, tau, mode, prec, alias=B is A)
             p.C.release()
+    ctx.set_option("gemm_quad", 1)
     if MB is not MA:
         MB.release()
     MA.release()
