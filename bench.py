@@ -743,7 +743,7 @@ def main():
     log(f"bench: 3D hybrid {args.prec} steps")
     r = config3_steps(ctx, dA, prec, args.steps, args.warmup, keep_last=not args.skip_extras)
     tile = ctx.get_option("gemm_tile")
-    quad = ctx.get_option("gemm_quad")
+    quad = r["tm"]["gemm_quad_launches"] > 0  # the GEMM the library chose for this workload
     if quad:
         kname = f"void spamm::k_gemm_quad<{prec}, {0 if prec == spamm.F64 else 1}>"
     else:

@@ -171,6 +171,7 @@ typedef struct spamm_timing {
   double pyramid_ms;  /* norm pyramids                                     */
   int64_t build_launches, trunc_launches, prune_launches, gemm_launches, pyramid_launches;
   double gemm_flops;  /* 2 * bs^3 * (products) over the timed GEMM launches */
+  int64_t gemm_quad_launches;  /* of gemm_launches, those on quads (SPAMM_OPT_GEMM_QUAD) */
 } spamm_timing;
 
 /* Name of a status code (static string). */
@@ -220,20 +221,24 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       kept products (0 for FP64 products).  Needs the FP64
  *                       copy of A and B (EUNSUPPORTED otherwise); costs the
  *                       FP64 products and one synchronisation.
- *  SPAMM_OPT_GEMM_QUAD  1 (default): the C leaves of a leaf-64 product
- *                       that are children of one quadtree node (up to four)
- *                       run in one workgroup over the merged k order of their
- *                       products, so that every A and B leaf staged serves
- *                       both children of its row or column half (half the
- *                       operand reads when all four keep a k); each C leaf
- *                       still sums its own products k ascending.  Quads take
- *                       16 x 16 MFMA tiles whatever GEMM_TILE says.  0: every
- *                       C leaf is one work unit of the one-leaf GEMM.  Other
- *                       leaf sizes ignore the option.
+ *  SPAMM_OPT_GEMM_QUAD  1: the C leaves of a leaf-64 product that are
+ *                       children of one quadtree node (up to four) run in one
+ *                       workgroup over the merged k order of their products,
+ *                       so that every A and B leaf staged serves both
+ *                       children of its row or column half (half the operand
+ *                       reads when all four keep a k); each C leaf still sums
+ *                       its own products k ascending.  Quads take 16 x 16
+ *                       MFMA tiles whatever GEMM_TILE says.  0: every C leaf
+ *                       is one work unit of the one-leaf GEMM.  -1 (default):
+ *                       quads for a launch group (one precision) whose C
+ *                       leaves average at least 128 (FP64), 144 (FP32), 36
+ *                       (BF16) or 16 (split BF16) kept products, the
+ *                       one-leaf GEMM below.  Other leaf sizes ignore the
+ *                       option.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
  * and GEMM_QUAD change the order of the sums inside one MFMA or one k-panel
  * (results stay within the precision's tolerance).  Errors: EINVAL (unknown
- * key or value). */
+ * key or value; values are 0 or 1, and -1 for UNIT_ORDER and GEMM_QUAD). */
 typedef enum {
   SPAMM_OPT_GEMM_TILE = 0,
   SPAMM_OPT_PLACEMENT = 1,

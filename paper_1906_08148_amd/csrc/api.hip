@@ -106,8 +106,18 @@ constexpr int kMaxL = 11;  // G <= 2048
 
 bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || bs == 256; }
 
-// Launch groups whose products run in quads of sibling C leaves.
-bool quad_group(const Ctx* c, int prec, int bs) { return c->gemm_quad && gemm_quad_supported(prec, bs); }
+// Whether a launch group's products run in quads of sibling C leaves:
+// option 1 always (leaf 64), 0 never, -1 when the group's C leaves average
+// at least a precision's threshold of kept products.  Below it the quads'
+// siblings share few k (a step often serves one or two children) and the
+// one-leaf kernel is faster; the thresholds are the measured crossovers on
+// 3D and 1D decay (FP64 / FP32 multiply-bound, BF16 forms load-bound).
+bool quad_group(const Ctx* c, int prec, int bs, int64_t kept, int64_t leaves) {
+  if (c->gemm_quad == 0 || !gemm_quad_supported(prec, bs)) return false;
+  if (c->gemm_quad == 1) return true;
+  const int64_t per_leaf = prec == SPAMM_F64 ? 128 : prec == SPAMM_F32 ? 144 : prec == SPAMM_BF16 ? 36 : 16;
+  return kept >= per_leaf * std::max<int64_t>(leaves, 1);
+}
 
 void grid_of(int64_t n, int bs, int& G, int& L) {
   const int64_t g = (n + bs - 1) / bs;
@@ -204,6 +214,12 @@ spamm_status nomem(Ctx* c, const char* what, size_t bytes) {
 #define ALLOC(var, bytes, what)                                 \
   do {                                                          \
     (var) = c->alloc(bytes);                                    \
+    if (!(var)) return nomem(c, what, size_t(bytes));           \
+  } while (0)
+// a block that lives only during the call (kept away from the results)
+#define ALLOC_TMP(var, bytes, what)                             \
+  do {                                                          \
+    (var) = c->alloc(bytes, 256, true);                         \
     if (!(var)) return nomem(c, what, size_t(bytes));           \
   } while (0)
 // leaf copies are aligned to their leaf size so that a leaf is one index
@@ -550,6 +566,10 @@ spamm_status spamm_ctx_set_option(spamm_ctx* ctx, spamm_option key, int64_t valu
     c->gemm_interleave = int(value);
     return SPAMM_OK;
   }
+  if (key == SPAMM_OPT_GEMM_QUAD && value == -1) {
+    c->gemm_quad = -1;
+    return SPAMM_OK;
+  }
   if (value != 0 && value != 1) return fail(c, SPAMM_EINVAL, "option value must be 0 or 1");
   switch (key) {
     case SPAMM_OPT_GEMM_TILE: c->gemm_tile = int(value); return SPAMM_OK;
@@ -599,6 +619,7 @@ spamm_status spamm_ctx_timing(spamm_ctx* ctx, int32_t enable, int32_t reset, spa
     out->gemm_launches = c->t_cnt[kTGemm];
     out->pyramid_launches = c->t_cnt[kTPyr];
     out->gemm_flops = c->gemm_flops;
+    out->gemm_quad_launches = c->gemm_quad_launches;
   }
   if (reset) {
     SPAMM_HIP(c, c->collect_timing());
@@ -607,6 +628,7 @@ spamm_status spamm_ctx_timing(spamm_ctx* ctx, int32_t enable, int32_t reset, spa
       c->t_cnt[k] = 0;
     }
     c->gemm_flops = 0.0;
+    c->gemm_quad_launches = 0;
   }
   c->timing = enable != 0;
   return SPAMM_OK;
@@ -1118,18 +1140,18 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   ReqTotals* totals_h = reinterpret_cast<ReqTotals*>(c->res_host);
   ReqTotals* totals_d = reinterpret_cast<ReqTotals*>(c->res_dev);
   RegionP packed, scanned, bnd_all, cand_all, pb_all, scan_scr;
-  ALLOC(packed, total_c * 8, "counts");
-  ALLOC(scanned, (total_c + 1) * 8, "offsets");
-  ALLOC(bnd_all, total_c * 8, "bounds");
-  ALLOC(cand_all, total_c * 4, "candidates");
-  ALLOC(pb_all, total_c * 8, "rounding bounds");
+  ALLOC_TMP(packed, total_c * 8, "counts");
+  ALLOC_TMP(scanned, (total_c + 1) * 8, "offsets");
+  ALLOC_TMP(bnd_all, total_c * 8, "bounds");
+  ALLOC_TMP(cand_all, total_c * 4, "candidates");
+  ALLOC_TMP(pb_all, total_c * 8, "rounding bounds");
   const size_t ssb = scan_scratch_bytes(total_c);
-  ALLOC(scan_scr, ssb, "scan scratch");
+  ALLOC_TMP(scan_scr, ssb, "scan scratch");
   // symmetric squares: one flag per request, set on the device when the
   // operand's (or D's) null map is not symmetric
   RegionP symflags;
   if (any_sym) {
-    ALLOC(symflags, int64_t(count) * 4, "symmetry flags");
+    ALLOC_TMP(symflags, int64_t(count) * 4, "symmetry flags");
     for (int r = 0; r < count; ++r) rd[r].asym = P<int32_t>(symflags) + r;
   }
   TableSet pre;
@@ -1167,14 +1189,14 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     const int64_t G2 = int64_t(C->G) * C->G;
     ALLOC(C->plan_off, (G2 + 1) * 8, "plan offsets");
     ALLOC(C->plan_bnd, G2 * 8, "skipped bounds");
-    ALLOC(cand_r[r], G2 * 4, "candidate counts");
-    ALLOC(trace_r[r], int64_t(C->G) * 8, "trace parts");
+    ALLOC_TMP(cand_r[r], G2 * 4, "candidate counts");
+    ALLOC_TMP(trace_r[r], int64_t(C->G) * 8, "trace parts");
     C->store = std::make_shared<Store>();
     C->plan_Astore = Au[r]->store;
     C->plan_Bstore = Bu[r]->store;
   }
   RegionP part;
-  if (st_out) ALLOC(part, total_chunks * sizeof(StatPartial), "stat partials");
+  if (st_out) ALLOC_TMP(part, total_chunks * sizeof(StatPartial), "stat partials");
   SPAMM_HIP(c, hipStreamSynchronize(c->stream));
   const std::vector<ReqTotals> ht(totals_h, totals_h + count);
   // the partial statistics need only the counting pass: they run while the
@@ -1189,7 +1211,6 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < count; ++r) groups[{reqs[r].prec, reqs[r].A->bs}].push_back(r);
   int64_t wu_total = 0;
-  std::vector<RegionP> quad_keep;  // per-request k arrays of the quad groups
   std::vector<std::pair<std::pair<int, int>, std::pair<int64_t, int64_t>>> launches;
   for (auto& gk : groups) {
     const int64_t start = wu_total;
@@ -1212,12 +1233,6 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     d.pairs = P<int2>(C->plan_pairs);
     d.pk = nullptr;
     d.qbase = 0;
-    if (quad_group(c, q.prec, q.A->bs)) {  // the k of every pair, for the quads' merged order
-      RegionP pkr;
-      ALLOC(pkr, std::max<int64_t>(nk, 1) * 4, "plan k");
-      d.pk = P<int32_t>(pkr);
-      quad_keep.push_back(std::move(pkr));
-    }
     d.off = P<int64_t>(C->plan_off);
     d.cslot = P<int32_t>(C->slot);
     d.ckeys = P<int32_t>(C->store->keys);
@@ -1299,6 +1314,16 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     sched.insert(sched.end(), pre.begin(), pre.end());
     sched.insert(sched.end(), Q.begin(), Q.end());
   }
+  // which launch groups run quads
+  std::vector<char> gquad;
+  for (auto& gk : groups) {
+    int64_t kept = 0, leaves = 0;
+    for (int r : gk.second) {
+      kept += ht[r].n_kept;
+      leaves += ht[r].c_nonnull;
+    }
+    gquad.push_back(quad_group(c, gk.first.first, gk.first.second, kept, leaves));
+  }
   // workgroups per launch: the resident maximum, a multiple of 8 (one rank
   // list per XCD)
   std::vector<int> kxs;
@@ -1306,8 +1331,8 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   {
     int gi = 0;
     for (auto& gk : groups) {
+      const bool quad = gquad[gi];
       const int64_t nwu = launches[gi++].second.second;
-      const bool quad = quad_group(c, gk.first.first, gk.first.second);
       const int64_t maxg = quad ? gemm_quad_max_groups(gk.first.first, c->n_cu)
                                 : gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
       // quads: at least a quarter of the units
@@ -1319,16 +1344,16 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     }
   }
   RegionP wus, costs, prefix, starts, wn, wt, sscr;
-  ALLOC(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
-  ALLOC(costs, std::max<int64_t>(wu_total, 1) * 8, "unit costs");
-  ALLOC(prefix, (wu_total + int64_t(groups.size())) * 8, "unit cost prefix");
-  ALLOC(starts, std::max<int64_t>(start_total, 1) * 8, "workgroup ranges");
-  ALLOC(wn, std::max<int64_t>(wu_total, 1) * 8, "unit norms");
-  ALLOC(wt, std::max<int64_t>(wu_total, 1) * 8, "unit diagonal sums");
-  ALLOC(sscr, std::max<int64_t>(scan_need, 1), "scan scratch");
+  ALLOC_TMP(wus, std::max<int64_t>(wu_total, 1) * sizeof(WorkUnit), "work units");
+  ALLOC_TMP(costs, std::max<int64_t>(wu_total, 1) * 8, "unit costs");
+  ALLOC_TMP(prefix, (wu_total + int64_t(groups.size())) * 8, "unit cost prefix");
+  ALLOC_TMP(starts, std::max<int64_t>(start_total, 1) * 8, "workgroup ranges");
+  ALLOC_TMP(wn, std::max<int64_t>(wu_total, 1) * 8, "unit norms");
+  ALLOC_TMP(wt, std::max<int64_t>(wu_total, 1) * 8, "unit diagonal sums");
+  ALLOC_TMP(sscr, std::max<int64_t>(scan_need, 1), "scan scratch");
   // quad plans: per quad group, flags, quad positions, step counts and
   // offsets, the quads' cost prefix (int64), the quad records and the steps
-  RegionP q_i64, q_rec, q_steps, q_mask;
+  RegionP q_i64, q_rec, q_steps, q_mask, q_pk;
   std::vector<std::array<int64_t, 3>> q_off;  // per group: int64, record and step offsets
   {
     int64_t n64 = 0, nrec = 0, nst = 0;
@@ -1336,7 +1361,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
     for (auto& gk : groups) {
       const int64_t nwu = launches[gi++].second.second;
       q_off.push_back({n64, nrec, nst});
-      if (!quad_group(c, gk.first.first, gk.first.second)) continue;
+      if (!gquad[gi - 1]) continue;
       int64_t kept = 0;
       for (int r : gk.second) {  // a request's steps sit where its products do
         rd[r].qbase = kept;
@@ -1347,10 +1372,20 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       nst += kept;
     }
     if (n64 > 0) {
-      ALLOC(q_i64, n64 * 8, "quad plan");
-      ALLOC(q_rec, std::max<int64_t>(nrec, 1) * sizeof(QuadUnit), "quad records");
-      ALLOC(q_steps, std::max<int64_t>(nst, 1) * 16, "quad steps");
-      ALLOC(q_mask, std::max<int64_t>(nst, 1), "quad step children");
+      ALLOC_TMP(q_i64, n64 * 8, "quad plan");
+      ALLOC_TMP(q_rec, std::max<int64_t>(nrec, 1) * sizeof(QuadUnit), "quad records");
+      ALLOC_TMP(q_steps, std::max<int64_t>(nst, 1) * 16, "quad steps");
+      ALLOC_TMP(q_mask, std::max<int64_t>(nst, 1), "quad step children");
+      // the k of every kept pair of the quad requests (for the merged k
+      // order), at the same index as the pair; one region after the results
+      // so that freeing it leaves no hole between them
+      ALLOC_TMP(q_pk, std::max<int64_t>(nst, 1) * 4, "plan k");
+      int gj = 0;
+      for (auto& gk : groups) {
+        ++gj;
+        if (!gquad[gj - 1]) continue;
+        for (int r : gk.second) rd[r].pk = P<int32_t>(q_pk) + q_off[gj - 1][2] + rd[r].qbase;
+      }
     }
   }
   // placement tables, the completed request table and C's pyramid jobs:
@@ -1408,7 +1443,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       soff += int64_t(kXcds) * kx + 1;
       ++gi;
       if (nwu == 0) continue;
-      if (quad_group(c, gk.first.first, gk.first.second)) {
+      if (gquad[gi - 1]) {
         const auto& qo = q_off[gi - 1];
         int64_t* flag = P<int64_t>(q_i64) + qo[0];
         int64_t* qpos = flag + nwu;        // nwu + 1
@@ -1444,6 +1479,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
         if (c->timing) {
           for (int r : gk.second)
             c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
+          ++c->gemm_quad_launches;
         }
         SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, ga));
         continue;

@@ -30,9 +30,12 @@ namespace spamm {
 class Arena {
  public:
   void init(char* base, size_t bytes);
-  // Returns offset or SIZE_MAX when no range fits.
-  size_t alloc(size_t bytes, size_t align = 256);
-  void release(size_t off, size_t bytes, size_t align);
+  // Returns offset or SIZE_MAX when no range fits.  high: a short-lived
+  // block, from the top of the highest range that fits (last fit).
+  size_t alloc(size_t bytes, size_t align = 256, bool high = false);
+  // merge: straight back into the range map (short-lived blocks), else into
+  // the exact-size cache.
+  void release(size_t off, size_t bytes, size_t align, bool merge = false);
   size_t used() const { return used_; }
   size_t size() const { return size_; }
   size_t free_bytes() const { return size_ - used_; }
@@ -40,7 +43,9 @@ class Arena {
   char* base() const { return base_; }
 
  private:
-  size_t fit(size_t bytes, size_t align) const;  // first-fit in the range map
+  size_t fit(size_t bytes, size_t align) const;       // first fit in the range map
+  size_t fit_high(size_t bytes, size_t align) const;  // last fit in the range map
+  void insert_free(size_t off, size_t bytes) const;   // into the range map, merged
   void trim() const;                              // buckets back into the range map
   char* base_ = nullptr;
   size_t size_ = 0;
@@ -55,6 +60,7 @@ struct Ctx;
 struct Region {
   Ctx* ctx = nullptr;
   size_t off = 0, bytes = 0, align = 256;
+  bool temp = false;  // short-lived (see Arena::alloc)
   ~Region();
   void* ptr() const;
 };
@@ -121,6 +127,7 @@ struct Ctx {
   double t_ms[kTClasses] = {0, 0, 0, 0, 0};
   int64_t t_cnt[kTClasses] = {0, 0, 0, 0, 0};
   double gemm_flops = 0.0;
+  int64_t gemm_quad_launches = 0;  // timed GEMM launches on quads
   hipEvent_t get_event();
   hipError_t collect_timing();  // sync + fold pending pairs into totals
   hipStream_t stream = nullptr;
@@ -147,7 +154,7 @@ struct Ctx {
                              // -1: per launch, 1 for short units and 0 for long ones)
   int use_graph = 0;   // launch the post-sizing kernels of a batch as one captured graph
   int validate = 0;    // measure every lower-precision product against an FP64 twin
-  int gemm_quad = 1;   // leaf-64 products in quads of sibling C leaves (k_gemm_quad)
+  int gemm_quad = -1;  // leaf-64 products in quads of sibling C leaves (k_gemm_quad): 1, 0, -1 automatic
   hipGraphExec_t gexec = nullptr;  // last instantiated batch graph (updated in place when the shape repeats)
   hipStream_t cap_stream = nullptr;  // private stream the batch graph is recorded on (nothing runs on it)
   std::map<uint64_t, int> tuned;  // reserved for autotune results
@@ -157,7 +164,7 @@ struct Ctx {
   char* res_host = nullptr;
   char* res_dev = nullptr;
   size_t res_bytes = 0;
-  RegionP alloc(size_t bytes, size_t align = 256);  // nullptr on exhaustion
+  RegionP alloc(size_t bytes, size_t align = 256, bool temp = false);  // nullptr on exhaustion
   void* stage(size_t bytes);      // grow pinned staging if needed
   bool results(size_t bytes);     // res_* holds at least `bytes` (synchronises to grow)
 };

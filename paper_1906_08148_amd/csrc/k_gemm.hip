@@ -863,12 +863,10 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // One k-panel of the stage at As / Bs into the accumulators of the wave's
-// tile (rows row0.., columns col0.. of the 128 x 128 quad).  FP64: with
-// `keep` false the A operand is zero, so the accumulators do not change
-// (every staged leaf is finite: builds refuse NaN and Inf).
+// tile (rows row0.., columns col0.. of the 128 x 128 quad).
 template <int P, int V>
 __device__ __forceinline__ void compute_quad_panel(QAcc<P, V>& acc, const char* As, const char* Bs, int row0,
-                                                   int col0, int li, int g, bool keep = true) {
+                                                   int col0, int li, int g) {
   using Q = QuadCfg<P, V>;
   if constexpr (Q::kBf) {
 #pragma unroll
@@ -928,10 +926,10 @@ __device__ __forceinline__ void compute_quad_panel(QAcc<P, V>& acc, const char* 
           const int o1 = R * Q::RB + (((kk / 2 + 1) ^ qswz<Q::CH>(R)) << 4);
           const f64x2 x0 = *reinterpret_cast<const f64x2*>(As + o0);
           const f64x2 x1 = *reinterpret_cast<const f64x2*>(As + o1);
-          av[a][0] = keep ? x0[0] : 0.0;
-          av[a][1] = keep ? x0[1] : 0.0;
-          av[a][2] = keep ? x1[0] : 0.0;
-          av[a][3] = keep ? x1[1] : 0.0;
+          av[a][0] = x0[0];
+          av[a][1] = x0[1];
+          av[a][2] = x1[0];
+          av[a][3] = x1[1];
         }
       }
 #pragma unroll
@@ -1178,24 +1176,23 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
         const char* As = smem + st[k] * Q::STAGE;
         const char* Bs = As + Q::PART;
         const bool mine = (meta[k] >> child) & 1u;
-        if constexpr (Q::TWO_LEVEL) {
-          // every wave multiplies every panel into its product sum; a wave
-          // whose child does not keep the step drops that sum instead
-          compute_quad_panel<P, V>(part, As, Bs, row0, col0, li, g);
-          if (meta[k] & 16u) {  // the product's sum joins the leaf's total
-            if (mine) {
+        // a wave whose child does not keep the step skips it (its SIMD
+        // partner, another child's wave, has the matrix core to itself)
+        if (mine) {
+          if constexpr (Q::TWO_LEVEL) {
+            compute_quad_panel<P, V>(part, As, Bs, row0, col0, li, g);
+            if (meta[k] & 16u) {  // the product's sum joins the leaf's total
 #pragma unroll
               for (int a = 0; a < Q::TM; ++a)
 #pragma unroll
-                for (int b = 0; b < Q::TN; ++b) acc[a][b] += part[a][b];
+                for (int b = 0; b < Q::TN; ++b) {
+                  acc[a][b] += part[a][b];
+                  part[a][b] = Acc<P, 128, V>{};
+                }
             }
-#pragma unroll
-            for (int a = 0; a < Q::TM; ++a)
-#pragma unroll
-              for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
+          } else {
+            compute_quad_panel<P, V>(acc, As, Bs, row0, col0, li, g);
           }
-        } else {  // FP64: one level, a wave whose child does not keep the step multiplies zeros
-          compute_quad_panel<P, V>(acc, As, Bs, row0, col0, li, g, mine);
         }
       }
     }

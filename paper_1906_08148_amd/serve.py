@@ -58,8 +58,10 @@ class RequestSpec:
     def footprint(self, nonnull=None) -> int:
         """Arena bytes the request may need: the leaf store of A in the
         request's precision (FP64 or FP32), C (FP64 or FP32), the kept pairs
-        and the per-leaf arrays.  `nonnull` (non-null leaves of A) defaults
-        to an upper bound for the kind."""
+        (with the quad plan of a leaf-64 product: merged steps, their
+        children and the k of every pair) and the per-leaf arrays.
+        `nonnull` (non-null leaves of A) defaults to an upper bound for the
+        kind."""
         g, G = self.grid()
         e2 = self.leaf * self.leaf
         if nonnull is None:
@@ -72,7 +74,8 @@ class RequestSpec:
         kept = min(g ** 3, c_leaves * 2 * row)
         eb = 8 if self.prec == 0 else 4
         store = nonnull * e2 * (eb if self.prec in (0, 1) else 12)  # BF16 needs FP32 plus two BF16 copies
-        return int(store + c_leaves * e2 * eb + kept * 8 + G * G * 96 + (16 << 20))
+        per_pair = 8 + (21 if self.leaf == 64 else 0)
+        return int(store + c_leaves * e2 * eb + kept * per_pair + G * G * 96 + (16 << 20))
 
 
 def _band_leaves(m: MatrixSpec, leaf: int) -> int:
@@ -285,10 +288,17 @@ class GpuLane:
         try:
             prods = self.ctx.multiply_batch(reqs)
         except S.SpammError as e:
-            if e.code != "ENOMEM" or len(specs) == 1:
+            if e.code != "ENOMEM":
                 raise
-            half = len(specs) // 2  # split the batch and retry
-            return self.run(specs[:half]) + self.run(specs[half:])
+            if len(specs) == 1:
+                # free space can be split: drop every other cached tree, once
+                if not any(x not in keys for x in self.cache):
+                    raise
+                self._evict(float("inf"), keys)
+                prods = self.ctx.multiply_batch(reqs)
+            else:
+                half = len(specs) // 2  # split the batch and retry
+                return self.run(specs[:half]) + self.run(specs[half:])
         import torch
         out = []
         with torch.cuda.stream(self.stream):

@@ -83,7 +83,7 @@ class Timing(ctypes.Structure):
                 ("pyramid_ms", ctypes.c_double), ("build_launches", ctypes.c_int64),
                 ("trunc_launches", ctypes.c_int64), ("prune_launches", ctypes.c_int64),
                 ("gemm_launches", ctypes.c_int64), ("pyramid_launches", ctypes.c_int64),
-                ("gemm_flops", ctypes.c_double)]
+                ("gemm_flops", ctypes.c_double), ("gemm_quad_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -375,8 +375,9 @@ class Context:
         """validate (1: measure ||C - C_FP64||_F into stats["val_err"]),
         gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
         slices, 1: request-major), graph (1: one captured graph per batch),
-        gemm_quad (1, the default: leaf-64 products in quads of sibling C
-        leaves; 0: one C leaf per work unit)."""
+        gemm_quad (1: leaf-64 products in quads of sibling C leaves; 0: one
+        C leaf per work unit; -1, the default: quads where the C leaves
+        average enough kept products)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 
     def get_option(self, name: str) -> int:

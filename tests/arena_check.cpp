@@ -1,6 +1,8 @@
 // Host-only check of the device-arena sub-allocator (first-fit ranges with an
-// exact-size cache in front).  Seeded random allocate/release sequences over a
-// 64 MiB arena of offsets (the base is never dereferenced); the invariants:
+// exact-size cache in front, and last-fit short-lived blocks released straight
+// to the range map).  Seeded random allocate/release sequences, a third of
+// them short-lived, over a 64 MiB arena of offsets (the base is never
+// dereferenced); the invariants:
 // every range is aligned and inside the arena, live ranges never overlap,
 // used() is the sum of the live sizes, a request is refused only when no
 // aligned gap of its size exists between the live ranges, and releasing
@@ -18,6 +20,7 @@ namespace {
 
 struct Live {
   size_t off, bytes, align;
+  bool high;
 };
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -60,6 +63,19 @@ int main(int argc, char** argv) {
     return fits(cur, size);
   };
 
+  {  // placement: long-lived from the bottom, short-lived from the top
+    const size_t lo = arena.alloc(size_t(1) << 20, 4096), hi = arena.alloc(size_t(1) << 20, 4096, true);
+    if (lo != 0 || hi != size - (size_t(1) << 20)) {
+      std::printf("FAIL seed %u: placement low %zu high %zu\n", seed, lo, hi);
+      return 1;
+    }
+    arena.release(hi, size_t(1) << 20, 4096, true);
+    arena.release(lo, size_t(1) << 20, 4096);
+    if (arena.used() != 0 || arena.largest_free() != size) {
+      std::printf("FAIL seed %u: placement blocks not returned\n", seed);
+      return 1;
+    }
+  }
   const size_t aligns[] = {256, 512, 4096, 16384, 65536};
   for (int step = 0; step < steps; ++step) {
     if (live.empty() || rng() % 100 < 55) {
@@ -67,7 +83,8 @@ int main(int argc, char** argv) {
       // repeated power-of-two shapes (exact-size cache hits) and arbitrary sizes
       const size_t bytes = rng() % 4 == 0 ? size_t(1) << (8 + rng() % 14) : 1 + rng() % (size_t(1) << 20);
       const size_t rounded = round_up(bytes, align);
-      const size_t off = arena.alloc(bytes, align);
+      const bool high = rng() % 3 == 0;
+      const size_t off = arena.alloc(bytes, align, high);
       if (off == SIZE_MAX) {
         ++refused;
         if (gap_fits(rounded, align)) {
@@ -76,11 +93,11 @@ int main(int argc, char** argv) {
         }
       } else {
         ++allocs;
-        live.push_back({off, rounded, align});
+        live.push_back({off, rounded, align, high});
       }
     } else {
       const size_t i = rng() % live.size();
-      arena.release(live[i].off, live[i].bytes, live[i].align);
+      arena.release(live[i].off, live[i].bytes, live[i].align, live[i].high);
       live[i] = live.back();
       live.pop_back();
       ++releases;
@@ -94,7 +111,7 @@ int main(int argc, char** argv) {
     std::printf("FAIL seed %u: invariant broken at the end\n", seed);
     return 1;
   }
-  for (const Live& l : live) arena.release(l.off, l.bytes, l.align);
+  for (const Live& l : live) arena.release(l.off, l.bytes, l.align, l.high);
   live.clear();
   if (arena.used() != 0 || arena.largest_free() != size) {
     std::printf("FAIL seed %u: used %zu, largest free %zu of %zu after releasing everything\n", seed, arena.used(),

@@ -1,7 +1,8 @@
 """The device-arena sub-allocator is host code: compile it with a small
 driver (tests/arena_check.cpp) and run seeded random allocate/release
-sequences against its invariants (alignment, no overlap, usage, refusals only
-when no aligned gap fits, full coalescing at the end)."""
+sequences, first-fit long-lived and last-fit short-lived blocks mixed,
+against its invariants (alignment, no overlap, usage, refusals only when no
+aligned gap fits, full coalescing at the end)."""
 import os
 import shutil
 import subprocess

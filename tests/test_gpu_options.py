@@ -59,7 +59,7 @@ def test_tile_variant_parity(prec):
     print(f"case: tile variant prec={prec}", flush=True)
     ctx = spamm.Context(arena_bytes=1 << 30)
     assert ctx.get_option("gemm_tile") == 1  # the default; the other parity tests run it
-    assert ctx.get_option("gemm_quad") == 1  # the default (quads ignore the tile variant)
+    assert ctx.get_option("gemm_quad") == -1  # the default: automatic (quads ignore the tile variant)
     ctx.set_option("gemm_tile", 0)
     ctx.set_option("gemm_quad", 0)  # leaf 64 on the one-leaf kernel, 32 x 32 tiles
     A = synth.DecaySpec("1d", 2100, 0.3, seed=5).dense()

@@ -180,3 +180,28 @@ def test_quad_graph_replays(ctx):
         ctx.set_option("graph", 0)
     eager.C.release()
     M.release()
+
+
+def test_automatic_choice_follows_products_per_leaf(ctx):
+    """With the default (-1) a launch group runs quads when its C leaves
+    average enough kept products for its precision (FP64: 128, split BF16:
+    16): a 3D product of 64 products per C leaf runs FP64 on the one-leaf
+    GEMM and split BF16 on quads, each bit for bit as when forced."""
+    import torch
+    print("case: automatic quad choice", flush=True)
+    A = synth.DecaySpec("3d", 4096, 1.0, seed=13).dense()
+    M = ctx.build(dev(A), 64, stores=ALL)
+    for prec, want in ((spamm.F64, 0), (spamm.BF16X3, 1)):
+        ctx.set_option("gemm_quad", -1)
+        ctx.timing(enable=True, reset=True)
+        auto = ctx.multiply(M, M, 1e-9, mode=spamm.SPAMM, prec=prec)
+        tm = ctx.timing(enable=False, reset=True)
+        assert auto.stats["n_kept"] == 64 ** 3  # every product: 64 per C leaf
+        assert tm["gemm_launches"] == 1 and tm["gemm_quad_launches"] == want, (prec, tm)
+        ctx.set_option("gemm_quad", want)
+        forced = ctx.multiply(M, M, 1e-9, mode=spamm.SPAMM, prec=prec)
+        assert torch.equal(ctx.to_dense(auto.C), ctx.to_dense(forced.C))
+        auto.C.release()
+        forced.C.release()
+    ctx.set_option("gemm_quad", 1)
+    M.release()
