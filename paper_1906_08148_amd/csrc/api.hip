@@ -115,7 +115,7 @@ bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || b
 bool quad_group(const Ctx* c, int prec, int bs, int64_t kept, int64_t leaves) {
   if (c->gemm_quad == 0 || !gemm_quad_supported(prec, bs)) return false;
   if (c->gemm_quad == 1) return true;
-  const int64_t per_leaf = prec == SPAMM_F64 ? 128 : prec == SPAMM_F32 ? 144 : prec == SPAMM_BF16 ? 36 : 16;
+  const int64_t per_leaf = prec == SPAMM_F64 || prec == SPAMM_F32 ? 128 : 16;
   return kept >= per_leaf * std::max<int64_t>(leaves, 1);
 }
 
@@ -1356,20 +1356,23 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
   RegionP q_i64, q_rec, q_steps, q_mask, q_pk;
   std::vector<std::array<int64_t, 3>> q_off;  // per group: int64, record and step offsets
   {
-    int64_t n64 = 0, nrec = 0, nst = 0;
+    int64_t n64 = 0, nrec = 0, nst = 0, npk = 0;
+    std::vector<int64_t> pk_base(count, 0);
     int gi = 0;
     for (auto& gk : groups) {
       const int64_t nwu = launches[gi++].second.second;
       q_off.push_back({n64, nrec, nst});
       if (!gquad[gi - 1]) continue;
-      int64_t kept = 0;
-      for (int r : gk.second) {  // a request's steps sit where its products do
-        rd[r].qbase = kept;
-        kept += ht[r].n_kept;
+      int64_t slots = 0;
+      for (int r : gk.second) {  // a quad's steps: its products + 1 slots (see k_quad.hip)
+        rd[r].qbase = slots;
+        slots += ht[r].n_kept + ht[r].c_nonnull;
+        pk_base[r] = npk;
+        npk += ht[r].n_kept;
       }
       n64 += 4 * nwu + 2;
       nrec += nwu;
-      nst += kept;
+      nst += slots;
     }
     if (n64 > 0) {
       ALLOC_TMP(q_i64, n64 * 8, "quad plan");
@@ -1377,14 +1380,13 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       ALLOC_TMP(q_steps, std::max<int64_t>(nst, 1) * 16, "quad steps");
       ALLOC_TMP(q_mask, std::max<int64_t>(nst, 1), "quad step children");
       // the k of every kept pair of the quad requests (for the merged k
-      // order), at the same index as the pair; one region after the results
-      // so that freeing it leaves no hole between them
-      ALLOC_TMP(q_pk, std::max<int64_t>(nst, 1) * 4, "plan k");
+      // order), at the pair's index
+      ALLOC_TMP(q_pk, std::max<int64_t>(npk, 1) * 4, "plan k");
       int gj = 0;
       for (auto& gk : groups) {
         ++gj;
         if (!gquad[gj - 1]) continue;
-        for (int r : gk.second) rd[r].pk = P<int32_t>(q_pk) + q_off[gj - 1][2] + rd[r].qbase;
+        for (int r : gk.second) rd[r].pk = P<int32_t>(q_pk) + pk_base[r];
       }
     }
   }
@@ -1458,7 +1460,8 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
           SPAMM_HIP(c, launch_quad_mark(c->stream, wu, nwu, flag));
           SPAMM_HIP(c, launch_scan_i64(c->stream, flag, qpos, nwu, sscr->ptr(), sscr->bytes));
           SPAMM_HIP(c, launch_zero_i32(c->stream, reinterpret_cast<int32_t*>(qcost), 2 * nwu));
-          SPAMM_HIP(c, launch_quad_plan(c->stream, reqd, wu, nwu, flag, qpos, qu, qcost, steps, smask));
+          SPAMM_HIP(c, launch_quad_plan(c->stream, reqd, wu, nwu, flag, qpos, qu, qcost, steps, smask,
+                                        gemm_quad_pad_even(gk.first.first) ? 1 : 0));
           SPAMM_HIP(c, launch_scan_i64(c->stream, qcost, qpre, nwu, sscr->ptr(), sscr->bytes));
           SPAMM_HIP(c, launch_wg_ranges(c->stream, qpre, nwu, kXcds * kx, stg));
         }

@@ -273,7 +273,7 @@ struct ReqDev {
   const int32_t* asym;    // symmetric square: nonzero when the operand's (or D's) null
                           // map is not symmetric (every C leaf is then formed)
   int32_t* pk;            // k of every kept pair (nullptr: not needed), beside `pairs`
-  int64_t qbase;          // quads: the request's first step in its group's step array
+  int64_t qbase;          // quads: the request's first step slot in its group's step array
 };
 
 // One truncation inside a batch (leaf-block truncation with budget tau^2).
@@ -467,7 +467,9 @@ int gemm_quad_max_groups(int prec, int n_cu);
 hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a);
 hipError_t launch_quad_mark(hipStream_t s, const WorkUnit* wu, int64_t nwu, int64_t* flag);
 hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
-                            const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask);
+                            const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask,
+                            int pad_even);
+bool gemm_quad_pad_even(int prec);  // quad steps padded to an even count
 int gemm_max_groups(int prec, int bs, int variant, int n_cu);  // resident workgroups of the kernel
 bool gemm_supported(int prec, int bs);
 int gemm_unit_tiles(int bs);  // work units per C leaf (4 for 256 leaves, else 1)

@@ -704,10 +704,9 @@ struct QuadCfg {
   static constexpr int VN = 16 / ES;                 // elements per chunk
   static constexpr int STAGE = 2 * PART;
   static constexpr int NSTAGE = 4;
-  // panels multiplied between two barriers: FP32 / FP64 take two (a longer
-  // run of MFMAs per barrier, the next two panels loading meanwhile), the
-  // BF16 forms one (three panels loading ahead)
-  static constexpr int GP = (P == SPAMM_F64 || P == SPAMM_F32) ? 2 : 1;
+  // panels multiplied between two barriers, the next GP loading meanwhile
+  // (BF16, one panel per product, has its quads' step counts padded to even)
+  static constexpr int GP = 2;
   static constexpr int VPT = PART / 1024 / NW;       // 1 KiB load blocks of a part per wave
   static constexpr int LOADS = 2 * VPT;              // load instructions per wave per panel
   static constexpr int64_t LEAF = int64_t(64) * 64 * (kBf ? 2 * ES : ES);  // bytes of a stored 64-leaf
@@ -715,7 +714,7 @@ struct QuadCfg {
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
   static_assert(VPT * NW * 1024 == PART, "whole load blocks per part");
   static_assert(MT == 16, "quads take 16 x 16 MFMA tiles");
-  static_assert(NP % GP == 0 && NSTAGE % GP == 0, "panel groups within a product");
+  static_assert((NP % GP == 0 || NP == 1) && NSTAGE % GP == 0, "panel groups: one product, or whole products");
 };
 
 template <int P, int V>
@@ -1075,8 +1074,8 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
   if (lmore) next_win();
   Win4 WN = load_win4(ga, PQ.sp, PQ.ns, pw, lmore && pq < u1);
 
-  // per panel in flight (up to four, one byte each, oldest lowest): bits 0-3
-  // the children that keep the step, bit 4 last panel of the step
+  // per panel in flight (up to four, one byte each, oldest lowest): the
+  // children that keep its step
   uint32_t fifo = 0;
   int ahead = 0, ist = 0, cst = 0;  // panels in flight, next stage to fill, stage to multiply
   auto issue = [&]() {
@@ -1086,7 +1085,7 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
     const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
     issue_panel<P, V>(smem + ist * Q::STAGE, base, offs, a0, a1, b0, b1, lsub, wave);
     const bool last_sub = lsub + 1 == Q::NP;
-    fifo |= (m | (last_sub ? 16u : 0u)) << (8 * ahead);
+    fifo |= m << (8 * ahead);
     ++ahead;
     ist = (ist + 1) % Q::NSTAGE;
     if (!last_sub) {
@@ -1112,19 +1111,12 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
     }
   };
 
-  Acc<P, 128, V> acc[Q::TM][Q::TN];
-  Acc<P, 128, V> part[Q::TWO_LEVEL ? Q::TM : 1][Q::TWO_LEVEL ? Q::TN : 1];
+  QAcc<P, V> acc;
   auto clear = [&]() {
 #pragma unroll
     for (int a = 0; a < Q::TM; ++a)
 #pragma unroll
       for (int b = 0; b < Q::TN; ++b) acc[a][b] = Acc<P, 128, V>{};
-    if constexpr (Q::TWO_LEVEL) {
-#pragma unroll
-      for (int a = 0; a < Q::TM; ++a)
-#pragma unroll
-        for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
-    }
   };
   clear();
 
@@ -1171,28 +1163,45 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
 #pragma unroll
       for (int k = 0; k < Q::GP; ++k)
         if (lmore) issue();  // into the stages multiplied last
+      // a wave whose child does not keep a step skips it (its SIMD partner,
+      // another child's wave, has the matrix core to itself)
+      if constexpr (!Q::TWO_LEVEL) {  // FP64: one level
 #pragma unroll
-      for (int k = 0; k < Q::GP; ++k) {
-        const char* As = smem + st[k] * Q::STAGE;
-        const char* Bs = As + Q::PART;
-        const bool mine = (meta[k] >> child) & 1u;
-        // a wave whose child does not keep the step skips it (its SIMD
-        // partner, another child's wave, has the matrix core to itself)
-        if (mine) {
-          if constexpr (Q::TWO_LEVEL) {
-            compute_quad_panel<P, V>(part, As, Bs, row0, col0, li, g);
-            if (meta[k] & 16u) {  // the product's sum joins the leaf's total
+        for (int k = 0; k < Q::GP; ++k)
+          if ((meta[k] >> child) & 1u)
+            compute_quad_panel<P, V>(acc, smem + st[k] * Q::STAGE, smem + st[k] * Q::STAGE + Q::PART, row0, col0,
+                                     li, g);
+      } else if constexpr (Q::NP == 1) {  // BF16: a product per panel, its sum from zero
 #pragma unroll
-              for (int a = 0; a < Q::TM; ++a)
+        for (int k = 0; k < Q::GP; ++k)
+          if ((meta[k] >> child) & 1u) {
+            QAcc<P, V> part;
 #pragma unroll
-                for (int b = 0; b < Q::TN; ++b) {
-                  acc[a][b] += part[a][b];
-                  part[a][b] = Acc<P, 128, V>{};
-                }
-            }
-          } else {
-            compute_quad_panel<P, V>(acc, As, Bs, row0, col0, li, g);
+            for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+              for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
+            compute_quad_panel<P, V>(part, smem + st[k] * Q::STAGE, smem + st[k] * Q::STAGE + Q::PART, row0,
+                                     col0, li, g);
+#pragma unroll
+            for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+              for (int b = 0; b < Q::TN; ++b) acc[a][b] += part[a][b];
           }
+      } else {  // the group is one product (both panels of one step)
+        if ((meta[0] >> child) & 1u) {
+          QAcc<P, V> part;
+#pragma unroll
+          for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+            for (int b = 0; b < Q::TN; ++b) part[a][b] = Acc<P, 128, V>{};
+#pragma unroll
+          for (int k = 0; k < Q::GP; ++k)
+            compute_quad_panel<P, V>(part, smem + st[k] * Q::STAGE, smem + st[k] * Q::STAGE + Q::PART, row0,
+                                     col0, li, g);
+#pragma unroll
+          for (int a = 0; a < Q::TM; ++a)
+#pragma unroll
+            for (int b = 0; b < Q::TN; ++b) acc[a][b] += part[a][b];
         }
       }
     }
@@ -1211,6 +1220,13 @@ static int max_groups_quad(int n_cu) {
     return v;
   }();
   return per_cu * n_cu;
+}
+
+bool gemm_quad_pad_even(int prec) {
+  static_assert(QuadCfg<SPAMM_BF16, 1>::NP == 1 && QuadCfg<SPAMM_F32, 1>::NP % 2 == 0 &&
+                    QuadCfg<SPAMM_BF16X3, 1>::NP % 2 == 0 && QuadCfg<SPAMM_F64, 0>::NP % 2 == 0,
+                "only BF16 has one panel per product");
+  return prec == SPAMM_BF16;
 }
 
 bool gemm_quad_supported(int prec, int bs) { return bs == 64 && prec >= SPAMM_F64 && prec <= SPAMM_BF16X3; }

@@ -13,9 +13,12 @@
 // each child's k in an LDS bit set, walks k in chunks of 64 (one lane per
 // k) and writes the steps; a child's product index at k is the count of its
 // set bits below k (ballot prefix).  A quad's steps are no more than its
-// children's products, so they go at the position of its first product in
-// the request's product list, with no scan; the cost (steps + 1) by quad
-// index feeds the workgroup ranges.
+// children's products, plus one when the count is padded to even (a step
+// no child keeps, for kernels that take two steps per barrier), so they go
+// at (its first product's index in the request's list) + (its first C
+// leaf's slot in the request), which leaves every quad products + 1 slots
+// in Morton order, with no scan; the cost (steps + 1) by quad index feeds
+// the workgroup ranges.
 #include "internal.h"
 #include "kern_common.h"
 
@@ -48,7 +51,8 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
                                                                const int64_t* __restrict__ flag,
                                                                const int64_t* __restrict__ qpos,
                                                                QuadUnit* __restrict__ qu, int64_t* __restrict__ cost,
-                                                               int4* __restrict__ steps, uint8_t* __restrict__ smask) {
+                                                               int4* __restrict__ steps, uint8_t* __restrict__ smask,
+                                                               int pad_even) {
   __shared__ uint32_t bits[kQuadWaves][4][kQuadMaxG / 32];
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t u = int64_t(blockIdx.x) * kQuadWaves + w;
@@ -81,8 +85,9 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
       ++n;
     }
   }
-  const int64_t sp = R.qbase + off[0];
+  const int64_t sp = R.qbase + off[0] + (int64_t(w0.cidx) - R.cidx);
   int32_t t = 0;  // steps written
+  int4 last = make_int4(-1, -1, -1, -1);  // the last step written
   if (kmax >= 0) {
     uint32_t(*B)[kQuadMaxG / 32] = bits[w];
     const int w0i = (kmin & ~63) >> 5, w1i = (kmax | 63) >> 5;  // words of the chunks walked
@@ -127,8 +132,20 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
         steps[at] = make_int4(a[0], a[1], b[0], b[1]);
         smask[at] = uint8_t(m);
       }
+      if (any) {
+        const int hi = 63 - __builtin_clzll(any);  // the lane of the chunk's last step
+        last = make_int4(__builtin_amdgcn_readlane(a[0], hi), __builtin_amdgcn_readlane(a[1], hi),
+                         __builtin_amdgcn_readlane(b[0], hi), __builtin_amdgcn_readlane(b[1], hi));
+      }
       t += popc64(any);
     }
+  }
+  if (pad_even && (t & 1)) {  // a step no child keeps, over the last step's leaves
+    if (lane == 0) {
+      steps[sp + t] = last;
+      smask[sp + t] = 0;
+    }
+    ++t;
   }
   if (lane == 0) {
     const int64_t qi = qpos[u];
@@ -144,10 +161,11 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
 }
 
 hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
-                            const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask) {
+                            const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask,
+                            int pad_even) {
   if (nwu == 0) return hipSuccess;
   hipLaunchKernelGGL(k_quad_plan, dim3(uint32_t((nwu + kQuadWaves - 1) / kQuadWaves)), dim3(kQuadWaves * 64), 0, s,
-                     reqs, wu, nwu, flag, qpos, qu, cost, steps, smask);
+                     reqs, wu, nwu, flag, qpos, qu, cost, steps, smask, pad_even);
   return hipGetLastError();
 }
 

@@ -184,8 +184,8 @@ def test_quad_graph_replays(ctx):
 
 def test_automatic_choice_follows_products_per_leaf(ctx):
     """With the default (-1) a launch group runs quads when its C leaves
-    average enough kept products for its precision (FP64: 128, split BF16:
-    16): a 3D product of 64 products per C leaf runs FP64 on the one-leaf
+    average enough kept products for its precision (FP64: 128, the BF16
+    forms: 16): a 3D product of 64 products per C leaf runs FP64 on the one-leaf
     GEMM and split BF16 on quads, each bit for bit as when forced."""
     import torch
     print("case: automatic quad choice", flush=True)
