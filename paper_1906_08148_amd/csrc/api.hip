@@ -1473,7 +1473,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
         ga.wn = P<double>(wn) + u0;
         ga.wt = P<double>(wt) + u0;
         ga.kx = kx;
-        ga.interleave = 0;
+        ga.interleave = std::max(c->gemm_interleave, 0);  // automatic: contiguous ranges
         ga.qu = qu;
         ga.steps = steps;
         ga.smask = smask;

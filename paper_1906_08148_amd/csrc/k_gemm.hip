@@ -1035,16 +1035,34 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
   const char* const base = ga.base;
   const QuadOffs<P, V> offs = quad_offsets<P, V>(wave, lane);
 
-  // this workgroup's contiguous range of quads (the last range is cut at
-  // the number of quads, known on the device only)
+  // the quads this workgroup visits (visit t = 0 .. u1 - 1): a contiguous
+  // range of equal cost, or the XCD's share dealt round-robin over its
+  // workgroups in chunks (Morton-adjacent quads running together share
+  // their operand leaves in the XCD's L2); ranges are cut at the number of
+  // quads, known on the device only
   const int xcd = int(blockIdx.x % kXcds), j = int(blockIdx.x / kXcds);
-  const int rank = xcd * ga.kx + j;
   const int64_t nq = *ga.nq;
-  const int64_t q0 = ga.start[rank];
-  const int64_t u1 = min(ga.start[rank + 1], nq) - q0;  // quads q0 .. q0 + u1 - 1
+  Visits vs;
+  if (ga.interleave > 0) {
+    const int64_t lo = min(ga.start[xcd * ga.kx], nq), hi = min(ga.start[(xcd + 1) * ga.kx], nq);
+    const int64_t c = ga.interleave, N = hi - lo, nch = (N + c - 1) / c;
+    const int64_t mine = j < nch ? (nch - j + ga.kx - 1) / ga.kx : 0;  // chunks j, j + kx, ...
+    vs.ubase = lo + int64_t(j) * c;
+    vs.cstride = int64_t(ga.kx) * c;
+    vs.chunk = c;
+    vs.n = mine * c;
+    if (mine > 0 && j + (mine - 1) * ga.kx == nch - 1 && N % c) vs.n -= c - N % c;  // the last chunk is partial
+  } else {
+    const int rank = xcd * ga.kx + j;
+    vs.ubase = ga.start[rank];
+    vs.cstride = 0;
+    vs.chunk = int64_t(1) << 62;
+    vs.n = min(ga.start[rank + 1], nq) - vs.ubase;
+  }
+  const int64_t u1 = vs.n;
   if (u1 <= 0) return;
   const GemmArgs* gp = &ga;
-  auto rec = [&](int64_t q) { return quad_at(*gp, q0 + q); };
+  auto rec = [&](int64_t t) { return quad_at(*gp, vs.unit(t)); };
 
   // loader: quad lq (with steps), step ls, panel lsub; WL holds the window of
   // step ls, WN the window after it, at (pq, pw)
