@@ -665,10 +665,11 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V
 // A quad (four sibling 64-leaves of C, see k_quad.hip) runs on a 128 x 128
 // tile: the A panel stacks the A leaves of the two row halves and the B
 // panel puts the B leaves of the two column halves side by side, so each
-// staged leaf serves both children of its row (column).  Eight waves, two
-// per child: wave w owns columns 32 (w % 2) .. + 31 of child w / 2 (2 * row
-// half + column half), so two waves share each SIMD and one's MFMAs run
-// while the other waits.  A merged step is one k: the waves of the
+// staged leaf serves both children of its row (column).  Each child (2 *
+// row half + column half) has its own waves, each a 32-column tile of it:
+// two waves of 64 rows (two waves per SIMD), or for FP64 four of 32 rows
+// (four per SIMD, so one's MFMAs run while the others wait on their
+// operand reads).  A merged step is one k: the waves of the
 // children that keep it add the product to their C leaf, the others only
 // take part in the barriers.  Each child sums its own products k
 // ascending, in the same panels and MFMA order whatever its siblings keep.
@@ -692,8 +693,11 @@ struct QuadCfg {
   static constexpr bool kBf = G::kBf;
   static constexpr int NH = G::NH, ES = G::ES, MT = G::MT, NG = G::NG, AE = G::AE;
   static constexpr bool TWO_LEVEL = G::TWO_LEVEL;
-  static constexpr int NW = 8, NT = NW * 64;         // two waves per child
-  static constexpr int TILE_M = 64, TILE_N = 32;     // a wave's part of its child
+  // waves: FP64 four per child (32 x 32 of it each, four waves per SIMD to
+  // hide the operand reads: 2% faster than two), the others two (64 x 32)
+  static constexpr int NW = P == SPAMM_F64 ? 16 : 8, NT = NW * 64;
+  static constexpr int WPC = NW / 4;                 // waves per child
+  static constexpr int TILE_M = WPC == 4 ? 32 : 64, TILE_N = 32;  // a wave's part of its child
   static constexpr int TM = TILE_M / MT, TN = TILE_N / MT;
   static constexpr int PART = 16384;                 // bytes of the A (or B) part of a stage
   static constexpr int KP = PART / (128 * ES * NH);  // k per panel: 64 BF16, 32 BF16X3 / FP32, 16 FP64
@@ -847,7 +851,9 @@ __device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ b
 __device__ __forceinline__ void wait_loads(int n) {
   switch (n) {
     case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
     case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
     case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
     default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
   }
@@ -960,7 +966,8 @@ __device__ __forceinline__ void compute_quad_panel(QAcc<P, V>& acc, const char* 
 // point (it holds a workgroup barrier); red: 2 * 8 partial sums.
 template <int P, int V>
 __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q, QAcc<P, V>& acc, double* red,
-                                              int wave, int lane, int child, int ccol0, int li, int g) {
+                                              int wave, int lane, int child, int crow0, int ccol0, int li,
+                                              int g) {
   using Q = QuadCfg<P, V>;
   using Out = typename GemmCfg<P, 128, V>::Out;
   const bool present = (q.cmask >> child) & 1;
@@ -991,7 +998,7 @@ __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q
       for (int b = 0; b < Q::TN; ++b)
 #pragma unroll
         for (int v = 0; v < Q::AE; ++v) {
-          const int row = a * Q::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
+          const int row = crow0 + a * Q::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
           const int col = ccol0 + b * Q::MT + li;
           Out val = Out(acc[a][b][v]);
           if (has_ep) {
@@ -1012,14 +1019,20 @@ __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q
     }
   }
   __syncthreads();
-  if (present && (wave & 1) == 0 && lane == 0) {  // the child's two halves, left first
-    as_global(ga.wn)[u] = red[wave] + red[wave + 1];
-    if (ci == cj) as_global(ga.wt)[u] = red[Q::NW + wave] + red[Q::NW + wave + 1];
+  if (present && wave % Q::WPC == 0 && lane == 0) {  // the child's parts, in wave order
+    double s = 0.0, t = 0.0;
+#pragma unroll
+    for (int x = 0; x < Q::WPC; ++x) {
+      s += red[wave + x];
+      t += red[Q::NW + wave + x];
+    }
+    as_global(ga.wn)[u] = s;
+    if (ci == cj) as_global(ga.wt)[u] = t;
   }
 }
 
 template <int P, int V>
-__global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
+__global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const GemmArgs ga) {
   using Q = QuadCfg<P, V>;
   __shared__ __attribute__((aligned(1024))) char smem[Q::NSTAGE * Q::STAGE];
   // partial norm and diagonal sums of the epilogue, two sets used in turn
@@ -1028,9 +1041,10 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int child = wave >> 1;  // the C leaf (2 * row half + column half) this wave works on
-  const int ccol0 = (wave & 1) * Q::TILE_N;                        // the wave's columns in the child
-  const int row0 = (child >> 1) * 64, col0 = (child & 1) * 64 + ccol0;  // ... and in the quad
+  const int child = wave / Q::WPC;  // the C leaf (2 * row half + column half) this wave works on
+  const int part_ = wave % Q::WPC;
+  const int crow0 = (part_ / 2) * Q::TILE_M, ccol0 = (part_ % 2) * Q::TILE_N;  // the wave's tile in the child
+  const int row0 = (child >> 1) * 64 + crow0, col0 = (child & 1) * 64 + ccol0;  // ... and in the quad
   const int li = lane % Q::MT, g = lane / Q::MT;
   const char* const base = ga.base;
   const QuadOffs<P, V> offs = quad_offsets<P, V>(wave, lane);
@@ -1145,7 +1159,7 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
     while (cq < u1) {
       const QuadS E = rec(cq);
       if (E.ns != 0) break;
-      epilogue_quad<P, V>(*gp, E, acc, red2[cq & 1], wave, lane, child, ccol0, li, g);
+      epilogue_quad<P, V>(*gp, E, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
       ++cq;
     }
   };
@@ -1183,12 +1197,14 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
         if (lmore) issue();  // into the stages multiplied last
       // a wave whose child does not keep a step skips it (its SIMD partner,
       // another child's wave, has the matrix core to itself)
-      if constexpr (!Q::TWO_LEVEL) {  // FP64: one level
+      if constexpr (!Q::TWO_LEVEL) {  // FP64: one level; the group is two panels of one step
+        static_assert(Q::NP % Q::GP == 0, "a group within one step");
+        if ((meta[0] >> child) & 1u) {
 #pragma unroll
-        for (int k = 0; k < Q::GP; ++k)
-          if ((meta[k] >> child) & 1u)
+          for (int k = 0; k < Q::GP; ++k)
             compute_quad_panel<P, V>(acc, smem + st[k] * Q::STAGE, smem + st[k] * Q::STAGE + Q::PART, row0, col0,
                                      li, g);
+        }
       } else if constexpr (Q::NP == 1) {  // BF16: a product per panel, its sum from zero
 #pragma unroll
         for (int k = 0; k < Q::GP; ++k)
@@ -1223,7 +1239,7 @@ __global__ void __launch_bounds__(512, 1) k_gemm_quad(const GemmArgs ga) {
         }
       }
     }
-    epilogue_quad<P, V>(ga, C, acc, red2[cq & 1], wave, lane, child, ccol0, li, g);
+    epilogue_quad<P, V>(ga, C, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
     clear();
     ++cq;
     flush_empty();
@@ -1234,7 +1250,9 @@ template <int P, int V>
 static int max_groups_quad(int n_cu) {
   static const int per_cu = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, 512, 0) != hipSuccess || v < 1) v = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, QuadCfg<P, V>::NT, 0) != hipSuccess ||
+        v < 1)
+      v = 1;
     return v;
   }();
   return per_cu * n_cu;
@@ -1271,7 +1289,8 @@ int gemm_quad_max_groups(int prec, int n_cu) {
 
 hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a) {
   return dispatch_quad(prec, [&](auto pc, auto vc) -> hipError_t {
-    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)), dim3(512),
+    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)),
+                       dim3(QuadCfg<decltype(pc)::value, decltype(vc)::value>::NT),
                        0, s, a);
     return hipGetLastError();
   });
