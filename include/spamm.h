@@ -207,13 +207,14 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       launch that (an instantiated graph of the same shape
  *                       is updated in place).  Ignored while event timing
  *                       is on.
- *  SPAMM_OPT_UNIT_ORDER c in 1..1024: the C leaves an XCD works on are dealt
- *                       round-robin over its workgroups in chunks of c
- *                       consecutive leaves, so the workgroups move through
- *                       the slice together (less L2 traffic); 0: each
- *                       workgroup takes a contiguous range of equal cost;
- *                       -1 (default): per launch, 1 when the C leaves average
- *                       fewer than 16 products, else 0.
+ *  SPAMM_OPT_UNIT_ORDER c in 1..1024: the C leaves (quads) an XCD works on
+ *                       are dealt round-robin over its workgroups in chunks
+ *                       of c consecutive ones, so the workgroups move
+ *                       through the slice together (less L2 traffic); 0:
+ *                       each workgroup takes a contiguous range of equal
+ *                       cost; -1 (default): per launch, 1 when the C leaves
+ *                       average fewer than 16 products, else 0, and 0 for
+ *                       quads.
  *  SPAMM_OPT_VALIDATE   0 (default): spamm_stats.val_err = -1; 1: every
  *                       product that is not FP64 runs beside an FP64 twin
  *                       (same operands, tau, mode and epilogue) in the same

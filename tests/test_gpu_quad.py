@@ -43,6 +43,9 @@ CASES = [
     (700, "1d", 0.3, 1e-4, MODES),          # narrow band, G = 16
     (2048, "3d", 1.0, 3e-3, MODES),         # 3D decay, some products pruned
     (3000, "3d", 1.0, 3e-3, (spamm.SPAMM,)),  # G = 64, ragged, a third of the products kept
+    (50, "1d", 0.3, 1e-6, MODES),           # a single C leaf (one quad of one child)
+    (100, "1d", 0.3, 1e-6, MODES),          # G = 2: one full quad
+    (200, "1d", 0.05, 1e-5, MODES),         # G = 4, ragged
 ]
 
 
