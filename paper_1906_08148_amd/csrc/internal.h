@@ -348,8 +348,8 @@ struct GemmArgs {
   int32_t interleave;    // c > 0: an XCD's units [start[x*kx], start[(x+1)*kx]) dealt round-robin over its
                          // workgroups in chunks of c; 0: workgroup rank r takes [start[r], start[r+1])
   // quad launches: the quads, and per merged step the A leaves of the two
-  // row halves and the B leaves of the two column halves (-1: not needed)
-  // and the children that take part (bit c)
+  // row halves and the B leaves of the two column halves (a half no child
+  // needs repeats its partner's) and the children that take part (bit c)
   const QuadUnit* qu;
   const int4* steps;
   const uint8_t* smask;

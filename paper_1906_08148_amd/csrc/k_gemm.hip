@@ -675,12 +675,14 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V
 // ascending, in the same panels and MFMA order whatever its siblings keep.
 //
 // Panels move from memory to LDS by direct loads (global_load_lds, 16 bytes
-// per lane, no registers) into a ring of four stages, three panels ahead of
-// the one being multiplied: a panel's loads wait on the memory latency
-// while the three before it are multiplied.  Every panel is the same number
-// of load instructions per wave (a leaf no child of the step needs is
-// replaced by its partner's), so the wait for a panel is a fixed count of
-// later loads.  A stage is 16 KiB of A and 16 KiB of B.  A row of the A
+// per lane, no registers) into a ring of four stages: two panels are
+// multiplied per barrier while the next two load, so a group's loads wait
+// on the memory latency while the group before it is multiplied.  A leaf
+// no child of the step needs is replaced by its partner's in the plan, so
+// every panel is the same loads and a wave's wait for a group is a count
+// of its later loads.  FP64 issues a group at once (one read of the step);
+// the eight-wave kernels issue panel by panel, which their compiled loops
+// run faster.  A stage is 16 KiB of A and 16 KiB of B.  A row of the A
 // part (and of transposed BF16 B) is the panel's k of one row, its 16-byte
 // chunks XOR-swizzled by row so that the operand reads of consecutive rows
 // fall on different banks; FP32 / FP64 B is k-major, one 64-column block
@@ -718,7 +720,7 @@ struct QuadCfg {
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
   static_assert(VPT * NW * 1024 == PART, "whole load blocks per part");
   static_assert(MT == 16, "quads take 16 x 16 MFMA tiles");
-  static_assert((NP % GP == 0 || NP == 1) && NSTAGE % GP == 0, "panel groups: one product, or whole products");
+  static_assert((NP % GP == 0 || NP == 1) && NSTAGE == 2 * GP, "panel groups: one step, or GP steps; two groups in the ring");
 };
 
 template <int P, int V>
@@ -810,44 +812,55 @@ __device__ __forceinline__ QuadOffs<P, V> quad_offsets(int wave, int lane) {
 }
 
 // Direct loads of k-panel `sub` of a step (leaves a0 / a1 of the A row
-// halves, b0 / b1 of the B column halves) into stage `st`.
+// halves, b0 / b1 of the B column halves; the plan has put a partner's leaf
+// where no child of the step needs one) into stage `st`.
 template <int P, int V>
 __device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ base, const QuadOffs<P, V>& o,
                                             int32_t a0, int32_t a1, int32_t b0, int32_t b1, int sub, int wave) {
   using Q = QuadCfg<P, V>;
-  if (a0 < 0) a0 = a1;  // a leaf no child needs: load the partner's instead
-  if (a1 < 0) a1 = a0;
-  if (b0 < 0) b0 = b1;
-  if (b1 < 0) b1 = b0;
+  // FP64 takes the plan's leaves as they are, in unsigned offsets (the
+  // fewest scalar instructions); the eight-wave kernels keep the signed
+  // form with the partner check, a no-op after the plan but measured to
+  // schedule better there
+  constexpr bool kLean = P == SPAMM_F64;
+  using LT = std::conditional_t<kLean, uint32_t, int32_t>;
+  using OT = std::conditional_t<kLean, uint64_t, int64_t>;
+  using ST = std::conditional_t<kLean, uint32_t, int64_t>;
+  if constexpr (!kLean) {
+    if (a0 < 0) a0 = a1;
+    if (a1 < 0) a1 = a0;
+    if (b0 < 0) b0 = b1;
+    if (b1 < 0) b1 = b0;
+  }
 #pragma unroll
   for (int i = 0; i < Q::VPT; ++i) {
     const int blk = i * Q::NW + wave;  // 1 KiB block of the part (wave-uniform)
     // an A block's rows lie in one row half
-    const int32_t leaf = ((blk * 64 / Q::CH) % 128) < 64 ? a0 : a1;
-    const auto L = as_global(base + int64_t(leaf) * Q::LEAF + sub * (Q::KP * Q::ES));
+    const LT leaf = ((blk * 64 / Q::CH) % 128) < 64 ? a0 : a1;
+    const auto L = as_global(base + OT(leaf) * Q::LEAF + sub * (Q::KP * Q::ES));
     __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.a[i]),
                                      (__attribute__((address_space(3))) void*)(st + blk * 1024), 16, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < Q::VPT; ++i) {
     const int blk = i * Q::NW + wave;
-    int32_t leaf;
-    int64_t so;
+    LT leaf;
+    ST so;
     if constexpr (Q::kBf) {
       leaf = ((blk * 64 / Q::CH) % 128) < 64 ? b0 : b1;
       so = sub * (Q::KP * Q::ES);
     } else {
       leaf = blk < 8 ? b0 : b1;  // blocks 0-7: the left B leaf, 8-15: the right
-      so = int64_t(sub) * Q::KP * 64 * Q::ES;
+      so = ST(sub) * ST(Q::KP * 64 * Q::ES);
     }
-    const auto L = as_global(base + int64_t(leaf) * Q::LEAF + so);
+    const auto L = as_global(base + OT(leaf) * Q::LEAF + so);
     __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.b[i]),
                                      (__attribute__((address_space(3))) void*)(st + Q::PART + blk * 1024), 16, 0, 0);
   }
 }
 
 // Wait until at most n of this wave's loads are outstanding (the loads of
-// the panels issued after the one wanted).
+// the panels issued after the ones wanted).
 __device__ __forceinline__ void wait_loads(int n) {
   switch (n) {
     case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
@@ -1076,7 +1089,12 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
   const int64_t u1 = vs.n;
   if (u1 <= 0) return;
   const GemmArgs* gp = &ga;
-  auto rec = [&](int64_t t) { return quad_at(*gp, vs.unit(t)); };
+  auto rec = [&](int64_t t) {
+    if constexpr (P == SPAMM_F64)  // (contiguous ranges need no division)
+      return quad_at(*gp, vs.cstride == 0 ? vs.ubase + t : vs.unit(t));
+    else
+      return quad_at(*gp, vs.unit(t));
+  };
 
   // loader: quad lq (with steps), step ls, panel lsub; WL holds the window of
   // step ls, WN the window after it, at (pq, pw)
@@ -1110,7 +1128,26 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
   // children that keep its step
   uint32_t fifo = 0;
   int ahead = 0, ist = 0, cst = 0;  // panels in flight, next stage to fill, stage to multiply
-  auto issue = [&]() {
+  auto next_step = [&](int by) {     // ls += by (the steps stay in one window and one quad)
+    ls += by;
+    if (ls == LQ.ns) {  // the next quad with steps: its first window is WN
+      lq = pq;
+      LQ = PQ;
+      ls = 0;
+      lmore = lq < u1;
+      WL = WN;
+      if (lmore) {
+        next_win();
+        WN = load_win4(*gp, PQ.sp, PQ.ns, pw, pq < u1);
+      }
+    } else if ((ls & 63) == 0) {  // the quad's next window
+      WL = WN;
+      next_win();
+      WN = load_win4(*gp, PQ.sp, PQ.ns, pw, pq < u1);
+    }
+  };
+  // the next panel of the stream into stage ist
+  auto issue_one = [&]() {
     const int l = ls & 63;
     const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
     const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
@@ -1142,6 +1179,41 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
       }
     }
   };
+  // the next GP panels of the stream into stages ist, ist + 1: GP k-panels
+  // of one step, or (one panel per product) GP steps, which share a window
+  // (the step counts are even)
+  auto issue_group = [&]() {
+    char* const st = smem + ist * Q::STAGE;
+    if constexpr (Q::NP % Q::GP == 0) {
+      const int l = ls & 63;
+      const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
+      const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
+      const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
+#pragma unroll
+      for (int k = 0; k < Q::GP; ++k) {
+        issue_panel<P, V>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, lsub + k, wave);
+        fifo |= m << (8 * (ahead + k));
+      }
+      lsub += Q::GP;
+      if (lsub == Q::NP) {
+        lsub = 0;
+        next_step(1);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q::GP; ++k) {
+        const int l = (ls + k) & 63;
+        const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
+        const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
+        const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
+        issue_panel<P, V>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, 0, wave);
+        fifo |= m << (8 * (ahead + k));
+      }
+      next_step(Q::GP);
+    }
+    ahead += Q::GP;
+    ist = (ist + Q::GP) & (Q::NSTAGE - 1);
+  };
 
   QAcc<P, V> acc;
   auto clear = [&]() {
@@ -1165,7 +1237,22 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
   };
   flush_empty();
 
-  for (int i = 0; i < Q::NSTAGE - Q::GP && lmore; ++i) issue();
+  // the loader: FP64 (sixteen waves) reads a group's steps once, the
+  // eight-wave kernels panel by panel (each measured faster that way)
+  auto issue_next = [&]() {
+    if constexpr (P == SPAMM_F64) {
+      if (lmore) issue_group();
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q::GP; ++k)
+        if (lmore) issue_one();
+    }
+  };
+  if constexpr (P == SPAMM_F64) {
+    if (lmore) issue_group();
+  } else {
+    for (int i = 0; i < Q::NSTAGE - Q::GP && lmore; ++i) issue_one();
+  }
   // the quads with steps in order, each over its panels (the loader issued
   // exactly these panels in this order), GP panels per barrier
   while (cq < u1) {
@@ -1180,21 +1267,29 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
       ls = __builtin_amdgcn_readfirstlane(ls);
       lsub = __builtin_amdgcn_readfirstlane(lsub);
       lmore = __builtin_amdgcn_readfirstlane(int32_t(lmore)) != 0;
-      wait_loads((ahead - Q::GP) * Q::LOADS);  // this wave's loads of the oldest GP panels are in LDS
-      lds_barrier();                            // every wave's are, and the stages multiplied last are free
+      // this wave's loads of the oldest GP panels are in LDS (FP64: all it
+      // issued, the ring holding two groups)
+      if constexpr (P == SPAMM_F64)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      else
+        wait_loads((ahead - Q::GP) * Q::LOADS);
+      lds_barrier();  // every wave's are, and the stages multiplied last are free
       uint32_t meta[Q::GP];
       int st[Q::GP];
 #pragma unroll
       for (int k = 0; k < Q::GP; ++k) {  // the oldest panels leave the queue
         meta[k] = fifo & 0xffu;
         fifo >>= 8;
-        st[k] = cst;
-        cst = (cst + 1) % Q::NSTAGE;
+        if constexpr (P == SPAMM_F64) {
+          st[k] = cst + k;  // (a group's stages are adjacent)
+        } else {
+          st[k] = cst;
+          cst = (cst + 1) % Q::NSTAGE;
+        }
       }
+      if constexpr (P == SPAMM_F64) cst = (cst + Q::GP) & (Q::NSTAGE - 1);
       ahead -= Q::GP;
-#pragma unroll
-      for (int k = 0; k < Q::GP; ++k)
-        if (lmore) issue();  // into the stages multiplied last
+      issue_next();  // the next group, into the stages multiplied last
       // a wave whose child does not keep a step skips it (its SIMD partner,
       // another child's wave, has the matrix core to itself)
       if constexpr (!Q::TWO_LEVEL) {  // FP64: one level; the group is two panels of one step

@@ -5,8 +5,9 @@
 // request's work units with one parent (placement keeps a request's C leaves
 // in Morton order, so siblings are neighbours); its children's products, each
 // list k ascending, are merged into steps in ascending k: a step names the
-// A leaves of the two row halves, the B leaves of the two column halves and
-// the children that keep that k.  Every child still sums its own products k
+// A leaves of the two row halves, the B leaves of the two column halves (a
+// half no child of the step needs repeats its partner's leaf) and the
+// children that keep that k.  Every child still sums its own products k
 // ascending, so C does not depend on which siblings share its quad.
 //
 // The plan: quad starts (flag) and their scan, then one wave per quad marks
@@ -127,6 +128,12 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
         done[i] += popc64(bal);
       }
       const uint64_t any = ballot64(m != 0);
+      // a half no child of the step needs takes its partner's leaf (every
+      // leaf of a step is then loadable; the children mask says who uses it)
+      if (a[0] < 0) a[0] = a[1];
+      if (a[1] < 0) a[1] = a[0];
+      if (b[0] < 0) b[0] = b[1];
+      if (b[1] < 0) b[1] = b[0];
       if (m != 0) {
         const int64_t at = sp + t + popc64(any & lt);
         steps[at] = make_int4(a[0], a[1], b[0], b[1]);
