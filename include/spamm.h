@@ -232,8 +232,9 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       MFMA tiles whatever GEMM_TILE says.  0: every C leaf
  *                       is one work unit of the one-leaf GEMM.  -1 (default):
  *                       quads for a launch group (one precision) whose C
- *                       leaves average at least 128 (FP64, FP32) or 16 (BF16,
- *                       split BF16) kept products, the one-leaf GEMM below.
+ *                       leaves average at least 32 (FP64), 128 (FP32) or 16
+ *                       (BF16, split BF16) kept products, the one-leaf GEMM
+ *                       below.
  *                       Other leaf sizes ignore the option.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
  * and GEMM_QUAD change the order of the sums inside one MFMA or one k-panel

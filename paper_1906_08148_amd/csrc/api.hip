@@ -115,7 +115,8 @@ bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || b
 bool quad_group(const Ctx* c, int prec, int bs, int64_t kept, int64_t leaves) {
   if (c->gemm_quad == 0 || !gemm_quad_supported(prec, bs)) return false;
   if (c->gemm_quad == 1) return true;
-  const int64_t per_leaf = prec == SPAMM_F64 || prec == SPAMM_F32 ? 128 : 16;
+  // measured crossovers against the one-leaf GEMM (3D and 1D decay)
+  const int64_t per_leaf = prec == SPAMM_F64 ? 32 : prec == SPAMM_F32 ? 128 : 16;
   return kept >= per_leaf * std::max<int64_t>(leaves, 1);
 }
 

@@ -187,14 +187,15 @@ def test_quad_graph_replays(ctx):
 
 def test_automatic_choice_follows_products_per_leaf(ctx):
     """With the default (-1) a launch group runs quads when its C leaves
-    average enough kept products for its precision (FP64: 128, the BF16
-    forms: 16): a 3D product of 64 products per C leaf runs FP64 on the one-leaf
-    GEMM and split BF16 on quads, each bit for bit as when forced."""
+    average enough kept products for its precision (FP64: 32, FP32: 128,
+    the BF16 forms: 16): a 3D product of 64 products per C leaf runs FP32
+    on the one-leaf GEMM and FP64 and split BF16 on quads, each bit for bit
+    as when forced."""
     import torch
     print("case: automatic quad choice", flush=True)
     A = synth.DecaySpec("3d", 4096, 1.0, seed=13).dense()
     M = ctx.build(dev(A), 64, stores=ALL)
-    for prec, want in ((spamm.F64, 0), (spamm.BF16X3, 1)):
+    for prec, want in ((spamm.F32, 0), (spamm.F64, 1), (spamm.BF16X3, 1)):
         ctx.set_option("gemm_quad", -1)
         ctx.timing(enable=True, reset=True)
         auto = ctx.multiply(M, M, 1e-9, mode=spamm.SPAMM, prec=prec)
