@@ -503,11 +503,13 @@ def paper_workloads():
     return {"model_problem": model, "leaf_library": sweep}
 
 
-def purification(steps, mode=None):
+def purification(steps, mode=None, tau_c=0.0):
     """20 trace-driven purification steps (X^2 or 2X - X^2, tau 1e-6, the
     symmetric square of Hybrid by default: the iterates are symmetric) on the
     3D decay matrix n = 32768 scaled into [0, 1], FP64 and FP32 chains side
-    by side; per step the trace, products, time and ||X32 - X64||_F."""
+    by side; per step the trace, products, time and ||X32 - X64||_F.  With
+    tau_c > 0 every iterate is truncated after its product (mirror pairs,
+    budget tau_c)."""
     import torch
     import synth
     from paper_1906_08148_amd import purify, spamm
@@ -519,12 +521,14 @@ def purification(steps, mode=None):
     torch.cuda.synchronize()
     del dA
     mode = spamm.HYBRID_SYM if mode is None else mode
-    recs, diffs, (lo, hi) = purify.sp2(ctx, X, N3D / 2, TAU3D, steps, precs=(spamm.F64, spamm.F32), mode=mode)
+    recs, diffs, (lo, hi) = purify.sp2(ctx, X, N3D / 2, TAU3D, steps, precs=(spamm.F64, spamm.F32), mode=mode,
+                                       tau_c=tau_c)
     X.release()
     ctx.close()
     out = {"workload": f"SP2 purification of the 3D decay matrix n={N3D}, leaf {LEAF3D}, "
                        f"{'hybrid_sym' if mode == spamm.HYBRID_SYM else 'hybrid'}, tau {TAU3D}, n_occ = n/2, "
-                       f"{steps} steps", "gershgorin": [lo, hi], "steps": []}
+                       f"{steps} steps" + (f", iterates truncated with tau_c {tau_c}" if tau_c > 0 else ""),
+           "gershgorin": [lo, hi], "steps": []}
     for k in range(steps):
         r64, r32 = recs[spamm.F64][k], recs[spamm.F32][k]
         out["steps"].append({"k": k, "trace64": round(r64.trace, 6), "trace32": round(r32.trace, 6),
@@ -533,6 +537,8 @@ def purification(steps, mode=None):
                              "ms64": round(r64.seconds * 1e3, 1), "ms32": round(r32.seconds * 1e3, 1),
                              "gflops32": round(r32.flops / r32.seconds / 1e9, 1),
                              "idempotency64": r64.idempotency, "x32_minus_x64": diffs[spamm.F32][k]})
+        if tau_c > 0:
+            out["steps"][-1].update(leaves64=r64.nonnull, dropped_sq64=r64.dropped_sq)
     t64 = sum(r.seconds for r in recs[spamm.F64])
     t32 = sum(r.seconds for r in recs[spamm.F32])
     out["total_s"] = {"f64": round(t64, 3), "f32": round(t32, 3)}

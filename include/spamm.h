@@ -76,12 +76,13 @@ typedef enum spamm_mode {
                           holds them).  If A's null map (or D's) is not
                           symmetric, every C leaf is formed as in SPAMM.
                           The caller asserts that A (and D) are symmetric. */
-  SPAMM_HYBRID_SYM = 4 /* the same for Hybrid: A is truncated as in HYBRID;
-                          if the truncated null map is symmetric, the upper
-                          C leaves are formed and mirrored as above, else
-                          (the truncation boundary split a mirror pair) the
-                          full Hybrid product is formed.  The check runs on
-                          the device; no extra synchronisation.            */
+  SPAMM_HYBRID_SYM = 4 /* the same for Hybrid: A is truncated in mirror
+                          pairs (spamm_truncate_symmetric), which keeps a
+                          symmetric null map symmetric; if the truncated
+                          null map is symmetric, the upper C leaves are
+                          formed and mirrored as above, else the full
+                          Hybrid product is formed.  The check runs on the
+                          device; no extra synchronisation.                */
 } spamm_mode;
 
 /* Arithmetic of the leaf products.  The norms, the tau tests and all error
@@ -314,6 +315,21 @@ spamm_status spamm_build_blocks_batch(spamm_ctx* ctx, int32_t count,
  * Synchronises once.  Errors: EINVAL, ENOMEM, EDEVICE. */
 spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau,
                             spamm_mat** out, double* dropped_sq);
+
+/* The same truncation in mirror pairs, for a symmetric matrix (a reading:
+ * Sec. 3's truncation, which the paper never applies to symmetric pairs,
+ * Sec. 5.4): leaf (I, K), I < K, and leaf (K, I) form one unit of weight
+ * s_IK + s_KI (FP64 sum; a diagonal leaf is a unit of its own); units with
+ * a non-null leaf are ordered by (weight, Morton key of the upper leaf) and
+ * the longest prefix whose summed weights are <= tau^2 is dropped, both
+ * leaves of a unit together.  ||in - out||_F <= tau still holds, and a
+ * symmetric null map stays symmetric, so mirror leaves whose norms differ
+ * only by rounding are never split.  SPAMM_HYBRID_SYM truncates its operand
+ * this way; a symmetric product (a purification iterate) is truncated this
+ * way after the multiply.  Storage, `dropped_sq`, synchronisation and errors
+ * as spamm_truncate. */
+spamm_status spamm_truncate_symmetric(spamm_ctx* ctx, const spamm_mat* in, double tau,
+                                      spamm_mat** out, double* dropped_sq);
 
 /* Element-wise input truncation, the truncated matrix of Thm. 1 (Sec. 3):
  * every entry with |a_ij| < tau becomes zero, so each dropped entry is below

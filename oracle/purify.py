@@ -11,6 +11,11 @@ second-order spectral projection scheme, SP2): squaring lowers the trace,
 Before the chain, the spectrum is mapped into [0, 1] with Gershgorin bounds,
 X_0 = (hi I - A) / (hi - lo), so the smallest eigenvalues of A land near 1.
 Every product is the oracle's multiply (a chosen scheme and tau), in FP64.
+Optionally each new iterate is truncated after the product (the removal of
+small leaves from the product matrix that the paper's Introduction reports
+as common practice besides truncation before the multiply): the leaf-block
+truncation of Sec. 3 with its own budget tau_c, in mirror pairs since the
+iterates are symmetric (``truncate_pairs``), so ||X - X~||_F <= tau_c.
 """
 import numpy as np
 
@@ -34,12 +39,15 @@ def scale_unit(A: np.ndarray):
 
 
 def sp2_chain(A: np.ndarray, bs: int, n_occ: float, tau: float, steps: int, mode: int = O.HYBRID,
-              sym: bool = False):
+              sym: bool = False, tau_c: float = 0.0):
     """Run `steps` SP2 steps on A scaled into [0, 1].  Each record holds the
     trace the decision used, the branch (0: X^2, 1: 2X - X^2), the number of
     leaf products formed and the new iterate (dense FP64).  With `sym` every
     square is the symmetric square (``multiply_symmetric``): the iterates
-    stay exactly symmetric."""
+    stay exactly symmetric.  With tau_c > 0 every new iterate is truncated
+    in mirror pairs (``truncate_pairs``, budget tau_c) before it is used; the
+    record then also holds the squared norm dropped, the leaves left and
+    whether the truncation boundary was a tie."""
     X, lo, hi = scale_unit(A)
     out = []
     for _ in range(steps):
@@ -51,6 +59,12 @@ def sp2_chain(A: np.ndarray, bs: int, n_occ: float, tau: float, steps: int, mode
             Xn, branch = X2, 0
         else:
             Xn, branch = 2.0 * X - X2, 1
-        out.append(dict(trace=tr, branch=branch, n_kept=int(r.stats["n_kept"]), X=Xn))
+        rec = dict(trace=tr, branch=branch, n_kept=int(r.stats["n_kept"]))
+        if tau_c > 0.0:
+            t = O.truncate_pairs(O.build(Xn, bs), tau_c)
+            Xn = t.tree.to_dense()
+            rec.update(dropped_sq=t.dropped_sq, nonnull=t.tree.nonnull_count(), trunc_tie=t.tie)
+        rec["X"] = Xn
+        out.append(rec)
         X = Xn
     return out, (lo, hi)

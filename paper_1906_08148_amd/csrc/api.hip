@@ -804,7 +804,8 @@ spamm_status spamm_build_blocks(spamm_ctx* ctx, int64_t n, int32_t leaf, int64_t
   return spamm_build_blocks_batch(ctx, 1, &b, out);
 }
 
-spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out, double* dropped_sq) {
+static spamm_status truncate_one(spamm_ctx* ctx, const spamm_mat* in, double tau, bool pairs, spamm_mat** out,
+                                 double* dropped_sq) {
   if (!ctx || !out) return SPAMM_EINVAL;
   Ctx* c = &ctx->c;
   *out = nullptr;
@@ -813,7 +814,7 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   std::vector<std::unique_ptr<spamm_mat>> ms;
   RegionP res;
   TruncPlan tp;
-  spamm_status st = trunc_plan(c, {{in, tau, false}}, ms, res, tp);
+  spamm_status st = trunc_plan(c, {{in, tau, pairs}}, ms, res, tp);
   if (st != SPAMM_OK) return st;
   TableSet tabs;
   const size_t oj = tabs.add(tp.jobs), op = tabs.add(tp.pyr);
@@ -829,6 +830,15 @@ spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spa
   c->live_handles++;
   *out = ms[0].release();
   return SPAMM_OK;
+}
+
+spamm_status spamm_truncate(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out, double* dropped_sq) {
+  return truncate_one(ctx, in, tau, false, out, dropped_sq);
+}
+
+spamm_status spamm_truncate_symmetric(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out,
+                                      double* dropped_sq) {
+  return truncate_one(ctx, in, tau, true, out, dropped_sq);
 }
 
 spamm_status spamm_truncate_elementwise(spamm_ctx* ctx, const spamm_mat* in, double tau, spamm_mat** out,

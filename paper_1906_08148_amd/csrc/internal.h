@@ -282,7 +282,7 @@ struct TruncJob {
   const double* leafnorm;  // input leaf norms (Morton)
   int32_t* out_slot;
   double* out_norm;        // leaf level of the output pyramid
-  double* result;          // [0] dropped squared norm, [1] dropped count (leaves; pairs in the pair form)
+  double* result;          // [0] dropped squared norm, [1] non-null leaves dropped
   double tau2;
   int64_t base;            // first element in the batch's concatenated arrays
   int32_t G;

@@ -231,6 +231,15 @@ __device__ __forceinline__ TruncUnit trunc_unit(const TruncJob& J, uint32_t m) {
   return u;
 }
 
+// Non-null leaves of the unit represented by candidate m (the count that
+// leaves the matrix when the unit is dropped).
+__device__ __forceinline__ int64_t unit_leaves(const TruncJob& J, uint32_t m) {
+  if (!J.pairs) return 1;  // (a candidate leaf is non-null)
+  uint32_t i, k;
+  demorton(m, i, k);
+  return int64_t(J.slot[m] >= 0) + int64_t(i != k && J.slot[morton(k, i)] >= 0);
+}
+
 // Candidates (units with a non-null leaf and weight <= tau^2) are flagged,
 // scanned, and compacted into (weight, Morton index) lists by the scan's
 // sink, which looks up the job of flagged entries only.  In the pair form
@@ -330,7 +339,7 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
       if (f <= tau2) {
         const uint64_t xh = __double_as_longlong(cs[x]);
         const uint32_t xl = uint32_t(cm[x]);
-        ++my_cnt;
+        my_cnt += unit_leaves(J, xl);
         if (!any || !key_le(xh, xl, my_hi, my_lo)) {
           my_hi = xh;
           my_lo = xl;
@@ -396,7 +405,7 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
       const double sv = cs[i];
       if (key_le(__double_as_longlong(sv), uint32_t(cm[i]), khi, klo)) {
         part += sv;
-        ++c;
+        c += unit_leaves(J, uint32_t(cm[i]));
       }
     }
     F = block_sum_f64(part, red);
@@ -407,7 +416,7 @@ __global__ void __launch_bounds__(kSelThreads) k_trunc_select(const TruncJob* __
       for (int q = 0; q < kSelThreads / kWave; ++q) cnt += ired[q];
   }
   if (threadIdx.x == 0) {
-    // a count of zero means nothing is dropped
+    // (non-null leaves dropped; zero means nothing is dropped)
     kst[3 * blockIdx.x] = khi;
     kst[3 * blockIdx.x + 1] = klo;
     kst[3 * blockIdx.x + 2] = uint64_t(cnt);

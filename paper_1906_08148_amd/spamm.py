@@ -110,6 +110,8 @@ _SIGS = {
                                           ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     "spamm_truncate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
+    "spamm_truncate_symmetric": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
     "spamm_truncate_elementwise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
     "spamm_multiply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -293,10 +295,13 @@ class Context:
         return [Matrix(self, outs[i]) for i in range(k)]
 
     # ---- truncation / multiply
-    def truncate(self, m: Matrix, tau: float):
+    def truncate(self, m: Matrix, tau: float, symmetric: bool = False):
+        """Leaf-block truncation with budget tau (Sec. 3); symmetric: in
+        mirror pairs.  Returns (matrix, dropped squared norm)."""
         out = ctypes.c_void_p()
         dropped = ctypes.c_double()
-        self._check(_lib.spamm_truncate(self.ptr, m.handle, tau, ctypes.byref(out), ctypes.byref(dropped)))
+        fn = _lib.spamm_truncate_symmetric if symmetric else _lib.spamm_truncate
+        self._check(fn(self.ptr, m.handle, tau, ctypes.byref(out), ctypes.byref(dropped)))
         return Matrix(self, out.value), dropped.value
 
     def truncate_elementwise(self, m: Matrix, tau: float):
