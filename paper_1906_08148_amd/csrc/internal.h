@@ -18,15 +18,14 @@ namespace spamm {
 
 // ---------------------------------------------------------------- arena
 
-// First-fit sub-allocator over one caller-owned device buffer.  Free ranges
-// are kept in an ordered map and coalesced on release.  All reuse is ordered
-// on the context's single stream.
-// First-fit ranges over the caller's buffer, with an exact-size cache in
+// Sub-allocator over one caller-owned device buffer: first-fit free ranges
+// in an ordered map, coalesced on release, with an exact-size cache in
 // front: a released range waits in the bucket of its (size, alignment) and
 // the next request of that shape takes it back in O(1) (the multiply and
 // build calls repeat their shapes from batch to batch).  The buckets return
 // to the coalescing range map when a request finds no fit, and before the
-// largest free range is reported.
+// largest free range is reported.  All reuse is ordered on the context's
+// single stream.
 class Arena {
  public:
   void init(char* base, size_t bytes);
