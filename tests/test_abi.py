@@ -52,3 +52,8 @@ def test_null_handles_are_rejected(lib):
     info = spamm.MatInfo()
     assert lib.spamm_mat_info_get(None, ctypes.byref(info)) == 1
     assert lib.spamm_ctx_destroy(None) == 1
+    out = ctypes.c_void_p()
+    d = ctypes.c_double()
+    for fn in (lib.spamm_truncate, lib.spamm_truncate_symmetric, lib.spamm_truncate_elementwise):
+        assert fn(None, None, 1.0, ctypes.byref(out), ctypes.byref(d)) == 1  # EINVAL, no context
+        assert fn(None, None, 1.0, None, None) == 1
