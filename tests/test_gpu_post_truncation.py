@@ -148,3 +148,39 @@ def test_sp2_with_truncated_iterates_matches_oracle(ctx):
     for m in (c64.X, c32.X, ident, X):
         m.release()
     torch.cuda.synchronize()
+
+
+def test_symmetric_truncation_edge_cases(ctx):
+    """The mirror-pair form on its own: tau = 0 drops nothing, a budget
+    above ||A||_F drops every leaf, and on random blocks (a null map that is
+    not symmetric, ragged n) a leaf whose mirror is null is a unit alone of
+    its own weight; against the oracle's pair truncation of the same input."""
+    print("case: symmetric truncation edge cases", flush=True)
+    A = synth.DecaySpec("3d", 1000, 1.0, seed=23).dense()  # G = 16, ragged
+    T = O.build(A, 64)
+    M = ctx.build(dev(A), 64)
+    Mt, dropped = ctx.truncate(M, 0.0, symmetric=True)
+    assert dropped == 0.0 and Mt.info.nonnull == M.info.nonnull
+    Mt.release()
+    Mt, dropped = ctx.truncate(M, 2.0 * T.fro(), symmetric=True)
+    assert Mt.info.nonnull == 0
+    assert not np.any(leaf_map(ctx, Mt))
+    assert abs(dropped - T.fro() ** 2) <= 1e-12 * T.fro() ** 2
+    Mt.release()
+    M.release()
+    c, d = synth.random_blocks(31, 1000, 64, 0.4)
+    keep = ~((c[:, 0] > c[:, 1]) & ((c[:, 0] + c[:, 1]) % 3 == 0))  # some lower leaves lose their mirror
+    c, d = c[keep], d[keep]
+    T = O.build_from_blocks(1000, 64, c, d)
+    assert not np.array_equal(T.leaf_present, T.leaf_present.T)
+    M = ctx.build_blocks(1000, 64, dev(c.astype(np.int32)), dev(d))
+    for tau in budgets(T, True, 1e-9):
+        tr = O.truncate_pairs(T, tau)
+        assert not tr.tie
+        Mt, dropped = ctx.truncate(M, tau, symmetric=True)
+        assert Mt.info.nonnull == tr.tree.nonnull_count()
+        assert np.array_equal(leaf_map(ctx, Mt), tr.tree.leaf_present)
+        assert abs(dropped - tr.dropped_sq) <= 1e-12 * tr.dropped_sq
+        assert np.array_equal(ctx.to_dense(Mt).cpu().numpy(), tr.tree.to_dense())
+        Mt.release()
+    M.release()
