@@ -374,7 +374,8 @@ def symmetric_3d(ctx, dA, C64):
 
 
 def autotune_3d(ctx, dA):
-    """Leaf size (32 ... 256) and MFMA tile picked by the autotuner for the 3D
+    """Leaf size (32 ... 256), MFMA tile and C leaves per workgroup (one, or
+    quads at leaf 64) picked by the autotuner for the 3D
     workload (Hybrid, tau 1e-6) per precision, among the candidates whose
     error meets sigma = 1e-5 ||A||_F^2: by the library's guaranteed bound,
     and by the error measured against the exact product."""
@@ -394,12 +395,13 @@ def autotune_3d(ctx, dA):
             best = tuner.tune(lambda leaf: ctx.build(dA, leaf, stores=store_for(prec)), sig,
                               TAU3D, spamm.HYBRID, prec, budget=budget, error_fn=fn)
             out[f"{PREC_NAMES[prec]}/{how}"] = {
-                "leaf": best["leaf"], "tile": best["tile"], "budget": budget,
+                "leaf": best["leaf"], "tile": best["tile"], "quad": best["quad"], "budget": budget,
                 "table": [{k: (round(v, 6) if isinstance(v, float) and k == "seconds" else v) for k, v in r.items()}
                           for r in best["table"]]}
             torch.cuda.empty_cache()
     del exact
     ctx.set_option("gemm_tile", 1)
+    ctx.set_option("gemm_quad", -1)
     return out
 
 

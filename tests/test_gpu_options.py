@@ -80,9 +80,12 @@ def test_autotuner_picks_a_candidate():
     tuner = autotune.Tuner(ctx, leaves=(32, 64), tiles=(0, 1), reps=2)
     sig = autotune.signature("3d", 4096, 1.0, 1e-6, spamm.HYBRID, spamm.F32)
     best = tuner.tune(lambda leaf: ctx.build(A, leaf), sig, 1e-6, spamm.HYBRID, spamm.F32)
-    assert (best["leaf"], best["tile"]) in {(32, 0), (32, 1), (64, 0), (64, 1)}
-    assert len(best["table"]) == 4 and all(r["seconds"] > 0 for r in best["table"])
-    assert ctx.get_option("gemm_tile") == best["tile"]
+    assert (best["leaf"], best["tile"], best["quad"]) in {(32, 0, 0), (32, 1, 0), (64, 0, 0), (64, 1, 0), (64, 1, 1)}
+    assert len(best["table"]) == 5 and all(r["seconds"] > 0 for r in best["table"])
+    # the quad candidate forms the same products as the one-leaf ones at leaf 64
+    kept = {(r["leaf"], r["quad"]): r["n_kept"] for r in best["table"]}
+    assert kept[(64, 1)] == kept[(64, 0)]
+    assert ctx.get_option("gemm_tile") == best["tile"] and ctx.get_option("gemm_quad") == best["quad"]
     assert tuner.tune(None, sig, 1e-6, spamm.HYBRID, spamm.F32) is best  # cached
     ctx.close()
 
