@@ -235,8 +235,12 @@ spamm_status spamm_ctx_set_stream(spamm_ctx* ctx, spamm_stream stream);
  *                       quads for a launch group (one precision) whose C
  *                       leaves average at least 32 (FP64), 128 (FP32) or 16
  *                       (BF16, split BF16) kept products, the one-leaf GEMM
- *                       below.
- *                       Other leaf sizes ignore the option.
+ *                       below.  Leaves 128 and 256: with 1 each 128 x 128
+ *                       tile of a C leaf runs on the same kernel as a quad
+ *                       of its four 64 x 64 blocks (a product is bs / 64
+ *                       merged steps, every block keeps every step); -1
+ *                       takes that for FP64 only.  Leaves 16 and 32 ignore
+ *                       the option.
  * PLACEMENT, GRAPH and UNIT_ORDER give bitwise identical results; GEMM_TILE
  * and GEMM_QUAD change the order of the sums inside one MFMA or one k-panel
  * (results stay within the precision's tolerance).  Errors: EINVAL (unknown

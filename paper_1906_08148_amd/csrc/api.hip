@@ -107,14 +107,17 @@ constexpr int kMaxL = 11;  // G <= 2048
 bool leaf_ok(int bs) { return bs == 16 || bs == 32 || bs == 64 || bs == 128 || bs == 256; }
 
 // Whether a launch group's products run in quads of sibling C leaves:
-// option 1 always (leaf 64), 0 never, -1 when the group's C leaves average
-// at least a precision's threshold of kept products.  Below it the quads'
-// siblings share few k (a step often serves one or two children) and the
-// one-leaf kernel is faster; the thresholds are the measured crossovers on
-// 3D and 1D decay (FP64 / FP32 multiply-bound, BF16 forms load-bound).
+// option 1 always, 0 never, -1: at leaf 64 when the group's C leaves
+// average at least a precision's threshold of kept products (below it the
+// quads' siblings share few k, a step often serves one or two children, and
+// the one-leaf kernel is faster; the thresholds are the measured crossovers
+// on 3D and 1D decay, FP64 / FP32 multiply-bound, BF16 forms load-bound);
+// at leaves 128 and 256 (every child keeps every step) for FP64 only, where
+// they measured 1.07-1.26x faster, the other precisions 0.7-1.1x.
 bool quad_group(const Ctx* c, int prec, int bs, int64_t kept, int64_t leaves) {
   if (c->gemm_quad == 0 || !gemm_quad_supported(prec, bs)) return false;
   if (c->gemm_quad == 1) return true;
+  if (bs > 64) return prec == SPAMM_F64;
   // measured crossovers against the one-leaf GEMM (3D and 1D decay)
   const int64_t per_leaf = prec == SPAMM_F64 ? 32 : prec == SPAMM_F32 ? 128 : 16;
   return kept >= per_leaf * std::max<int64_t>(leaves, 1);
@@ -1346,8 +1349,10 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       const int64_t nwu = launches[gi++].second.second;
       const int64_t maxg = quad ? gemm_quad_max_groups(gk.first.first, c->n_cu)
                                 : gemm_max_groups(gk.first.first, gk.first.second, c->gemm_tile, c->n_cu);
-      // quads: at least a quarter of the units
-      const int64_t want = std::max<int64_t>(1, std::min<int64_t>(maxg, quad ? (nwu + 3) / 4 : nwu));
+      // quads of 64-leaves: at least a quarter of the units (large leaves:
+      // one quad per unit)
+      const int64_t want =
+          std::max<int64_t>(1, std::min<int64_t>(maxg, quad && gk.first.second == 64 ? (nwu + 3) / 4 : nwu));
       const int kx = int((want + kXcds - 1) / kXcds);
       kxs.push_back(kx);
       start_total += int64_t(kXcds) * kx + 1;
@@ -1375,11 +1380,16 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       q_off.push_back({n64, nrec, nst});
       if (!gquad[gi - 1]) continue;
       int64_t slots = 0;
-      for (int r : gk.second) {  // a quad's steps: its products + 1 slots (see k_quad.hip)
+      const int bsg = gk.first.second;
+      for (int r : gk.second) {
         rd[r].qbase = slots;
-        slots += ht[r].n_kept + ht[r].c_nonnull;
-        pk_base[r] = npk;
-        npk += ht[r].n_kept;
+        if (bsg == 64) {  // a quad's steps: its products + 1 slots (see k_quad.hip)
+          slots += ht[r].n_kept + ht[r].c_nonnull;
+          pk_base[r] = npk;
+          npk += ht[r].n_kept;
+        } else {  // bs / 64 steps per product and 128-tile (four tiles per 256-leaf)
+          slots += int64_t(bsg / 64) * (bsg / 128) * (bsg / 128) * ht[r].n_kept;
+        }
       }
       n64 += 4 * nwu + 2;
       nrec += nwu;
@@ -1396,7 +1406,7 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
       int gj = 0;
       for (auto& gk : groups) {
         ++gj;
-        if (!gquad[gj - 1]) continue;
+        if (!gquad[gj - 1] || gk.first.second != 64) continue;
         for (int r : gk.second) rd[r].pk = P<int32_t>(q_pk) + pk_base[r];
       }
     }
@@ -1466,7 +1476,15 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
         int4* steps = P<int4>(q_steps) + qo[2];
         uint8_t* smask = P<uint8_t>(q_mask) + qo[2];
         const WorkUnit* wu = P<WorkUnit>(wus) + u0;
-        {
+        const int bsg = gk.first.second;
+        if (bsg > 64) {  // one quad per unit; flag[0] receives the number of quads
+          TimedScope ts(c, kTPrune);
+          SPAMM_HIP(c, launch_quad_plan_big(c->stream, reqd, wu, nwu, bsg,
+                                            gk.first.first == SPAMM_BF16 || gk.first.first == SPAMM_BF16X3 ? 1 : 0,
+                                            qu, qcost, steps, smask, flag));
+          SPAMM_HIP(c, launch_scan_i64(c->stream, qcost, qpre, nwu, sscr->ptr(), sscr->bytes));
+          SPAMM_HIP(c, launch_wg_ranges(c->stream, qpre, nwu, kXcds * kx, stg));
+        } else {
           TimedScope ts(c, kTPrune);
           SPAMM_HIP(c, launch_quad_mark(c->stream, wu, nwu, flag));
           SPAMM_HIP(c, launch_scan_i64(c->stream, flag, qpos, nwu, sscr->ptr(), sscr->bytes));
@@ -1488,14 +1506,14 @@ static spamm_status multiply_core(Ctx* c, int32_t count, const spamm_request* re
         ga.qu = qu;
         ga.steps = steps;
         ga.smask = smask;
-        ga.nq = qpos + nwu;
+        ga.nq = bsg > 64 ? flag : qpos + nwu;
         TimedScope ts(c, kTGemm);
         if (c->timing) {
           for (int r : gk.second)
             c->gemm_flops += 2.0 * double(reqs[r].A->bs) * reqs[r].A->bs * reqs[r].A->bs * double(ht[r].n_kept);
           ++c->gemm_quad_launches;
         }
-        SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, ga));
+        SPAMM_HIP(c, launch_gemm_quad(c->stream, gk.first.first, bsg, ga));
         continue;
       }
       {

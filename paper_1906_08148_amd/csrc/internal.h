@@ -463,12 +463,16 @@ hipError_t launch_gemm(hipStream_t s, int prec, int bs, int variant, const GemmA
 // (steps + 1, by quad index).
 bool gemm_quad_supported(int prec, int bs);
 int gemm_quad_max_groups(int prec, int n_cu);
-hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a);
+hipError_t launch_gemm_quad(hipStream_t s, int prec, int bs, const GemmArgs& a);
 hipError_t launch_quad_mark(hipStream_t s, const WorkUnit* wu, int64_t nwu, int64_t* flag);
 hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
                             const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask,
                             int pad_even);
 bool gemm_quad_pad_even(int prec);  // quad steps padded to an even count
+// quads of leaves 128 / 256: one per work unit (a 128 x 128 tile), every
+// child kept; *nq receives the number of quads
+hipError_t launch_quad_plan_big(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, int bs, int bf,
+                                QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask, int64_t* nq);
 int gemm_max_groups(int prec, int bs, int variant, int n_cu);  // resident workgroups of the kernel
 bool gemm_supported(int prec, int bs);
 int gemm_unit_tiles(int bs);  // work units per C leaf (4 for 256 leaves, else 1)

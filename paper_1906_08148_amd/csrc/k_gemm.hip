@@ -689,7 +689,7 @@ __global__ void __launch_bounds__((GemmCfg<P, BS, V, LS>::NT), (GemmCfg<P, BS, V
 // per B leaf, its columns swizzled by lane group.  Each load instruction
 // reads one leaf: a scalar leaf address plus a fixed per-lane offset.
 
-template <int P, int V>
+template <int P, int V, int RS = 64>
 struct QuadCfg {
   using G = GemmCfg<P, 128, V>;
   static constexpr bool kBf = G::kBf;
@@ -715,11 +715,19 @@ struct QuadCfg {
   static constexpr int GP = 2;
   static constexpr int VPT = PART / 1024 / NW;       // 1 KiB load blocks of a part per wave
   static constexpr int LOADS = 2 * VPT;              // load instructions per wave per panel
-  static constexpr int64_t LEAF = int64_t(64) * 64 * (kBf ? 2 * ES : ES);  // bytes of a stored 64-leaf
+  // stored leaves of side RS: 64 (the quad's children are four C leaves),
+  // or 128 / 256 (the quad is a 128 x 128 tile of one C leaf, its children
+  // the tile's four 64 x 64 blocks)
+  static constexpr int64_t LEAF = int64_t(RS) * RS * (kBf ? 2 * ES : ES);  // bytes of a stored leaf
+  // the unit of a step's operand indices: whole leaves at RS = 64, else
+  // 64-element offsets from the arena base (the start of a 64 x 64 block)
+  static constexpr int64_t UNIT = RS == 64 ? LEAF : int64_t(64) * ES;
+  static constexpr int NSUB = RS / 128;  // 128-tiles per side of a C leaf (RS > 64)
   static_assert(CH >= 1 && CH <= 8 && 8 % CH == 0, "row chunks");
   static_assert(kBf ? KG % 8 == 0 : KG % 4 == 0, "lane group k slice");
   static_assert(VPT * NW * 1024 == PART, "whole load blocks per part");
   static_assert(MT == 16, "quads take 16 x 16 MFMA tiles");
+  static_assert(RS == 64 || RS == 128 || RS == 256, "leaf sides of the quad kernel");
   static_assert((NP % GP == 0 || NP == 1) && NSTAGE == 2 * GP, "panel groups: one step, or GP steps; two groups in the ring");
 };
 
@@ -778,15 +786,15 @@ __device__ __forceinline__ Win4 load_win4(const GemmArgs& ga, int64_t sp, int32_
 }
 
 // Per-lane byte offsets (within a leaf, panel 0) of the wave's load blocks.
-template <int P, int V>
+template <int P, int V, int RS>
 struct QuadOffs {
-  uint32_t a[QuadCfg<P, V>::VPT], b[QuadCfg<P, V>::VPT];
+  uint32_t a[QuadCfg<P, V, RS>::VPT], b[QuadCfg<P, V, RS>::VPT];
 };
 
-template <int P, int V>
-__device__ __forceinline__ QuadOffs<P, V> quad_offsets(int wave, int lane) {
-  using Q = QuadCfg<P, V>;
-  QuadOffs<P, V> o;
+template <int P, int V, int RS>
+__device__ __forceinline__ QuadOffs<P, V, RS> quad_offsets(int wave, int lane) {
+  using Q = QuadCfg<P, V, RS>;
+  QuadOffs<P, V, RS> o;
 #pragma unroll
   for (int i = 0; i < Q::VPT; ++i) {
     const int q = (i * Q::NW + wave) * 64 + lane;  // chunk of the part
@@ -794,18 +802,18 @@ __device__ __forceinline__ QuadOffs<P, V> quad_offsets(int wave, int lane) {
       const int R = q / Q::CH, phys = q % Q::CH;
       const int h = R / 128, r = R % 128;
       const int kc = phys ^ qswz<Q::CH>(R);
-      o.a[i] = uint32_t((h * 4096 + (r & 63) * 64 + kc * Q::VN) * Q::ES);
+      o.a[i] = uint32_t((h * RS * RS + (r & 63) * RS + kc * Q::VN) * Q::ES);
     }
     if constexpr (Q::kBf) {  // transposed copy: a row is a B column, k contiguous
       const int R = q / Q::CH, phys = q % Q::CH;
       const int h = R / 128, r = R % 128;
       const int kc = phys ^ qswz<Q::CH>(R);
-      o.b[i] = uint32_t((h * 4096 + (r & 63) * 64 + kc * Q::VN) * Q::ES);
+      o.b[i] = uint32_t((h * RS * RS + (r & 63) * RS + kc * Q::VN) * Q::ES);
     } else {  // k-major: one 64-column block per leaf, row kr of 64 columns
       const int qh = q % (Q::KP * 64 / Q::VN);
       const int kr = qh / (64 / Q::VN), pc = (qh % (64 / Q::VN)) * Q::VN;
       const int col = pc ^ (((kr / Q::KG) * Q::MT) % 64);
-      o.b[i] = uint32_t((kr * 64 + col) * Q::ES);
+      o.b[i] = uint32_t((kr * RS + col) * Q::ES);
     }
   }
   return o;
@@ -814,15 +822,16 @@ __device__ __forceinline__ QuadOffs<P, V> quad_offsets(int wave, int lane) {
 // Direct loads of k-panel `sub` of a step (leaves a0 / a1 of the A row
 // halves, b0 / b1 of the B column halves; the plan has put a partner's leaf
 // where no child of the step needs one) into stage `st`.
-template <int P, int V>
-__device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ base, const QuadOffs<P, V>& o,
+template <int P, int V, int RS>
+__device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ base, const QuadOffs<P, V, RS>& o,
                                             int32_t a0, int32_t a1, int32_t b0, int32_t b1, int sub, int wave) {
-  using Q = QuadCfg<P, V>;
-  // FP64 takes the plan's leaves as they are, in unsigned offsets (the
-  // fewest scalar instructions); the eight-wave kernels keep the signed
-  // form with the partner check, a no-op after the plan but measured to
-  // schedule better there
-  constexpr bool kLean = P == SPAMM_F64;
+  using Q = QuadCfg<P, V, RS>;
+  // FP64 (and every precision on large leaves, whose block offsets may
+  // exceed 2^31) takes the plan's indices as they are, unsigned (the fewest
+  // scalar instructions); the eight-wave kernels on 64-leaves keep the
+  // signed form with the partner check, a no-op after the plan but
+  // measured to schedule better there
+  constexpr bool kLean = P == SPAMM_F64 || RS > 64;
   using LT = std::conditional_t<kLean, uint32_t, int32_t>;
   using OT = std::conditional_t<kLean, uint64_t, int64_t>;
   using ST = std::conditional_t<kLean, uint32_t, int64_t>;
@@ -837,7 +846,7 @@ __device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ b
     const int blk = i * Q::NW + wave;  // 1 KiB block of the part (wave-uniform)
     // an A block's rows lie in one row half
     const LT leaf = ((blk * 64 / Q::CH) % 128) < 64 ? a0 : a1;
-    const auto L = as_global(base + OT(leaf) * Q::LEAF + sub * (Q::KP * Q::ES));
+    const auto L = as_global(base + OT(leaf) * Q::UNIT + sub * (Q::KP * Q::ES));
     __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.a[i]),
                                      (__attribute__((address_space(3))) void*)(st + blk * 1024), 16, 0, 0);
   }
@@ -851,9 +860,9 @@ __device__ __forceinline__ void issue_panel(char* st, const char* __restrict__ b
       so = sub * (Q::KP * Q::ES);
     } else {
       leaf = blk < 8 ? b0 : b1;  // blocks 0-7: the left B leaf, 8-15: the right
-      so = ST(sub) * ST(Q::KP * 64 * Q::ES);
+      so = ST(sub) * ST(Q::KP * RS * Q::ES);
     }
-    const auto L = as_global(base + OT(leaf) * Q::LEAF + so);
+    const auto L = as_global(base + OT(leaf) * Q::UNIT + so);
     __builtin_amdgcn_global_load_lds(reinterpret_cast<const __attribute__((address_space(1))) void*>(L + o.b[i]),
                                      (__attribute__((address_space(3))) void*)(st + Q::PART + blk * 1024), 16, 0, 0);
   }
@@ -973,24 +982,35 @@ __device__ __forceinline__ void compute_quad_panel(QAcc<P, V>& acc, const char* 
   }
 }
 
-// The C leaves of a quad from the waves' accumulators: C (optionally
-// alpha * AB + beta * D), its FP64 squared norm and, on a diagonal leaf, its
-// diagonal sum, for the child's work unit.  Called by every wave at the same
-// point (it holds a workgroup barrier); red: 2 * 8 partial sums.
-template <int P, int V>
+// The C blocks of a quad from the waves' accumulators: C (optionally
+// alpha * AB + beta * D), its FP64 squared norm and, on the diagonal, its
+// diagonal sum, for the work unit (a child's C leaf at RS = 64, else the
+// quad's 128 x 128 tile of one C leaf).  Called by every wave at the same
+// point (it holds a workgroup barrier); red: 2 * NW partial sums.
+template <int P, int V, int RS>
 __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q, QAcc<P, V>& acc, double* red,
                                               int wave, int lane, int child, int crow0, int ccol0, int li,
                                               int g) {
-  using Q = QuadCfg<P, V>;
+  using Q = QuadCfg<P, V, RS>;
   using Out = typename GemmCfg<P, 128, V>::Out;
-  const bool present = (q.cmask >> child) & 1;
-  const int64_t u = int64_t(q.u0) + __builtin_popcount(uint32_t(q.cmask) & ((1u << child) - 1u));
+  const bool present = RS > 64 || ((q.cmask >> child) & 1);
+  const int64_t u =
+      RS > 64 ? int64_t(q.u0) : int64_t(q.u0) + __builtin_popcount(uint32_t(q.cmask) & ((1u << child) - 1u));
   uint32_t ci = 0, cj = 0;
+  int r0 = 0, c0 = 0;  // the child's block in its C leaf
+  bool diag_tile = true;
   if (present) {
     const WorkUnit W = ga.wu[u];
     const auto Cl =
-        as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(W.cidx) * 64 * 64 * sizeof(Out)));
+        as_global(reinterpret_cast<Out*>(const_cast<char*>(ga.base) + int64_t(W.cidx) * RS * RS * sizeof(Out)));
     const uint32_t cm = uint32_t(W.cflags & kUnitMorton);
+    if constexpr (RS > 64) {
+      const int tile = unit_tile(W.cflags);
+      const int tr0 = (tile / Q::NSUB) * 128, tc0 = (tile % Q::NSUB) * 128;
+      diag_tile = tr0 == tc0;
+      r0 = tr0 + 64 * (child >> 1);
+      c0 = tc0 + 64 * (child & 1);
+    }
     const bool has_ep = (W.cflags & kUnitEp) != 0;
     Out alpha = Out(1), beta = Out(0);
     const Out* Dl = nullptr;
@@ -1000,7 +1020,7 @@ __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q
       beta = Out(R->beta);
       if (R->Dslot != nullptr) {
         const int32_t ds = R->Dslot[cm];
-        if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * 64 * 64;
+        if (ds >= 0) Dl = static_cast<const Out*>(R->Dstore) + int64_t(ds) * RS * RS;
       }
     }
     demorton(cm, ci, cj);
@@ -1011,15 +1031,15 @@ __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q
       for (int b = 0; b < Q::TN; ++b)
 #pragma unroll
         for (int v = 0; v < Q::AE; ++v) {
-          const int row = crow0 + a * Q::MT + acc_row<P, 128, V>(g, v);  // within the child's leaf
-          const int col = ccol0 + b * Q::MT + li;
+          const int row = r0 + crow0 + a * Q::MT + acc_row<P, 128, V>(g, v);  // within the C leaf
+          const int col = c0 + ccol0 + b * Q::MT + li;
           Out val = Out(acc[a][b][v]);
           if (has_ep) {
             const Out prod = alpha * val;
-            const Out dv = Dl ? beta * as_global(Dl)[row * 64 + col] : Out(0);
+            const Out dv = Dl ? beta * as_global(Dl)[row * RS + col] : Out(0);
             val = prod + dv;
           }
-          Cl[row * 64 + col] = val;
+          Cl[row * RS + col] = val;
           const double dval = double(val);
           nsq += dval * dval;
           if (row == col) tr += dval;
@@ -1032,21 +1052,24 @@ __device__ __forceinline__ void epilogue_quad(const GemmArgs& ga, const QuadS& q
     }
   }
   __syncthreads();
-  if (present && wave % Q::WPC == 0 && lane == 0) {  // the child's parts, in wave order
+  // the unit's parts, in wave order: a child's waves at RS = 64, every wave
+  // of the quad else
+  constexpr int WPU = RS > 64 ? Q::NW : Q::WPC;
+  if (present && wave % WPU == 0 && lane == 0) {
     double s = 0.0, t = 0.0;
 #pragma unroll
-    for (int x = 0; x < Q::WPC; ++x) {
+    for (int x = 0; x < WPU; ++x) {
       s += red[wave + x];
       t += red[Q::NW + wave + x];
     }
     as_global(ga.wn)[u] = s;
-    if (ci == cj) as_global(ga.wt)[u] = t;
+    if (ci == cj && diag_tile) as_global(ga.wt)[u] = t;
   }
 }
 
-template <int P, int V>
-__global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const GemmArgs ga) {
-  using Q = QuadCfg<P, V>;
+template <int P, int V, int RS>
+__global__ void __launch_bounds__((QuadCfg<P, V, RS>::NT), 1) k_gemm_quad(const GemmArgs ga) {
+  using Q = QuadCfg<P, V, RS>;
   __shared__ __attribute__((aligned(1024))) char smem[Q::NSTAGE * Q::STAGE];
   // partial norm and diagonal sums of the epilogue, two sets used in turn
   __shared__ double red2[2][2 * Q::NW];
@@ -1060,7 +1083,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
   const int row0 = (child >> 1) * 64 + crow0, col0 = (child & 1) * 64 + ccol0;  // ... and in the quad
   const int li = lane % Q::MT, g = lane / Q::MT;
   const char* const base = ga.base;
-  const QuadOffs<P, V> offs = quad_offsets<P, V>(wave, lane);
+  const QuadOffs<P, V, RS> offs = quad_offsets<P, V, RS>(wave, lane);
 
   // the quads this workgroup visits (visit t = 0 .. u1 - 1): a contiguous
   // range of equal cost, or the XCD's share dealt round-robin over its
@@ -1152,7 +1175,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
     const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
     const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
     const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
-    issue_panel<P, V>(smem + ist * Q::STAGE, base, offs, a0, a1, b0, b1, lsub, wave);
+    issue_panel<P, V, RS>(smem + ist * Q::STAGE, base, offs, a0, a1, b0, b1, lsub, wave);
     const bool last_sub = lsub + 1 == Q::NP;
     fifo |= m << (8 * ahead);
     ++ahead;
@@ -1191,7 +1214,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
       const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
 #pragma unroll
       for (int k = 0; k < Q::GP; ++k) {
-        issue_panel<P, V>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, lsub + k, wave);
+        issue_panel<P, V, RS>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, lsub + k, wave);
         fifo |= m << (8 * (ahead + k));
       }
       lsub += Q::GP;
@@ -1206,7 +1229,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
         const int32_t a0 = __builtin_amdgcn_readlane(WL.a0, l), a1 = __builtin_amdgcn_readlane(WL.a1, l);
         const int32_t b0 = __builtin_amdgcn_readlane(WL.b0, l), b1 = __builtin_amdgcn_readlane(WL.b1, l);
         const uint32_t m = uint32_t(__builtin_amdgcn_readlane(WL.m, l));
-        issue_panel<P, V>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, 0, wave);
+        issue_panel<P, V, RS>(st + k * Q::STAGE, base, offs, a0, a1, b0, b1, 0, wave);
         fifo |= m << (8 * (ahead + k));
       }
       next_step(Q::GP);
@@ -1231,7 +1254,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
     while (cq < u1) {
       const QuadS E = rec(cq);
       if (E.ns != 0) break;
-      epilogue_quad<P, V>(*gp, E, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
+      epilogue_quad<P, V, RS>(*gp, E, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
       ++cq;
     }
   };
@@ -1334,7 +1357,7 @@ __global__ void __launch_bounds__((QuadCfg<P, V>::NT), 1) k_gemm_quad(const Gemm
         }
       }
     }
-    epilogue_quad<P, V>(ga, C, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
+    epilogue_quad<P, V, RS>(ga, C, acc, red2[cq & 1], wave, lane, child, crow0, ccol0, li, g);
     clear();
     ++cq;
     flush_empty();
@@ -1345,7 +1368,7 @@ template <int P, int V>
 static int max_groups_quad(int n_cu) {
   static const int per_cu = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V>, QuadCfg<P, V>::NT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_gemm_quad<P, V, 64>, QuadCfg<P, V>::NT, 0) != hipSuccess ||
         v < 1)
       v = 1;
     return v;
@@ -1360,7 +1383,9 @@ bool gemm_quad_pad_even(int prec) {
   return prec == SPAMM_BF16;
 }
 
-bool gemm_quad_supported(int prec, int bs) { return bs == 64 && prec >= SPAMM_F64 && prec <= SPAMM_BF16X3; }
+bool gemm_quad_supported(int prec, int bs) {
+  return (bs == 64 || bs == 128 || bs == 256) && prec >= SPAMM_F64 && prec <= SPAMM_BF16X3;
+}
 
 // Quads take 16 x 16 MFMA tiles in every precision (the 32 x 32 variant
 // needs more registers than the pipelined kernel leaves).
@@ -1382,12 +1407,21 @@ int gemm_quad_max_groups(int prec, int n_cu) {
   });
 }
 
-hipError_t launch_gemm_quad(hipStream_t s, int prec, const GemmArgs& a) {
+template <int P, int V, int RS>
+static hipError_t launch_quad_rs(hipStream_t s, const GemmArgs& a) {
+  hipLaunchKernelGGL((k_gemm_quad<P, V, RS>), dim3(uint32_t(kXcds * a.kx)), dim3(QuadCfg<P, V, RS>::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_quad(hipStream_t s, int prec, int bs, const GemmArgs& a) {
+  if (!gemm_quad_supported(prec, bs)) return hipErrorInvalidValue;
   return dispatch_quad(prec, [&](auto pc, auto vc) -> hipError_t {
-    hipLaunchKernelGGL((k_gemm_quad<decltype(pc)::value, decltype(vc)::value>), dim3(uint32_t(kXcds * a.kx)),
-                       dim3(QuadCfg<decltype(pc)::value, decltype(vc)::value>::NT),
-                       0, s, a);
-    return hipGetLastError();
+    constexpr int P = decltype(pc)::value, V = decltype(vc)::value;
+    switch (bs) {
+      case 64: return launch_quad_rs<P, V, 64>(s, a);
+      case 128: return launch_quad_rs<P, V, 128>(s, a);
+      default: return launch_quad_rs<P, V, 256>(s, a);
+    }
   });
 }
 

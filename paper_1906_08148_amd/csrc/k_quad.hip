@@ -167,6 +167,72 @@ __global__ void __launch_bounds__(kQuadWaves * 64) k_quad_plan(const ReqDev* __r
   }
 }
 
+// Quads of large leaves (128 and 256): a work unit is a 128 x 128 tile of
+// one C leaf, run by the quad kernel as four 64 x 64 children that keep
+// every step.  A product A(I,K) B(K,J) of bs = 64 s contributes s steps (its
+// k blocks of 64, ascending); a step names the 64 x 64 blocks of A in the
+// tile's two block rows and of B in its two block columns, as offsets from
+// the arena base in units of 64 elements (A row-major, FP32/FP64 B
+// row-major with k as its row, BF16 B from the transposed copy with k
+// contiguous).  One wave per unit.  The four tiles of a 256-leaf share their
+// leaf's products, so a leaf's steps take 4 s slots per product, tile t at
+// s t cnt after the leaf's first: a unit's steps sit at the request's step
+// base plus s (tiles * first product + t * cnt), with no scan.
+__global__ void __launch_bounds__(256) k_quad_plan_big(const ReqDev* __restrict__ reqs,
+                                                       const WorkUnit* __restrict__ wu, int64_t nwu, int bs,
+                                                       int bf, QuadUnit* __restrict__ qu, int64_t* __restrict__ cost,
+                                                       int4* __restrict__ steps, uint8_t* __restrict__ smask,
+                                                       int64_t* __restrict__ nq) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t u = int64_t(blockIdx.x) * 4 + w;
+  if (u == 0 && lane == 0) *nq = nwu;
+  if (u >= nwu) return;
+  const WorkUnit x = wu[u];
+  const ReqDev& R = reqs[x.req];
+  const int spp = bs / 64;                                 // steps per product
+  const int nsub = bs / 128;                               // 128-tiles per side
+  const int tile = unit_tile(x.cflags);
+  const uint32_t tr = uint32_t((tile / nsub) * 128), tc = uint32_t((tile % nsub) * 128);
+  const uint32_t lu = uint32_t(bs) * uint32_t(bs) * (bf ? 2u : 1u) / 64u;  // 64-element units per stored leaf
+  const int64_t off = x.pp - R.pairs_idx;                  // first product within the request's list
+  const int64_t sp = R.qbase + int64_t(spp) * (int64_t(nsub) * nsub * off + int64_t(tile) * x.cnt);
+  const int32_t ns = spp * x.cnt;
+  if (lane == 0) {
+    QuadUnit q;
+    q.sp = sp;
+    q.ns = ns;
+    q.u0 = int32_t(u);
+    q.cmask = 0xF;
+    q.req = x.req;
+    qu[u] = q;
+    cost[u] = int64_t(ns) + 1;
+  }
+  for (int32_t t = lane; t < ns; t += 64) {
+    const int2 pr = R.pairs[off + t / spp];
+    const uint32_t kh = uint32_t(t % spp);
+    const uint32_t ab = uint32_t(pr.x) * lu, bb = uint32_t(pr.y) * lu;
+    const uint32_t a0 = ab + tr * uint32_t(bs) / 64u + kh, a1 = a0 + uint32_t(bs);  // block rows tr, tr + 64
+    uint32_t b0, b1;
+    if (bf) {  // transposed copy: row j, k contiguous
+      b0 = bb + tc * uint32_t(bs) / 64u + kh;
+      b1 = b0 + uint32_t(bs);
+    } else {  // row k, j contiguous
+      b0 = bb + kh * uint32_t(bs) + tc / 64u;
+      b1 = b0 + 1u;
+    }
+    steps[sp + t] = make_int4(int32_t(a0), int32_t(a1), int32_t(b0), int32_t(b1));
+    smask[sp + t] = 0xF;
+  }
+}
+
+hipError_t launch_quad_plan_big(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, int bs, int bf,
+                                QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask, int64_t* nq) {
+  if (bs != 128 && bs != 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_quad_plan_big, dim3(uint32_t(std::max<int64_t>((nwu + 3) / 4, 1))), dim3(256), 0, s, reqs,
+                     wu, nwu, bs, bf, qu, cost, steps, smask, nq);
+  return hipGetLastError();
+}
+
 hipError_t launch_quad_plan(hipStream_t s, const ReqDev* reqs, const WorkUnit* wu, int64_t nwu, const int64_t* flag,
                             const int64_t* qpos, QuadUnit* qu, int64_t* cost, int4* steps, uint8_t* smask,
                             int pad_even) {

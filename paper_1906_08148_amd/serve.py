@@ -59,7 +59,9 @@ class RequestSpec:
         """Arena bytes the request may need: the leaf store of A in the
         request's precision (FP64 or FP32), C (FP64 or FP32), the kept pairs
         (with the quad plan of a leaf-64 product: merged steps, their
-        children and the k of every pair) and the per-leaf arrays.
+        children and the k of every pair; of an FP64 leaf-128 / 256 product:
+        bs / 64 steps of 17 bytes per pair and 128-tile) and the per-leaf
+        arrays.
         `nonnull` (non-null leaves of A) defaults to an upper bound for the
         kind."""
         g, G = self.grid()
@@ -74,7 +76,12 @@ class RequestSpec:
         kept = min(g ** 3, c_leaves * 2 * row)
         eb = 8 if self.prec == 0 else 4
         store = nonnull * e2 * (eb if self.prec in (0, 1) else 12)  # BF16 needs FP32 plus two BF16 copies
-        per_pair = 8 + (21 if self.leaf == 64 else 0)
+        if self.leaf == 64:
+            per_pair = 8 + 21
+        elif self.leaf > 64 and self.prec == 0:
+            per_pair = 8 + 17 * (self.leaf // 64) * (self.leaf // 128) ** 2
+        else:
+            per_pair = 8
         return int(store + c_leaves * e2 * eb + kept * per_pair + G * G * 96 + (16 << 20))
 
 

@@ -380,9 +380,11 @@ class Context:
         """validate (1: measure ||C - C_FP64||_F into stats["val_err"]),
         gemm_tile (1: 16x16 MFMA tiles, the default; 0: 32x32), placement (0: XCD
         slices, 1: request-major), graph (1: one captured graph per batch),
-        gemm_quad (1: leaf-64 products in quads of sibling C leaves; 0: one
-        C leaf per work unit; -1, the default: quads where the C leaves
-        average enough kept products)."""
+        gemm_quad (1: leaf-64 products in quads of sibling C leaves, and
+        leaf-128 / 256 tiles as quads of their 64 x 64 blocks; 0: one C leaf
+        (or tile) per work unit; -1, the default: leaf 64 on quads where the
+        C leaves average enough kept products, leaves 128 / 256 on quads in
+        FP64)."""
         self._check(_lib.spamm_ctx_set_option(self.ptr, self.OPTIONS[name], int(value)))
 
     def get_option(self, name: str) -> int:

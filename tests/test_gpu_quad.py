@@ -209,3 +209,73 @@ def test_automatic_choice_follows_products_per_leaf(ctx):
         forced.C.release()
     ctx.set_option("gemm_quad", 1)
     M.release()
+
+
+# large leaves (128, 256): every work unit (a 128 x 128 tile of a C leaf) is
+# one quad of its four 64 x 64 blocks, each product bs / 64 merged steps
+BIG_CASES = [
+    (1500, "1d", 0.05, 1e-6, 128),   # G = 12 -> 16, ragged, banded
+    (2048, "3d", 1.0, 0.7, 128),     # pruning (no mirror pair split by the truncation)
+    (1500, "1d", 0.05, 1e-6, 256),   # G = 6 -> 8, ragged, four tiles per leaf
+    (2048, "3d", 1.0, 3.0, 256),
+    (200, "1d", 0.05, 1e-5, 256),    # a single C leaf
+]
+
+
+@pytest.mark.parametrize("quad", [1, 0])
+@pytest.mark.parametrize("n,kind,alpha,tau,leaf", BIG_CASES)
+def test_large_leaf_quads_match_the_oracle(ctx, n, kind, alpha, tau, leaf, quad):
+    """Leaves 128 and 256 on the quad kernel (the default) and on the
+    one-leaf kernel, every scheme and precision, against the oracle."""
+    print(f"case: large-leaf quad={quad} leaf={leaf} n={n} {kind} alpha={alpha} tau={tau}", flush=True)
+    ctx.set_option("gemm_quad", quad)
+    A = synth.DecaySpec(kind, n, alpha, seed=3).dense()
+    B = A if kind == "3d" else synth.DecaySpec(kind, n, alpha * 1.5, seed=4).dense()
+    TA = O.build(A, leaf)
+    TB = TA if B is A else O.build(B, leaf)
+    MA = ctx.build(dev(A), leaf, stores=ALL)
+    MB = MA if B is A else ctx.build(dev(B), leaf, stores=ALL)
+    for mode in MODES:
+        for prec in PRECS:
+            ctx.timing(enable=True, reset=True)
+            p, _, _ = check_product(ctx, MA, MB, TA, TB, tau, mode, prec, alias=B is A)
+            tm = ctx.timing(enable=False, reset=True)
+            if p.stats["n_kept"] > 0:
+                assert (tm["gemm_quad_launches"] > 0) == (quad == 1), tm
+            p.C.release()
+    ctx.set_option("gemm_quad", 1)
+    if MB is not MA:
+        MB.release()
+    MA.release()
+
+
+@pytest.mark.parametrize("leaf", [128, 256])
+def test_large_leaf_quads_epilogue_and_symmetric(ctx, leaf):
+    """alpha * AB + beta * D with C leaves from D alone, and the symmetric
+    square, on large-leaf quads."""
+    from test_gpu_symmetric import _check_sym
+    print(f"case: large-leaf quad epilogue / symmetric leaf={leaf}", flush=True)
+    A = synth.DecaySpec("1d", 1500, 0.5, seed=6).dense()
+    D = synth.dense_from_blocks(1500, leaf, *synth.random_blocks(7, 1500, leaf, 0.5))
+    TA = O.build(A, leaf)
+    MA, MD = ctx.build(dev(A), leaf), ctx.build(dev(D), leaf)
+    for prec in (spamm.F64, spamm.F32):
+        p = ctx.multiply(MA, MA, 1e-9, mode=spamm.HYBRID, prec=prec, alpha=-1.0, beta=2.0, D=MD)
+        ref = O.multiply(TA, TA, 1e-9, O.HYBRID)
+        want = 2.0 * D - ref.C.to_dense()
+        assert rel_fro(ctx.to_dense(p.C).cpu().numpy(), want) <= TOL[prec]
+        assert p.C.info.nonnull == int((ref.C.leaf_present | O.build(D, leaf).leaf_present).sum())
+        assert abs(p.stats["trace"] - float(np.trace(want))) <= TOL[prec] * max(1.0, abs(float(np.trace(want))))
+        p.C.release()
+    MA.release()
+    MD.release()
+    S = synth.DecaySpec("3d", 2048, 1.0, seed=8).dense()
+    T = O.build(S, leaf)
+    M = ctx.build(dev(S), leaf, stores=ALL)
+    ref = O.multiply_symmetric(T, 3e-3, O.SPAMM)
+    assert not ref.stats["trunc_tie"] and not ref.stats["sym_fallback"]
+    for prec in (spamm.F64, spamm.F32, spamm.BF16X3):
+        p = ctx.multiply(M, M, 3e-3, mode=spamm.SPAMM_SYM, prec=prec)
+        _check_sym(ctx, p, ref, T, prec, 3e-3)
+        p.C.release()
+    M.release()
