@@ -753,7 +753,7 @@ def main():
     tile = ctx.get_option("gemm_tile")
     quad = r["tm"]["gemm_quad_launches"] > 0  # the GEMM the library chose for this workload
     if quad:
-        kname = f"void spamm::k_gemm_quad<{prec}, {0 if prec == spamm.F64 else 1}>"
+        kname = f"void spamm::k_gemm_quad<{prec}, {0 if prec == spamm.F64 else 1}, {LEAF3D}>"
     else:
         kname = f"void spamm::k_gemm<{prec}, {LEAF3D}, {0 if prec == spamm.F64 else tile}, {LEAF3D}>"
     st = r["stats"]
