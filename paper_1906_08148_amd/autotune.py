@@ -9,7 +9,9 @@ tile variant (32 x 32 or 16 x 16 MFMA tiles for FP32 / BF16) changes the
 register budget and the issue pattern of the leaf GEMM.  At leaf 64 the
 GEMM can also run the four sibling C leaves of a quadtree node in one
 workgroup (quads, option gemm_quad), which halves the operand loads where
-siblings share their k and costs time where they do not.
+siblings share their k and costs time where they do not; at leaves 128 and
+256 the same kernel runs a C leaf's 128 x 128 tile as a quad of its 64 x 64
+blocks.
 
 For every candidate the tuner times the full multiply (prune + GEMM +
 epilogue) on the device and takes its error: by default the library's
@@ -52,11 +54,11 @@ def _time_multiply(ctx, M, tau, mode, prec, reps):
 
 def candidates(leaves, tiles, quads=True):
     """(leaf, tile, quad) to try: every leaf with every tile on one C leaf
-    per workgroup, and at leaf 64 quads once (they take 16 x 16 tiles
-    whatever the tile option says)."""
+    (or 128-tile) per workgroup, and at leaves 64 to 256 quads once each
+    (they take 16 x 16 tiles whatever the tile option says)."""
     out = [(l, t, 0) for l in leaves for t in tiles]
-    if quads and 64 in leaves:
-        out.append((64, 1, 1))
+    if quads:
+        out += [(l, 1, 1) for l in leaves if l >= 64]
     return out
 
 

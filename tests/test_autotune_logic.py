@@ -2,10 +2,10 @@
 from paper_1906_08148_amd import autotune
 
 
-def test_candidates_add_quads_at_leaf_64_only():
+def test_candidates_add_quads_from_leaf_64():
     c = autotune.candidates((32, 64, 128), (0, 1))
-    assert c == [(32, 0, 0), (32, 1, 0), (64, 0, 0), (64, 1, 0), (128, 0, 0), (128, 1, 0), (64, 1, 1)]
-    assert autotune.candidates((32, 128), (0,)) == [(32, 0, 0), (128, 0, 0)]
+    assert c == [(32, 0, 0), (32, 1, 0), (64, 0, 0), (64, 1, 0), (128, 0, 0), (128, 1, 0), (64, 1, 1), (128, 1, 1)]
+    assert autotune.candidates((16, 32), (0,)) == [(16, 0, 0), (32, 0, 0)]
     assert autotune.candidates((64,), (0,), quads=False) == [(64, 0, 0)]
 
 
