@@ -1,6 +1,8 @@
 """Quads of sibling C leaves (leaf 64, option gemm_quad, on by default):
 the leaf GEMM that runs the up to four children of a quadtree node of C in
-one workgroup over the merged k order of their products.  Checked against the CPU oracle in
+one workgroup over the merged k order of their products; at leaves 128 and
+256 the same kernel runs a C leaf's 128 x 128 tile as a quad of its four
+64 x 64 blocks.  Checked against the CPU oracle in
 every scheme and precision (ragged tails, banded matrices whose quads have
 one to four children, 3D decay with partial pruning), against the one-leaf
 path, for repeatability, batches, C leaves from D alone, the symmetric
