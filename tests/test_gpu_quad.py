@@ -105,14 +105,18 @@ def test_quad_equals_one_leaf_path(ctx):
 
 
 def test_quad_batch_equals_alone(ctx):
-    """Quads never span requests: each request of a mixed batch (quad and
-    other leaf sizes) gives the C it gives alone, bit for bit."""
+    """Quads never span requests: each request of a mixed batch (quads of
+    sibling leaves, quads of 128- and 256-leaf blocks, and leaf 32 on the
+    one-leaf kernel) gives the C it gives alone, bit for bit."""
     import torch
     print("case: quad batch vs alone", flush=True)
     A = synth.DecaySpec("3d", 2048, 0.8, seed=10).dense()
     B = synth.DecaySpec("1d", 2048, 0.05, seed=11).dense()
     MA, MB, M32 = ctx.build(dev(A), 64, stores=ALL), ctx.build(dev(B), 64, stores=ALL), ctx.build(dev(A), 32)
+    M128, M256 = ctx.build(dev(B), 128), ctx.build(dev(A), 256)
     reqs = [dict(A=MA, B=MA, tau=1e-4, mode=spamm.HYBRID, prec=spamm.F32),
+            dict(A=M128, B=M128, tau=1e-6, mode=spamm.SPAMM, prec=spamm.F64),
+            dict(A=M256, B=M256, tau=1e-3, mode=spamm.HYBRID, prec=spamm.F64),
             dict(A=MB, B=MB, tau=1e-6, mode=spamm.SPAMM, prec=spamm.F32),
             dict(A=M32, B=M32, tau=1e-5, mode=spamm.SPAMM, prec=spamm.F32),
             dict(A=MA, B=MB, tau=1e-6, mode=spamm.TRUNCMUL, prec=spamm.BF16X3),
@@ -123,7 +127,7 @@ def test_quad_batch_equals_alone(ctx):
         assert torch.equal(ctx.to_dense(a.C), ctx.to_dense(b.C))
         a.C.release()
         b.C.release()
-    for m in (MA, MB, M32):
+    for m in (MA, MB, M32, M128, M256):
         m.release()
 
 
