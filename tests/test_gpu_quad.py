@@ -175,20 +175,21 @@ def test_quad_graph_replays(ctx):
     import torch
     print("case: quad graph", flush=True)
     A = synth.DecaySpec("3d", 2048, 1.0, seed=12).dense()
-    M = ctx.build(dev(A), 64, stores=ALL)
-    eager = ctx.multiply(M, M, 1e-3, mode=spamm.HYBRID, prec=spamm.BF16X3)
-    want = ctx.to_dense(eager.C)
-    ctx.set_option("graph", 1)
-    try:
-        for _ in range(3):
-            p = ctx.multiply(M, M, 1e-3, mode=spamm.HYBRID, prec=spamm.BF16X3)
-            assert torch.equal(ctx.to_dense(p.C), want)
-            p.C.release()
-            torch.cuda.synchronize()
-    finally:
-        ctx.set_option("graph", 0)
-    eager.C.release()
-    M.release()
+    for leaf, prec in ((64, spamm.BF16X3), (128, spamm.F64)):  # quads of siblings, of a tile's blocks
+        M = ctx.build(dev(A), leaf, stores=ALL)
+        eager = ctx.multiply(M, M, 1e-3, mode=spamm.HYBRID, prec=prec)
+        want = ctx.to_dense(eager.C)
+        ctx.set_option("graph", 1)
+        try:
+            for _ in range(3):
+                p = ctx.multiply(M, M, 1e-3, mode=spamm.HYBRID, prec=prec)
+                assert torch.equal(ctx.to_dense(p.C), want)
+                p.C.release()
+                torch.cuda.synchronize()
+        finally:
+            ctx.set_option("graph", 0)
+        eager.C.release()
+        M.release()
 
 
 def test_automatic_choice_follows_products_per_leaf(ctx):
